@@ -1,0 +1,193 @@
+"""Python access to the plain FP64 CPU oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg use it as the correctness reference.  The GPU library never
+imports, links or calls anything here, and nothing here imports the GPU
+library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+HAMS = {"LL": 0, "DC": 1, "DCG": 2, "GAUNT": 3}
+
+
+def build(verbose: bool = False) -> str:
+    """Compile liboracle.so with gcc (no FMA contraction, OpenMP)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-fPIC", "-shared", "-Wall", "-Wno-unused-variable",
+           os.path.join(_HERE, "oracle.c"), "-o", _SO + ".tmp", "-lm"]
+    subprocess.run(cmd, check=True, capture_output=not verbose)
+    os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+class _Basis(ctypes.Structure):
+    _fields_ = [("nfunc", ctypes.c_int32),
+                ("centers", ctypes.POINTER(ctypes.c_double)),
+                ("nprim", ctypes.POINTER(ctypes.c_int32)),
+                ("exps", ctypes.POINTER(ctypes.c_double)),
+                ("coefs", ctypes.POINTER(ctypes.c_double))]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("kept", ctypes.c_int64 * 4), ("total", ctypes.c_int64 * 4),
+                ("kept_gaunt", ctypes.c_int64), ("total_gaunt", ctypes.c_int64),
+                ("tie_band", ctypes.c_int64),
+                ("seconds_first_half", ctypes.c_double),
+                ("seconds_second_half", ctypes.c_double),
+                ("threads", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"kept": list(self.kept), "total": list(self.total),
+                "kept_gaunt": self.kept_gaunt, "total_gaunt": self.total_gaunt,
+                "tie_band": self.tie_band, "seconds_first_half": self.seconds_first_half,
+                "seconds_second_half": self.seconds_second_half, "threads": self.threads}
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = ctypes.CDLL(_SO)
+        dp = ctypes.POINTER(ctypes.c_double)
+        bp = ctypes.POINTER(_Basis)
+        L.orc_boys0.restype = ctypes.c_double
+        L.orc_boys0.argtypes = [ctypes.c_double]
+        L.orc_norm_coefs.argtypes = [bp, dp]
+        L.orc_eri.restype = ctypes.c_double
+        L.orc_eri.argtypes = [bp, ctypes.c_int, ctypes.c_int, bp, ctypes.c_int, ctypes.c_int]
+        L.orc_eri_tensor.argtypes = [bp, bp, bp, bp, dp]
+        L.orc_schwarz.argtypes = [bp, bp, dp]
+        L.orc_dmax_coulomb.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp]
+        L.orc_transform_def.restype = ctypes.c_int
+        L.orc_transform_def.argtypes = [bp, bp, dp, dp, ctypes.c_int, ctypes.c_int, dp, dp, dp]
+        L.orc_transform_direct.restype = ctypes.c_int
+        L.orc_transform_direct.argtypes = [bp, bp, dp, dp, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
+                                           ctypes.c_int, dp, ctypes.POINTER(Stats)]
+        L.orc_num_bra_pairs.restype = ctypes.c_int64
+        L.orc_num_bra_pairs.argtypes = [bp, bp, ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class _B:
+    """Keeps the numpy buffers of a basis alive next to its ctypes struct."""
+
+    def __init__(self, b):
+        self.centers = np.ascontiguousarray(b.centers, dtype=np.float64)
+        self.nprim = np.ascontiguousarray(b.nprim, dtype=np.int32)
+        self.exps = np.ascontiguousarray(b.exps, dtype=np.float64)
+        self.coefs = np.ascontiguousarray(b.coefs, dtype=np.float64)
+        self.s = _Basis(int(self.nprim.shape[0]), _dp(self.centers),
+                        self.nprim.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                        _dp(self.exps), _dp(self.coefs))
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.s)
+
+
+def boys0(T: float) -> float:
+    return lib().orc_boys0(float(T))
+
+
+def norm_coefs(b) -> np.ndarray:
+    B = _B(b)
+    out = np.empty_like(B.coefs)
+    lib().orc_norm_coefs(B.ref, _dp(out))
+    return out
+
+
+def eri(A, mu, nu, B, ka, la) -> float:
+    a, b = _B(A), _B(B)
+    return lib().orc_eri(a.ref, mu, nu, b.ref, ka, la)
+
+
+def eri_tensor(A, B=None, C=None, D=None) -> np.ndarray:
+    B = A if B is None else B
+    C = A if C is None else C
+    D = C if D is None else D
+    bs = [_B(x) for x in (A, B, C, D)]
+    out = np.empty((A.nfunc, B.nfunc, C.nfunc, D.nfunc))
+    lib().orc_eri_tensor(bs[0].ref, bs[1].ref, bs[2].ref, bs[3].ref, _dp(out))
+    return out
+
+
+def schwarz(A, B=None) -> np.ndarray:
+    B = A if B is None else B
+    a, b = _B(A), _B(B)
+    out = np.empty((A.nfunc, B.nfunc))
+    lib().orc_schwarz(a.ref, b.ref, _dp(out))
+    return out
+
+
+def dmax_coulomb(C: np.ndarray) -> np.ndarray:
+    C = np.ascontiguousarray(C, dtype=np.float64)
+    N, n = C.shape[1], C.shape[2]
+    out = np.empty((N, N))
+    lib().orc_dmax_coulomb(N, _dp(C), n, _dp(out))
+    return out
+
+
+def _prep(L, S, CL, CS):
+    bl = _B(L)
+    bs = _B(S) if S is not None else None
+    CL = np.ascontiguousarray(CL, dtype=np.float64)
+    CS = np.ascontiguousarray(CS, dtype=np.float64) if CS is not None else None
+    return bl, bs, CL, CS
+
+
+def transform_def(L, S, CL, CS, ham: str = "LL", return_spinor: bool = False):
+    """Unscreened definition route (literal four-spinor operators)."""
+    bl, bs, CL, CS = _prep(L, S, CL, CS)
+    n = CL.shape[2]
+    G = np.zeros((n, n, n, n, 4, 4))
+    sp = np.zeros((2 * n,) * 4 + (2,)) if return_spinor else None
+    im = ctypes.c_double(0.0)
+    rc = lib().orc_transform_def(bl.ref, bs.ref if bs else None, _dp(CL),
+                                 _dp(CS) if CS is not None else None, n, HAMS[ham], _dp(G),
+                                 _dp(sp) if sp is not None else None, ctypes.byref(im))
+    if rc != 0:
+        raise ValueError("orc_transform_def rejected the problem (too large or invalid)")
+    if return_spinor:
+        return G, sp[..., 0] + 1j * sp[..., 1], im.value
+    return G, im.value
+
+
+def transform_direct(L, S, CL, CS, ham: str = "LL", tau: float = 0.0, rows=(0, -1),
+                     second_half: bool = True):
+    """The paper's screened direct route.  Returns (G or None, stats dict)."""
+    bl, bs, CL, CS = _prep(L, S, CL, CS)
+    n = CL.shape[2]
+    G = np.zeros((n, n, n, n, 4, 4)) if second_half else None
+    st = Stats()
+    rc = lib().orc_transform_direct(bl.ref, bs.ref if bs else None, _dp(CL),
+                                    _dp(CS) if CS is not None else None, n, HAMS[ham],
+                                    float(tau), int(rows[0]), int(rows[1]),
+                                    1 if second_half else 0,
+                                    _dp(G) if G is not None else None, ctypes.byref(st))
+    if rc != 0:
+        raise ValueError("orc_transform_direct rejected its arguments")
+    return G, st.as_dict()
+
+
+def num_bra_pairs(L, S, ham: str) -> int:
+    bl = _B(L)
+    bs = _B(S) if S is not None else None
+    return int(lib().orc_num_bra_pairs(bl.ref, bs.ref if bs else None, HAMS[ham]))

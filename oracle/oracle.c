@@ -1,0 +1,744 @@
+/* oracle.c -- plain FP64 CPU oracle for the quaternion AO->MO two-electron
+ * integral transformation (TEST INFRASTRUCTURE ONLY; see oracle.h).
+ *
+ * Written for checkability, not speed: every quantity is computed from its
+ * textbook or paper definition with no blocking, fusion or reordering beyond
+ * what that definition states.  Complex arithmetic is C99 `double complex`.
+ *
+ * Paper references (arXiv 2606.04316):
+ *   Sec. 2, notation           alpha_K = [[0, sigma_K], [sigma_K, 0]] and the
+ *                              Pauli matrices as printed.
+ *   Eq. (breit)                Gaunt (magnetic) term -alpha_1 . alpha_2 / r12.
+ *   Eqs. (Lspinor), (Sspinor)  two-spinor expansions of the L and S parts.
+ *   Eq. (AOtoMO), (DCInt),     the MO integrals as sums over AO integrals and
+ *   (GauntInt)                 the L/S class decomposition.
+ *   Eq. (Den)                  density matrix D_{nu mu} = sum_i c*_{mu i} c_{nu i}.
+ *   Eq. (QuaternionScatter)    Pauli components D_s, D_x, D_y, D_z.
+ *   Eq. (firsthalf)            first-half contraction of AO integrals with
+ *                              pair densities.
+ *   Sec. 2.4.2, Eq. (secondhalf)  Pauli -> two-spinor block conversion and the
+ *                              two-spinor second half as two matrix products.
+ *   Eq. (SchwarzDen)           density-weighted Cauchy-Schwarz bound.
+ */
+#include "oracle.h"
+
+#include <complex.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include <time.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+typedef double complex cplx;
+
+/* ------------------------------------------------------------------------ */
+/* Boys function and AO integrals over s-type Gaussians                      */
+/* ------------------------------------------------------------------------ */
+
+/* F0(T) = int_0^1 exp(-T u^2) du = (1/2) sqrt(pi/T) erf(sqrt(T)); the first
+ * two terms of its Taylor series are used where T is too small for the
+ * closed form to be evaluated (T = 0 for concentric charge distributions). */
+double orc_boys0(double T)
+{
+    if (T < 1e-12) return 1.0 - T / 3.0;
+    return 0.5 * sqrt(M_PI / T) * erf(sqrt(T));
+}
+
+static int64_t *prim_offsets(const orc_basis *b)
+{
+    int64_t *off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(b->nfunc + 1));
+    off[0] = 0;
+    for (int f = 0; f < b->nfunc; ++f) off[f + 1] = off[f] + b->nprim[f];
+    return off;
+}
+
+/* Normalized primitive: (2a/pi)^{3/4} exp(-a r^2).  Overlap of two
+ * unnormalized s primitives on one centre: (pi/(a+b))^{3/2}. */
+void orc_norm_coefs(const orc_basis *b, double *out)
+{
+    int64_t *off = prim_offsets(b);
+    for (int f = 0; f < b->nfunc; ++f) {
+        double s = 0.0;
+        for (int64_t i = off[f]; i < off[f + 1]; ++i)
+            for (int64_t j = off[f]; j < off[f + 1]; ++j) {
+                double di = b->coefs[i] * pow(2.0 * b->exps[i] / M_PI, 0.75);
+                double dj = b->coefs[j] * pow(2.0 * b->exps[j] / M_PI, 0.75);
+                s += di * dj * pow(M_PI / (b->exps[i] + b->exps[j]), 1.5);
+            }
+        for (int64_t i = off[f]; i < off[f + 1]; ++i)
+            out[i] = b->coefs[i] * pow(2.0 * b->exps[i] / M_PI, 0.75) / sqrt(s);
+    }
+    free(off);
+}
+
+/* Primitive ERI over unnormalized s Gaussians exp(-a|r-A|^2) ... :
+ * [ab|cd] = 2 pi^{5/2} / (p q sqrt(p+q)) K_ab K_cd F0(p q/(p+q) |P-Q|^2),
+ * p = a+b, P = (aA+bB)/p, K_ab = exp(-ab/p |A-B|^2). */
+static double prim_eri(double a, const double *A, double b, const double *B, double c,
+                       const double *C, double d, const double *D)
+{
+    double p = a + b, q = c + d;
+    double rab2 = 0, rcd2 = 0, rpq2 = 0;
+    for (int k = 0; k < 3; ++k) {
+        double P = (a * A[k] + b * B[k]) / p;
+        double Q = (c * C[k] + d * D[k]) / q;
+        rab2 += (A[k] - B[k]) * (A[k] - B[k]);
+        rcd2 += (C[k] - D[k]) * (C[k] - D[k]);
+        rpq2 += (P - Q) * (P - Q);
+    }
+    double T = p * q / (p + q) * rpq2;
+    return 2.0 * pow(M_PI, 2.5) / (p * q * sqrt(p + q)) * exp(-a * b / p * rab2) *
+           exp(-c * d / q * rcd2) * orc_boys0(T);
+}
+
+/* Contracted ERI with per-basis normalized coefficient arrays. */
+static double eri4(const orc_basis *A, const double *nA, const int64_t *oA, int i,
+                   const orc_basis *B, const double *nB, const int64_t *oB, int j,
+                   const orc_basis *C, const double *nC, const int64_t *oC, int k,
+                   const orc_basis *D, const double *nD, const int64_t *oD, int l)
+{
+    double s = 0.0;
+    for (int64_t pi = oA[i]; pi < oA[i + 1]; ++pi)
+        for (int64_t pj = oB[j]; pj < oB[j + 1]; ++pj)
+            for (int64_t pk = oC[k]; pk < oC[k + 1]; ++pk)
+                for (int64_t pl = oD[l]; pl < oD[l + 1]; ++pl)
+                    s += nA[pi] * nB[pj] * nC[pk] * nD[pl] *
+                         prim_eri(A->exps[pi], A->centers + 3 * i, B->exps[pj],
+                                  B->centers + 3 * j, C->exps[pk], C->centers + 3 * k,
+                                  D->exps[pl], D->centers + 3 * l);
+    return s;
+}
+
+typedef struct {
+    const orc_basis *b;
+    double *nc;
+    int64_t *off;
+} nbasis;
+
+static nbasis nb_make(const orc_basis *b)
+{
+    nbasis r;
+    r.b = b;
+    int64_t *off = prim_offsets(b);
+    r.off = off;
+    r.nc = (double *)malloc(sizeof(double) * (size_t)(off[b->nfunc] > 0 ? off[b->nfunc] : 1));
+    orc_norm_coefs(b, r.nc);
+    return r;
+}
+
+static void nb_free(nbasis *r)
+{
+    free(r->nc);
+    free(r->off);
+}
+
+static double nb_eri(const nbasis *A, int i, const nbasis *B, int j, const nbasis *C, int k,
+                     const nbasis *D, int l)
+{
+    return eri4(A->b, A->nc, A->off, i, B->b, B->nc, B->off, j, C->b, C->nc, C->off, k, D->b,
+                D->nc, D->off, l);
+}
+
+double orc_eri(const orc_basis *A, int mu, int nu, const orc_basis *B, int ka, int la)
+{
+    nbasis a = nb_make(A), b = nb_make(B);
+    double v = nb_eri(&a, mu, &a, nu, &b, ka, &b, la);
+    nb_free(&a);
+    nb_free(&b);
+    return v;
+}
+
+void orc_eri_tensor(const orc_basis *A, const orc_basis *B, const orc_basis *C,
+                    const orc_basis *D, double *out)
+{
+    nbasis a = nb_make(A), b = nb_make(B), c = nb_make(C), d = nb_make(D);
+    int NA = A->nfunc, NB = B->nfunc, NC = C->nfunc, ND = D->nfunc;
+#pragma omp parallel for schedule(dynamic)
+    for (int i = 0; i < NA; ++i)
+        for (int j = 0; j < NB; ++j)
+            for (int k = 0; k < NC; ++k)
+                for (int l = 0; l < ND; ++l)
+                    out[(((size_t)i * NB + j) * NC + k) * ND + l] =
+                        nb_eri(&a, i, &b, j, &c, k, &d, l);
+    nb_free(&a);
+    nb_free(&b);
+    nb_free(&c);
+    nb_free(&d);
+}
+
+void orc_schwarz(const orc_basis *A, const orc_basis *B, double *Q)
+{
+    nbasis a = nb_make(A), b = nb_make(B);
+#pragma omp parallel for schedule(dynamic)
+    for (int i = 0; i < A->nfunc; ++i)
+        for (int j = 0; j < B->nfunc; ++j)
+            Q[(size_t)i * B->nfunc + j] = sqrt(nb_eri(&a, i, &b, j, &a, i, &b, j));
+    nb_free(&a);
+    nb_free(&b);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Quaternions, the 2x2 spinor representation and Pauli matrices              */
+/* ------------------------------------------------------------------------ */
+
+/* Q(q) = q0 I + q1 (i sigma_z) + q2 (i sigma_y) + q3 (i sigma_x). */
+static void qrep(const double q[4], cplx M[2][2])
+{
+    M[0][0] = q[0] + I * q[1];
+    M[0][1] = q[2] + I * q[3];
+    M[1][0] = -q[2] + I * q[3];
+    M[1][1] = q[0] - I * q[1];
+}
+
+/* Pauli matrices as printed in Sec. 2: index 0 = x, 1 = y, 2 = z. */
+static const cplx *pauli(int K)
+{
+    static cplx s[3][2][2];
+    static int init = 0;
+    if (!init) {
+        s[0][0][0] = 0; s[0][0][1] = 1; s[0][1][0] = 1; s[0][1][1] = 0;
+        s[1][0][0] = 0; s[1][0][1] = -I; s[1][1][0] = I; s[1][1][1] = 0;
+        s[2][0][0] = 1; s[2][0][1] = 0; s[2][1][0] = 0; s[2][1][1] = -1;
+        init = 1;
+    }
+    return &s[K][0][0];
+}
+
+/* Two-spinor coefficients c[mu][tau][a] (a over 2n spinors) from planar
+ * quaternion C[4][N][n]: the columns of Q(C_{mu p}) are spinors 2p, 2p+1. */
+static cplx *spinor_coefs(int N, int n, const double *C)
+{
+    cplx *c = (cplx *)calloc((size_t)N * 2 * 2 * n, sizeof(cplx));
+    for (int mu = 0; mu < N; ++mu)
+        for (int p = 0; p < n; ++p) {
+            double q[4];
+            cplx M[2][2];
+            for (int z = 0; z < 4; ++z) q[z] = C[((size_t)z * N + mu) * n + p];
+            qrep(q, M);
+            for (int tau = 0; tau < 2; ++tau)
+                for (int s = 0; s < 2; ++s)
+                    c[((size_t)mu * 2 + tau) * 2 * n + 2 * p + s] = M[tau][s];
+        }
+    return c;
+}
+
+/* Quaternion component x of a Kramers block B[2][2] of a quantity that equals
+ * Q(g) for some quaternion g: g_x = (1/2) tr(Q(e_x)^dagger B).  Returns the
+ * real part; *im receives the imaginary part (zero in exact arithmetic). */
+static double qproject(int x, const cplx B[2][2], double *im)
+{
+    double e[4] = {0, 0, 0, 0};
+    cplx E[2][2];
+    e[x] = 1.0;
+    qrep(e, E);
+    cplx s = 0;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) s += conj(E[a][b]) * B[a][b];
+    s *= 0.5;
+    if (im) *im = cimag(s);
+    return creal(s);
+}
+
+/* G[p][q][r][s][x][y] = (1/4) sum conj(Q(e_x)_{a'b'}) conj(Q(e_y)_{c'd'})
+ *                        (2p+a', 2q+b' | 2r+c', 2s+d'). */
+static void project_G(int n, const cplx *sp, double *G, double *imag_max)
+{
+    int m = 2 * n;
+    double imx = 0.0;
+    cplx E[4][2][2];
+    for (int x = 0; x < 4; ++x) {
+        double e[4] = {0, 0, 0, 0};
+        e[x] = 1.0;
+        qrep(e, E[x]);
+    }
+    for (int p = 0; p < n; ++p)
+        for (int q = 0; q < n; ++q)
+            for (int r = 0; r < n; ++r)
+                for (int s = 0; s < n; ++s)
+                    for (int x = 0; x < 4; ++x)
+                        for (int y = 0; y < 4; ++y) {
+                            cplx acc = 0;
+                            for (int a = 0; a < 2; ++a)
+                                for (int b = 0; b < 2; ++b)
+                                    for (int c = 0; c < 2; ++c)
+                                        for (int d = 0; d < 2; ++d)
+                                            acc += conj(E[x][a][b]) * conj(E[y][c][d]) *
+                                                   sp[(((size_t)(2 * p + a) * m + 2 * q + b) * m +
+                                                       2 * r + c) * m + 2 * s + d];
+                            acc *= 0.25;
+                            if (fabs(cimag(acc)) > imx) imx = fabs(cimag(acc));
+                            G[(((((size_t)p * n + q) * n + r) * n + s) * 4 + x) * 4 + y] =
+                                creal(acc);
+                        }
+    if (imag_max) *imag_max = imx;
+}
+
+/* Quaternion product a*b. */
+static void qmul(const double a[4], const double b[4], double r[4])
+{
+    r[0] = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+    r[1] = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+    r[2] = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+    r[3] = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+}
+
+void orc_dmax_coulomb(int NA, const double *CA, int n, double *Dmax)
+{
+    for (int k = 0; k < NA; ++k)
+        for (int l = 0; l < NA; ++l) {
+            double m = 0.0;
+            for (int r = 0; r < n; ++r)
+                for (int t = 0; t < n; ++t) {
+                    double a[4], b[4], d[4];
+                    for (int z = 0; z < 4; ++z) {
+                        a[z] = CA[((size_t)z * NA + k) * n + r] * (z ? -1.0 : 1.0);
+                        b[z] = CA[((size_t)z * NA + l) * n + t];
+                    }
+                    qmul(a, b, d);
+                    for (int z = 0; z < 4; ++z)
+                        if (fabs(d[z]) > m) m = fabs(d[z]);
+                }
+            Dmax[(size_t)k * NA + l] = m;
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Definition route: literal four-spinor operator matrices                     */
+/* ------------------------------------------------------------------------ */
+
+/* Four-spinor basis: each scalar function f of the combined list F = L (+ S)
+ * carries two four-component basis spinors; L functions occupy components
+ * 0,1 (alpha, beta of the large part), S functions components 2,3.
+ * c4[f][w][a] is the coefficient of spinor a on basis spinor (f, w). */
+int orc_transform_def(const orc_basis *L, const orc_basis *S, const double *CL,
+                      const double *CS, int n, int ham, double *G, double *spinor_out,
+                      double *imag_max)
+{
+    int with_S = (ham != 0);
+    if (with_S && (!S || !CS)) return -1;
+    int NL = L->nfunc, NS = with_S ? S->nfunc : 0, NF = NL + NS, m = 2 * n;
+    if (NF > 64 || m > 64 || n <= 0) return -1;
+
+    /* combined scalar basis */
+    nbasis bl = nb_make(L), bs;
+    if (with_S) bs = nb_make(S);
+    const nbasis **fb = (const nbasis **)malloc(sizeof(nbasis *) * NF);
+    int *fi = (int *)malloc(sizeof(int) * NF);
+    for (int f = 0; f < NF; ++f) {
+        fb[f] = f < NL ? &bl : &bs;
+        fi[f] = f < NL ? f : f - NL;
+    }
+    size_t nf2 = (size_t)NF * NF;
+    double *eri = (double *)malloc(sizeof(double) * nf2 * nf2);
+#pragma omp parallel for schedule(dynamic)
+    for (int i = 0; i < NF; ++i)
+        for (int j = 0; j < NF; ++j)
+            for (int k = 0; k < NF; ++k)
+                for (int l = 0; l < NF; ++l)
+                    eri[((size_t)i * NF + j) * nf2 + (size_t)k * NF + l] =
+                        nb_eri(fb[i], fi[i], fb[j], fi[j], fb[k], fi[k], fb[l], fi[l]);
+
+    cplx *cl = spinor_coefs(NL, n, CL);
+    cplx *cs = with_S ? spinor_coefs(NS, n, CS) : NULL;
+    cplx *c4 = (cplx *)calloc((size_t)NF * 4 * m, sizeof(cplx));
+    for (int f = 0; f < NF; ++f)
+        for (int tau = 0; tau < 2; ++tau)
+            for (int a = 0; a < m; ++a) {
+                if (f < NL)
+                    c4[((size_t)f * 4 + tau) * m + a] = cl[((size_t)f * 2 + tau) * m + a];
+                else
+                    c4[((size_t)f * 4 + 2 + tau) * m + a] =
+                        cs[((size_t)(f - NL) * 2 + tau) * m + a];
+            }
+
+    /* operator list: (weight, 4x4 matrix) */
+    cplx ops[4][4][4];
+    double w[4];
+    int nops = 0;
+    if (ham != 3) { /* Coulomb: identity */
+        memset(ops[nops], 0, sizeof(ops[nops]));
+        for (int d = 0; d < 4; ++d) ops[nops][d][d] = 1;
+        w[nops++] = 1.0;
+    }
+    if (ham >= 2) { /* Gaunt: -sum_K alpha_K x alpha_K */
+        for (int K = 0; K < 3; ++K) {
+            const cplx *sg = pauli(K);
+            memset(ops[nops], 0, sizeof(ops[nops]));
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                    ops[nops][a][2 + b] = sg[a * 2 + b];
+                    ops[nops][2 + a][b] = sg[a * 2 + b];
+                }
+            w[nops++] = -1.0;
+        }
+    }
+
+    size_t m2 = (size_t)m * m;
+    cplx *sp = (cplx *)calloc(m2 * m2, sizeof(cplx));
+    cplx *T = (cplx *)malloc(sizeof(cplx) * nf2 * m2);
+    cplx *X = (cplx *)malloc(sizeof(cplx) * nf2 * m2);
+    for (int o = 0; o < nops; ++o) {
+        /* T_{ij,ab} = sum_{w,w'} conj(c4[i][w][a]) O[w][w'] c4[j][w'][b] */
+#pragma omp parallel for schedule(static)
+        for (int i = 0; i < NF; ++i)
+            for (int j = 0; j < NF; ++j)
+                for (int a = 0; a < m; ++a)
+                    for (int b = 0; b < m; ++b) {
+                        cplx s = 0;
+                        for (int u = 0; u < 4; ++u)
+                            for (int v = 0; v < 4; ++v)
+                                s += conj(c4[((size_t)i * 4 + u) * m + a]) * ops[o][u][v] *
+                                     c4[((size_t)j * 4 + v) * m + b];
+                        T[((size_t)i * NF + j) * m2 + (size_t)a * m + b] = s;
+                    }
+        /* X_{ij,cd} = sum_{kl} (ij|kl) T_{kl,cd} */
+#pragma omp parallel for schedule(static)
+        for (size_t ij = 0; ij < nf2; ++ij) {
+            for (size_t cd = 0; cd < m2; ++cd) X[ij * m2 + cd] = 0;
+            for (size_t kl = 0; kl < nf2; ++kl) {
+                double e = eri[ij * nf2 + kl];
+                for (size_t cd = 0; cd < m2; ++cd) X[ij * m2 + cd] += e * T[kl * m2 + cd];
+            }
+        }
+        /* (ab|cd) += w sum_{ij} T_{ij,ab} X_{ij,cd} */
+#pragma omp parallel for schedule(static)
+        for (size_t ab = 0; ab < m2; ++ab)
+            for (size_t ij = 0; ij < nf2; ++ij) {
+                cplx t = w[o] * T[ij * m2 + ab];
+                for (size_t cd = 0; cd < m2; ++cd) sp[ab * m2 + cd] += t * X[ij * m2 + cd];
+            }
+    }
+    project_G(n, sp, G, imag_max);
+    if (spinor_out) memcpy(spinor_out, sp, sizeof(cplx) * m2 * m2);
+
+    free(sp);
+    free(T);
+    free(X);
+    free(c4);
+    free(cl);
+    free(cs);
+    free(eri);
+    free(fb);
+    free(fi);
+    nb_free(&bl);
+    if (with_S) nb_free(&bs);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The paper's direct route                                                   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int cls;   /* 0 = LL, 1 = SS, 2 = LS (mu in L, nu in S) */
+    int mu, nu;
+} opair;
+
+static double now_s(void)
+{
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return ts.tv_sec + 1e-9 * ts.tv_nsec;
+}
+
+int64_t orc_num_bra_pairs(const orc_basis *L, const orc_basis *S, int ham)
+{
+    int64_t NL = L->nfunc, NS = (S && ham != 0) ? S->nfunc : 0;
+    int64_t np = 0;
+    if (ham != 3) np += NL * (NL + 1) / 2 + NS * (NS + 1) / 2;
+    if (ham >= 2) np += NL * NS;
+    return np;
+}
+
+/* Pauli-scalar pair density of spinor pair (c,d), Eqs. (Den) and
+ * (QuaternionScatter): D_s = D_aa + D_bb with D_{lambda kappa} = c*_kappa c_lambda. */
+static cplx dens_s(const cplx *cx, int m, int ka, int la, int c, int d)
+{
+    cplx s = 0;
+    for (int tau = 0; tau < 2; ++tau)
+        s += conj(cx[((size_t)ka * 2 + tau) * m + c]) * cx[((size_t)la * 2 + tau) * m + d];
+    return s;
+}
+
+/* Pauli-vector pair density (component K) of the L-S product distribution
+ * chi^L_ka chi^S_la for spinor pair (c,d): the sigma_K-weighted density of both
+ * L-S orderings of the four-spinor product psi_c^dagger alpha_K psi_d. */
+static cplx dens_gaunt(const cplx *cl, const cplx *cs, int m, int K, int ka, int la, int c,
+                       int d)
+{
+    const cplx *sg = pauli(K);
+    cplx s = 0;
+    for (int t1 = 0; t1 < 2; ++t1)
+        for (int t2 = 0; t2 < 2; ++t2) {
+            cplx sk = sg[t1 * 2 + t2];
+            if (sk == 0) continue;
+            s += conj(cl[((size_t)ka * 2 + t1) * m + c]) * sk * cs[((size_t)la * 2 + t2) * m + d];
+            s += conj(cs[((size_t)la * 2 + t1) * m + c]) * sk * cl[((size_t)ka * 2 + t2) * m + d];
+        }
+    return s;
+}
+
+int orc_transform_direct(const orc_basis *L, const orc_basis *S, const double *CL,
+                         const double *CS, int n, int ham, double tau, int64_t row0,
+                         int64_t row1, int do_second, double *G, orc_stats *st)
+{
+    int with_S = (ham != 0);
+    if (with_S && (!S || !CS)) return -1;
+    if (n <= 0 || tau < 0 || ham < 0 || ham > 3) return -1;
+    int NL = L->nfunc, NS = with_S ? S->nfunc : 0, m = 2 * n;
+    size_t m2 = (size_t)m * m;
+    int coul = (ham != 3), gaunt = (ham >= 2);
+
+    nbasis bl = nb_make(L), bs;
+    if (with_S) bs = nb_make(S);
+    cplx *cl = spinor_coefs(NL, n, CL);
+    cplx *cs = with_S ? spinor_coefs(NS, n, CS) : NULL;
+
+    /* bra/ket pair lists */
+    int64_t nLL = (int64_t)NL * (NL + 1) / 2, nSS = (int64_t)NS * (NS + 1) / 2;
+    int64_t nLS = gaunt ? (int64_t)NL * NS : 0;
+    int64_t np = (coul ? nLL + nSS : 0) + nLS;
+    opair *pl = (opair *)malloc(sizeof(opair) * (size_t)(np > 0 ? np : 1));
+    int64_t k = 0;
+    if (coul) {
+        for (int nu = 0; nu < NL; ++nu)
+            for (int mu = 0; mu <= nu; ++mu) pl[k++] = (opair){0, mu, nu};
+        for (int nu = 0; nu < NS; ++nu)
+            for (int mu = 0; mu <= nu; ++mu) pl[k++] = (opair){1, mu, nu};
+    }
+    for (int mu = 0; mu < NL && gaunt; ++mu)
+        for (int nu = 0; nu < NS; ++nu) pl[k++] = (opair){2, mu, nu};
+    if (row1 < 0 || row1 > np) row1 = np;
+    if (row0 < 0) row0 = 0;
+    if (row0 > row1) row0 = row1;
+
+    /* Schwarz factors Q = sqrt((mn|mn)) of each pair, Eq. (SchwarzDen) */
+    double *Q = (double *)malloc(sizeof(double) * (size_t)(np > 0 ? np : 1));
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < np; ++i) {
+        const nbasis *A = pl[i].cls == 1 ? &bs : &bl;
+        const nbasis *B = pl[i].cls == 0 ? &bl : &bs;
+        Q[i] = sqrt(nb_eri(A, pl[i].mu, B, pl[i].nu, A, pl[i].mu, B, pl[i].nu));
+    }
+
+    /* Density bound per ket pair: infinity norm over all MO pairs (r,t) of the
+     * quaternion pair density, read off the spinor-pair densities of each
+     * Kramers block (Coulomb: D_s; Gaunt: the sigma_K densities, which equal
+     * -i Q(D^K)). */
+    double *Dmax = (double *)malloc(sizeof(double) * (size_t)(np > 0 ? np : 1));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < np; ++i) {
+        double mx = 0.0;
+        const opair P = pl[i];
+        for (int r = 0; r < n; ++r)
+            for (int t = 0; t < n; ++t) {
+                int nK = P.cls == 2 ? 3 : 1;
+                for (int K = 0; K < nK; ++K)
+                    for (int orient = 0; orient < (P.cls == 2 ? 1 : 2); ++orient) {
+                        cplx B[2][2];
+                        for (int a = 0; a < 2; ++a)
+                            for (int b = 0; b < 2; ++b) {
+                                if (P.cls == 2) {
+                                    B[a][b] = I * dens_gaunt(cl, cs, m, K, P.mu, P.nu, 2 * r + a,
+                                                             2 * t + b);
+                                } else {
+                                    const cplx *cx = P.cls == 0 ? cl : cs;
+                                    int ka = orient ? P.nu : P.mu, la = orient ? P.mu : P.nu;
+                                    B[a][b] = dens_s(cx, m, ka, la, 2 * r + a, 2 * t + b);
+                                }
+                            }
+                        for (int x = 0; x < 4; ++x) {
+                            double v = fabs(qproject(x, B, NULL));
+                            if (v > mx) mx = v;
+                        }
+                    }
+            }
+        Dmax[i] = mx;
+    }
+
+    /* First half, Eq. (firsthalf): V_{mn,cd} = sum_{kl kept} (mn|kl) D_{kl,cd},
+     * complex spinor-pair columns (c,d); ket pairs are unordered, so both
+     * orderings (kl) and (lk) of the Coulomb density enter. */
+    int64_t nrow = row1 - row0;
+    int nvK = gaunt ? 3 : 1;
+    cplx *V = (cplx *)calloc((size_t)(nrow > 0 ? nrow : 1) * nvK * m2, sizeof(cplx));
+    int64_t kept[4] = {0, 0, 0, 0}, total[4] = {0, 0, 0, 0}, keptG = 0, totalG = 0, ties = 0;
+    double t0 = now_s();
+    int nthreads = 1;
+#pragma omp parallel
+    {
+#ifdef _OPENMP
+#pragma omp single
+        nthreads = omp_get_num_threads();
+#endif
+        cplx *Dk = (cplx *)malloc(sizeof(cplx) * 3 * m2);
+        int64_t lk[4] = {0, 0, 0, 0}, lt[4] = {0, 0, 0, 0}, lkG = 0, ltG = 0, lties = 0;
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t i = row0; i < row1; ++i) {
+            const opair B = pl[i];
+            cplx *Vi = V + (size_t)(i - row0) * nvK * m2;
+            const nbasis *bA = B.cls == 1 ? &bs : &bl;
+            const nbasis *bB = B.cls == 0 ? &bl : &bs;
+            for (int64_t j = 0; j < np; ++j) {
+                const opair Kp = pl[j];
+                if ((B.cls == 2) != (Kp.cls == 2)) continue; /* Coulomb and Gaunt never mix */
+                int cp = (B.cls == 2) ? -1 : B.cls * 2 + Kp.cls;
+                if (cp >= 0) lt[cp]++;
+                else ltG++;
+                double bound = Q[i] * Q[j] * Dmax[j];
+                if (tau > 0 && fabs(bound / tau - 1.0) < 1e-12) lties++;
+                if (!(bound >= tau)) continue;
+                if (cp >= 0) lk[cp]++;
+                else lkG++;
+                const nbasis *kA = Kp.cls == 1 ? &bs : &bl;
+                const nbasis *kB = Kp.cls == 0 ? &bl : &bs;
+                double e = nb_eri(bA, B.mu, bB, B.nu, kA, Kp.mu, kB, Kp.nu);
+                if (Kp.cls == 2) {
+                    for (int K = 0; K < 3; ++K)
+                        for (int c = 0; c < m; ++c)
+                            for (int d = 0; d < m; ++d)
+                                Vi[(size_t)K * m2 + (size_t)c * m + d] +=
+                                    e * dens_gaunt(cl, cs, m, K, Kp.mu, Kp.nu, c, d);
+                } else {
+                    const cplx *cx = Kp.cls == 0 ? cl : cs;
+                    for (int c = 0; c < m; ++c)
+                        for (int d = 0; d < m; ++d) {
+                            cplx D = dens_s(cx, m, Kp.mu, Kp.nu, c, d);
+                            if (Kp.mu != Kp.nu) D += dens_s(cx, m, Kp.nu, Kp.mu, c, d);
+                            Vi[(size_t)c * m + d] += e * D;
+                        }
+                }
+            }
+        }
+#pragma omp critical
+        {
+            for (int c = 0; c < 4; ++c) {
+                kept[c] += lk[c];
+                total[c] += lt[c];
+            }
+            keptG += lkG;
+            totalG += ltG;
+            ties += lties;
+        }
+        free(Dk);
+    }
+    double t1 = now_s();
+
+    if (do_second && G) {
+        /* Second half, Sec. 2.4.2: the Pauli components of V are converted to
+         * 2x2 spin blocks V^{t1 t2} (Coulomb: V_s on the diagonal; Gaunt:
+         * -sum_K sigma_K[t1][t2] V_K, the minus sign of -alpha.alpha), then
+         * contracted with two-spinor coefficients, Eq. (secondhalf), as two
+         * matrix products:  W[mu][t1][b][cd] = sum_{nu,t2} c_{nu t2,b} V^{t1 t2}_{mu nu,cd},
+         * (ab|cd) = sum_{mu,t1} conj(c_{mu t1,a}) W[mu][t1][b][cd]. */
+        cplx *sp = (cplx *)calloc(m2 * m2, sizeof(cplx));
+        for (int cls = 0; cls < 3; ++cls) {
+            if (cls == 2 && !gaunt) continue;
+            if (cls < 2 && !coul) continue;
+            if (cls == 1 && !with_S) continue;
+            /* orientations: for LS pairs the bra product chi^L_mu chi^S_nu enters
+             * as (L on the conjugated side, S unconjugated) and the reverse. */
+            for (int orient = 0; orient < (cls == 2 ? 2 : 1); ++orient) {
+                int NA, NB;
+                const cplx *ca, *cb;
+                if (cls == 0) { NA = NB = NL; ca = cb = cl; }
+                else if (cls == 1) { NA = NB = NS; ca = cb = cs; }
+                else if (orient == 0) { NA = NL; NB = NS; ca = cl; cb = cs; }
+                else { NA = NS; NB = NL; ca = cs; cb = cl; }
+                cplx *W = (cplx *)calloc((size_t)NA * 2 * m * m2, sizeof(cplx));
+#pragma omp parallel for schedule(dynamic, 1)
+                for (int mu = 0; mu < NA; ++mu) {
+                    for (int nu = 0; nu < NB; ++nu) {
+                        /* locate the stored (unordered / LS) pair row */
+                        int64_t idx;
+                        if (cls == 0) {
+                            int a = mu < nu ? mu : nu, b = mu < nu ? nu : mu;
+                            idx = (int64_t)b * (b + 1) / 2 + a;
+                        } else if (cls == 1) {
+                            int a = mu < nu ? mu : nu, b = mu < nu ? nu : mu;
+                            idx = nLL + (int64_t)b * (b + 1) / 2 + a;
+                        } else {
+                            int lmu = orient == 0 ? mu : nu, snu = orient == 0 ? nu : mu;
+                            idx = (coul ? nLL + nSS : 0) + (int64_t)lmu * NS + snu;
+                        }
+                        if (idx < row0 || idx >= row1) continue;
+                        const cplx *Vr = V + (size_t)(idx - row0) * nvK * m2;
+                        for (int t1 = 0; t1 < 2; ++t1)
+                            for (int t2 = 0; t2 < 2; ++t2) {
+                                /* spin block weight per Pauli component */
+                                cplx wK[3] = {0, 0, 0};
+                                cplx ws = 0;
+                                if (cls < 2) {
+                                    if (t1 != t2) continue;
+                                    ws = 1.0;
+                                } else {
+                                    for (int K = 0; K < 3; ++K) wK[K] = -pauli(K)[t1 * 2 + t2];
+                                    if (wK[0] == 0 && wK[1] == 0 && wK[2] == 0) continue;
+                                }
+                                for (int b = 0; b < m; ++b) {
+                                    cplx cbv = cb[((size_t)nu * 2 + t2) * m + b];
+                                    cplx *Wrow = W + (((size_t)mu * 2 + t1) * m + b) * m2;
+                                    if (cls < 2) {
+                                        cplx f = ws * cbv;
+                                        for (size_t cd = 0; cd < m2; ++cd) Wrow[cd] += f * Vr[cd];
+                                    } else {
+                                        for (int K = 0; K < 3; ++K) {
+                                            if (wK[K] == 0) continue;
+                                            cplx f = wK[K] * cbv;
+                                            const cplx *VK = Vr + (size_t)K * m2;
+                                            for (size_t cd = 0; cd < m2; ++cd) Wrow[cd] += f * VK[cd];
+                                        }
+                                    }
+                                }
+                            }
+                    }
+                }
+#pragma omp parallel for schedule(static)
+                for (int a = 0; a < m; ++a)
+                    for (int mu = 0; mu < NA; ++mu)
+                        for (int t1 = 0; t1 < 2; ++t1) {
+                            cplx ca_ = conj(ca[((size_t)mu * 2 + t1) * m + a]);
+                            if (ca_ == 0) continue;
+                            for (int b = 0; b < m; ++b) {
+                                const cplx *Wrow = W + (((size_t)mu * 2 + t1) * m + b) * m2;
+                                cplx *out = sp + ((size_t)a * m + b) * m2;
+                                for (size_t cd = 0; cd < m2; ++cd) out[cd] += ca_ * Wrow[cd];
+                            }
+                        }
+                free(W);
+            }
+        }
+        project_G(n, sp, G, NULL);
+        free(sp);
+    }
+    double t2 = now_s();
+
+    if (st) {
+        memset(st, 0, sizeof(*st));
+        for (int c = 0; c < 4; ++c) {
+            st->kept[c] = kept[c];
+            st->total[c] = total[c];
+        }
+        st->kept_gaunt = keptG;
+        st->total_gaunt = totalG;
+        st->tie_band = ties;
+        st->seconds_first_half = t1 - t0;
+        st->seconds_second_half = t2 - t1;
+        st->threads = nthreads;
+    }
+    free(V);
+    free(Q);
+    free(Dmax);
+    free(pl);
+    free(cl);
+    free(cs);
+    nb_free(&bl);
+    if (with_S) nb_free(&bs);
+    return 0;
+}

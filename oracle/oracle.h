@@ -1,0 +1,108 @@
+/* oracle.h -- plain FP64 CPU oracle for the quaternion AO->MO two-electron
+ * integral transformation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the correctness reference that
+ * the GPU path is compared against.  It shares no code with the GPU library;
+ * only the tests, the smoke check and the benchmark's CPU-baseline leg may
+ * load it.  Nothing in the product path calls it.
+ *
+ * Conventions (all arrays C-contiguous, FP64 unless stated):
+ *   basis     s-type contracted Gaussians; coefs multiply normalized
+ *             primitives (2a/pi)^{3/4} exp(-a r^2); each contracted function
+ *             is rescaled to unit self-overlap.
+ *   C         quaternion MO coefficients, planar [4][N][n]:
+ *             C = C0 + i C1 + j C2 + k C3.
+ *   G         quaternion MO integrals [n][n][n][n][4][4] = G^{xy}_{pqrs}
+ *             (x: bra quaternion component, y: ket component).
+ *   spinors   quaternion MO p is the Kramers pair (2p, 2p+1); its two-spinor
+ *             coefficients are the columns of the 2x2 complex matrix
+ *             Q(q) = [[q0 + i q1, q2 + i q3], [-q2 + i q3, q0 - i q1]]
+ *             with rows alpha, beta.
+ *   ham       0 = LL (large-component Coulomb only), 1 = DC (all four L/S
+ *             Coulomb classes), 2 = DCG (DC + Gaunt), 3 = Gaunt term alone.
+ */
+#ifndef QDCB_ORACLE_H
+#define QDCB_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t nfunc;
+    const double *centers; /* [nfunc][3] */
+    const int32_t *nprim;  /* [nfunc] */
+    const double *exps;    /* [sum nprim] */
+    const double *coefs;   /* [sum nprim] */
+} orc_basis;
+
+typedef struct {
+    int64_t kept[4];     /* kept directed pair contributions: LL<-LL, LL<-SS, SS<-LL, SS<-SS */
+    int64_t total[4];    /* all directed pair contributions of those class pairs */
+    int64_t kept_gaunt;  /* LS<-LS */
+    int64_t total_gaunt;
+    int64_t tie_band;    /* |Q Q Dmax / tau - 1| < 1e-12 */
+    double seconds_first_half;
+    double seconds_second_half;
+    int32_t threads;
+} orc_stats;
+
+/* Boys function F0(T) = int_0^1 exp(-T u^2) du. */
+double orc_boys0(double T);
+
+/* Coefficients multiplying the unnormalized primitives exp(-a r^2) so that
+ * each contracted function has unit norm; out has sum(nprim) entries. */
+void orc_norm_coefs(const orc_basis *b, double *out);
+
+/* Contracted ERI (mu nu | ka la) in chemists' notation; mu, nu index basis A,
+ * ka, la index basis B. */
+double orc_eri(const orc_basis *A, int mu, int nu, const orc_basis *B, int ka, int la);
+
+/* Full tensor out[i][j][k][l] = (i^A j^B | k^C l^D). */
+void orc_eri_tensor(const orc_basis *A, const orc_basis *B, const orc_basis *C,
+                    const orc_basis *D, double *out);
+
+/* Schwarz factors Q[mu][nu] = sqrt((mu^A nu^B | mu^A nu^B)), [NA][NB]. */
+void orc_schwarz(const orc_basis *A, const orc_basis *B, double *Q);
+
+/* Density bound Dmax[ka][la] = max over all ordered quaternion MO pairs (r,t)
+ * and components y of |[conj(C^A_{ka r}) e C^B_{la t}]_y| where e = 1
+ * (Coulomb, A = B) -- i.e. the infinity norm over all MO pairs of the
+ * quaternion pair density. */
+void orc_dmax_coulomb(int NA, const double *CA, int n, double *Dmax);
+
+/* Definition route (unscreened): four-spinor integrals built from the literal
+ * 4x4 operator matrices (identity for Coulomb, alpha_K for Gaunt) and
+ * projected onto the quaternion basis.  spinor_out (nullable) receives the
+ * complex spinor integrals (ab|cd) as interleaved re/im, [2n]^4 x 2.
+ * imag_max (nullable) receives the largest |imaginary part| met in the
+ * projection.  Returns 0, or -1 when the problem is too large for it. */
+int orc_transform_def(const orc_basis *L, const orc_basis *S, const double *CL,
+                      const double *CS, int n, int ham, double *G, double *spinor_out,
+                      double *imag_max);
+
+/* The paper's direct route: quaternion (Pauli scalar / vector) pair densities
+ * in two-spinor arithmetic, density-weighted Cauchy-Schwarz screening per
+ * directed pair contribution, first-half contraction, conversion and
+ * second-half two-spinor contraction, projected onto the quaternion basis.
+ *   tau         screening threshold; a contribution (mu nu <- ka la) is kept
+ *               iff (Q_mn * Q_kl) * Dmax_kl >= tau.
+ *   row0,row1   restrict the bra pairs to the half-open range [row0,row1) of
+ *               the concatenated bra pair list (LL pairs, then SS pairs, then
+ *               LS pairs); pass 0,-1 for all.
+ *   do_second   0 = stop after the first half (timing samples), G untouched.
+ *   G           output (when do_second); only bra pairs in range contribute.
+ * Returns 0, or -1 on invalid arguments. */
+int orc_transform_direct(const orc_basis *L, const orc_basis *S, const double *CL,
+                         const double *CS, int n, int ham, double tau, int64_t row0,
+                         int64_t row1, int do_second, double *G, orc_stats *st);
+
+/* Number of bra pairs of the concatenated list for this ham. */
+int64_t orc_num_bra_pairs(const orc_basis *L, const orc_basis *S, int ham);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
