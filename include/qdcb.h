@@ -1,0 +1,163 @@
+/* qdcb.h -- C ABI of the MI355X quaternion Dirac-Coulomb(-Breit) AO->MO
+ * two-electron integral transformation (arXiv 2606.04316).
+ *
+ * The library implements the paper's AO-driven direct transformation
+ * (Sec. 2.4): scalar AO two-electron integrals over s-type contracted
+ * Gaussians are generated on the GPU, filtered by the quaternion-density-
+ * weighted Cauchy-Schwarz bound (Sec. 2.5, Eq. SchwarzDen), contracted with
+ * quaternion MO-pair densities in the first half (Eq. firsthalf, Eqs. Den and
+ * QuaternionScatter) and with the MO coefficients in the second half
+ * (Sec. 2.4.2, Eq. secondhalf).  The result is the quaternion MO integral
+ * tensor (pq|rs) of the Dirac-Coulomb classes of Eq. (DCInt) and, for the
+ * DCG Hamiltonian, the Gaunt classes of Eq. (GauntInt).
+ *
+ * Conventions
+ *   - All functions return a qdcb_status; 0 is success, negative is an error.
+ *     On error no output buffer has been written and qdcb_last_error()
+ *     returns a message for the calling thread.  No C++ exception crosses
+ *     this boundary.
+ *   - Basis: s-type contracted Gaussians.  coefs multiply normalized
+ *     primitives (2a/pi)^{3/4} exp(-a r^2); the library rescales every
+ *     contracted function to unit self-overlap.  Bohr units.
+ *   - MO coefficients (Eqs. Lspinor, Sspinor in the Kramers-paired quaternion
+ *     form): planar float64 [4][N][n_mo], C = C0 + i C1 + j C2 + k C3.
+ *     Quaternion MO p stands for the Kramers pair of two-spinors given by the
+ *     columns of Q(C) = [[C0 + i C1, C2 + i C3], [-C2 + i C3, C0 - i C1]].
+ *   - Output G: float64 [n][n][n][n][4][4]; G[p][q][r][s][x][y] is component
+ *     x (bra) and y (ket) of the quaternion MO integral
+ *       G^{xy}_{pqrs} = sum [conj(C_mu p) C_nu q]_x (mu nu|ka la) [conj(C_ka r) C_la s]_y
+ *     summed over the integral classes of the Hamiltonian.  The 16 spinor
+ *     integrals of the Kramers block are (ab|cd) = sum_xy G^{xy} Q(e_x)_ab Q(e_y)_cd.
+ *   - Ownership: the caller owns every pointer it passes; the library copies
+ *     what it keeps.  Library objects own their device memory.
+ *   - Threading: a context may be shared between threads; a plan is used by
+ *     one thread at a time.
+ */
+#ifndef QDCB_H
+#define QDCB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QDCB_ABI_VERSION 1
+
+typedef enum {
+    QDCB_OK = 0,
+    QDCB_E_INVALID = -1,     /* bad argument (non-finite input, exponent <= 0, sizes) */
+    QDCB_E_NOMEM = -2,       /* device memory budget exceeded */
+    QDCB_E_DEVICE = -3,      /* HIP runtime error */
+    QDCB_E_UNSUPPORTED = -4  /* valid request this build does not implement */
+} qdcb_status;
+
+typedef enum {
+    QDCB_HAM_LL = 0,  /* (LL|LL) only: the nonrelativistic-like large-component block */
+    QDCB_HAM_DC = 1,  /* Dirac-Coulomb, Eq. (DCInt): LL|LL + LL|SS + SS|LL + SS|SS */
+    QDCB_HAM_DCG = 2  /* DC plus the Gaunt term, Eqs. (breit) and (GauntInt) */
+} qdcb_ham;
+
+typedef enum { QDCB_PREC_FP64 = 0, QDCB_PREC_MIXED = 1 } qdcb_prec;
+
+/* transform flags */
+#define QDCB_PTR_DEVICE 0x1u /* CL, CS and G are device pointers (else host) */
+
+typedef struct qdcb_ctx qdcb_ctx;
+typedef struct qdcb_basis qdcb_basis;
+typedef struct qdcb_plan qdcb_plan;
+
+/* ABI version compiled into the library (QDCB_ABI_VERSION). */
+int qdcb_abi_version(void);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char *qdcb_last_error(void);
+
+/* Context bound to HIP device `device`; hbm_budget_bytes caps the device
+ * memory all plans of this context may hold (0 = 90% of the device). */
+qdcb_status qdcb_ctx_create(int device, size_t hbm_budget_bytes, qdcb_ctx **out);
+void qdcb_ctx_destroy(qdcb_ctx *ctx);
+
+/* s-type contracted basis (host arrays, copied).  centers [nfunc][3],
+ * nprim [nfunc] (>= 1), exps and coefs [sum nprim] with exps > 0.  Builds
+ * the primitive-pair data of all function pairs and the Schwarz factors
+ * Q_mn = sqrt((mn|mn)) (Eq. SchwarzDen) on the device; both stay resident
+ * for the basis's lifetime and are shared by every plan that uses it. */
+qdcb_status qdcb_basis_create(qdcb_ctx *ctx, int32_t nfunc, const double *centers,
+                              const int32_t *nprim, const double *exps, const double *coefs,
+                              qdcb_basis **out);
+void qdcb_basis_destroy(qdcb_basis *basis);
+
+/* Schwarz factors of the basis's own function pairs: Q[mu][nu] (host,
+ * [nfunc][nfunc], symmetric). */
+qdcb_status qdcb_basis_schwarz(const qdcb_basis *basis, double *Q);
+
+/* Contracted AO integrals (mu nu | ka la), mu, nu in basis A and ka, la in
+ * basis B, for nq quartets idx[q] = {mu, nu, ka, la} (host arrays), computed
+ * by the library's device integral code.  out: host [nq]. */
+qdcb_status qdcb_eri_quartets(const qdcb_basis *A, const qdcb_basis *B, int64_t nq,
+                              const int32_t *idx, double *out);
+
+typedef struct {
+    int32_t ham;       /* qdcb_ham */
+    int32_t prec;      /* qdcb_prec; QDCB_PREC_MIXED is not available yet */
+    int32_t n_mo;      /* number of quaternion MOs n (Kramers pairs) */
+    int32_t reserved;  /* 0 */
+    double tau;        /* Schwarz threshold: a directed contribution (mn <- kl) is
+                          kept iff (Q_mn * Q_kl) * Dmax_kl >= tau, Eq. (SchwarzDen) */
+    double tier_fp32;  /* mixed precision tier bounds (reserved) */
+    double tier_bf16;
+} qdcb_plan_desc;
+
+/* Plan for transforming with fixed bases and n_mo.  S must be NULL for
+ * QDCB_HAM_LL and non-NULL otherwise.  Orders the pairs by their Schwarz
+ * factor and allocates the per-transform device buffers. */
+qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basis *S,
+                             const qdcb_plan_desc *desc, qdcb_plan **out);
+void qdcb_plan_destroy(qdcb_plan *plan);
+
+/* Device bytes the plan holds (pair data excluded: it belongs to the bases). */
+qdcb_status qdcb_plan_footprint(const qdcb_plan *plan, size_t *bytes);
+
+typedef struct {
+    double ms_total;         /* wall time of the transform on its stream */
+    double ms_density;       /* pair densities + Dmax + tile bounds */
+    double ms_screen;        /* task lists */
+    double ms_eri;           /* AO integral tiles */
+    double ms_first_half;    /* integral-density contraction */
+    double ms_second_half;   /* MO-coefficient contraction and output */
+    int64_t kept[4];         /* kept directed pair contributions LL<-LL, LL<-SS, SS<-LL, SS<-SS */
+    int64_t total[4];        /* all directed pair contributions of the same class pairs */
+    int64_t kept_gaunt;      /* LS<-LS (DCG) */
+    int64_t total_gaunt;
+    int64_t tiles_kept;      /* kept (bra tile, ket tile) pairs */
+    int64_t tiles_total;
+    double flops_first_half; /* algorithmic: 2 * columns * kept contributions */
+    double flops_second_half;
+    double flops_mfma;       /* MFMA flops issued by the first-half kernel (incl. masked) */
+    int32_t n_batches;
+    int32_t pad;
+} qdcb_stats;
+
+/* Transform.  CL [4][N_L][n], CS [4][N_S][n] (NULL for LL), G [n^4][4][4];
+ * host or device pointers per QDCB_PTR_DEVICE.  Work is enqueued on
+ * hip_stream (a hipStream_t; NULL = the null stream); the call returns after
+ * G is complete.  stats may be NULL. */
+qdcb_status qdcb_transform(qdcb_plan *plan, const double *CL, const double *CS, double *G,
+                           uint32_t flags, void *hip_stream, qdcb_stats *stats);
+
+/* Intermediates of the plan's last transform, copied to host memory.
+ *   QDCB_FETCH_DMAX  float64 [P]: density bound Dmax of every Coulomb pair in
+ *                    canonical order (LL pairs mu <= nu by nu-major packing
+ *                    nu(nu+1)/2 + mu, then SS pairs likewise).
+ *   QDCB_FETCH_Q     float64 [P]: Schwarz factors in the same order. */
+#define QDCB_FETCH_DMAX 1
+#define QDCB_FETCH_Q 2
+qdcb_status qdcb_plan_fetch(const qdcb_plan *plan, int32_t what, void *host_out,
+                            size_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

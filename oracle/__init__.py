@@ -74,7 +74,7 @@ def lib():
         L.orc_transform_def.argtypes = [bp, bp, dp, dp, ctypes.c_int, ctypes.c_int, dp, dp, dp]
         L.orc_transform_direct.restype = ctypes.c_int
         L.orc_transform_direct.argtypes = [bp, bp, dp, dp, ctypes.c_int, ctypes.c_int,
-                                           ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
+                                           ctypes.c_double, ctypes.c_void_p, ctypes.c_int64,
                                            ctypes.c_int, dp, ctypes.POINTER(Stats)]
         L.orc_num_bra_pairs.restype = ctypes.c_int64
         L.orc_num_bra_pairs.argtypes = [bp, bp, ctypes.c_int]
@@ -170,16 +170,20 @@ def transform_def(L, S, CL, CS, ham: str = "LL", return_spinor: bool = False):
     return G, im.value
 
 
-def transform_direct(L, S, CL, CS, ham: str = "LL", tau: float = 0.0, rows=(0, -1),
+def transform_direct(L, S, CL, CS, ham: str = "LL", tau: float = 0.0, rows=None,
                      second_half: bool = True):
-    """The paper's screened direct route.  Returns (G or None, stats dict)."""
+    """The paper's screened direct route.  ``rows`` optionally restricts the
+    bra pairs (indices into the concatenated LL, SS, LS pair list).
+    Returns (G or None, stats dict)."""
     bl, bs, CL, CS = _prep(L, S, CL, CS)
+    sel = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
     n = CL.shape[2]
     G = np.zeros((n, n, n, n, 4, 4)) if second_half else None
     st = Stats()
     rc = lib().orc_transform_direct(bl.ref, bs.ref if bs else None, _dp(CL),
                                     _dp(CS) if CS is not None else None, n, HAMS[ham],
-                                    float(tau), int(rows[0]), int(rows[1]),
+                                    float(tau), sel.ctypes.data if sel is not None else None,
+                                    0 if sel is None else int(sel.shape[0]),
                                     1 if second_half else 0,
                                     _dp(G) if G is not None else None, ctypes.byref(st))
     if rc != 0:

@@ -485,8 +485,8 @@ static cplx dens_gaunt(const cplx *cl, const cplx *cs, int m, int K, int ka, int
 }
 
 int orc_transform_direct(const orc_basis *L, const orc_basis *S, const double *CL,
-                         const double *CS, int n, int ham, double tau, int64_t row0,
-                         int64_t row1, int do_second, double *G, orc_stats *st)
+                         const double *CS, int n, int ham, double tau, const int64_t *rows,
+                         int64_t nrows_sel, int do_second, double *G, orc_stats *st)
 {
     int with_S = (ham != 0);
     if (with_S && (!S || !CS)) return -1;
@@ -514,9 +514,26 @@ int orc_transform_direct(const orc_basis *L, const orc_basis *S, const double *C
     }
     for (int mu = 0; mu < NL && gaunt; ++mu)
         for (int nu = 0; nu < NS; ++nu) pl[k++] = (opair){2, mu, nu};
-    if (row1 < 0 || row1 > np) row1 = np;
-    if (row0 < 0) row0 = 0;
-    if (row0 > row1) row0 = row1;
+    /* selected bra rows: slot[i] = position of pair i among the selected rows, or -1 */
+    int64_t nrow = rows ? nrows_sel : np;
+    int64_t *slot = (int64_t *)malloc(sizeof(int64_t) * (size_t)(np > 0 ? np : 1));
+    int64_t *sel = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nrow > 0 ? nrow : 1));
+    for (int64_t i = 0; i < np; ++i) slot[i] = rows ? -1 : i;
+    for (int64_t r = 0; r < nrow; ++r) {
+        int64_t i = rows ? rows[r] : r;
+        if (i < 0 || i >= np || (rows && slot[i] >= 0)) {
+            free(slot);
+            free(sel);
+            free(pl);
+            free(cl);
+            free(cs);
+            nb_free(&bl);
+            if (with_S) nb_free(&bs);
+            return -1;
+        }
+        slot[i] = r;
+        sel[r] = i;
+    }
 
     /* Schwarz factors Q = sqrt((mn|mn)) of each pair, Eq. (SchwarzDen) */
     double *Q = (double *)malloc(sizeof(double) * (size_t)(np > 0 ? np : 1));
@@ -565,7 +582,6 @@ int orc_transform_direct(const orc_basis *L, const orc_basis *S, const double *C
     /* First half, Eq. (firsthalf): V_{mn,cd} = sum_{kl kept} (mn|kl) D_{kl,cd},
      * complex spinor-pair columns (c,d); ket pairs are unordered, so both
      * orderings (kl) and (lk) of the Coulomb density enter. */
-    int64_t nrow = row1 - row0;
     int nvK = gaunt ? 3 : 1;
     cplx *V = (cplx *)calloc((size_t)(nrow > 0 ? nrow : 1) * nvK * m2, sizeof(cplx));
     int64_t kept[4] = {0, 0, 0, 0}, total[4] = {0, 0, 0, 0}, keptG = 0, totalG = 0, ties = 0;
@@ -580,9 +596,10 @@ int orc_transform_direct(const orc_basis *L, const orc_basis *S, const double *C
         cplx *Dk = (cplx *)malloc(sizeof(cplx) * 3 * m2);
         int64_t lk[4] = {0, 0, 0, 0}, lt[4] = {0, 0, 0, 0}, lkG = 0, ltG = 0, lties = 0;
 #pragma omp for schedule(dynamic, 1)
-        for (int64_t i = row0; i < row1; ++i) {
+        for (int64_t r = 0; r < nrow; ++r) {
+            const int64_t i = sel[r];
             const opair B = pl[i];
-            cplx *Vi = V + (size_t)(i - row0) * nvK * m2;
+            cplx *Vi = V + (size_t)r * nvK * m2;
             const nbasis *bA = B.cls == 1 ? &bs : &bl;
             const nbasis *bB = B.cls == 0 ? &bl : &bs;
             for (int64_t j = 0; j < np; ++j) {
@@ -667,8 +684,8 @@ int orc_transform_direct(const orc_basis *L, const orc_basis *S, const double *C
                             int lmu = orient == 0 ? mu : nu, snu = orient == 0 ? nu : mu;
                             idx = (coul ? nLL + nSS : 0) + (int64_t)lmu * NS + snu;
                         }
-                        if (idx < row0 || idx >= row1) continue;
-                        const cplx *Vr = V + (size_t)(idx - row0) * nvK * m2;
+                        if (slot[idx] < 0) continue;
+                        const cplx *Vr = V + (size_t)slot[idx] * nvK * m2;
                         for (int t1 = 0; t1 < 2; ++t1)
                             for (int t2 = 0; t2 < 2; ++t2) {
                                 /* spin block weight per Pauli component */
@@ -735,6 +752,8 @@ int orc_transform_direct(const orc_basis *L, const orc_basis *S, const double *C
     free(V);
     free(Q);
     free(Dmax);
+    free(slot);
+    free(sel);
     free(pl);
     free(cl);
     free(cs);

@@ -89,15 +89,16 @@ int orc_transform_def(const orc_basis *L, const orc_basis *S, const double *CL,
  * second-half two-spinor contraction, projected onto the quaternion basis.
  *   tau         screening threshold; a contribution (mu nu <- ka la) is kept
  *               iff (Q_mn * Q_kl) * Dmax_kl >= tau.
- *   row0,row1   restrict the bra pairs to the half-open range [row0,row1) of
- *               the concatenated bra pair list (LL pairs, then SS pairs, then
- *               LS pairs); pass 0,-1 for all.
+ *   rows,nrows  restrict the bra pairs to this list of distinct indices into
+ *               the concatenated bra pair list (LL pairs mu <= nu in nu-major
+ *               order, then SS pairs likewise, then LS pairs mu-major); pass
+ *               NULL for all pairs.
  *   do_second   0 = stop after the first half (timing samples), G untouched.
  *   G           output (when do_second); only bra pairs in range contribute.
  * Returns 0, or -1 on invalid arguments. */
 int orc_transform_direct(const orc_basis *L, const orc_basis *S, const double *CL,
-                         const double *CS, int n, int ham, double tau, int64_t row0,
-                         int64_t row1, int do_second, double *G, orc_stats *st);
+                         const double *CS, int n, int ham, double tau, const int64_t *rows,
+                         int64_t nrows, int do_second, double *G, orc_stats *st);
 
 /* Number of bra pairs of the concatenated list for this ham. */
 int64_t orc_num_bra_pairs(const orc_basis *L, const orc_basis *S, int ham);

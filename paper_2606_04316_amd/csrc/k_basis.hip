@@ -1,0 +1,136 @@
+// k_basis.hip -- basis-level device work: contracted normalization,
+// primitive-pair (Gaussian product) data and Schwarz factors.
+//
+// Schwarz factors Q_mn = sqrt((mn|mn)) are the integral part of the
+// density-weighted Cauchy-Schwarz bound of Eq. (SchwarzDen); one wavefront
+// sums the (K_m K_n)^2 primitive quartets of a pair and reduces them with
+// cross-lane shuffles.
+#include "kernels.h"
+
+namespace qdcb {
+
+// nc[i] = c_i (2a_i/pi)^{3/4} / sqrt(<chi|chi>) multiplies exp(-a_i r^2).
+__global__ void k_norm_coefs(int nfunc, const int32_t *first, const double *exps,
+                             const double *coefs, double *nc) {
+  int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nfunc) return;
+  int i0 = first[f], i1 = first[f + 1];
+  double s = 0.0;
+  for (int i = i0; i < i1; ++i) {
+    double di = coefs[i] * pow(2.0 * exps[i] / PI, 0.75);
+    for (int j = i0; j < i1; ++j) {
+      double dj = coefs[j] * pow(2.0 * exps[j] / PI, 0.75);
+      s += di * dj * pow(PI / (exps[i] + exps[j]), 1.5);
+    }
+  }
+  double inv = 1.0 / sqrt(s);
+  for (int i = i0; i < i1; ++i) nc[i] = coefs[i] * pow(2.0 * exps[i] / PI, 0.75) * inv;
+}
+
+void launch_norm_coefs(int nfunc, const int32_t *first, const double *exps, const double *coefs,
+                       double *nc, hipStream_t s) {
+  if (nfunc <= 0) return;
+  hipLaunchKernelGGL(k_norm_coefs, dim3((nfunc + 127) / 128), dim3(128), 0, s, nfunc, first,
+                     exps, coefs, nc);
+}
+
+__global__ void k_pair_data(int64_t npairs, const int32_t *mu, const int32_t *nu,
+                            const int64_t *pair_first, const double *cA, const int32_t *fA,
+                            const double *eA, const double *nA, const double *cB,
+                            const int32_t *fB, const double *eB, const double *nB,
+                            PrimPairs out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npairs) return;
+  int m = mu[i], n = nu[i];
+  double Ax = cA[3 * m], Ay = cA[3 * m + 1], Az = cA[3 * m + 2];
+  double Bx = cB[3 * n], By = cB[3 * n + 1], Bz = cB[3 * n + 2];
+  double r2 = (Ax - Bx) * (Ax - Bx) + (Ay - By) * (Ay - By) + (Az - Bz) * (Az - Bz);
+  int64_t o = pair_first[i];
+  for (int a = fA[m]; a < fA[m + 1]; ++a)
+    for (int b = fB[n]; b < fB[n + 1]; ++b) {
+      double ea = eA[a], eb = eB[b];
+      double p = ea + eb;
+      double ip = 1.0 / p;
+      out.p[o] = p;
+      out.x[o] = (ea * Ax + eb * Bx) * ip;
+      out.y[o] = (ea * Ay + eb * By) * ip;
+      out.z[o] = (ea * Az + eb * Bz) * ip;
+      out.e[o] = nA[a] * nB[b] * exp(-ea * eb * ip * r2) * SQRT2_PI54 * ip;
+      ++o;
+    }
+}
+
+void launch_pair_data(int64_t npairs, const int32_t *mu, const int32_t *nu,
+                      const int64_t *pair_first, const double *centA, const int32_t *firstA,
+                      const double *expA, const double *ncA, const double *centB,
+                      const int32_t *firstB, const double *expB, const double *ncB,
+                      PrimPairs out, hipStream_t s) {
+  if (npairs <= 0) return;
+  hipLaunchKernelGGL(k_pair_data, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, s,
+                     npairs, mu, nu, pair_first, centA, firstA, expA, ncA, centB, firstB, expB,
+                     ncB, out);
+}
+
+// One wavefront per pair: lanes stride over the (ij, kl) primitive quartets.
+__global__ void __launch_bounds__(256) k_schwarz(int64_t npairs, const int64_t *pair_first,
+                                                 PrimPairsC pp, double *Q) {
+  int lane = threadIdx.x & 63;
+  int64_t pair = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (pair >= npairs) return;
+  int64_t f0 = pair_first[pair];
+  int k = (int)(pair_first[pair + 1] - f0);
+  double acc = 0.0;
+  for (int t = lane; t < k * k; t += 64) {
+    int64_t i = f0 + t / k, j = f0 + t % k;
+    acc += prim_quartet(pp.p[i], pp.x[i], pp.y[i], pp.z[i], pp.e[i], pp.p[j], pp.x[j],
+                        pp.y[j], pp.z[j], pp.e[j]);
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) Q[pair] = sqrt(acc);
+}
+
+void launch_schwarz(int64_t npairs, const int64_t *pair_first, PrimPairsC pp, double *Q,
+                    hipStream_t s) {
+  if (npairs <= 0) return;
+  hipLaunchKernelGGL(k_schwarz, dim3((unsigned)((npairs + 3) / 4)), dim3(256), 0, s, npairs,
+                     pair_first, pp, Q);
+}
+
+__global__ void k_gather_pairs(int64_t nrows, const int64_t *src_first, const int32_t *cnt,
+                               const int64_t *dst_first, PrimPairsC src, PrimPairs dst) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  int64_t s0 = src_first[r], d0 = dst_first[r];
+  for (int i = 0; i < cnt[r]; ++i) {
+    dst.p[d0 + i] = src.p[s0 + i];
+    dst.x[d0 + i] = src.x[s0 + i];
+    dst.y[d0 + i] = src.y[s0 + i];
+    dst.z[d0 + i] = src.z[s0 + i];
+    dst.e[d0 + i] = src.e[s0 + i];
+  }
+}
+
+void launch_gather_pairs(int64_t nrows, const int64_t *src_first, const int32_t *cnt,
+                         const int64_t *dst_first, PrimPairsC src, PrimPairs dst,
+                         hipStream_t s) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL(k_gather_pairs, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, s,
+                     nrows, src_first, cnt, dst_first, src, dst);
+}
+
+__global__ void k_eri_list(int64_t nq, const int64_t *af, const int64_t *bf, const int32_t *ac,
+                           const int32_t *bc, PrimPairsC A, PrimPairsC B, double *out) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  out[q] = contracted_eri(A, af[q], af[q] + ac[q], B, bf[q], bf[q] + bc[q]);
+}
+
+void launch_eri_list(int64_t nq, const int64_t *a_first, const int64_t *b_first,
+                     const int32_t *a_cnt, const int32_t *b_cnt, PrimPairsC A, PrimPairsC B,
+                     double *out, hipStream_t s) {
+  if (nq <= 0) return;
+  hipLaunchKernelGGL(k_eri_list, dim3((unsigned)((nq + 127) / 128)), dim3(128), 0, s, nq,
+                     a_first, b_first, a_cnt, b_cnt, A, B, out);
+}
+
+}  // namespace qdcb

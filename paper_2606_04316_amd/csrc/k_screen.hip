@@ -1,0 +1,99 @@
+// k_screen.hip -- density-weighted Cauchy-Schwarz screening at tile level.
+//
+// Eq. (SchwarzDen): |(mn|kl) D_kl| <= Q_mn Q_kl ||D~_kl||_inf.  Pairs are
+// ordered by decreasing Q, so a 64-pair tile has a tight maximum.  A
+// (bra tile b, ket tile k) is kept when Qmax_b * Bmax_k >= tau, with
+// Bmax_k = max over the tile of Q_kl Dmax_kl; every element is then masked
+// individually by the exact directed predicate (Q_mn * Q_kl) * Dmax_kl >= tau
+// when its integral tile is built.  The tile test carries a relative slack
+// of 1e-12 so that rounding of the two different products can never drop a
+// tile that still holds a kept element.
+#include "kernels.h"
+
+namespace qdcb {
+
+__global__ void __launch_bounds__(64) k_tile_bounds(int ntiles, const double *Q,
+                                                    const double *Dmax, double *Qmax,
+                                                    double *Bmax) {
+  int t = blockIdx.x;
+  int64_t row = (int64_t)t * TILE + threadIdx.x;
+  double q = Q[row];
+  double b = q * Dmax[row];
+  q = wave_max(q);
+  b = wave_max(b);
+  if (threadIdx.x == 0) {
+    Qmax[t] = q;
+    Bmax[t] = b;
+  }
+}
+
+void launch_tile_bounds(int ntiles, const double *Q, const double *Dmax, double *Qmax,
+                        double *Bmax, hipStream_t s) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(k_tile_bounds, dim3(ntiles), dim3(64), 0, s, ntiles, Q, Dmax, Qmax, Bmax);
+}
+
+__device__ __forceinline__ bool tile_kept(double qb, double bk, double tau) {
+  return qb * bk >= tau * (1.0 - 1e-12);
+}
+
+__global__ void __launch_bounds__(256) k_screen_count(int ntiles, const double *Qmax,
+                                                      const double *Bmax, double tau,
+                                                      int32_t *count) {
+  __shared__ int red[4];
+  int b = blockIdx.x;
+  double qb = Qmax[b];
+  int c = 0;
+  for (int k = threadIdx.x; k < ntiles; k += 256) c += tile_kept(qb, Bmax[k], tau) ? 1 : 0;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) count[b] = red[0] + red[1] + red[2] + red[3];
+}
+
+void launch_screen_count(int ntiles, const double *Qmax, const double *Bmax, double tau,
+                         int32_t *count, hipStream_t s) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(k_screen_count, dim3(ntiles), dim3(256), 0, s, ntiles, Qmax, Bmax, tau,
+                     count);
+}
+
+// Ordered compaction: chunks of 256 ket tiles, block-wide exclusive scan of
+// the keep flags (wave ballots + per-wave offsets).
+__global__ void __launch_bounds__(256) k_screen_fill(int b0, int ntiles, const double *Qmax,
+                                                     const double *Bmax, double tau,
+                                                     const int64_t *slot_base,
+                                                     int32_t *tasks, int32_t *task_bra) {
+  __shared__ int wsum[4];
+  int b = b0 + blockIdx.x;
+  double qb = Qmax[b];
+  int64_t out = slot_base[b];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int k0 = 0; k0 < ntiles; k0 += 256) {
+    int k = k0 + threadIdx.x;
+    bool keep = k < ntiles && tile_kept(qb, Bmax[k], tau);
+    unsigned long long m = __ballot(keep);
+    int before = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[w] = __popcll(m);
+    __syncthreads();
+    int off = 0;
+    for (int i = 0; i < w; ++i) off += wsum[i];
+    int total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    if (keep) {
+      tasks[out + off + before] = k;
+      task_bra[out + off + before] = b;
+    }
+    out += total;
+    __syncthreads();
+  }
+}
+
+void launch_screen_fill(int b0, int b1, int ntiles, const double *Qmax, const double *Bmax,
+                        double tau, const int64_t *slot_base, int32_t *tasks,
+                        int32_t *task_bra, hipStream_t s) {
+  if (b1 <= b0) return;
+  hipLaunchKernelGGL(k_screen_fill, dim3(b1 - b0), dim3(256), 0, s, b0, ntiles, Qmax, Bmax, tau,
+                     slot_base, tasks, task_bra);
+}
+
+}  // namespace qdcb

@@ -1,0 +1,116 @@
+// kernels.h -- launchers of the qdcb HIP kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace qdcb {
+
+// ---- basis: normalization, primitive pairs, Schwarz factors (k_basis.hip)
+void launch_norm_coefs(int nfunc, const int32_t *prim_first, const double *exps,
+                       const double *coefs, double *nc, hipStream_t s);
+// Primitive-pair data of pairs (mu[i] in A, nu[i] in B), written at pair_first[i].
+void launch_pair_data(int64_t npairs, const int32_t *mu, const int32_t *nu,
+                      const int64_t *pair_first, const double *centA, const int32_t *firstA,
+                      const double *expA, const double *ncA, const double *centB,
+                      const int32_t *firstB, const double *expB, const double *ncB,
+                      PrimPairs out, hipStream_t s);
+// Q[i] = sqrt((i|i)) over the primitive pairs [pair_first[i], pair_first[i+1]).
+void launch_schwarz(int64_t npairs, const int64_t *pair_first, PrimPairsC pp, double *Q,
+                    hipStream_t s);
+// Gather pair rows into a new order: row r takes cnt[r] primitive pairs from
+// src_first[r] and stores them at dst_first[r].
+void launch_gather_pairs(int64_t nrows, const int64_t *src_first, const int32_t *cnt,
+                         const int64_t *dst_first, PrimPairsC src, PrimPairs dst,
+                         hipStream_t s);
+// ERIs of explicit quartets (test entry point): out[q] = (pair a[q] | pair b[q]).
+void launch_eri_list(int64_t nq, const int64_t *a_first, const int64_t *b_first,
+                     const int32_t *a_cnt, const int32_t *b_cnt, PrimPairsC A,
+                     PrimPairsC B, double *out, hipStream_t s);
+
+// ---- densities (k_density.hip)
+// Pair densities D~[row][4*idx(r,s)+y] for r <= s and Dmax[row].
+struct DensityArgs {
+  int64_t nrows;          // padded pair rows
+  int n;                  // MOs
+  int npair_mo;           // n(n+1)/2
+  int64_t ld;             // row stride of D (>= 4*npair_mo)
+  const int32_t *cls;     // [nrows] 0 = L, 1 = S, -1 = padding
+  const int32_t *mu;      // [nrows]
+  const int32_t *nu;      // [nrows]
+  const double *CL;       // [4][NL][n]
+  const double *CS;       // [4][NS][n]
+  int NL, NS;
+  const int32_t *rs;      // [npair_mo]: r | s << 16
+  double *D;              // [nrows][ld]
+  double *Dmax;           // [nrows]
+};
+void launch_density(const DensityArgs &a, hipStream_t s);
+
+// ---- screening (k_screen.hip)
+// Tile bounds: Qmax[t] = max Q, Bmax[t] = max Q*Dmax over the 64 rows of tile t.
+void launch_tile_bounds(int ntiles, const double *Q, const double *Dmax, double *Qmax,
+                        double *Bmax, hipStream_t s);
+// count[b] = number of ket tiles k with Qmax[b]*Bmax[k] >= tau*(1-1e-12).
+void launch_screen_count(int ntiles, const double *Qmax, const double *Bmax, double tau,
+                         int32_t *count, hipStream_t s);
+// tasks[slot_base[b] + j] = j-th kept ket tile of bra tile b (ascending) and
+// task_bra[slot_base[b] + j] = b, for b in [b0,b1).
+void launch_screen_fill(int b0, int b1, int ntiles, const double *Qmax, const double *Bmax,
+                        double tau, const int64_t *slot_base, int32_t *tasks,
+                        int32_t *task_bra, hipStream_t s);
+
+// ---- AO integral tiles (k_eri.hip)
+struct EriTileArgs {
+  const int32_t *tasks;       // [slots] ket tile per slot
+  const int32_t *task_bra;    // [slots] bra tile per slot
+  int64_t slot0;              // slot index of the panel buffer's first entry
+  const int64_t *row_first;   // [nrows+1] primitive-pair offsets of the sorted rows
+  PrimPairsC pp;
+  const double *Q;            // [nrows]
+  const double *Dmax;         // [nrows]
+  const int32_t *cls;         // [nrows]
+  double tau;
+  double *panel;              // [slots][64 ket][64 bra]
+  unsigned long long *kept;   // [4] kept directed contributions per class pair
+};
+void launch_eri_tiles(const EriTileArgs &a, int64_t nslots, hipStream_t s);
+
+// ---- first-half contraction (k_gemm.hip)
+struct FirstHalfArgs {
+  int b0, b1;
+  const int64_t *slot_base;
+  const int32_t *count;
+  const int32_t *tasks;
+  int64_t slot0;
+  const double *panel;   // [slots][64][64]
+  const double *D;       // [nrows][ld]
+  double *V;             // [nrows][ld]
+  int64_t ld;
+  int ncol_tiles;        // ceil(ncol / 128)
+};
+void launch_first_half(const FirstHalfArgs &a, hipStream_t s);
+
+// Batched FP64 GEMM, row-major: C[b] = alpha * op(A[b]) * B[b] + beta * C[b].
+// op(A) = A (transA = 0, A[m][k] at m*lda + k) or A^T (transA = 1, A[k][m] at k*lda + m).
+void launch_dgemm_batched(int transA, int M, int N, int K, double alpha, const double *A,
+                          int64_t lda, int64_t strideA, const double *B, int64_t ldb,
+                          int64_t strideB, double beta, double *C, int64_t ldc,
+                          int64_t strideC, int batch, hipStream_t s);
+
+// ---- second half (k_second.hip)
+// Cq[nu][z*n + q] = C[z][nu][q];  Chat[(mu,z)][(x,p)] = coefficient of W_z in
+// [conj(C_mu p) W]_x.
+void launch_build_coef_mats(int N, int n, const double *C, double *Call, double *Chat,
+                            hipStream_t s);
+// Vfull[c][mu][nu] = V[rowmap[mu*N + nu]][c0 + c] for c < nc.
+void launch_unpack(int N, const int32_t *rowmap, const double *V, int64_t ld, int64_t c0,
+                   int nc, double *Vfull, hipStream_t s);
+// Scatter Gc[c][(x,p)][q] (columns c0..c0+nc of the (r<=s, y) column space) into
+// G[p][q][r][s][x][y] and mirror r<->s with the sign of component y.
+void launch_pack(int n, const int32_t *rs, int64_t c0, int nc, const double *Gc, double *G,
+                 hipStream_t s);
+
+}  // namespace qdcb

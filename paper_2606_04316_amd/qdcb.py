@@ -1,0 +1,230 @@
+"""Python binding of libqdcb.so (the C ABI in include/qdcb.h).
+
+Argument marshalling only: every step of the transformation runs in the
+library's HIP kernels.  Host numpy arrays or torch CUDA tensors are accepted
+for the MO coefficients and the output; torch is used only for device
+memory and streams.  If the shared library has not been built, every entry
+point raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqdcb.so")
+
+HAM = {"LL": 0, "DC": 1, "DCG": 2}
+PREC = {"fp64": 0, "mixed": 1}
+PTR_DEVICE = 0x1
+FETCH_DMAX, FETCH_Q = 1, 2
+
+STATUS = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_UNSUPPORTED"}
+
+
+class QdcbError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("ham", ctypes.c_int32), ("prec", ctypes.c_int32), ("n_mo", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("tau", ctypes.c_double),
+                ("tier_fp32", ctypes.c_double), ("tier_bf16", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("ms_total", ctypes.c_double), ("ms_density", ctypes.c_double),
+                ("ms_screen", ctypes.c_double), ("ms_eri", ctypes.c_double),
+                ("ms_first_half", ctypes.c_double), ("ms_second_half", ctypes.c_double),
+                ("kept", ctypes.c_int64 * 4), ("total", ctypes.c_int64 * 4),
+                ("kept_gaunt", ctypes.c_int64), ("total_gaunt", ctypes.c_int64),
+                ("tiles_kept", ctypes.c_int64), ("tiles_total", ctypes.c_int64),
+                ("flops_first_half", ctypes.c_double), ("flops_second_half", ctypes.c_double),
+                ("flops_mfma", ctypes.c_double), ("n_batches", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+    def as_dict(self):
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if isinstance(v, ctypes.Array) else v
+        d.pop("pad", None)
+        return d
+
+
+_lib = None
+_P = ctypes.c_void_p
+_DP = ctypes.POINTER(ctypes.c_double)
+_IP = ctypes.POINTER(ctypes.c_int32)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        L.qdcb_abi_version.restype = ctypes.c_int
+        L.qdcb_last_error.restype = ctypes.c_char_p
+        L.qdcb_ctx_create.argtypes = [ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(_P)]
+        L.qdcb_ctx_destroy.argtypes = [_P]
+        L.qdcb_ctx_destroy.restype = None
+        L.qdcb_basis_create.argtypes = [_P, ctypes.c_int32, _DP, _IP, _DP, _DP, ctypes.POINTER(_P)]
+        L.qdcb_basis_destroy.argtypes = [_P]
+        L.qdcb_basis_destroy.restype = None
+        L.qdcb_basis_schwarz.argtypes = [_P, _DP]
+        L.qdcb_eri_quartets.argtypes = [_P, _P, ctypes.c_int64, _IP, _DP]
+        L.qdcb_plan_create.argtypes = [_P, _P, _P, ctypes.POINTER(PlanDesc), ctypes.POINTER(_P)]
+        L.qdcb_plan_destroy.argtypes = [_P]
+        L.qdcb_plan_destroy.restype = None
+        L.qdcb_plan_footprint.argtypes = [_P, ctypes.POINTER(ctypes.c_size_t)]
+        L.qdcb_transform.argtypes = [_P, _P, _P, _P, ctypes.c_uint32, _P,
+                                     ctypes.POINTER(Stats)]
+        L.qdcb_plan_fetch.argtypes = [_P, ctypes.c_int32, _P, ctypes.c_size_t]
+        for f in ("qdcb_ctx_create", "qdcb_basis_create", "qdcb_basis_schwarz",
+                  "qdcb_eri_quartets", "qdcb_plan_create", "qdcb_plan_footprint",
+                  "qdcb_transform", "qdcb_plan_fetch"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != 0:
+        raise QdcbError(st, lib().qdcb_last_error().decode())
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _is_torch_cuda(x) -> bool:
+    return hasattr(x, "is_cuda") and hasattr(x, "data_ptr") and bool(x.is_cuda)
+
+
+class Context:
+    def __init__(self, device: int = 0, budget_bytes: int = 0):
+        h = _P()
+        _check(lib().qdcb_ctx_create(int(device), int(budget_bytes), ctypes.byref(h)))
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            lib().qdcb_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Basis:
+    """Device-resident s-type basis: ``basis`` has centers, nprim, exps, coefs."""
+
+    def __init__(self, ctx: Context, basis):
+        self.ctx = ctx
+        self.nfunc = int(np.asarray(basis.nprim).shape[0])
+        c = _f64(basis.centers)
+        k = np.ascontiguousarray(basis.nprim, dtype=np.int32)
+        e = _f64(basis.exps)
+        d = _f64(basis.coefs)
+        h = _P()
+        _check(lib().qdcb_basis_create(ctx.h, self.nfunc, c.ctypes.data_as(_DP),
+                                       k.ctypes.data_as(_IP), e.ctypes.data_as(_DP),
+                                       d.ctypes.data_as(_DP), ctypes.byref(h)))
+        self.h = h
+
+    def schwarz(self) -> np.ndarray:
+        Q = np.empty((self.nfunc, self.nfunc))
+        _check(lib().qdcb_basis_schwarz(self.h, Q.ctypes.data_as(_DP)))
+        return Q
+
+    def close(self):
+        if self.h:
+            lib().qdcb_basis_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def eri_quartets(A: Basis, B: Basis, idx) -> np.ndarray:
+    idx = np.ascontiguousarray(idx, dtype=np.int32).reshape(-1, 4)
+    out = np.empty(idx.shape[0])
+    _check(lib().qdcb_eri_quartets(A.h, B.h, idx.shape[0], idx.ctypes.data_as(_IP),
+                                   out.ctypes.data_as(_DP)))
+    return out
+
+
+class Plan:
+    def __init__(self, ctx: Context, L: Basis, S: Optional[Basis], ham: str, n_mo: int,
+                 tau: float, prec: str = "fp64", tier_fp32: float = 1e-4,
+                 tier_bf16: float = 1e-7):
+        self.ctx, self.L, self.S = ctx, L, S
+        self.n = int(n_mo)
+        self.ham = ham
+        desc = PlanDesc(HAM[ham], PREC[prec], self.n, 0, float(tau), float(tier_fp32),
+                        float(tier_bf16))
+        h = _P()
+        _check(lib().qdcb_plan_create(ctx.h, L.h, S.h if S is not None else None,
+                                      ctypes.byref(desc), ctypes.byref(h)))
+        self.h = h
+
+    def footprint(self) -> int:
+        b = ctypes.c_size_t(0)
+        _check(lib().qdcb_plan_footprint(self.h, ctypes.byref(b)))
+        return int(b.value)
+
+    def transform(self, CL, CS=None, G=None, stream=None):
+        """Returns (G, stats).  numpy inputs use the host path; torch CUDA
+        tensors the device path (G must then be a CUDA float64 tensor or None)."""
+        n = self.n
+        st = Stats()
+        if _is_torch_cuda(CL):
+            import torch
+            if G is None:
+                G = torch.empty((n, n, n, n, 4, 4), dtype=torch.float64, device=CL.device)
+            for t in (CL, CS, G):
+                if t is not None and (t.dtype != torch.float64 or not t.is_contiguous()):
+                    raise ValueError("device tensors must be contiguous float64")
+            if stream is None:
+                stream = torch.cuda.current_stream(CL.device).cuda_stream
+            _check(lib().qdcb_transform(self.h, CL.data_ptr(),
+                                        CS.data_ptr() if CS is not None else None,
+                                        G.data_ptr(), PTR_DEVICE, stream, ctypes.byref(st)))
+            return G, st.as_dict()
+        CLh = _f64(CL)
+        CSh = _f64(CS) if CS is not None else None
+        if G is None:
+            G = np.empty((n, n, n, n, 4, 4))
+        _check(lib().qdcb_transform(self.h, CLh.ctypes.data,
+                                    CSh.ctypes.data if CSh is not None else None,
+                                    G.ctypes.data, 0, stream, ctypes.byref(st)))
+        return G, st.as_dict()
+
+    def fetch(self, what: int, count: int) -> np.ndarray:
+        out = np.empty(count)
+        _check(lib().qdcb_plan_fetch(self.h, int(what), out.ctypes.data, out.nbytes))
+        return out
+
+    def close(self):
+        if self.h:
+            lib().qdcb_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
