@@ -111,8 +111,11 @@ typedef struct {
 } qdcb_plan_desc;
 
 /* Plan for transforming with fixed bases and n_mo.  S must be NULL for
- * QDCB_HAM_LL and non-NULL otherwise.  Orders the pairs by their Schwarz
- * factor and allocates the per-transform device buffers. */
+ * QDCB_HAM_LL and non-NULL otherwise.  Orders the pairs of each integral
+ * class space (Coulomb: LL and SS pairs; Gaunt, for DCG: ordered LS pairs) by
+ * their Schwarz factor and allocates the per-transform device buffers; the
+ * MO-pair columns are processed in chunks when they do not fit at once.
+ * QDCB_E_NOMEM if even the smallest chunk does not fit the context budget. */
 qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basis *S,
                              const qdcb_plan_desc *desc, qdcb_plan **out);
 void qdcb_plan_destroy(qdcb_plan *plan);
@@ -136,8 +139,8 @@ typedef struct {
     double flops_first_half; /* algorithmic: 2 * columns * kept contributions */
     double flops_second_half;
     double flops_mfma;       /* MFMA flops issued by the first-half kernel (incl. masked) */
-    int32_t n_batches;
-    int32_t pad;
+    int32_t n_batches;       /* first-half kernel launches */
+    int32_t n_chunks;        /* MO-pair column chunks */
 } qdcb_stats;
 
 /* Transform.  CL [4][N_L][n], CS [4][N_S][n] (NULL for LL), G [n^4][4][4];
@@ -148,12 +151,17 @@ qdcb_status qdcb_transform(qdcb_plan *plan, const double *CL, const double *CS, 
                            uint32_t flags, void *hip_stream, qdcb_stats *stats);
 
 /* Intermediates of the plan's last transform, copied to host memory.
- *   QDCB_FETCH_DMAX  float64 [P]: density bound Dmax of every Coulomb pair in
- *                    canonical order (LL pairs mu <= nu by nu-major packing
- *                    nu(nu+1)/2 + mu, then SS pairs likewise).
- *   QDCB_FETCH_Q     float64 [P]: Schwarz factors in the same order. */
+ *   QDCB_FETCH_DMAX        float64 [P]: density bound Dmax of every Coulomb pair
+ *                          in canonical order (LL pairs mu <= nu by nu-major
+ *                          packing nu(nu+1)/2 + mu, then SS pairs likewise).
+ *   QDCB_FETCH_Q           float64 [P]: Schwarz factors in the same order.
+ *   QDCB_FETCH_DMAX_GAUNT  float64 [N_L*N_S]: Gaunt density bound of the LS pair
+ *                          (mu in L, nu in S) at mu*N_S + nu (DCG plans).
+ *   QDCB_FETCH_Q_GAUNT     float64 [N_L*N_S]: Schwarz factors of the LS pairs. */
 #define QDCB_FETCH_DMAX 1
 #define QDCB_FETCH_Q 2
+#define QDCB_FETCH_DMAX_GAUNT 3
+#define QDCB_FETCH_Q_GAUNT 4
 qdcb_status qdcb_plan_fetch(const qdcb_plan *plan, int32_t what, void *host_out,
                             size_t bytes);
 

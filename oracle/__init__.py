@@ -70,6 +70,7 @@ def lib():
         L.orc_eri_tensor.argtypes = [bp, bp, bp, bp, dp]
         L.orc_schwarz.argtypes = [bp, bp, dp]
         L.orc_dmax_coulomb.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp]
+        L.orc_dmax_gaunt.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp, ctypes.c_int, dp]
         L.orc_transform_def.restype = ctypes.c_int
         L.orc_transform_def.argtypes = [bp, bp, dp, dp, ctypes.c_int, ctypes.c_int, dp, dp, dp]
         L.orc_transform_direct.restype = ctypes.c_int
@@ -142,6 +143,15 @@ def dmax_coulomb(C: np.ndarray) -> np.ndarray:
     N, n = C.shape[1], C.shape[2]
     out = np.empty((N, N))
     lib().orc_dmax_coulomb(N, _dp(C), n, _dp(out))
+    return out
+
+
+def dmax_gaunt(CL: np.ndarray, CS: np.ndarray) -> np.ndarray:
+    CL = np.ascontiguousarray(CL, dtype=np.float64)
+    CS = np.ascontiguousarray(CS, dtype=np.float64)
+    NL, NS, n = CL.shape[1], CS.shape[1], CL.shape[2]
+    out = np.empty((NL, NS))
+    lib().orc_dmax_gaunt(NL, _dp(CL), NS, _dp(CS), n, _dp(out))
     return out
 
 

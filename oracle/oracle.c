@@ -308,6 +308,35 @@ void orc_dmax_coulomb(int NA, const double *CA, int n, double *Dmax)
         }
 }
 
+void orc_dmax_gaunt(int NL, const double *CL, int NS, const double *CS, int n, double *Dmax)
+{
+    /* e_K for K = x, y, z: the quaternion units with sigma_K = -i Q(e_K) */
+    const double unit[3][4] = {{0, 0, 0, 1}, {0, 0, 1, 0}, {0, 1, 0, 0}};
+    for (int mu = 0; mu < NL; ++mu)
+        for (int nu = 0; nu < NS; ++nu) {
+            double m = 0.0;
+            for (int K = 0; K < 3; ++K)
+                for (int r = 0; r < n; ++r)
+                    for (int t = 0; t < n; ++t) {
+                        double lr[4], sr[4], lt[4], st[4], a[4], b[4], d1[4], d2[4];
+                        for (int z = 0; z < 4; ++z) {
+                            double sg = z ? -1.0 : 1.0;
+                            lr[z] = sg * CL[((size_t)z * NL + mu) * n + r];
+                            sr[z] = sg * CS[((size_t)z * NS + nu) * n + r];
+                            lt[z] = CL[((size_t)z * NL + mu) * n + t];
+                            st[z] = CS[((size_t)z * NS + nu) * n + t];
+                        }
+                        qmul(lr, unit[K], a);
+                        qmul(a, st, d1);
+                        qmul(sr, unit[K], b);
+                        qmul(b, lt, d2);
+                        for (int z = 0; z < 4; ++z)
+                            if (fabs(d1[z] + d2[z]) > m) m = fabs(d1[z] + d2[z]);
+                    }
+            Dmax[(size_t)mu * NS + nu] = m;
+        }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Definition route: literal four-spinor operator matrices                     */
 /* ------------------------------------------------------------------------ */

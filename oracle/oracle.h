@@ -73,6 +73,12 @@ void orc_schwarz(const orc_basis *A, const orc_basis *B, double *Q);
  * quaternion pair density. */
 void orc_dmax_coulomb(int NA, const double *CA, int n, double *Dmax);
 
+/* Gaunt density bound of the L-S pair (mu in L, nu in S): Dmax[mu][nu] = max
+ * over K, all ordered (r,t) and components x of
+ * |[conj(C^L_{mu r}) e_K C^S_{nu t} + conj(C^S_{nu r}) e_K C^L_{mu t}]_x|
+ * with e_x = k, e_y = j, e_z = i; [NL][NS]. */
+void orc_dmax_gaunt(int NL, const double *CL, int NS, const double *CS, int n, double *Dmax);
+
 /* Definition route (unscreened): four-spinor integrals built from the literal
  * 4x4 operator matrices (identity for Coulomb, alpha_K for Gaunt) and
  * projected onto the quaternion basis.  spinor_out (nullable) receives the

@@ -10,7 +10,7 @@ constexpr int TILE = 64;  // pairs per bra/ket tile (one wavefront of bra rows)
 constexpr double PI = 3.14159265358979323846;
 // sqrt(2) * pi^(5/4): folded into every primitive-pair prefactor so that
 // E_ij E_kl = 2 pi^(5/2) c_i c_j c_k c_l K_ij K_kl / (p q).
-constexpr double SQRT2_PI54 = 5.0464190163490266;
+constexpr double SQRT2_PI54 = 5.914967172795613;
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 

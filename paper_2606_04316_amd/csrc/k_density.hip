@@ -1,24 +1,59 @@
 // k_density.hip -- quaternion MO-pair densities and their infinity-norm bound.
 //
-// For an AO pair (ka, la) of class X and MO pair r <= s the quaternion pair
-// density is D^{rs}_{ka la} = conj(C_ka r) C_la s (the Kramers-paired form of
-// Eqs. Den and QuaternionScatter: its four real components are the four
-// Pauli-scalar densities of the Kramers block).  Because the AO integral is
-// symmetric in ka <-> la, the first half contracts with the symmetrized
-//   D~ = D_{ka la} + D_{la ka}   (ka != la),   D_{ka ka}   (ka = la),
-// stored as D~[row][4*idx(r,s) + y].  Dmax_{ka la} is the largest |component|
-// of D over all ordered MO pairs (r, t), the ||D~||_inf of Eq. (SchwarzDen);
-// the r <= s loop covers it because conj(D^{rt}_{ka la}) = D^{tr}_{la ka}.
+// Coulomb classes (LL, SS rows).  For an AO pair (ka, la) and MO pair r <= s
+// the quaternion pair density is D^{rs}_{ka la} = conj(C_ka r) C_la s, the
+// Kramers-paired form of Eqs. (Den) and (QuaternionScatter): its four real
+// components are the four Pauli-scalar densities of the Kramers block.  The AO
+// integral is symmetric in ka <-> la, so the first half contracts with
+//   D~ = D_{ka la} + D_{la ka}   (ka != la),   D_{ka ka}   (ka = la).
+// Dmax_{ka la} is the largest |component| of D over all ordered MO pairs
+// (r, t), the ||D~||_inf of Eq. (SchwarzDen); the r <= s loop covers it
+// because conj(D^{rt}_{ka la}) = D^{tr}_{la ka}.
 //
-// One workgroup per AO pair row: the two coefficient rows are staged in LDS,
-// threads stride over MO pairs and write 32 contiguous bytes each (coalesced
-// rows), and a block reduction forms Dmax.  HBM-bound (write of D~).
+// Gaunt class (LS rows, ka in L, la in S).  The density of the Gaunt term
+// -alpha_1.alpha_2/r12 (Eqs. breit, GauntInt) for Pauli component K is
+//   D^{K,rs}_{ka la} = conj(C^L_ka r) e_K C^S_la s + conj(C^S_la r) e_K C^L_ka s,
+// e_x = k, e_y = j, e_z = i (sigma_K = -i Q(e_K)).  D^{K,sr} = -conj(D^{K,rs}),
+// so r <= s again covers every ordered pair for Dmax.
+//
+// One workgroup per pair row; the coefficient rows are staged in LDS, threads
+// stride over MO pairs and write 32 contiguous bytes each; a block reduction
+// forms Dmax.  Bound-only launches compute Dmax over all MO pairs without
+// writing D; write launches fill the columns of MO pairs [i0, i1).
 #include "kernels.h"
 
 namespace qdcb {
 
 constexpr int DENS_THREADS = 256;
 constexpr int MAX_N = 512;
+
+__device__ __forceinline__ void qmul4(const double a[4], const double b[4], double r[4]) {
+  r[0] = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+  r[1] = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+  r[2] = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+  r[3] = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+}
+
+// conj(c) * e_K for K = 0 (x: e = k), 1 (y: e = j), 2 (z: e = i)
+__device__ __forceinline__ void conj_times_unit(const double c[4], int K, double r[4]) {
+  const double a0 = c[0], a1 = -c[1], a2 = -c[2], a3 = -c[3];
+  if (K == 2) {  // q * i = (-q1, q0, q3, -q2)
+    r[0] = -a1; r[1] = a0; r[2] = a3; r[3] = -a2;
+  } else if (K == 1) {  // q * j = (-q2, -q3, q0, q1)
+    r[0] = -a2; r[1] = -a3; r[2] = a0; r[3] = a1;
+  } else {  // q * k = (-q3, q2, -q1, q0)
+    r[0] = -a3; r[1] = a2; r[2] = -a1; r[3] = a0;
+  }
+}
+
+__device__ __forceinline__ double block_max(double mx, double *red) {
+  mx = wave_max(mx);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  double m = red[0];
+  for (int w = 1; w < DENS_THREADS / 64; ++w) m = fmax(m, red[w]);
+  return m;
+}
 
 __global__ void __launch_bounds__(DENS_THREADS) k_density(DensityArgs a) {
   __shared__ double ck[4][MAX_N];
@@ -27,10 +62,13 @@ __global__ void __launch_bounds__(DENS_THREADS) k_density(DensityArgs a) {
   const int64_t row = blockIdx.x;
   const int cls = a.cls[row];
   const int n = a.n;
+  const int i0 = a.bound_only ? 0 : a.i0, i1 = a.bound_only ? a.npair_mo : a.i1;
   double *Drow = a.D + row * a.ld;
   if (cls < 0) {  // padding row: zero density, zero bound
-    for (int c = threadIdx.x; c < 4 * a.npair_mo; c += DENS_THREADS) Drow[c] = 0.0;
-    if (threadIdx.x == 0) a.Dmax[row] = 0.0;
+    if (!a.bound_only)
+      for (int c = threadIdx.x; c < 4 * (i1 - i0); c += DENS_THREADS) Drow[c] = 0.0;
+    else if (threadIdx.x == 0)
+      a.Dmax[row] = 0.0;
     return;
   }
   const double *C = cls == 0 ? a.CL : a.CS;
@@ -44,7 +82,7 @@ __global__ void __launch_bounds__(DENS_THREADS) k_density(DensityArgs a) {
   __syncthreads();
   const bool offdiag = ka != la;
   double mx = 0.0;
-  for (int idx = threadIdx.x; idx < a.npair_mo; idx += DENS_THREADS) {
+  for (int idx = i0 + threadIdx.x; idx < i1; idx += DENS_THREADS) {
     int rs = a.rs[idx];
     int r = rs & 0xffff, s = rs >> 16;
     double d0, d1, d2, d3;
@@ -61,23 +99,79 @@ __global__ void __launch_bounds__(DENS_THREADS) k_density(DensityArgs a) {
       d2 += e2;
       d3 += e3;
     }
-    double2 *dst = reinterpret_cast<double2 *>(Drow + 4 * idx);
-    dst[0] = make_double2(d0, d1);
-    dst[1] = make_double2(d2, d3);
+    if (!a.bound_only) {
+      double2 *dst = reinterpret_cast<double2 *>(Drow + 4 * (idx - i0));
+      dst[0] = make_double2(d0, d1);
+      dst[1] = make_double2(d2, d3);
+    }
   }
-  mx = wave_max(mx);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  if (a.bound_only) {
+    double m = block_max(mx, red);
+    if (threadIdx.x == 0) a.Dmax[row] = m;
+  }
+}
+
+__global__ void __launch_bounds__(DENS_THREADS) k_density_gaunt(DensityArgs a) {
+  __shared__ double ck[4][MAX_N];  // C^L row ka
+  __shared__ double cl[4][MAX_N];  // C^S row la
+  __shared__ double red[DENS_THREADS / 64];
+  const int64_t row = blockIdx.x;
+  const int cls = a.cls[row];
+  const int n = a.n;
+  const int i0 = a.bound_only ? 0 : a.i0, i1 = a.bound_only ? a.npair_mo : a.i1;
+  double *Drow = a.D + row * a.ld;
+  if (cls < 0) {
+    if (!a.bound_only) {
+      for (int K = 0; K < 3; ++K)
+        for (int c = threadIdx.x; c < 4 * (i1 - i0); c += DENS_THREADS)
+          Drow[K * a.ldK + c] = 0.0;
+    } else if (threadIdx.x == 0) {
+      a.Dmax[row] = 0.0;
+    }
+    return;
+  }
+  const int ka = a.mu[row], la = a.nu[row];
+  for (int t = threadIdx.x; t < 4 * n; t += DENS_THREADS) {
+    int z = t / n, r = t % n;
+    ck[z][r] = a.CL[((int64_t)z * a.NL + ka) * n + r];
+    cl[z][r] = a.CS[((int64_t)z * a.NS + la) * n + r];
+  }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = red[0];
-    for (int w = 1; w < DENS_THREADS / 64; ++w) m = fmax(m, red[w]);
-    a.Dmax[row] = m;
+  double mx = 0.0;
+  for (int idx = i0 + threadIdx.x; idx < i1; idx += DENS_THREADS) {
+    int rs = a.rs[idx];
+    int r = rs & 0xffff, s = rs >> 16;
+    const double lr[4] = {ck[0][r], ck[1][r], ck[2][r], ck[3][r]};
+    const double sr[4] = {cl[0][r], cl[1][r], cl[2][r], cl[3][r]};
+    const double ls[4] = {ck[0][s], ck[1][s], ck[2][s], ck[3][s]};
+    const double ss[4] = {cl[0][s], cl[1][s], cl[2][s], cl[3][s]};
+    for (int K = 0; K < 3; ++K) {
+      double u[4], v[4], d1[4], d2[4];
+      conj_times_unit(lr, K, u);
+      qmul4(u, ss, d1);
+      conj_times_unit(sr, K, v);
+      qmul4(v, ls, d2);
+      double d0 = d1[0] + d2[0], dd1 = d1[1] + d2[1], dd2 = d1[2] + d2[2], dd3 = d1[3] + d2[3];
+      mx = fmax(mx, fmax(fmax(fabs(d0), fabs(dd1)), fmax(fabs(dd2), fabs(dd3))));
+      if (!a.bound_only) {
+        double2 *dst = reinterpret_cast<double2 *>(Drow + K * a.ldK + 4 * (idx - i0));
+        dst[0] = make_double2(d0, dd1);
+        dst[1] = make_double2(dd2, dd3);
+      }
+    }
+  }
+  if (a.bound_only) {
+    double m = block_max(mx, red);
+    if (threadIdx.x == 0) a.Dmax[row] = m;
   }
 }
 
 void launch_density(const DensityArgs &a, hipStream_t s) {
   if (a.nrows <= 0) return;
-  hipLaunchKernelGGL(k_density, dim3((unsigned)a.nrows), dim3(DENS_THREADS), 0, s, a);
+  if (a.gaunt)
+    hipLaunchKernelGGL(k_density_gaunt, dim3((unsigned)a.nrows), dim3(DENS_THREADS), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_density, dim3((unsigned)a.nrows), dim3(DENS_THREADS), 0, s, a);
 }
 
 }  // namespace qdcb

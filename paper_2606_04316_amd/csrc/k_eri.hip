@@ -40,9 +40,11 @@ __global__ void __launch_bounds__(256) k_eri_tiles(EriTileArgs a) {
     }
     out[j * TILE + lane] = v;
   }
-  for (int c = 0; c < 4; ++c) {
-    long long t = wave_sum_ll(kept[c]);
-    if (lane == 0 && t) atomicAdd(a.kept + c, (unsigned long long)t);
+  if (a.kept) {
+    for (int c = 0; c < 4; ++c) {
+      long long t = wave_sum_ll(kept[c]);
+      if (lane == 0 && t) atomicAdd(a.kept + c, (unsigned long long)t);
+    }
   }
 }
 

@@ -12,7 +12,7 @@
 // transforms (Sec. 2.4.2).
 //
 // Both use v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16] and
-// B[l/16][l%16]; accumulator element i of lane l is D[4*(l/16)+i][l%16].
+// B[l/16][l%16]; accumulator element i of lane l is D[l/16 + 4*i][l%16].
 #include "kernels.h"
 
 namespace qdcb {
@@ -27,8 +27,10 @@ constexpr int BS_LD = 128;    // LDS row stride of the density slice [j][col]
 __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a) {
   __shared__ double As[FH_KH * AS_LD];
   __shared__ double Bs[FH_KH * BS_LD];
-  const int ct = blockIdx.x;
-  const int bt = a.b0 + blockIdx.y;
+  // bra tiles vary fastest: workgroups in flight share the column slice and,
+  // through the ordered ket lists of neighbouring bra tiles, the density rows
+  const int bt = a.b0 + blockIdx.x;
+  const int ct = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int64_t c0 = (int64_t)ct * FH_COLS;
   dbl4 acc[4][2];
@@ -85,14 +87,14 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a) {
     for (int c = 0; c < 2; ++c)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        int64_t row = row0 + r * 16 + 4 * lk + i;
+        int64_t row = row0 + r * 16 + lk + 4 * i;
         a.V[row * a.ld + c0 + w * 32 + c * 16 + lr] = acc[r][c][i];
       }
 }
 
 void launch_first_half(const FirstHalfArgs &a, hipStream_t s) {
   if (a.b1 <= a.b0 || a.ncol_tiles <= 0) return;
-  hipLaunchKernelGGL(k_first_half, dim3(a.ncol_tiles, a.b1 - a.b0), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_first_half, dim3(a.b1 - a.b0, a.ncol_tiles), dim3(256), 0, s, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -157,7 +159,7 @@ __global__ void __launch_bounds__(256) k_dgemm_batched(int transA, int M, int N,
   for (int r = 0; r < 2; ++r)
     for (int c = 0; c < 2; ++c)
       for (int i = 0; i < 4; ++i) {
-        int gm = m0 + wr + r * 16 + 4 * lk + i, gn = n0 + wc + c * 16 + lr;
+        int gm = m0 + wr + r * 16 + lk + 4 * i, gn = n0 + wc + c * 16 + lr;
         if (gm < M && gn < N) {
           double *p = C + (int64_t)gm * ldc + gn;
           double v = alpha * acc[r][c][i];

@@ -1,77 +1,86 @@
 // k_second.hip -- second-half helpers (Sec. 2.4.2, Eq. secondhalf).
 //
-// The half-transformed V[mn][(rs, y)] is real and symmetric in (m, n) for
-// every column, so G_{pq} = sum_mn conj(C_mp) V_mn C_nq is done per column as
-// two real GEMMs on quaternion planes:
-//   W[m][(z, q)]  = sum_n V[m][n] C_z[n][q]                 (4 planes at once)
+// The half-transformed V[mn][(rs, y)] is a real N_A x N_B matrix for every
+// column, so G_pq = sum_mn a_mp V_mn b_nq (a, b quaternion coefficient rows)
+// is done per column as two real GEMMs on quaternion planes:
+//   W[m][(z, q)]  = sum_n V[m][n] b_z[n][q]                 (4 planes at once)
 //   G[(x, p)][q]  = sum_(m, z) Chat[(m, z)][(x, p)] W[(m, z)][q]
-// where Chat holds the signed components of conj(C_mp) that multiply W_z in
-// component x of the quaternion product.  These kernels build Chat, unpack V
-// column slices into dense matrices and scatter the result into G.
+// where Chat holds the left-multiplication matrix of a_mp.  Coulomb uses
+// a = conj(C), b = C; the Gaunt chains use a = conj(C^L) e_K, b = C^S and
+// a = conj(C^S) e_K, b = C^L (Eq. GauntInt).  These kernels build Chat, unpack
+// V column slices into dense matrices and scatter the result into G.
 #include "kernels.h"
 
 namespace qdcb {
 
-__global__ void k_build_coef_mats(int N, int n, const double *C, double *Call, double *Chat) {
+__global__ void k_build_coef_mats(int N, int n, const double *C, int unit, double *Call,
+                                  double *Chat) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)N * n) return;
   int mu = (int)(t / n), p = (int)(t % n);
-  double a0 = C[((int64_t)0 * N + mu) * n + p];
-  double a1 = C[((int64_t)1 * N + mu) * n + p];
-  double a2 = C[((int64_t)2 * N + mu) * n + p];
-  double a3 = C[((int64_t)3 * N + mu) * n + p];
-  Call[(int64_t)mu * 4 * n + 0 * n + p] = a0;
-  Call[(int64_t)mu * 4 * n + 1 * n + p] = a1;
-  Call[(int64_t)mu * 4 * n + 2 * n + p] = a2;
-  Call[(int64_t)mu * 4 * n + 3 * n + p] = a3;
-  // [conj(a) w]_x = sum_z coef[x][z] w_z
-  const double coef[4][4] = {{a0, a1, a2, a3},
-                             {-a1, a0, a3, -a2},
-                             {-a2, -a3, a0, a1},
-                             {-a3, a2, -a1, a0}};
+  double c[4];
+  for (int z = 0; z < 4; ++z) {
+    c[z] = C[((int64_t)z * N + mu) * n + p];
+    Call[(int64_t)mu * 4 * n + z * n + p] = c[z];
+  }
+  // a = conj(c) * e
+  double a0 = c[0], a1 = -c[1], a2 = -c[2], a3 = -c[3];
+  double q0 = a0, q1 = a1, q2 = a2, q3 = a3;
+  if (unit == 2) {  // * i
+    q0 = -a1; q1 = a0; q2 = a3; q3 = -a2;
+  } else if (unit == 1) {  // * j
+    q0 = -a2; q1 = -a3; q2 = a0; q3 = a1;
+  } else if (unit == 0) {  // * k
+    q0 = -a3; q1 = a2; q2 = -a1; q3 = a0;
+  }
+  // left multiplication: (q w)_x = sum_z L[x][z] w_z
+  const double L[4][4] = {{q0, -q1, -q2, -q3},
+                          {q1, q0, -q3, q2},
+                          {q2, q3, q0, -q1},
+                          {q3, -q2, q1, q0}};
   for (int z = 0; z < 4; ++z)
-    for (int x = 0; x < 4; ++x)
-      Chat[((int64_t)mu * 4 + z) * 4 * n + x * n + p] = coef[x][z];
+    for (int x = 0; x < 4; ++x) Chat[((int64_t)mu * 4 + z) * 4 * n + x * n + p] = L[x][z];
 }
 
-void launch_build_coef_mats(int N, int n, const double *C, double *Call, double *Chat,
-                            hipStream_t s) {
+void launch_build_coef_mats(int N, int n, const double *C, int unit, double *Call,
+                            double *Chat, hipStream_t s) {
   int64_t tot = (int64_t)N * n;
   if (tot <= 0) return;
   hipLaunchKernelGGL(k_build_coef_mats, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, N,
-                     n, C, Call, Chat);
+                     n, C, unit, Call, Chat);
 }
 
 // LDS transpose: 64 (nu) x 64 (columns) per workgroup, fixed mu.
-__global__ void __launch_bounds__(256) k_unpack(int N, const int32_t *rowmap, const double *V,
-                                                int64_t ld, int64_t c0, int nc, double *Vfull) {
+__global__ void __launch_bounds__(256) k_unpack(int NA, int NB, const int32_t *rowmap,
+                                                const double *V, int64_t ld, int64_t col0,
+                                                int nc, double *Vfull) {
   __shared__ double tile[64][65];
   const int nu0 = blockIdx.x * 64, mu = blockIdx.y, cb = blockIdx.z * 64;
   for (int e = threadIdx.x; e < 64 * 64; e += 256) {
     int nl = e >> 6, cl = e & 63;
     int nu = nu0 + nl, c = cb + cl;
     double v = 0.0;
-    if (nu < N && c < nc) v = V[(int64_t)rowmap[(int64_t)mu * N + nu] * ld + c0 + c];
+    if (nu < NB && c < nc) v = V[(int64_t)rowmap[(int64_t)mu * NB + nu] * ld + col0 + c];
     tile[nl][cl] = v;
   }
   __syncthreads();
   for (int e = threadIdx.x; e < 64 * 64; e += 256) {
     int cl = e >> 6, nl = e & 63;
     int nu = nu0 + nl, c = cb + cl;
-    if (nu < N && c < nc) Vfull[((int64_t)c * N + mu) * N + nu] = tile[nl][cl];
+    if (nu < NB && c < nc) Vfull[((int64_t)c * NA + mu) * NB + nu] = tile[nl][cl];
   }
 }
 
-void launch_unpack(int N, const int32_t *rowmap, const double *V, int64_t ld, int64_t c0, int nc,
-                   double *Vfull, hipStream_t s) {
-  if (N <= 0 || nc <= 0) return;
-  dim3 grid((N + 63) / 64, N, (nc + 63) / 64);
-  hipLaunchKernelGGL(k_unpack, grid, dim3(256), 0, s, N, rowmap, V, ld, c0, nc, Vfull);
+void launch_unpack(int NA, int NB, const int32_t *rowmap, const double *V, int64_t ld,
+                   int64_t col0, int nc, double *Vfull, hipStream_t s) {
+  if (NA <= 0 || NB <= 0 || nc <= 0) return;
+  dim3 grid((NB + 63) / 64, NA, (nc + 63) / 64);
+  hipLaunchKernelGGL(k_unpack, grid, dim3(256), 0, s, NA, NB, rowmap, V, ld, col0, nc, Vfull);
 }
 
-// One thread per (MO pair r <= s of the chunk, p, q): 16 contiguous outputs.
+// One thread per (MO pair r <= s of the slice, p, q): 16 contiguous outputs.
 __global__ void k_pack(int n, const int32_t *rs, int64_t c0, int nc, const double *Gc,
-                       double *G) {
+                       double *G, double mirror, int accumulate) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t nidx = nc / 4;
   if (t >= nidx * n * n) return;
@@ -87,23 +96,39 @@ __global__ void k_pack(int n, const int32_t *rs, int64_t c0, int nc, const doubl
       v[x][y] = Gc[((il * 4 + y) * 4 * n + (int64_t)x * n + p) * n + q];
   double *o = G + ((((int64_t)p * n + q) * n + r) * n + s) * 16;
   for (int x = 0; x < 4; ++x)
-    for (int y = 0; y < 4; y += 2)
-      reinterpret_cast<double2 *>(o + x * 4 + y)[0] = make_double2(v[x][y], v[x][y + 1]);
+    for (int y = 0; y < 4; y += 2) {
+      double2 *d = reinterpret_cast<double2 *>(o + x * 4 + y);
+      double2 w = make_double2(v[x][y], v[x][y + 1]);
+      if (accumulate) {
+        double2 old = d[0];
+        w.x += old.x;
+        w.y += old.y;
+      }
+      d[0] = w;
+    }
   if (r != s) {
     double *m = G + ((((int64_t)p * n + q) * n + s) * n + r) * 16;
     for (int x = 0; x < 4; ++x)
-      for (int y = 0; y < 4; y += 2)
-        reinterpret_cast<double2 *>(m + x * 4 + y)[0] =
-            make_double2(y == 0 ? v[x][0] : -v[x][y], -v[x][y + 1]);
+      for (int y = 0; y < 4; y += 2) {
+        double2 *d = reinterpret_cast<double2 *>(m + x * 4 + y);
+        // s_y = +1 for y = 0, -1 otherwise
+        double2 w = make_double2(mirror * (y == 0 ? v[x][0] : -v[x][y]), -mirror * v[x][y + 1]);
+        if (accumulate) {
+          double2 old = d[0];
+          w.x += old.x;
+          w.y += old.y;
+        }
+        d[0] = w;
+      }
   }
 }
 
 void launch_pack(int n, const int32_t *rs, int64_t c0, int nc, const double *Gc, double *G,
-                 hipStream_t s) {
+                 double mirror, int accumulate, hipStream_t s) {
   int64_t tot = (int64_t)(nc / 4) * n * n;
   if (tot <= 0) return;
   hipLaunchKernelGGL(k_pack, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, rs, c0, nc,
-                     Gc, G);
+                     Gc, G, mirror, accumulate);
 }
 
 }  // namespace qdcb

@@ -31,13 +31,16 @@ void launch_eri_list(int64_t nq, const int64_t *a_first, const int64_t *b_first,
                      PrimPairsC B, double *out, hipStream_t s);
 
 // ---- densities (k_density.hip)
-// Pair densities D~[row][4*idx(r,s)+y] for r <= s and Dmax[row].
 struct DensityArgs {
+  int gaunt;              // 0: Coulomb rows (LL/SS), 1: Gaunt rows (LS)
+  int bound_only;         // 1: Dmax over all MO pairs, no D writes
   int64_t nrows;          // padded pair rows
   int n;                  // MOs
   int npair_mo;           // n(n+1)/2
-  int64_t ld;             // row stride of D (>= 4*npair_mo)
-  const int32_t *cls;     // [nrows] 0 = L, 1 = S, -1 = padding
+  int i0, i1;             // MO-pair range written (write launches)
+  int64_t ld;             // row stride of D
+  int64_t ldK;            // Gaunt: stride between the K blocks of a row
+  const int32_t *cls;     // [nrows] 0 = L, 1 = S (Gaunt: 0), -1 = padding
   const int32_t *mu;      // [nrows]
   const int32_t *nu;      // [nrows]
   const double *CL;       // [4][NL][n]
@@ -74,7 +77,7 @@ struct EriTileArgs {
   const int32_t *cls;         // [nrows]
   double tau;
   double *panel;              // [slots][64 ket][64 bra]
-  unsigned long long *kept;   // [4] kept directed contributions per class pair
+  unsigned long long *kept;   // [4] kept directed contributions per class pair, or NULL
 };
 void launch_eri_tiles(const EriTileArgs &a, int64_t nslots, hipStream_t s);
 
@@ -89,7 +92,7 @@ struct FirstHalfArgs {
   const double *D;       // [nrows][ld]
   double *V;             // [nrows][ld]
   int64_t ld;
-  int ncol_tiles;        // ceil(ncol / 128)
+  int ncol_tiles;        // ld / 128
 };
 void launch_first_half(const FirstHalfArgs &a, hipStream_t s);
 
@@ -101,16 +104,18 @@ void launch_dgemm_batched(int transA, int M, int N, int K, double alpha, const d
                           int64_t strideC, int batch, hipStream_t s);
 
 // ---- second half (k_second.hip)
-// Cq[nu][z*n + q] = C[z][nu][q];  Chat[(mu,z)][(x,p)] = coefficient of W_z in
-// [conj(C_mu p) W]_x.
-void launch_build_coef_mats(int N, int n, const double *C, double *Call, double *Chat,
-                            hipStream_t s);
-// Vfull[c][mu][nu] = V[rowmap[mu*N + nu]][c0 + c] for c < nc.
-void launch_unpack(int N, const int32_t *rowmap, const double *V, int64_t ld, int64_t c0,
-                   int nc, double *Vfull, hipStream_t s);
-// Scatter Gc[c][(x,p)][q] (columns c0..c0+nc of the (r<=s, y) column space) into
-// G[p][q][r][s][x][y] and mirror r<->s with the sign of component y.
+// Call[nu][z*n + q] = C[z][nu][q] and Chat[(mu,z)][(x,p)] = L(a)[x][z] with
+// a = conj(C_mu p) * e (e = 1 for unit < 0, else e_x = k, e_y = j, e_z = i for
+// unit = 0, 1, 2) and L(a) the matrix of left multiplication by a.
+void launch_build_coef_mats(int N, int n, const double *C, int unit, double *Call,
+                            double *Chat, hipStream_t s);
+// Vfull[c][mu][nu] = V[rowmap[mu*NB + nu]][col0 + c] for c < nc (mu < NA, nu < NB).
+void launch_unpack(int NA, int NB, const int32_t *rowmap, const double *V, int64_t ld,
+                   int64_t col0, int nc, double *Vfull, hipStream_t s);
+// Scatter Gc[c][(x,p)][q] for MO-pair columns c of [c0, c0+nc) (c = 4 idx + y)
+// into G[p][q][r][s][x][y] and its mirror G[p][q][s][r][x][y] = mirror * s_y * v,
+// s = (+1,-1,-1,-1); accumulate = 1 adds to G instead of storing.
 void launch_pack(int n, const int32_t *rs, int64_t c0, int nc, const double *Gc, double *G,
-                 hipStream_t s);
+                 double mirror, int accumulate, hipStream_t s);
 
 }  // namespace qdcb

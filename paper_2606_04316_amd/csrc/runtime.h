@@ -1,0 +1,164 @@
+// runtime.h -- host-side objects of the qdcb runtime (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/qdcb.h"
+#include "kernels.h"
+
+namespace qdcb {
+
+extern thread_local std::string g_err;
+
+struct Fail {
+  qdcb_status st;
+  std::string msg;
+};
+
+[[noreturn]] inline void fail(qdcb_status st, const std::string &m) { throw Fail{st, m}; }
+
+inline void hip_check(hipError_t e, const char *what) {
+  if (e != hipSuccess) fail(QDCB_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+#define HIPC(x) ::qdcb::hip_check((x), #x)
+
+template <class F>
+qdcb_status guarded(F &&f) {
+  try {
+    f();
+    g_err.clear();
+    return QDCB_OK;
+  } catch (const Fail &e) {
+    g_err = e.msg;
+    return e.st;
+  } catch (const std::bad_alloc &) {
+    g_err = "host allocation failed";
+    return QDCB_E_NOMEM;
+  } catch (const std::exception &e) {
+    g_err = e.what();
+    return QDCB_E_DEVICE;
+  }
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    HIPC(hipGetDevice(&prev));
+    if (prev != dev) HIPC(hipSetDevice(dev));
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+}  // namespace qdcb
+
+struct qdcb_ctx {
+  int device = 0;
+  size_t budget = 0;
+  size_t used = 0;
+
+  void *alloc(size_t bytes) {
+    if (bytes == 0) return nullptr;
+    if (used + bytes > budget)
+      qdcb::fail(QDCB_E_NOMEM, "device memory budget exceeded (" + std::to_string(used + bytes) +
+                                   " > " + std::to_string(budget) + " bytes)");
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess)
+      qdcb::fail(QDCB_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    used += bytes;
+    return p;
+  }
+  void release(void *p, size_t bytes) {
+    if (!p) return;
+    (void)hipFree(p);
+    used -= bytes;
+  }
+  size_t room() const { return budget > used ? budget - used : 0; }
+};
+
+namespace qdcb {
+
+// Device buffer owned by a context.
+template <class T>
+struct DBuf {
+  qdcb_ctx *ctx = nullptr;
+  T *p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf &) = delete;
+  DBuf &operator=(const DBuf &) = delete;
+  ~DBuf() { free(); }
+  void alloc(qdcb_ctx *c, size_t count) {
+    free();
+    ctx = c;
+    n = count;
+    p = static_cast<T *>(c->alloc(count * sizeof(T)));
+  }
+  void upload(qdcb_ctx *c, const std::vector<T> &v) {
+    alloc(c, v.size());
+    if (!v.empty()) HIPC(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  }
+  void free() {
+    if (ctx && p) ctx->release(p, n * sizeof(T));
+    p = nullptr;
+    n = 0;
+  }
+  size_t bytes() const { return n * sizeof(T); }
+};
+
+struct PairStore {
+  DBuf<double> p, x, y, z, e;
+  void alloc(qdcb_ctx *c, size_t n) {
+    p.alloc(c, n);
+    x.alloc(c, n);
+    y.alloc(c, n);
+    z.alloc(c, n);
+    e.alloc(c, n);
+  }
+  PrimPairs view() { return PrimPairs{p.p, x.p, y.p, z.p, e.p}; }
+  PrimPairsC cview() const { return PrimPairsC(PrimPairs{p.p, x.p, y.p, z.p, e.p}); }
+  void free() {
+    p.free();
+    x.free();
+    y.free();
+    z.free();
+    e.free();
+  }
+  size_t bytes() const { return p.bytes() * 5; }
+};
+
+}  // namespace qdcb
+
+struct qdcb_basis {
+  qdcb_ctx *ctx = nullptr;
+  int nfunc = 0;
+  std::vector<int32_t> first;       // primitive offsets [nfunc+1]
+  std::vector<int32_t> nprim;       // [nfunc]
+  std::vector<int64_t> pair_first;  // canonical pairs (mu <= nu, nu-major) [npairs+1]
+  std::vector<double> Q;            // host copy of the Schwarz factors
+  int64_t npairs = 0;
+  qdcb::DBuf<double> cent, exps, coefs, nc;
+  qdcb::DBuf<int32_t> dfirst;
+  qdcb::DBuf<int64_t> dpair_first;
+  qdcb::PairStore pp;
+  qdcb::DBuf<double> dQ;
+
+  static int64_t canon(int mu, int nu) {
+    if (mu > nu) std::swap(mu, nu);
+    return (int64_t)nu * (nu + 1) / 2 + mu;
+  }
+};

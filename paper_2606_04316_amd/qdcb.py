@@ -46,14 +46,13 @@ class Stats(ctypes.Structure):
                 ("tiles_kept", ctypes.c_int64), ("tiles_total", ctypes.c_int64),
                 ("flops_first_half", ctypes.c_double), ("flops_second_half", ctypes.c_double),
                 ("flops_mfma", ctypes.c_double), ("n_batches", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("n_chunks", ctypes.c_int32)]
 
     def as_dict(self):
         d = {}
         for name, _ in self._fields_:
             v = getattr(self, name)
             d[name] = list(v) if isinstance(v, ctypes.Array) else v
-        d.pop("pad", None)
         return d
 
 
@@ -68,6 +67,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first")
+        # torch ships its own HIP runtime (same soname); load it first so that the
+        # library binds to that one and device pointers and streams are shared.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         L.qdcb_abi_version.restype = ctypes.c_int
         L.qdcb_last_error.restype = ctypes.c_char_p

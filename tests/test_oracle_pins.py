@@ -335,3 +335,20 @@ def test_zero_threshold_keeps_everything_including_zeros():
     G1, st1 = oracle.transform_direct(s.L, None, C, None, "LL", 1e-300)
     assert st1["kept"][0] < st1["total"][0]
     assert np.array_equal(G0, G1)
+
+
+def test_gaunt_density_bound_matches_direct_route_screening():
+    # orc_dmax_gaunt (quaternion products) against the direct route, whose Gaunt
+    # bound is read off the sigma_K spinor densities: identical kept counts.
+    s = wl.linear_chain(seed=17, n_atoms=4, spacing=3.0, nl_per_atom=2, ns_per_atom=2, n=3)
+    QLS = oracle.schwarz(s.L, s.S)
+    D = oracle.dmax_gaunt(s.CL, s.CS)
+    q = QLS.reshape(-1)
+    d = D.reshape(-1)
+    b = np.outer(q, q * d)
+    tau = float(np.quantile(b, 0.5))
+    kept = int(((q[:, None] * q[None, :]) * d[None, :] >= tau).sum())
+    _, st = oracle.transform_direct(s.L, s.S, s.CL, s.CS, "GAUNT", tau, second_half=False)
+    assert st["tie_band"] == 0
+    assert st["kept_gaunt"] == kept
+    assert 0 < kept < q.size ** 2
