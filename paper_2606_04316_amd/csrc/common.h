@@ -8,45 +8,52 @@ namespace qdcb {
 
 constexpr int TILE = 64;  // pairs per bra/ket tile (one wavefront of bra rows)
 constexpr double PI = 3.14159265358979323846;
-// sqrt(2) * pi^(5/4): folded into every primitive-pair prefactor so that
-// E_ij E_kl = 2 pi^(5/2) c_i c_j c_k c_l K_ij K_kl / (p q).
-constexpr double SQRT2_PI54 = 5.914967172795613;
+constexpr double TWO_OVER_SQRTPI = 1.1283791670955126;
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-// Primitive-pair data of the Gaussian product exp(-a|r-A|^2) exp(-b|r-B|^2)
-// = K_ab exp(-p|r-P|^2), structure of arrays indexed by primitive pair.
+// Primitive-pair data of the Gaussian product
+//   c_a exp(-a|r-A|^2) c_b exp(-b|r-B|^2) = c_a c_b K_ab exp(-p|r-P|^2),
+// p = a + b, K_ab = exp(-ab/p |A-B|^2), stored as structure of arrays:
+//   ip = 1/p,  P,  e = c_a c_b K_ab (pi/p)^{3/2}  (the charge of the product).
+// The s-type ERI of two such charge distributions is
+//   [ab|cd] = e_ab e_cd erf(sqrt(rho) R) / R,  R = |P - Q|, 1/rho = 1/p + 1/q,
+// i.e. 2 pi^{5/2} / (p q sqrt(p+q)) K_ab K_cd F0(rho R^2) with the Boys
+// function in its erf form F0(T) = (1/2) sqrt(pi/T) erf(sqrt T).
 struct PrimPairs {
-  double *p;   // a + b
-  double *x;   // P
+  double *ip;
+  double *x;
   double *y;
   double *z;
-  double *e;   // c_a c_b K_ab sqrt(2) pi^(5/4) / p
+  double *e;
 };
 
 struct PrimPairsC {
-  const double *p, *x, *y, *z, *e;
-  __host__ __device__ PrimPairsC() : p(nullptr), x(nullptr), y(nullptr), z(nullptr), e(nullptr) {}
-  __host__ __device__ PrimPairsC(const PrimPairs &s) : p(s.p), x(s.x), y(s.y), z(s.z), e(s.e) {}
+  const double *ip, *x, *y, *z, *e;
+  __host__ __device__ PrimPairsC() : ip(nullptr), x(nullptr), y(nullptr), z(nullptr), e(nullptr) {}
+  __host__ __device__ PrimPairsC(const PrimPairs &s) : ip(s.ip), x(s.x), y(s.y), z(s.z), e(s.e) {}
 };
 
-// Boys function F0(T) = (1/2) sqrt(pi/T) erf(sqrt(T)); two Taylor terms where
-// T is too small for the closed form (T = 0 for concentric distributions).
-__device__ __forceinline__ double boys0(double T) {
-  if (T < 1e-12) return 1.0 - T * (1.0 / 3.0);
-  return 0.5 * sqrt(PI / T) * erf(sqrt(T));
+// erf(sqrt(rho) R) / R for one primitive quartet; two Taylor terms of
+// (2/sqrt(pi)) sqrt(rho) (1 - rho R^2 / 3 + ...) where rho R^2 is too small for
+// the quotient; erfc(6) < 2.2e-17, so erf is 1 to double precision beyond 6.
+__device__ __forceinline__ double coulomb_kernel(double ip, double px, double py, double pz,
+                                                 double iq, double qx, double qy, double qz) {
+  const double t = ip + iq;  // 1/rho
+  const double sr = rsqrt(t);
+  const double dx = px - qx, dy = py - qy, dz = pz - qz;
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double T = r2 * (sr * sr);
+  if (T < 1e-20) return TWO_OVER_SQRTPI * sr * (1.0 - T * (1.0 / 3.0));
+  const double iR = rsqrt(r2);
+  const double x = r2 * iR * sr;
+  return x >= 6.0 ? iR : erf(x) * iR;
 }
 
-// One primitive quartet: E_ij E_kl F0(pq/(p+q) |P-Q|^2) / sqrt(p+q).
-__device__ __forceinline__ double prim_quartet(double p, double px, double py, double pz,
-                                               double pe, double q, double qx, double qy,
+__device__ __forceinline__ double prim_quartet(double ip, double px, double py, double pz,
+                                               double pe, double iq, double qx, double qy,
                                                double qz, double qe) {
-  double s = p + q;
-  double is = 1.0 / s;
-  double dx = px - qx, dy = py - qy, dz = pz - qz;
-  double r2 = dx * dx + dy * dy + dz * dz;
-  double T = p * q * is * r2;
-  return pe * qe * boys0(T) * sqrt(is);
+  return pe * qe * coulomb_kernel(ip, px, py, pz, iq, qx, qy, qz);
 }
 
 // Contracted ERI between pair a (primitive pairs [a0, a1)) and pair b ([b0, b1)).
@@ -54,9 +61,11 @@ __device__ __forceinline__ double contracted_eri(const PrimPairsC &A, int64_t a0
                                                  const PrimPairsC &B, int64_t b0, int64_t b1) {
   double acc = 0.0;
   for (int64_t i = a0; i < a1; ++i) {
-    double p = A.p[i], px = A.x[i], py = A.y[i], pz = A.z[i], pe = A.e[i];
+    const double ip = A.ip[i], px = A.x[i], py = A.y[i], pz = A.z[i];
+    double s = 0.0;
     for (int64_t k = b0; k < b1; ++k)
-      acc += prim_quartet(p, px, py, pz, pe, B.p[k], B.x[k], B.y[k], B.z[k], B.e[k]);
+      s += B.e[k] * coulomb_kernel(ip, px, py, pz, B.ip[k], B.x[k], B.y[k], B.z[k]);
+    acc += A.e[i] * s;
   }
   return acc;
 }

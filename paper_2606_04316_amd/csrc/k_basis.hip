@@ -51,11 +51,12 @@ __global__ void k_pair_data(int64_t npairs, const int32_t *mu, const int32_t *nu
       double ea = eA[a], eb = eB[b];
       double p = ea + eb;
       double ip = 1.0 / p;
-      out.p[o] = p;
+      out.ip[o] = ip;
       out.x[o] = (ea * Ax + eb * Bx) * ip;
       out.y[o] = (ea * Ay + eb * By) * ip;
       out.z[o] = (ea * Az + eb * Bz) * ip;
-      out.e[o] = nA[a] * nB[b] * exp(-ea * eb * ip * r2) * SQRT2_PI54 * ip;
+      double pp = PI * ip;
+      out.e[o] = nA[a] * nB[b] * exp(-ea * eb * ip * r2) * pp * sqrt(pp);
       ++o;
     }
 }
@@ -82,7 +83,7 @@ __global__ void __launch_bounds__(256) k_schwarz(int64_t npairs, const int64_t *
   double acc = 0.0;
   for (int t = lane; t < k * k; t += 64) {
     int64_t i = f0 + t / k, j = f0 + t % k;
-    acc += prim_quartet(pp.p[i], pp.x[i], pp.y[i], pp.z[i], pp.e[i], pp.p[j], pp.x[j],
+    acc += prim_quartet(pp.ip[i], pp.x[i], pp.y[i], pp.z[i], pp.e[i], pp.ip[j], pp.x[j],
                         pp.y[j], pp.z[j], pp.e[j]);
   }
   acc = wave_sum(acc);
@@ -96,26 +97,68 @@ void launch_schwarz(int64_t npairs, const int64_t *pair_first, PrimPairsC pp, do
                      pair_first, pp, Q);
 }
 
-__global__ void k_gather_pairs(int64_t nrows, const int64_t *src_first, const int32_t *cnt,
-                               const int64_t *dst_first, PrimPairsC src, PrimPairs dst) {
+// Primitive-pair screening.  With q_i = |e_i| p_i^{1/4} proportional to the
+// primitive Schwarz factor sqrt([i|i]) and S = sum_i q_i over the n primitive
+// pairs of a row, a primitive pair with q_i <= eps S / n is dropped.  Every
+// primitive integral obeys |[i|k]| <= sqrt([i|i][k|k]), so the dropped part of
+// any contracted integral (A|B) is at most 2 eps S_A S_B in Schwarz units:
+// about eps of the sum of its absolute primitive contributions.
+__device__ __forceinline__ double prim_weight(const PrimPairsC &s, int64_t i) {
+  return fabs(s.e[i]) * sqrt(sqrt(1.0 / s.ip[i]));
+}
+
+__device__ __forceinline__ double row_cut(const PrimPairsC &s, int64_t s0, int n, double eps) {
+  double S = 0.0;
+  for (int i = 0; i < n; ++i) S += prim_weight(s, s0 + i);
+  return eps * S / (double)(n > 0 ? n : 1);
+}
+
+__global__ void k_prim_count(int64_t nrows, const int64_t *src_first, const int32_t *cnt,
+                             PrimPairsC src, double eps, int32_t *kept) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrows) return;
-  int64_t s0 = src_first[r], d0 = dst_first[r];
-  for (int i = 0; i < cnt[r]; ++i) {
-    dst.p[d0 + i] = src.p[s0 + i];
-    dst.x[d0 + i] = src.x[s0 + i];
-    dst.y[d0 + i] = src.y[s0 + i];
-    dst.z[d0 + i] = src.z[s0 + i];
-    dst.e[d0 + i] = src.e[s0 + i];
+  const int64_t s0 = src_first[r];
+  const int n = cnt[r];
+  const double cut = row_cut(src, s0, n, eps);
+  int k = 0;
+  for (int i = 0; i < n; ++i) k += prim_weight(src, s0 + i) > cut ? 1 : 0;
+  kept[r] = k;
+}
+
+void launch_prim_count(int64_t nrows, const int64_t *src_first, const int32_t *cnt,
+                       PrimPairsC src, double eps, int32_t *kept, hipStream_t s) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL(k_prim_count, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, s, nrows,
+                     src_first, cnt, src, eps, kept);
+}
+
+__global__ void k_gather_pairs(int64_t nrows, const int64_t *src_first, const int32_t *cnt,
+                               const int64_t *dst_first, PrimPairsC src, PrimPairs dst,
+                               double eps) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  const int64_t s0 = src_first[r];
+  const int n = cnt[r];
+  const double cut = row_cut(src, s0, n, eps);
+  int64_t d = dst_first[r];
+  for (int i = 0; i < n; ++i) {
+    const int64_t si = s0 + i;
+    if (!(prim_weight(src, si) > cut)) continue;
+    dst.ip[d] = src.ip[si];
+    dst.x[d] = src.x[si];
+    dst.y[d] = src.y[si];
+    dst.z[d] = src.z[si];
+    dst.e[d] = src.e[si];
+    ++d;
   }
 }
 
 void launch_gather_pairs(int64_t nrows, const int64_t *src_first, const int32_t *cnt,
-                         const int64_t *dst_first, PrimPairsC src, PrimPairs dst,
+                         const int64_t *dst_first, PrimPairsC src, PrimPairs dst, double eps,
                          hipStream_t s) {
   if (nrows <= 0) return;
   hipLaunchKernelGGL(k_gather_pairs, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, s,
-                     nrows, src_first, cnt, dst_first, src, dst);
+                     nrows, src_first, cnt, dst_first, src, dst, eps);
 }
 
 __global__ void k_eri_list(int64_t nq, const int64_t *af, const int64_t *bf, const int32_t *ac,

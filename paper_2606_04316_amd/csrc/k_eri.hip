@@ -2,31 +2,39 @@
 //
 // For every kept (bra tile, ket tile) a 64 x 64 block of contracted s-type
 // ERIs (mn|kl) is generated from the primitive-pair data (Gaussian product
-// theorem + Boys F0) and stored as panel[slot][ket j][bra m].  Each element
-// is masked individually by the directed density-weighted Schwarz predicate
-// of Eq. (SchwarzDen): it is computed only when (Q_mn * Q_kl) * Dmax_kl >= tau
-// and is 0 otherwise, which is exactly the skip of that contribution.
+// theorem, Boys F0 in erf form) and stored as panel[slot][ket j][bra m].  Each
+// element is masked individually by the directed density-weighted Schwarz
+// predicate of Eq. (SchwarzDen): it is computed only when
+// (Q_mn * Q_kl) * Dmax_kl >= tau and is 0 otherwise, which is exactly the skip
+// of that contribution.
 //
-// Work layout: 4 wavefronts x 16 ket rows each; lane = bra row.  The ket
-// pair of a wavefront is uniform across its lanes, so its primitive data
-// comes through scalar loads; the bra primitive data is per lane.  Stores are
-// one 512-byte row of 64 bra values per ket row (coalesced).
+// Work layout: 4 wavefronts x 16 ket rows each; lane = bra row.  The primitive
+// pairs of the 64 bra rows are contiguous in the sorted store and are staged in
+// LDS once per workgroup when they fit; the ket pair of a wavefront is uniform
+// across its lanes, so its primitive data comes through scalar loads.  Stores
+// are one 512-byte row of 64 bra values per ket row (coalesced).
 #include "kernels.h"
 
 namespace qdcb {
 
-__global__ void __launch_bounds__(256) k_eri_tiles(EriTileArgs a) {
-  const int64_t slot = a.slot0 + blockIdx.x;
-  const int kt = a.tasks[slot];
-  const int bt = a.task_bra[slot];
-  const int lane = threadIdx.x & 63;
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+constexpr int ERI_LDS_PRIMS = 1536;  // 60 KB of bra primitive data
+
+template <bool LDS>
+__device__ __forceinline__ void eri_tile_body(const EriTileArgs &a, const double *sip,
+                                              const double *sx, const double *sy,
+                                              const double *sz, const double *se, int64_t bp0,
+                                              int kt, int bt, int lane, int w, double *out,
+                                              long long kept[4]) {
   const int64_t brow = (int64_t)bt * TILE + lane;
   const double qb = a.Q[brow];
   const int cb = a.cls[brow];
-  const int64_t bf0 = a.row_first[brow], bf1 = a.row_first[brow + 1];
-  double *out = a.panel + (int64_t)blockIdx.x * TILE * TILE;
-  long long kept[4] = {0, 0, 0, 0};
+  const int64_t bf0 = a.row_first[brow] - (LDS ? bp0 : 0);
+  const int64_t bf1 = a.row_first[brow + 1] - (LDS ? bp0 : 0);
+  const double *bip = LDS ? sip : a.pp.ip;
+  const double *bx = LDS ? sx : a.pp.x;
+  const double *by = LDS ? sy : a.pp.y;
+  const double *bz = LDS ? sz : a.pp.z;
+  const double *be = LDS ? se : a.pp.e;
   for (int i = 0; i < TILE / 4; ++i) {
     const int j = w + 4 * i;
     const int64_t krow = (int64_t)kt * TILE + j;
@@ -35,10 +43,44 @@ __global__ void __launch_bounds__(256) k_eri_tiles(EriTileArgs a) {
     const int64_t kf0 = a.row_first[krow], kf1 = a.row_first[krow + 1];
     double v = 0.0;
     if ((qb * qk) * dk >= a.tau) {
-      v = contracted_eri(a.pp, bf0, bf1, a.pp, kf0, kf1);
+      for (int64_t k = kf0; k < kf1; ++k) {
+        const double iq = a.pp.ip[k], qx = a.pp.x[k], qy = a.pp.y[k], qz = a.pp.z[k];
+        double s = 0.0;
+        for (int64_t b = bf0; b < bf1; ++b)
+          s += be[b] * coulomb_kernel(bip[b], bx[b], by[b], bz[b], iq, qx, qy, qz);
+        v += a.pp.e[k] * s;
+      }
       if (cb >= 0 && ck >= 0) kept[cb * 2 + ck] += 1;
     }
     out[j * TILE + lane] = v;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_eri_tiles(EriTileArgs a) {
+  __shared__ double sip[ERI_LDS_PRIMS], sx[ERI_LDS_PRIMS], sy[ERI_LDS_PRIMS],
+      sz[ERI_LDS_PRIMS], se[ERI_LDS_PRIMS];
+  const int64_t slot = a.slot0 + blockIdx.x;
+  const int kt = a.tasks[slot];
+  const int bt = a.task_bra[slot];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t bp0 = a.row_first[(int64_t)bt * TILE];
+  const int64_t nbp = a.row_first[(int64_t)bt * TILE + TILE] - bp0;
+  double *out = a.panel + (int64_t)blockIdx.x * TILE * TILE;
+  long long kept[4] = {0, 0, 0, 0};
+  if (nbp <= ERI_LDS_PRIMS) {
+    for (int64_t t = threadIdx.x; t < nbp; t += 256) {
+      sip[t] = a.pp.ip[bp0 + t];
+      sx[t] = a.pp.x[bp0 + t];
+      sy[t] = a.pp.y[bp0 + t];
+      sz[t] = a.pp.z[bp0 + t];
+      se[t] = a.pp.e[bp0 + t];
+    }
+    __syncthreads();
+    eri_tile_body<true>(a, sip, sx, sy, sz, se, bp0, kt, bt, lane, w, out, kept);
+  } else {
+    eri_tile_body<false>(a, nullptr, nullptr, nullptr, nullptr, nullptr, bp0, kt, bt, lane, w,
+                         out, kept);
   }
   if (a.kept) {
     for (int c = 0; c < 4; ++c) {

@@ -20,10 +20,15 @@ void launch_pair_data(int64_t npairs, const int32_t *mu, const int32_t *nu,
 // Q[i] = sqrt((i|i)) over the primitive pairs [pair_first[i], pair_first[i+1]).
 void launch_schwarz(int64_t npairs, const int64_t *pair_first, PrimPairsC pp, double *Q,
                     hipStream_t s);
-// Gather pair rows into a new order: row r takes cnt[r] primitive pairs from
-// src_first[r] and stores them at dst_first[r].
+// Primitive-pair screening: kept[r] = number of the cnt[r] primitive pairs of
+// row r (starting at src_first[r]) whose Schwarz weight exceeds eps times the
+// row's mean weight.
+void launch_prim_count(int64_t nrows, const int64_t *src_first, const int32_t *cnt,
+                       PrimPairsC src, double eps, int32_t *kept, hipStream_t s);
+// Gather pair rows into a new order: row r takes its kept primitive pairs
+// (same criterion) from src_first[r] and stores them from dst_first[r] on.
 void launch_gather_pairs(int64_t nrows, const int64_t *src_first, const int32_t *cnt,
-                         const int64_t *dst_first, PrimPairsC src, PrimPairs dst,
+                         const int64_t *dst_first, PrimPairsC src, PrimPairs dst, double eps,
                          hipStream_t s);
 // ERIs of explicit quartets (test entry point): out[q] = (pair a[q] | pair b[q]).
 void launch_eri_list(int64_t nq, const int64_t *a_first, const int64_t *b_first,

@@ -49,6 +49,10 @@ struct Space {
   }
 };
 
+// Primitive pairs whose Schwarz weight is below 1e-17 of their row's mean are
+// dropped (bounded effect: ~1e-17 of the sum of absolute primitive terms).
+constexpr double PRIM_EPS = 1e-17;
+
 // Sorted rows of a space: order by decreasing Q (stable in the input order).
 struct RowSrc {
   double Q;
@@ -72,9 +76,9 @@ void build_space(qdcb_ctx *ctx, Space &sp, std::vector<RowSrc> &rows,
   sp.h_nu.assign(sp.Ppad, 0);
   sp.h_key.assign(sp.Ppad, -1);
   std::vector<double> hQ(sp.Ppad, 0.0);
-  std::vector<int64_t> rf(sp.Ppad + 1, 0);
-  std::vector<std::vector<int64_t>> src(stores.size()), dst(stores.size());
-  std::vector<std::vector<int32_t>> cnt(stores.size());
+  const size_t ns = stores.size();
+  std::vector<std::vector<int64_t>> src(ns), dst(ns), rowidx(ns);
+  std::vector<std::vector<int32_t>> cnt(ns);
   for (int64_t r = 0; r < sp.P; ++r) {
     const RowSrc &s = rows[r];
     sp.h_cls[r] = s.cls;
@@ -82,27 +86,43 @@ void build_space(qdcb_ctx *ctx, Space &sp, std::vector<RowSrc> &rows,
     sp.h_nu[r] = s.nu;
     sp.h_key[r] = s.key;
     hQ[r] = s.Q;
-    rf[r + 1] = rf[r] + s.cnt;
     src[s.which].push_back(s.src_first);
-    dst[s.which].push_back(rf[r]);
     cnt[s.which].push_back(s.cnt);
+    rowidx[s.which].push_back(r);
   }
-  for (int64_t r = sp.P; r < sp.Ppad; ++r) rf[r + 1] = rf[r];
+  // primitive pairs kept per row after primitive screening
+  std::vector<DBuf<int64_t>> dsrc(ns);
+  std::vector<DBuf<int32_t>> dcnt(ns);
+  std::vector<int32_t> kept_prims(sp.Ppad, 0);
+  for (size_t w = 0; w < ns; ++w) {
+    if (src[w].empty()) continue;
+    dsrc[w].upload(ctx, src[w]);
+    dcnt[w].upload(ctx, cnt[w]);
+    DBuf<int32_t> dk;
+    dk.alloc(ctx, src[w].size());
+    launch_prim_count((int64_t)src[w].size(), dsrc[w].p, dcnt[w].p, stores[w]->cview(),
+                      PRIM_EPS, dk.p, nullptr);
+    HIPC(hipGetLastError());
+    std::vector<int32_t> k(src[w].size());
+    HIPC(hipMemcpy(k.data(), dk.p, k.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < k.size(); ++i) kept_prims[rowidx[w][i]] = k[i];
+  }
+  std::vector<int64_t> rf(sp.Ppad + 1, 0);
+  for (int64_t r = 0; r < sp.Ppad; ++r) rf[r + 1] = rf[r] + kept_prims[r];
+  for (size_t w = 0; w < ns; ++w)
+    for (int64_t r : rowidx[w]) dst[w].push_back(rf[r]);
   sp.cls.upload(ctx, sp.h_cls);
   sp.mu.upload(ctx, sp.h_mu);
   sp.nu.upload(ctx, sp.h_nu);
   sp.Q.upload(ctx, hQ);
   sp.row_first.upload(ctx, rf);
   sp.pp.alloc(ctx, (size_t)std::max<int64_t>(rf[sp.Ppad], 1));
-  for (size_t w = 0; w < stores.size(); ++w) {
+  for (size_t w = 0; w < ns; ++w) {
     if (src[w].empty()) continue;
-    DBuf<int64_t> ds, dd;
-    DBuf<int32_t> dc;
-    ds.upload(ctx, src[w]);
+    DBuf<int64_t> dd;
     dd.upload(ctx, dst[w]);
-    dc.upload(ctx, cnt[w]);
-    launch_gather_pairs((int64_t)src[w].size(), ds.p, dc.p, dd.p, stores[w]->cview(),
-                        sp.pp.view(), nullptr);
+    launch_gather_pairs((int64_t)src[w].size(), dsrc[w].p, dcnt[w].p, dd.p, stores[w]->cview(),
+                        sp.pp.view(), PRIM_EPS, nullptr);
     HIPC(hipGetLastError());
     HIPC(hipDeviceSynchronize());
   }
@@ -118,7 +138,7 @@ void build_space(qdcb_ctx *ctx, Space &sp, std::vector<RowSrc> &rows,
 
 struct qdcb_plan {
   qdcb_ctx *ctx = nullptr;
-  const qdcb_basis *L = nullptr, *S = nullptr;
+  int64_t nLL = 0, nSS = 0;  // pair counts of the bases (plans do not keep basis pointers)
   qdcb_plan_desc desc{};
   int n = 0, NL = 0, NS = 0;
   int npair_mo = 0;
@@ -154,8 +174,8 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
     std::unique_ptr<qdcb_plan> pl(new qdcb_plan());
     qdcb_plan &p = *pl;
     p.ctx = ctx;
-    p.L = L;
-    p.S = S;
+    p.nLL = L->npairs;
+    p.nSS = S ? S->npairs : 0;
     p.desc = *desc;
     p.n = desc->n_mo;
     p.NL = L->nfunc;
@@ -261,13 +281,27 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
         p.BhatK[K].alloc(ctx, (size_t)4 * p.NS * 4 * p.n);
       }
 
+    // --- task lists: one slot per (bra tile, ket tile), the worst case
+    for (Space *sp : {&p.C, &p.G}) {
+      if (sp == &p.G && !p.gaunt) continue;
+      size_t cap = (size_t)sp->ntiles * (size_t)sp->ntiles;
+      sp->tasks.alloc(ctx, cap);
+      sp->task_bra.alloc(ctx, cap);
+    }
+    // room left for the sized buffers, keeping space for the G staging buffer
+    // of host-pointer transforms
+    const size_t g_stage = sizeof(double) * (size_t)p.n * p.n * p.n * p.n * 16;
+    auto room = [&]() -> size_t {
+      size_t r = ctx->room();
+      return r > g_stage ? r - g_stage : 0;
+    };
     // --- first-half column chunk: D~ and V of both spaces within ~45% of the room
     auto dv_bytes = [&](int64_t ci) {
       int64_t ldK = round_up(4 * ci, 128);
       return (double)16 * ((double)p.C.Ppad * ldK + (p.gaunt ? 3.0 * p.G.Ppad * ldK : 0.0));
     };
     int64_t ci = p.npair_mo;
-    const double room0 = (double)ctx->room();
+    const double room0 = (double)room();
     while (ci > 32 && dv_bytes(ci) > 0.45 * room0) ci = std::max<int64_t>(32, (ci / 2) / 32 * 32);
     if (dv_bytes(ci) > 0.6 * room0) fail(QDCB_E_NOMEM, "no room for a 32-MO-pair column chunk");
     p.ci = (int)ci;
@@ -285,7 +319,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
       if (p.gaunt) vmax = std::max<int64_t>(vmax, (int64_t)p.NL * p.NS);
       int64_t wmax = (int64_t)std::max(p.NL, p.NS) * 4 * p.n;
       size_t per_col = sizeof(double) * (size_t)(vmax + wmax + (int64_t)4 * p.n * p.n);
-      int64_t sc = (int64_t)(ctx->room() / 8 / per_col);
+      int64_t sc = (int64_t)(room() / 8 / per_col);
       sc = std::min<int64_t>(sc, 4 * ci);
       sc = std::min<int64_t>(sc, 65532);
       sc = sc >= 64 ? sc / 64 * 64 : sc / 4 * 4;  // whole MO pairs (4 columns each)
@@ -301,25 +335,28 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
       int nsp = p.gaunt ? 2 : 1;
       for (Space *sp : {&p.C, &p.G}) {
         if (sp == &p.G && !p.gaunt) continue;
-        int64_t slots = (int64_t)(ctx->room() / 4 / nsp / slot_bytes);
-        if (sp == &p.G) slots = (int64_t)(ctx->room() / 4 / slot_bytes);
+        int64_t slots = (int64_t)(room() / 4 / nsp / slot_bytes);
+        if (sp == &p.G) slots = (int64_t)(room() / 4 / slot_bytes);
         slots = std::min<int64_t>(slots, (int64_t)1 << 22);
         if (slots < sp->ntiles) fail(QDCB_E_NOMEM, "no room for one bra row of integral tiles");
         sp->panel_slots = slots;
         sp->panel.alloc(ctx, (size_t)slots * TILE * TILE);
       }
     }
+    ctx->retain();
     *out = pl.release();
   });
 }
 
 void qdcb_plan_destroy(qdcb_plan *p) {
   if (!p) return;
+  qdcb_ctx *ctx = p->ctx;
   int prev = -1;
   (void)hipGetDevice(&prev);
-  (void)hipSetDevice(p->ctx->device);
+  (void)hipSetDevice(ctx->device);
   delete p;
   if (prev >= 0) (void)hipSetDevice(prev);
+  qdcb_ctx::release_ref(ctx);
 }
 
 qdcb_status qdcb_plan_footprint(const qdcb_plan *p, size_t *bytes) {
@@ -431,11 +468,7 @@ void screen(qdcb_plan &p, Space &sp, hipStream_t s) {
   }
   HIPC(hipMemcpyAsync(sp.slot_base.p, sp.base.data(), sp.base.size() * sizeof(int64_t),
                       hipMemcpyHostToDevice, s));
-  if ((int64_t)sp.tasks.n < std::max<int64_t>(sp.total, 1)) {
-    HIPC(hipStreamSynchronize(s));
-    sp.tasks.alloc(p.ctx, (size_t)std::max<int64_t>(sp.total, 1));
-    sp.task_bra.alloc(p.ctx, (size_t)std::max<int64_t>(sp.total, 1));
-  }
+  if ((int64_t)sp.tasks.n < sp.total) fail(QDCB_E_DEVICE, "task list capacity exceeded");
   launch_screen_fill(0, sp.ntiles, sp.ntiles, sp.Qmax.p, sp.Bmax.p, p.desc.tau,
                      sp.slot_base.p, sp.tasks.p, sp.task_bra.p, s);
   HIPC(hipMemsetAsync(sp.kept.p, 0, sp.kept.bytes(), s));
@@ -625,7 +658,7 @@ qdcb_status qdcb_transform(qdcb_plan *plan, const double *CL, const double *CS, 
         stats->kept[c] = (int64_t)kc[c];
         ktot += (double)kc[c];
       }
-      int64_t nLL = p.L->npairs, nSS = p.S ? p.S->npairs : 0;
+      const int64_t nLL = p.nLL, nSS = p.nSS;
       stats->total[0] = nLL * nLL;
       stats->total[1] = nLL * nSS;
       stats->total[2] = nSS * nLL;
@@ -670,7 +703,7 @@ qdcb_status qdcb_plan_fetch(const qdcb_plan *p, int32_t what, void *host_out, si
     HIPC(hipMemcpy(sorted.data(), dm ? sp.Dmax.p : sp.Q.p, sp.Ppad * sizeof(double),
                    hipMemcpyDeviceToHost));
     double *o = static_cast<double *>(host_out);
-    const int64_t nLL = p->L->npairs;
+    const int64_t nLL = p->nLL;
     for (int64_t r = 0; r < sp.P; ++r) {
       int64_t idx = sp.h_key[r];
       if (!gaunt_item && sp.h_cls[r] == 1) idx += nLL;

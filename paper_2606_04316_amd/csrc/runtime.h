@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -65,10 +66,18 @@ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 }  // namespace qdcb
 
+// A context lives until it has been destroyed by its owner and every basis
+// and plan created from it has been destroyed (reference count).
 struct qdcb_ctx {
   int device = 0;
   size_t budget = 0;
   size_t used = 0;
+  std::atomic<int> refs{1};
+
+  void retain() { refs.fetch_add(1); }
+  static void release_ref(qdcb_ctx *c) {
+    if (c && c->refs.fetch_sub(1) == 1) delete c;
+  }
 
   void *alloc(size_t bytes) {
     if (bytes == 0) return nullptr;

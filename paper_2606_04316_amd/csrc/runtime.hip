@@ -33,7 +33,7 @@ qdcb_status qdcb_ctx_create(int device, size_t budget, qdcb_ctx **out) {
   });
 }
 
-void qdcb_ctx_destroy(qdcb_ctx *ctx) { delete ctx; }
+void qdcb_ctx_destroy(qdcb_ctx *ctx) { qdcb_ctx::release_ref(ctx); }
 
 qdcb_status qdcb_basis_create(qdcb_ctx *ctx, int32_t nfunc, const double *centers,
                               const int32_t *nprim, const double *exps, const double *coefs,
@@ -94,17 +94,20 @@ qdcb_status qdcb_basis_create(qdcb_ctx *ctx, int32_t nfunc, const double *center
     HIPC(hipGetLastError());
     b->Q.resize(npairs);
     HIPC(hipMemcpy(b->Q.data(), b->dQ.p, npairs * sizeof(double), hipMemcpyDeviceToHost));
+    ctx->retain();
     *out = b.release();
   });
 }
 
 void qdcb_basis_destroy(qdcb_basis *b) {
   if (!b) return;
+  qdcb_ctx *ctx = b->ctx;
   int prev = -1;
   (void)hipGetDevice(&prev);
-  (void)hipSetDevice(b->ctx->device);
+  (void)hipSetDevice(ctx->device);
   delete b;
   if (prev >= 0) (void)hipSetDevice(prev);
+  qdcb_ctx::release_ref(ctx);
 }
 
 qdcb_status qdcb_basis_schwarz(const qdcb_basis *b, double *Q) {

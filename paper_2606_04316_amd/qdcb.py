@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libqdcb.so")
 HAM = {"LL": 0, "DC": 1, "DCG": 2}
 PREC = {"fp64": 0, "mixed": 1}
 PTR_DEVICE = 0x1
-FETCH_DMAX, FETCH_Q = 1, 2
+FETCH_DMAX, FETCH_Q, FETCH_DMAX_GAUNT, FETCH_Q_GAUNT = 1, 2, 3, 4
 
 STATUS = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_UNSUPPORTED"}
 
