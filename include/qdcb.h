@@ -123,6 +123,14 @@ void qdcb_plan_destroy(qdcb_plan *plan);
 /* Device bytes the plan holds (pair data excluded: it belongs to the bases). */
 qdcb_status qdcb_plan_footprint(const qdcb_plan *plan, size_t *bytes);
 
+/* Device bytes a plan for (L, S, desc) needs to hold every MO-pair column at
+ * once (no column chunking), with integral panels for up to 65,536 tiles per
+ * pair space or the full set of tiles, whichever is smaller: the admission
+ * size a request loop reserves before creating the plan in a context of that
+ * budget.  Host-side arithmetic only; nothing is allocated. */
+qdcb_status qdcb_plan_estimate(const qdcb_basis *L, const qdcb_basis *S,
+                               const qdcb_plan_desc *desc, size_t *bytes);
+
 typedef struct {
     double ms_total;         /* wall time of the transform on its stream */
     double ms_density;       /* pair densities + Dmax + tile bounds */
@@ -141,6 +149,8 @@ typedef struct {
     double flops_mfma;       /* MFMA flops issued by the first-half kernel (incl. masked) */
     int32_t n_batches;       /* first-half kernel launches */
     int32_t n_chunks;        /* MO-pair column chunks */
+    int32_t graph_replay;    /* 1: produced by qdcb_plan_replay */
+    int32_t graph_fallback;  /* 1: the replay's kept tiles outgrew the panel; redone eagerly */
 } qdcb_stats;
 
 /* Transform.  CL [4][N_L][n], CS [4][N_S][n] (NULL for LL), G [n^4][4][4];
@@ -149,6 +159,18 @@ typedef struct {
  * G is complete.  stats may be NULL. */
 qdcb_status qdcb_transform(qdcb_plan *plan, const double *CL, const double *CS, double *G,
                            uint32_t flags, void *hip_stream, qdcb_stats *stats);
+
+/* Re-transforms (e.g. successive orbital updates): record one whole
+ * transformation of the device buffers CL, CS -> G (which must stay valid)
+ * into a HIP graph on the non-null stream hip_stream; every step, including
+ * screening and task-list construction, stays on the device in fixed-capacity
+ * buffers.  qdcb_plan_replay launches it on hip_stream after the caller has
+ * written new coefficients into CL and CS, waits for it, and fills stats; if
+ * the new coefficients keep more integral tiles than the plan's panel holds,
+ * the replay is redone eagerly and stats->graph_fallback is set. */
+qdcb_status qdcb_plan_capture(qdcb_plan *plan, const double *CL, const double *CS, double *G,
+                              void *hip_stream);
+qdcb_status qdcb_plan_replay(qdcb_plan *plan, void *hip_stream, qdcb_stats *stats);
 
 /* Intermediates of the plan's last transform, copied to host memory.
  *   QDCB_FETCH_DMAX        float64 [P]: density bound Dmax of every Coulomb pair

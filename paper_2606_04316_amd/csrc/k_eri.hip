@@ -59,6 +59,7 @@ __device__ __forceinline__ void eri_tile_body(const EriTileArgs &a, const double
 __global__ void __launch_bounds__(256) k_eri_tiles(EriTileArgs a) {
   __shared__ double sip[ERI_LDS_PRIMS], sx[ERI_LDS_PRIMS], sy[ERI_LDS_PRIMS],
       sz[ERI_LDS_PRIMS], se[ERI_LDS_PRIMS];
+  if (a.d_total && (int64_t)blockIdx.x >= min(*a.d_total, a.cap)) return;  // uniform exit
   const int64_t slot = a.slot0 + blockIdx.x;
   const int kt = a.tasks[slot];
   const int bt = a.task_bra[slot];

@@ -88,6 +88,53 @@ __global__ void __launch_bounds__(256) k_screen_fill(int b0, int ntiles, const d
   }
 }
 
+// Device-side exclusive scan of the per-bra-tile counts (one workgroup of
+// 1024 threads, each over a contiguous run of counts): slot_base, the total,
+// and an overflow flag when the total exceeds the integral-panel capacity.
+__global__ void __launch_bounds__(1024) k_scan_counts(int ntiles, const int32_t *count,
+                                                      int64_t *slot_base, int64_t *total,
+                                                      int64_t capacity, int32_t *overflow) {
+  __shared__ int64_t part[1024];
+  const int t = threadIdx.x;
+  const int per = (ntiles + 1023) / 1024;
+  const int i0 = t * per, i1 = min(ntiles, i0 + per);
+  int64_t s = 0;
+  for (int i = i0; i < i1; ++i) s += count[i];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {  // Hillis-Steele inclusive scan
+    int64_t v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int64_t run = part[t] - s;
+  for (int i = i0; i < i1; ++i) {
+    slot_base[i] = run;
+    run += count[i];
+  }
+  if (t == 1023) {
+    *total = part[1023];
+    *overflow = part[1023] > capacity ? 1 : 0;
+  }
+}
+
+void launch_scan_counts(int ntiles, const int32_t *count, int64_t *slot_base, int64_t *total,
+                        int64_t capacity, int32_t *overflow, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, ntiles, count, slot_base, total,
+                     capacity, overflow);
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+void launch_zero_u64(unsigned long long *p, int n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_zero_u64, dim3((n + 63) / 64), dim3(64), 0, s, p, n);
+}
+
 void launch_screen_fill(int b0, int b1, int ntiles, const double *Qmax, const double *Bmax,
                         double tau, const int64_t *slot_base, int32_t *tasks,
                         int32_t *task_bra, hipStream_t s) {

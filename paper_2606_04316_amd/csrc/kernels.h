@@ -70,8 +70,16 @@ void launch_screen_fill(int b0, int b1, int ntiles, const double *Qmax, const do
                         double tau, const int64_t *slot_base, int32_t *tasks,
                         int32_t *task_bra, hipStream_t s);
 
+// Device-side scan of the counts: slot_base[b], *total, *overflow = total > capacity.
+void launch_scan_counts(int ntiles, const int32_t *count, int64_t *slot_base, int64_t *total,
+                        int64_t capacity, int32_t *overflow, hipStream_t s);
+// Zero n 64-bit counters with a kernel (safe inside captured graphs).
+void launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
+
 // ---- AO integral tiles (k_eri.hip)
 struct EriTileArgs {
+  const int64_t *d_total = nullptr;  // graph mode: slots beyond *d_total (or the
+  int64_t cap = 0;                   // panel capacity cap) exit at once
   const int32_t *tasks;       // [slots] ket tile per slot
   const int32_t *task_bra;    // [slots] bra tile per slot
   int64_t slot0;              // slot index of the panel buffer's first entry
@@ -88,6 +96,7 @@ void launch_eri_tiles(const EriTileArgs &a, int64_t nslots, hipStream_t s);
 
 // ---- first-half contraction (k_gemm.hip)
 struct FirstHalfArgs {
+  const int32_t *overflow = nullptr;  // graph mode: nothing to do when set
   int b0, b1;
   const int64_t *slot_base;
   const int32_t *count;

@@ -1,4 +1,4 @@
-// plan.hip -- C ABI: plans and the transformation driver.
+// plan.hip -- C ABI: plans (pair spaces, buffers, sizing) and fetches.
 //
 // A plan holds one or two pair spaces:
 //   Coulomb  LL pairs (mu <= nu) and, for DC/DCG, SS pairs: the classes of
@@ -7,51 +7,12 @@
 //   Gaunt    ordered LS pairs (mu in L, nu in S) of Eq. (GauntInt), with three
 //            Pauli components K per MO-pair column.
 // Rows of a space are ordered by decreasing Schwarz factor and padded to a
-// multiple of 64.  A transformation runs the paper's four stages (Sec. 3.3.1):
-// quaternion densities (and their bound), screening, AO integral tiles with the
-// first-half contraction, and the second half -- all on the GPU; the host only
-// sizes batches from the per-bra-tile counts of kept tiles.
-#include "runtime.h"
+// multiple of 64.  The transformation itself is driven by transform.hip.
+#include "plan.h"
 
 using namespace qdcb;
 
 namespace {
-
-struct Space {
-  int gaunt = 0;
-  int64_t P = 0, Ppad = 0;
-  int ntiles = 0;
-  std::vector<int32_t> h_cls, h_mu, h_nu;
-  std::vector<int64_t> h_key;  // canonical index (Coulomb) or mu*NS + nu (Gaunt)
-  DBuf<int32_t> cls, mu, nu;
-  DBuf<int64_t> row_first;
-  DBuf<double> Q;
-  PairStore pp;
-  int nK = 1;
-  int64_t ldK = 0, ld = 0;
-  DBuf<double> D, V, Dmax, Qmax, Bmax;
-  DBuf<int32_t> count, tasks, task_bra;
-  DBuf<int64_t> slot_base;
-  DBuf<double> panel;
-  int64_t panel_slots = 0;
-  DBuf<unsigned long long> kept;
-  // per transform
-  std::vector<int32_t> cnt;
-  std::vector<int64_t> base;
-  int64_t total = 0;
-
-  size_t bytes() const {
-    size_t b = cls.bytes() + mu.bytes() + nu.bytes() + row_first.bytes() + Q.bytes() +
-               pp.bytes() + D.bytes() + V.bytes() + Dmax.bytes() + Qmax.bytes() + Bmax.bytes() +
-               count.bytes() + tasks.bytes() + task_bra.bytes() + slot_base.bytes() +
-               panel.bytes() + kept.bytes();
-    return b;
-  }
-};
-
-// Primitive pairs whose Schwarz weight is below 1e-17 of their row's mean are
-// dropped (bounded effect: ~1e-17 of the sum of absolute primitive terms).
-constexpr double PRIM_EPS = 1e-17;
 
 // Sorted rows of a space: order by decreasing Q (stable in the input order).
 struct RowSrc {
@@ -132,28 +93,11 @@ void build_space(qdcb_ctx *ctx, Space &sp, std::vector<RowSrc> &rows,
   sp.count.alloc(ctx, sp.ntiles);
   sp.slot_base.alloc(ctx, sp.ntiles);
   sp.kept.alloc(ctx, 4);
+  sp.dtotal.alloc(ctx, 1);
+  sp.overflow.alloc(ctx, 1);
 }
 
 }  // namespace
-
-struct qdcb_plan {
-  qdcb_ctx *ctx = nullptr;
-  int64_t nLL = 0, nSS = 0;  // pair counts of the bases (plans do not keep basis pointers)
-  qdcb_plan_desc desc{};
-  int n = 0, NL = 0, NS = 0;
-  int npair_mo = 0;
-  int64_t ncol = 0;  // 4 * npair_mo
-  int ci = 0;        // MO pairs per column chunk of the first half
-  int sc = 0;        // columns per second-half slice
-  bool gaunt = false;
-  Space C, G;
-  DBuf<int32_t> rs, rowmapL, rowmapS, rowmapLS;
-  DBuf<double> CLd, CSd, Gd;
-  DBuf<double> CallL, CallS, ChatL, ChatS;
-  DBuf<double> AhatK[3], BhatK[3];
-  DBuf<double> Vfull, W, Gc;
-  bool have_last = false;
-};
 
 extern "C" {
 
@@ -169,7 +113,9 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
       fail(QDCB_E_INVALID, "S must be NULL exactly for QDCB_HAM_LL");
     if (desc->n_mo < 1 || desc->n_mo > 512) fail(QDCB_E_INVALID, "n_mo must be in [1, 512]");
     if (!std::isfinite(desc->tau) || desc->tau < 0) fail(QDCB_E_INVALID, "tau must be >= 0");
-    if (L->ctx != ctx || (S && S->ctx != ctx)) fail(QDCB_E_INVALID, "basis of another context");
+    // bases may belong to another context (resident, shared) on the same device
+    if (L->ctx->device != ctx->device || (S && S->ctx->device != ctx->device))
+      fail(QDCB_E_INVALID, "basis on another device");
     DeviceGuard g(ctx->device);
     std::unique_ptr<qdcb_plan> pl(new qdcb_plan());
     qdcb_plan &p = *pl;
@@ -343,6 +289,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
         sp->panel.alloc(ctx, (size_t)slots * TILE * TILE);
       }
     }
+    HIPC(hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking));
     ctx->retain();
     *out = pl.release();
   });
@@ -357,6 +304,37 @@ void qdcb_plan_destroy(qdcb_plan *p) {
   delete p;
   if (prev >= 0) (void)hipSetDevice(prev);
   qdcb_ctx::release_ref(ctx);
+}
+
+qdcb_status qdcb_plan_estimate(const qdcb_basis *L, const qdcb_basis *S,
+                               const qdcb_plan_desc *desc, size_t *bytes) {
+  return guarded([&] {
+    if (!L || !desc || !bytes) fail(QDCB_E_INVALID, "NULL argument");
+    if ((desc->ham == QDCB_HAM_LL) != (S == nullptr))
+      fail(QDCB_E_INVALID, "S must be NULL exactly for QDCB_HAM_LL");
+    if (desc->n_mo < 1 || desc->n_mo > 512) fail(QDCB_E_INVALID, "n_mo must be in [1, 512]");
+    const bool gaunt = desc->ham == QDCB_HAM_DCG;
+    const double n = desc->n_mo, NL = L->nfunc, NS = S ? S->nfunc : 0;
+    const double npair = n * (n + 1) / 2;
+    const double ldK = (double)round_up((int64_t)(4 * npair), 128);
+    const double PC = (double)round_up(L->npairs + (S ? S->npairs : 0), TILE);
+    const double PG = gaunt ? (double)round_up((int64_t)(NL * NS), TILE) : 0.0;
+    const double ntC = PC / TILE, ntG = PG / TILE;
+    double prims = (double)L->pair_first.back() + (S ? (double)S->pair_first.back() : 0.0);
+    if (gaunt) prims += 2.0 * (double)L->first.back() * (double)S->first.back();
+    double b = 40.0 * prims;                              // primitive-pair data
+    b += 48.0 * (PC + PG);                                // row metadata
+    b += 16.0 * (PC * ldK + 3.0 * PG * ldK);              // D~ and V, all columns
+    b += 8.0 * (ntC * ntC + ntG * ntG);                   // task lists
+    double vmax = std::max(NL * NL, NS * NS);
+    if (gaunt) vmax = std::max(vmax, NL * NS);
+    b += 8.0 * 256 * (vmax + std::max(NL, NS) * 4 * n + 4 * n * n);  // second-half slice
+    b += 8.0 * 20.0 * (NL + NS) * n * 4;                  // coefficient matrices
+    auto slots = [](double nt) { return std::min(nt * nt, std::max(nt, 65536.0)); };
+    b += 8.0 * TILE * TILE * (slots(ntC) + (gaunt ? slots(ntG) : 0.0));  // integral panels
+    b += 8.0 * 16.0 * n * n * n * n;                      // host-path G staging
+    *bytes = (size_t)(b * 1.05);
+  });
 }
 
 qdcb_status qdcb_plan_footprint(const qdcb_plan *p, size_t *bytes) {
@@ -374,319 +352,7 @@ qdcb_status qdcb_plan_footprint(const qdcb_plan *p, size_t *bytes) {
 
 }  // extern "C"
 
-namespace {
-
-void check_finite_host(const double *x, size_t n, const char *what) {
-  for (size_t i = 0; i < n; ++i)
-    if (!std::isfinite(x[i])) fail(QDCB_E_INVALID, std::string("non-finite value in ") + what);
-}
-
-// Stage timing with events read back after the final synchronization.
-struct StageTimer {
-  hipStream_t s;
-  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
-  hipEvent_t open = nullptr;
-  int open_stage = -1;
-  explicit StageTimer(hipStream_t st) : s(st) {}
-  ~StageTimer() {
-    for (auto &m : marks) {
-      (void)hipEventDestroy(m.second.first);
-      (void)hipEventDestroy(m.second.second);
-    }
-    if (open) (void)hipEventDestroy(open);
-  }
-  void begin(int stage) {
-    HIPC(hipEventCreate(&open));
-    HIPC(hipEventRecord(open, s));
-    open_stage = stage;
-  }
-  void end() {
-    hipEvent_t e;
-    HIPC(hipEventCreate(&e));
-    HIPC(hipEventRecord(e, s));
-    marks.push_back({open_stage, {open, e}});
-    open = nullptr;
-  }
-  double total(int stage) {
-    double t = 0;
-    for (auto &m : marks)
-      if (m.first == stage) {
-        float ms = 0;
-        HIPC(hipEventElapsedTime(&ms, m.second.first, m.second.second));
-        t += ms;
-      }
-    return t;
-  }
-  int launches(int stage) {
-    int c = 0;
-    for (auto &m : marks) c += m.first == stage;
-    return c;
-  }
-};
-
-enum { ST_DENS = 0, ST_SCREEN = 1, ST_ERI = 2, ST_FH = 3, ST_SH = 4, ST_ALL = 5 };
-
-void density(qdcb_plan &p, Space &sp, const double *dCL, const double *dCS, int bound_only,
-             int i0, int i1, hipStream_t s) {
-  DensityArgs da;
-  da.gaunt = sp.gaunt;
-  da.bound_only = bound_only;
-  da.nrows = sp.Ppad;
-  da.n = p.n;
-  da.npair_mo = p.npair_mo;
-  da.i0 = i0;
-  da.i1 = i1;
-  da.ld = sp.ld;
-  da.ldK = sp.ldK;
-  da.cls = sp.cls.p;
-  da.mu = sp.mu.p;
-  da.nu = sp.nu.p;
-  da.CL = dCL;
-  da.CS = dCS;
-  da.NL = p.NL;
-  da.NS = p.NS;
-  da.rs = p.rs.p;
-  da.D = sp.D.p;
-  da.Dmax = sp.Dmax.p;
-  launch_density(da, s);
-  HIPC(hipGetLastError());
-}
-
-void screen(qdcb_plan &p, Space &sp, hipStream_t s) {
-  launch_tile_bounds(sp.ntiles, sp.Q.p, sp.Dmax.p, sp.Qmax.p, sp.Bmax.p, s);
-  launch_screen_count(sp.ntiles, sp.Qmax.p, sp.Bmax.p, p.desc.tau, sp.count.p, s);
-  HIPC(hipGetLastError());
-  sp.cnt.resize(sp.ntiles);
-  HIPC(hipMemcpyAsync(sp.cnt.data(), sp.count.p, sp.cnt.size() * sizeof(int32_t),
-                      hipMemcpyDeviceToHost, s));
-  HIPC(hipStreamSynchronize(s));
-  sp.base.resize(sp.ntiles);
-  sp.total = 0;
-  for (int b = 0; b < sp.ntiles; ++b) {
-    sp.base[b] = sp.total;
-    sp.total += sp.cnt[b];
-  }
-  HIPC(hipMemcpyAsync(sp.slot_base.p, sp.base.data(), sp.base.size() * sizeof(int64_t),
-                      hipMemcpyHostToDevice, s));
-  if ((int64_t)sp.tasks.n < sp.total) fail(QDCB_E_DEVICE, "task list capacity exceeded");
-  launch_screen_fill(0, sp.ntiles, sp.ntiles, sp.Qmax.p, sp.Bmax.p, p.desc.tau,
-                     sp.slot_base.p, sp.tasks.p, sp.task_bra.p, s);
-  HIPC(hipMemsetAsync(sp.kept.p, 0, sp.kept.bytes(), s));
-  HIPC(hipGetLastError());
-}
-
-// Integral tiles + first half of one space over its current column chunk.
-int first_half(qdcb_plan &p, Space &sp, bool make_tiles, bool count, StageTimer &tm,
-               hipStream_t s) {
-  int nb = 0;
-  for (int b0 = 0; b0 < sp.ntiles;) {
-    int b1 = b0;
-    int64_t used = 0;
-    while (b1 < sp.ntiles && used + sp.cnt[b1] <= sp.panel_slots) used += sp.cnt[b1++];
-    if (make_tiles) {
-      EriTileArgs ea;
-      ea.tasks = sp.tasks.p;
-      ea.task_bra = sp.task_bra.p;
-      ea.slot0 = sp.base[b0];
-      ea.row_first = sp.row_first.p;
-      ea.pp = sp.pp.cview();
-      ea.Q = sp.Q.p;
-      ea.Dmax = sp.Dmax.p;
-      ea.cls = sp.cls.p;
-      ea.tau = p.desc.tau;
-      ea.panel = sp.panel.p;
-      ea.kept = count ? sp.kept.p : nullptr;
-      tm.begin(ST_ERI);
-      launch_eri_tiles(ea, used, s);
-      tm.end();
-      HIPC(hipGetLastError());
-    }
-    FirstHalfArgs fa;
-    fa.b0 = b0;
-    fa.b1 = b1;
-    fa.slot_base = sp.slot_base.p;
-    fa.count = sp.count.p;
-    fa.tasks = sp.tasks.p;
-    fa.slot0 = sp.base[b0];
-    fa.panel = sp.panel.p;
-    fa.D = sp.D.p;
-    fa.V = sp.V.p;
-    fa.ld = sp.ld;
-    fa.ncol_tiles = (int)(sp.ld / 128);
-    tm.begin(ST_FH);
-    launch_first_half(fa, s);
-    tm.end();
-    HIPC(hipGetLastError());
-    ++nb;
-    b0 = b1;
-  }
-  return nb;
-}
-
-}  // namespace
-
 extern "C" {
-
-qdcb_status qdcb_transform(qdcb_plan *plan, const double *CL, const double *CS, double *G,
-                           uint32_t flags, void *hip_stream, qdcb_stats *stats) {
-  return guarded([&] {
-    if (!plan || !CL || !G) fail(QDCB_E_INVALID, "NULL argument");
-    qdcb_plan &p = *plan;
-    if (p.NS && !CS) fail(QDCB_E_INVALID, "CS is required for this Hamiltonian");
-    qdcb_ctx *ctx = p.ctx;
-    DeviceGuard g(ctx->device);
-    hipStream_t s = (hipStream_t)hip_stream;
-    const bool dev = flags & QDCB_PTR_DEVICE;
-    const int n = p.n;
-    const size_t nG = (size_t)n * n * n * n * 16;
-    const double *dCL = CL, *dCS = CS;
-    double *dG = G;
-    if (!dev) {
-      check_finite_host(CL, (size_t)4 * p.NL * n, "CL");
-      if (p.NS) check_finite_host(CS, (size_t)4 * p.NS * n, "CS");
-      HIPC(hipMemcpyAsync(p.CLd.p, CL, p.CLd.bytes(), hipMemcpyHostToDevice, s));
-      dCL = p.CLd.p;
-      if (p.NS) {
-        HIPC(hipMemcpyAsync(p.CSd.p, CS, p.CSd.bytes(), hipMemcpyHostToDevice, s));
-        dCS = p.CSd.p;
-      }
-      if (p.Gd.n != nG) p.Gd.alloc(ctx, nG);
-      dG = p.Gd.p;
-    }
-    std::vector<Space *> spaces{&p.C};
-    if (p.gaunt) spaces.push_back(&p.G);
-    StageTimer tm(s);
-    hipEvent_t ev_start;
-    HIPC(hipEventCreate(&ev_start));
-    HIPC(hipEventRecord(ev_start, s));
-
-    // density bounds and screening (the kept set is the same for every chunk)
-    for (Space *sp : spaces) {
-      tm.begin(ST_DENS);
-      density(p, *sp, dCL, dCS, 1, 0, p.npair_mo, s);
-      tm.end();
-      tm.begin(ST_SCREEN);
-      screen(p, *sp, s);
-      tm.end();
-    }
-    // second-half coefficient matrices
-    launch_build_coef_mats(p.NL, n, dCL, -1, p.CallL.p, p.ChatL.p, s);
-    if (p.NS) launch_build_coef_mats(p.NS, n, dCS, -1, p.CallS.p, p.ChatS.p, s);
-    if (p.gaunt)
-      for (int K = 0; K < 3; ++K) {
-        launch_build_coef_mats(p.NL, n, dCL, K, p.CallL.p, p.AhatK[K].p, s);
-        launch_build_coef_mats(p.NS, n, dCS, K, p.CallS.p, p.BhatK[K].p, s);
-      }
-    HIPC(hipGetLastError());
-
-    int nb = 0;
-    double mfma = 0;
-    for (int i0 = 0; i0 < p.npair_mo; i0 += p.ci) {
-      const int i1 = std::min(p.npair_mo, i0 + p.ci);
-      for (Space *sp : spaces) {
-        tm.begin(ST_DENS);
-        density(p, *sp, dCL, dCS, 0, i0, i1, s);
-        tm.end();
-        const bool resident = sp->total <= sp->panel_slots;
-        nb += first_half(p, *sp, !resident || i0 == 0, i0 == 0, tm, s);
-        mfma += 2.0 * TILE * TILE * (double)sp->ld * (double)sp->total;
-      }
-      // second half of this chunk's columns, slice by slice
-      tm.begin(ST_SH);
-      const int64_t cend = 4LL * i1;
-      for (int64_t c0 = 4LL * i0; c0 < cend; c0 += p.sc) {
-        const int nc = (int)std::min<int64_t>(p.sc, cend - c0);
-        const int64_t lc0 = c0 - 4LL * i0;
-        for (int cls = 0; cls < (p.NS ? 2 : 1); ++cls) {
-          const int N = cls ? p.NS : p.NL;
-          launch_unpack(N, N, cls ? p.rowmapS.p : p.rowmapL.p, p.C.V.p, p.C.ld, lc0, nc,
-                        p.Vfull.p, s);
-          launch_dgemm_batched(0, N, 4 * n, N, 1.0, p.Vfull.p, N, (int64_t)N * N,
-                               cls ? p.CallS.p : p.CallL.p, 4 * n, 0, 0.0, p.W.p, 4 * n,
-                               (int64_t)N * 4 * n, nc, s);
-          launch_dgemm_batched(1, 4 * n, n, 4 * N, 1.0, cls ? p.ChatS.p : p.ChatL.p, 4 * n, 0,
-                               p.W.p, n, (int64_t)N * 4 * n, cls ? 1.0 : 0.0, p.Gc.p, n,
-                               (int64_t)4 * n * n, nc, s);
-        }
-        launch_pack(n, p.rs.p, c0, nc, p.Gc.p, dG, 1.0, 0, s);
-        if (p.gaunt) {
-          const int NL = p.NL, NS = p.NS;
-          for (int K = 0; K < 3; ++K) {
-            launch_unpack(NL, NS, p.rowmapLS.p, p.G.V.p, p.G.ld, K * p.G.ldK + lc0, nc,
-                          p.Vfull.p, s);
-            // conj(C^L) e_K (V C^S)
-            launch_dgemm_batched(0, NL, 4 * n, NS, 1.0, p.Vfull.p, NS, (int64_t)NL * NS,
-                                 p.CallS.p, 4 * n, 0, 0.0, p.W.p, 4 * n, (int64_t)NL * 4 * n, nc,
-                                 s);
-            launch_dgemm_batched(1, 4 * n, n, 4 * NL, 1.0, p.AhatK[K].p, 4 * n, 0, p.W.p, n,
-                                 (int64_t)NL * 4 * n, K ? 1.0 : 0.0, p.Gc.p, n,
-                                 (int64_t)4 * n * n, nc, s);
-            // conj(C^S) e_K (V^T C^L)
-            launch_dgemm_batched(1, NS, 4 * n, NL, 1.0, p.Vfull.p, NS, (int64_t)NL * NS,
-                                 p.CallL.p, 4 * n, 0, 0.0, p.W.p, 4 * n, (int64_t)NS * 4 * n, nc,
-                                 s);
-            launch_dgemm_batched(1, 4 * n, n, 4 * NS, 1.0, p.BhatK[K].p, 4 * n, 0, p.W.p, n,
-                                 (int64_t)NS * 4 * n, 1.0, p.Gc.p, n, (int64_t)4 * n * n, nc,
-                                 s);
-          }
-          launch_pack(n, p.rs.p, c0, nc, p.Gc.p, dG, -1.0, 1, s);
-        }
-        HIPC(hipGetLastError());
-      }
-      tm.end();
-    }
-    hipEvent_t ev_end;
-    HIPC(hipEventCreate(&ev_end));
-    HIPC(hipEventRecord(ev_end, s));
-    tm.marks.push_back({ST_ALL, {ev_start, ev_end}});
-    if (!dev) HIPC(hipMemcpyAsync(G, dG, nG * sizeof(double), hipMemcpyDeviceToHost, s));
-    unsigned long long kc[4] = {0, 0, 0, 0}, kg[4] = {0, 0, 0, 0};
-    HIPC(hipMemcpyAsync(kc, p.C.kept.p, sizeof(kc), hipMemcpyDeviceToHost, s));
-    if (p.gaunt) HIPC(hipMemcpyAsync(kg, p.G.kept.p, sizeof(kg), hipMemcpyDeviceToHost, s));
-    HIPC(hipStreamSynchronize(s));
-    p.have_last = true;
-    if (stats) {
-      std::memset(stats, 0, sizeof(*stats));
-      stats->ms_density = tm.total(ST_DENS);
-      stats->ms_screen = tm.total(ST_SCREEN);
-      stats->ms_eri = tm.total(ST_ERI);
-      stats->ms_first_half = tm.total(ST_FH);
-      stats->ms_second_half = tm.total(ST_SH);
-      stats->ms_total = tm.total(ST_ALL);
-      double ktot = 0;
-      for (int c = 0; c < 4; ++c) {
-        stats->kept[c] = (int64_t)kc[c];
-        ktot += (double)kc[c];
-      }
-      const int64_t nLL = p.nLL, nSS = p.nSS;
-      stats->total[0] = nLL * nLL;
-      stats->total[1] = nLL * nSS;
-      stats->total[2] = nSS * nLL;
-      stats->total[3] = nSS * nSS;
-      stats->kept_gaunt = (int64_t)kg[0];
-      stats->total_gaunt = p.gaunt ? p.G.P * p.G.P : 0;
-      stats->tiles_kept = p.C.total + (p.gaunt ? p.G.total : 0);
-      stats->tiles_total = (int64_t)p.C.ntiles * p.C.ntiles +
-                           (p.gaunt ? (int64_t)p.G.ntiles * p.G.ntiles : 0);
-      stats->flops_first_half =
-          2.0 * (double)p.ncol * ktot + 2.0 * 3.0 * (double)p.ncol * (double)kg[0];
-      double f2 = 0;
-      for (int cls = 0; cls < (p.NS ? 2 : 1); ++cls) {
-        double N = cls ? p.NS : p.NL;
-        f2 += (8.0 * N * N * n + 32.0 * N * n * n) * (double)p.ncol;
-      }
-      if (p.gaunt)
-        f2 += 3.0 * (16.0 * p.NL * (double)p.NS * n + 32.0 * (p.NL + p.NS) * (double)n * n) *
-              (double)p.ncol;
-      stats->flops_second_half = f2;
-      stats->flops_mfma = mfma;
-      stats->n_batches = tm.launches(ST_FH);
-      stats->n_chunks = (p.npair_mo + p.ci - 1) / p.ci;
-      (void)nb;
-    }
-  });
-}
-
 qdcb_status qdcb_plan_fetch(const qdcb_plan *p, int32_t what, void *host_out, size_t bytes) {
   return guarded([&] {
     if (!p || !host_out) fail(QDCB_E_INVALID, "NULL argument");

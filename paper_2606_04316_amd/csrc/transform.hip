@@ -1,0 +1,509 @@
+// transform.hip -- C ABI: the transformation driver, eager and captured.
+//
+// One transformation enqueues the paper's four stages (Sec. 3.3.1) on the
+// caller's stream: quaternion densities and their bound, screening (task
+// lists), AO integral tiles with the first-half contraction, and the second
+// half.  Eager mode reads the per-bra-tile counts of kept tiles back to the
+// host to size batches that fit the integral panel.  Captured mode keeps every
+// step on the device (device-side scan of the counts, one batch, fixed launch
+// sizes, no memsets) so the whole transformation can be recorded once into a
+// hipGraph and replayed for re-transforms with new coefficients written into
+// the same buffers; a replay whose kept tiles exceed the panel sets a flag
+// and is redone eagerly.
+#include "plan.h"
+
+using namespace qdcb;
+
+namespace {
+
+void check_finite_host(const double *x, size_t n, const char *what) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(x[i])) fail(QDCB_E_INVALID, std::string("non-finite value in ") + what);
+}
+
+enum { ST_DENS = 0, ST_SCREEN = 1, ST_ERI = 2, ST_FH = 3, ST_SH = 4, NSTAGE = 5 };
+
+// Stage timing with events read back after the final synchronization;
+// disabled (null) while a graph is being captured.
+struct StageTimer {
+  hipStream_t s;
+  bool on;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
+  hipEvent_t open = nullptr;
+  int open_stage = -1;
+  StageTimer(hipStream_t st, bool enabled) : s(st), on(enabled) {}
+  ~StageTimer() {
+    for (auto e : sync_events) (void)hipEventDestroy(e);
+    for (auto &m : marks) {
+      (void)hipEventDestroy(m.second.first);
+      (void)hipEventDestroy(m.second.second);
+    }
+    if (open) (void)hipEventDestroy(open);
+  }
+  void begin(int stage, hipStream_t st = nullptr) {
+    if (!on) return;
+    HIPC(hipEventCreate(&open));
+    HIPC(hipEventRecord(open, st ? st : s));
+    open_stage = stage;
+  }
+  void end(hipStream_t st = nullptr) {
+    if (!on) return;
+    hipEvent_t e;
+    HIPC(hipEventCreate(&e));
+    HIPC(hipEventRecord(e, st ? st : s));
+    marks.push_back({open_stage, {open, e}});
+    open = nullptr;
+  }
+  // ordering events (no timing), destroyed with the timer after the final sync
+  std::vector<hipEvent_t> sync_events;
+  hipEvent_t record(hipStream_t st) {
+    hipEvent_t e;
+    HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    sync_events.push_back(e);
+    HIPC(hipEventRecord(e, st));
+    return e;
+  }
+  double total(int stage) {
+    double t = 0;
+    for (auto &m : marks)
+      if (m.first == stage) {
+        float ms = 0;
+        HIPC(hipEventElapsedTime(&ms, m.second.first, m.second.second));
+        t += ms;
+      }
+    return t;
+  }
+  int launches(int stage) {
+    int c = 0;
+    for (auto &m : marks) c += m.first == stage;
+    return c;
+  }
+};
+
+void density(qdcb_plan &p, Space &sp, const double *dCL, const double *dCS, int bound_only,
+             int i0, int i1, hipStream_t s) {
+  DensityArgs da;
+  da.gaunt = sp.gaunt;
+  da.bound_only = bound_only;
+  da.nrows = sp.Ppad;
+  da.n = p.n;
+  da.npair_mo = p.npair_mo;
+  da.i0 = i0;
+  da.i1 = i1;
+  da.ld = sp.ld;
+  da.ldK = sp.ldK;
+  da.cls = sp.cls.p;
+  da.mu = sp.mu.p;
+  da.nu = sp.nu.p;
+  da.CL = dCL;
+  da.CS = dCS;
+  da.NL = p.NL;
+  da.NS = p.NS;
+  da.rs = p.rs.p;
+  da.D = sp.D.p;
+  da.Dmax = sp.Dmax.p;
+  launch_density(da, s);
+  HIPC(hipGetLastError());
+}
+
+// Task lists of one space.  Eager: counts to the host, batches sized there.
+// Captured: device-side scan, one batch of at most panel_slots tiles.
+void screen(qdcb_plan &p, Space &sp, bool captured, hipStream_t s) {
+  launch_tile_bounds(sp.ntiles, sp.Q.p, sp.Dmax.p, sp.Qmax.p, sp.Bmax.p, s);
+  launch_screen_count(sp.ntiles, sp.Qmax.p, sp.Bmax.p, p.desc.tau, sp.count.p, s);
+  HIPC(hipGetLastError());
+  if (captured) {
+    launch_scan_counts(sp.ntiles, sp.count.p, sp.slot_base.p, sp.dtotal.p, sp.panel_slots,
+                       sp.overflow.p, s);
+  } else {
+    sp.cnt.resize(sp.ntiles);
+    HIPC(hipMemcpyAsync(sp.cnt.data(), sp.count.p, sp.cnt.size() * sizeof(int32_t),
+                        hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    sp.base.resize(sp.ntiles);
+    sp.total = 0;
+    for (int b = 0; b < sp.ntiles; ++b) {
+      sp.base[b] = sp.total;
+      sp.total += sp.cnt[b];
+    }
+    HIPC(hipMemcpyAsync(sp.slot_base.p, sp.base.data(), sp.base.size() * sizeof(int64_t),
+                        hipMemcpyHostToDevice, s));
+    if ((int64_t)sp.tasks.n < sp.total) fail(QDCB_E_DEVICE, "task list capacity exceeded");
+  }
+  launch_screen_fill(0, sp.ntiles, sp.ntiles, sp.Qmax.p, sp.Bmax.p, p.desc.tau, sp.slot_base.p,
+                     sp.tasks.p, sp.task_bra.p, s);
+  launch_zero_u64(sp.kept.p, 4, s);
+  HIPC(hipGetLastError());
+}
+
+EriTileArgs eri_args(qdcb_plan &p, Space &sp, int64_t slot0, bool count) {
+  EriTileArgs ea;
+  ea.tasks = sp.tasks.p;
+  ea.task_bra = sp.task_bra.p;
+  ea.slot0 = slot0;
+  ea.row_first = sp.row_first.p;
+  ea.pp = sp.pp.cview();
+  ea.Q = sp.Q.p;
+  ea.Dmax = sp.Dmax.p;
+  ea.cls = sp.cls.p;
+  ea.tau = p.desc.tau;
+  ea.panel = sp.panel.p;
+  ea.kept = count ? sp.kept.p : nullptr;
+  return ea;
+}
+
+FirstHalfArgs fh_args(Space &sp, int b0, int b1, int64_t slot0) {
+  FirstHalfArgs fa;
+  fa.b0 = b0;
+  fa.b1 = b1;
+  fa.slot_base = sp.slot_base.p;
+  fa.count = sp.count.p;
+  fa.tasks = sp.tasks.p;
+  fa.slot0 = slot0;
+  fa.panel = sp.panel.p;
+  fa.D = sp.D.p;
+  fa.V = sp.V.p;
+  fa.ld = sp.ld;
+  fa.ncol_tiles = (int)(sp.ld / 128);
+  return fa;
+}
+
+// Integral tiles + first half of one space over its current column chunk.
+void first_half(qdcb_plan &p, Space &sp, bool make_tiles, bool count, bool captured,
+                StageTimer &tm, hipStream_t s) {
+  if (captured) {
+    if (make_tiles) {
+      EriTileArgs ea = eri_args(p, sp, 0, count);
+      ea.d_total = sp.dtotal.p;
+      ea.cap = sp.panel_slots;
+      launch_eri_tiles(ea, std::min<int64_t>(sp.panel_slots, (int64_t)sp.ntiles * sp.ntiles), s);
+    }
+    FirstHalfArgs fa = fh_args(sp, 0, sp.ntiles, 0);
+    fa.overflow = sp.overflow.p;
+    launch_first_half(fa, s);
+    HIPC(hipGetLastError());
+    return;
+  }
+  // Batches of consecutive bra tiles.  When the tiles are generated here, the
+  // integral tiles of a batch are made on the side stream while the main
+  // stream contracts the previous batch.  With every kept tile resident the
+  // batches use disjoint panel slots (about four batches); otherwise the panel
+  // is used as two halves and the tiles of batch i wait until the
+  // contraction of batch i-2 has released its half.
+  const int64_t cap = sp.panel_slots;
+  const bool resident_all = sp.total <= cap;
+  int maxcnt = 0;
+  for (int b = 0; b < sp.ntiles; ++b) maxcnt = std::max(maxcnt, sp.cnt[b]);
+  const bool pipe = make_tiles && (resident_all || maxcnt <= cap / 2);
+  const int64_t limit = !pipe ? cap : resident_all ? std::max<int64_t>((sp.total + 3) / 4, 1)
+                                                   : cap / 2;
+  struct Batch {
+    int b0, b1;
+    int64_t used, off;
+  };
+  std::vector<Batch> batches;
+  for (int b0 = 0; b0 < sp.ntiles;) {
+    int b1 = b0;
+    int64_t used = 0;
+    while (b1 < sp.ntiles && (b1 == b0 || used + sp.cnt[b1] <= limit)) used += sp.cnt[b1++];
+    int64_t off = 0;
+    if (pipe && !resident_all) off = (batches.size() % 2) * (cap / 2);
+    else if (pipe) off = sp.base[b0];
+    batches.push_back({b0, b1, used, off});
+    b0 = b1;
+  }
+  hipEvent_t ready = pipe ? tm.record(s) : nullptr;
+  std::vector<hipEvent_t> made(batches.size()), done(batches.size());
+  for (size_t i = 0; i < batches.size(); ++i) {
+    const Batch &B = batches[i];
+    double *panel = sp.panel.p + B.off * (int64_t)(TILE * TILE);
+    if (make_tiles) {
+      hipStream_t es = pipe ? p.side : s;
+      if (pipe) {
+        HIPC(hipStreamWaitEvent(es, ready, 0));
+        if (!resident_all && i >= 2) HIPC(hipStreamWaitEvent(es, done[i - 2], 0));
+      }
+      EriTileArgs ea = eri_args(p, sp, sp.base[B.b0], count);
+      ea.panel = panel;
+      tm.begin(ST_ERI, es);
+      launch_eri_tiles(ea, B.used, es);
+      tm.end(es);
+      HIPC(hipGetLastError());
+      if (pipe) {
+        made[i] = tm.record(es);
+        HIPC(hipStreamWaitEvent(s, made[i], 0));
+      }
+    }
+    FirstHalfArgs fa = fh_args(sp, B.b0, B.b1, sp.base[B.b0]);
+    fa.panel = panel;
+    tm.begin(ST_FH);
+    launch_first_half(fa, s);
+    tm.end();
+    HIPC(hipGetLastError());
+    if (pipe && !resident_all) done[i] = tm.record(s);
+  }
+}
+
+void second_half(qdcb_plan &p, int i0, int i1, double *dG, hipStream_t s) {
+  const int n = p.n;
+  const int64_t cend = 4LL * i1;
+  for (int64_t c0 = 4LL * i0; c0 < cend; c0 += p.sc) {
+    const int nc = (int)std::min<int64_t>(p.sc, cend - c0);
+    const int64_t lc0 = c0 - 4LL * i0;
+    for (int cls = 0; cls < (p.NS ? 2 : 1); ++cls) {
+      const int N = cls ? p.NS : p.NL;
+      launch_unpack(N, N, cls ? p.rowmapS.p : p.rowmapL.p, p.C.V.p, p.C.ld, lc0, nc, p.Vfull.p,
+                    s);
+      launch_dgemm_batched(0, N, 4 * n, N, 1.0, p.Vfull.p, N, (int64_t)N * N,
+                           cls ? p.CallS.p : p.CallL.p, 4 * n, 0, 0.0, p.W.p, 4 * n,
+                           (int64_t)N * 4 * n, nc, s);
+      launch_dgemm_batched(1, 4 * n, n, 4 * N, 1.0, cls ? p.ChatS.p : p.ChatL.p, 4 * n, 0, p.W.p,
+                           n, (int64_t)N * 4 * n, cls ? 1.0 : 0.0, p.Gc.p, n, (int64_t)4 * n * n,
+                           nc, s);
+    }
+    launch_pack(n, p.rs.p, c0, nc, p.Gc.p, dG, 1.0, 0, s);
+    if (p.gaunt) {
+      const int NL = p.NL, NS = p.NS;
+      for (int K = 0; K < 3; ++K) {
+        launch_unpack(NL, NS, p.rowmapLS.p, p.G.V.p, p.G.ld, K * p.G.ldK + lc0, nc, p.Vfull.p, s);
+        // conj(C^L) e_K (V C^S)
+        launch_dgemm_batched(0, NL, 4 * n, NS, 1.0, p.Vfull.p, NS, (int64_t)NL * NS, p.CallS.p,
+                             4 * n, 0, 0.0, p.W.p, 4 * n, (int64_t)NL * 4 * n, nc, s);
+        launch_dgemm_batched(1, 4 * n, n, 4 * NL, 1.0, p.AhatK[K].p, 4 * n, 0, p.W.p, n,
+                             (int64_t)NL * 4 * n, K ? 1.0 : 0.0, p.Gc.p, n, (int64_t)4 * n * n,
+                             nc, s);
+        // conj(C^S) e_K (V^T C^L)
+        launch_dgemm_batched(1, NS, 4 * n, NL, 1.0, p.Vfull.p, NS, (int64_t)NL * NS, p.CallL.p,
+                             4 * n, 0, 0.0, p.W.p, 4 * n, (int64_t)NS * 4 * n, nc, s);
+        launch_dgemm_batched(1, 4 * n, n, 4 * NS, 1.0, p.BhatK[K].p, 4 * n, 0, p.W.p, n,
+                             (int64_t)NS * 4 * n, 1.0, p.Gc.p, n, (int64_t)4 * n * n, nc, s);
+      }
+      launch_pack(n, p.rs.p, c0, nc, p.Gc.p, dG, -1.0, 1, s);
+    }
+    HIPC(hipGetLastError());
+  }
+}
+
+// Enqueue one whole transformation of device inputs into device G.
+void enqueue(qdcb_plan &p, const double *dCL, const double *dCS, double *dG, bool captured,
+             StageTimer &tm, hipStream_t s) {
+  std::vector<Space *> spaces{&p.C};
+  if (p.gaunt) spaces.push_back(&p.G);
+  for (Space *sp : spaces) {
+    tm.begin(ST_DENS);
+    density(p, *sp, dCL, dCS, 1, 0, p.npair_mo, s);
+    tm.end();
+    tm.begin(ST_SCREEN);
+    screen(p, *sp, captured, s);
+    tm.end();
+  }
+  launch_build_coef_mats(p.NL, p.n, dCL, -1, p.CallL.p, p.ChatL.p, s);
+  if (p.NS) launch_build_coef_mats(p.NS, p.n, dCS, -1, p.CallS.p, p.ChatS.p, s);
+  if (p.gaunt)
+    for (int K = 0; K < 3; ++K) {
+      launch_build_coef_mats(p.NL, p.n, dCL, K, p.CallL.p, p.AhatK[K].p, s);
+      launch_build_coef_mats(p.NS, p.n, dCS, K, p.CallS.p, p.BhatK[K].p, s);
+    }
+  HIPC(hipGetLastError());
+  for (int i0 = 0; i0 < p.npair_mo; i0 += p.ci) {
+    const int i1 = std::min(p.npair_mo, i0 + p.ci);
+    for (Space *sp : spaces) {
+      tm.begin(ST_DENS);
+      density(p, *sp, dCL, dCS, 0, i0, i1, s);
+      tm.end();
+      // captured mode keeps the tiles of the first chunk (one batch, resident)
+      const bool resident = captured || sp->total <= sp->panel_slots;
+      first_half(p, *sp, !resident || i0 == 0, i0 == 0, captured, tm, s);
+    }
+    tm.begin(ST_SH);
+    second_half(p, i0, i1, dG, s);
+    tm.end();
+  }
+}
+
+void fill_stats(qdcb_plan &p, qdcb_stats *stats, StageTimer *tm, double ms_total,
+                const unsigned long long kc[4], const unsigned long long kg[4], int64_t tiles_c,
+                int64_t tiles_g) {
+  std::memset(stats, 0, sizeof(*stats));
+  const int n = p.n;
+  if (tm) {
+    stats->ms_density = tm->total(ST_DENS);
+    stats->ms_screen = tm->total(ST_SCREEN);
+    stats->ms_eri = tm->total(ST_ERI);
+    stats->ms_first_half = tm->total(ST_FH);
+    stats->ms_second_half = tm->total(ST_SH);
+    stats->n_batches = tm->launches(ST_FH);
+  }
+  stats->ms_total = ms_total;
+  double ktot = 0;
+  for (int c = 0; c < 4; ++c) {
+    stats->kept[c] = (int64_t)kc[c];
+    ktot += (double)kc[c];
+  }
+  stats->total[0] = p.nLL * p.nLL;
+  stats->total[1] = p.nLL * p.nSS;
+  stats->total[2] = p.nSS * p.nLL;
+  stats->total[3] = p.nSS * p.nSS;
+  stats->kept_gaunt = (int64_t)kg[0];
+  stats->total_gaunt = p.gaunt ? p.G.P * p.G.P : 0;
+  stats->tiles_kept = tiles_c + tiles_g;
+  stats->tiles_total =
+      (int64_t)p.C.ntiles * p.C.ntiles + (p.gaunt ? (int64_t)p.G.ntiles * p.G.ntiles : 0);
+  stats->flops_first_half = 2.0 * (double)p.ncol * ktot + 6.0 * (double)p.ncol * (double)kg[0];
+  double f2 = 0;
+  for (int cls = 0; cls < (p.NS ? 2 : 1); ++cls) {
+    double N = cls ? p.NS : p.NL;
+    f2 += (8.0 * N * N * n + 32.0 * N * n * n) * (double)p.ncol;
+  }
+  if (p.gaunt)
+    f2 += 3.0 * (16.0 * p.NL * (double)p.NS * n + 32.0 * (p.NL + p.NS) * (double)n * n) *
+          (double)p.ncol;
+  stats->flops_second_half = f2;
+  const int nchunks = (p.npair_mo + p.ci - 1) / p.ci;
+  stats->n_chunks = nchunks;
+  stats->flops_mfma = 2.0 * TILE * TILE * nchunks *
+                      ((double)p.C.ld * tiles_c + (p.gaunt ? (double)p.G.ld * tiles_g : 0.0));
+}
+
+void read_counters(qdcb_plan &p, hipStream_t s, unsigned long long kc[4],
+                   unsigned long long kg[4]) {
+  for (int c = 0; c < 4; ++c) kc[c] = kg[c] = 0;
+  HIPC(hipMemcpyAsync(kc, p.C.kept.p, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  if (p.gaunt)
+    HIPC(hipMemcpyAsync(kg, p.G.kept.p, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                        s));
+}
+
+void run_eager(qdcb_plan &p, const double *dCL, const double *dCS, double *dG, hipStream_t s,
+               qdcb_stats *stats) {
+  StageTimer tm(s, true);
+  hipEvent_t e0, e1;
+  HIPC(hipEventCreate(&e0));
+  HIPC(hipEventCreate(&e1));
+  HIPC(hipEventRecord(e0, s));
+  enqueue(p, dCL, dCS, dG, false, tm, s);
+  HIPC(hipEventRecord(e1, s));
+  unsigned long long kc[4], kg[4];
+  read_counters(p, s, kc, kg);
+  HIPC(hipStreamSynchronize(s));
+  float ms = 0;
+  HIPC(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p.have_last = true;
+  if (stats) fill_stats(p, stats, &tm, ms, kc, kg, p.C.total, p.gaunt ? p.G.total : 0);
+}
+
+}  // namespace
+
+extern "C" {
+
+qdcb_status qdcb_transform(qdcb_plan *plan, const double *CL, const double *CS, double *G,
+                           uint32_t flags, void *hip_stream, qdcb_stats *stats) {
+  return guarded([&] {
+    if (!plan || !CL || !G) fail(QDCB_E_INVALID, "NULL argument");
+    qdcb_plan &p = *plan;
+    if (p.NS && !CS) fail(QDCB_E_INVALID, "CS is required for this Hamiltonian");
+    DeviceGuard g(p.ctx->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    const bool dev = flags & QDCB_PTR_DEVICE;
+    const int n = p.n;
+    const size_t nG = (size_t)n * n * n * n * 16;
+    const double *dCL = CL, *dCS = CS;
+    double *dG = G;
+    if (!dev) {
+      check_finite_host(CL, (size_t)4 * p.NL * n, "CL");
+      if (p.NS) check_finite_host(CS, (size_t)4 * p.NS * n, "CS");
+      HIPC(hipMemcpyAsync(p.CLd.p, CL, p.CLd.bytes(), hipMemcpyHostToDevice, s));
+      dCL = p.CLd.p;
+      if (p.NS) {
+        HIPC(hipMemcpyAsync(p.CSd.p, CS, p.CSd.bytes(), hipMemcpyHostToDevice, s));
+        dCS = p.CSd.p;
+      }
+      if (p.Gd.n != nG) p.Gd.alloc(p.ctx, nG);
+      dG = p.Gd.p;
+    }
+    run_eager(p, dCL, dCS, dG, s, stats);
+    if (!dev) {
+      HIPC(hipMemcpyAsync(G, dG, nG * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPC(hipStreamSynchronize(s));
+    }
+  });
+}
+
+qdcb_status qdcb_plan_capture(qdcb_plan *plan, const double *CL, const double *CS, double *G,
+                              void *hip_stream) {
+  return guarded([&] {
+    if (!plan || !CL || !G || !hip_stream) fail(QDCB_E_INVALID, "NULL argument");
+    qdcb_plan &p = *plan;
+    if (p.NS && !CS) fail(QDCB_E_INVALID, "CS is required for this Hamiltonian");
+    DeviceGuard g(p.ctx->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (p.graph_exec) {
+      (void)hipGraphExecDestroy(p.graph_exec);
+      p.graph_exec = nullptr;
+    }
+    if (p.graph) {
+      (void)hipGraphDestroy(p.graph);
+      p.graph = nullptr;
+    }
+    StageTimer tm(s, false);
+    HIPC(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    try {
+      enqueue(p, CL, CS, G, true, tm, s);
+    } catch (...) {
+      hipGraph_t dead = nullptr;
+      (void)hipStreamEndCapture(s, &dead);
+      if (dead) (void)hipGraphDestroy(dead);
+      throw;
+    }
+    HIPC(hipStreamEndCapture(s, &p.graph));
+    HIPC(hipGraphInstantiate(&p.graph_exec, p.graph, nullptr, nullptr, 0));
+    p.g_CL = CL;
+    p.g_CS = CS;
+    p.g_G = G;
+  });
+}
+
+qdcb_status qdcb_plan_replay(qdcb_plan *plan, void *hip_stream, qdcb_stats *stats) {
+  return guarded([&] {
+    if (!plan) fail(QDCB_E_INVALID, "NULL argument");
+    qdcb_plan &p = *plan;
+    if (!p.graph_exec) fail(QDCB_E_INVALID, "no captured transform (call qdcb_plan_capture)");
+    DeviceGuard g(p.ctx->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipEvent_t e0, e1;
+    HIPC(hipEventCreate(&e0));
+    HIPC(hipEventCreate(&e1));
+    HIPC(hipEventRecord(e0, s));
+    HIPC(hipGraphLaunch(p.graph_exec, s));
+    HIPC(hipEventRecord(e1, s));
+    int32_t ovf[2] = {0, 0};
+    int64_t tot[2] = {0, 0};
+    HIPC(hipMemcpyAsync(&ovf[0], p.C.overflow.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(&tot[0], p.C.dtotal.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    if (p.gaunt) {
+      HIPC(hipMemcpyAsync(&ovf[1], p.G.overflow.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      HIPC(hipMemcpyAsync(&tot[1], p.G.dtotal.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    }
+    unsigned long long kc[4], kg[4];
+    read_counters(p, s, kc, kg);
+    HIPC(hipStreamSynchronize(s));
+    float ms = 0;
+    HIPC(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (ovf[0] || ovf[1]) {  // the kept tiles outgrew the panel: redo eagerly
+      run_eager(p, p.g_CL, p.g_CS, p.g_G, s, stats);
+      if (stats) stats->graph_fallback = 1;
+      return;
+    }
+    p.have_last = true;
+    if (stats) {
+      fill_stats(p, stats, nullptr, ms, kc, kg, tot[0], tot[1]);
+      stats->graph_replay = 1;
+    }
+  });
+}
+
+}  // extern "C"

@@ -46,7 +46,8 @@ class Stats(ctypes.Structure):
                 ("tiles_kept", ctypes.c_int64), ("tiles_total", ctypes.c_int64),
                 ("flops_first_half", ctypes.c_double), ("flops_second_half", ctypes.c_double),
                 ("flops_mfma", ctypes.c_double), ("n_batches", ctypes.c_int32),
-                ("n_chunks", ctypes.c_int32)]
+                ("n_chunks", ctypes.c_int32), ("graph_replay", ctypes.c_int32),
+                ("graph_fallback", ctypes.c_int32)]
 
     def as_dict(self):
         d = {}
@@ -91,9 +92,14 @@ def lib():
         L.qdcb_transform.argtypes = [_P, _P, _P, _P, ctypes.c_uint32, _P,
                                      ctypes.POINTER(Stats)]
         L.qdcb_plan_fetch.argtypes = [_P, ctypes.c_int32, _P, ctypes.c_size_t]
+        L.qdcb_plan_estimate.argtypes = [_P, _P, ctypes.POINTER(PlanDesc),
+                                         ctypes.POINTER(ctypes.c_size_t)]
+        L.qdcb_plan_capture.argtypes = [_P, _P, _P, _P, _P]
+        L.qdcb_plan_replay.argtypes = [_P, _P, ctypes.POINTER(Stats)]
         for f in ("qdcb_ctx_create", "qdcb_basis_create", "qdcb_basis_schwarz",
                   "qdcb_eri_quartets", "qdcb_plan_create", "qdcb_plan_footprint",
-                  "qdcb_transform", "qdcb_plan_fetch"):
+                  "qdcb_transform", "qdcb_plan_fetch", "qdcb_plan_estimate",
+                  "qdcb_plan_capture", "qdcb_plan_replay"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -191,6 +197,15 @@ class Plan:
         _check(lib().qdcb_plan_footprint(self.h, ctypes.byref(b)))
         return int(b.value)
 
+    @staticmethod
+    def estimate(L: Basis, S: Optional[Basis], ham: str, n_mo: int, tau: float = 0.0,
+                 prec: str = "fp64") -> int:
+        desc = PlanDesc(HAM[ham], PREC[prec], int(n_mo), 0, float(tau), 1e-4, 1e-7)
+        b = ctypes.c_size_t(0)
+        _check(lib().qdcb_plan_estimate(L.h, S.h if S is not None else None, ctypes.byref(desc),
+                                        ctypes.byref(b)))
+        return int(b.value)
+
     def transform(self, CL, CS=None, G=None, stream=None):
         """Returns (G, stats).  numpy inputs use the host path; torch CUDA
         tensors the device path (G must then be a CUDA float64 tensor or None)."""
@@ -217,6 +232,22 @@ class Plan:
                                     CSh.ctypes.data if CSh is not None else None,
                                     G.ctypes.data, 0, stream, ctypes.byref(st)))
         return G, st.as_dict()
+
+    def capture(self, CL, CS, G, stream):
+        """Record the transformation of the device tensors CL, CS -> G into a
+        HIP graph on ``stream`` (a torch.cuda.Stream, not the null stream)."""
+        for t in (CL, CS, G):
+            if t is not None and not _is_torch_cuda(t):
+                raise ValueError("capture needs device tensors")
+        self._graph_bufs = (CL, CS, G)  # keep the recorded buffers alive
+        _check(lib().qdcb_plan_capture(self.h, CL.data_ptr(),
+                                       CS.data_ptr() if CS is not None else None, G.data_ptr(),
+                                       stream.cuda_stream))
+
+    def replay(self, stream):
+        st = Stats()
+        _check(lib().qdcb_plan_replay(self.h, stream.cuda_stream, ctypes.byref(st)))
+        return st.as_dict()
 
     def fetch(self, what: int, count: int) -> np.ndarray:
         out = np.empty(count)
