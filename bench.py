@@ -36,9 +36,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="chain40", choices=["chain40", "ll24"])
+    ap.add_argument("--mode", default="transform", choices=["transform", "replay", "serving"],
+                    help="transform: the headline line; replay: captured re-transforms; "
+                         "serving: the request loop")
+    ap.add_argument("--workload", default=None,
+                    help="transform: chain40 (default) or ll24; replay: cluster24 (default), "
+                         "chain40_dcg, chain40")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=32)
+    ap.add_argument("--cpu-rows", type=int, default=96)
+    ap.add_argument("--requests", type=int, default=48)
+    ap.add_argument("--slots", type=int, default=4)
     return ap.parse_args()
 
 
@@ -65,10 +72,19 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.mode == "replay":
+        return main_replay(args)
+    if args.mode == "serving":
+        return main_serving(args)
+    return main_transform(args)
+
+
+def main_transform(args):
     import numpy as np
     import torch
     from paper_2606_04316_amd import qdcb, workloads as wl
 
+    args.workload = args.workload or "chain40"
     sysm = wl.config(args.workload)
     n = sysm.n_mo
     dev = torch.device("cuda:0")
@@ -129,6 +145,88 @@ def main():
         print("cpu baseline: oracle sample ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(sysm, args.cpu_rows, n)
     print(json.dumps(line), flush=True)
+
+
+def main_replay(args):
+    """Re-transforms as captured-graph replays: the transformation is recorded
+    once, then replayed for coefficients C_k (the system's orbitals perturbed
+    by 1e-2 Gaussian noise, seed 3000 + k, re-orthonormalized) written into the
+    same device buffers; eager transforms of C_0 and C_last are compared."""
+    import torch
+    from paper_2606_04316_amd import qdcb, workloads as wl
+
+    name = args.workload or "cluster24"
+    sysm = wl.config(name)
+    n = sysm.n_mo
+    dev = torch.device("cuda:0")
+    ctx = qdcb.Context(0)
+    L, S = qdcb.Basis(ctx, sysm.L), qdcb.Basis(ctx, sysm.S)
+    plan = qdcb.Plan(ctx, L, S, sysm.ham, n, sysm.tau)
+    CL = torch.from_numpy(sysm.CL).to(dev)
+    CS = torch.from_numpy(sysm.CS).to(dev)
+    G = torch.empty((n, n, n, n, 4, 4), dtype=torch.float64, device=dev)
+    stream = torch.cuda.Stream()
+    nrep = max(1, args.steps)
+    coefs = [(sysm.CL, sysm.CS)] + [wl.perturbed_coefficients(sysm, k) for k in range(1, nrep)]
+    # eager reference timings
+    eager_ms = []
+    for cl, cs in (coefs[0], coefs[-1]):
+        CL.copy_(torch.from_numpy(cl))
+        CS.copy_(torch.from_numpy(cs))
+        _, st = plan.transform(CL, CS, G)
+        eager_ms.append(st["ms_total"])
+    Geager_last = G.clone()
+    plan.capture(CL, CS, G, stream)
+    rep_ms, fallbacks = [], 0
+    t0 = time.perf_counter()
+    for k, (cl, cs) in enumerate(coefs):
+        CL.copy_(torch.from_numpy(cl))
+        CS.copy_(torch.from_numpy(cs))
+        torch.cuda.synchronize()
+        st = plan.replay(stream)
+        rep_ms.append(st["ms_total"])
+        fallbacks += st["graph_fallback"]
+        print(f"replay {k + 1}/{nrep}: {st['ms_total']:.1f} ms", file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    same = bool(torch.equal(G, Geager_last))
+    print(json.dumps({
+        "metric": "re-transform time (captured-graph replays)", "mode": "replay",
+        "value": sum(rep_ms) / len(rep_ms), "unit": "ms per re-transform",
+        "higher_is_better": False, "replays": nrep, "fallbacks": fallbacks,
+        "eager_ms": eager_ms, "replay_ms": rep_ms, "wall_s": wall,
+        "last_replay_equals_eager": same, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": sysm.name, "n_atoms": int(sysm.atoms.shape[0]),
+                   "N_L": sysm.L.nfunc, "N_S": sysm.S.nfunc, "n_mo": n, "ham": sysm.ham,
+                   "tau": sysm.tau}}), flush=True)
+
+
+def main_serving(args):
+    """The request loop on a seeded Poisson stream (mean gap 20 ms); each
+    request is a cluster drawn from a pool, with its own active-space size and
+    Hamiltonian (DC or DCG).  Sizes are the stream recipe's reduced ranges
+    (see the design doc); eight requests are re-run alone and compared bitwise."""
+    from paper_2606_04316_amd import serving
+
+    reqs = serving.request_stream(args.requests, seed=5, mean_gap_s=0.02, pool=12,
+                                  atoms=(10, 40), nl=(40, 160), n_mo=(8, 32),
+                                  radius_scale=20.0)
+    ex = serving.GpuExecutor(slots=args.slots)
+    import torch
+    budget = int(0.5 * torch.cuda.mem_get_info()[0])
+    srv = serving.Server(ex, ex.reserve, slots=args.slots, budget_bytes=budget)
+    out = srv.run(reqs)
+    summ = serving.summarize(out)
+    alone = serving.GpuExecutor(slots=1)
+    same = 0
+    for r in out[:: max(1, len(out) // 8)][:8]:
+        solo = serving.Request(rid=r.rid, system=r.system, arrival=0.0)
+        solo.reserve = alone.reserve(solo)
+        same += alone(solo, 0)["digest"] == r.result["digest"]
+    summ.update({"metric": "serving latency", "mode": "serving", "unit": "ms",
+                 "slots": args.slots, "max_concurrency": srv.max_concurrency,
+                 "peak_reserved_GB": srv.peak_in_use / 2 ** 30,
+                 "alone_equals_mix": f"{same}/8", "dtype": "f64", "data": "synthetic"})
+    print(json.dumps(summ), flush=True)
 
 
 def qdcb_kernel_rev():

@@ -103,12 +103,20 @@ typedef struct {
     int32_t ham;       /* qdcb_ham */
     int32_t prec;      /* qdcb_prec; QDCB_PREC_MIXED is not available yet */
     int32_t n_mo;      /* number of quaternion MOs n (Kramers pairs) */
-    int32_t reserved;  /* 0 */
+    int32_t flags;     /* QDCB_PLAN_* bits, 0 by default */
     double tau;        /* Schwarz threshold: a directed contribution (mn <- kl) is
                           kept iff (Q_mn * Q_kl) * Dmax_kl >= tau, Eq. (SchwarzDen) */
     double tier_fp32;  /* mixed precision tier bounds (reserved) */
     double tier_bf16;
 } qdcb_plan_desc;
+
+/* plan flags.  By default the eager transform generates one integral tile
+ * per unique tile pair (b >= k) of the symmetric matrix (mn|kl) = (kl|mn)
+ * whenever all of them fit the integral panel, and the contraction reads it
+ * for both directed tasks (b, k) and (k, b) with the directed predicate
+ * applied per element; QDCB_PLAN_DIRECTED_TILES generates one tile per
+ * directed task instead (the results agree to rounding). */
+#define QDCB_PLAN_DIRECTED_TILES 0x1u
 
 /* Plan for transforming with fixed bases and n_mo.  S must be NULL for
  * QDCB_HAM_LL and non-NULL otherwise.  Orders the pairs of each integral
@@ -151,6 +159,7 @@ typedef struct {
     int32_t n_chunks;        /* MO-pair column chunks */
     int32_t graph_replay;    /* 1: produced by qdcb_plan_replay */
     int32_t graph_fallback;  /* 1: the replay's kept tiles outgrew the panel; redone eagerly */
+    int64_t tiles_made;      /* integral tiles generated (unique or directed, all chunks) */
 } qdcb_stats;
 
 /* Transform.  CL [4][N_L][n], CS [4][N_S][n] (NULL for LL), G [n^4][4][4];

@@ -8,6 +8,11 @@
 // (Q_mn * Q_kl) * Dmax_kl >= tau and is 0 otherwise, which is exactly the skip
 // of that contribution.
 //
+// Unique mode: (mn|kl) = (kl|mn), so one computed tile of a unique pair
+// (b >= k) fills both directed tiles (b <- k) and (k <- b), each masked by
+// its own directed predicate; the transposed one is written column-wise
+// (a minor cost next to the primitive-quartet work of each element).
+//
 // Work layout: 4 wavefronts x 16 ket rows each; lane = bra row.  The primitive
 // pairs of the 64 bra rows are contiguous in the sorted store and are staged in
 // LDS once per workgroup when they fit; the ket pair of a wavefront is uniform
@@ -19,14 +24,17 @@ namespace qdcb {
 
 constexpr int ERI_LDS_PRIMS = 1536;  // 60 KB of bra primitive data
 
+// out: directed tile (bt <- kt) stored [ket j][bra lane], or NULL; outT (unique
+// mode): directed tile (kt <- bt), whose ket rows are bt's, stored [lane][j], or NULL.
 template <bool LDS>
 __device__ __forceinline__ void eri_tile_body(const EriTileArgs &a, const double *sip,
                                               const double *sx, const double *sy,
                                               const double *sz, const double *se, int64_t bp0,
                                               int kt, int bt, int lane, int w, double *out,
-                                              long long kept[4]) {
+                                              double *outT, long long kept[4]) {
   const int64_t brow = (int64_t)bt * TILE + lane;
   const double qb = a.Q[brow];
+  const double db = a.Dmax[brow];
   const int cb = a.cls[brow];
   const int64_t bf0 = a.row_first[brow] - (LDS ? bp0 : 0);
   const int64_t bf1 = a.row_first[brow + 1] - (LDS ? bp0 : 0);
@@ -42,7 +50,9 @@ __device__ __forceinline__ void eri_tile_body(const EriTileArgs &a, const double
     const int ck = a.cls[krow];
     const int64_t kf0 = a.row_first[krow], kf1 = a.row_first[krow + 1];
     double v = 0.0;
-    if ((qb * qk) * dk >= a.tau) {
+    const bool keep_bk = out && (qb * qk) * dk >= a.tau;    // (bra row <- ket row)
+    const bool keep_kb = outT && (qk * qb) * db >= a.tau;   // (ket row <- bra row)
+    if (keep_bk || keep_kb) {
       for (int64_t k = kf0; k < kf1; ++k) {
         const double iq = a.pp.ip[k], qx = a.pp.x[k], qy = a.pp.y[k], qz = a.pp.z[k];
         double s = 0.0;
@@ -50,15 +60,21 @@ __device__ __forceinline__ void eri_tile_body(const EriTileArgs &a, const double
           s += be[b] * coulomb_kernel(bip[b], bx[b], by[b], bz[b], iq, qx, qy, qz);
         v += a.pp.e[k] * s;
       }
-      if (cb >= 0 && ck >= 0) kept[cb * 2 + ck] += 1;
+      if (cb >= 0 && ck >= 0) {
+        if (keep_bk) kept[cb * 2 + ck] += 1;
+        if (keep_kb) kept[ck * 2 + cb] += 1;
+      }
     }
-    out[j * TILE + lane] = v;
+    if (out) out[j * TILE + lane] = keep_bk ? v : 0.0;
+    // transposed tile: its bra rows are kt's rows (j), its ket rows bt's (lane)
+    if (outT) outT[lane * TILE + j] = keep_kb ? v : 0.0;
   }
 }
 
 __global__ void __launch_bounds__(256) k_eri_tiles(EriTileArgs a) {
   __shared__ double sip[ERI_LDS_PRIMS], sx[ERI_LDS_PRIMS], sy[ERI_LDS_PRIMS],
       sz[ERI_LDS_PRIMS], se[ERI_LDS_PRIMS];
+  if (a.overflow && *a.overflow) return;  // uniform: the panel cannot hold the tiles
   if (a.d_total && (int64_t)blockIdx.x >= min(*a.d_total, a.cap)) return;  // uniform exit
   const int64_t slot = a.slot0 + blockIdx.x;
   const int kt = a.tasks[slot];
@@ -67,7 +83,14 @@ __global__ void __launch_bounds__(256) k_eri_tiles(EriTileArgs a) {
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t bp0 = a.row_first[(int64_t)bt * TILE];
   const int64_t nbp = a.row_first[(int64_t)bt * TILE + TILE] - bp0;
-  double *out = a.panel + (int64_t)blockIdx.x * TILE * TILE;
+  double *out, *outT = nullptr;
+  if (a.uslot_bk) {
+    const int32_t s1 = a.uslot_bk[slot], s2 = a.uslot_kb[slot];
+    out = s1 >= 0 ? a.panel + (int64_t)s1 * TILE * TILE : nullptr;
+    outT = s2 >= 0 ? a.panel + (int64_t)s2 * TILE * TILE : nullptr;
+  } else {
+    out = a.panel + (int64_t)blockIdx.x * TILE * TILE;
+  }
   long long kept[4] = {0, 0, 0, 0};
   if (nbp <= ERI_LDS_PRIMS) {
     for (int64_t t = threadIdx.x; t < nbp; t += 256) {
@@ -78,10 +101,10 @@ __global__ void __launch_bounds__(256) k_eri_tiles(EriTileArgs a) {
       se[t] = a.pp.e[bp0 + t];
     }
     __syncthreads();
-    eri_tile_body<true>(a, sip, sx, sy, sz, se, bp0, kt, bt, lane, w, out, kept);
+    eri_tile_body<true>(a, sip, sx, sy, sz, se, bp0, kt, bt, lane, w, out, outT, kept);
   } else {
     eri_tile_body<false>(a, nullptr, nullptr, nullptr, nullptr, nullptr, bp0, kt, bt, lane, w,
-                         out, kept);
+                         out, outT, kept);
   }
   if (a.kept) {
     for (int c = 0; c < 4; ++c) {

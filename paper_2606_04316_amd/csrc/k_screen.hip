@@ -88,6 +88,110 @@ __global__ void __launch_bounds__(256) k_screen_fill(int b0, int ntiles, const d
   }
 }
 
+// Directed slot map: one workgroup per bra tile b, the same ordered
+// compaction as k_screen_fill, writing dmap[b][k] = slot of task (b, k).
+__global__ void __launch_bounds__(256) k_screen_fill_map(int ntiles, const double *Qmax,
+                                                         const double *Bmax, double tau,
+                                                         const int64_t *slot_base,
+                                                         int32_t *dmap) {
+  __shared__ int wsum[4];
+  const int b = blockIdx.x;
+  const double qb = Qmax[b];
+  int64_t out = slot_base[b];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int k0 = 0; k0 < ntiles; k0 += 256) {
+    const int k = k0 + threadIdx.x;
+    const bool keep = k < ntiles && tile_kept(qb, Bmax[k], tau);
+    unsigned long long m = __ballot(keep);
+    int before = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[w] = __popcll(m);
+    __syncthreads();
+    int off = 0;
+    for (int i = 0; i < w; ++i) off += wsum[i];
+    const int total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    if (keep) dmap[(int64_t)b * ntiles + k] = (int32_t)(out + off + before);
+    out += total;
+    __syncthreads();
+  }
+}
+
+void launch_screen_fill_map(int ntiles, const double *Qmax, const double *Bmax, double tau,
+                            const int64_t *slot_base, int32_t *dmap, hipStream_t s) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(k_screen_fill_map, dim3(ntiles), dim3(256), 0, s, ntiles, Qmax, Bmax, tau,
+                     slot_base, dmap);
+}
+
+// Unique (symmetric) tile pairs: (b, k) with k <= b is needed when either
+// direction is kept, T[b][k] or T[k][b].  ucount[b] counts them per row.
+__global__ void __launch_bounds__(256) k_screen_count_u(int ntiles, const double *Qmax,
+                                                        const double *Bmax, double tau,
+                                                        int32_t *ucount) {
+  __shared__ int red[4];
+  const int b = blockIdx.x;
+  const double qb = Qmax[b], bb = Bmax[b];
+  int c = 0;
+  for (int k = threadIdx.x; k <= b; k += 256)
+    c += (tile_kept(qb, Bmax[k], tau) || tile_kept(Qmax[k], bb, tau)) ? 1 : 0;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) ucount[b] = red[0] + red[1] + red[2] + red[3];
+}
+
+void launch_screen_count_u(int ntiles, const double *Qmax, const double *Bmax, double tau,
+                           int32_t *ucount, hipStream_t s) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(k_screen_count_u, dim3(ntiles), dim3(256), 0, s, ntiles, Qmax, Bmax, tau,
+                     ucount);
+}
+
+// Fill the unique pairs of row b in ascending k with their two directed
+// slots (the directed map must be complete: same stream, launched before).
+__global__ void __launch_bounds__(256) k_screen_fill_u(int ntiles, const double *Qmax,
+                                                       const double *Bmax, double tau,
+                                                       const int64_t *ubase,
+                                                       const int32_t *dmap, int32_t *utask_k,
+                                                       int32_t *utask_b, int32_t *uslot_bk,
+                                                       int32_t *uslot_kb) {
+  __shared__ int wsum[4];
+  const int b = blockIdx.x;
+  const double qb = Qmax[b], bb = Bmax[b];
+  int64_t out = ubase[b];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int k0 = 0; k0 <= b; k0 += 256) {
+    const int k = k0 + threadIdx.x;
+    const bool fwd = k <= b && tile_kept(qb, Bmax[k], tau);
+    const bool rev = k < b && tile_kept(Qmax[k], bb, tau);
+    const bool keep = fwd || rev;
+    unsigned long long m = __ballot(keep);
+    int before = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[w] = __popcll(m);
+    __syncthreads();
+    int off = 0;
+    for (int i = 0; i < w; ++i) off += wsum[i];
+    const int total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    if (keep) {
+      const int64_t slot = out + off + before;
+      utask_k[slot] = k;
+      utask_b[slot] = b;
+      uslot_bk[slot] = fwd ? dmap[(int64_t)b * ntiles + k] : -1;
+      uslot_kb[slot] = rev ? dmap[(int64_t)k * ntiles + b] : -1;
+    }
+    out += total;
+    __syncthreads();
+  }
+}
+
+void launch_screen_fill_u(int ntiles, const double *Qmax, const double *Bmax, double tau,
+                          const int64_t *ubase, const int32_t *dmap, int32_t *utask_k,
+                          int32_t *utask_b, int32_t *uslot_bk, int32_t *uslot_kb,
+                          hipStream_t s) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(k_screen_fill_u, dim3(ntiles), dim3(256), 0, s, ntiles, Qmax, Bmax, tau,
+                     ubase, dmap, utask_k, utask_b, uslot_bk, uslot_kb);
+}
+
 // Device-side exclusive scan of the per-bra-tile counts (one workgroup of
 // 1024 threads, each over a contiguous run of counts): slot_base, the total,
 // and an overflow flag when the total exceeds the integral-panel capacity.

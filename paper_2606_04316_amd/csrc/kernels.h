@@ -70,6 +70,19 @@ void launch_screen_fill(int b0, int b1, int ntiles, const double *Qmax, const do
                         double tau, const int64_t *slot_base, int32_t *tasks,
                         int32_t *task_bra, hipStream_t s);
 
+// Directed slot map: dmap[b*ntiles + k] = slot of the kept task (b, k), as
+// written by launch_screen_fill (slots must fit int32).
+void launch_screen_fill_map(int ntiles, const double *Qmax, const double *Bmax, double tau,
+                            const int64_t *slot_base, int32_t *dmap, hipStream_t s);
+// Unique tile pairs (k <= b, either direction kept): counts per row, then the
+// ordered fill with utask_k/utask_b at ubase[b] + rank and, per unique pair,
+// the directed slots of (b, k) and (k, b) from dmap (-1: direction not kept).
+void launch_screen_count_u(int ntiles, const double *Qmax, const double *Bmax, double tau,
+                           int32_t *ucount, hipStream_t s);
+void launch_screen_fill_u(int ntiles, const double *Qmax, const double *Bmax, double tau,
+                          const int64_t *ubase, const int32_t *dmap, int32_t *utask_k,
+                          int32_t *utask_b, int32_t *uslot_bk, int32_t *uslot_kb,
+                          hipStream_t s);
 // Device-side scan of the counts: slot_base[b], *total, *overflow = total > capacity.
 void launch_scan_counts(int ntiles, const int32_t *count, int64_t *slot_base, int64_t *total,
                         int64_t capacity, int32_t *overflow, hipStream_t s);
@@ -80,6 +93,13 @@ void launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
 struct EriTileArgs {
   const int64_t *d_total = nullptr;  // graph mode: slots beyond *d_total (or the
   int64_t cap = 0;                   // panel capacity cap) exit at once
+  const int32_t *overflow = nullptr;  // graph mode: nothing to do when set
+  // unique mode (uslot_bk != NULL): slot i is the unique pair (task_bra[i] >=
+  // tasks[i]); an element is computed when either direction is kept and is
+  // written, masked per direction, to directed slot uslot_bk[i] as is and to
+  // uslot_kb[i] transposed (-1: that direction has no tile); both directions
+  // are counted
+  const int32_t *uslot_bk = nullptr, *uslot_kb = nullptr;
   const int32_t *tasks;       // [slots] ket tile per slot
   const int32_t *task_bra;    // [slots] bra tile per slot
   int64_t slot0;              // slot index of the panel buffer's first entry

@@ -30,7 +30,8 @@ void build_space(qdcb_ctx *ctx, Space &sp, std::vector<RowSrc> &rows,
                    [](const RowSrc &a, const RowSrc &b) { return a.Q > b.Q; });
   sp.P = (int64_t)rows.size();
   sp.Ppad = std::max<int64_t>(round_up(sp.P, TILE), TILE);
-  if (sp.Ppad / TILE > (1 << 30)) fail(QDCB_E_INVALID, "too many pairs");
+  // unique-tile slot numbers are int32: ntiles (ntiles + 1) / 2 < 2^31
+  if (sp.Ppad / TILE > 65535) fail(QDCB_E_INVALID, "too many pairs (at most 65535 tiles)");
   sp.ntiles = (int)(sp.Ppad / TILE);
   sp.h_cls.assign(sp.Ppad, -1);
   sp.h_mu.assign(sp.Ppad, 0);
@@ -113,6 +114,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
       fail(QDCB_E_INVALID, "S must be NULL exactly for QDCB_HAM_LL");
     if (desc->n_mo < 1 || desc->n_mo > 512) fail(QDCB_E_INVALID, "n_mo must be in [1, 512]");
     if (!std::isfinite(desc->tau) || desc->tau < 0) fail(QDCB_E_INVALID, "tau must be >= 0");
+    if (desc->flags & ~(int32_t)QDCB_PLAN_DIRECTED_TILES) fail(QDCB_E_INVALID, "unknown plan flag");
     // bases may belong to another context (resident, shared) on the same device
     if (L->ctx->device != ctx->device || (S && S->ctx->device != ctx->device))
       fail(QDCB_E_INVALID, "basis on another device");
@@ -233,6 +235,16 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
       size_t cap = (size_t)sp->ntiles * (size_t)sp->ntiles;
       sp->tasks.alloc(ctx, cap);
       sp->task_bra.alloc(ctx, cap);
+      size_t ucap = (size_t)sp->ntiles * (size_t)(sp->ntiles + 1) / 2;
+      sp->ucount.alloc(ctx, sp->ntiles);
+      sp->ubase.alloc(ctx, sp->ntiles);
+      sp->utask_k.alloc(ctx, ucap);
+      sp->utask_b.alloc(ctx, ucap);
+      sp->uslot_bk.alloc(ctx, ucap);
+      sp->uslot_kb.alloc(ctx, ucap);
+      sp->dmap.alloc(ctx, cap);
+      sp->udtotal.alloc(ctx, 1);
+      sp->uoverflow.alloc(ctx, 1);
     }
     // room left for the sized buffers, keeping space for the G staging buffer
     // of host-pointer transforms
@@ -325,7 +337,7 @@ qdcb_status qdcb_plan_estimate(const qdcb_basis *L, const qdcb_basis *S,
     double b = 40.0 * prims;                              // primitive-pair data
     b += 48.0 * (PC + PG);                                // row metadata
     b += 16.0 * (PC * ldK + 3.0 * PG * ldK);              // D~ and V, all columns
-    b += 8.0 * (ntC * ntC + ntG * ntG);                   // task lists
+    b += 20.0 * (ntC * ntC + ntG * ntG);                  // task lists, unique pairs, slot map
     double vmax = std::max(NL * NL, NS * NS);
     if (gaunt) vmax = std::max(vmax, NL * NS);
     b += 8.0 * 256 * (vmax + std::max(NL, NS) * 4 * n + 4 * n * n);  // second-half slice

@@ -107,8 +107,11 @@ void density(qdcb_plan &p, Space &sp, const double *dCL, const double *dCS, int 
 }
 
 // Task lists of one space.  Eager: counts to the host, batches sized there.
-// Captured: device-side scan, one batch of at most panel_slots tiles.
+// Captured: device-side scan, one batch of at most panel_slots tiles.  When
+// every directed tile fits the panel (and the plan allows it), the unique
+// tile pairs are listed as well, each with its two directed slots.
 void screen(qdcb_plan &p, Space &sp, bool captured, hipStream_t s) {
+  const bool want_sym = !(p.desc.flags & QDCB_PLAN_DIRECTED_TILES);
   launch_tile_bounds(sp.ntiles, sp.Q.p, sp.Dmax.p, sp.Qmax.p, sp.Bmax.p, s);
   launch_screen_count(sp.ntiles, sp.Qmax.p, sp.Bmax.p, p.desc.tau, sp.count.p, s);
   HIPC(hipGetLastError());
@@ -134,6 +137,37 @@ void screen(qdcb_plan &p, Space &sp, bool captured, hipStream_t s) {
                      sp.tasks.p, sp.task_bra.p, s);
   launch_zero_u64(sp.kept.p, 4, s);
   HIPC(hipGetLastError());
+  sp.sym = false;
+  // directed slots are int32 in the slot map: panel_slots < 2^31 always holds
+  if (!want_sym || (!captured && sp.total > sp.panel_slots)) return;
+  // a captured transform whose directed tiles outgrow the panel writes slots
+  // beyond it into dmap; its integral and contraction kernels then do nothing
+  launch_screen_fill_map(sp.ntiles, sp.Qmax.p, sp.Bmax.p, p.desc.tau, sp.slot_base.p,
+                         sp.dmap.p, s);
+  launch_screen_count_u(sp.ntiles, sp.Qmax.p, sp.Bmax.p, p.desc.tau, sp.ucount.p, s);
+  HIPC(hipGetLastError());
+  if (captured) {
+    launch_scan_counts(sp.ntiles, sp.ucount.p, sp.ubase.p, sp.udtotal.p,
+                       (int64_t)sp.utask_k.n, sp.uoverflow.p, s);
+  } else {
+    sp.ucnt.resize(sp.ntiles);
+    HIPC(hipMemcpyAsync(sp.ucnt.data(), sp.ucount.p, sp.ucnt.size() * sizeof(int32_t),
+                        hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    sp.ub.resize(sp.ntiles);
+    sp.utotal = 0;
+    for (int b = 0; b < sp.ntiles; ++b) {
+      sp.ub[b] = sp.utotal;
+      sp.utotal += sp.ucnt[b];
+    }
+    if ((int64_t)sp.utask_k.n < sp.utotal) fail(QDCB_E_DEVICE, "unique task capacity exceeded");
+    HIPC(hipMemcpyAsync(sp.ubase.p, sp.ub.data(), sp.ub.size() * sizeof(int64_t),
+                        hipMemcpyHostToDevice, s));
+  }
+  launch_screen_fill_u(sp.ntiles, sp.Qmax.p, sp.Bmax.p, p.desc.tau, sp.ubase.p, sp.dmap.p,
+                       sp.utask_k.p, sp.utask_b.p, sp.uslot_bk.p, sp.uslot_kb.p, s);
+  HIPC(hipGetLastError());
+  sp.sym = true;
 }
 
 EriTileArgs eri_args(qdcb_plan &p, Space &sp, int64_t slot0, bool count) {
@@ -171,6 +205,37 @@ FirstHalfArgs fh_args(Space &sp, int b0, int b1, int64_t slot0) {
 // Integral tiles + first half of one space over its current column chunk.
 void first_half(qdcb_plan &p, Space &sp, bool make_tiles, bool count, bool captured,
                 StageTimer &tm, hipStream_t s) {
+  if (sp.sym) {
+    // every directed tile is resident: the unique tiles are computed once
+    // (first chunk) and written to both of their directed slots; then all bra
+    // tiles are contracted in one launch
+    if (make_tiles) {
+      EriTileArgs ea = eri_args(p, sp, 0, count);
+      ea.tasks = sp.utask_k.p;
+      ea.task_bra = sp.utask_b.p;
+      ea.uslot_bk = sp.uslot_bk.p;
+      ea.uslot_kb = sp.uslot_kb.p;
+      if (captured) {
+        ea.overflow = sp.overflow.p;
+        ea.d_total = sp.udtotal.p;
+        ea.cap = sp.panel_slots;
+        launch_eri_tiles(ea, std::min<int64_t>(sp.panel_slots, (int64_t)sp.utask_k.n), s);
+      } else {
+        tm.begin(ST_ERI);
+        launch_eri_tiles(ea, sp.utotal, s);
+        tm.end();
+        p.tiles_made += sp.utotal;
+      }
+      HIPC(hipGetLastError());
+    }
+    FirstHalfArgs fa = fh_args(sp, 0, sp.ntiles, 0);
+    if (captured) fa.overflow = sp.overflow.p;
+    tm.begin(ST_FH);
+    launch_first_half(fa, s);
+    tm.end();
+    HIPC(hipGetLastError());
+    return;
+  }
   if (captured) {
     if (make_tiles) {
       EriTileArgs ea = eri_args(p, sp, 0, count);
@@ -227,6 +292,7 @@ void first_half(qdcb_plan &p, Space &sp, bool make_tiles, bool count, bool captu
       ea.panel = panel;
       tm.begin(ST_ERI, es);
       launch_eri_tiles(ea, B.used, es);
+      p.tiles_made += B.used;
       tm.end(es);
       HIPC(hipGetLastError());
       if (pipe) {
@@ -289,6 +355,7 @@ void enqueue(qdcb_plan &p, const double *dCL, const double *dCS, double *dG, boo
              StageTimer &tm, hipStream_t s) {
   std::vector<Space *> spaces{&p.C};
   if (p.gaunt) spaces.push_back(&p.G);
+  p.tiles_made = 0;
   for (Space *sp : spaces) {
     tm.begin(ST_DENS);
     density(p, *sp, dCL, dCS, 1, 0, p.npair_mo, s);
@@ -312,7 +379,7 @@ void enqueue(qdcb_plan &p, const double *dCL, const double *dCS, double *dG, boo
       density(p, *sp, dCL, dCS, 0, i0, i1, s);
       tm.end();
       // captured mode keeps the tiles of the first chunk (one batch, resident)
-      const bool resident = captured || sp->total <= sp->panel_slots;
+      const bool resident = captured || sp->sym || sp->total <= sp->panel_slots;
       first_half(p, *sp, !resident || i0 == 0, i0 == 0, captured, tm, s);
     }
     tm.begin(ST_SH);
@@ -391,7 +458,10 @@ void run_eager(qdcb_plan &p, const double *dCL, const double *dCS, double *dG, h
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   p.have_last = true;
-  if (stats) fill_stats(p, stats, &tm, ms, kc, kg, p.C.total, p.gaunt ? p.G.total : 0);
+  if (stats) {
+    fill_stats(p, stats, &tm, ms, kc, kg, p.C.total, p.gaunt ? p.G.total : 0);
+    stats->tiles_made = p.tiles_made;
+  }
 }
 
 }  // namespace
@@ -462,6 +532,7 @@ qdcb_status qdcb_plan_capture(qdcb_plan *plan, const double *CL, const double *C
     p.g_CL = CL;
     p.g_CS = CS;
     p.g_G = G;
+    p.g_sym = p.C.sym;
   });
 }
 
@@ -479,12 +550,14 @@ qdcb_status qdcb_plan_replay(qdcb_plan *plan, void *hip_stream, qdcb_stats *stat
     HIPC(hipGraphLaunch(p.graph_exec, s));
     HIPC(hipEventRecord(e1, s));
     int32_t ovf[2] = {0, 0};
-    int64_t tot[2] = {0, 0};
-    HIPC(hipMemcpyAsync(&ovf[0], p.C.overflow.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIPC(hipMemcpyAsync(&tot[0], p.C.dtotal.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    if (p.gaunt) {
-      HIPC(hipMemcpyAsync(&ovf[1], p.G.overflow.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      HIPC(hipMemcpyAsync(&tot[1], p.G.dtotal.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    int64_t tot[2] = {0, 0}, made[2] = {0, 0};
+    const int nsp = p.gaunt ? 2 : 1;
+    for (int i = 0; i < nsp; ++i) {
+      const Space &sp = i ? p.G : p.C;
+      HIPC(hipMemcpyAsync(&ovf[i], sp.overflow.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      HIPC(hipMemcpyAsync(&tot[i], sp.dtotal.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      HIPC(hipMemcpyAsync(&made[i], p.g_sym ? sp.udtotal.p : sp.dtotal.p, sizeof(int64_t),
+                          hipMemcpyDeviceToHost, s));
     }
     unsigned long long kc[4], kg[4];
     read_counters(p, s, kc, kg);
@@ -501,6 +574,7 @@ qdcb_status qdcb_plan_replay(qdcb_plan *plan, void *hip_stream, qdcb_stats *stat
     p.have_last = true;
     if (stats) {
       fill_stats(p, stats, nullptr, ms, kc, kg, tot[0], tot[1]);
+      stats->tiles_made = made[0] + made[1];
       stats->graph_replay = 1;
     }
   });

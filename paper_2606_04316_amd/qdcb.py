@@ -21,6 +21,7 @@ HAM = {"LL": 0, "DC": 1, "DCG": 2}
 PREC = {"fp64": 0, "mixed": 1}
 PTR_DEVICE = 0x1
 FETCH_DMAX, FETCH_Q, FETCH_DMAX_GAUNT, FETCH_Q_GAUNT = 1, 2, 3, 4
+PLAN_DIRECTED_TILES = 0x1
 
 STATUS = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_UNSUPPORTED"}
 
@@ -33,7 +34,7 @@ class QdcbError(RuntimeError):
 
 class PlanDesc(ctypes.Structure):
     _fields_ = [("ham", ctypes.c_int32), ("prec", ctypes.c_int32), ("n_mo", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("tau", ctypes.c_double),
+                ("flags", ctypes.c_int32), ("tau", ctypes.c_double),
                 ("tier_fp32", ctypes.c_double), ("tier_bf16", ctypes.c_double)]
 
 
@@ -47,7 +48,7 @@ class Stats(ctypes.Structure):
                 ("flops_first_half", ctypes.c_double), ("flops_second_half", ctypes.c_double),
                 ("flops_mfma", ctypes.c_double), ("n_batches", ctypes.c_int32),
                 ("n_chunks", ctypes.c_int32), ("graph_replay", ctypes.c_int32),
-                ("graph_fallback", ctypes.c_int32)]
+                ("graph_fallback", ctypes.c_int32), ("tiles_made", ctypes.c_int64)]
 
     def as_dict(self):
         d = {}
@@ -181,11 +182,11 @@ def eri_quartets(A: Basis, B: Basis, idx) -> np.ndarray:
 class Plan:
     def __init__(self, ctx: Context, L: Basis, S: Optional[Basis], ham: str, n_mo: int,
                  tau: float, prec: str = "fp64", tier_fp32: float = 1e-4,
-                 tier_bf16: float = 1e-7):
+                 tier_bf16: float = 1e-7, flags: int = 0):
         self.ctx, self.L, self.S = ctx, L, S
         self.n = int(n_mo)
         self.ham = ham
-        desc = PlanDesc(HAM[ham], PREC[prec], self.n, 0, float(tau), float(tier_fp32),
+        desc = PlanDesc(HAM[ham], PREC[prec], self.n, int(flags), float(tau), float(tier_fp32),
                         float(tier_bf16))
         h = _P()
         _check(lib().qdcb_plan_create(ctx.h, L.h, S.h if S is not None else None,

@@ -326,6 +326,11 @@ def config(name: str) -> System:
         return small_ll(seed=1)
     if name == "chain40":
         return linear_chain(seed=2)
+    if name == "chain40_dcg":
+        return linear_chain(seed=2, ham="DCG")
     if name == "cluster60":
         return cluster(seed=3)
+    if name == "cluster24":
+        # the cluster recipe at 24 atoms (radius scaled by (24/60)^(1/3)), n = 64
+        return cluster(seed=3, n_atoms=24, radius=20.0 * (24 / 60) ** (1 / 3), n=64)
     raise KeyError(name)

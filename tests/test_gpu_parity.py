@@ -36,12 +36,12 @@ def ctx(q):
     c.close()
 
 
-def _gpu_transform(q, ctx, s, tau, C=None):
+def _gpu_transform(q, ctx, s, tau, C=None, flags=0):
     L = q.Basis(ctx, s.L)
     S = q.Basis(ctx, s.S) if s.S is not None else None
     CL = s.CL if C is None else C[0]
     CS = s.CS if C is None else C[1]
-    plan = q.Plan(ctx, L, S, s.ham, CL.shape[2], tau)
+    plan = q.Plan(ctx, L, S, s.ham, CL.shape[2], tau, flags=flags)
     G, st = plan.transform(CL, CS)
     return G, st, plan, (L, S)
 
@@ -229,15 +229,57 @@ def test_column_chunks_and_panel_batches_are_exact(q, budget_mb):
     # A small device budget forces several MO-pair column chunks, narrow
     # second-half slices and (at 24 MB) several integral-panel batches whose
     # tiles are regenerated per chunk; every column is still accumulated in the
-    # same order, so G is bitwise identical to the unconstrained run.
+    # same order, so G is bitwise identical to the unconstrained run.  One
+    # tile per directed task on both sides, so that the integral values are
+    # the same bits.
     s = wl.linear_chain(seed=42, n_atoms=6, spacing=3.0, nl_per_atom=3, ns_per_atom=5, n=16,
                         tau=1e-10, ham="DCG")
     big = q.Context(0)
-    Gref, st_ref, _, _ = _gpu_transform(q, big, s, s.tau)
+    f = q.PLAN_DIRECTED_TILES
+    Gref, st_ref, _, _ = _gpu_transform(q, big, s, s.tau, flags=f)
     assert st_ref["n_chunks"] == 1
     small = q.Context(0, budget_bytes=budget_mb << 20)
-    G, st, _, _ = _gpu_transform(q, small, s, s.tau)
+    G, st, _, _ = _gpu_transform(q, small, s, s.tau, flags=f)
     print(f"budget {budget_mb} MB: chunks {st['n_chunks']}, launches {st['n_batches']}")
     assert st["n_chunks"] > 1
     assert st["kept"] == st_ref["kept"] and st["kept_gaunt"] == st_ref["kept_gaunt"]
     assert np.array_equal(G, Gref)
+
+
+def test_unique_tiles_chunked_are_exact(q):
+    # Unique tile pairs resident across several column chunks: the same tile
+    # bits are read by every chunk, so G equals the one-chunk run bitwise.
+    s = wl.linear_chain(seed=42, n_atoms=6, spacing=3.0, nl_per_atom=3, ns_per_atom=5, n=16,
+                        tau=1e-10, ham="DCG")
+    big = q.Context(0)
+    Gref, st_ref, _, _ = _gpu_transform(q, big, s, s.tau)
+    small = q.Context(0, budget_bytes=40 << 20)
+    G, st, _, _ = _gpu_transform(q, small, s, s.tau)
+    print(f"unique tiles: made {st['tiles_made']} of {st['tiles_kept']} directed, "
+          f"chunks {st['n_chunks']}")
+    assert st["n_chunks"] > 1
+    assert st_ref["tiles_made"] < st_ref["tiles_kept"]
+    assert st["tiles_made"] == st_ref["tiles_made"]
+    assert np.array_equal(G, Gref)
+
+
+@pytest.mark.parametrize("ham,tau", [("DC", 0.0), ("DC", 1e-8), ("DCG", 1e-9)])
+def test_unique_tiles_match_directed_tiles_and_oracle(q, ctx, ham, tau):
+    # One integral tile per unique pair (b >= k), read directly for (b, k) and
+    # transposed for (k, b), against one tile per directed task: same kept
+    # counts, G equal to rounding (the transposed integrals are summed over
+    # primitives in the other order), both at oracle parity.
+    s = wl.linear_chain(seed=43, n_atoms=7, spacing=3.2, nl_per_atom=3, ns_per_atom=4, n=5,
+                        tau=tau, ham=ham)
+    Gu, stu, _, _ = _gpu_transform(q, ctx, s, tau)
+    Gd, std, _, _ = _gpu_transform(q, ctx, s, tau, flags=q.PLAN_DIRECTED_TILES)
+    Go, sto = oracle.transform_direct(s.L, s.S, s.CL, s.CS, ham, tau)
+    assert sto["tie_band"] == 0
+    assert stu["kept"] == std["kept"] == sto["kept"]
+    assert stu["kept_gaunt"] == std["kept_gaunt"] == sto["kept_gaunt"]
+    assert stu["tiles_kept"] == std["tiles_kept"]
+    assert std["tiles_made"] == std["tiles_kept"]
+    assert stu["tiles_made"] < std["tiles_made"]
+    scale = _scale(s, s.CL, s.CS) + (_gaunt_scale(s) if ham == "DCG" else 0.0)
+    assert np.abs(Gu - Gd).max() <= 1e-13 * scale
+    assert np.abs(Gu - Go).max() <= 1e-12 * scale
