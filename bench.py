@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=96)
     ap.add_argument("--requests", type=int, default=48)
     ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="before the transform, run one elementwise copy kernel of this many "
+                         "MiB (read and write), the reference for HBM byte counters")
     return ap.parse_args()
 
 
@@ -95,6 +98,14 @@ def main_transform(args):
     CL = torch.from_numpy(sysm.CL).to(dev)
     CS = torch.from_numpy(sysm.CS).to(dev) if sysm.CS is not None else None
     G = torch.empty((n, n, n, n, 4, 4), dtype=torch.float64, device=dev)
+    if args.copy_calibration_mib:
+        src = torch.ones(args.copy_calibration_mib << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        print(f"copy calibration: {src.numel() * 8} bytes read and written", file=sys.stderr,
+              flush=True)
+        del src, dst
     for i in range(args.warmup):
         plan.transform(CL, CS, G)
         print(f"warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
