@@ -23,27 +23,79 @@ namespace qdcb {
 // First half: one workgroup owns a pair of consecutive 64-row bra tiles (128
 // rows, similar Schwarz factors, hence nearly identical ket lists) and a
 // 128-column slice.  The two ordered ket-tile lists are merged on the fly;
-// a ket tile kept for only one of the two bra tiles contributes zeros to the
-// other half and that half's wavefronts skip its MFMAs.  Four wavefronts hold
-// 64 x 64 accumulator blocks (16 MFMA tiles each).  Per staged step of 32 ket
-// rows the workgroup reads 32 KB of integral tile and 32 KB of density slice
-// for 2 x 128 x 128 x 32 flops.
-constexpr int FH_COLS = 128;       // columns per workgroup
-constexpr int FH_ROWS = 2 * TILE;  // bra rows per workgroup
-constexpr int FH_KH = 32;          // ket rows staged per step
-constexpr int AS_LD = FH_ROWS + 2; // LDS row strides (padded against bank conflicts)
-constexpr int BS_LD = FH_COLS + 2;
+// a ket tile kept for only one of the two bra tiles leaves the other half's
+// staging rows stale and that half's wavefronts skip its MFMAs.  Four
+// wavefronts hold 64 x 64 accumulator blocks (16 MFMA tiles each).
+//
+// Staging: steps of KH ket rows.  Each step's integral rows (2 x 64 bra
+// values per ket row) and density rows (128 columns per ket row) go straight
+// from global memory into LDS with 16-byte direct loads (one 1 KB row per
+// wavefront instruction, no registers), double-buffered: the loads of step
+// t+1 are issued right after the barrier that opens step t and complete while
+// step t's MFMAs run.
+//
+// Workgroup order: the chip's 8 XCDs take workgroups round-robin and each
+// has its own L2.  With at least 8 column slices, XCD x gets the slices
+// x, x+8, ... and walks bra-tile pairs in order with its slices fastest, so
+// the workgroups resident on one XCD share integral tiles (same bra pair,
+// other slices) and density rows (neighbouring bra pairs, same slices).
+constexpr int FH_COLS = 128;        // columns per workgroup
+constexpr int FH_ROWS = 2 * TILE;   // bra rows per workgroup
+constexpr int FH_KH = 16;           // ket rows staged per step
+constexpr int AS_LD = FH_ROWS + 2;  // LDS row strides in doubles (padded against bank
+constexpr int BS_LD = FH_COLS + 2;  // conflicts; 1040 B keeps rows 16-byte aligned)
+constexpr int N_XCD = 8;
 
-__global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a) {
-  __shared__ double As[FH_KH * AS_LD];
-  __shared__ double Bs[FH_KH * BS_LD];
+typedef __attribute__((address_space(3))) void *lds_ptr;
+
+__device__ __forceinline__ void load_row_lds(const double *src, double *lds_row) {
+  __builtin_amdgcn_global_load_lds(src, (lds_ptr)lds_row, 16, 0, 0);
+}
+
+__device__ __forceinline__ void wait_loads() {
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt, lgkmcnt unchanged (max)
+}
+
+// One step's MFMAs from staged buffers A (KH x AS_LD) and B (KH x BS_LD).
+template <int KH>
+__device__ __forceinline__ void fh_mfma(const double *Ac, const double *Bc, int wr, int wc, int lr,
+                                        int lk, dbl4 (&acc)[4][4]) {
+#pragma unroll
+  for (int kk = 0; kk < KH / 4; ++kk) {
+    const int j = kk * 4 + lk;
+    double av[4], bv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) av[r] = Ac[j * AS_LD + wr * 64 + r * 16 + lr];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) bv[c] = Bc[j * BS_LD + wc * 64 + c * 16 + lr];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[r][c] = MFMA_F64(av[r], bv[c], acc[r][c]);
+  }
+}
+
+template <int KH>
+__global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, int nct, int ncx) {
+  // two staging buffers as distinct objects, so that the compiler can tell
+  // the loads into one from the reads of the other
+  __shared__ __attribute__((aligned(16))) double As0[KH * AS_LD], As1[KH * AS_LD];
+  __shared__ __attribute__((aligned(16))) double Bs0[KH * BS_LD], Bs1[KH * BS_LD];
   if (a.overflow && *a.overflow) return;  // uniform: the task lists did not fit
-  // bra-tile pairs vary fastest: workgroups in flight share the column slice
-  // and, through the ordered ket lists of neighbouring bra tiles, density rows
-  const int bt0 = a.b0 + 2 * blockIdx.x;
+  int bp, ct;
+  if (ncx > 0) {  // XCD-aware order (see above)
+    const int L = blockIdx.x, x = L % N_XCD, loc = L / N_XCD;
+    bp = loc / ncx;
+    ct = x + N_XCD * (loc % ncx);
+    if (ct >= nct) return;  // uniform: ragged column slices
+  } else {
+    bp = blockIdx.x % nbp;
+    ct = blockIdx.x / nbp;
+  }
+  const int bt0 = a.b0 + 2 * bp;
   const bool two = bt0 + 1 < a.b1;
-  const int ct = blockIdx.y;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = w >> 1, wc = w & 1;  // wave's 64-row half (bra tile) and 64-column half
   const int64_t c0 = (int64_t)ct * FH_COLS;
   const int lr = lane & 15, lk = lane >> 4;
@@ -54,54 +106,77 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a) {
   const int64_t s0 = a.slot_base[bt0], s1 = two ? a.slot_base[bt0 + 1] : 0;
   const int n0 = a.count[bt0], n1 = two ? a.count[bt0 + 1] : 0;
   int i0 = 0, i1 = 0;
-  while (i0 < n0 || i1 < n1) {
-    const int k0 = i0 < n0 ? a.tasks[s0 + i0] : INT_MAX;
-    const int k1 = i1 < n1 ? a.tasks[s1 + i1] : INT_MAX;
-    const int kt = k0 < k1 ? k0 : k1;
-    const bool has0 = k0 == kt, has1 = k1 == kt;
-    const double *P0 = has0 ? a.panel + (s0 + i0 - a.slot0) * (TILE * TILE) : nullptr;
-    const double *P1 = has1 ? a.panel + (s1 + i1 - a.slot0) * (TILE * TILE) : nullptr;
-    i0 += has0;
-    i1 += has1;
-    const bool active = wr == 0 ? has0 : has1;  // uniform per wavefront
-    for (int h = 0; h < TILE / FH_KH; ++h) {
-      // integral slice: ket rows j of this step x 128 bra rows (two tiles)
-#pragma unroll
-      for (int i = 0; i < (FH_KH * FH_ROWS / 2) / 256; ++i) {
-        const int e = tid + 256 * i;  // double2 index
-        const int jj = e / (FH_ROWS / 2), m2 = e % (FH_ROWS / 2);
-        const int half = m2 >= TILE / 2;
-        const double *P = half ? P1 : P0;
-        double2 v = make_double2(0.0, 0.0);
-        if (P) v = reinterpret_cast<const double2 *>(P + (h * FH_KH + jj) * TILE)[m2 - half * (TILE / 2)];
-        *reinterpret_cast<double2 *>(As + jj * AS_LD + 2 * m2) = v;
-      }
-      const int64_t krow0 = (int64_t)kt * TILE + h * FH_KH;
-#pragma unroll
-      for (int i = 0; i < (FH_KH * FH_COLS / 2) / 256; ++i) {
-        const int e = tid + 256 * i;
-        const int r = e / (FH_COLS / 2), c2 = e % (FH_COLS / 2);
-        const double2 v = reinterpret_cast<const double2 *>(a.D + (krow0 + r) * a.ld + c0)[c2];
-        *reinterpret_cast<double2 *>(Bs + r * BS_LD + 2 * c2) = v;
-      }
-      __syncthreads();
-      if (active) {
-#pragma unroll
-        for (int kk = 0; kk < FH_KH / 4; ++kk) {
-          const int j = kk * 4 + lk;
-          double av[4], bv[4];
-#pragma unroll
-          for (int r = 0; r < 4; ++r) av[r] = As[j * AS_LD + wr * 64 + r * 16 + lr];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) bv[c] = Bs[j * BS_LD + wc * 64 + c * 16 + lr];
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) acc[r][c] = MFMA_F64(av[r], bv[c], acc[r][c]);
-        }
-      }
-      __syncthreads();
+  // step state: current task's ket tile and tiles, sub-step h within the task
+  const double *P0 = nullptr, *P1 = nullptr;
+  int kt = 0, h = TILE / KH;
+  bool has0 = false, has1 = false;
+  // heads of the two ordered lists, read one task ahead so that the list
+  // reads are off the path between a barrier and the next step's loads
+  int nk0 = n0 > 0 ? a.tasks[s0] : INT_MAX;
+  int nk1 = n1 > 0 ? a.tasks[s1] : INT_MAX;
+  // advance to the next step; false when the merged lists are exhausted
+  auto advance = [&]() -> bool {
+    if (++h < TILE / KH) return true;
+    const int k0 = __builtin_amdgcn_readfirstlane(nk0), k1 = __builtin_amdgcn_readfirstlane(nk1);
+    if (k0 == INT_MAX && k1 == INT_MAX) return false;
+    kt = k0 < k1 ? k0 : k1;
+    has0 = k0 == kt;
+    has1 = k1 == kt;
+    P0 = has0 ? a.panel + (s0 + i0 - a.slot0) * (TILE * TILE) : nullptr;
+    P1 = has1 ? a.panel + (s1 + i1 - a.slot0) * (TILE * TILE) : nullptr;
+    if (has0) {
+      ++i0;
+      nk0 = i0 < n0 ? a.tasks[s0 + i0] : INT_MAX;
     }
+    if (has1) {
+      ++i1;
+      nk1 = i1 < n1 ? a.tasks[s1 + i1] : INT_MAX;
+    }
+    h = 0;
+    return true;
+  };
+  // direct loads of the current step: wave w stages rows w, w+4, ... of the
+  // integral slice (lanes 0-31: tile of bra tile bt0, lanes 32-63: of bt0+1)
+  // and of the density slice
+  auto issue = [&](double *A, double *B) {
+    const double *P = lane < 32 ? P0 : P1;
+#pragma unroll
+    for (int q = 0; q < KH / 4; ++q) {
+      const int jj = w + 4 * q;
+      if (P) load_row_lds(P + (h * KH + jj) * TILE + 2 * (lane & 31), A + jj * AS_LD);
+    }
+    const double *Dr = a.D + ((int64_t)kt * TILE + h * KH) * a.ld + c0 + 2 * lane;
+#pragma unroll
+    for (int q = 0; q < KH / 4; ++q) {
+      const int r = w + 4 * q;
+      load_row_lds(Dr + r * a.ld, B + r * BS_LD);
+    }
+  };
+
+  // steps alternate between the two buffers: even steps in 0, odd in 1
+  bool more = advance();
+  bool act = wr == 0 ? has0 : has1;  // uniform per wavefront
+  if (more) issue(As0, Bs0);
+  while (more) {
+    wait_loads();
+    __syncthreads();  // even step staged by every wave; buffer 1's readers are done
+    bool act_cur = act;
+    more = advance();
+    if (more) {
+      act = wr == 0 ? has0 : has1;
+      issue(As1, Bs1);
+    }
+    if (act_cur) fh_mfma<KH>(As0, Bs0, wr, wc, lr, lk, acc);
+    if (!more) break;
+    wait_loads();
+    __syncthreads();  // odd step staged; buffer 0's readers are done
+    act_cur = act;
+    more = advance();
+    if (more) {
+      act = wr == 0 ? has0 : has1;
+      issue(As0, Bs0);
+    }
+    if (act_cur) fh_mfma<KH>(As1, Bs1, wr, wc, lr, lk, acc);
   }
   if (wr == 1 && !two) return;
   const int64_t row0 = (int64_t)(bt0 + wr) * TILE;
@@ -118,7 +193,11 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a) {
 
 void launch_first_half(const FirstHalfArgs &a, hipStream_t s) {
   if (a.b1 <= a.b0 || a.ncol_tiles <= 0) return;
-  hipLaunchKernelGGL(k_first_half, dim3((a.b1 - a.b0 + 1) / 2, a.ncol_tiles), dim3(256), 0, s, a);
+  const int nbp = (a.b1 - a.b0 + 1) / 2, nct = a.ncol_tiles;
+  const int ncx = nct >= N_XCD ? (nct + N_XCD - 1) / N_XCD : 0;
+  // at most 32768 bra pairs x (ncol / 128 + 8) slices: well inside the grid limit
+  const int64_t grid = ncx ? (int64_t)N_XCD * ncx * nbp : (int64_t)nbp * nct;
+  hipLaunchKernelGGL(k_first_half<FH_KH>, dim3((unsigned)grid), dim3(256), 0, s, a, nbp, nct, ncx);
 }
 
 // ---------------------------------------------------------------------------
