@@ -36,9 +36,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", default="transform", choices=["transform", "replay", "serving"],
+    ap.add_argument("--mode", default="transform",
+                    choices=["transform", "replay", "serving", "mixed"],
                     help="transform: the headline line; replay: captured re-transforms; "
-                         "serving: the request loop")
+                         "serving: the request loop; mixed: FP64/FP32/BF16 tiers vs FP64")
+    ap.add_argument("--tiers", default="1e-4:1e-7:screen,1e-4:1e-7:g,1e-6:1e-9:g,1e-8:1e-11:g",
+                    help="mixed: comma-separated tier_fp32:tier_bf16:rule settings "
+                         "(rule screen = screening bound, g = bound including the bra side)")
     ap.add_argument("--workload", default=None,
                     help="transform: chain40 (default) or ll24; replay: cluster24 (default), "
                          "chain40_dcg, chain40")
@@ -79,6 +83,8 @@ def main():
         return main_replay(args)
     if args.mode == "serving":
         return main_serving(args)
+    if args.mode == "mixed":
+        return main_mixed(args)
     return main_transform(args)
 
 
@@ -209,6 +215,76 @@ def main_replay(args):
         "config": {"workload": sysm.name, "n_atoms": int(sysm.atoms.shape[0]),
                    "N_L": sysm.L.nfunc, "N_S": sysm.S.nfunc, "n_mo": n, "ham": sysm.ham,
                    "tau": sysm.tau}}), flush=True)
+
+
+def main_mixed(args):
+    """Mixed precision against the FP64 transform of the same inputs: for each
+    tier setting, max |G_mixed - G_fp64|, the occupied-block Coulomb sum
+    J_occ = 4 sum_{p,r < n/2} G^00_pprr, its change, the time and the speedup,
+    with the tiles and first-half time per tier."""
+    import torch
+    from paper_2606_04316_amd import qdcb, workloads as wl
+
+    name = args.workload or "cluster24"
+    sysm = wl.config(name)
+    n = sysm.n_mo
+    dev = torch.device("cuda:0")
+    ctx = qdcb.Context(0)
+    L = qdcb.Basis(ctx, sysm.L)
+    S = qdcb.Basis(ctx, sysm.S) if sysm.S is not None else None
+    CL = torch.from_numpy(sysm.CL).to(dev)
+    CS = torch.from_numpy(sysm.CS).to(dev) if sysm.CS is not None else None
+    occ = torch.arange(n // 2, device=dev)
+
+    def j_occ(G):
+        return 4.0 * float(G[occ][:, occ][:, :, occ][:, :, :, occ][..., 0, 0]
+                           .diagonal(0, 0, 1).diagonal(0, 0, 1).sum())
+
+    def timed(plan, G):
+        for _ in range(max(1, args.warmup)):
+            plan.transform(CL, CS, G)
+        ms, st = [], None
+        for _ in range(max(1, args.steps)):
+            _, st = plan.transform(CL, CS, G)
+            ms.append(st["ms_total"])
+        return sorted(ms)[len(ms) // 2], st
+
+    ref = qdcb.Plan(ctx, L, S, sysm.ham, n, sysm.tau)
+    G0 = torch.empty((n, n, n, n, 4, 4), dtype=torch.float64, device=dev)
+    ms0, st0 = timed(ref, G0)
+    ref.close()
+    j0 = j_occ(G0)
+    gmax = float(G0.abs().max())
+    print(f"fp64: {ms0:.1f} ms", file=sys.stderr, flush=True)
+    G1 = torch.empty_like(G0)
+    runs = []
+    for spec in args.tiers.split(","):
+        t32, t16, rule = spec.split(":")
+        flags = qdcb.PLAN_TIER_BY_G if rule == "g" else 0
+        plan = qdcb.Plan(ctx, L, S, sysm.ham, n, sysm.tau, prec="mixed", tier_fp32=float(t32),
+                         tier_bf16=float(t16), flags=flags)
+        ms, st = timed(plan, G1)
+        plan.close()
+        err = float((G1 - G0).abs().max())
+        run = {"tier_fp32": float(t32), "tier_bf16": float(t16), "rule": rule, "ms": ms,
+               "speedup": ms0 / ms, "max_abs_err": err, "abs_err_J_occ": abs(j_occ(G1) - j0),
+               "meets_1e-10": err <= 1e-10, "tiles_tier": st["tiles_tier"],
+               "ms_tier": st["ms_tier"], "ms_eri": st["ms_eri"],
+               "ms_second_half": st["ms_second_half"]}
+        runs.append(run)
+        print(f"{spec}: {ms:.1f} ms, err {err:.2e}", file=sys.stderr, flush=True)
+    ok = [r for r in runs if r["meets_1e-10"]]
+    best = max(ok, key=lambda r: r["speedup"]) if ok else None
+    print(json.dumps({
+        "metric": "mixed vs FP64 speedup at max |dG| <= 1e-10 Eh", "mode": "mixed",
+        "value": best["speedup"] if best else None, "unit": "x",
+        "higher_is_better": True, "fp64_ms": ms0, "fp64_ms_tier": st0["ms_tier"],
+        "fp64_ms_first_half": st0["ms_first_half"], "fp64_ms_eri": st0["ms_eri"],
+        "max_abs_G": gmax, "J_occ": j0, "best": best, "runs": runs,
+        "dtype": "f64+f32+bf16", "data": "synthetic",
+        "config": {"workload": sysm.name, "n_atoms": int(sysm.atoms.shape[0]),
+                   "N_L": sysm.L.nfunc, "N_S": sysm.S.nfunc if sysm.S is not None else 0,
+                   "n_mo": n, "ham": sysm.ham, "tau": sysm.tau}}), flush=True)
 
 
 def main_serving(args):

@@ -101,12 +101,17 @@ qdcb_status qdcb_eri_quartets(const qdcb_basis *A, const qdcb_basis *B, int64_t 
 
 typedef struct {
     int32_t ham;       /* qdcb_ham */
-    int32_t prec;      /* qdcb_prec; QDCB_PREC_MIXED is not available yet */
+    int32_t prec;      /* qdcb_prec */
     int32_t n_mo;      /* number of quaternion MOs n (Kramers pairs) */
     int32_t flags;     /* QDCB_PLAN_* bits, 0 by default */
     double tau;        /* Schwarz threshold: a directed contribution (mn <- kl) is
                           kept iff (Q_mn * Q_kl) * Dmax_kl >= tau, Eq. (SchwarzDen) */
-    double tier_fp32;  /* mixed precision tier bounds (reserved) */
+    double tier_fp32;  /* QDCB_PREC_MIXED: a kept directed tile (b, k) with bound
+                          B = max_b Q * max_k (Q Dmax) is contracted in FP64 when
+                          B >= tier_fp32, with FP32 MFMA operands when
+                          tier_bf16 <= B < tier_fp32, else with BF16 operands (FP32
+                          accumulation, power-of-2 block scales, V and the second
+                          half in FP64).  Requires 0 <= tier_bf16 <= tier_fp32. */
     double tier_bf16;
 } qdcb_plan_desc;
 
@@ -117,6 +122,11 @@ typedef struct {
  * applied per element; QDCB_PLAN_DIRECTED_TILES generates one tile per
  * directed task instead (the results agree to rounding). */
 #define QDCB_PLAN_DIRECTED_TILES 0x1u
+/* QDCB_PREC_MIXED: assign tiers by B = max_b (Q Dmax) * max_k (Q Dmax), which
+ * also bounds the bra-side coefficient products that carry a first-half
+ * contribution into G (Dmax of the bra pair bounds |conj(C_mp) C_nq|), instead
+ * of the screening bound max_b Q * max_k (Q Dmax). */
+#define QDCB_PLAN_TIER_BY_G 0x2u
 
 /* Plan for transforming with fixed bases and n_mo.  S must be NULL for
  * QDCB_HAM_LL and non-NULL otherwise.  Orders the pairs of each integral
@@ -160,6 +170,9 @@ typedef struct {
     int32_t graph_replay;    /* 1: produced by qdcb_plan_replay */
     int32_t graph_fallback;  /* 1: the replay's kept tiles outgrew the panel; redone eagerly */
     int64_t tiles_made;      /* integral tiles generated (unique or directed, all chunks) */
+    int64_t tiles_tier[3];   /* mixed: kept directed tiles contracted in FP64, FP32, BF16
+                                (eager transforms) */
+    double ms_tier[3];       /* mixed: first-half time per tier (eager transforms) */
 } qdcb_stats;
 
 /* Transform.  CL [4][N_L][n], CS [4][N_S][n] (NULL for LL), G [n^4][4][4];

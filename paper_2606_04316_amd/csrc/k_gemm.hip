@@ -13,6 +13,7 @@
 // Both use v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16] and
 // B[l/16][l%16]; accumulator element i of lane l is D[l/16 + 4*i][l%16].
 #include <climits>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -56,26 +57,97 @@ __device__ __forceinline__ void wait_loads() {
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt, lgkmcnt unchanged (max)
 }
 
-// One step's MFMAs from staged buffers A (KH x AS_LD) and B (KH x BS_LD).
-template <int KH>
+// Precision of a first-half launch: FP64 (stores V) or a reduced tier (adds
+// to V).  The reduced tiers read the same FP64 staging buffers and round each
+// operand as it is loaded for the MFMA:
+//   FP32: v_mfma_f32_16x16x4f32, lane l supplies A[l%16][l/16] and B[l/16][l%16];
+//   BF16: v_mfma_f32_16x16x16bf16_1k, lane l supplies A[l%16][4(l/16)..+3] and
+//         B[4(l/16)..+3][l%16];
+// both accumulate D[4(l/16)+i][l%16] in FP32.  Block scaling: the integral
+// tile (b, k) is multiplied by 2^-eI with 2^eI above the Cauchy-Schwarz bound
+// Qmax_b Qmax_k of its elements and the density rows of ket tile k by 2^-eD
+// with 2^eD above 2 max Dmax (the symmetrized density is a sum of two terms),
+// so every rounded operand is at most 1 in magnitude; each task's products
+// go to a scaled FP32 partial that is multiplied back by the exact
+// 2^(eI+eD) into the FP32 running sum, and V (FP64) receives the sum once.
+enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };
+
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int scale_exp(double bound) {
+  int e = 0;
+  (void)frexp(bound, &e);  // bound < 2^e
+  return bound > 0.0 ? e : 0;
+}
+
+template <int PREC>
+struct FhAcc {
+  typedef typename std::conditional<PREC == PREC_F64, dbl4, flt4>::type V;
+  V acc[4][4];
+  V part[PREC == PREC_F64 ? 1 : 4][PREC == PREC_F64 ? 1 : 4];
+};
+
+// One step's MFMAs from staged FP64 buffers A (KH x AS_LD) and B (KH x BS_LD).
+template <int KH, int PREC>
 __device__ __forceinline__ void fh_mfma(const double *Ac, const double *Bc, int wr, int wc, int lr,
-                                        int lk, dbl4 (&acc)[4][4]) {
+                                        int lk, double sI, double sD, FhAcc<PREC> &f) {
+  if constexpr (PREC == PREC_F64) {
 #pragma unroll
-  for (int kk = 0; kk < KH / 4; ++kk) {
-    const int j = kk * 4 + lk;
-    double av[4], bv[4];
+    for (int kk = 0; kk < KH / 4; ++kk) {
+      const int j = kk * 4 + lk;
+      double av[4], bv[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) av[r] = Ac[j * AS_LD + wr * 64 + r * 16 + lr];
+      for (int r = 0; r < 4; ++r) av[r] = Ac[j * AS_LD + wr * 64 + r * 16 + lr];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) bv[c] = Bc[j * BS_LD + wc * 64 + c * 16 + lr];
+      for (int c = 0; c < 4; ++c) bv[c] = Bc[j * BS_LD + wc * 64 + c * 16 + lr];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+      for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[r][c] = MFMA_F64(av[r], bv[c], acc[r][c]);
+        for (int c = 0; c < 4; ++c)
+          f.acc[r][c] = MFMA_F64(av[r], bv[c], f.acc[r][c]);
+    }
+  } else if constexpr (PREC == PREC_F32) {
+#pragma unroll
+    for (int kk = 0; kk < KH / 4; ++kk) {
+      const int j = kk * 4 + lk;
+      float av[4], bv[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) av[r] = (float)(Ac[j * AS_LD + wr * 64 + r * 16 + lr] * sI);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bv[c] = (float)(Bc[j * BS_LD + wc * 64 + c * 16 + lr] * sD);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          f.part[r][c] =
+              __builtin_amdgcn_mfma_f32_16x16x4f32(av[r], bv[c], f.part[r][c], 0, 0, 0);
+    }
+  } else {
+#pragma unroll
+    for (int kk = 0; kk < KH / 16; ++kk) {
+      bf16x4 av[4], bv[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int j = kk * 16 + 4 * lk + t;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          av[r][t] = (__bf16)(float)(Ac[j * AS_LD + wr * 64 + r * 16 + lr] * sI);
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          bv[c][t] = (__bf16)(float)(Bc[j * BS_LD + wc * 64 + c * 16 + lr] * sD);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          f.part[r][c] =
+              __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[r], bv[c], f.part[r][c], 0, 0, 0);
+    }
   }
 }
 
-template <int KH>
+template <int KH, int PREC>
 __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, int nct, int ncx) {
   // two staging buffers as distinct objects, so that the compiler can tell
   // the loads into one from the reads of the other
@@ -94,26 +166,35 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
   }
   const int bt0 = a.b0 + 2 * bp;
   const bool two = bt0 + 1 < a.b1;
+  // panel slot bases and list starts of the two bra tiles
+  const int64_t s0 = a.slot_base[bt0], s1 = two ? a.slot_base[bt0 + 1] : 0;
+  const int64_t l0 = s0 + (a.toff ? a.toff[bt0] : 0);
+  const int64_t l1 = two ? s1 + (a.toff ? a.toff[bt0 + 1] : 0) : 0;
+  const int n0 = a.count[bt0], n1 = two ? a.count[bt0 + 1] : 0;
+  if (PREC != PREC_F64 && n0 + n1 == 0) return;  // uniform: nothing to add in this tier
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = w >> 1, wc = w & 1;  // wave's 64-row half (bra tile) and 64-column half
   const int64_t c0 = (int64_t)ct * FH_COLS;
   const int lr = lane & 15, lk = lane >> 4;
-  dbl4 acc[4][4];
+  FhAcc<PREC> f;
   for (int r = 0; r < 4; ++r)
-    for (int c = 0; c < 4; ++c) acc[r][c] = (dbl4){0.0, 0.0, 0.0, 0.0};
-
-  const int64_t s0 = a.slot_base[bt0], s1 = two ? a.slot_base[bt0 + 1] : 0;
-  const int n0 = a.count[bt0], n1 = two ? a.count[bt0 + 1] : 0;
+    for (int c = 0; c < 4; ++c) f.acc[r][c] = (typename FhAcc<PREC>::V){0, 0, 0, 0};
+  if constexpr (PREC != PREC_F64)
+    for (int r = 0; r < 4; ++r)
+      for (int c = 0; c < 4; ++c) f.part[r][c] = (typename FhAcc<PREC>::V){0, 0, 0, 0};
+  // bra tile bound of this wave's half (block scales of the reduced tiers)
+  const double qbw = PREC != PREC_F64 ? a.Qmax[bt0 + (two ? wr : 0)] : 0.0;
   int i0 = 0, i1 = 0;
   // step state: current task's ket tile and tiles, sub-step h within the task
   const double *P0 = nullptr, *P1 = nullptr;
   int kt = 0, h = TILE / KH;
   bool has0 = false, has1 = false;
+  int eI = 0, eD = 0;  // block-scale exponents of the current task (this wave's half)
   // heads of the two ordered lists, read one task ahead so that the list
   // reads are off the path between a barrier and the next step's loads
-  int nk0 = n0 > 0 ? a.tasks[s0] : INT_MAX;
-  int nk1 = n1 > 0 ? a.tasks[s1] : INT_MAX;
+  int nk0 = n0 > 0 ? a.tasks[l0] : INT_MAX;
+  int nk1 = n1 > 0 ? a.tasks[l1] : INT_MAX;
   // advance to the next step; false when the merged lists are exhausted
   auto advance = [&]() -> bool {
     if (++h < TILE / KH) return true;
@@ -122,15 +203,25 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
     kt = k0 < k1 ? k0 : k1;
     has0 = k0 == kt;
     has1 = k1 == kt;
-    P0 = has0 ? a.panel + (s0 + i0 - a.slot0) * (TILE * TILE) : nullptr;
-    P1 = has1 ? a.panel + (s1 + i1 - a.slot0) * (TILE * TILE) : nullptr;
     if (has0) {
+      const int64_t r0 = a.rank ? a.rank[l0 + i0] : i0;
+      P0 = a.panel + (s0 + r0 - a.slot0) * (TILE * TILE);
       ++i0;
-      nk0 = i0 < n0 ? a.tasks[s0 + i0] : INT_MAX;
+      nk0 = i0 < n0 ? a.tasks[l0 + i0] : INT_MAX;
+    } else {
+      P0 = nullptr;
     }
     if (has1) {
+      const int64_t r1 = a.rank ? a.rank[l1 + i1] : i1;
+      P1 = a.panel + (s1 + r1 - a.slot0) * (TILE * TILE);
       ++i1;
-      nk1 = i1 < n1 ? a.tasks[s1 + i1] : INT_MAX;
+      nk1 = i1 < n1 ? a.tasks[l1 + i1] : INT_MAX;
+    } else {
+      P1 = nullptr;
+    }
+    if (PREC != PREC_F64) {
+      eI = scale_exp(qbw * a.Qmax[kt]);
+      eD = scale_exp(2.0 * a.Dtmax[kt]);
     }
     h = 0;
     return true;
@@ -152,31 +243,56 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
       load_row_lds(Dr + r * a.ld, B + r * BS_LD);
     }
   };
+  // what the MFMAs of a staged step need, taken when the step is issued
+  struct StepDesc {
+    bool act, last;
+    int eI, eD;
+  };
+  auto desc = [&]() -> StepDesc {
+    return StepDesc{wr == 0 ? has0 : has1, h == TILE / KH - 1, eI, eD};
+  };
+  // one staged step: MFMAs when this wave's bra tile keeps the task; at the
+  // task's last step the reduced tiers fold the scaled partial into the sum
+  auto run = [&](const double *A, const double *B, const StepDesc &d) {
+    if (!d.act) return;
+    fh_mfma<KH, PREC>(A, B, wr, wc, lr, lk, ldexp(1.0, -d.eI), ldexp(1.0, -d.eD), f);
+    if constexpr (PREC != PREC_F64) {
+      if (!d.last) return;
+      const float sc = ldexpf(1.0f, d.eI + d.eD);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          f.acc[r][c] += f.part[r][c] * sc;
+          f.part[r][c] = (typename FhAcc<PREC>::V){0, 0, 0, 0};
+        }
+    }
+  };
 
   // steps alternate between the two buffers: even steps in 0, odd in 1
   bool more = advance();
-  bool act = wr == 0 ? has0 : has1;  // uniform per wavefront
+  StepDesc nxt = desc();
   if (more) issue(As0, Bs0);
   while (more) {
     wait_loads();
     __syncthreads();  // even step staged by every wave; buffer 1's readers are done
-    bool act_cur = act;
+    StepDesc cur = nxt;
     more = advance();
     if (more) {
-      act = wr == 0 ? has0 : has1;
+      nxt = desc();
       issue(As1, Bs1);
     }
-    if (act_cur) fh_mfma<KH>(As0, Bs0, wr, wc, lr, lk, acc);
+    run(As0, Bs0, cur);
     if (!more) break;
     wait_loads();
     __syncthreads();  // odd step staged; buffer 0's readers are done
-    act_cur = act;
+    cur = nxt;
     more = advance();
     if (more) {
-      act = wr == 0 ? has0 : has1;
+      nxt = desc();
       issue(As0, Bs0);
     }
-    if (act_cur) fh_mfma<KH>(As1, Bs1, wr, wc, lr, lk, acc);
+    run(As1, Bs1, cur);
   }
   if (wr == 1 && !two) return;
   const int64_t row0 = (int64_t)(bt0 + wr) * TILE;
@@ -186,8 +302,13 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
     for (int c = 0; c < 4; ++c)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int64_t row = row0 + r * 16 + lk + 4 * i;
-        a.V[row * a.ld + c0 + wc * 64 + c * 16 + lr] = acc[r][c][i];
+        if constexpr (PREC == PREC_F64) {
+          const int64_t row = row0 + r * 16 + lk + 4 * i;
+          a.V[row * a.ld + c0 + wc * 64 + c * 16 + lr] = f.acc[r][c][i];
+        } else {
+          const int64_t row = row0 + r * 16 + 4 * lk + i;
+          a.V[row * a.ld + c0 + wc * 64 + c * 16 + lr] += (double)f.acc[r][c][i];
+        }
       }
 }
 
@@ -197,7 +318,21 @@ void launch_first_half(const FirstHalfArgs &a, hipStream_t s) {
   const int ncx = nct >= N_XCD ? (nct + N_XCD - 1) / N_XCD : 0;
   // at most 32768 bra pairs x (ncol / 128 + 8) slices: well inside the grid limit
   const int64_t grid = ncx ? (int64_t)N_XCD * ncx * nbp : (int64_t)nbp * nct;
-  hipLaunchKernelGGL(k_first_half<FH_KH>, dim3((unsigned)grid), dim3(256), 0, s, a, nbp, nct, ncx);
+  hipLaunchKernelGGL((k_first_half<FH_KH, PREC_F64>), dim3((unsigned)grid), dim3(256), 0, s, a,
+                     nbp, nct, ncx);
+}
+
+void launch_first_half_lp(const FirstHalfArgs &a, int tier, hipStream_t s) {
+  if (a.b1 <= a.b0 || a.ncol_tiles <= 0) return;
+  const int nbp = (a.b1 - a.b0 + 1) / 2, nct = a.ncol_tiles;
+  const int ncx = nct >= N_XCD ? (nct + N_XCD - 1) / N_XCD : 0;
+  const int64_t grid = ncx ? (int64_t)N_XCD * ncx * nbp : (int64_t)nbp * nct;
+  if (tier == 2)
+    hipLaunchKernelGGL((k_first_half<FH_KH, PREC_BF16>), dim3((unsigned)grid), dim3(256), 0, s,
+                       a, nbp, nct, ncx);
+  else
+    hipLaunchKernelGGL((k_first_half<FH_KH, PREC_F32>), dim3((unsigned)grid), dim3(256), 0, s,
+                       a, nbp, nct, ncx);
 }
 
 // ---------------------------------------------------------------------------

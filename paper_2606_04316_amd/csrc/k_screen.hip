@@ -14,23 +14,27 @@ namespace qdcb {
 
 __global__ void __launch_bounds__(64) k_tile_bounds(int ntiles, const double *Q,
                                                     const double *Dmax, double *Qmax,
-                                                    double *Bmax) {
+                                                    double *Bmax, double *Dtmax) {
   int t = blockIdx.x;
   int64_t row = (int64_t)t * TILE + threadIdx.x;
   double q = Q[row];
-  double b = q * Dmax[row];
+  double d = Dmax[row];
+  double b = q * d;
   q = wave_max(q);
   b = wave_max(b);
+  d = wave_max(d);
   if (threadIdx.x == 0) {
     Qmax[t] = q;
     Bmax[t] = b;
+    if (Dtmax) Dtmax[t] = d;
   }
 }
 
 void launch_tile_bounds(int ntiles, const double *Q, const double *Dmax, double *Qmax,
-                        double *Bmax, hipStream_t s) {
+                        double *Bmax, double *Dtmax, hipStream_t s) {
   if (ntiles <= 0) return;
-  hipLaunchKernelGGL(k_tile_bounds, dim3(ntiles), dim3(64), 0, s, ntiles, Q, Dmax, Qmax, Bmax);
+  hipLaunchKernelGGL(k_tile_bounds, dim3(ntiles), dim3(64), 0, s, ntiles, Q, Dmax, Qmax, Bmax,
+                     Dtmax);
 }
 
 __device__ __forceinline__ bool tile_kept(double qb, double bk, double tau) {
@@ -190,6 +194,65 @@ void launch_screen_fill_u(int ntiles, const double *Qmax, const double *Bmax, do
   if (ntiles <= 0) return;
   hipLaunchKernelGGL(k_screen_fill_u, dim3(ntiles), dim3(256), 0, s, ntiles, Qmax, Bmax, tau,
                      ubase, dmap, utask_k, utask_b, uslot_bk, uslot_kb);
+}
+
+// Tier split: one workgroup per bra tile, three ordered compactions of its
+// task list (one per tier) into the same segment.
+__global__ void __launch_bounds__(256) k_tier_split(int ntiles, const double *Qmax,
+                                                    const double *Bmax, int gbound, double t32,
+                                                    double t16,
+                                                    const int64_t *slot_base,
+                                                    const int32_t *count, const int32_t *tasks,
+                                                    int32_t *ttasks, int32_t *trank,
+                                                    int32_t *tcount, int32_t *toff) {
+  __shared__ int wsum[4];
+  const int b = blockIdx.x;
+  const double qb = gbound ? Bmax[b] : Qmax[b];
+  const int64_t base = slot_base[b];
+  const int n = count[b];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int out = 0;
+  for (int tier = 0; tier < 3; ++tier) {
+    const int first = out;
+    for (int i0 = 0; i0 < n; i0 += 256) {
+      const int i = i0 + threadIdx.x;
+      int k = 0;
+      bool keep = false;
+      if (i < n) {
+        k = tasks[base + i];
+        const double B = qb * Bmax[k];
+        const int t = B >= t32 ? 0 : (B >= t16 ? 1 : 2);
+        keep = t == tier;
+      }
+      unsigned long long m = __ballot(keep);
+      int before = __popcll(m & ((1ull << lane) - 1ull));
+      if (lane == 0) wsum[w] = __popcll(m);
+      __syncthreads();
+      int off = 0;
+      for (int j = 0; j < w; ++j) off += wsum[j];
+      const int total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+      if (keep) {
+        ttasks[base + out + off + before] = k;
+        trank[base + out + off + before] = i;
+      }
+      out += total;
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      toff[tier * ntiles + b] = first;
+      tcount[tier * ntiles + b] = out - first;
+    }
+  }
+}
+
+void launch_tier_split(int ntiles, const double *Qmax, const double *Bmax, int gbound,
+                       double t32, double t16, const int64_t *slot_base, const int32_t *count,
+                       const int32_t *tasks, int32_t *ttasks, int32_t *trank, int32_t *tcount,
+                       int32_t *toff, hipStream_t s) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(k_tier_split, dim3(ntiles), dim3(256), 0, s, ntiles, Qmax, Bmax, gbound,
+                     t32, t16,
+                     slot_base, count, tasks, ttasks, trank, tcount, toff);
 }
 
 // Device-side exclusive scan of the per-bra-tile counts (one workgroup of

@@ -58,9 +58,21 @@ struct DensityArgs {
 void launch_density(const DensityArgs &a, hipStream_t s);
 
 // ---- screening (k_screen.hip)
-// Tile bounds: Qmax[t] = max Q, Bmax[t] = max Q*Dmax over the 64 rows of tile t.
+// Tile bounds: Qmax[t] = max Q, Bmax[t] = max Q*Dmax over the 64 rows of tile t,
+// and (when Dtmax is not NULL) Dtmax[t] = max Dmax.
 void launch_tile_bounds(int ntiles, const double *Q, const double *Dmax, double *Qmax,
-                        double *Bmax, hipStream_t s);
+                        double *Bmax, double *Dtmax, hipStream_t s);
+// Precision tiers of the directed tasks: tier 0 (FP64) when the tile bound
+// B = Qmax[b] * Bmax[k] >= t32, tier 1 (FP32) when >= t16, else tier 2 (BF16);
+// gbound = 1 uses B = Bmax[b] * Bmax[k] instead (bra-side density included).  Each
+// bra tile's ordered list tasks[slot_base[b] + i] (i < count[b]) is split into
+// three ordered sub-lists stored in its own segment: ttasks[slot_base[b] +
+// toff[t*ntiles + b] + i] for i < tcount[t*ntiles + b], with trank = the
+// task's rank i in the full list (its panel slot is slot_base[b] + rank).
+void launch_tier_split(int ntiles, const double *Qmax, const double *Bmax, int gbound,
+                       double t32, double t16, const int64_t *slot_base, const int32_t *count,
+                       const int32_t *tasks, int32_t *ttasks, int32_t *trank, int32_t *tcount,
+                       int32_t *toff, hipStream_t s);
 // count[b] = number of ket tiles k with Qmax[b]*Bmax[k] >= tau*(1-1e-12).
 void launch_screen_count(int ntiles, const double *Qmax, const double *Bmax, double tau,
                          int32_t *count, hipStream_t s);
@@ -117,6 +129,11 @@ void launch_eri_tiles(const EriTileArgs &a, int64_t nslots, hipStream_t s);
 // ---- first-half contraction (k_gemm.hip)
 struct FirstHalfArgs {
   const int32_t *overflow = nullptr;  // graph mode: nothing to do when set
+  // tier sub-lists (NULL: the full directed lists): bra tile b's list starts at
+  // slot_base[b] + toff[b], and entry e's panel slot is slot_base[b] + rank[e]
+  const int32_t *toff = nullptr, *rank = nullptr;
+  // FP32 / BF16 tiers: per-tile bounds that set the power-of-2 block scales
+  const double *Qmax = nullptr, *Dtmax = nullptr;
   int b0, b1;
   const int64_t *slot_base;
   const int32_t *count;
@@ -129,6 +146,9 @@ struct FirstHalfArgs {
   int ncol_tiles;        // ld / 128
 };
 void launch_first_half(const FirstHalfArgs &a, hipStream_t s);
+// Reduced-precision tiers: V += the tier's contributions, computed with FP32
+// (tier 1) or BF16 (tier 2) MFMA operands and FP32 accumulation.
+void launch_first_half_lp(const FirstHalfArgs &a, int tier, hipStream_t s);
 
 // Batched FP64 GEMM, row-major: C[b] = alpha * op(A[b]) * B[b] + beta * C[b].
 // op(A) = A (transA = 0, A[m][k] at m*lda + k) or A^T (transA = 1, A[k][m] at k*lda + m).

@@ -108,13 +108,18 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
     if (!ctx || !L || !desc || !out) fail(QDCB_E_INVALID, "NULL argument");
     if (desc->ham != QDCB_HAM_LL && desc->ham != QDCB_HAM_DC && desc->ham != QDCB_HAM_DCG)
       fail(QDCB_E_INVALID, "unknown Hamiltonian");
-    if (desc->prec != QDCB_PREC_FP64)
-      fail(QDCB_E_UNSUPPORTED, "only QDCB_PREC_FP64 is available in this build");
+    if (desc->prec != QDCB_PREC_FP64 && desc->prec != QDCB_PREC_MIXED)
+      fail(QDCB_E_INVALID, "unknown precision mode");
+    if (desc->prec == QDCB_PREC_MIXED &&
+        !(std::isfinite(desc->tier_fp32) && std::isfinite(desc->tier_bf16) &&
+          desc->tier_bf16 >= 0 && desc->tier_bf16 <= desc->tier_fp32))
+      fail(QDCB_E_INVALID, "mixed precision needs finite tiers 0 <= tier_bf16 <= tier_fp32");
     if ((desc->ham == QDCB_HAM_LL) != (S == nullptr))
       fail(QDCB_E_INVALID, "S must be NULL exactly for QDCB_HAM_LL");
     if (desc->n_mo < 1 || desc->n_mo > 512) fail(QDCB_E_INVALID, "n_mo must be in [1, 512]");
     if (!std::isfinite(desc->tau) || desc->tau < 0) fail(QDCB_E_INVALID, "tau must be >= 0");
-    if (desc->flags & ~(int32_t)QDCB_PLAN_DIRECTED_TILES) fail(QDCB_E_INVALID, "unknown plan flag");
+    if (desc->flags & ~(int32_t)(QDCB_PLAN_DIRECTED_TILES | QDCB_PLAN_TIER_BY_G))
+      fail(QDCB_E_INVALID, "unknown plan flag");
     // bases may belong to another context (resident, shared) on the same device
     if (L->ctx->device != ctx->device || (S && S->ctx->device != ctx->device))
       fail(QDCB_E_INVALID, "basis on another device");
@@ -240,6 +245,13 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
       sp->ubase.alloc(ctx, sp->ntiles);
       sp->utask_k.alloc(ctx, ucap);
       sp->utask_b.alloc(ctx, ucap);
+      sp->Dtmax.alloc(ctx, sp->ntiles);
+      if (desc->prec == QDCB_PREC_MIXED) {
+        sp->ttasks.alloc(ctx, cap);
+        sp->trank.alloc(ctx, cap);
+        sp->tcount.alloc(ctx, 3 * (size_t)sp->ntiles);
+        sp->toff.alloc(ctx, 3 * (size_t)sp->ntiles);
+      }
       sp->uslot_bk.alloc(ctx, ucap);
       sp->uslot_kb.alloc(ctx, ucap);
       sp->dmap.alloc(ctx, cap);
@@ -338,6 +350,7 @@ qdcb_status qdcb_plan_estimate(const qdcb_basis *L, const qdcb_basis *S,
     b += 48.0 * (PC + PG);                                // row metadata
     b += 16.0 * (PC * ldK + 3.0 * PG * ldK);              // D~ and V, all columns
     b += 20.0 * (ntC * ntC + ntG * ntG);                  // task lists, unique pairs, slot map
+    if (desc->prec == QDCB_PREC_MIXED) b += 8.0 * (ntC * ntC + ntG * ntG);  // tier sub-lists
     double vmax = std::max(NL * NL, NS * NS);
     if (gaunt) vmax = std::max(vmax, NL * NS);
     b += 8.0 * 256 * (vmax + std::max(NL, NS) * 4 * n + 4 * n * n);  // second-half slice

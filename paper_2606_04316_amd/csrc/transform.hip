@@ -21,7 +21,7 @@ void check_finite_host(const double *x, size_t n, const char *what) {
     if (!std::isfinite(x[i])) fail(QDCB_E_INVALID, std::string("non-finite value in ") + what);
 }
 
-enum { ST_DENS = 0, ST_SCREEN = 1, ST_ERI = 2, ST_FH = 3, ST_SH = 4, NSTAGE = 5 };
+enum { ST_DENS = 0, ST_SCREEN = 1, ST_ERI = 2, ST_FH = 3, ST_SH = 4, ST_FH32 = 5, ST_FH16 = 6 };
 
 // Stage timing with events read back after the final synchronization;
 // disabled (null) while a graph is being captured.
@@ -112,7 +112,7 @@ void density(qdcb_plan &p, Space &sp, const double *dCL, const double *dCS, int 
 // tile pairs are listed as well, each with its two directed slots.
 void screen(qdcb_plan &p, Space &sp, bool captured, hipStream_t s) {
   const bool want_sym = !(p.desc.flags & QDCB_PLAN_DIRECTED_TILES);
-  launch_tile_bounds(sp.ntiles, sp.Q.p, sp.Dmax.p, sp.Qmax.p, sp.Bmax.p, s);
+  launch_tile_bounds(sp.ntiles, sp.Q.p, sp.Dmax.p, sp.Qmax.p, sp.Bmax.p, sp.Dtmax.p, s);
   launch_screen_count(sp.ntiles, sp.Qmax.p, sp.Bmax.p, p.desc.tau, sp.count.p, s);
   HIPC(hipGetLastError());
   if (captured) {
@@ -137,6 +137,19 @@ void screen(qdcb_plan &p, Space &sp, bool captured, hipStream_t s) {
                      sp.tasks.p, sp.task_bra.p, s);
   launch_zero_u64(sp.kept.p, 4, s);
   HIPC(hipGetLastError());
+  if (p.desc.prec == QDCB_PREC_MIXED) {
+    launch_tier_split(sp.ntiles, sp.Qmax.p, sp.Bmax.p,
+                      (p.desc.flags & QDCB_PLAN_TIER_BY_G) ? 1 : 0, p.desc.tier_fp32,
+                      p.desc.tier_bf16,
+                      sp.slot_base.p, sp.count.p, sp.tasks.p, sp.ttasks.p, sp.trank.p,
+                      sp.tcount.p, sp.toff.p, s);
+    HIPC(hipGetLastError());
+    if (!captured) {
+      sp.h_tcount.resize(3 * (size_t)sp.ntiles);
+      HIPC(hipMemcpyAsync(sp.h_tcount.data(), sp.tcount.p, sp.h_tcount.size() * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, s));
+    }
+  }
   sp.sym = false;
   // directed slots are int32 in the slot map: panel_slots < 2^31 always holds
   if (!want_sym || (!captured && sp.total > sp.panel_slots)) return;
@@ -202,6 +215,35 @@ FirstHalfArgs fh_args(Space &sp, int b0, int b1, int64_t slot0) {
   return fa;
 }
 
+// First-half contraction of bra tiles [fa.b0, fa.b1): FP64 plans in one
+// launch; mixed plans as the FP64 tier (which stores V) followed by the FP32
+// and BF16 tiers (which add to it).
+void contract(qdcb_plan &p, Space &sp, FirstHalfArgs fa, StageTimer &tm, hipStream_t s) {
+  if (p.desc.prec != QDCB_PREC_MIXED) {
+    tm.begin(ST_FH);
+    launch_first_half(fa, s);
+    tm.end();
+    HIPC(hipGetLastError());
+    return;
+  }
+  fa.tasks = sp.ttasks.p;
+  fa.rank = sp.trank.p;
+  fa.Qmax = sp.Qmax.p;
+  fa.Dtmax = sp.Dtmax.p;
+  const int stage[3] = {ST_FH, ST_FH32, ST_FH16};
+  for (int t = 0; t < 3; ++t) {
+    fa.count = sp.tcount.p + (size_t)t * sp.ntiles;
+    fa.toff = sp.toff.p + (size_t)t * sp.ntiles;
+    tm.begin(stage[t]);
+    if (t == 0)
+      launch_first_half(fa, s);
+    else
+      launch_first_half_lp(fa, t, s);
+    tm.end();
+    HIPC(hipGetLastError());
+  }
+}
+
 // Integral tiles + first half of one space over its current column chunk.
 void first_half(qdcb_plan &p, Space &sp, bool make_tiles, bool count, bool captured,
                 StageTimer &tm, hipStream_t s) {
@@ -230,10 +272,7 @@ void first_half(qdcb_plan &p, Space &sp, bool make_tiles, bool count, bool captu
     }
     FirstHalfArgs fa = fh_args(sp, 0, sp.ntiles, 0);
     if (captured) fa.overflow = sp.overflow.p;
-    tm.begin(ST_FH);
-    launch_first_half(fa, s);
-    tm.end();
-    HIPC(hipGetLastError());
+    contract(p, sp, fa, tm, s);
     return;
   }
   if (captured) {
@@ -245,8 +284,7 @@ void first_half(qdcb_plan &p, Space &sp, bool make_tiles, bool count, bool captu
     }
     FirstHalfArgs fa = fh_args(sp, 0, sp.ntiles, 0);
     fa.overflow = sp.overflow.p;
-    launch_first_half(fa, s);
-    HIPC(hipGetLastError());
+    contract(p, sp, fa, tm, s);
     return;
   }
   // Batches of consecutive bra tiles.  When the tiles are generated here, the
@@ -302,10 +340,7 @@ void first_half(qdcb_plan &p, Space &sp, bool make_tiles, bool count, bool captu
     }
     FirstHalfArgs fa = fh_args(sp, B.b0, B.b1, sp.base[B.b0]);
     fa.panel = panel;
-    tm.begin(ST_FH);
-    launch_first_half(fa, s);
-    tm.end();
-    HIPC(hipGetLastError());
+    contract(p, sp, fa, tm, s);
     if (pipe && !resident_all) done[i] = tm.record(s);
   }
 }
@@ -397,9 +432,12 @@ void fill_stats(qdcb_plan &p, qdcb_stats *stats, StageTimer *tm, double ms_total
     stats->ms_density = tm->total(ST_DENS);
     stats->ms_screen = tm->total(ST_SCREEN);
     stats->ms_eri = tm->total(ST_ERI);
-    stats->ms_first_half = tm->total(ST_FH);
+    stats->ms_first_half = tm->total(ST_FH) + tm->total(ST_FH32) + tm->total(ST_FH16);
     stats->ms_second_half = tm->total(ST_SH);
     stats->n_batches = tm->launches(ST_FH);
+    stats->ms_tier[0] = tm->total(ST_FH);
+    stats->ms_tier[1] = tm->total(ST_FH32);
+    stats->ms_tier[2] = tm->total(ST_FH16);
   }
   stats->ms_total = ms_total;
   double ktot = 0;
@@ -430,6 +468,15 @@ void fill_stats(qdcb_plan &p, qdcb_stats *stats, StageTimer *tm, double ms_total
   stats->n_chunks = nchunks;
   stats->flops_mfma = 2.0 * TILE * TILE * nchunks *
                       ((double)p.C.ld * tiles_c + (p.gaunt ? (double)p.G.ld * tiles_g : 0.0));
+  if (p.desc.prec == QDCB_PREC_MIXED) {
+    for (Space *sp : {&p.C, &p.G}) {
+      if (sp == &p.G && !p.gaunt) continue;
+      if (sp->h_tcount.size() != 3 * (size_t)sp->ntiles) continue;
+      for (int t = 0; t < 3; ++t)
+        for (int b = 0; b < sp->ntiles; ++b)
+          stats->tiles_tier[t] += sp->h_tcount[(size_t)t * sp->ntiles + b];
+    }
+  }
 }
 
 void read_counters(qdcb_plan &p, hipStream_t s, unsigned long long kc[4],

@@ -22,6 +22,7 @@ PREC = {"fp64": 0, "mixed": 1}
 PTR_DEVICE = 0x1
 FETCH_DMAX, FETCH_Q, FETCH_DMAX_GAUNT, FETCH_Q_GAUNT = 1, 2, 3, 4
 PLAN_DIRECTED_TILES = 0x1
+PLAN_TIER_BY_G = 0x2
 
 STATUS = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_UNSUPPORTED"}
 
@@ -48,7 +49,8 @@ class Stats(ctypes.Structure):
                 ("flops_first_half", ctypes.c_double), ("flops_second_half", ctypes.c_double),
                 ("flops_mfma", ctypes.c_double), ("n_batches", ctypes.c_int32),
                 ("n_chunks", ctypes.c_int32), ("graph_replay", ctypes.c_int32),
-                ("graph_fallback", ctypes.c_int32), ("tiles_made", ctypes.c_int64)]
+                ("graph_fallback", ctypes.c_int32), ("tiles_made", ctypes.c_int64),
+                ("tiles_tier", ctypes.c_int64 * 3), ("ms_tier", ctypes.c_double * 3)]
 
     def as_dict(self):
         d = {}
