@@ -50,6 +50,35 @@ __device__ __forceinline__ double coulomb_kernel(double ip, double px, double py
   return x >= 6.0 ? iR : erf(x) * iR;
 }
 
+// Boys F0 by Taylor expansion about a grid: T_i = i / 8 (i = 0 .. BOYS_N - 1,
+// T < 36), tab[8 i + k] = (-1)^k F_k(T_i) / k!, so that for |d| <= 1/16
+//   F0(T_i + d) = sum_k tab[8 i + k] d^k  (k <= 7),
+// remainder below F_8(T_i) (1/16)^8 / 8! < 3e-16 relative.  For T >= 36
+// erf(sqrt T) = 1 to double precision and the kernel is 1 / R.  Same value
+// as coulomb_kernel, without the range branches of erf.
+constexpr int BOYS_N = 289;
+constexpr double BOYS_TMAX = 36.0;
+
+__device__ __forceinline__ double coulomb_kernel_tab(const double *tab, double ip, double px,
+                                                     double py, double pz, double iq, double qx,
+                                                     double qy, double qz) {
+  const double t = ip + iq;  // 1/rho
+  const double sr = rsqrt(t);
+  const double dx = px - qx, dy = py - qy, dz = pz - qz;
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double T = r2 * (sr * sr);
+  if (T < BOYS_TMAX) {
+    const int i = (int)rint(T * 8.0);
+    const double d = T - 0.125 * i;
+    const double *c = tab + 8 * i;
+    double f = c[7];
+#pragma unroll
+    for (int k = 6; k >= 0; --k) f = fma(f, d, c[k]);
+    return TWO_OVER_SQRTPI * sr * f;
+  }
+  return rsqrt(r2);
+}
+
 __device__ __forceinline__ double prim_quartet(double ip, double px, double py, double pz,
                                                double pe, double iq, double qx, double qy,
                                                double qz, double qe) {

@@ -13,7 +13,10 @@
 // its own directed predicate; the transposed one is written column-wise
 // (a minor cost next to the primitive-quartet work of each element).
 //
-// Work layout: 4 wavefronts x 16 ket rows each; lane = bra row.  The primitive
+// The Boys function comes from a Taylor table staged in LDS (no range branches
+// to diverge across lanes; see common.h).
+//
+// Work layout: 8 wavefronts x 8 ket rows each; lane = bra row.  The primitive
 // pairs of the 64 bra rows are contiguous in the sorted store and are staged in
 // LDS once per workgroup when they fit; the ket pair of a wavefront is uniform
 // across its lanes, so its primitive data comes through scalar loads.  Stores
@@ -23,15 +26,18 @@
 namespace qdcb {
 
 constexpr int ERI_LDS_PRIMS = 1536;  // 60 KB of bra primitive data
+constexpr int ERI_WAVES = 8;         // wavefronts per tile, TILE / ERI_WAVES ket rows each
+constexpr int ERI_THREADS = 64 * ERI_WAVES;
 
 // out: directed tile (bt <- kt) stored [ket j][bra lane], or NULL; outT (unique
 // mode): directed tile (kt <- bt), whose ket rows are bt's, stored [lane][j], or NULL.
 template <bool LDS>
 __device__ __forceinline__ void eri_tile_body(const EriTileArgs &a, const double *sip,
                                               const double *sx, const double *sy,
-                                              const double *sz, const double *se, int64_t bp0,
-                                              int kt, int bt, int lane, int w, double *out,
-                                              double *outT, long long kept[4]) {
+                                              const double *sz, const double *se,
+                                              const double *tab, int64_t bp0, int kt, int bt,
+                                              int lane, int w, double *out, double *outT,
+                                              long long kept[4]) {
   const int64_t brow = (int64_t)bt * TILE + lane;
   const double qb = a.Q[brow];
   const double db = a.Dmax[brow];
@@ -43,8 +49,8 @@ __device__ __forceinline__ void eri_tile_body(const EriTileArgs &a, const double
   const double *by = LDS ? sy : a.pp.y;
   const double *bz = LDS ? sz : a.pp.z;
   const double *be = LDS ? se : a.pp.e;
-  for (int i = 0; i < TILE / 4; ++i) {
-    const int j = w + 4 * i;
+  for (int i = 0; i < TILE / ERI_WAVES; ++i) {
+    const int j = w + ERI_WAVES * i;
     const int64_t krow = (int64_t)kt * TILE + j;
     const double qk = a.Q[krow], dk = a.Dmax[krow];
     const int ck = a.cls[krow];
@@ -57,7 +63,7 @@ __device__ __forceinline__ void eri_tile_body(const EriTileArgs &a, const double
         const double iq = a.pp.ip[k], qx = a.pp.x[k], qy = a.pp.y[k], qz = a.pp.z[k];
         double s = 0.0;
         for (int64_t b = bf0; b < bf1; ++b)
-          s += be[b] * coulomb_kernel(bip[b], bx[b], by[b], bz[b], iq, qx, qy, qz);
+          s += be[b] * coulomb_kernel_tab(tab, bip[b], bx[b], by[b], bz[b], iq, qx, qy, qz);
         v += a.pp.e[k] * s;
       }
       if (cb >= 0 && ck >= 0) {
@@ -71,9 +77,10 @@ __device__ __forceinline__ void eri_tile_body(const EriTileArgs &a, const double
   }
 }
 
-__global__ void __launch_bounds__(256) k_eri_tiles(EriTileArgs a) {
+__global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles(EriTileArgs a) {
   __shared__ double sip[ERI_LDS_PRIMS], sx[ERI_LDS_PRIMS], sy[ERI_LDS_PRIMS],
       sz[ERI_LDS_PRIMS], se[ERI_LDS_PRIMS];
+  __shared__ __attribute__((aligned(16))) double tab[BOYS_N * 8];
   if (a.overflow && *a.overflow) return;  // uniform: the panel cannot hold the tiles
   if (a.d_total && (int64_t)blockIdx.x >= min(*a.d_total, a.cap)) return;  // uniform exit
   const int64_t slot = a.slot0 + blockIdx.x;
@@ -92,8 +99,9 @@ __global__ void __launch_bounds__(256) k_eri_tiles(EriTileArgs a) {
     out = a.panel + (int64_t)blockIdx.x * TILE * TILE;
   }
   long long kept[4] = {0, 0, 0, 0};
+  for (int t = threadIdx.x; t < BOYS_N * 8; t += ERI_THREADS) tab[t] = a.boys[t];
   if (nbp <= ERI_LDS_PRIMS) {
-    for (int64_t t = threadIdx.x; t < nbp; t += 256) {
+    for (int64_t t = threadIdx.x; t < nbp; t += ERI_THREADS) {
       sip[t] = a.pp.ip[bp0 + t];
       sx[t] = a.pp.x[bp0 + t];
       sy[t] = a.pp.y[bp0 + t];
@@ -101,10 +109,11 @@ __global__ void __launch_bounds__(256) k_eri_tiles(EriTileArgs a) {
       se[t] = a.pp.e[bp0 + t];
     }
     __syncthreads();
-    eri_tile_body<true>(a, sip, sx, sy, sz, se, bp0, kt, bt, lane, w, out, outT, kept);
+    eri_tile_body<true>(a, sip, sx, sy, sz, se, tab, bp0, kt, bt, lane, w, out, outT, kept);
   } else {
-    eri_tile_body<false>(a, nullptr, nullptr, nullptr, nullptr, nullptr, bp0, kt, bt, lane, w,
-                         out, outT, kept);
+    __syncthreads();
+    eri_tile_body<false>(a, nullptr, nullptr, nullptr, nullptr, nullptr, tab, bp0, kt, bt, lane,
+                         w, out, outT, kept);
   }
   if (a.kept) {
     for (int c = 0; c < 4; ++c) {
@@ -116,7 +125,7 @@ __global__ void __launch_bounds__(256) k_eri_tiles(EriTileArgs a) {
 
 void launch_eri_tiles(const EriTileArgs &a, int64_t nslots, hipStream_t s) {
   if (nslots <= 0) return;
-  hipLaunchKernelGGL(k_eri_tiles, dim3((unsigned)nslots), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_eri_tiles, dim3((unsigned)nslots), dim3(ERI_THREADS), 0, s, a);
 }
 
 }  // namespace qdcb

@@ -112,6 +112,7 @@ struct EriTileArgs {
   // uslot_kb[i] transposed (-1: that direction has no tile); both directions
   // are counted
   const int32_t *uslot_bk = nullptr, *uslot_kb = nullptr;
+  const double *boys = nullptr;  // [BOYS_N][8] Taylor table of F0 (see common.h)
   const int32_t *tasks;       // [slots] ket tile per slot
   const int32_t *task_bra;    // [slots] bra tile per slot
   int64_t slot0;              // slot index of the panel buffer's first entry

@@ -98,6 +98,32 @@ void build_space(qdcb_ctx *ctx, Space &sp, std::vector<RowSrc> &rows,
   sp.overflow.alloc(ctx, 1);
 }
 
+// Taylor table of the Boys function, tab[8 i + k] = (-1)^k F_k(T_i) / k! at
+// T_i = i / 8: F_7 from its series e^-T sum_j (2T)^j / ((2m+1)(2m+3)...(2m+2j+1)),
+// then the stable downward recursion F_{m-1} = (2 T F_m + e^-T) / (2m - 1),
+// in long double.
+std::vector<double> boys_table() {
+  std::vector<double> tab((size_t)BOYS_N * 8);
+  for (int i = 0; i < BOYS_N; ++i) {
+    const long double T = (long double)i / 8.0L, eT = expl(-T);
+    long double term = 1.0L / 15.0L, sum = term;  // m = 7: first term 1/(2m+1)
+    for (int j = 1; j < 400; ++j) {
+      term *= 2.0L * T / (15.0L + 2.0L * j);
+      sum += term;
+      if (term < 1e-22L * sum) break;
+    }
+    long double F[8];
+    F[7] = eT * sum;
+    for (int m = 7; m >= 1; --m) F[m - 1] = (2.0L * T * F[m] + eT) / (2.0L * m - 1.0L);
+    long double fact = 1.0L;
+    for (int k = 0; k < 8; ++k) {
+      if (k) fact *= k;
+      tab[(size_t)8 * i + k] = (double)((k & 1 ? -F[k] : F[k]) / fact);
+    }
+  }
+  return tab;
+}
+
 }  // namespace
 
 extern "C" {
@@ -313,6 +339,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
         sp->panel.alloc(ctx, (size_t)slots * TILE * TILE);
       }
     }
+    p.boys.upload(ctx, boys_table());
     HIPC(hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking));
     ctx->retain();
     *out = pl.release();
@@ -366,7 +393,7 @@ qdcb_status qdcb_plan_footprint(const qdcb_plan *p, size_t *bytes) {
   return guarded([&] {
     if (!p || !bytes) fail(QDCB_E_INVALID, "NULL argument");
     size_t b = p->C.bytes() + p->G.bytes();
-    for (auto *x : {&p->CLd, &p->CSd, &p->Gd, &p->CallL, &p->CallS, &p->ChatL, &p->ChatS,
+    for (auto *x : {&p->CLd, &p->CSd, &p->Gd, &p->CallL, &p->CallS, &p->ChatL, &p->ChatS, &p->boys,
                     &p->Vfull, &p->W, &p->Gc})
       b += x->bytes();
     for (int K = 0; K < 3; ++K) b += p->AhatK[K].bytes() + p->BhatK[K].bytes();

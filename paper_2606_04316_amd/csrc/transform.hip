@@ -196,6 +196,7 @@ EriTileArgs eri_args(qdcb_plan &p, Space &sp, int64_t slot0, bool count) {
   ea.tau = p.desc.tau;
   ea.panel = sp.panel.p;
   ea.kept = count ? sp.kept.p : nullptr;
+  ea.boys = p.boys.p;
   return ea;
 }
 
