@@ -193,8 +193,11 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
   int eI = 0, eD = 0;  // block-scale exponents of the current task (this wave's half)
   // heads of the two ordered lists, read one task ahead so that the list
   // reads are off the path between a barrier and the next step's loads
+  // (with their panel ranks when the lists are tier sub-lists)
   int nk0 = n0 > 0 ? a.tasks[l0] : INT_MAX;
   int nk1 = n1 > 0 ? a.tasks[l1] : INT_MAX;
+  int nr0 = n0 > 0 && a.rank ? a.rank[l0] : 0;
+  int nr1 = n1 > 0 && a.rank ? a.rank[l1] : 0;
   // advance to the next step; false when the merged lists are exhausted
   auto advance = [&]() -> bool {
     if (++h < TILE / KH) return true;
@@ -204,18 +207,20 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
     has0 = k0 == kt;
     has1 = k1 == kt;
     if (has0) {
-      const int64_t r0 = a.rank ? a.rank[l0 + i0] : i0;
+      const int64_t r0 = a.rank ? __builtin_amdgcn_readfirstlane(nr0) : i0;
       P0 = a.panel + (s0 + r0 - a.slot0) * (TILE * TILE);
       ++i0;
       nk0 = i0 < n0 ? a.tasks[l0 + i0] : INT_MAX;
+      if (a.rank && i0 < n0) nr0 = a.rank[l0 + i0];
     } else {
       P0 = nullptr;
     }
     if (has1) {
-      const int64_t r1 = a.rank ? a.rank[l1 + i1] : i1;
+      const int64_t r1 = a.rank ? __builtin_amdgcn_readfirstlane(nr1) : i1;
       P1 = a.panel + (s1 + r1 - a.slot0) * (TILE * TILE);
       ++i1;
       nk1 = i1 < n1 ? a.tasks[l1 + i1] : INT_MAX;
+      if (a.rank && i1 < n1) nr1 = a.rank[l1 + i1];
     } else {
       P1 = nullptr;
     }
