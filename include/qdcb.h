@@ -209,6 +209,19 @@ qdcb_status qdcb_plan_replay(qdcb_plan *plan, void *hip_stream, qdcb_stats *stat
 qdcb_status qdcb_plan_fetch(const qdcb_plan *plan, int32_t what, void *host_out,
                             size_t bytes);
 
+/* First-half rows V (Eq. firsthalf) of the plan's last transform for the bra
+ * pairs listed in pairs[npairs] (host), in quaternion components, for parity
+ * checks at full size.  Pair indices follow the concatenated list: LL pairs
+ * mu <= nu at nu (nu + 1) / 2 + mu, then SS pairs likewise from nLL, then
+ * (DCG) LS pairs mu * N_S + nu from nLL + nSS.  out (host) is [npairs][W] with
+ * W = (DCG ? 3 : 1) * 4 * npair_mo, npair_mo = n (n + 1) / 2; column
+ * K * 4 * npair_mo + 4 * idx + y holds component y of MO pair idx (p <= q, p
+ * outer) for Pauli component K of a Gaunt row; Coulomb rows fill K = 0 and
+ * leave the rest 0.  When the plan processes its MO-pair columns in chunks, V
+ * holds the last chunk only: columns of the other MO pairs are set to NaN. */
+qdcb_status qdcb_plan_fetch_v(const qdcb_plan *plan, const int64_t *pairs, int64_t npairs,
+                              double *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -77,6 +77,9 @@ def lib():
         L.orc_transform_direct.argtypes = [bp, bp, dp, dp, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_double, ctypes.c_void_p, ctypes.c_int64,
                                            ctypes.c_int, dp, ctypes.POINTER(Stats)]
+        L.orc_first_half_rows.restype = ctypes.c_int
+        L.orc_first_half_rows.argtypes = [bp, bp, dp, dp, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_double, ctypes.c_void_p, ctypes.c_int64, dp]
         L.orc_num_bra_pairs.restype = ctypes.c_int64
         L.orc_num_bra_pairs.argtypes = [bp, bp, ctypes.c_int]
         _lib = L
@@ -199,6 +202,24 @@ def transform_direct(L, S, CL, CS, ham: str = "LL", tau: float = 0.0, rows=None,
     if rc != 0:
         raise ValueError("orc_transform_direct rejected its arguments")
     return G, st.as_dict()
+
+
+def first_half_rows(L, S, CL, CS, ham: str, tau: float, rows) -> np.ndarray:
+    """First-half rows V of the selected bra pairs (indices into the
+    concatenated LL, SS, LS pair list) in quaternion components, columns
+    K * 4 * npair + 4 * idx(p <= q) + y (K blocks only with Gaunt)."""
+    bl, bs, CL, CS = _prep(L, S, CL, CS)
+    sel = np.ascontiguousarray(rows, dtype=np.int64)
+    n = CL.shape[2]
+    npair = n * (n + 1) // 2
+    width = (3 if ham in ("DCG", "GAUNT") else 1) * 4 * npair
+    Vq = np.zeros((sel.shape[0], width))
+    rc = lib().orc_first_half_rows(bl.ref, bs.ref if bs else None, _dp(CL),
+                                   _dp(CS) if CS is not None else None, n, HAMS[ham],
+                                   float(tau), sel.ctypes.data, int(sel.shape[0]), _dp(Vq))
+    if rc != 0:
+        raise ValueError("orc_first_half_rows rejected its arguments")
+    return Vq
 
 
 def num_bra_pairs(L, S, ham: str) -> int:

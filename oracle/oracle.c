@@ -513,9 +513,28 @@ static cplx dens_gaunt(const cplx *cl, const cplx *cs, int m, int K, int ka, int
     return s;
 }
 
+static int direct_impl(const orc_basis *L, const orc_basis *S, const double *CL,
+                       const double *CS, int n, int ham, double tau, const int64_t *rows,
+                       int64_t nrows_sel, int do_second, double *G, orc_stats *st, double *Vq);
+
 int orc_transform_direct(const orc_basis *L, const orc_basis *S, const double *CL,
                          const double *CS, int n, int ham, double tau, const int64_t *rows,
                          int64_t nrows_sel, int do_second, double *G, orc_stats *st)
+{
+    return direct_impl(L, S, CL, CS, n, ham, tau, rows, nrows_sel, do_second, G, st, NULL);
+}
+
+int orc_first_half_rows(const orc_basis *L, const orc_basis *S, const double *CL,
+                        const double *CS, int n, int ham, double tau, const int64_t *rows,
+                        int64_t nrows, double *Vq)
+{
+    if (!rows || nrows <= 0 || !Vq) return -1;
+    return direct_impl(L, S, CL, CS, n, ham, tau, rows, nrows, 0, NULL, NULL, Vq);
+}
+
+static int direct_impl(const orc_basis *L, const orc_basis *S, const double *CL,
+                       const double *CS, int n, int ham, double tau, const int64_t *rows,
+                       int64_t nrows_sel, int do_second, double *G, orc_stats *st, double *Vq)
 {
     int with_S = (ham != 0);
     if (with_S && (!S || !CS)) return -1;
@@ -675,6 +694,35 @@ int orc_transform_direct(const orc_basis *L, const orc_basis *S, const double *C
         free(Dk);
     }
     double t1 = now_s();
+
+    if (Vq) {
+        /* First-half rows in quaternion components: the (r, s) spinor block of
+         * a Coulomb row is Q(V^{rs}) and of a Gaunt row -i Q(V^{K,rs}); columns
+         * (K, r <= s, y) at K * 4 * npair + 4 * idx(r, s) + y, idx counting the
+         * pairs r <= s with r outer. */
+        const int64_t npair = (int64_t)n * (n + 1) / 2, width = (int64_t)nvK * 4 * npair;
+        for (int64_t r = 0; r < nrow; ++r) {
+            const opair B = pl[sel[r]];
+            const cplx *Vr = V + (size_t)r * nvK * m2;
+            double *out = Vq + (size_t)r * width;
+            for (int64_t c = 0; c < width; ++c) out[c] = 0.0;
+            int nK = B.cls == 2 ? 3 : 1;
+            for (int K = 0; K < nK; ++K) {
+                int64_t idx = 0;
+                for (int p = 0; p < n; ++p)
+                    for (int q = p; q < n; ++q, ++idx) {
+                        cplx blk[2][2];
+                        for (int a = 0; a < 2; ++a)
+                            for (int b = 0; b < 2; ++b) {
+                                cplx v = Vr[(size_t)K * m2 + (size_t)(2 * p + a) * m + 2 * q + b];
+                                blk[a][b] = B.cls == 2 ? I * v : v;
+                            }
+                        for (int y = 0; y < 4; ++y)
+                            out[(int64_t)K * 4 * npair + 4 * idx + y] = qproject(y, blk, NULL);
+                    }
+            }
+        }
+    }
 
     if (do_second && G) {
         /* Second half, Sec. 2.4.2: the Pauli components of V are converted to

@@ -106,6 +106,18 @@ int orc_transform_direct(const orc_basis *L, const orc_basis *S, const double *C
                          const double *CS, int n, int ham, double tau, const int64_t *rows,
                          int64_t nrows, int do_second, double *G, orc_stats *st);
 
+/* First-half rows of the direct route for the selected bra pairs (same
+ * indexing as orc_transform_direct's rows), in quaternion components:
+ * Vq[r][K * 4 * npair + 4 * idx(p <= q) + y], npair = n (n + 1) / 2, idx counting
+ * the MO pairs p <= q with p outer, K = 0 only (Coulomb rows) or K = x, y, z
+ * (Gaunt rows); rows are 3 * 4 * npair wide when ham includes Gaunt, else
+ * 4 * npair.  Coulomb: V^{pq}_y = sum_kept (mn|kl) [D~^{pq}_kl]_y with the
+ * symmetrized quaternion density; Gaunt likewise with D^{K,pq}.
+ * Returns 0, or -1 on invalid arguments. */
+int orc_first_half_rows(const orc_basis *L, const orc_basis *S, const double *CL,
+                        const double *CS, int n, int ham, double tau, const int64_t *rows,
+                        int64_t nrows, double *Vq);
+
 /* Number of bra pairs of the concatenated list for this ham. */
 int64_t orc_num_bra_pairs(const orc_basis *L, const orc_basis *S, int ham);
 

@@ -430,4 +430,38 @@ qdcb_status qdcb_plan_fetch(const qdcb_plan *p, int32_t what, void *host_out, si
   });
 }
 
+qdcb_status qdcb_plan_fetch_v(const qdcb_plan *p, const int64_t *pairs, int64_t npairs,
+                              double *out) {
+  return guarded([&] {
+    if (!p || !pairs || !out || npairs < 0) fail(QDCB_E_INVALID, "NULL argument");
+    if (!p->have_last) fail(QDCB_E_INVALID, "no transform yet");
+    DeviceGuard g(p->ctx->device);
+    const int64_t c0 = 4LL * p->v_i0, nc = 4LL * (p->v_i1 - p->v_i0);  // resident columns
+    const int64_t nLL = p->nLL, nSS = p->nSS, nLS = p->gaunt ? (int64_t)p->NL * p->NS : 0;
+    const int64_t wK = 4LL * p->npair_mo, width = (p->gaunt ? 3 : 1) * wK;
+    // sorted row of every pair of the concatenated list
+    std::vector<int64_t> rowC(nLL + nSS, -1), rowG(nLS, -1);
+    for (int64_t r = 0; r < p->C.P; ++r)
+      rowC[p->C.h_key[r] + (p->C.h_cls[r] == 1 ? nLL : 0)] = r;
+    for (int64_t r = 0; r < p->G.P && p->gaunt; ++r) rowG[p->G.h_key[r]] = r;
+    for (int64_t i = 0; i < npairs; ++i) {
+      const int64_t k = pairs[i];
+      if (k < 0 || k >= nLL + nSS + nLS) fail(QDCB_E_INVALID, "pair index out of range");
+      double *o = out + i * width;
+      const bool gaunt_row = k >= nLL + nSS;
+      const int nK = gaunt_row ? 3 : 1;
+      std::fill(o, o + width, 0.0);
+      for (int K = 0; K < nK; ++K) {  // columns outside the resident chunk
+        std::fill(o + K * wK, o + K * wK + c0, std::nan(""));
+        std::fill(o + K * wK + c0 + nc, o + (K + 1) * wK, std::nan(""));
+      }
+      const Space &sp = gaunt_row ? p->G : p->C;
+      const int64_t r = gaunt_row ? rowG[k - nLL - nSS] : rowC[k];
+      for (int K = 0; K < nK; ++K)
+        HIPC(hipMemcpy(o + K * wK + c0, sp.V.p + r * sp.ld + K * sp.ldK, nc * sizeof(double),
+                       hipMemcpyDeviceToHost));
+    }
+  });
+}
+
 }  // extern "C"

@@ -410,6 +410,8 @@ void enqueue(qdcb_plan &p, const double *dCL, const double *dCS, double *dG, boo
   HIPC(hipGetLastError());
   for (int i0 = 0; i0 < p.npair_mo; i0 += p.ci) {
     const int i1 = std::min(p.npair_mo, i0 + p.ci);
+    p.v_i0 = i0;
+    p.v_i1 = i1;
     for (Space *sp : spaces) {
       tm.begin(ST_DENS);
       density(p, *sp, dCL, dCS, 0, i0, i1, s);

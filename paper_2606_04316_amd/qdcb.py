@@ -99,10 +99,11 @@ def lib():
                                          ctypes.POINTER(ctypes.c_size_t)]
         L.qdcb_plan_capture.argtypes = [_P, _P, _P, _P, _P]
         L.qdcb_plan_replay.argtypes = [_P, _P, ctypes.POINTER(Stats)]
+        L.qdcb_plan_fetch_v.argtypes = [_P, _P, ctypes.c_int64, _P]
         for f in ("qdcb_ctx_create", "qdcb_basis_create", "qdcb_basis_schwarz",
                   "qdcb_eri_quartets", "qdcb_plan_create", "qdcb_plan_footprint",
                   "qdcb_transform", "qdcb_plan_fetch", "qdcb_plan_estimate",
-                  "qdcb_plan_capture", "qdcb_plan_replay"):
+                  "qdcb_plan_capture", "qdcb_plan_replay", "qdcb_plan_fetch_v"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -255,6 +256,16 @@ class Plan:
     def fetch(self, what: int, count: int) -> np.ndarray:
         out = np.empty(count)
         _check(lib().qdcb_plan_fetch(self.h, int(what), out.ctypes.data, out.nbytes))
+        return out
+
+    def fetch_v(self, pairs) -> np.ndarray:
+        """First-half rows of the last transform for the given bra pairs
+        (concatenated LL, SS, LS indexing), quaternion components."""
+        idx = np.ascontiguousarray(pairs, dtype=np.int64)
+        npair = self.n * (self.n + 1) // 2
+        out = np.empty((idx.shape[0], (3 if self.ham == "DCG" else 1) * 4 * npair))
+        _check(lib().qdcb_plan_fetch_v(self.h, idx.ctypes.data, int(idx.shape[0]),
+                                       out.ctypes.data))
         return out
 
     def close(self):

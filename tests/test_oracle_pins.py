@@ -352,3 +352,56 @@ def test_gaunt_density_bound_matches_direct_route_screening():
     assert st["tie_band"] == 0
     assert st["kept_gaunt"] == kept
     assert 0 < kept < q.size ** 2
+
+
+@pytest.mark.parametrize("ham", ["DC", "DCG"])
+def test_first_half_rows_reproduce_partial_G(ham):
+    # The quaternion-component first-half rows (the comparison points of the
+    # full-size GPU checks) carried through the quaternion second half written
+    # here from the definitions, G^xy_pqrs = sum_mn [conj(C_mp) C_nq]_x V_mn^{rs}_y
+    # (Coulomb, both orders of an unordered pair) + sum_K sum_LS [D^{K,pq}_mn]_x
+    # V^{K,rs}_mn,y (Gaunt), must equal the direct route's G restricted to the
+    # same bra pairs, which is computed in complex two-spinor arithmetic.
+    s = wl.linear_chain(seed=71, n_atoms=4, spacing=3.0, nl_per_atom=2, ns_per_atom=3, n=3,
+                        tau=1e-9, ham=ham)
+    NL, NS, n = s.L.nfunc, s.S.nfunc, s.n_mo
+    nLL, nSS = NL * (NL + 1) // 2, NS * (NS + 1) // 2
+    P = oracle.num_bra_pairs(s.L, s.S, ham)
+    rows = np.sort(np.random.default_rng(3).choice(P, size=min(P, 25), replace=False))
+    if ham == "DCG":  # make sure some Gaunt rows are in
+        rows = np.unique(np.concatenate([rows, [nLL + nSS, nLL + nSS + 7, P - 1]]))
+    Vq = oracle.first_half_rows(s.L, s.S, s.CL, s.CS, ham, s.tau, rows)
+    Gref, _ = oracle.transform_direct(s.L, s.S, s.CL, s.CS, ham, s.tau, rows=rows)
+    npair = n * (n + 1) // 2
+    iu = [(p, q) for p in range(n) for q in range(p, n)]
+    G = np.zeros((n, n, n, n, 4, 4))
+    units = [np.array([0, 0, 0, 1.0]), np.array([0, 0, 1.0, 0]), np.array([0, 1.0, 0, 0])]
+    for r_i, row in enumerate(rows):
+        if row < nLL + nSS:  # Coulomb pair (canonical index b(b+1)/2 + a)
+            C = s.CL if row < nLL else s.CS
+            k = row if row < nLL else row - nLL
+            b = int((np.sqrt(8 * k + 1) - 1) // 2)
+            a = k - b * (b + 1) // 2
+            orders = [(a, b)] if a == b else [(a, b), (b, a)]
+            for (m, nn) in orders:
+                W = qalg.qmul(qalg.qconj(C[:, m, :])[:, :, None], C[:, nn, :][:, None, :])
+                for c, (r, t) in enumerate(iu):
+                    G[:, :, r, t] += np.einsum("xpq,y->pqxy", W, Vq[r_i, 4 * c:4 * c + 4])
+        else:  # Gaunt pair mu in L, nu in S
+            g = row - nLL - nSS
+            m, nn = g // NS, g % NS
+            for K in range(3):
+                e = units[K][:, None, None]
+                DK = (qalg.qmul(qalg.qmul(qalg.qconj(s.CL[:, m, :])[:, :, None], e),
+                                s.CS[:, nn, :][:, None, :])
+                      + qalg.qmul(qalg.qmul(qalg.qconj(s.CS[:, nn, :])[:, :, None], e),
+                                  s.CL[:, m, :][:, None, :]))
+                for c, (r, t) in enumerate(iu):
+                    v = Vq[r_i, K * 4 * npair + 4 * c:K * 4 * npair + 4 * c + 4]
+                    G[:, :, r, t] += np.einsum("xpq,y->pqxy", DK, v)
+    sel = np.zeros((n, n), bool)
+    for (r, t) in iu:
+        sel[r, t] = True
+    scale = np.abs(Gref).max()
+    assert scale > 0
+    assert np.abs(G[:, :, sel] - Gref[:, :, sel]).max() <= 1e-12 * scale
