@@ -174,11 +174,13 @@ def main_replay(args):
 
     name = args.workload or "cluster24"
     sysm = wl.config(name)
+    print(f"workload {name} ready", file=sys.stderr, flush=True)
     n = sysm.n_mo
     dev = torch.device("cuda:0")
     ctx = qdcb.Context(0)
     L, S = qdcb.Basis(ctx, sysm.L), qdcb.Basis(ctx, sysm.S)
     plan = qdcb.Plan(ctx, L, S, sysm.ham, n, sysm.tau)
+    print("plan ready", file=sys.stderr, flush=True)
     CL = torch.from_numpy(sysm.CL).to(dev)
     CS = torch.from_numpy(sysm.CS).to(dev)
     G = torch.empty((n, n, n, n, 4, 4), dtype=torch.float64, device=dev)
@@ -192,8 +194,10 @@ def main_replay(args):
         CS.copy_(torch.from_numpy(cs))
         _, st = plan.transform(CL, CS, G)
         eager_ms.append(st["ms_total"])
+        print(f"eager transform: {st['ms_total']:.1f} ms", file=sys.stderr, flush=True)
     Geager_last = G.clone()
     plan.capture(CL, CS, G, stream)
+    print("captured", file=sys.stderr, flush=True)
     rep_ms, fallbacks = [], 0
     t0 = time.perf_counter()
     for k, (cl, cs) in enumerate(coefs):

@@ -1,5 +1,6 @@
-// k_dgemm.hip -- batched FP64 MFMA GEMM for the second-half quarter
-// transforms (Sec. 2.4.2).
+// k_dgemm.hip -- FP64 MFMA GEMMs for the second-half quarter transforms
+// (Sec. 2.4.2): the gathered first quarter (k_gather_gemm) and a plain
+// batched GEMM (k_dgemm_batched).
 //
 // v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16] and B[l/16][l%16];
 // accumulator element i of lane l is D[l/16 + 4*i][l%16].
@@ -88,6 +89,126 @@ void launch_dgemm_batched(int transA, int M, int N, int K, double alpha, const d
   dim3 grid((M + GB_M - 1) / GB_M, (N + GB_N - 1) / GB_N, batch);
   hipLaunchKernelGGL(k_dgemm_batched, grid, dim3(256), 0, s, transA, M, N, K, alpha, A, lda,
                      strideA, B, ldb, strideB, beta, C, ldc, strideC);
+}
+
+// ---------------------------------------------------------------------------
+// Gathered GEMM.  Workgroup: 128 slice columns (c) x 128 output columns (j)
+// of one batch, four wavefronts of 64 x 64.  Steps of 16 k rows; each row of
+// the A^T tile (128 consecutive V columns of row rowmap[b, k]) and of the B
+// tile (128 consecutive B columns) is one wavefront instruction of 16-byte
+// direct global->LDS loads, double-buffered so that the loads of step t+1
+// run under step t's MFMAs.  Rows k >= K are zero-filled; lanes past the V
+// row or past J load nothing (they only feed outputs that are not stored).
+constexpr int GG_KH = 16;
+constexpr int GG_LD = 130;  // LDS row stride (doubles): 16-byte rows, padded
+
+typedef __attribute__((address_space(3))) void *gg_lds_ptr;
+
+__device__ __forceinline__ void gg_mfma(const double *A, const double *B, int wr, int wc, int lr,
+                                        int lk, dbl4 (&acc)[4][4]) {
+#pragma unroll
+  for (int kk = 0; kk < GG_KH / 4; ++kk) {
+    const int j = kk * 4 + lk;
+    double av[4], bv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) av[r] = A[j * GG_LD + wr * 64 + r * 16 + lr];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) bv[c] = B[j * GG_LD + wc * 64 + c * 16 + lr];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[r][c] = MFMA_F64(av[r], bv[c], acc[r][c]);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_gather_gemm(GatherGemmArgs a) {
+  __shared__ __attribute__((aligned(16))) double As0[GG_KH * GG_LD], As1[GG_KH * GG_LD];
+  __shared__ __attribute__((aligned(16))) double Bs0[GG_KH * GG_LD], Bs1[GG_KH * GG_LD];
+  const int ct = blockIdx.x, jt = blockIdx.y, b = blockIdx.z;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = w >> 1, wc = w & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int64_t c0 = (int64_t)ct * 128 + 2 * lane;  // this lane's two columns
+  const int j0 = jt * 128 + 2 * lane;
+  const bool c_ok = a.col0 + c0 + 1 < a.ld;
+  const bool j_ok = j0 + 1 < a.J;
+  dbl4 acc[4][4];
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) acc[r][c] = (dbl4){0.0, 0.0, 0.0, 0.0};
+  const int nsteps = (a.K + GG_KH - 1) / GG_KH;
+  // V rows of this wave's k rows, read one step ahead of their loads so that
+  // the only memory waits are the ones at the step barriers
+  int nrow[GG_KH / 4];
+  auto fetch_rows = [&](int t) {
+#pragma unroll
+    for (int q = 0; q < GG_KH / 4; ++q) {
+      const int k = t * GG_KH + w + 4 * q;
+      nrow[q] = k < a.K ? a.rowmap[(int64_t)b * a.sb + (int64_t)k * a.sk] : 0;
+    }
+  };
+  auto issue = [&](int t, double *A, double *B) {
+#pragma unroll
+    for (int q = 0; q < GG_KH / 4; ++q) {
+      const int kk = w + 4 * q, k = t * GG_KH + kk;
+      if (k < a.K) {
+        const int64_t row = __builtin_amdgcn_readfirstlane(nrow[q]);
+        if (c_ok)
+          __builtin_amdgcn_global_load_lds(a.V + row * a.ld + a.col0 + c0,
+                                           (gg_lds_ptr)(A + kk * GG_LD), 16, 0, 0);
+        if (j_ok)
+          __builtin_amdgcn_global_load_lds(a.B + (int64_t)k * a.ldb + j0,
+                                           (gg_lds_ptr)(B + kk * GG_LD), 16, 0, 0);
+      } else {
+        *reinterpret_cast<double2 *>(A + kk * GG_LD + 2 * lane) = make_double2(0.0, 0.0);
+        *reinterpret_cast<double2 *>(B + kk * GG_LD + 2 * lane) = make_double2(0.0, 0.0);
+      }
+    }
+  };
+  auto mfma = [&](const double *A, const double *B) { gg_mfma(A, B, wr, wc, lr, lk, acc); };
+  fetch_rows(0);
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  bool more = nsteps > 0;
+  if (more) issue(0, As0, Bs0);
+  fetch_rows(1);
+  int t = 0;  // step staged in the buffer about to be read
+  while (more) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // this wave's loads of step t done
+    __syncthreads();                     // ... and every wave's; buffer 1 free
+    more = t + 1 < nsteps;
+    if (more) {
+      issue(t + 1, As1, Bs1);
+      fetch_rows(t + 2);
+    }
+    mfma(As0, Bs0);
+    ++t;
+    if (!more) break;
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+    more = t + 1 < nsteps;
+    if (more) {
+      issue(t + 1, As0, Bs0);
+      fetch_rows(t + 2);
+    }
+    mfma(As1, Bs1);
+    ++t;
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t cc = (int64_t)ct * 128 + wr * 64 + r * 16 + lk + 4 * i;
+        const int jj = jt * 128 + wc * 64 + c * 16 + lr;
+        if (cc < a.nc && jj < a.J) a.C[cc * a.ldc_c + (int64_t)b * a.ldc_b + jj] = acc[r][c][i];
+      }
+}
+
+void launch_gather_gemm(const GatherGemmArgs &a, hipStream_t s) {
+  if (a.nc <= 0 || a.J <= 0 || a.nb <= 0) return;
+  dim3 grid((a.nc + 127) / 128, (a.J + 127) / 128, a.nb);
+  hipLaunchKernelGGL(k_gather_gemm, grid, dim3(256), 0, s, a);
 }
 
 }  // namespace qdcb

@@ -7,8 +7,9 @@
 //   G[(x, p)][q]  = sum_(m, z) Chat[(m, z)][(x, p)] W[(m, z)][q]
 // where Chat holds the left-multiplication matrix of a_mp.  Coulomb uses
 // a = conj(C), b = C; the Gaunt chains use a = conj(C^L) e_K, b = C^S and
-// a = conj(C^S) e_K, b = C^L (Eq. GauntInt).  These kernels build Chat, unpack
-// V column slices into dense matrices and scatter the result into G.
+// a = conj(C^S) e_K, b = C^L (Eq. GauntInt).  The first product reads the
+// rows of V directly (k_dgemm.hip, gathered GEMM); these kernels build Chat
+// and scatter the result into G.
 #include "kernels.h"
 
 namespace qdcb {
@@ -48,34 +49,6 @@ void launch_build_coef_mats(int N, int n, const double *C, int unit, double *Cal
   if (tot <= 0) return;
   hipLaunchKernelGGL(k_build_coef_mats, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, N,
                      n, C, unit, Call, Chat);
-}
-
-// LDS transpose: 64 (nu) x 64 (columns) per workgroup, fixed mu.
-__global__ void __launch_bounds__(256) k_unpack(int NA, int NB, const int32_t *rowmap,
-                                                const double *V, int64_t ld, int64_t col0,
-                                                int nc, double *Vfull) {
-  __shared__ double tile[64][65];
-  const int nu0 = blockIdx.x * 64, mu = blockIdx.y, cb = blockIdx.z * 64;
-  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-    int nl = e >> 6, cl = e & 63;
-    int nu = nu0 + nl, c = cb + cl;
-    double v = 0.0;
-    if (nu < NB && c < nc) v = V[(int64_t)rowmap[(int64_t)mu * NB + nu] * ld + col0 + c];
-    tile[nl][cl] = v;
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-    int cl = e >> 6, nl = e & 63;
-    int nu = nu0 + nl, c = cb + cl;
-    if (nu < NB && c < nc) Vfull[((int64_t)c * NA + mu) * NB + nu] = tile[nl][cl];
-  }
-}
-
-void launch_unpack(int NA, int NB, const int32_t *rowmap, const double *V, int64_t ld,
-                   int64_t col0, int nc, double *Vfull, hipStream_t s) {
-  if (NA <= 0 || NB <= 0 || nc <= 0) return;
-  dim3 grid((NB + 63) / 64, NA, (nc + 63) / 64);
-  hipLaunchKernelGGL(k_unpack, grid, dim3(256), 0, s, NA, NB, rowmap, V, ld, col0, nc, Vfull);
 }
 
 // One thread per (MO pair r <= s of the slice, p, q): 16 contiguous outputs.

@@ -158,15 +158,30 @@ void launch_dgemm_batched(int transA, int M, int N, int K, double alpha, const d
                           int64_t strideB, double beta, double *C, int64_t ldc,
                           int64_t strideC, int batch, hipStream_t s);
 
+// Second-half first quarter straight from the first-half rows: for every
+// batch b < nb and slice column c < nc,
+//   C[c * ldc_c + b * ldc_b + j] = sum_{k < K} V[rowmap[b * sb + k * sk] * ld + col0 + c] * B[k * ldb + j]
+// for j < J (the dense V of a column is never formed).  col0, ld and ldb must
+// be multiples of 2 (16-byte rows).
+struct GatherGemmArgs {
+  const double *V;
+  int64_t ld, col0;
+  const int32_t *rowmap;
+  int64_t sb, sk;
+  int nc, K, J, nb;
+  const double *B;
+  int64_t ldb;
+  double *C;
+  int64_t ldc_c, ldc_b;
+};
+void launch_gather_gemm(const GatherGemmArgs &a, hipStream_t s);
+
 // ---- second half (k_second.hip)
 // Call[nu][z*n + q] = C[z][nu][q] and Chat[(mu,z)][(x,p)] = L(a)[x][z] with
 // a = conj(C_mu p) * e (e = 1 for unit < 0, else e_x = k, e_y = j, e_z = i for
 // unit = 0, 1, 2) and L(a) the matrix of left multiplication by a.
 void launch_build_coef_mats(int N, int n, const double *C, int unit, double *Call,
                             double *Chat, hipStream_t s);
-// Vfull[c][mu][nu] = V[rowmap[mu*NB + nu]][col0 + c] for c < nc (mu < NA, nu < NB).
-void launch_unpack(int NA, int NB, const int32_t *rowmap, const double *V, int64_t ld,
-                   int64_t col0, int nc, double *Vfull, hipStream_t s);
 // Scatter Gc[c][(x,p)][q] for MO-pair columns c of [c0, c0+nc) (c = 4 idx + y)
 // into G[p][q][r][s][x][y] and its mirror G[p][q][s][r][x][y] = mirror * s_y * v,
 // s = (+1,-1,-1,-1); accumulate = 1 adds to G instead of storing.

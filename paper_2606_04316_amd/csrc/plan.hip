@@ -126,6 +126,119 @@ std::vector<double> boys_table() {
 
 }  // namespace
 
+namespace qdcb {
+
+double dv_bytes(const qdcb_plan &p, int64_t ci) {
+  const int64_t ldK = round_up(4 * ci, 128);
+  return 16.0 * ((double)p.C.Ppad * ldK + (p.gaunt ? 3.0 * p.G.Ppad * ldK : 0.0));
+}
+
+size_t g_stage_bytes(const qdcb_plan &p) {
+  return sizeof(double) * (size_t)p.n * p.n * p.n * p.n * 16;
+}
+
+// (Re)allocate the sized buffers: D~ and V of the column chunk, the
+// second-half slices and the integral panels.  slotsC, slotsG = 0: the
+// default split (D~ and V within ~45% of the room, the slices ~1/8 of the
+// rest, the panels a quarter of what is left); otherwise panels of exactly
+// that many slots and the largest column chunk that fits beside them.  The
+// G staging buffer of host-pointer transforms is kept out of the room.
+void size_plan(qdcb_plan &p, int64_t slotsC, int64_t slotsG) {
+  qdcb_ctx *ctx = p.ctx;
+  for (Space *sp : {&p.C, &p.G}) {
+    sp->D.free();
+    sp->V.free();
+    sp->panel.free();
+    sp->panel_slots = 0;
+  }
+  p.W.free();
+  p.Gc.free();
+  const size_t g_stage = g_stage_bytes(p);
+  auto room = [&]() -> size_t {
+    size_t r = ctx->room();
+    return r > g_stage ? r - g_stage : 0;
+  };
+  const size_t slot_bytes = sizeof(double) * TILE * TILE;
+  const int64_t wmax = (int64_t)std::max(p.NL, p.NS) * 4 * p.n;
+  const size_t per_col = sizeof(double) * (size_t)(wmax + (int64_t)4 * p.n * p.n);
+  const bool fixed = slotsC > 0;
+  const double panels = fixed ? (double)slot_bytes * (slotsC + slotsG) : 0.0;
+  // --- first-half column chunk
+  int64_t ci = p.npair_mo;
+  const double room0 = (double)room();
+  if (fixed) {
+    // beside the panels, keep ~1/8 of the remainder for the second-half slices
+    const double avail = (room0 - panels) * 0.85;
+    while (ci > 32 && dv_bytes(p, ci) > avail) ci = std::max<int64_t>(32, (ci / 2) / 32 * 32);
+    if (dv_bytes(p, ci) > avail) fail(QDCB_E_NOMEM, "no room for the panels and a column chunk");
+  } else {
+    while (ci > 32 && dv_bytes(p, ci) > 0.45 * room0) ci = std::max<int64_t>(32, (ci / 2) / 32 * 32);
+    if (dv_bytes(p, ci) > 0.6 * room0) fail(QDCB_E_NOMEM, "no room for a 32-MO-pair column chunk");
+  }
+  p.ci = (int)ci;
+  for (Space *sp : {&p.C, &p.G}) {
+    if (sp == &p.G && !p.gaunt) continue;
+    sp->ldK = round_up(4 * ci, 128);
+    sp->ld = sp->nK * sp->ldK;
+    sp->D.alloc(ctx, (size_t)sp->Ppad * sp->ld);
+    HIPC(hipMemset(sp->D.p, 0, sp->D.bytes()));
+    sp->V.alloc(ctx, (size_t)sp->Ppad * sp->ld);
+  }
+  // --- second-half slice: W and G slices
+  {
+    const double avail = fixed ? (double)room() - panels : (double)room() / 8;
+    int64_t sc = avail > 0 ? (int64_t)(avail / per_col) : 0;
+    sc = std::min<int64_t>(sc, 4 * ci);
+    sc = std::min<int64_t>(sc, 65532);
+    sc = sc >= 64 ? sc / 64 * 64 : sc / 4 * 4;  // whole MO pairs (4 columns each)
+    if (sc < 4) fail(QDCB_E_NOMEM, "no room for a second-half slice");
+    p.sc = (int)sc;
+    p.W.alloc(ctx, (size_t)p.sc * wmax);
+    p.Gc.alloc(ctx, (size_t)p.sc * 4 * p.n * p.n);
+  }
+  // --- integral panels
+  const int nsp = p.gaunt ? 2 : 1;
+  for (Space *sp : {&p.C, &p.G}) {
+    if (sp == &p.G && !p.gaunt) continue;
+    int64_t slots;
+    if (fixed) {
+      slots = sp == &p.G ? slotsG : slotsC;
+    } else {
+      slots = (int64_t)(room() / 4 / nsp / slot_bytes);
+      if (sp == &p.G) slots = (int64_t)(room() / 4 / slot_bytes);
+    }
+    slots = std::min<int64_t>(slots, (int64_t)1 << 23);
+    if (slots < sp->ntiles) fail(QDCB_E_NOMEM, "no room for one bra row of integral tiles");
+    sp->panel_slots = slots;
+    sp->panel.alloc(ctx, (size_t)slots * TILE * TILE);
+  }
+}
+
+// Make every kept directed tile of both spaces resident (slack x the kept
+// counts of the current screening) when the budget allows it with a column
+// chunk of at least 32 MO pairs; otherwise keep the current sizing (panel
+// batches).  Returns true when the buffers were reallocated.
+bool ensure_residency(qdcb_plan &p, double slack) {
+  const int64_t needC = std::max<int64_t>((int64_t)(p.C.total * slack) + 1, p.C.ntiles);
+  const int64_t needG = p.gaunt ? std::max<int64_t>((int64_t)(p.G.total * slack) + 1, p.G.ntiles) : 0;
+  if (needC <= p.C.panel_slots && (!p.gaunt || needG <= p.G.panel_slots)) return false;
+  if (needC > ((int64_t)1 << 23) || needG > ((int64_t)1 << 23)) return false;
+  // memory the resizable buffers may use: what they hold now plus the free room
+  size_t held = p.W.bytes() + p.Gc.bytes();
+  for (const Space *sp : {&p.C, &p.G}) held += sp->D.bytes() + sp->V.bytes() + sp->panel.bytes();
+  const size_t g_stage = g_stage_bytes(p);
+  const double room0 = (double)p.ctx->room() + (double)held - (double)g_stage;
+  const double panels = (double)sizeof(double) * TILE * TILE * (needC + needG);
+  const int64_t wmax = (int64_t)std::max(p.NL, p.NS) * 4 * p.n;
+  const double per_col = (double)sizeof(double) * (wmax + 4.0 * p.n * p.n);
+  if (panels + dv_bytes(p, 32) + 64.0 * per_col > 0.85 * room0) return false;
+  HIPC(hipDeviceSynchronize());
+  size_plan(p, needC, needG);
+  return true;
+}
+
+}  // namespace qdcb
+
 extern "C" {
 
 qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basis *S,
@@ -284,61 +397,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
       sp->udtotal.alloc(ctx, 1);
       sp->uoverflow.alloc(ctx, 1);
     }
-    // room left for the sized buffers, keeping space for the G staging buffer
-    // of host-pointer transforms
-    const size_t g_stage = sizeof(double) * (size_t)p.n * p.n * p.n * p.n * 16;
-    auto room = [&]() -> size_t {
-      size_t r = ctx->room();
-      return r > g_stage ? r - g_stage : 0;
-    };
-    // --- first-half column chunk: D~ and V of both spaces within ~45% of the room
-    auto dv_bytes = [&](int64_t ci) {
-      int64_t ldK = round_up(4 * ci, 128);
-      return (double)16 * ((double)p.C.Ppad * ldK + (p.gaunt ? 3.0 * p.G.Ppad * ldK : 0.0));
-    };
-    int64_t ci = p.npair_mo;
-    const double room0 = (double)room();
-    while (ci > 32 && dv_bytes(ci) > 0.45 * room0) ci = std::max<int64_t>(32, (ci / 2) / 32 * 32);
-    if (dv_bytes(ci) > 0.6 * room0) fail(QDCB_E_NOMEM, "no room for a 32-MO-pair column chunk");
-    p.ci = (int)ci;
-    for (Space *sp : {&p.C, &p.G}) {
-      if (sp == &p.G && !p.gaunt) continue;
-      sp->ldK = round_up(4 * ci, 128);
-      sp->ld = sp->nK * sp->ldK;
-      sp->D.alloc(ctx, (size_t)sp->Ppad * sp->ld);
-      HIPC(hipMemset(sp->D.p, 0, sp->D.bytes()));
-      sp->V.alloc(ctx, (size_t)sp->Ppad * sp->ld);
-    }
-    // --- second-half slice: dense V, W and G slices within ~1/8 of the room
-    {
-      int64_t vmax = std::max<int64_t>((int64_t)p.NL * p.NL, (int64_t)p.NS * p.NS);
-      if (p.gaunt) vmax = std::max<int64_t>(vmax, (int64_t)p.NL * p.NS);
-      int64_t wmax = (int64_t)std::max(p.NL, p.NS) * 4 * p.n;
-      size_t per_col = sizeof(double) * (size_t)(vmax + wmax + (int64_t)4 * p.n * p.n);
-      int64_t sc = (int64_t)(room() / 8 / per_col);
-      sc = std::min<int64_t>(sc, 4 * ci);
-      sc = std::min<int64_t>(sc, 65532);
-      sc = sc >= 64 ? sc / 64 * 64 : sc / 4 * 4;  // whole MO pairs (4 columns each)
-      if (sc < 4) fail(QDCB_E_NOMEM, "no room for a second-half slice");
-      p.sc = (int)sc;
-      p.Vfull.alloc(ctx, (size_t)p.sc * vmax);
-      p.W.alloc(ctx, (size_t)p.sc * wmax);
-      p.Gc.alloc(ctx, (size_t)p.sc * 4 * p.n * p.n);
-    }
-    // --- integral panels: a quarter of what is left, split between the spaces
-    {
-      size_t slot_bytes = sizeof(double) * TILE * TILE;
-      int nsp = p.gaunt ? 2 : 1;
-      for (Space *sp : {&p.C, &p.G}) {
-        if (sp == &p.G && !p.gaunt) continue;
-        int64_t slots = (int64_t)(room() / 4 / nsp / slot_bytes);
-        if (sp == &p.G) slots = (int64_t)(room() / 4 / slot_bytes);
-        slots = std::min<int64_t>(slots, (int64_t)1 << 22);
-        if (slots < sp->ntiles) fail(QDCB_E_NOMEM, "no room for one bra row of integral tiles");
-        sp->panel_slots = slots;
-        sp->panel.alloc(ctx, (size_t)slots * TILE * TILE);
-      }
-    }
+    size_plan(p, 0, 0);
     p.boys.upload(ctx, boys_table());
     HIPC(hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking));
     ctx->retain();
@@ -378,9 +437,7 @@ qdcb_status qdcb_plan_estimate(const qdcb_basis *L, const qdcb_basis *S,
     b += 16.0 * (PC * ldK + 3.0 * PG * ldK);              // D~ and V, all columns
     b += 20.0 * (ntC * ntC + ntG * ntG);                  // task lists, unique pairs, slot map
     if (desc->prec == QDCB_PREC_MIXED) b += 8.0 * (ntC * ntC + ntG * ntG);  // tier sub-lists
-    double vmax = std::max(NL * NL, NS * NS);
-    if (gaunt) vmax = std::max(vmax, NL * NS);
-    b += 8.0 * 256 * (vmax + std::max(NL, NS) * 4 * n + 4 * n * n);  // second-half slice
+    b += 8.0 * 256 * (std::max(NL, NS) * 4 * n + 4 * n * n);  // second-half slice
     b += 8.0 * 20.0 * (NL + NS) * n * 4;                  // coefficient matrices
     auto slots = [](double nt) { return std::min(nt * nt, std::max(nt, 65536.0)); };
     b += 8.0 * TILE * TILE * (slots(ntC) + (gaunt ? slots(ntG) : 0.0));  // integral panels
@@ -394,7 +451,7 @@ qdcb_status qdcb_plan_footprint(const qdcb_plan *p, size_t *bytes) {
     if (!p || !bytes) fail(QDCB_E_INVALID, "NULL argument");
     size_t b = p->C.bytes() + p->G.bytes();
     for (auto *x : {&p->CLd, &p->CSd, &p->Gd, &p->CallL, &p->CallS, &p->ChatL, &p->ChatS, &p->boys,
-                    &p->Vfull, &p->W, &p->Gc})
+                    &p->W, &p->Gc})
       b += x->bytes();
     for (int K = 0; K < 3; ++K) b += p->AhatK[K].bytes() + p->BhatK[K].bytes();
     b += p->rs.bytes() + p->rowmapL.bytes() + p->rowmapS.bytes() + p->rowmapLS.bytes();

@@ -31,6 +31,7 @@ struct StageTimer {
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
   hipEvent_t open = nullptr;
   int open_stage = -1;
+  bool probe_only = false;  // densities and screening only (sizing before a capture)
   StageTimer(hipStream_t st, bool enabled) : s(st), on(enabled) {}
   ~StageTimer() {
     for (auto e : sync_events) (void)hipEventDestroy(e);
@@ -151,8 +152,11 @@ void screen(qdcb_plan &p, Space &sp, bool captured, hipStream_t s) {
     }
   }
   sp.sym = false;
-  // directed slots are int32 in the slot map: panel_slots < 2^31 always holds
-  if (!want_sym || (!captured && sp.total > sp.panel_slots)) return;
+  // directed slots are int32 in the slot map: panel_slots < 2^31 always holds.
+  // Eager: the unique lists are built whenever the plan allows them; they are
+  // used if every directed tile ends up resident (decided after screening).
+  if (!want_sym) return;
+  if (!captured && sp.total >= ((int64_t)1 << 31)) return;
   // a captured transform whose directed tiles outgrow the panel writes slots
   // beyond it into dmap; its integral and contraction kernels then do nothing
   launch_screen_fill_map(sp.ntiles, sp.Qmax.p, sp.Bmax.p, p.desc.tau, sp.slot_base.p,
@@ -180,7 +184,7 @@ void screen(qdcb_plan &p, Space &sp, bool captured, hipStream_t s) {
   launch_screen_fill_u(sp.ntiles, sp.Qmax.p, sp.Bmax.p, p.desc.tau, sp.ubase.p, sp.dmap.p,
                        sp.utask_k.p, sp.utask_b.p, sp.uslot_bk.p, sp.uslot_kb.p, s);
   HIPC(hipGetLastError());
-  sp.sym = true;
+  sp.sym = captured || sp.total <= sp.panel_slots;
 }
 
 EriTileArgs eri_args(qdcb_plan &p, Space &sp, int64_t slot0, bool count) {
@@ -346,6 +350,30 @@ void first_half(qdcb_plan &p, Space &sp, bool make_tiles, bool count, bool captu
   }
 }
 
+// First quarter of the second half, read straight from V: W[c][b][zq] =
+// sum_k V[rowmap[b * sb + k * sk]][col0 + c] Call[k][zq] for batches b < nb.
+void gather_quarter(const qdcb_plan &p, const Space &sp, const int32_t *rowmap, int64_t sb,
+                    int64_t sk, int nb, int K, const double *Call, int64_t col0, int nc,
+                    hipStream_t s) {
+  GatherGemmArgs g;
+  g.V = sp.V.p;
+  g.ld = sp.ld;
+  g.col0 = col0;
+  g.rowmap = rowmap;
+  g.sb = sb;
+  g.sk = sk;
+  g.nc = nc;
+  g.K = K;
+  g.J = 4 * p.n;
+  g.nb = nb;
+  g.B = Call;
+  g.ldb = 4 * p.n;
+  g.C = p.W.p;
+  g.ldc_c = (int64_t)nb * 4 * p.n;
+  g.ldc_b = 4 * p.n;
+  launch_gather_gemm(g, s);
+}
+
 void second_half(qdcb_plan &p, int i0, int i1, double *dG, hipStream_t s) {
   const int n = p.n;
   const int64_t cend = 4LL * i1;
@@ -354,11 +382,10 @@ void second_half(qdcb_plan &p, int i0, int i1, double *dG, hipStream_t s) {
     const int64_t lc0 = c0 - 4LL * i0;
     for (int cls = 0; cls < (p.NS ? 2 : 1); ++cls) {
       const int N = cls ? p.NS : p.NL;
-      launch_unpack(N, N, cls ? p.rowmapS.p : p.rowmapL.p, p.C.V.p, p.C.ld, lc0, nc, p.Vfull.p,
-                    s);
-      launch_dgemm_batched(0, N, 4 * n, N, 1.0, p.Vfull.p, N, (int64_t)N * N,
-                           cls ? p.CallS.p : p.CallL.p, 4 * n, 0, 0.0, p.W.p, 4 * n,
-                           (int64_t)N * 4 * n, nc, s);
+      // W_c = V_c C (V_c the symmetric N x N first-half matrix of column c)
+      gather_quarter(p, p.C, cls ? p.rowmapS.p : p.rowmapL.p, N, 1, N, N,
+                     cls ? p.CallS.p : p.CallL.p, lc0, nc, s);
+      // G_c (+)= Chat^T W_c
       launch_dgemm_batched(1, 4 * n, n, 4 * N, 1.0, cls ? p.ChatS.p : p.ChatL.p, 4 * n, 0, p.W.p,
                            n, (int64_t)N * 4 * n, cls ? 1.0 : 0.0, p.Gc.p, n, (int64_t)4 * n * n,
                            nc, s);
@@ -367,16 +394,14 @@ void second_half(qdcb_plan &p, int i0, int i1, double *dG, hipStream_t s) {
     if (p.gaunt) {
       const int NL = p.NL, NS = p.NS;
       for (int K = 0; K < 3; ++K) {
-        launch_unpack(NL, NS, p.rowmapLS.p, p.G.V.p, p.G.ld, K * p.G.ldK + lc0, nc, p.Vfull.p, s);
-        // conj(C^L) e_K (V C^S)
-        launch_dgemm_batched(0, NL, 4 * n, NS, 1.0, p.Vfull.p, NS, (int64_t)NL * NS, p.CallS.p,
-                             4 * n, 0, 0.0, p.W.p, 4 * n, (int64_t)NL * 4 * n, nc, s);
+        const int64_t col0 = K * p.G.ldK + lc0;
+        // conj(C^L) e_K (V C^S): batches mu in L, sum over nu in S
+        gather_quarter(p, p.G, p.rowmapLS.p, NS, 1, NL, NS, p.CallS.p, col0, nc, s);
         launch_dgemm_batched(1, 4 * n, n, 4 * NL, 1.0, p.AhatK[K].p, 4 * n, 0, p.W.p, n,
                              (int64_t)NL * 4 * n, K ? 1.0 : 0.0, p.Gc.p, n, (int64_t)4 * n * n,
                              nc, s);
-        // conj(C^S) e_K (V^T C^L)
-        launch_dgemm_batched(1, NS, 4 * n, NL, 1.0, p.Vfull.p, NS, (int64_t)NL * NS, p.CallL.p,
-                             4 * n, 0, 0.0, p.W.p, 4 * n, (int64_t)NS * 4 * n, nc, s);
+        // conj(C^S) e_K (V^T C^L): batches nu in S, sum over mu in L
+        gather_quarter(p, p.G, p.rowmapLS.p, 1, NS, NS, NL, p.CallL.p, col0, nc, s);
         launch_dgemm_batched(1, 4 * n, n, 4 * NS, 1.0, p.BhatK[K].p, 4 * n, 0, p.W.p, n,
                              (int64_t)NS * 4 * n, 1.0, p.Gc.p, n, (int64_t)4 * n * n, nc, s);
       }
@@ -400,6 +425,12 @@ void enqueue(qdcb_plan &p, const double *dCL, const double *dCS, double *dG, boo
     screen(p, *sp, captured, s);
     tm.end();
   }
+  if (!captured && !tm.probe_only && ensure_residency(p, 1.0)) {
+    // the panels now hold every kept tile: the unique path applies
+    for (Space *sp : spaces)
+      sp->sym = !(p.desc.flags & QDCB_PLAN_DIRECTED_TILES) && sp->total <= sp->panel_slots;
+  }
+  if (tm.probe_only) return;
   launch_build_coef_mats(p.NL, p.n, dCL, -1, p.CallL.p, p.ChatL.p, s);
   if (p.NS) launch_build_coef_mats(p.NS, p.n, dCS, -1, p.CallS.p, p.ChatS.p, s);
   if (p.gaunt)
@@ -566,6 +597,15 @@ qdcb_status qdcb_plan_capture(qdcb_plan *plan, const double *CL, const double *C
     if (p.graph) {
       (void)hipGraphDestroy(p.graph);
       p.graph = nullptr;
+    }
+    // size the panels for the capture-time kept tiles (with 25% slack for
+    // re-transforms whose screening keeps more), so that replays stay resident
+    {
+      StageTimer probe(s, false);
+      probe.probe_only = true;
+      enqueue(p, CL, CS, G, false, probe, s);
+      HIPC(hipStreamSynchronize(s));
+      (void)ensure_residency(p, 1.25);
     }
     StageTimer tm(s, false);
     HIPC(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
