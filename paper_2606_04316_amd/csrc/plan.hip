@@ -227,7 +227,12 @@ bool ensure_residency(qdcb_plan &p, double slack) {
   size_t held = p.W.bytes() + p.Gc.bytes();
   for (const Space *sp : {&p.C, &p.G}) held += sp->D.bytes() + sp->V.bytes() + sp->panel.bytes();
   const size_t g_stage = g_stage_bytes(p);
-  const double room0 = (double)p.ctx->room() + (double)held - (double)g_stage;
+  // within the context budget and within what the device has free now (other
+  // allocations of the process, such as the caller's G, count against it)
+  size_t fr = 0, tot = 0;
+  HIPC(hipMemGetInfo(&fr, &tot));
+  const double room0 = std::min((double)p.ctx->room(), 0.95 * (double)fr) + (double)held -
+                       (double)g_stage;
   const double panels = (double)sizeof(double) * TILE * TILE * (needC + needG);
   const int64_t wmax = (int64_t)std::max(p.NL, p.NS) * 4 * p.n;
   const double per_col = (double)sizeof(double) * (wmax + 4.0 * p.n * p.n);
