@@ -238,7 +238,15 @@ bool ensure_residency(qdcb_plan &p, double slack) {
   const double per_col = (double)sizeof(double) * (wmax + 4.0 * p.n * p.n);
   if (panels + dv_bytes(p, 32) + 64.0 * per_col > 0.85 * room0) return false;
   HIPC(hipDeviceSynchronize());
-  size_plan(p, needC, needG);
+  try {
+    size_plan(p, needC, needG);
+  } catch (const Fail &) {
+    // the device could not hold the resident sizing after all: return to the
+    // default sizing (panel batches) so that the plan stays usable
+    (void)hipGetLastError();
+    size_plan(p, 0, 0);
+    return false;
+  }
   return true;
 }
 
