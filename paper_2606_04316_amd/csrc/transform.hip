@@ -425,8 +425,10 @@ void enqueue(qdcb_plan &p, const double *dCL, const double *dCS, double *dG, boo
     screen(p, *sp, captured, s);
     tm.end();
   }
-  if (!captured && !tm.probe_only && ensure_residency(p, 1.0)) {
-    // the panels now hold every kept tile: the unique path applies
+  if (!captured && !tm.probe_only) {
+    (void)ensure_residency(p, 1.0);
+    // the panels may have been resized: the unique path applies when every
+    // directed tile is resident (its lists exist whenever that can hold)
     for (Space *sp : spaces)
       sp->sym = !(p.desc.flags & QDCB_PLAN_DIRECTED_TILES) && sp->total <= sp->panel_slots;
   }
