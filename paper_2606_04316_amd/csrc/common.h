@@ -58,7 +58,11 @@ __device__ __forceinline__ double coulomb_kernel(double ip, double px, double py
 // as coulomb_kernel, without the range branches of erf.
 constexpr int BOYS_N = 289;
 constexpr double BOYS_TMAX = 36.0;
+// LDS copies of the table pad each row to BOYS_LD doubles (80 bytes: rows
+// stay 16-byte aligned and rows i, i' share banks only when i = i' mod 16)
+constexpr int BOYS_LD = 10;
 
+template <int LD = 8>
 __device__ __forceinline__ double coulomb_kernel_tab(const double *tab, double ip, double px,
                                                      double py, double pz, double iq, double qx,
                                                      double qy, double qz) {
@@ -70,7 +74,7 @@ __device__ __forceinline__ double coulomb_kernel_tab(const double *tab, double i
   if (T < BOYS_TMAX) {
     const int i = (int)rint(T * 8.0);
     const double d = T - 0.125 * i;
-    const double *c = tab + 8 * i;
+    const double *c = tab + LD * i;
     double f = c[7];
 #pragma unroll
     for (int k = 6; k >= 0; --k) f = fma(f, d, c[k]);
