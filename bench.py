@@ -50,6 +50,11 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=96)
     ap.add_argument("--requests", type=int, default=48)
     ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--tune", default="auto", choices=["auto", "default"],
+                    help="transform / replay: pick the plan's launch choices with the "
+                         "autotuner before the untimed warm-up (auto), or keep the defaults")
+    ap.add_argument("--tune-cache", default=None,
+                    help="tuning cache file (JSON lines) for --tune auto")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before the transform, run one elementwise copy kernel of this many "
                          "MiB (read and write), the reference for HBM byte counters")
@@ -72,6 +77,20 @@ def cpu_baseline(sysm, n_rows, n):
                        f"drawn with seed 0, {t_sample:.2f} s, scaled by {P}/{len(rows)} to "
                        f"the whole transform; density set-up and the second half "
                        f"(a few percent in the paper) not included")}
+
+
+def autotune(args, plan, CL, CS, G):
+    """Run the autotuner (untimed, before the warm-up) unless --tune default."""
+    if args.tune != "auto":
+        return {"chosen": plan.tune, "autotuned": False}
+    t0 = time.perf_counter()
+    rep = plan.autotune(CL, CS, G, cache=args.tune_cache)
+    rep["autotuned"] = True
+    rep["wall_s"] = time.perf_counter() - t0
+    print(f"autotune: {rep['chosen']} (ERI ms {rep['ms_eri']}, first half ms "
+          f"{rep['ms_first_half']}, second half ms {rep['ms_second_half']}, "
+          f"{rep['wall_s']:.1f} s)", file=sys.stderr, flush=True)
+    return rep
 
 
 def main():
@@ -114,6 +133,7 @@ def main_transform(args):
         print(f"copy calibration: {src.numel() * 8} bytes read and written", file=sys.stderr,
               flush=True)
         del src, dst
+    tune = autotune(args, plan, CL, CS, G)
     for i in range(args.warmup):
         plan.transform(CL, CS, G)
         print(f"warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
@@ -153,6 +173,7 @@ def main_transform(args):
         "spinor_integrals_per_s": (2 * n) ** 4 * args.steps / elapsed,
         "stages_ms": {k: st0[k] for k in ("ms_density", "ms_screen", "ms_eri", "ms_first_half",
                                           "ms_second_half", "ms_total")},
+        "tune": tune,
         "kept_fraction": sum(st0["kept"]) / max(1, sum(st0["total"])),
         "tile_fill": st0["flops_first_half"] / max(1.0, st0["flops_mfma"]),
         "roofline": {"kernel": "k_first_half", "bound": "mfma", "achieved": achieved,
@@ -187,6 +208,7 @@ def main_replay(args):
     L, S = qdcb.Basis(ctx, sysm.L), qdcb.Basis(ctx, sysm.S)
     plan = qdcb.Plan(ctx, L, S, sysm.ham, n, sysm.tau)
     print("plan ready", file=sys.stderr, flush=True)
+    tune = autotune(args, plan, CL, CS, G)
     stream = torch.cuda.Stream()
     nrep = max(1, args.steps)
     coefs = [(sysm.CL, sysm.CS)] + [wl.perturbed_coefficients(sysm, k) for k in range(1, nrep)]
@@ -218,7 +240,7 @@ def main_replay(args):
         "value": sum(rep_ms) / len(rep_ms), "unit": "ms per re-transform",
         "higher_is_better": False, "replays": nrep, "fallbacks": fallbacks,
         "eager_ms": eager_ms, "replay_ms": rep_ms, "wall_s": wall,
-        "last_replay_equals_eager": same, "dtype": "f64", "data": "synthetic",
+        "last_replay_equals_eager": same, "tune": tune, "dtype": "f64", "data": "synthetic",
         "config": {"workload": sysm.name, "n_atoms": int(sysm.atoms.shape[0]),
                    "N_L": sysm.L.nfunc, "N_S": sysm.S.nfunc, "n_mo": n, "ham": sysm.ham,
                    "tau": sysm.tau}}), flush=True)

@@ -222,6 +222,73 @@ qdcb_status qdcb_plan_fetch(const qdcb_plan *plan, int32_t what, void *host_out,
 qdcb_status qdcb_plan_fetch_v(const qdcb_plan *plan, const int64_t *pairs, int64_t npairs,
                               double *out);
 
+/* Launch choices of a plan: tile shapes and schedules that change how fast a
+ * transform runs, not what it computes.  Integral tiles and first-half rows
+ * are bitwise the same under every choice; the second-quarter tile changes
+ * the summation order of that GEMM only (results agree to rounding).
+ *   eri_sched  0: one workgroup per unique integral tile, in list order;
+ *              1: a persistent integral launch (two workgroups per compute
+ *                 unit) that takes the unique tiles from a device queue in
+ *                 order of decreasing primitive-quartet count (longest first,
+ *                 for bases of uneven contraction depth).  Applies when the
+ *                 transform generates unique tiles (see QDCB_PLAN_DIRECTED_TILES).
+ *   fh_order   0: XCD-aware workgroup order of the first-half contraction
+ *                 (each XCD's L2 shares integral tiles and density rows);
+ *              1: plain order, bra-tile pairs fastest.
+ *   sq_tile    64 or 128: edge of the output tiles of the second half's second
+ *              quarter (G_c = conj(C)^T W_c); 128 requires an even n_mo.
+ * A new plan starts from eri_sched 0, fh_order 0 and sq_tile 128 when n_mo is
+ * even and at least 128, else 64. */
+typedef struct {
+    int32_t eri_sched;
+    int32_t fh_order;
+    int32_t sq_tile;
+    int32_t reserved;  /* 0 */
+} qdcb_tune;
+
+/* Set or read the launch choices.  QDCB_E_INVALID for a value outside the
+ * lists above (sq_tile 128 with an odd n_mo included). */
+qdcb_status qdcb_plan_set_tune(qdcb_plan *plan, const qdcb_tune *tune);
+qdcb_status qdcb_plan_get_tune(const qdcb_plan *plan, qdcb_tune *tune);
+
+/* Shape key of a plan for the tuning cache: the Hamiltonian, precision,
+ * n_mo, basis sizes, largest contraction depths, tau, tile counts and the
+ * device's compute-unit count, as one line of text (no quotes or newlines).
+ * QDCB_E_INVALID when len is too small (256 bytes always suffice). */
+qdcb_status qdcb_plan_tune_key(const qdcb_plan *plan, char *buf, size_t len);
+
+/* Tuning cache: a text file of JSON lines
+ *   {"key": "<shape key>", "eri_sched": E, "fh_order": F, "sq_tile": T}
+ * Lookup takes the last line with the given key (*found = 0 when none, also
+ * when the file does not exist); store appends a line.  Host file access only:
+ * neither needs a device. */
+qdcb_status qdcb_tune_cache_lookup(const char *path, const char *key, qdcb_tune *tune,
+                                   int32_t *found);
+qdcb_status qdcb_tune_cache_store(const char *path, const char *key, const qdcb_tune *tune);
+
+typedef struct {
+    qdcb_tune chosen;       /* also set on the plan */
+    int32_t from_cache;     /* 1: taken from the cache, nothing timed */
+    int32_t trials;         /* timed transforms (the warm-up excluded) */
+    double ms_eri[2];       /* best integral-tile time per eri_sched value (NaN: untimed) */
+    double ms_first_half[2];/* best first-half time per fh_order value */
+    double ms_second_half[2];/* best second-half time per sq_tile (64, 128) */
+} qdcb_tune_report;
+
+/* Autotuner.  Unless the cache holds the plan's key, runs one warm-up and four
+ * timed transforms of the given coefficients that alternate between the two
+ * values of every choice, each limited to the first MO-pair column chunk (the
+ * integral tiles are generated in full, the contractions cover that chunk),
+ * times each stage with HIP events on hip_stream, and keeps per choice the
+ * value of the faster stage (the first value unless the other is faster by
+ * more than 1%).  Arguments as for qdcb_transform; G is used as scratch and
+ * its contents are unspecified afterwards.  cache_path may be NULL, in which
+ * case the environment variable QDCB_TUNE_CACHE names the cache file if set;
+ * with a cache file the result is appended to it.  report may be NULL. */
+qdcb_status qdcb_plan_autotune(qdcb_plan *plan, const double *CL, const double *CS, double *G,
+                               uint32_t flags, void *hip_stream, const char *cache_path,
+                               qdcb_tune_report *report);
+
 #ifdef __cplusplus
 }
 #endif

@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(256) k_gather_gemm(GatherGemmArgs a) {
 #pragma unroll
     for (int q = 0; q < GG_KH / 4; ++q) {
       const int k = t * GG_KH + w + 4 * q;
-      nrow[q] = k < a.K ? a.rowmap[(int64_t)b * a.sb + (int64_t)k * a.sk] : 0;
+      nrow[q] = k >= a.K ? 0 : a.rowmap ? a.rowmap[(int64_t)b * a.sb + (int64_t)k * a.sk] : k;
     }
   };
   auto issue = [&](int t, double *A, double *B) {
@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(256) k_gather_gemm(GatherGemmArgs a) {
           __builtin_amdgcn_global_load_lds(a.V + row * a.ld + a.col0 + c0,
                                            (gg_lds_ptr)(A + kk * GG_LD), 16, 0, 0);
         if (j_ok)
-          __builtin_amdgcn_global_load_lds(a.B + (int64_t)k * a.ldb + j0,
+          __builtin_amdgcn_global_load_lds(a.B + (int64_t)b * a.sbB + (int64_t)k * a.ldb + j0,
                                            (gg_lds_ptr)(B + kk * GG_LD), 16, 0, 0);
       } else {
         *reinterpret_cast<double2 *>(A + kk * GG_LD + 2 * lane) = make_double2(0.0, 0.0);
@@ -182,16 +182,17 @@ __global__ void __launch_bounds__(256) k_gather_gemm(GatherGemmArgs a) {
     }
     mfma(As0, Bs0);
     ++t;
-    if (!more) break;
-    __builtin_amdgcn_s_waitcnt(0x0F70);
-    __syncthreads();
-    more = t + 1 < nsteps;
     if (more) {
-      issue(t + 1, As0, Bs0);
-      fetch_rows(t + 2);
+      __builtin_amdgcn_s_waitcnt(0x0F70);
+      __syncthreads();
+      more = t + 1 < nsteps;
+      if (more) {
+        issue(t + 1, As0, Bs0);
+        fetch_rows(t + 2);
+      }
+      mfma(As1, Bs1);
+      ++t;
     }
-    mfma(As1, Bs1);
-    ++t;
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r)
@@ -201,7 +202,10 @@ __global__ void __launch_bounds__(256) k_gather_gemm(GatherGemmArgs a) {
       for (int i = 0; i < 4; ++i) {
         const int64_t cc = (int64_t)ct * 128 + wr * 64 + r * 16 + lk + 4 * i;
         const int jj = jt * 128 + wc * 64 + c * 16 + lr;
-        if (cc < a.nc && jj < a.J) a.C[cc * a.ldc_c + (int64_t)b * a.ldc_b + jj] = acc[r][c][i];
+        if (cc < a.nc && jj < a.J) {
+          double *o = a.C + cc * a.ldc_c + (int64_t)b * a.ldc_b + jj;
+          *o = a.accumulate ? *o + acc[r][c][i] : acc[r][c][i];
+        }
       }
 }
 

@@ -2,7 +2,7 @@
 //
 // For every kept (bra tile, ket tile) a 64 x 64 block of contracted s-type
 // ERIs (mn|kl) is generated from the primitive-pair data (Gaussian product
-// theorem, Boys F0 in erf form) and stored as panel[slot][ket j][bra m].  Each
+// theorem, Boys F0 from a Taylor table) and stored as panel[slot][ket j][bra m].  Each
 // element is masked individually by the directed density-weighted Schwarz
 // predicate of Eq. (SchwarzDen): it is computed only when
 // (Q_mn * Q_kl) * Dmax_kl >= tau and is 0 otherwise, which is exactly the skip
@@ -16,12 +16,19 @@
 // The Boys function comes from a Taylor table staged in LDS (no range branches
 // to diverge across lanes; see common.h).
 //
-// Work layout: 8 wavefronts x 8 ket rows each; lane = bra row.  The primitive
-// pairs of the 64 bra rows are staged in LDS once per workgroup when no row has
-// more than ERI_LDS_ROWPRIMS of them, primitive-major ([t][row]) so that the
-// lanes of a wavefront read consecutive words; the ket pair of a wavefront is uniform
+// Work layout: 8 wavefronts x 8 ket rows each; lane = bra row.  The first
+// ERI_LDS_ROWPRIMS primitive pairs of each of the 64 bra rows are staged in LDS
+// once per tile, primitive-major ([t][row]) so that the lanes of a wavefront
+// read consecutive words; deeper rows read the rest from global memory.  The
+// ket pair of a wavefront is uniform
 // across its lanes, so its primitive data comes through scalar loads.  Stores
 // are one 512-byte row of 64 bra values per ket row (coalesced).
+//
+// Schedules: one workgroup per tile in list order (k_eri_tiles), or a
+// persistent grid of a few workgroups per compute unit that pull tiles from a
+// device queue ordered by decreasing primitive-quartet count
+// (k_eri_tiles_queue, longest first, so that tiles of uneven contraction depth
+// do not leave a long tail).
 #include "kernels.h"
 
 namespace qdcb {
@@ -31,29 +38,31 @@ constexpr int ERI_LDS_PRIMS = ERI_LDS_ROWPRIMS * 64;  // 55 KB of bra primitive 
 constexpr int ERI_WAVES = 8;         // wavefronts per tile, TILE / ERI_WAVES ket rows each
 constexpr int ERI_THREADS = 64 * ERI_WAVES;
 
+// LDS of an integral workgroup: the first ERI_LDS_ROWPRIMS primitive pairs of
+// each bra row, primitive-major ([t][row]), the Boys table, and the largest
+// primitive count of the current tile's bra rows
+struct EriLds {
+  double sip[ERI_LDS_PRIMS], sx[ERI_LDS_PRIMS], sy[ERI_LDS_PRIMS], sz[ERI_LDS_PRIMS],
+      se[ERI_LDS_PRIMS];
+  __attribute__((aligned(16))) double tab[BOYS_N * BOYS_LD];
+  int maxcnt;
+};
+
 // out: directed tile (bt <- kt) stored [ket j][bra lane], or NULL; outT (unique
 // mode): directed tile (kt <- bt), whose ket rows are bt's, stored [lane][j], or NULL.
-template <bool LDS>
-__device__ __forceinline__ void eri_tile_body(const EriTileArgs &a, const double *sip,
-                                              const double *sx, const double *sy,
-                                              const double *sz, const double *se,
-                                              const double *tab, int kt, int bt,
-                                              int lane, int w, double *out, double *outT,
-                                              long long kept[4]) {
+__device__ __forceinline__ void eri_tile_body(const EriTileArgs &a, const EriLds &L, int kt,
+                                              int bt, int lane, int w, double *out,
+                                              double *outT, long long kept[4]) {
   const int64_t brow = (int64_t)bt * TILE + lane;
   const double qb = a.Q[brow];
   const double db = a.Dmax[brow];
   const int cb = a.cls[brow];
-  // this lane's bra primitives: LDS [t][lane] (t < count), or global [first + t]
+  // this lane's bra primitives: t < nl from LDS [t][lane], the rest (rows of
+  // deep contractions) from global memory [first + t]; the sum runs over t in
+  // order either way
   const int64_t bfirst = a.row_first[brow];
   const int bcount = (int)(a.row_first[brow + 1] - bfirst);
-  const int64_t bbase = LDS ? lane : bfirst;
-  const int64_t bstride = LDS ? TILE : 1;
-  const double *bip = LDS ? sip : a.pp.ip;
-  const double *bx = LDS ? sx : a.pp.x;
-  const double *by = LDS ? sy : a.pp.y;
-  const double *bz = LDS ? sz : a.pp.z;
-  const double *be = LDS ? se : a.pp.e;
+  const int nl = min(bcount, ERI_LDS_ROWPRIMS);
   // the ket row data of the next row and the ket primitive data of the next
   // primitive are read one iteration ahead (their loads overlap the quartets)
   int64_t krow = (int64_t)kt * TILE + w;
@@ -95,9 +104,15 @@ __device__ __forceinline__ void eri_tile_body(const EriTileArgs &a, const double
           pe = a.pp.e[k + 1];
         }
         double s = 0.0;
-        for (int t = 0; t < bcount; ++t) {
-          const int64_t b = bbase + t * bstride;
-          s += be[b] * coulomb_kernel_tab<BOYS_LD>(tab, bip[b], bx[b], by[b], bz[b], iq, qx, qy, qz);
+        for (int t = 0; t < nl; ++t) {
+          const int b = t * TILE + lane;
+          s += L.se[b] * coulomb_kernel_tab<BOYS_LD>(L.tab, L.sip[b], L.sx[b], L.sy[b], L.sz[b],
+                                                     iq, qx, qy, qz);
+        }
+        for (int t = nl; t < bcount; ++t) {
+          const int64_t b = bfirst + t;
+          s += a.pp.e[b] * coulomb_kernel_tab<BOYS_LD>(L.tab, a.pp.ip[b], a.pp.x[b], a.pp.y[b],
+                                                       a.pp.z[b], iq, qx, qy, qz);
         }
         v += ek * s;
       }
@@ -112,14 +127,16 @@ __device__ __forceinline__ void eri_tile_body(const EriTileArgs &a, const double
   }
 }
 
-__global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles(EriTileArgs a) {
-  __shared__ double sip[ERI_LDS_PRIMS], sx[ERI_LDS_PRIMS], sy[ERI_LDS_PRIMS],
-      sz[ERI_LDS_PRIMS], se[ERI_LDS_PRIMS];
-  __shared__ __attribute__((aligned(16))) double tab[BOYS_N * BOYS_LD];
-  __shared__ int s_maxcnt;
-  if (a.overflow && *a.overflow) return;  // uniform: the panel cannot hold the tiles
-  if (a.d_total && (int64_t)blockIdx.x >= min(*a.d_total, a.cap)) return;  // uniform exit
-  const int64_t slot = a.slot0 + blockIdx.x;
+__device__ __forceinline__ void eri_stage_table(const EriTileArgs &a, EriLds &L) {
+  for (int t = threadIdx.x; t < BOYS_N * 8; t += ERI_THREADS)
+    L.tab[(t >> 3) * BOYS_LD + (t & 7)] = a.boys[t];
+}
+
+// One tile: task `slot` of the lists, written to its panel slot(s).  Opens
+// with a barrier-separated staging phase, so consecutive calls of one
+// workgroup may reuse the LDS (the table must have been staged before).
+__device__ __forceinline__ void eri_one_tile(const EriTileArgs &a, EriLds &L, int64_t slot,
+                                             long long kept[4]) {
   const int kt = a.tasks[slot];
   const int bt = a.task_bra[slot];
   const int lane = threadIdx.x & 63;
@@ -130,52 +147,91 @@ __global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles(EriTileArgs a) {
     out = s1 >= 0 ? a.panel + (int64_t)s1 * TILE * TILE : nullptr;
     outT = s2 >= 0 ? a.panel + (int64_t)s2 * TILE * TILE : nullptr;
   } else {
-    out = a.panel + (int64_t)blockIdx.x * TILE * TILE;
+    out = a.panel + (slot - a.slot0) * TILE * TILE;
   }
-  long long kept[4] = {0, 0, 0, 0};
-  for (int t = threadIdx.x; t < BOYS_N * 8; t += ERI_THREADS)
-    tab[(t >> 3) * BOYS_LD + (t & 7)] = a.boys[t];
   // largest primitive count of the tile's bra rows
   if (threadIdx.x < 64) {
     const int64_t r = (int64_t)bt * TILE + threadIdx.x;
     int c = (int)(a.row_first[r + 1] - a.row_first[r]);
     for (int o = 32; o > 0; o >>= 1) c = max(c, __shfl_xor(c, o, 64));
-    if (threadIdx.x == 0) s_maxcnt = c;
+    if (threadIdx.x == 0) L.maxcnt = c;
   }
   __syncthreads();
-  if (s_maxcnt <= ERI_LDS_ROWPRIMS) {
-    // primitive t of bra row m at [t][m]: a wavefront's reads of one t are
-    // consecutive doubles (no bank conflicts)
-    for (int e = threadIdx.x; e < s_maxcnt * TILE; e += ERI_THREADS) {
-      const int t = e / TILE, m = e % TILE;
-      const int64_t r = (int64_t)bt * TILE + m;
-      const int64_t f = a.row_first[r];
-      if (f + t < a.row_first[r + 1]) {
-        sip[e] = a.pp.ip[f + t];
-        sx[e] = a.pp.x[f + t];
-        sy[e] = a.pp.y[f + t];
-        sz[e] = a.pp.z[f + t];
-        se[e] = a.pp.e[f + t];
-      }
-    }
-    __syncthreads();
-    eri_tile_body<true>(a, sip, sx, sy, sz, se, tab, kt, bt, lane, w, out, outT, kept);
-  } else {
-    __syncthreads();
-    eri_tile_body<false>(a, nullptr, nullptr, nullptr, nullptr, nullptr, tab, kt, bt, lane,
-                         w, out, outT, kept);
-  }
-  if (a.kept) {
-    for (int c = 0; c < 4; ++c) {
-      long long t = wave_sum_ll(kept[c]);
-      if (lane == 0 && t) atomicAdd(a.kept + c, (unsigned long long)t);
+  const int nstage = min(L.maxcnt, ERI_LDS_ROWPRIMS);
+  // primitive t of bra row m at [t][m]: a wavefront's reads of one t are
+  // consecutive doubles (no bank conflicts)
+  for (int e = threadIdx.x; e < nstage * TILE; e += ERI_THREADS) {
+    const int t = e / TILE, m = e % TILE;
+    const int64_t r = (int64_t)bt * TILE + m;
+    const int64_t f = a.row_first[r];
+    if (f + t < a.row_first[r + 1]) {
+      L.sip[e] = a.pp.ip[f + t];
+      L.sx[e] = a.pp.x[f + t];
+      L.sy[e] = a.pp.y[f + t];
+      L.sz[e] = a.pp.z[f + t];
+      L.se[e] = a.pp.e[f + t];
     }
   }
+  __syncthreads();
+  eri_tile_body(a, L, kt, bt, lane, w, out, outT, kept);
+}
+
+__device__ __forceinline__ void eri_count(const EriTileArgs &a, const long long kept[4]) {
+  if (!a.kept) return;
+  const int lane = threadIdx.x & 63;
+  for (int c = 0; c < 4; ++c) {
+    long long t = wave_sum_ll(kept[c]);
+    if (lane == 0 && t) atomicAdd(a.kept + c, (unsigned long long)t);
+  }
+}
+
+// One workgroup per tile, in list order.
+__global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles(EriTileArgs a) {
+  __shared__ EriLds L;
+  if (a.overflow && *a.overflow) return;  // uniform: the panel cannot hold the tiles
+  if (a.d_total && (int64_t)blockIdx.x >= min(*a.d_total, a.cap)) return;  // uniform exit
+  long long kept[4] = {0, 0, 0, 0};
+  eri_stage_table(a, L);
+  eri_one_tile(a, L, a.slot0 + blockIdx.x, kept);
+  eri_count(a, kept);
+}
+
+// Persistent: a fixed grid whose workgroups take tasks order[i] from a queue
+// (counter *qctr, zero at launch) until the list is exhausted; every
+// workgroup's last fetch returns an index past the end, so all of them exit.
+// The Boys table is staged once per workgroup.  Which workgroup computes a
+// tile does not change its values.
+__global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles_queue(EriTileArgs a,
+                                                                 const int32_t *order,
+                                                                 unsigned long long *qctr,
+                                                                 int64_t n_host) {
+  __shared__ EriLds L;
+  __shared__ int64_t s_next;
+  if (a.overflow && *a.overflow) return;  // uniform
+  const int64_t n = a.d_total ? min(*a.d_total, a.cap) : n_host;
+  long long kept[4] = {0, 0, 0, 0};
+  eri_stage_table(a, L);
+  for (;;) {
+    __syncthreads();  // the previous tile's LDS reads (and s_next's) are done
+    if (threadIdx.x == 0) s_next = (int64_t)atomicAdd(qctr, 1ull);
+    __syncthreads();
+    const int64_t i = s_next;
+    if (i >= n) break;  // uniform
+    eri_one_tile(a, L, order[i], kept);
+  }
+  eri_count(a, kept);
 }
 
 void launch_eri_tiles(const EriTileArgs &a, int64_t nslots, hipStream_t s) {
   if (nslots <= 0) return;
   hipLaunchKernelGGL(k_eri_tiles, dim3((unsigned)nslots), dim3(ERI_THREADS), 0, s, a);
+}
+
+void launch_eri_tiles_queue(const EriTileArgs &a, const int32_t *order, unsigned long long *qctr,
+                            int64_t n_host, int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return;
+  hipLaunchKernelGGL(k_eri_tiles_queue, dim3((unsigned)nblocks), dim3(ERI_THREADS), 0, s, a,
+                     order, qctr, n_host);
 }
 
 }  // namespace qdcb

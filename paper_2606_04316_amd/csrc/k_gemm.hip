@@ -317,7 +317,7 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
 void launch_first_half(const FirstHalfArgs &a, hipStream_t s) {
   if (a.b1 <= a.b0 || a.ncol_tiles <= 0) return;
   const int nbp = (a.b1 - a.b0 + 1) / 2, nct = a.ncol_tiles;
-  const int ncx = nct >= N_XCD ? (nct + N_XCD - 1) / N_XCD : 0;
+  const int ncx = !a.plain_order && nct >= N_XCD ? (nct + N_XCD - 1) / N_XCD : 0;
   // at most 32768 bra pairs x (ncol / 128 + 8) slices: well inside the grid limit
   const int64_t grid = ncx ? (int64_t)N_XCD * ncx * nbp : (int64_t)nbp * nct;
   hipLaunchKernelGGL((k_first_half<FH_KH, PREC_F64>), dim3((unsigned)grid), dim3(256), 0, s, a,
@@ -327,7 +327,7 @@ void launch_first_half(const FirstHalfArgs &a, hipStream_t s) {
 void launch_first_half_lp(const FirstHalfArgs &a, int tier, hipStream_t s) {
   if (a.b1 <= a.b0 || a.ncol_tiles <= 0) return;
   const int nbp = (a.b1 - a.b0 + 1) / 2, nct = a.ncol_tiles;
-  const int ncx = nct >= N_XCD ? (nct + N_XCD - 1) / N_XCD : 0;
+  const int ncx = !a.plain_order && nct >= N_XCD ? (nct + N_XCD - 1) / N_XCD : 0;
   const int64_t grid = ncx ? (int64_t)N_XCD * ncx * nbp : (int64_t)nbp * nct;
   if (tier == 2)
     hipLaunchKernelGGL((k_first_half<FH_KH, PREC_BF16>), dim3((unsigned)grid), dim3(256), 0, s,

@@ -302,6 +302,94 @@ void launch_zero_u64(unsigned long long *p, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_u64, dim3((n + 63) / 64), dim3(64), 0, s, p, n);
 }
 
+// ---------------------------------------------------------------------------
+// Longest-first order of the unique integral tiles (persistent schedule).  The
+// cost class of a tile pair is floor(log2(P_b * P_k)), P_t the primitive pairs
+// of tile t's 64 rows (P_b * P_k is the tile pair's primitive-quartet count
+// when no element is masked); its index is the product's count of leading zero
+// bits, so ascending indices run from the costliest tiles down.
+__device__ __forceinline__ int lpt_class(const int64_t *row_first, int bt, int kt) {
+  const int64_t pb = row_first[(int64_t)(bt + 1) * TILE] - row_first[(int64_t)bt * TILE];
+  const int64_t pk = row_first[(int64_t)(kt + 1) * TILE] - row_first[(int64_t)kt * TILE];
+  const unsigned long long c =
+      (unsigned long long)max(pb, (int64_t)1) * (unsigned long long)max(pk, (int64_t)1);
+  return __clzll((long long)c);  // c >= 1: 0..63
+}
+
+__device__ __forceinline__ int64_t lpt_n(int64_t n_host, const int64_t *d_total, int64_t cap) {
+  return d_total ? min(*d_total, cap) : n_host;
+}
+
+// class sizes: work[c] += number of tasks of class c
+__global__ void __launch_bounds__(256) k_lpt_count(int64_t n_host, const int64_t *d_total,
+                                                   int64_t cap, const int32_t *tk,
+                                                   const int32_t *tb, const int64_t *row_first,
+                                                   unsigned long long *work) {
+  __shared__ unsigned int h[LPT_CLASSES];
+  if (threadIdx.x < LPT_CLASSES) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t n = lpt_n(n_host, d_total, cap);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    atomicAdd(&h[lpt_class(row_first, tb[i], tk[i])], 1u);
+  __syncthreads();
+  if (threadIdx.x < LPT_CLASSES && h[threadIdx.x])
+    atomicAdd(&work[threadIdx.x], (unsigned long long)h[threadIdx.x]);
+}
+
+// work[64 + c] = first position of class c; the queue counter work[128] = 0
+__global__ void k_lpt_scan(unsigned long long *work) {
+  if (threadIdx.x != 0) return;
+  unsigned long long acc = 0;
+  for (int c = 0; c < LPT_CLASSES; ++c) {
+    work[LPT_CLASSES + c] = acc;
+    acc += work[c];
+  }
+  work[2 * LPT_CLASSES] = 0;
+}
+
+// order[pos] = task index; each block reserves a range per class for its 256
+// tasks with one atomic, then places them by their rank inside the block
+__global__ void __launch_bounds__(256) k_lpt_scatter(int64_t n_host, const int64_t *d_total,
+                                                     int64_t cap, const int32_t *tk,
+                                                     const int32_t *tb, const int64_t *row_first,
+                                                     unsigned long long *work, int32_t *order) {
+  __shared__ unsigned int h[LPT_CLASSES];
+  __shared__ unsigned long long base[LPT_CLASSES];
+  const int64_t n = lpt_n(n_host, d_total, cap);
+  for (int64_t i0 = (int64_t)blockIdx.x * 256; i0 < n; i0 += (int64_t)gridDim.x * 256) {
+    if (threadIdx.x < LPT_CLASSES) h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t i = i0 + threadIdx.x;
+    int c = -1;
+    unsigned int r = 0;
+    if (i < n) {
+      c = lpt_class(row_first, tb[i], tk[i]);
+      r = atomicAdd(&h[c], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < LPT_CLASSES && h[threadIdx.x])
+      base[threadIdx.x] =
+          atomicAdd(&work[LPT_CLASSES + threadIdx.x], (unsigned long long)h[threadIdx.x]);
+    __syncthreads();
+    if (c >= 0) order[base[c] + r] = (int32_t)i;
+    __syncthreads();
+  }
+}
+
+void launch_lpt_order(int64_t n_host, const int64_t *d_total, int64_t cap, int64_t grid_cap,
+                      const int32_t *task_k, const int32_t *task_b, const int64_t *row_first,
+                      unsigned long long *work, int32_t *order, hipStream_t s) {
+  launch_zero_u64(work, LPT_WORK, s);
+  const int64_t m = d_total ? grid_cap : n_host;
+  if (m <= 0) return;
+  const unsigned nb = (unsigned)std::min<int64_t>((m + 255) / 256, 2048);
+  hipLaunchKernelGGL(k_lpt_count, dim3(nb), dim3(256), 0, s, n_host, d_total, cap, task_k,
+                     task_b, row_first, work);
+  hipLaunchKernelGGL(k_lpt_scan, dim3(1), dim3(64), 0, s, work);
+  hipLaunchKernelGGL(k_lpt_scatter, dim3(nb), dim3(256), 0, s, n_host, d_total, cap, task_k,
+                     task_b, row_first, work, order);
+}
+
 void launch_screen_fill(int b0, int b1, int ntiles, const double *Qmax, const double *Bmax,
                         double tau, const int64_t *slot_base, int32_t *tasks,
                         int32_t *task_bra, hipStream_t s) {

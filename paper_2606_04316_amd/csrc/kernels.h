@@ -126,6 +126,21 @@ struct EriTileArgs {
   unsigned long long *kept;   // [4] kept directed contributions per class pair, or NULL
 };
 void launch_eri_tiles(const EriTileArgs &a, int64_t nslots, hipStream_t s);
+// Persistent integral launch of nblocks workgroups over the tasks order[i],
+// i < n (n = min(*a.d_total, a.cap) when a.d_total is set, else n_host); the
+// queue counter *qctr must be 0 at launch.
+void launch_eri_tiles_queue(const EriTileArgs &a, const int32_t *order, unsigned long long *qctr,
+                            int64_t n_host, int nblocks, hipStream_t s);
+// Longest-first order of n unique tile tasks (n as for launch_eri_tiles_queue,
+// from d_total/cap or n_host): order lists the task indices by decreasing
+// floor(log2(bra primitive pairs x ket primitive pairs)) of their tiles (order
+// within a class unspecified).  work: LPT_WORK 64-bit words; its last word is
+// the queue counter of the integral launch, zeroed here.
+constexpr int LPT_CLASSES = 64;
+constexpr int LPT_WORK = 2 * LPT_CLASSES + 1;
+void launch_lpt_order(int64_t n_host, const int64_t *d_total, int64_t cap, int64_t grid_cap,
+                      const int32_t *task_k, const int32_t *task_b, const int64_t *row_first,
+                      unsigned long long *work, int32_t *order, hipStream_t s);
 
 // ---- first-half contraction (k_gemm.hip)
 struct FirstHalfArgs {
@@ -145,6 +160,9 @@ struct FirstHalfArgs {
   double *V;             // [nrows][ld]
   int64_t ld;
   int ncol_tiles;        // ld / 128
+  // workgroup order: 0 = XCD-aware (with at least 8 column slices), 1 = plain
+  // (bra-tile pairs fastest); the order does not change any result
+  int plain_order = 0;
 };
 void launch_first_half(const FirstHalfArgs &a, hipStream_t s);
 // Reduced-precision tiers: V += the tier's contributions, computed with FP32
@@ -158,11 +176,13 @@ void launch_dgemm_batched(int transA, int M, int N, int K, double alpha, const d
                           int64_t strideB, double beta, double *C, int64_t ldc,
                           int64_t strideC, int batch, hipStream_t s);
 
-// Second-half first quarter straight from the first-half rows: for every
-// batch b < nb and slice column c < nc,
-//   C[c * ldc_c + b * ldc_b + j] = sum_{k < K} V[rowmap[b * sb + k * sk] * ld + col0 + c] * B[k * ldb + j]
-// for j < J (the dense V of a column is never formed).  col0, ld and ldb must
-// be multiples of 2 (16-byte rows).
+// Gathered GEMM, 128 x 128 tiles: for every batch b < nb, c < nc and j < J,
+//   C[c * ldc_c + b * ldc_b + j] (+)= sum_{k < K} V[row(b, k) * ld + col0 + c] * B[b * sbB + k * ldb + j]
+// with row(b, k) = rowmap[b * sb + k * sk], or k when rowmap is NULL; "+=" when
+// accumulate is set.  Serves the second half's first quarter straight from
+// the first-half rows (the dense V of a column is never formed) and, with
+// identity rows, its second quarter.  col0, ld, ldb, sbB and J must be even
+// (16-byte rows, two columns per lane).
 struct GatherGemmArgs {
   const double *V;
   int64_t ld, col0;
@@ -170,9 +190,10 @@ struct GatherGemmArgs {
   int64_t sb, sk;
   int nc, K, J, nb;
   const double *B;
-  int64_t ldb;
+  int64_t ldb, sbB;
   double *C;
   int64_t ldc_c, ldc_b;
+  int accumulate;
 };
 void launch_gather_gemm(const GatherGemmArgs &a, hipStream_t s);
 

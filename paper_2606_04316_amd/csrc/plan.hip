@@ -409,6 +409,23 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
       sp->dmap.alloc(ctx, cap);
       sp->udtotal.alloc(ctx, 1);
       sp->uoverflow.alloc(ctx, 1);
+      sp->uorder.alloc(ctx, ucap);
+      sp->lpt.alloc(ctx, LPT_WORK);
+    }
+    // --- launch choices and the shape key of the tuning cache
+    HIPC(hipDeviceGetAttribute(&p.n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    p.tune.eri_sched = 0;
+    p.tune.fh_order = 0;
+    p.tune.sq_tile = (p.n % 2 == 0 && p.n >= 128) ? 128 : 64;
+    {
+      int kL = *std::max_element(L->nprim.begin(), L->nprim.end());
+      int kS = S ? *std::max_element(S->nprim.begin(), S->nprim.end()) : 0;
+      char key[256];
+      std::snprintf(key, sizeof key,
+                    "v1 ham=%d prec=%d n=%d NL=%d NS=%d kL=%d kS=%d tau=%.3e tC=%d tG=%d cu=%d",
+                    (int)desc->ham, (int)desc->prec, p.n, p.NL, p.NS, kL, kS, desc->tau,
+                    p.C.ntiles, p.gaunt ? p.G.ntiles : 0, p.n_cu);
+      p.tune_key = key;
     }
     size_plan(p, 0, 0);
     p.boys.upload(ctx, boys_table());
@@ -448,7 +465,7 @@ qdcb_status qdcb_plan_estimate(const qdcb_basis *L, const qdcb_basis *S,
     double b = 40.0 * prims;                              // primitive-pair data
     b += 48.0 * (PC + PG);                                // row metadata
     b += 16.0 * (PC * ldK + 3.0 * PG * ldK);              // D~ and V, all columns
-    b += 20.0 * (ntC * ntC + ntG * ntG);                  // task lists, unique pairs, slot map
+    b += 22.0 * (ntC * ntC + ntG * ntG);                  // task lists, unique pairs, slot map
     if (desc->prec == QDCB_PREC_MIXED) b += 8.0 * (ntC * ntC + ntG * ntG);  // tier sub-lists
     b += 8.0 * 256 * (std::max(NL, NS) * 4 * n + 4 * n * n);  // second-half slice
     b += 8.0 * 20.0 * (NL + NS) * n * 4;                  // coefficient matrices

@@ -10,6 +10,13 @@
 // hipGraph and replayed for re-transforms with new coefficients written into
 // the same buffers; a replay whose kept tiles exceed the panel sets a flag
 // and is redone eagerly.
+//
+// The autotuner times the launch choices of a plan (integral schedule,
+// first-half workgroup order, second-quarter tile) on the plan's own workload,
+// one column chunk per trial, and keeps the faster value of each.
+#include <cstdlib>
+#include <limits>
+
 #include "plan.h"
 
 using namespace qdcb;
@@ -32,6 +39,7 @@ struct StageTimer {
   hipEvent_t open = nullptr;
   int open_stage = -1;
   bool probe_only = false;  // densities and screening only (sizing before a capture)
+  int max_chunks = 0;       // > 0: stop after that many MO-pair column chunks (tuning runs)
   StageTimer(hipStream_t st, bool enabled) : s(st), on(enabled) {}
   ~StageTimer() {
     for (auto e : sync_events) (void)hipEventDestroy(e);
@@ -183,6 +191,10 @@ void screen(qdcb_plan &p, Space &sp, bool captured, hipStream_t s) {
   }
   launch_screen_fill_u(sp.ntiles, sp.Qmax.p, sp.Bmax.p, p.desc.tau, sp.ubase.p, sp.dmap.p,
                        sp.utask_k.p, sp.utask_b.p, sp.uslot_bk.p, sp.uslot_kb.p, s);
+  if (p.tune.eri_sched == 1)  // persistent integral schedule: longest tiles first
+    launch_lpt_order(captured ? 0 : sp.utotal, captured ? sp.udtotal.p : nullptr,
+                     (int64_t)sp.utask_k.n, (int64_t)sp.utask_k.n, sp.utask_k.p, sp.utask_b.p,
+                     sp.row_first.p, sp.lpt.p, sp.uorder.p, s);
   HIPC(hipGetLastError());
   sp.sym = captured || sp.total <= sp.panel_slots;
 }
@@ -224,6 +236,7 @@ FirstHalfArgs fh_args(Space &sp, int b0, int b1, int64_t slot0) {
 // launch; mixed plans as the FP64 tier (which stores V) followed by the FP32
 // and BF16 tiers (which add to it).
 void contract(qdcb_plan &p, Space &sp, FirstHalfArgs fa, StageTimer &tm, hipStream_t s) {
+  fa.plain_order = p.tune.fh_order;
   if (p.desc.prec != QDCB_PREC_MIXED) {
     tm.begin(ST_FH);
     launch_first_half(fa, s);
@@ -249,6 +262,11 @@ void contract(qdcb_plan &p, Space &sp, FirstHalfArgs fa, StageTimer &tm, hipStre
   }
 }
 
+// Workgroups of the persistent integral launch: two per compute unit (the
+// integral kernel's register and LDS use allow two resident 512-thread
+// workgroups per compute unit).
+int eri_queue_blocks(const qdcb_plan &p) { return 2 * std::max(p.n_cu, 1); }
+
 // Integral tiles + first half of one space over its current column chunk.
 void first_half(qdcb_plan &p, Space &sp, bool make_tiles, bool count, bool captured,
                 StageTimer &tm, hipStream_t s) {
@@ -262,14 +280,23 @@ void first_half(qdcb_plan &p, Space &sp, bool make_tiles, bool count, bool captu
       ea.task_bra = sp.utask_b.p;
       ea.uslot_bk = sp.uslot_bk.p;
       ea.uslot_kb = sp.uslot_kb.p;
+      const bool queue = p.tune.eri_sched == 1;
+      unsigned long long *qctr = sp.lpt.p + 2 * LPT_CLASSES;  // zeroed with the order
       if (captured) {
         ea.overflow = sp.overflow.p;
         ea.d_total = sp.udtotal.p;
         ea.cap = sp.panel_slots;
-        launch_eri_tiles(ea, std::min<int64_t>(sp.panel_slots, (int64_t)sp.utask_k.n), s);
+        if (queue)
+          launch_eri_tiles_queue(ea, sp.uorder.p, qctr, 0, eri_queue_blocks(p), s);
+        else
+          launch_eri_tiles(ea, std::min<int64_t>(sp.panel_slots, (int64_t)sp.utask_k.n), s);
       } else {
         tm.begin(ST_ERI);
-        launch_eri_tiles(ea, sp.utotal, s);
+        if (queue)
+          launch_eri_tiles_queue(ea, sp.uorder.p, qctr, sp.utotal,
+                                 (int)std::min<int64_t>(eri_queue_blocks(p), sp.utotal), s);
+        else
+          launch_eri_tiles(ea, sp.utotal, s);
         tm.end();
         p.tiles_made += sp.utotal;
       }
@@ -355,7 +382,7 @@ void first_half(qdcb_plan &p, Space &sp, bool make_tiles, bool count, bool captu
 void gather_quarter(const qdcb_plan &p, const Space &sp, const int32_t *rowmap, int64_t sb,
                     int64_t sk, int nb, int K, const double *Call, int64_t col0, int nc,
                     hipStream_t s) {
-  GatherGemmArgs g;
+  GatherGemmArgs g{};
   g.V = sp.V.p;
   g.ld = sp.ld;
   g.col0 = col0;
@@ -374,6 +401,37 @@ void gather_quarter(const qdcb_plan &p, const Space &sp, const int32_t *rowmap, 
   launch_gather_gemm(g, s);
 }
 
+// Second quarter for nc columns: Gc[c] (+)= Ahat^T W[c], Ahat [4N][4n] (rows
+// (mu, z), columns (x, p)), W[c] [4N][n], Gc[c] [4n][n].  Tile 128: the
+// gathered-GEMM kernel with identity rows (A^T rows are Ahat's rows, one
+// W block per batch); tile 64: the batched GEMM.
+void second_quarter(const qdcb_plan &p, const double *Ahat, int N, bool accumulate, int nc,
+                    hipStream_t s) {
+  const int n = p.n;
+  if (p.tune.sq_tile == 128) {
+    GatherGemmArgs g{};
+    g.V = Ahat;
+    g.ld = 4 * n;
+    g.col0 = 0;
+    g.rowmap = nullptr;
+    g.nc = 4 * n;
+    g.K = 4 * N;
+    g.J = n;
+    g.nb = nc;
+    g.B = p.W.p;
+    g.ldb = n;
+    g.sbB = (int64_t)N * 4 * n;
+    g.C = p.Gc.p;
+    g.ldc_c = n;
+    g.ldc_b = (int64_t)4 * n * n;
+    g.accumulate = accumulate ? 1 : 0;
+    launch_gather_gemm(g, s);
+  } else {
+    launch_dgemm_batched(1, 4 * n, n, 4 * N, 1.0, Ahat, 4 * n, 0, p.W.p, n, (int64_t)N * 4 * n,
+                         accumulate ? 1.0 : 0.0, p.Gc.p, n, (int64_t)4 * n * n, nc, s);
+  }
+}
+
 void second_half(qdcb_plan &p, int i0, int i1, double *dG, hipStream_t s) {
   const int n = p.n;
   const int64_t cend = 4LL * i1;
@@ -386,9 +444,7 @@ void second_half(qdcb_plan &p, int i0, int i1, double *dG, hipStream_t s) {
       gather_quarter(p, p.C, cls ? p.rowmapS.p : p.rowmapL.p, N, 1, N, N,
                      cls ? p.CallS.p : p.CallL.p, lc0, nc, s);
       // G_c (+)= Chat^T W_c
-      launch_dgemm_batched(1, 4 * n, n, 4 * N, 1.0, cls ? p.ChatS.p : p.ChatL.p, 4 * n, 0, p.W.p,
-                           n, (int64_t)N * 4 * n, cls ? 1.0 : 0.0, p.Gc.p, n, (int64_t)4 * n * n,
-                           nc, s);
+      second_quarter(p, cls ? p.ChatS.p : p.ChatL.p, N, cls != 0, nc, s);
     }
     launch_pack(n, p.rs.p, c0, nc, p.Gc.p, dG, 1.0, 0, s);
     if (p.gaunt) {
@@ -397,13 +453,10 @@ void second_half(qdcb_plan &p, int i0, int i1, double *dG, hipStream_t s) {
         const int64_t col0 = K * p.G.ldK + lc0;
         // conj(C^L) e_K (V C^S): batches mu in L, sum over nu in S
         gather_quarter(p, p.G, p.rowmapLS.p, NS, 1, NL, NS, p.CallS.p, col0, nc, s);
-        launch_dgemm_batched(1, 4 * n, n, 4 * NL, 1.0, p.AhatK[K].p, 4 * n, 0, p.W.p, n,
-                             (int64_t)NL * 4 * n, K ? 1.0 : 0.0, p.Gc.p, n, (int64_t)4 * n * n,
-                             nc, s);
+        second_quarter(p, p.AhatK[K].p, NL, K != 0, nc, s);
         // conj(C^S) e_K (V^T C^L): batches nu in S, sum over mu in L
         gather_quarter(p, p.G, p.rowmapLS.p, 1, NS, NS, NL, p.CallL.p, col0, nc, s);
-        launch_dgemm_batched(1, 4 * n, n, 4 * NS, 1.0, p.BhatK[K].p, 4 * n, 0, p.W.p, n,
-                             (int64_t)NS * 4 * n, 1.0, p.Gc.p, n, (int64_t)4 * n * n, nc, s);
+        second_quarter(p, p.BhatK[K].p, NS, true, nc, s);
       }
       launch_pack(n, p.rs.p, c0, nc, p.Gc.p, dG, -1.0, 1, s);
     }
@@ -441,7 +494,8 @@ void enqueue(qdcb_plan &p, const double *dCL, const double *dCS, double *dG, boo
       launch_build_coef_mats(p.NS, p.n, dCS, K, p.CallS.p, p.BhatK[K].p, s);
     }
   HIPC(hipGetLastError());
-  for (int i0 = 0; i0 < p.npair_mo; i0 += p.ci) {
+  for (int i0 = 0, k = 0; i0 < p.npair_mo && (tm.max_chunks <= 0 || k < tm.max_chunks);
+       i0 += p.ci, ++k) {
     const int i1 = std::min(p.npair_mo, i0 + p.ci);
     p.v_i0 = i0;
     p.v_i1 = i1;
@@ -547,9 +601,106 @@ void run_eager(qdcb_plan &p, const double *dCL, const double *dCS, double *dG, h
   }
 }
 
+// Device copies of host inputs (QDCB_PTR_DEVICE unset): CL, CS into the
+// plan's coefficient buffers, G into its staging buffer.
+struct DevIO {
+  const double *CL, *CS;
+  double *G;
+};
+DevIO device_io(qdcb_plan &p, const double *CL, const double *CS, double *G, bool dev,
+                hipStream_t s) {
+  if (dev) return {CL, CS, G};
+  const size_t nG = (size_t)p.n * p.n * p.n * p.n * 16;
+  check_finite_host(CL, (size_t)4 * p.NL * p.n, "CL");
+  if (p.NS) check_finite_host(CS, (size_t)4 * p.NS * p.n, "CS");
+  HIPC(hipMemcpyAsync(p.CLd.p, CL, p.CLd.bytes(), hipMemcpyHostToDevice, s));
+  DevIO io{p.CLd.p, nullptr, nullptr};
+  if (p.NS) {
+    HIPC(hipMemcpyAsync(p.CSd.p, CS, p.CSd.bytes(), hipMemcpyHostToDevice, s));
+    io.CS = p.CSd.p;
+  }
+  if (p.Gd.n != nG) p.Gd.alloc(p.ctx, nG);
+  io.G = p.Gd.p;
+  return io;
+}
+
 }  // namespace
 
 extern "C" {
+
+qdcb_status qdcb_plan_autotune(qdcb_plan *plan, const double *CL, const double *CS, double *G,
+                               uint32_t flags, void *hip_stream, const char *cache_path,
+                               qdcb_tune_report *report) {
+  return guarded([&] {
+    if (!plan || !CL || !G) fail(QDCB_E_INVALID, "NULL argument");
+    qdcb_plan &p = *plan;
+    if (p.NS && !CS) fail(QDCB_E_INVALID, "CS is required for this Hamiltonian");
+    const char *path = cache_path ? cache_path : std::getenv("QDCB_TUNE_CACHE");
+    if (path && !*path) path = nullptr;
+    qdcb_tune_report rep{};
+    for (int v = 0; v < 2; ++v)
+      rep.ms_eri[v] = rep.ms_first_half[v] = rep.ms_second_half[v] = std::nan("");
+    if (path) {
+      qdcb_tune t{};
+      int32_t found = 0;
+      const qdcb_status st = qdcb_tune_cache_lookup(path, p.tune_key.c_str(), &t, &found);
+      if (st != QDCB_OK) fail(st, qdcb_last_error());
+      if (found && qdcb_plan_set_tune(plan, &t) == QDCB_OK) {
+        rep.chosen = p.tune;
+        rep.from_cache = 1;
+        if (report) *report = rep;
+        return;
+      }
+    }
+    DeviceGuard g(p.ctx->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    const DevIO io = device_io(p, CL, CS, G, flags & QDCB_PTR_DEVICE, s);
+    const qdcb_tune saved = p.tune;
+    // the two candidates differ in every choice; alternating them gives each
+    // value of each choice two timings of its own stage
+    const qdcb_tune cand[2] = {{0, 0, 64, 0}, {1, 1, p.n % 2 ? 64 : 128, 0}};
+    const double inf = std::numeric_limits<double>::infinity();
+    double best[3][2] = {{inf, inf}, {inf, inf}, {inf, inf}};
+    auto trial = [&](const qdcb_tune &t, bool keep) {
+      p.tune = t;
+      StageTimer tm(s, true);
+      tm.max_chunks = 1;
+      enqueue(p, io.CL, io.CS, io.G, false, tm, s);
+      HIPC(hipStreamSynchronize(s));
+      if (!keep) return;
+      const double ms[3] = {tm.total(ST_ERI),
+                            tm.total(ST_FH) + tm.total(ST_FH32) + tm.total(ST_FH16),
+                            tm.total(ST_SH)};
+      const int val[3] = {t.eri_sched, t.fh_order, t.sq_tile == 128 ? 1 : 0};
+      for (int c = 0; c < 3; ++c) best[c][val[c]] = std::min(best[c][val[c]], ms[c]);
+    };
+    try {
+      trial(saved, false);  // warm-up: panel sizing, first launches of every kernel
+      for (int r = 0; r < 4; ++r) trial(cand[r & 1], true);
+    } catch (...) {
+      p.tune = saved;
+      throw;
+    }
+    auto pick = [&](int c) { return best[c][1] < 0.99 * best[c][0] ? 1 : 0; };
+    qdcb_tune t{};
+    t.eri_sched = pick(0);
+    t.fh_order = pick(1);
+    t.sq_tile = pick(2) ? 128 : 64;
+    p.tune = t;
+    rep.chosen = t;
+    rep.trials = 4;
+    for (int v = 0; v < 2; ++v) {
+      if (best[0][v] < inf) rep.ms_eri[v] = best[0][v];
+      if (best[1][v] < inf) rep.ms_first_half[v] = best[1][v];
+      if (best[2][v] < inf) rep.ms_second_half[v] = best[2][v];
+    }
+    if (path) {
+      const qdcb_status st = qdcb_tune_cache_store(path, p.tune_key.c_str(), &t);
+      if (st != QDCB_OK) fail(st, qdcb_last_error());
+    }
+    if (report) *report = rep;
+  });
+}
 
 qdcb_status qdcb_transform(qdcb_plan *plan, const double *CL, const double *CS, double *G,
                            uint32_t flags, void *hip_stream, qdcb_stats *stats) {
@@ -562,21 +713,9 @@ qdcb_status qdcb_transform(qdcb_plan *plan, const double *CL, const double *CS, 
     const bool dev = flags & QDCB_PTR_DEVICE;
     const int n = p.n;
     const size_t nG = (size_t)n * n * n * n * 16;
-    const double *dCL = CL, *dCS = CS;
-    double *dG = G;
-    if (!dev) {
-      check_finite_host(CL, (size_t)4 * p.NL * n, "CL");
-      if (p.NS) check_finite_host(CS, (size_t)4 * p.NS * n, "CS");
-      HIPC(hipMemcpyAsync(p.CLd.p, CL, p.CLd.bytes(), hipMemcpyHostToDevice, s));
-      dCL = p.CLd.p;
-      if (p.NS) {
-        HIPC(hipMemcpyAsync(p.CSd.p, CS, p.CSd.bytes(), hipMemcpyHostToDevice, s));
-        dCS = p.CSd.p;
-      }
-      if (p.Gd.n != nG) p.Gd.alloc(p.ctx, nG);
-      dG = p.Gd.p;
-    }
-    run_eager(p, dCL, dCS, dG, s, stats);
+    const DevIO io = device_io(p, CL, CS, G, dev, s);
+    double *dG = io.G;
+    run_eager(p, io.CL, io.CS, dG, s, stats);
     if (!dev) {
       HIPC(hipMemcpyAsync(G, dG, nG * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPC(hipStreamSynchronize(s));

@@ -60,6 +60,26 @@ class Stats(ctypes.Structure):
         return d
 
 
+class Tune(ctypes.Structure):
+    _fields_ = [("eri_sched", ctypes.c_int32), ("fh_order", ctypes.c_int32),
+                ("sq_tile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"eri_sched": self.eri_sched, "fh_order": self.fh_order, "sq_tile": self.sq_tile}
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("chosen", Tune), ("from_cache", ctypes.c_int32), ("trials", ctypes.c_int32),
+                ("ms_eri", ctypes.c_double * 2), ("ms_first_half", ctypes.c_double * 2),
+                ("ms_second_half", ctypes.c_double * 2)]
+
+    def as_dict(self):
+        return {"chosen": self.chosen.as_dict(), "from_cache": self.from_cache,
+                "trials": self.trials, "ms_eri": list(self.ms_eri),
+                "ms_first_half": list(self.ms_first_half),
+                "ms_second_half": list(self.ms_second_half)}
+
+
 _lib = None
 _P = ctypes.c_void_p
 _DP = ctypes.POINTER(ctypes.c_double)
@@ -100,10 +120,21 @@ def lib():
         L.qdcb_plan_capture.argtypes = [_P, _P, _P, _P, _P]
         L.qdcb_plan_replay.argtypes = [_P, _P, ctypes.POINTER(Stats)]
         L.qdcb_plan_fetch_v.argtypes = [_P, _P, ctypes.c_int64, _P]
+        L.qdcb_plan_set_tune.argtypes = [_P, ctypes.POINTER(Tune)]
+        L.qdcb_plan_get_tune.argtypes = [_P, ctypes.POINTER(Tune)]
+        L.qdcb_plan_tune_key.argtypes = [_P, ctypes.c_char_p, ctypes.c_size_t]
+        L.qdcb_tune_cache_lookup.argtypes = [ctypes.c_char_p, ctypes.c_char_p,
+                                             ctypes.POINTER(Tune), _IP]
+        L.qdcb_tune_cache_store.argtypes = [ctypes.c_char_p, ctypes.c_char_p,
+                                            ctypes.POINTER(Tune)]
+        L.qdcb_plan_autotune.argtypes = [_P, _P, _P, _P, ctypes.c_uint32, _P, ctypes.c_char_p,
+                                         ctypes.POINTER(TuneReport)]
         for f in ("qdcb_ctx_create", "qdcb_basis_create", "qdcb_basis_schwarz",
                   "qdcb_eri_quartets", "qdcb_plan_create", "qdcb_plan_footprint",
                   "qdcb_transform", "qdcb_plan_fetch", "qdcb_plan_estimate",
-                  "qdcb_plan_capture", "qdcb_plan_replay", "qdcb_plan_fetch_v"):
+                  "qdcb_plan_capture", "qdcb_plan_replay", "qdcb_plan_fetch_v",
+                  "qdcb_plan_set_tune", "qdcb_plan_get_tune", "qdcb_plan_tune_key",
+                  "qdcb_tune_cache_lookup", "qdcb_tune_cache_store", "qdcb_plan_autotune"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -174,6 +205,18 @@ class Basis:
             pass
 
 
+def tune_cache_lookup(path: str, key: str) -> Optional[dict]:
+    t, found = Tune(), ctypes.c_int32(0)
+    _check(lib().qdcb_tune_cache_lookup(path.encode(), key.encode(), ctypes.byref(t),
+                                        ctypes.byref(found)))
+    return t.as_dict() if found.value else None
+
+
+def tune_cache_store(path: str, key: str, tune: dict):
+    t = Tune(int(tune["eri_sched"]), int(tune["fh_order"]), int(tune["sq_tile"]), 0)
+    _check(lib().qdcb_tune_cache_store(path.encode(), key.encode(), ctypes.byref(t)))
+
+
 def eri_quartets(A: Basis, B: Basis, idx) -> np.ndarray:
     idx = np.ascontiguousarray(idx, dtype=np.int32).reshape(-1, 4)
     out = np.empty(idx.shape[0])
@@ -236,6 +279,50 @@ class Plan:
                                     CSh.ctypes.data if CSh is not None else None,
                                     G.ctypes.data, 0, stream, ctypes.byref(st)))
         return G, st.as_dict()
+
+    @property
+    def tune(self) -> dict:
+        t = Tune()
+        _check(lib().qdcb_plan_get_tune(self.h, ctypes.byref(t)))
+        return t.as_dict()
+
+    @tune.setter
+    def tune(self, d: dict):
+        cur = self.tune
+        cur.update(d)
+        t = Tune(int(cur["eri_sched"]), int(cur["fh_order"]), int(cur["sq_tile"]), 0)
+        _check(lib().qdcb_plan_set_tune(self.h, ctypes.byref(t)))
+
+    def tune_key(self) -> str:
+        buf = ctypes.create_string_buffer(512)
+        _check(lib().qdcb_plan_tune_key(self.h, buf, len(buf)))
+        return buf.value.decode()
+
+    def autotune(self, CL, CS=None, G=None, stream=None, cache: Optional[str] = None) -> dict:
+        """Pick the plan's launch choices by timing them on these coefficients
+        (or take them from the cache file); G is scratch.  Returns the report."""
+        n = self.n
+        rep = TuneReport()
+        path = cache.encode() if cache else None
+        if _is_torch_cuda(CL):
+            import torch
+            if G is None:
+                G = torch.empty((n, n, n, n, 4, 4), dtype=torch.float64, device=CL.device)
+            if stream is None:
+                stream = torch.cuda.current_stream(CL.device).cuda_stream
+            _check(lib().qdcb_plan_autotune(self.h, CL.data_ptr(),
+                                            CS.data_ptr() if CS is not None else None,
+                                            G.data_ptr(), PTR_DEVICE, stream, path,
+                                            ctypes.byref(rep)))
+            return rep.as_dict()
+        CLh = _f64(CL)
+        CSh = _f64(CS) if CS is not None else None
+        if G is None:
+            G = np.empty((n, n, n, n, 4, 4))
+        _check(lib().qdcb_plan_autotune(self.h, CLh.ctypes.data,
+                                        CSh.ctypes.data if CSh is not None else None,
+                                        G.ctypes.data, 0, stream, path, ctypes.byref(rep)))
+        return rep.as_dict()
 
     def capture(self, CL, CS, G, stream):
         """Record the transformation of the device tensors CL, CS -> G into a
