@@ -157,7 +157,8 @@ def main_transform(args):
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
-        if tr.get("workload") == args.workload and tr.get("kernel_rev") == qdcb_kernel_rev():
+        if (tr.get("workload") == args.workload and tr.get("kernel_rev") == qdcb_kernel_rev()
+                and tr.get("fh_order") == plan.tune["fh_order"]):
             traffic = tr.get("bytes_per_launch")
     st0 = stats[-1]
     line = {
