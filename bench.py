@@ -48,7 +48,10 @@ def parse():
                          "chain40_dcg, chain40")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=96)
-    ap.add_argument("--requests", type=int, default=48)
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--serving-prec", default="fp64,mixed",
+                    help="serving: precisions to serve the stream in, one run each "
+                         "(mixed: tiers 1e-6 / 1e-9 with the G-bound rule)")
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--tune", default="auto", choices=["auto", "default"],
                     help="transform / replay: pick the plan's launch choices with the "
@@ -327,26 +330,39 @@ def main_serving(args):
     (see the design doc); eight requests are re-run alone and compared bitwise."""
     from paper_2606_04316_amd import serving
 
-    reqs = serving.request_stream(args.requests, seed=5, mean_gap_s=0.02, pool=12,
-                                  atoms=(10, 40), nl=(40, 160), n_mo=(8, 32),
-                                  radius_scale=20.0)
-    ex = serving.GpuExecutor(slots=args.slots)
     import torch
-    budget = int(0.5 * torch.cuda.mem_get_info()[0])
-    srv = serving.Server(ex, ex.reserve, slots=args.slots, budget_bytes=budget)
-    out = srv.run(reqs)
-    summ = serving.summarize(out)
-    alone = serving.GpuExecutor(slots=1)
-    same = 0
-    for r in out[:: max(1, len(out) // 8)][:8]:
-        solo = serving.Request(rid=r.rid, system=r.system, arrival=0.0)
-        solo.reserve = alone.reserve(solo)
-        same += alone(solo, 0)["digest"] == r.result["digest"]
-    summ.update({"metric": "serving latency", "mode": "serving", "unit": "ms",
-                 "slots": args.slots, "max_concurrency": srv.max_concurrency,
-                 "peak_reserved_GB": srv.peak_in_use / 2 ** 30,
-                 "alone_equals_mix": f"{same}/8", "dtype": "f64", "data": "synthetic"})
-    print(json.dumps(summ), flush=True)
+    runs = {}
+    for prec in args.serving_prec.split(","):
+        reqs = serving.request_stream(args.requests, seed=5, mean_gap_s=0.02, pool=12,
+                                      atoms=(10, 40), nl=(40, 160), n_mo=(8, 32),
+                                      radius_scale=20.0)
+        ex = serving.GpuExecutor(slots=args.slots, prec=prec)
+        budget = int(0.5 * torch.cuda.mem_get_info()[0])
+        srv = serving.Server(ex, ex.reserve, slots=args.slots, budget_bytes=budget)
+        out = srv.run(reqs)
+        summ = serving.summarize(out)
+        print(f"serving {prec}: {summ}", file=sys.stderr, flush=True)
+        alone = serving.GpuExecutor(slots=1, prec=prec)
+        same = 0
+        for r in out[:: max(1, len(out) // 8)][:8]:
+            solo = serving.Request(rid=r.rid, system=r.system, arrival=0.0)
+            solo.reserve = alone.reserve(solo)
+            same += alone(solo, 0)["digest"] == r.result["digest"]
+        summ.update({"max_concurrency": srv.max_concurrency,
+                     "peak_reserved_GB": srv.peak_in_use / 2 ** 30,
+                     "alone_equals_mix": f"{same}/8"})
+        if prec == "mixed":
+            summ["tiers"] = {"tier_fp32": ex.tiers[0], "tier_bf16": ex.tiers[1], "rule": "g"}
+        runs[prec] = summ
+    first = runs[next(iter(runs))]
+    line = {"metric": "serving p99 latency", "mode": "serving", "value": first["p99_ms"],
+            "unit": "ms", "higher_is_better": False, "slots": args.slots,
+            "requests": args.requests, "runs": runs, "data": "synthetic",
+            "dtype": "f64" if "mixed" not in runs else "f64 / f64+f32+bf16"}
+    if "fp64" in runs and "mixed" in runs:
+        line["mixed_vs_fp64_throughput"] = (runs["mixed"]["mo_integrals_per_s"]
+                                            / runs["fp64"]["mo_integrals_per_s"])
+    print(json.dumps(line), flush=True)
 
 
 def qdcb_kernel_rev():

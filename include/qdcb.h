@@ -31,7 +31,8 @@
  *   - Ownership: the caller owns every pointer it passes; the library copies
  *     what it keeps.  Library objects own their device memory.
  *   - Threading: a context may be shared between threads; a plan is used by
- *     one thread at a time.
+ *     one call at a time (a concurrent call on the same plan returns
+ *     QDCB_E_BUSY).
  */
 #ifndef QDCB_H
 #define QDCB_H
@@ -50,7 +51,9 @@ typedef enum {
     QDCB_E_INVALID = -1,     /* bad argument (non-finite input, exponent <= 0, sizes) */
     QDCB_E_NOMEM = -2,       /* device memory budget exceeded */
     QDCB_E_DEVICE = -3,      /* HIP runtime error */
-    QDCB_E_UNSUPPORTED = -4  /* valid request this build does not implement */
+    QDCB_E_UNSUPPORTED = -4, /* valid request this build does not implement */
+    QDCB_E_BUSY = -5,        /* the plan is in use by another call (plans are not reentrant) */
+    QDCB_E_ABORTED = -6      /* a block callback asked to stop */
 } qdcb_status;
 
 typedef enum {
@@ -63,6 +66,13 @@ typedef enum { QDCB_PREC_FP64 = 0, QDCB_PREC_MIXED = 1 } qdcb_prec;
 
 /* transform flags */
 #define QDCB_PTR_DEVICE 0x1u /* CL, CS and G are device pointers (else host) */
+/* Integral classes to include (neither bit: every class of the plan's
+ * Hamiltonian).  QDCB_CLASS_COULOMB: the Dirac-Coulomb classes of Eq. (DCInt)
+ * (LL|LL for QDCB_HAM_LL); QDCB_CLASS_GAUNT: the Gaunt classes of Eq.
+ * (GauntInt), DCG plans only.  The output holds the sum of the selected
+ * classes, so a DCG transform equals the sum of its two single-class ones. */
+#define QDCB_CLASS_COULOMB 0x2u
+#define QDCB_CLASS_GAUNT 0x4u
 
 typedef struct qdcb_ctx qdcb_ctx;
 typedef struct qdcb_basis qdcb_basis;
@@ -173,14 +183,38 @@ typedef struct {
     int64_t tiles_tier[3];   /* mixed: kept directed tiles contracted in FP64, FP32, BF16
                                 (eager transforms) */
     double ms_tier[3];       /* mixed: first-half time per tier (eager transforms) */
+    int32_t classes;         /* integral classes included: 1 Coulomb, 2 Gaunt, 3 both */
+    int32_t reserved;
 } qdcb_stats;
 
 /* Transform.  CL [4][N_L][n], CS [4][N_S][n] (NULL for LL), G [n^4][4][4];
- * host or device pointers per QDCB_PTR_DEVICE.  Work is enqueued on
- * hip_stream (a hipStream_t; NULL = the null stream); the call returns after
- * G is complete.  stats may be NULL. */
+ * host or device pointers per QDCB_PTR_DEVICE; class bits select integral
+ * classes (see QDCB_CLASS_COULOMB).  Work is enqueued on hip_stream (a
+ * hipStream_t; NULL = the null stream); the call returns after G is
+ * complete.  stats may be NULL (its kept counts and tiles cover the selected
+ * classes). */
 qdcb_status qdcb_transform(qdcb_plan *plan, const double *CL, const double *CS, double *G,
                            uint32_t flags, void *hip_stream, qdcb_stats *stats);
+
+/* Blocked output, for callers that do not hold all of G at once.  The same
+ * transformation as qdcb_transform, delivered in blocks of MO pairs (r <= s)
+ * in the canonical order (r outer, s inner; pair index i of (r, s) is
+ * r n - r (r - 1) / 2 + s - r).  For each block [i0, i1) the library calls
+ * cb(user, i0, i1, B, on_device) after the block is complete, with
+ *   B[i - i0][p][q][0][x][y] = G[p][q][r][s][x][y],
+ *   B[i - i0][p][q][1][x][y] = G[p][q][s][r][x][y]   ((r, s) = pair i),
+ * n^2 * 32 doubles per pair.  B is a device pointer (on_device = 1) when
+ * flags has QDCB_PTR_DEVICE, else host memory; it belongs to the library and
+ * is valid only during the call.  Blocks come in increasing order, each pair
+ * exactly once; their size follows the plan's second-half slice.  A nonzero
+ * return from cb stops the transformation: QDCB_E_ABORTED.  The callback runs
+ * on the calling thread and must not use the same plan (QDCB_E_BUSY).  flags:
+ * QDCB_PTR_DEVICE (CL, CS and the blocks on the device) and the class bits. */
+typedef int (*qdcb_block_cb)(void *user, int64_t i0, int64_t i1, const double *B,
+                             int on_device);
+qdcb_status qdcb_transform_blocks(qdcb_plan *plan, const double *CL, const double *CS,
+                                  qdcb_block_cb cb, void *user, uint32_t flags,
+                                  void *hip_stream, qdcb_stats *stats);
 
 /* Re-transforms (e.g. successive orbital updates): record one whole
  * transformation of the device buffers CL, CS -> G (which must stay valid)

@@ -96,6 +96,39 @@ __global__ void k_pack(int n, const int32_t *rs, int64_t c0, int nc, const doubl
   }
 }
 
+// Block output: one thread per (MO pair r <= s of the slice, p, q) writes
+// B[i][p][q][0][x][y] = G_pqrs^xy and B[i][p][q][1][x][y] = G_pqsr^xy (the same
+// entry when r = s), i the pair's index in the block (first pair b_i0).
+__global__ void k_pack_block(int n, const int32_t *rs, int64_t c0, int nc, const double *Gc,
+                             double *B, int64_t b_i0, double mirror, int accumulate) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t nidx = nc / 4;
+  if (t >= nidx * n * n) return;
+  int q = (int)(t % n);
+  int p = (int)((t / n) % n);
+  int64_t il = t / ((int64_t)n * n);
+  const int rsv = rs[c0 / 4 + il];
+  const bool diag = (rsv & 0xffff) == (rsv >> 16);
+  int64_t i = c0 / 4 + il - b_i0;
+  double *o = B + ((i * n + p) * n + q) * 32;
+  for (int x = 0; x < 4; ++x)
+    for (int y = 0; y < 4; ++y) {
+      const double v = Gc[((il * 4 + y) * 4 * n + (int64_t)x * n + p) * n + q];
+      // s_y = +1 for y = 0, -1 otherwise
+      const double m = diag ? v : mirror * (y == 0 ? v : -v);
+      o[x * 4 + y] = accumulate ? o[x * 4 + y] + v : v;
+      o[16 + x * 4 + y] = accumulate ? o[16 + x * 4 + y] + m : m;
+    }
+}
+
+void launch_pack_block(int n, const int32_t *rs, int64_t c0, int nc, const double *Gc,
+                       double *B, int64_t b_i0, double mirror, int accumulate, hipStream_t s) {
+  int64_t tot = (int64_t)(nc / 4) * n * n;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_pack_block, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, rs,
+                     c0, nc, Gc, B, b_i0, mirror, accumulate);
+}
+
 void launch_pack(int n, const int32_t *rs, int64_t c0, int nc, const double *Gc, double *G,
                  double mirror, int accumulate, hipStream_t s) {
   int64_t tot = (int64_t)(nc / 4) * n * n;

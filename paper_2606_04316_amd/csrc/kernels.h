@@ -208,5 +208,10 @@ void launch_build_coef_mats(int N, int n, const double *C, int unit, double *Cal
 // s = (+1,-1,-1,-1); accumulate = 1 adds to G instead of storing.
 void launch_pack(int n, const int32_t *rs, int64_t c0, int nc, const double *Gc, double *G,
                  double mirror, int accumulate, hipStream_t s);
+// Block output of the same slice: B[i][p][q][0][x][y] = v, B[i][p][q][1][x][y] =
+// mirror * s_y * v (v itself when r = s) for the slice's MO pairs, i = pair
+// index - b_i0.
+void launch_pack_block(int n, const int32_t *rs, int64_t c0, int nc, const double *Gc,
+                       double *B, int64_t b_i0, double mirror, int accumulate, hipStream_t s);
 
 }  // namespace qdcb

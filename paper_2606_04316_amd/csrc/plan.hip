@@ -495,6 +495,7 @@ extern "C" {
 qdcb_status qdcb_plan_fetch(const qdcb_plan *p, int32_t what, void *host_out, size_t bytes) {
   return guarded([&] {
     if (!p || !host_out) fail(QDCB_E_INVALID, "NULL argument");
+    PlanUse use(*p);
     DeviceGuard g(p->ctx->device);
     const bool gaunt_item = what == QDCB_FETCH_DMAX_GAUNT || what == QDCB_FETCH_Q_GAUNT;
     if (what != QDCB_FETCH_DMAX && what != QDCB_FETCH_Q && !gaunt_item)
@@ -522,6 +523,7 @@ qdcb_status qdcb_plan_fetch_v(const qdcb_plan *p, const int64_t *pairs, int64_t 
   return guarded([&] {
     if (!p || !pairs || !out || npairs < 0) fail(QDCB_E_INVALID, "NULL argument");
     if (!p->have_last) fail(QDCB_E_INVALID, "no transform yet");
+    PlanUse use(*p);
     DeviceGuard g(p->ctx->device);
     const int64_t c0 = 4LL * p->v_i0, nc = 4LL * (p->v_i1 - p->v_i0);  // resident columns
     const int64_t nLL = p->nLL, nSS = p->nSS, nLS = p->gaunt ? (int64_t)p->NL * p->NS : 0;

@@ -432,13 +432,46 @@ void second_quarter(const qdcb_plan &p, const double *Ahat, int N, bool accumula
   }
 }
 
-void second_half(qdcb_plan &p, int i0, int i1, double *dG, hipStream_t s) {
+// Receiver of the blocked output: after each second-half slice the stream is
+// synchronized and the slice's MO pairs are handed to the callback.
+struct BlockSink {
+  qdcb_block_cb cb = nullptr;
+  void *user = nullptr;
+  bool on_device = true;
+  int64_t pairs = 1;  // MO pairs per block (the block buffer's capacity)
+  void deliver(qdcb_plan &p, int64_t i0, int64_t i1, hipStream_t s) {
+    const size_t nb = (size_t)(i1 - i0) * p.n * p.n * 32;
+    const double *B = p.Gb.p;
+    if (!on_device) {
+      if (p.h_Gb.size() < nb) p.h_Gb.resize(nb);
+      HIPC(hipMemcpyAsync(p.h_Gb.data(), p.Gb.p, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+      B = p.h_Gb.data();
+    }
+    HIPC(hipStreamSynchronize(s));
+    if (cb(user, i0, i1, B, on_device ? 1 : 0) != 0)
+      fail(QDCB_E_ABORTED, "the block callback asked to stop");
+  }
+};
+
+enum { CLS_COULOMB = 1, CLS_GAUNT = 2 };
+
+void second_half(qdcb_plan &p, int i0, int i1, double *dG, hipStream_t s,
+                 int classes = CLS_COULOMB | CLS_GAUNT, BlockSink *sink = nullptr) {
   const int n = p.n;
   const int64_t cend = 4LL * i1;
-  for (int64_t c0 = 4LL * i0; c0 < cend; c0 += p.sc) {
-    const int nc = (int)std::min<int64_t>(p.sc, cend - c0);
+  const bool do_c = classes & CLS_COULOMB, do_g = p.gaunt && (classes & CLS_GAUNT);
+  // slices of whole MO pairs; with blocked output, of at most one block
+  const int64_t step = sink ? std::min<int64_t>(p.sc, 4 * sink->pairs) : p.sc;
+  for (int64_t c0 = 4LL * i0; c0 < cend; c0 += step) {
+    const int nc = (int)std::min<int64_t>(step, cend - c0);
     const int64_t lc0 = c0 - 4LL * i0;
-    for (int cls = 0; cls < (p.NS ? 2 : 1); ++cls) {
+    auto pack = [&](double mirror, int accumulate) {
+      if (sink)
+        launch_pack_block(n, p.rs.p, c0, nc, p.Gc.p, p.Gb.p, c0 / 4, mirror, accumulate, s);
+      else
+        launch_pack(n, p.rs.p, c0, nc, p.Gc.p, dG, mirror, accumulate, s);
+    };
+    for (int cls = 0; do_c && cls < (p.NS ? 2 : 1); ++cls) {
       const int N = cls ? p.NS : p.NL;
       // W_c = V_c C (V_c the symmetric N x N first-half matrix of column c)
       gather_quarter(p, p.C, cls ? p.rowmapS.p : p.rowmapL.p, N, 1, N, N,
@@ -446,8 +479,8 @@ void second_half(qdcb_plan &p, int i0, int i1, double *dG, hipStream_t s) {
       // G_c (+)= Chat^T W_c
       second_quarter(p, cls ? p.ChatS.p : p.ChatL.p, N, cls != 0, nc, s);
     }
-    launch_pack(n, p.rs.p, c0, nc, p.Gc.p, dG, 1.0, 0, s);
-    if (p.gaunt) {
+    if (do_c) pack(1.0, 0);
+    if (do_g) {
       const int NL = p.NL, NS = p.NS;
       for (int K = 0; K < 3; ++K) {
         const int64_t col0 = K * p.G.ldK + lc0;
@@ -458,17 +491,23 @@ void second_half(qdcb_plan &p, int i0, int i1, double *dG, hipStream_t s) {
         gather_quarter(p, p.G, p.rowmapLS.p, 1, NS, NS, NL, p.CallL.p, col0, nc, s);
         second_quarter(p, p.BhatK[K].p, NS, true, nc, s);
       }
-      launch_pack(n, p.rs.p, c0, nc, p.Gc.p, dG, -1.0, 1, s);
+      pack(-1.0, do_c ? 1 : 0);
     }
     HIPC(hipGetLastError());
+    if (sink) sink->deliver(p, c0 / 4, (c0 + nc) / 4, s);
   }
 }
 
 // Enqueue one whole transformation of device inputs into device G.
 void enqueue(qdcb_plan &p, const double *dCL, const double *dCS, double *dG, bool captured,
-             StageTimer &tm, hipStream_t s) {
-  std::vector<Space *> spaces{&p.C};
-  if (p.gaunt) spaces.push_back(&p.G);
+             StageTimer &tm, hipStream_t s, int classes = CLS_COULOMB | CLS_GAUNT,
+             BlockSink *sink = nullptr) {
+  std::vector<Space *> spaces;
+  if (classes & CLS_COULOMB) spaces.push_back(&p.C);
+  else launch_zero_u64(p.C.kept.p, 4, s);
+  if (p.gaunt && (classes & CLS_GAUNT)) spaces.push_back(&p.G);
+  else if (p.gaunt) launch_zero_u64(p.G.kept.p, 4, s);
+  p.classes = classes;
   p.tiles_made = 0;
   for (Space *sp : spaces) {
     tm.begin(ST_DENS);
@@ -508,7 +547,7 @@ void enqueue(qdcb_plan &p, const double *dCL, const double *dCS, double *dG, boo
       first_half(p, *sp, !resident || i0 == 0, i0 == 0, captured, tm, s);
     }
     tm.begin(ST_SH);
-    second_half(p, i0, i1, dG, s);
+    second_half(p, i0, i1, dG, s, classes, sink);
     tm.end();
   }
 }
@@ -535,22 +574,25 @@ void fill_stats(qdcb_plan &p, qdcb_stats *stats, StageTimer *tm, double ms_total
     stats->kept[c] = (int64_t)kc[c];
     ktot += (double)kc[c];
   }
-  stats->total[0] = p.nLL * p.nLL;
-  stats->total[1] = p.nLL * p.nSS;
-  stats->total[2] = p.nSS * p.nLL;
-  stats->total[3] = p.nSS * p.nSS;
+  if (p.classes & CLS_COULOMB) {
+    stats->total[0] = p.nLL * p.nLL;
+    stats->total[1] = p.nLL * p.nSS;
+    stats->total[2] = p.nSS * p.nLL;
+    stats->total[3] = p.nSS * p.nSS;
+  }
   stats->kept_gaunt = (int64_t)kg[0];
-  stats->total_gaunt = p.gaunt ? p.G.P * p.G.P : 0;
+  stats->total_gaunt = p.gaunt && (p.classes & CLS_GAUNT) ? p.G.P * p.G.P : 0;
   stats->tiles_kept = tiles_c + tiles_g;
-  stats->tiles_total =
-      (int64_t)p.C.ntiles * p.C.ntiles + (p.gaunt ? (int64_t)p.G.ntiles * p.G.ntiles : 0);
+  stats->tiles_total = ((p.classes & CLS_COULOMB) ? (int64_t)p.C.ntiles * p.C.ntiles : 0) +
+                       (p.gaunt && (p.classes & CLS_GAUNT) ? (int64_t)p.G.ntiles * p.G.ntiles
+                                                          : 0);
   stats->flops_first_half = 2.0 * (double)p.ncol * ktot + 6.0 * (double)p.ncol * (double)kg[0];
   double f2 = 0;
-  for (int cls = 0; cls < (p.NS ? 2 : 1); ++cls) {
+  for (int cls = 0; (p.classes & CLS_COULOMB) && cls < (p.NS ? 2 : 1); ++cls) {
     double N = cls ? p.NS : p.NL;
     f2 += (8.0 * N * N * n + 32.0 * N * n * n) * (double)p.ncol;
   }
-  if (p.gaunt)
+  if (p.gaunt && (p.classes & CLS_GAUNT))
     f2 += 3.0 * (16.0 * p.NL * (double)p.NS * n + 32.0 * (p.NL + p.NS) * (double)n * n) *
           (double)p.ncol;
   stats->flops_second_half = f2;
@@ -558,9 +600,11 @@ void fill_stats(qdcb_plan &p, qdcb_stats *stats, StageTimer *tm, double ms_total
   stats->n_chunks = nchunks;
   stats->flops_mfma = 2.0 * TILE * TILE * nchunks *
                       ((double)p.C.ld * tiles_c + (p.gaunt ? (double)p.G.ld * tiles_g : 0.0));
+  stats->classes = p.classes;
   if (p.desc.prec == QDCB_PREC_MIXED) {
     for (Space *sp : {&p.C, &p.G}) {
-      if (sp == &p.G && !p.gaunt) continue;
+      if (sp == &p.G && !(p.gaunt && (p.classes & CLS_GAUNT))) continue;
+      if (sp == &p.C && !(p.classes & CLS_COULOMB)) continue;
       if (sp->h_tcount.size() != 3 * (size_t)sp->ntiles) continue;
       for (int t = 0; t < 3; ++t)
         for (int b = 0; b < sp->ntiles; ++b)
@@ -579,13 +623,14 @@ void read_counters(qdcb_plan &p, hipStream_t s, unsigned long long kc[4],
 }
 
 void run_eager(qdcb_plan &p, const double *dCL, const double *dCS, double *dG, hipStream_t s,
-               qdcb_stats *stats) {
+               qdcb_stats *stats, int classes = CLS_COULOMB | CLS_GAUNT,
+               BlockSink *sink = nullptr) {
   StageTimer tm(s, true);
   hipEvent_t e0, e1;
   HIPC(hipEventCreate(&e0));
   HIPC(hipEventCreate(&e1));
   HIPC(hipEventRecord(e0, s));
-  enqueue(p, dCL, dCS, dG, false, tm, s);
+  enqueue(p, dCL, dCS, dG, false, tm, s, classes, sink);
   HIPC(hipEventRecord(e1, s));
   unsigned long long kc[4], kg[4];
   read_counters(p, s, kc, kg);
@@ -596,9 +641,23 @@ void run_eager(qdcb_plan &p, const double *dCL, const double *dCS, double *dG, h
   (void)hipEventDestroy(e1);
   p.have_last = true;
   if (stats) {
-    fill_stats(p, stats, &tm, ms, kc, kg, p.C.total, p.gaunt ? p.G.total : 0);
+    fill_stats(p, stats, &tm, ms, kc, kg, (classes & CLS_COULOMB) ? p.C.total : 0,
+               p.gaunt && (classes & CLS_GAUNT) ? p.G.total : 0);
     stats->tiles_made = p.tiles_made;
   }
+}
+
+// Integral classes selected by transform flags.
+int class_mask(const qdcb_plan &p, uint32_t flags) {
+  if (flags & ~(uint32_t)(QDCB_PTR_DEVICE | QDCB_CLASS_COULOMB | QDCB_CLASS_GAUNT))
+    fail(QDCB_E_INVALID, "unknown transform flag");
+  int m = 0;
+  if (flags & QDCB_CLASS_COULOMB) m |= CLS_COULOMB;
+  if (flags & QDCB_CLASS_GAUNT) m |= CLS_GAUNT;
+  if (!m) m = CLS_COULOMB | CLS_GAUNT;
+  if ((m & CLS_GAUNT) && !(m & CLS_COULOMB) && !p.gaunt)
+    fail(QDCB_E_INVALID, "QDCB_CLASS_GAUNT needs a DCG plan");
+  return m;
 }
 
 // Device copies of host inputs (QDCB_PTR_DEVICE unset): CL, CS into the
@@ -634,6 +693,7 @@ qdcb_status qdcb_plan_autotune(qdcb_plan *plan, const double *CL, const double *
   return guarded([&] {
     if (!plan || !CL || !G) fail(QDCB_E_INVALID, "NULL argument");
     qdcb_plan &p = *plan;
+    PlanUse use(p);
     if (p.NS && !CS) fail(QDCB_E_INVALID, "CS is required for this Hamiltonian");
     const char *path = cache_path ? cache_path : std::getenv("QDCB_TUNE_CACHE");
     if (path && !*path) path = nullptr;
@@ -645,7 +705,8 @@ qdcb_status qdcb_plan_autotune(qdcb_plan *plan, const double *CL, const double *
       int32_t found = 0;
       const qdcb_status st = qdcb_tune_cache_lookup(path, p.tune_key.c_str(), &t, &found);
       if (st != QDCB_OK) fail(st, qdcb_last_error());
-      if (found && qdcb_plan_set_tune(plan, &t) == QDCB_OK) {
+      if (found && !tune_problem(p, t)) {
+        p.tune = t;
         rep.chosen = p.tune;
         rep.from_cache = 1;
         if (report) *report = rep;
@@ -707,19 +768,67 @@ qdcb_status qdcb_transform(qdcb_plan *plan, const double *CL, const double *CS, 
   return guarded([&] {
     if (!plan || !CL || !G) fail(QDCB_E_INVALID, "NULL argument");
     qdcb_plan &p = *plan;
+    PlanUse use(p);
     if (p.NS && !CS) fail(QDCB_E_INVALID, "CS is required for this Hamiltonian");
     DeviceGuard g(p.ctx->device);
     hipStream_t s = (hipStream_t)hip_stream;
     const bool dev = flags & QDCB_PTR_DEVICE;
+    const int classes = class_mask(p, flags);
     const int n = p.n;
     const size_t nG = (size_t)n * n * n * n * 16;
     const DevIO io = device_io(p, CL, CS, G, dev, s);
     double *dG = io.G;
-    run_eager(p, io.CL, io.CS, dG, s, stats);
+    run_eager(p, io.CL, io.CS, dG, s, stats, classes);
     if (!dev) {
       HIPC(hipMemcpyAsync(G, dG, nG * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPC(hipStreamSynchronize(s));
     }
+  });
+}
+
+qdcb_status qdcb_transform_blocks(qdcb_plan *plan, const double *CL, const double *CS,
+                                  qdcb_block_cb cb, void *user, uint32_t flags,
+                                  void *hip_stream, qdcb_stats *stats) {
+  return guarded([&] {
+    if (!plan || !CL || !cb) fail(QDCB_E_INVALID, "NULL argument");
+    qdcb_plan &p = *plan;
+    PlanUse use(p);
+    if (p.NS && !CS) fail(QDCB_E_INVALID, "CS is required for this Hamiltonian");
+    DeviceGuard g(p.ctx->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    const bool dev = flags & QDCB_PTR_DEVICE;
+    const int classes = class_mask(p, flags);
+    // block buffer: at most one second-half slice of MO pairs, both (r, s)
+    // and (s, r), within what the context budget leaves
+    const size_t pair_doubles = (size_t)p.n * p.n * 32;
+    int64_t pairs = p.sc / 4;
+    if (p.Gb.n < (size_t)pairs * pair_doubles) {
+      const size_t room = p.ctx->room() + p.Gb.bytes();
+      pairs = std::min<int64_t>(pairs, (int64_t)(room / (pair_doubles * sizeof(double))));
+      if (pairs < 1) fail(QDCB_E_NOMEM, "no room for the block buffer of one MO pair");
+      if (p.Gb.n < (size_t)pairs * pair_doubles) {
+        p.Gb.free();
+        p.Gb.alloc(p.ctx, (size_t)pairs * pair_doubles);
+      }
+    }
+    BlockSink sink;
+    sink.cb = cb;
+    sink.user = user;
+    sink.on_device = dev;
+    sink.pairs = (int64_t)(p.Gb.n / pair_doubles);
+    // the host-pointer path needs device copies of CL and CS only (no G)
+    const double *dCL = CL, *dCS = CS;
+    if (!dev) {
+      check_finite_host(CL, (size_t)4 * p.NL * p.n, "CL");
+      if (p.NS) check_finite_host(CS, (size_t)4 * p.NS * p.n, "CS");
+      HIPC(hipMemcpyAsync(p.CLd.p, CL, p.CLd.bytes(), hipMemcpyHostToDevice, s));
+      dCL = p.CLd.p;
+      if (p.NS) {
+        HIPC(hipMemcpyAsync(p.CSd.p, CS, p.CSd.bytes(), hipMemcpyHostToDevice, s));
+        dCS = p.CSd.p;
+      }
+    }
+    run_eager(p, dCL, dCS, nullptr, s, stats, classes, &sink);
   });
 }
 
@@ -728,6 +837,7 @@ qdcb_status qdcb_plan_capture(qdcb_plan *plan, const double *CL, const double *C
   return guarded([&] {
     if (!plan || !CL || !G || !hip_stream) fail(QDCB_E_INVALID, "NULL argument");
     qdcb_plan &p = *plan;
+    PlanUse use(p);
     if (p.NS && !CS) fail(QDCB_E_INVALID, "CS is required for this Hamiltonian");
     DeviceGuard g(p.ctx->device);
     hipStream_t s = (hipStream_t)hip_stream;
@@ -771,6 +881,7 @@ qdcb_status qdcb_plan_replay(qdcb_plan *plan, void *hip_stream, qdcb_stats *stat
   return guarded([&] {
     if (!plan) fail(QDCB_E_INVALID, "NULL argument");
     qdcb_plan &p = *plan;
+    PlanUse use(p);
     if (!p.graph_exec) fail(QDCB_E_INVALID, "no captured transform (call qdcb_plan_capture)");
     DeviceGuard g(p.ctx->device);
     hipStream_t s = (hipStream_t)hip_stream;

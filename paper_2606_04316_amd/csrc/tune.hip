@@ -10,15 +10,20 @@
 
 using namespace qdcb;
 
-namespace {
+namespace qdcb {
 
-void check_tune(const qdcb_plan &p, const qdcb_tune &t) {
-  if (t.eri_sched != 0 && t.eri_sched != 1) fail(QDCB_E_INVALID, "eri_sched must be 0 or 1");
-  if (t.fh_order != 0 && t.fh_order != 1) fail(QDCB_E_INVALID, "fh_order must be 0 or 1");
-  if (t.sq_tile != 64 && t.sq_tile != 128) fail(QDCB_E_INVALID, "sq_tile must be 64 or 128");
-  if (t.sq_tile == 128 && p.n % 2) fail(QDCB_E_INVALID, "sq_tile 128 needs an even n_mo");
-  if (t.reserved != 0) fail(QDCB_E_INVALID, "reserved must be 0");
+const char *tune_problem(const qdcb_plan &p, const qdcb_tune &t) {
+  if (t.eri_sched != 0 && t.eri_sched != 1) return "eri_sched must be 0 or 1";
+  if (t.fh_order != 0 && t.fh_order != 1) return "fh_order must be 0 or 1";
+  if (t.sq_tile != 64 && t.sq_tile != 128) return "sq_tile must be 64 or 128";
+  if (t.sq_tile == 128 && p.n % 2) return "sq_tile 128 needs an even n_mo";
+  if (t.reserved != 0) return "reserved must be 0";
+  return nullptr;
 }
+
+}  // namespace qdcb
+
+namespace {
 
 bool key_ok(const char *k) {
   for (; *k; ++k)
@@ -40,7 +45,8 @@ extern "C" {
 qdcb_status qdcb_plan_set_tune(qdcb_plan *p, const qdcb_tune *t) {
   return guarded([&] {
     if (!p || !t) fail(QDCB_E_INVALID, "NULL argument");
-    check_tune(*p, *t);
+    PlanUse use(*p);
+    if (const char *why = tune_problem(*p, *t)) fail(QDCB_E_INVALID, why);
     p->tune = *t;
   });
 }

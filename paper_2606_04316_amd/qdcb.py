@@ -20,11 +20,15 @@ LIB_PATH = os.path.join(HERE, "libqdcb.so")
 HAM = {"LL": 0, "DC": 1, "DCG": 2}
 PREC = {"fp64": 0, "mixed": 1}
 PTR_DEVICE = 0x1
+CLASS_COULOMB = 0x2
+CLASS_GAUNT = 0x4
+CLASSES = {None: 0, "all": 0, "coulomb": CLASS_COULOMB, "gaunt": CLASS_GAUNT}
 FETCH_DMAX, FETCH_Q, FETCH_DMAX_GAUNT, FETCH_Q_GAUNT = 1, 2, 3, 4
 PLAN_DIRECTED_TILES = 0x1
 PLAN_TIER_BY_G = 0x2
 
-STATUS = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_UNSUPPORTED"}
+STATUS = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_UNSUPPORTED",
+          -5: "E_BUSY", -6: "E_ABORTED"}
 
 
 class QdcbError(RuntimeError):
@@ -50,7 +54,8 @@ class Stats(ctypes.Structure):
                 ("flops_mfma", ctypes.c_double), ("n_batches", ctypes.c_int32),
                 ("n_chunks", ctypes.c_int32), ("graph_replay", ctypes.c_int32),
                 ("graph_fallback", ctypes.c_int32), ("tiles_made", ctypes.c_int64),
-                ("tiles_tier", ctypes.c_int64 * 3), ("ms_tier", ctypes.c_double * 3)]
+                ("tiles_tier", ctypes.c_int64 * 3), ("ms_tier", ctypes.c_double * 3),
+                ("classes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         d = {}
@@ -79,6 +84,9 @@ class TuneReport(ctypes.Structure):
                 "ms_first_half": list(self.ms_first_half),
                 "ms_second_half": list(self.ms_second_half)}
 
+
+BLOCK_CB = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                            ctypes.c_void_p, ctypes.c_int)
 
 _lib = None
 _P = ctypes.c_void_p
@@ -120,6 +128,8 @@ def lib():
         L.qdcb_plan_capture.argtypes = [_P, _P, _P, _P, _P]
         L.qdcb_plan_replay.argtypes = [_P, _P, ctypes.POINTER(Stats)]
         L.qdcb_plan_fetch_v.argtypes = [_P, _P, ctypes.c_int64, _P]
+        L.qdcb_transform_blocks.argtypes = [_P, _P, _P, BLOCK_CB, _P, ctypes.c_uint32, _P,
+                                            ctypes.POINTER(Stats)]
         L.qdcb_plan_set_tune.argtypes = [_P, ctypes.POINTER(Tune)]
         L.qdcb_plan_get_tune.argtypes = [_P, ctypes.POINTER(Tune)]
         L.qdcb_plan_tune_key.argtypes = [_P, ctypes.c_char_p, ctypes.c_size_t]
@@ -134,7 +144,8 @@ def lib():
                   "qdcb_transform", "qdcb_plan_fetch", "qdcb_plan_estimate",
                   "qdcb_plan_capture", "qdcb_plan_replay", "qdcb_plan_fetch_v",
                   "qdcb_plan_set_tune", "qdcb_plan_get_tune", "qdcb_plan_tune_key",
-                  "qdcb_tune_cache_lookup", "qdcb_tune_cache_store", "qdcb_plan_autotune"):
+                  "qdcb_tune_cache_lookup", "qdcb_tune_cache_store", "qdcb_plan_autotune",
+                  "qdcb_transform_blocks"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -253,11 +264,13 @@ class Plan:
                                         ctypes.byref(b)))
         return int(b.value)
 
-    def transform(self, CL, CS=None, G=None, stream=None):
+    def transform(self, CL, CS=None, G=None, stream=None, classes=None):
         """Returns (G, stats).  numpy inputs use the host path; torch CUDA
-        tensors the device path (G must then be a CUDA float64 tensor or None)."""
+        tensors the device path (G must then be a CUDA float64 tensor or None).
+        classes: None (all), "coulomb" or "gaunt"."""
         n = self.n
         st = Stats()
+        cf = CLASSES[classes]
         if _is_torch_cuda(CL):
             import torch
             if G is None:
@@ -269,7 +282,7 @@ class Plan:
                 stream = torch.cuda.current_stream(CL.device).cuda_stream
             _check(lib().qdcb_transform(self.h, CL.data_ptr(),
                                         CS.data_ptr() if CS is not None else None,
-                                        G.data_ptr(), PTR_DEVICE, stream, ctypes.byref(st)))
+                                        G.data_ptr(), PTR_DEVICE | cf, stream, ctypes.byref(st)))
             return G, st.as_dict()
         CLh = _f64(CL)
         CSh = _f64(CS) if CS is not None else None
@@ -277,8 +290,54 @@ class Plan:
             G = np.empty((n, n, n, n, 4, 4))
         _check(lib().qdcb_transform(self.h, CLh.ctypes.data,
                                     CSh.ctypes.data if CSh is not None else None,
-                                    G.ctypes.data, 0, stream, ctypes.byref(st)))
+                                    G.ctypes.data, cf, stream, ctypes.byref(st)))
         return G, st.as_dict()
+
+    def transform_blocks(self, CL, CS, callback, stream=None, classes=None):
+        """Blocked output: callback(i0, i1, B) for consecutive blocks of MO pairs
+        (r <= s, r outer).  numpy inputs: B is a host array [i1 - i0][n][n][2][4][4]
+        (a view valid during the call; [..., 0, :, :] = G_pqrs, [..., 1, :, :] =
+        G_pqsr).  torch CUDA inputs: B is the integer device address of that
+        array.  A truthy return value stops the transformation (QdcbError
+        E_ABORTED).  Returns stats."""
+        n = self.n
+        st = Stats()
+        cf = CLASSES[classes]
+        dev = _is_torch_cuda(CL)
+        err = []
+
+        def cb(user, i0, i1, ptr, on_device):
+            try:
+                if on_device:
+                    stop = callback(int(i0), int(i1), int(ptr))
+                else:
+                    cnt = (i1 - i0) * n * n * 32
+                    arr = np.ctypeslib.as_array(ctypes.cast(ptr, _DP), shape=(cnt,))
+                    stop = callback(int(i0), int(i1), arr.reshape(i1 - i0, n, n, 2, 4, 4))
+                return 1 if stop else 0
+            except BaseException as e:  # reported after the call
+                err.append(e)
+                return 1
+
+        fn = BLOCK_CB(cb)
+        if dev:
+            import torch
+            if stream is None:
+                stream = torch.cuda.current_stream(CL.device).cuda_stream
+            st_code = lib().qdcb_transform_blocks(self.h, CL.data_ptr(),
+                                                  CS.data_ptr() if CS is not None else None,
+                                                  fn, None, PTR_DEVICE | cf, stream,
+                                                  ctypes.byref(st))
+        else:
+            CLh = _f64(CL)
+            CSh = _f64(CS) if CS is not None else None
+            st_code = lib().qdcb_transform_blocks(self.h, CLh.ctypes.data,
+                                                  CSh.ctypes.data if CSh is not None else None,
+                                                  fn, None, cf, stream, ctypes.byref(st))
+        if err:
+            raise err[0]
+        _check(st_code)
+        return st.as_dict()
 
     @property
     def tune(self) -> dict:

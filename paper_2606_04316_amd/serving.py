@@ -100,7 +100,10 @@ class Server:
                 r.result = self.executor(r, slot)
             except Exception as e:  # reported per request
                 r.error = f"{type(e).__name__}: {e}"
-            r.t_done = time.perf_counter() - t0
+            # the result is delivered when the executor says so (e.g. G on the
+            # host), before any bookkeeping it does afterwards
+            t_res = r.result.get("t_result") if isinstance(r.result, dict) else None
+            r.t_done = (t_res if t_res is not None else time.perf_counter()) - t0
             with self._lock:
                 self._in_use -= r.reserve
                 self._running -= 1
@@ -153,9 +156,12 @@ def basis_key(b) -> str:
 class GpuExecutor:
     """Runs requests through the C ABI: a resident basis cache, one plan and
     one HIP stream (torch) per request, the plan created in a context whose
-    budget is the request's reservation."""
+    budget is the request's reservation.  ``prec="mixed"`` runs every plan
+    with the reduced-precision tiers (``tiers`` = tier_fp32, tier_bf16, plan
+    flags)."""
 
-    def __init__(self, slots: int, device: int = 0, keep_outputs: bool = False):
+    def __init__(self, slots: int, device: int = 0, keep_outputs: bool = False,
+                 prec: str = "fp64", tiers=(1e-6, 1e-9, 0x2)):
         import torch
         from paper_2606_04316_amd import qdcb
         self.torch = torch
@@ -167,6 +173,8 @@ class GpuExecutor:
         self.bases: Dict[str, object] = {}
         self.block = threading.Lock()
         self.keep_outputs = keep_outputs
+        self.prec = prec
+        self.tiers = tiers
 
     def basis(self, b):
         k = basis_key(b)
@@ -179,7 +187,7 @@ class GpuExecutor:
         s = r.system
         L = self.basis(s.L)
         S = self.basis(s.S) if s.S is not None else None
-        return self.qdcb.Plan.estimate(L, S, s.ham, s.n_mo, s.tau)
+        return self.qdcb.Plan.estimate(L, S, s.ham, s.n_mo, s.tau, prec=self.prec)
 
     def __call__(self, r: Request, slot: int):
         torch, qdcb = self.torch, self.qdcb
@@ -189,15 +197,22 @@ class GpuExecutor:
         ctx = qdcb.Context(self.device, budget_bytes=r.reserve)
         stream = self.streams[slot]
         with torch.cuda.stream(stream):
-            plan = qdcb.Plan(ctx, L, S, s.ham, s.n_mo, s.tau)
+            if self.prec == "mixed":
+                t32, t16, flags = self.tiers
+                plan = qdcb.Plan(ctx, L, S, s.ham, s.n_mo, s.tau, prec="mixed",
+                                 tier_fp32=t32, tier_bf16=t16, flags=flags)
+            else:
+                plan = qdcb.Plan(ctx, L, S, s.ham, s.n_mo, s.tau)
             CL = torch.from_numpy(s.CL).to(self.dev, non_blocking=False)
             CS = torch.from_numpy(s.CS).to(self.dev) if s.CS is not None else None
             n = s.n_mo
             G = torch.empty((n, n, n, n, 4, 4), dtype=torch.float64, device=self.dev)
             G, st = plan.transform(CL, CS, G, stream=stream.cuda_stream)
             stream.synchronize()
-        digest = hashlib.sha1(G.cpu().numpy().tobytes()).hexdigest()
-        out = {"digest": digest, "n": n, "ms_gpu": st["ms_total"],
+        Gh = G.cpu().numpy()
+        t_result = time.perf_counter()  # G is on the host: the request is served
+        digest = hashlib.sha1(Gh.tobytes()).hexdigest()
+        out = {"digest": digest, "n": n, "ms_gpu": st["ms_total"], "t_result": t_result,
                "flops": st["flops_first_half"] + st["flops_second_half"]}
         if self.keep_outputs:
             out["G"] = G

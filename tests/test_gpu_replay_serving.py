@@ -52,18 +52,22 @@ def test_graph_replays_equal_eager(q, ham, budget_mb):
         print(f"fallbacks at {budget_mb} MB: {fallbacks}")
 
 
-def test_served_requests_equal_alone(q):
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_served_requests_equal_alone(q, prec):
     from paper_2606_04316_amd import serving
     reqs = serving.request_stream(12, seed=7, mean_gap_s=0.005, pool=4, atoms=(3, 6),
                                   nl=(6, 24), n_mo=(2, 6), radius_scale=8.0)
-    ex = serving.GpuExecutor(slots=3)
+    # mixed: every tile in a reduced tier (FP32, BF16 below 1e-3), so that the
+    # reduced-precision kernels run in the mix
+    tiers = (1e300, 1e-3, 0)
+    ex = serving.GpuExecutor(slots=3, prec=prec, tiers=tiers)
     srv = serving.Server(ex, ex.reserve, slots=3, budget_bytes=8 << 30)
     out = srv.run(reqs)
     assert all(r.error is None for r in out), [r.error for r in out if r.error]
     summ = serving.summarize(out)
     assert summ["failed"] == 0 and summ["p99_ms"] >= summ["p50_ms"] > 0
     # the same requests one at a time, nothing else on the device
-    alone_ex = serving.GpuExecutor(slots=1)
+    alone_ex = serving.GpuExecutor(slots=1, prec=prec, tiers=tiers)
     for r in out[:8]:
         solo = serving.Request(rid=r.rid, system=r.system, arrival=0.0)
         solo.reserve = alone_ex.reserve(solo)
