@@ -340,14 +340,16 @@ def main_serving(args):
         budget = int(0.5 * torch.cuda.mem_get_info()[0])
         srv = serving.Server(ex, ex.reserve, slots=args.slots, budget_bytes=budget)
         out = srv.run(reqs)
+        ex.drain()
         summ = serving.summarize(out)
         print(f"serving {prec}: {summ}", file=sys.stderr, flush=True)
         alone = serving.GpuExecutor(slots=1, prec=prec)
         same = 0
-        for r in out[:: max(1, len(out) // 8)][:8]:
+        for r in [r for r in out if r.error is None][:: max(1, len(out) // 8)][:8]:
             solo = serving.Request(rid=r.rid, system=r.system, arrival=0.0)
             solo.reserve = alone.reserve(solo)
             same += alone(solo, 0)["digest"] == r.result["digest"]
+        alone.drain()
         summ.update({"max_concurrency": srv.max_concurrency,
                      "peak_reserved_GB": srv.peak_in_use / 2 ** 30,
                      "alone_equals_mix": f"{same}/8"})

@@ -271,7 +271,7 @@ qdcb_status qdcb_plan_fetch_v(const qdcb_plan *plan, const int64_t *pairs, int64
  *              1: plain order, bra-tile pairs fastest.
  *   sq_tile    64 or 128: edge of the output tiles of the second half's second
  *              quarter (G_c = conj(C)^T W_c); 128 requires an even n_mo.
- * A new plan starts from eri_sched 0, fh_order 0 and sq_tile 128 when n_mo is
+ * A new plan starts from eri_sched 1, fh_order 0 and sq_tile 128 when n_mo is
  * even and at least 128, else 64. */
 typedef struct {
     int32_t eri_sched;

@@ -51,8 +51,9 @@ __device__ __forceinline__ double coulomb_kernel(double ip, double px, double py
 }
 
 // Boys F0 by Taylor expansion about a grid: T_i = i / 8 (i = 0 .. BOYS_N - 1,
-// T < 36), tab[8 i + k] = (-1)^k F_k(T_i) / k!, so that for |d| <= 1/16
-//   F0(T_i + d) = sum_k tab[8 i + k] d^k  (k <= 7),
+// T < 36), tab[8 i + k] = (2 / sqrt(pi)) (-1)^k F_k(T_i) / k!, so that for
+// |d| <= 1/16
+//   (2 / sqrt(pi)) F0(T_i + d) = sum_k tab[8 i + k] d^k  (k <= 7),
 // remainder below F_8(T_i) (1/16)^8 / 8! < 3e-16 relative.  For T >= 36
 // erf(sqrt T) = 1 to double precision and the kernel is 1 / R.  Same value
 // as coulomb_kernel, without the range branches of erf.
@@ -62,24 +63,34 @@ constexpr double BOYS_TMAX = 36.0;
 // stay 16-byte aligned and rows i, i' share banks only when i = i' mod 16)
 constexpr int BOYS_LD = 10;
 
+// 1/sqrt(x) for finite x > 0: the hardware estimate y and one second-order
+// correction from the binomial series, y (1 + e/2 + 3 e^2/8), e = 1 - x y^2.
+__device__ __forceinline__ double rsqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
 template <int LD = 8>
 __device__ __forceinline__ double coulomb_kernel_tab(const double *tab, double ip, double px,
                                                      double py, double pz, double iq, double qx,
                                                      double qy, double qz) {
-  const double t = ip + iq;  // 1/rho
-  const double sr = rsqrt(t);
+  const double t = ip + iq;  // 1/rho > 0
+  const double sr = rsqrt_pos(t);
   const double dx = px - qx, dy = py - qy, dz = pz - qz;
   const double r2 = dx * dx + dy * dy + dz * dz;
   const double T = r2 * (sr * sr);
   if (T < BOYS_TMAX) {
-    const int i = (int)rint(T * 8.0);
-    const double d = T - 0.125 * i;
+    const int i = (int)fma(T, 8.0, 0.5);  // nearest grid point (T >= 0)
+    const double d = fma(-0.125, (double)i, T);
     const double *c = tab + LD * i;
     double f = c[7];
 #pragma unroll
     for (int k = 6; k >= 0; --k) f = fma(f, d, c[k]);
-    return TWO_OVER_SQRTPI * sr * f;
+    return sr * f;  // the table carries the factor 2 / sqrt(pi)
   }
+  // far field, 1/R: the library rsqrt, whose longer sequence the compiler
+  // keeps behind a branch that wavefronts without such lanes skip
   return rsqrt(r2);
 }
 

@@ -98,7 +98,7 @@ void build_space(qdcb_ctx *ctx, Space &sp, std::vector<RowSrc> &rows,
   sp.overflow.alloc(ctx, 1);
 }
 
-// Taylor table of the Boys function, tab[8 i + k] = (-1)^k F_k(T_i) / k! at
+// Taylor table of the Boys function, tab[8 i + k] = (2/sqrt(pi)) (-1)^k F_k(T_i) / k! at
 // T_i = i / 8: F_7 from its series e^-T sum_j (2T)^j / ((2m+1)(2m+3)...(2m+2j+1)),
 // then the stable downward recursion F_{m-1} = (2 T F_m + e^-T) / (2m - 1),
 // in long double.
@@ -115,10 +115,12 @@ std::vector<double> boys_table() {
     long double F[8];
     F[7] = eT * sum;
     for (int m = 7; m >= 1; --m) F[m - 1] = (2.0L * T * F[m] + eT) / (2.0L * m - 1.0L);
+    // scaled by 2 / sqrt(pi), the factor of the kernel erf(sqrt(rho) R) / R
+    const long double two_over_sqrtpi = 2.0L / sqrtl(3.14159265358979323846264338327950288L);
     long double fact = 1.0L;
     for (int k = 0; k < 8; ++k) {
       if (k) fact *= k;
-      tab[(size_t)8 * i + k] = (double)((k & 1 ? -F[k] : F[k]) / fact);
+      tab[(size_t)8 * i + k] = (double)(two_over_sqrtpi * (k & 1 ? -F[k] : F[k]) / fact);
     }
   }
   return tab;
@@ -414,7 +416,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
     }
     // --- launch choices and the shape key of the tuning cache
     HIPC(hipDeviceGetAttribute(&p.n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
-    p.tune.eri_sched = 0;
+    p.tune.eri_sched = 1;  // faster or equal on every workload measured
     p.tune.fh_order = 0;
     p.tune.sq_tile = (p.n % 2 == 0 && p.n >= 128) ? 128 : 64;
     {

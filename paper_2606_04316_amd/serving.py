@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import dataclasses
 import hashlib
+import queue
 import threading
 import time
 from typing import Callable, Dict, List, Optional
@@ -61,6 +62,11 @@ class Server:
         self.max_concurrency = 0
         self._running = 0
 
+    def _release_memory(self, r: Request):
+        with self._lock:
+            self._in_use -= r.reserve
+            self._lock.notify_all()
+
     def _try_admit(self) -> List[tuple]:
         """Admissions possible now (called with the lock held)."""
         out = []
@@ -95,6 +101,13 @@ class Server:
         t0 = time.perf_counter()
         threads = []
 
+        # an executor that frees device memory after returning (deferred
+        # release) reports each request's release through on_release; its
+        # reservation stays counted until then
+        deferred = bool(getattr(self.executor, "deferred_release", False))
+        if deferred:
+            self.executor.on_release = self._release_memory
+
         def work(r: Request, slot: int):
             try:
                 r.result = self.executor(r, slot)
@@ -105,7 +118,8 @@ class Server:
             t_res = r.result.get("t_result") if isinstance(r.result, dict) else None
             r.t_done = (t_res if t_res is not None else time.perf_counter()) - t0
             with self._lock:
-                self._in_use -= r.reserve
+                if not deferred:
+                    self._in_use -= r.reserve
                 self._running -= 1
                 self._free_slots.append(slot)
                 self._free_slots.sort()
@@ -158,7 +172,14 @@ class GpuExecutor:
     one HIP stream (torch) per request, the plan created in a context whose
     budget is the request's reservation.  ``prec="mixed"`` runs every plan
     with the reduced-precision tiers (``tiers`` = tier_fp32, tier_bf16, plan
-    flags)."""
+    flags).
+
+    G comes to the host through a pinned staging buffer per slot (reused, so
+    a result is delivered as the digest of that copy, or as the device tensor
+    with keep_outputs).  Finished plans and their contexts are destroyed by a
+    background thread: freeing device memory waits for the work of every
+    stream on the device, which would otherwise hold the slot until the other
+    slots' transforms finish.  ``drain()`` waits for those releases."""
 
     def __init__(self, slots: int, device: int = 0, keep_outputs: bool = False,
                  prec: str = "fp64", tiers=(1e-6, 1e-9, 0x2)):
@@ -175,6 +196,43 @@ class GpuExecutor:
         self.keep_outputs = keep_outputs
         self.prec = prec
         self.tiers = tiers
+        self.staging = [None] * slots  # pinned host buffers for G, per slot
+        self._retire: "queue.Queue" = queue.Queue()
+        self._reaper = threading.Thread(target=self._reap, daemon=True)
+        self._reaper.start()
+
+    # the request loop counts a request's reservation until its plan is gone
+    deferred_release = True
+    on_release = None
+
+    def _reap(self):
+        while True:
+            plan, ctx, r = self._retire.get()
+            try:
+                if plan is not None:
+                    plan.close()
+                if ctx is not None:
+                    ctx.close()
+            finally:
+                if self.on_release is not None:
+                    self.on_release(r)
+                self._retire.task_done()
+
+    def drain(self):
+        """Wait until every finished plan has been destroyed."""
+        self._retire.join()
+
+    def _host_copy(self, G, slot: int, stream):
+        torch = self.torch
+        buf = self.staging[slot]
+        if buf is None or buf.numel() < G.numel():
+            buf = torch.empty(G.numel(), dtype=torch.float64, pin_memory=True)
+            self.staging[slot] = buf
+        h = buf[:G.numel()].view(G.shape)
+        with torch.cuda.stream(stream):
+            h.copy_(G, non_blocking=True)
+        stream.synchronize()
+        return h.numpy()
 
     def basis(self, b):
         k = basis_key(b)
@@ -190,11 +248,18 @@ class GpuExecutor:
         return self.qdcb.Plan.estimate(L, S, s.ham, s.n_mo, s.tau, prec=self.prec)
 
     def __call__(self, r: Request, slot: int):
+        held = {}  # the request's context and plan, destroyed by the reaper
+        try:
+            return self._run_request(r, slot, held)
+        finally:
+            self._retire.put((held.get("plan"), held.get("ctx"), r))
+
+    def _run_request(self, r: Request, slot: int, held: dict):
         torch, qdcb = self.torch, self.qdcb
         s = r.system
         L = self.basis(s.L)
         S = self.basis(s.S) if s.S is not None else None
-        ctx = qdcb.Context(self.device, budget_bytes=r.reserve)
+        ctx = held["ctx"] = qdcb.Context(self.device, budget_bytes=r.reserve)
         stream = self.streams[slot]
         with torch.cuda.stream(stream):
             if self.prec == "mixed":
@@ -203,21 +268,19 @@ class GpuExecutor:
                                  tier_fp32=t32, tier_bf16=t16, flags=flags)
             else:
                 plan = qdcb.Plan(ctx, L, S, s.ham, s.n_mo, s.tau)
+            held["plan"] = plan
             CL = torch.from_numpy(s.CL).to(self.dev, non_blocking=False)
             CS = torch.from_numpy(s.CS).to(self.dev) if s.CS is not None else None
             n = s.n_mo
             G = torch.empty((n, n, n, n, 4, 4), dtype=torch.float64, device=self.dev)
             G, st = plan.transform(CL, CS, G, stream=stream.cuda_stream)
-            stream.synchronize()
-        Gh = G.cpu().numpy()
+        Gh = self._host_copy(G, slot, stream)
         t_result = time.perf_counter()  # G is on the host: the request is served
         digest = hashlib.sha1(Gh.tobytes()).hexdigest()
         out = {"digest": digest, "n": n, "ms_gpu": st["ms_total"], "t_result": t_result,
                "flops": st["flops_first_half"] + st["flops_second_half"]}
         if self.keep_outputs:
             out["G"] = G
-        plan.close()
-        ctx.close()
         return out
 
 
@@ -253,12 +316,21 @@ def request_stream(count: int, seed: int = 5, mean_gap_s: float = 0.02, pool: in
 
 
 def summarize(reqs: List[Request]) -> dict:
+    errors = sorted({r.error for r in reqs if r.error is not None})[:3]
     lat = np.array([r.latency_ms for r in reqs if r.error is None])
     done = [r for r in reqs if r.error is None]
     span = max(r.t_done for r in reqs) - min(r.arrival for r in reqs) if reqs else 0.0
     mo = sum(r.system.n_mo ** 4 for r in done)
+    wait = np.array([1e3 * (r.t_admit - r.arrival) for r in done])
+    serve = np.array([1e3 * (r.t_done - r.t_admit) for r in done])
+    gpu = np.array([r.result["ms_gpu"] for r in done
+                    if isinstance(r.result, dict) and "ms_gpu" in r.result])
     return {"requests": len(reqs), "failed": sum(r.error is not None for r in reqs),
             "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
             "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
             "mean_ms": float(lat.mean()) if lat.size else None,
-            "span_s": span, "mo_integrals_per_s": mo / span if span > 0 else None}
+            "mean_wait_ms": float(wait.mean()) if wait.size else None,
+            "mean_service_ms": float(serve.mean()) if serve.size else None,
+            "mean_transform_ms": float(gpu.mean()) if gpu.size else None,
+            "span_s": span, "mo_integrals_per_s": mo / span if span > 0 else None,
+            "errors": errors}

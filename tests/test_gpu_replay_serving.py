@@ -63,6 +63,7 @@ def test_served_requests_equal_alone(q, prec):
     ex = serving.GpuExecutor(slots=3, prec=prec, tiers=tiers)
     srv = serving.Server(ex, ex.reserve, slots=3, budget_bytes=8 << 30)
     out = srv.run(reqs)
+    ex.drain()
     assert all(r.error is None for r in out), [r.error for r in out if r.error]
     summ = serving.summarize(out)
     assert summ["failed"] == 0 and summ["p99_ms"] >= summ["p50_ms"] > 0
@@ -73,3 +74,4 @@ def test_served_requests_equal_alone(q, prec):
         solo.reserve = alone_ex.reserve(solo)
         res = alone_ex(solo, 0)
         assert res["digest"] == r.result["digest"], r.rid
+    alone_ex.drain()

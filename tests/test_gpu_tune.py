@@ -116,7 +116,7 @@ def test_invalid_choices_are_rejected(q, ctx):
     for bad in ({"sq_tile": 128}, {"sq_tile": 96}, {"eri_sched": 2}, {"fh_order": -1}):
         with pytest.raises(q.QdcbError):
             plan.tune = bad
-    assert plan.tune == {"eri_sched": 0, "fh_order": 0, "sq_tile": 64}
+    assert plan.tune == {"eri_sched": 1, "fh_order": 0, "sq_tile": 64}
 
 
 def test_replays_with_persistent_schedule_equal_eager(q):

@@ -76,3 +76,41 @@ def test_executor_errors_are_reported_per_request():
     out = Server(bad, lambda r: 1, slots=2, budget_bytes=10).run(reqs)
     assert out[1].error and "boom" in out[1].error
     assert out[0].error is None and out[2].error is None
+
+
+class DeferredExec(FakeExec):
+    """Frees a request's memory some time after returning, from another thread,
+    and reports it through on_release (as the GPU executor does)."""
+    deferred_release = True
+    on_release = None
+
+    def __call__(self, r, slot):
+        with self.lock:
+            self.in_use += r.reserve
+            self.running += 1
+            self.peak = max(self.peak, self.in_use)
+            self.peak_running = max(self.peak_running, self.running)
+        time.sleep(0.01)
+        with self.lock:
+            self.running -= 1
+
+        def later():
+            time.sleep(0.03)
+            with self.lock:
+                self.in_use -= r.reserve
+            self.on_release(r)
+
+        threading.Thread(target=later, daemon=True).start()
+        return {"digest": str(r.rid)}
+
+
+def test_deferred_release_keeps_memory_counted_until_freed():
+    fx = DeferredExec(100)
+    reqs = [Request(rid=i, system=30 + (i * 13) % 40, arrival=0.002 * i) for i in range(30)]
+    srv = Server(fx, fx.reserve, slots=4, budget_bytes=100)
+    out = srv.run(reqs)
+    assert all(r.error is None for r in out)
+    # memory still being freed after a request returned counted against the budget
+    assert fx.peak <= 100 and srv.peak_in_use <= 100
+    time.sleep(0.1)
+    assert fx.in_use == 0 and srv._in_use == 0
