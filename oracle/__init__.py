@@ -80,6 +80,11 @@ def lib():
         L.orc_first_half_rows.restype = ctypes.c_int
         L.orc_first_half_rows.argtypes = [bp, bp, dp, dp, ctypes.c_int, ctypes.c_int,
                                           ctypes.c_double, ctypes.c_void_p, ctypes.c_int64, dp]
+        L.orc_transform_spinor_def.restype = ctypes.c_int
+        L.orc_transform_spinor_def.argtypes = [bp, bp, dp, dp, ctypes.c_int, ctypes.c_int, dp]
+        L.orc_transform_spinor_direct.restype = ctypes.c_int
+        L.orc_transform_spinor_direct.argtypes = [bp, bp, dp, dp, ctypes.c_int, ctypes.c_int,
+                                                  ctypes.c_double, dp, ctypes.POINTER(Stats)]
         L.orc_num_bra_pairs.restype = ctypes.c_int64
         L.orc_num_bra_pairs.argtypes = [bp, bp, ctypes.c_int]
         _lib = L
@@ -181,6 +186,35 @@ def transform_def(L, S, CL, CS, ham: str = "LL", return_spinor: bool = False):
     if return_spinor:
         return G, sp[..., 0] + 1j * sp[..., 1], im.value
     return G, im.value
+
+
+def transform_spinor_def(L, S, CL, CS, ham: str = "LL") -> np.ndarray:
+    """General two-spinor input (planes [4][N][m]: alpha re, alpha im, beta re,
+    beta im): unscreened definition route, complex (ab|cd) [m]^4."""
+    bl, bs, CL, CS = _prep(L, S, CL, CS)
+    m = CL.shape[2]
+    sp = np.zeros((m,) * 4 + (2,))
+    rc = lib().orc_transform_spinor_def(bl.ref, bs.ref if bs else None, _dp(CL),
+                                        _dp(CS) if CS is not None else None, m, HAMS[ham],
+                                        _dp(sp))
+    if rc != 0:
+        raise ValueError("orc_transform_spinor_def rejected the problem")
+    return sp[..., 0] + 1j * sp[..., 1]
+
+
+def transform_spinor(L, S, CL, CS, ham: str = "LL", tau: float = 0.0):
+    """General two-spinor input: the paper's direct route with screening;
+    returns (complex (ab|cd) [m]^4, stats)."""
+    bl, bs, CL, CS = _prep(L, S, CL, CS)
+    m = CL.shape[2]
+    sp = np.zeros((m,) * 4 + (2,))
+    st = Stats()
+    rc = lib().orc_transform_spinor_direct(bl.ref, bs.ref if bs else None, _dp(CL),
+                                           _dp(CS) if CS is not None else None, m, HAMS[ham],
+                                           float(tau), _dp(sp), ctypes.byref(st))
+    if rc != 0:
+        raise ValueError("orc_transform_spinor_direct rejected the problem")
+    return sp[..., 0] + 1j * sp[..., 1], st.as_dict()
 
 
 def transform_direct(L, S, CL, CS, ham: str = "LL", tau: float = 0.0, rows=None,

@@ -93,11 +93,28 @@ def spinor4(CL, CS):
     return c4
 
 
-def spinor_integrals(L, S, CL, CS, ham: str) -> np.ndarray:
-    """(ab|cd) as one sum over all AO and spinor indices."""
+def spinor4_general(CL, CS):
+    """Four-spinor coefficients c4[f, w, a] of general spinors given as planes
+    [4][N][m] (alpha re, alpha im, beta re, beta im)."""
+    m = CL.shape[2]
+    NL = CL.shape[1]
+    NS = CS.shape[1] if CS is not None else 0
+    c4 = np.zeros((NL + NS, 4, m), dtype=complex)
+    c4[:NL, 0] = CL[0] + 1j * CL[1]
+    c4[:NL, 1] = CL[2] + 1j * CL[3]
+    if NS:
+        c4[NL:, 2] = CS[0] + 1j * CS[1]
+        c4[NL:, 3] = CS[2] + 1j * CS[3]
+    return c4
+
+
+def spinor_integrals(L, S, CL, CS, ham: str, general: bool = False) -> np.ndarray:
+    """(ab|cd) as one sum over all AO and spinor indices; general: CL, CS are
+    general two-spinor planes instead of quaternion coefficients."""
     funcs = _norm_prims(L) + (_norm_prims(S) if ham != "LL" else [])
     eri = eri_tensor(funcs)
-    c4 = spinor4(CL, CS if ham != "LL" else None)
+    make = spinor4_general if general else spinor4
+    c4 = make(CL, CS if ham != "LL" else None)
     cc = c4.conj()
     out = 0
     if ham in ("LL", "DC", "DCG"):

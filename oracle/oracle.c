@@ -228,6 +228,19 @@ static cplx *spinor_coefs(int N, int n, const double *C)
     return c;
 }
 
+/* Two-spinor coefficients c[mu][tau][a] of m general (Kramers-unrestricted)
+ * spinors from planes C[4][N][m]: alpha re, alpha im, beta re, beta im. */
+static cplx *spinor_coefs_general(int N, int m, const double *C)
+{
+    cplx *c = (cplx *)calloc((size_t)N * 2 * m, sizeof(cplx));
+    for (int mu = 0; mu < N; ++mu)
+        for (int tau = 0; tau < 2; ++tau)
+            for (int a = 0; a < m; ++a)
+                c[((size_t)mu * 2 + tau) * m + a] = C[((size_t)(2 * tau) * N + mu) * m + a] +
+                                                    I * C[((size_t)(2 * tau + 1) * N + mu) * m + a];
+    return c;
+}
+
 /* Quaternion component x of a Kramers block B[2][2] of a quantity that equals
  * Q(g) for some quaternion g: g_x = (1/2) tr(Q(e_x)^dagger B).  Returns the
  * real part; *im receives the imaginary part (zero in exact arithmetic). */
@@ -345,13 +358,33 @@ void orc_dmax_gaunt(int NL, const double *CL, int NS, const double *CS, int n, d
  * carries two four-component basis spinors; L functions occupy components
  * 0,1 (alpha, beta of the large part), S functions components 2,3.
  * c4[f][w][a] is the coefficient of spinor a on basis spinor (f, w). */
+static int def_impl(const orc_basis *L, const orc_basis *S, const double *CL, const double *CS,
+                    int n, int ham, int general, double *G, double *spinor_out,
+                    double *imag_max);
+
 int orc_transform_def(const orc_basis *L, const orc_basis *S, const double *CL,
                       const double *CS, int n, int ham, double *G, double *spinor_out,
                       double *imag_max)
 {
+    return def_impl(L, S, CL, CS, n, ham, 0, G, spinor_out, imag_max);
+}
+
+int orc_transform_spinor_def(const orc_basis *L, const orc_basis *S, const double *CL,
+                             const double *CS, int m, int ham, double *spinor_out)
+{
+    if (!spinor_out) return -1;
+    return def_impl(L, S, CL, CS, m, ham, 1, NULL, spinor_out, NULL);
+}
+
+/* n: Kramers pairs (quaternion C, m = 2n spinors) or, with general, the
+ * number m of general spinors. */
+static int def_impl(const orc_basis *L, const orc_basis *S, const double *CL, const double *CS,
+                    int n, int ham, int general, double *G, double *spinor_out,
+                    double *imag_max)
+{
     int with_S = (ham != 0);
     if (with_S && (!S || !CS)) return -1;
-    int NL = L->nfunc, NS = with_S ? S->nfunc : 0, NF = NL + NS, m = 2 * n;
+    int NL = L->nfunc, NS = with_S ? S->nfunc : 0, NF = NL + NS, m = general ? n : 2 * n;
     if (NF > 64 || m > 64 || n <= 0) return -1;
 
     /* combined scalar basis */
@@ -373,8 +406,8 @@ int orc_transform_def(const orc_basis *L, const orc_basis *S, const double *CL,
                     eri[((size_t)i * NF + j) * nf2 + (size_t)k * NF + l] =
                         nb_eri(fb[i], fi[i], fb[j], fi[j], fb[k], fi[k], fb[l], fi[l]);
 
-    cplx *cl = spinor_coefs(NL, n, CL);
-    cplx *cs = with_S ? spinor_coefs(NS, n, CS) : NULL;
+    cplx *cl = general ? spinor_coefs_general(NL, m, CL) : spinor_coefs(NL, n, CL);
+    cplx *cs = !with_S ? NULL : general ? spinor_coefs_general(NS, m, CS) : spinor_coefs(NS, n, CS);
     cplx *c4 = (cplx *)calloc((size_t)NF * 4 * m, sizeof(cplx));
     for (int f = 0; f < NF; ++f)
         for (int tau = 0; tau < 2; ++tau)
@@ -443,7 +476,7 @@ int orc_transform_def(const orc_basis *L, const orc_basis *S, const double *CL,
                 for (size_t cd = 0; cd < m2; ++cd) sp[ab * m2 + cd] += t * X[ij * m2 + cd];
             }
     }
-    project_G(n, sp, G, imag_max);
+    if (G) project_G(n, sp, G, imag_max);
     if (spinor_out) memcpy(spinor_out, sp, sizeof(cplx) * m2 * m2);
 
     free(sp);
@@ -515,13 +548,15 @@ static cplx dens_gaunt(const cplx *cl, const cplx *cs, int m, int K, int ka, int
 
 static int direct_impl(const orc_basis *L, const orc_basis *S, const double *CL,
                        const double *CS, int n, int ham, double tau, const int64_t *rows,
-                       int64_t nrows_sel, int do_second, double *G, orc_stats *st, double *Vq);
+                       int64_t nrows_sel, int do_second, double *G, orc_stats *st, double *Vq,
+                       int general, double *sp_out);
 
 int orc_transform_direct(const orc_basis *L, const orc_basis *S, const double *CL,
                          const double *CS, int n, int ham, double tau, const int64_t *rows,
                          int64_t nrows_sel, int do_second, double *G, orc_stats *st)
 {
-    return direct_impl(L, S, CL, CS, n, ham, tau, rows, nrows_sel, do_second, G, st, NULL);
+    return direct_impl(L, S, CL, CS, n, ham, tau, rows, nrows_sel, do_second, G, st, NULL, 0,
+                       NULL);
 }
 
 int orc_first_half_rows(const orc_basis *L, const orc_basis *S, const double *CL,
@@ -529,24 +564,37 @@ int orc_first_half_rows(const orc_basis *L, const orc_basis *S, const double *CL
                         int64_t nrows, double *Vq)
 {
     if (!rows || nrows <= 0 || !Vq) return -1;
-    return direct_impl(L, S, CL, CS, n, ham, tau, rows, nrows, 0, NULL, NULL, Vq);
+    return direct_impl(L, S, CL, CS, n, ham, tau, rows, nrows, 0, NULL, NULL, Vq, 0, NULL);
 }
 
+int orc_transform_spinor_direct(const orc_basis *L, const orc_basis *S, const double *CL,
+                                const double *CS, int m, int ham, double tau,
+                                double *spinor_out, orc_stats *st)
+{
+    if (!spinor_out) return -1;
+    return direct_impl(L, S, CL, CS, m, ham, tau, NULL, 0, 1, NULL, st, NULL, 1, spinor_out);
+}
+
+/* n: Kramers pairs (quaternion C, m = 2n spinors, output G projected onto the
+ * quaternion basis) or, with general, the number m of general spinors (output
+ * the spinor integrals sp_out). */
 static int direct_impl(const orc_basis *L, const orc_basis *S, const double *CL,
                        const double *CS, int n, int ham, double tau, const int64_t *rows,
-                       int64_t nrows_sel, int do_second, double *G, orc_stats *st, double *Vq)
+                       int64_t nrows_sel, int do_second, double *G, orc_stats *st, double *Vq,
+                       int general, double *sp_out)
 {
     int with_S = (ham != 0);
     if (with_S && (!S || !CS)) return -1;
     if (n <= 0 || tau < 0 || ham < 0 || ham > 3) return -1;
-    int NL = L->nfunc, NS = with_S ? S->nfunc : 0, m = 2 * n;
+    if (general && Vq) return -1;
+    int NL = L->nfunc, NS = with_S ? S->nfunc : 0, m = general ? n : 2 * n;
     size_t m2 = (size_t)m * m;
     int coul = (ham != 3), gaunt = (ham >= 2);
 
     nbasis bl = nb_make(L), bs;
     if (with_S) bs = nb_make(S);
-    cplx *cl = spinor_coefs(NL, n, CL);
-    cplx *cs = with_S ? spinor_coefs(NS, n, CS) : NULL;
+    cplx *cl = general ? spinor_coefs_general(NL, m, CL) : spinor_coefs(NL, n, CL);
+    cplx *cs = !with_S ? NULL : general ? spinor_coefs_general(NS, m, CS) : spinor_coefs(NS, n, CS);
 
     /* bra/ket pair lists */
     int64_t nLL = (int64_t)NL * (NL + 1) / 2, nSS = (int64_t)NS * (NS + 1) / 2;
@@ -597,6 +645,33 @@ static int direct_impl(const orc_basis *L, const orc_basis *S, const double *CL,
      * Kramers block (Coulomb: D_s; Gaunt: the sigma_K densities, which equal
      * -i Q(D^K)). */
     double *Dmax = (double *)malloc(sizeof(double) * (size_t)(np > 0 ? np : 1));
+    if (general) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < np; ++i) {
+        /* general spinors: the largest |real| or |imaginary| part of the
+         * Pauli-scalar (Coulomb, both orderings of the pair) or sigma_K-weighted
+         * (Gaunt) pair density over all ordered spinor pairs (c, d) */
+        double mx = 0.0;
+        const opair P = pl[i];
+        for (int c = 0; c < m; ++c)
+            for (int d = 0; d < m; ++d) {
+                cplx v[6];
+                int nv = 0;
+                if (P.cls == 2) {
+                    for (int K = 0; K < 3; ++K) v[nv++] = dens_gaunt(cl, cs, m, K, P.mu, P.nu, c, d);
+                } else {
+                    const cplx *cx = P.cls == 0 ? cl : cs;
+                    v[nv++] = dens_s(cx, m, P.mu, P.nu, c, d);
+                    v[nv++] = dens_s(cx, m, P.nu, P.mu, c, d);
+                }
+                for (int k2 = 0; k2 < nv; ++k2) {
+                    if (fabs(creal(v[k2])) > mx) mx = fabs(creal(v[k2]));
+                    if (fabs(cimag(v[k2])) > mx) mx = fabs(cimag(v[k2]));
+                }
+            }
+        Dmax[i] = mx;
+    }
+    } else {
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < np; ++i) {
         double mx = 0.0;
@@ -625,6 +700,7 @@ static int direct_impl(const orc_basis *L, const orc_basis *S, const double *CL,
                     }
             }
         Dmax[i] = mx;
+    }
     }
 
     /* First half, Eq. (firsthalf): V_{mn,cd} = sum_{kl kept} (mn|kl) D_{kl,cd},
@@ -724,7 +800,7 @@ static int direct_impl(const orc_basis *L, const orc_basis *S, const double *CL,
         }
     }
 
-    if (do_second && G) {
+    if (do_second && (G || sp_out)) {
         /* Second half, Sec. 2.4.2: the Pauli components of V are converted to
          * 2x2 spin blocks V^{t1 t2} (Coulomb: V_s on the diagonal; Gaunt:
          * -sum_K sigma_K[t1][t2] V_K, the minus sign of -alpha.alpha), then
@@ -808,7 +884,8 @@ static int direct_impl(const orc_basis *L, const orc_basis *S, const double *CL,
                 free(W);
             }
         }
-        project_G(n, sp, G, NULL);
+        if (G && !general) project_G(n, sp, G, NULL);
+        if (sp_out) memcpy(sp_out, sp, sizeof(cplx) * m2 * m2);
         free(sp);
     }
     double t2 = now_s();

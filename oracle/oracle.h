@@ -118,6 +118,24 @@ int orc_first_half_rows(const orc_basis *L, const orc_basis *S, const double *CL
                         const double *CS, int n, int ham, double tau, const int64_t *rows,
                         int64_t nrows, double *Vq);
 
+/* Kramers-unrestricted (general) two-spinor input, the paper's own setting:
+ * m spinors with coefficients c_{mu tau, a} given as planes C[4][N][m] (alpha
+ * re, alpha im, beta re, beta im).  Output: the complex spinor MO integrals
+ * (ab|cd), interleaved re/im, [m]^4 x 2.
+ *   _def     unscreened definition route (literal four-spinor operators),
+ *            m and the basis size limited as for orc_transform_def.
+ *   _direct  the direct route with the same screening predicate, where
+ *            Dmax_kl is the largest |real| or |imaginary| part of the pair
+ *            density over all ordered spinor pairs (c, d): the Pauli-scalar
+ *            density of both orderings (k l) and (l k) for Coulomb pairs, the
+ *            sigma_K-weighted density of every K for Gaunt (L-S) pairs.
+ * Return 0, or -1 on invalid arguments. */
+int orc_transform_spinor_def(const orc_basis *L, const orc_basis *S, const double *CL,
+                             const double *CS, int m, int ham, double *spinor_out);
+int orc_transform_spinor_direct(const orc_basis *L, const orc_basis *S, const double *CL,
+                                const double *CS, int m, int ham, double tau,
+                                double *spinor_out, orc_stats *st);
+
 /* Number of bra pairs of the concatenated list for this ham. */
 int64_t orc_num_bra_pairs(const orc_basis *L, const orc_basis *S, int ham);
 

@@ -334,3 +334,50 @@ def config(name: str) -> System:
         # the cluster recipe at 24 atoms (radius scaled by (24/60)^(1/3)), n = 64
         return cluster(seed=3, n_atoms=24, radius=20.0 * (24 / 60) ** (1 / 3), n=64)
     raise KeyError(name)
+
+
+# ----------------------------------------------------------------------------
+# general (Kramers-unrestricted) two-spinor inputs
+# ----------------------------------------------------------------------------
+
+def quat_to_spinor_planes(C: np.ndarray) -> np.ndarray:
+    """Two-spinor planes [4][N][2n] (alpha re, alpha im, beta re, beta im) of the
+    Kramers pairs that quaternion coefficients C[4][N][n] stand for: spinors
+    2p and 2p + 1 are the columns of Q(C_mu p) = [[c0 + i c1, c2 + i c3],
+    [-c2 + i c3, c0 - i c1]] (rows alpha, beta)."""
+    c0, c1, c2, c3 = C
+    N, n = C.shape[1], C.shape[2]
+    P = np.empty((4, N, 2 * n))
+    P[0, :, 0::2], P[1, :, 0::2] = c0, c1      # alpha of spinor 2p
+    P[0, :, 1::2], P[1, :, 1::2] = c2, c3      # alpha of spinor 2p + 1
+    P[2, :, 0::2], P[3, :, 0::2] = -c2, c3     # beta of spinor 2p
+    P[2, :, 1::2], P[3, :, 1::2] = c0, -c1     # beta of spinor 2p + 1
+    return P
+
+
+def mix_spinors(P: np.ndarray, U: np.ndarray) -> np.ndarray:
+    """Planes of the spinors c' = c U (U complex [m][m'])."""
+    ca = (P[0] + 1j * P[1]) @ U
+    cb = (P[2] + 1j * P[3]) @ U
+    return np.stack([ca.real, ca.imag, cb.real, cb.imag])
+
+
+def random_unitary(rng: np.random.Generator, m: int, k: int) -> np.ndarray:
+    """First k columns of a random m x m unitary (QR of a complex Gaussian)."""
+    Z = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    Q, R = np.linalg.qr(Z)
+    Q = Q * (np.diag(R) / np.abs(np.diag(R)))[None, :]
+    return Q[:, :k]
+
+
+def general_spinors(system: System, m: int, seed: int = 0):
+    """m orthonormal general two-spinor MOs for a system: its 2n Kramers-paired
+    spinors mixed by a random unitary (seeded), which breaks every Kramers
+    pair.  Returns (planes for L, planes for S or None, U)."""
+    n = system.n_mo
+    if m > 2 * n:
+        raise ValueError("at most 2 n_mo spinors")
+    U = random_unitary(np.random.default_rng(7000 + seed), 2 * n, m)
+    PL = mix_spinors(quat_to_spinor_planes(system.CL), U)
+    PS = mix_spinors(quat_to_spinor_planes(system.CS), U) if system.CS is not None else None
+    return PL, PS, U

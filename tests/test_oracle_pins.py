@@ -405,3 +405,95 @@ def test_first_half_rows_reproduce_partial_G(ham):
     scale = np.abs(Gref).max()
     assert scale > 0
     assert np.abs(G[:, :, sel] - Gref[:, :, sel]).max() <= 1e-12 * scale
+
+
+# --------------------------------------------------------------------------
+# General (Kramers-unrestricted) two-spinor input
+# --------------------------------------------------------------------------
+
+def _tiny_general(ham, m=3):
+    s = _tiny(ham)
+    PL, PS, U = wl.general_spinors(s, m, seed=1)
+    return s, PL, (PS if ham != "LL" else None), U
+
+
+@pytest.mark.parametrize("ham", ["LL", "DC", "DCG", "GAUNT"])
+def test_general_spinors_brute_force_vs_definition_vs_direct(ham):
+    s, PL, PS, _ = _tiny_general(ham)
+    spb = brute.spinor_integrals(s.L, s.S, PL, PS, ham, general=True)
+    spd = oracle.transform_spinor_def(s.L, s.S, PL, PS, ham)
+    spr, st = oracle.transform_spinor(s.L, s.S, PL, PS, ham, 0.0)
+    scale = np.abs(spb).max()
+    assert scale > 0
+    assert np.abs(spd - spb).max() <= 1e-12 * scale
+    assert np.abs(spr - spb).max() <= 1e-12 * scale
+    # the spinors are not Kramers pairs: the result is not of quaternion form
+    assert np.abs(spb[0::2, 0::2] - spb[1::2, 1::2].conj()).max() > 1e-3 * scale
+
+
+@pytest.mark.parametrize("ham", ["DC", "DCG"])
+def test_general_spinor_route_equals_unitary_mixing_of_kramers_route(ham):
+    # (a'b'|c'd') = sum U*_{aa'} U_{bb'} U*_{cc'} U_{dd'} (ab|cd): the general
+    # route on mixed spinors against the quaternion route's spinor integrals
+    s = wl.linear_chain(seed=9, n_atoms=3, spacing=2.8, nl_per_atom=2, ns_per_atom=3, n=3,
+                        tau=0.0, ham=ham)
+    _, sp, _ = oracle.transform_def(s.L, s.S, s.CL, s.CS, ham, return_spinor=True)
+    PL, PS, U = wl.general_spinors(s, 5, seed=2)
+    mixed = np.einsum("aA,bB,cC,dD,abcd->ABCD", U.conj(), U, U.conj(), U, sp)
+    spr, _ = oracle.transform_spinor(s.L, s.S, PL, PS, ham, 0.0)
+    assert np.abs(spr - mixed).max() <= 1e-12 * np.abs(sp).max()
+
+
+@pytest.mark.parametrize("ham", ["DC", "DCG"])
+def test_general_spinor_integral_symmetries(ham):
+    s = wl.linear_chain(seed=10, n_atoms=3, spacing=3.0, nl_per_atom=2, ns_per_atom=3, n=3,
+                        tau=0.0, ham=ham)
+    PL, PS, _ = wl.general_spinors(s, 6, seed=3)
+    sp, _ = oracle.transform_spinor(s.L, s.S, PL, PS, ham, 0.0)
+    scale = np.abs(sp).max()
+    assert np.abs(sp - sp.transpose(2, 3, 0, 1)).max() <= 1e-12 * scale  # bra <-> ket
+    assert np.abs(sp - sp.transpose(1, 0, 3, 2).conj()).max() <= 1e-12 * scale  # hermiticity
+
+
+def _spinor_pair_density(P, a, b):
+    # Pauli-scalar density sum_tau conj(c_{a tau}) c_{b tau} for all spinor pairs
+    ca = P[0] + 1j * P[1]
+    cb = P[2] + 1j * P[3]
+    return np.outer(ca[a].conj(), ca[b]) + np.outer(cb[a].conj(), cb[b])
+
+
+def test_general_spinor_screening_counts_and_certificate():
+    s = wl.small_ll(seed=13, n_atoms=6, nfunc=12, n=3, edge=14.0)
+    s.CL = wl.quat_qr_plus(np.random.default_rng(2).standard_normal((4, 12, 3)))
+    PL, _, _ = wl.general_spinors(s, 5, seed=4)
+    N, m = 12, 5
+    Qm = oracle.schwarz(s.L)
+    pairs = [(mu, nu) for nu in range(N) for mu in range(nu + 1)]
+    # Dmax: largest |re| or |im| of the density of both orderings, all spinor pairs
+    Dp = np.array([max(np.abs(_spinor_pair_density(PL, a, b).real).max(),
+                       np.abs(_spinor_pair_density(PL, a, b).imag).max(),
+                       np.abs(_spinor_pair_density(PL, b, a).real).max(),
+                       np.abs(_spinor_pair_density(PL, b, a).imag).max()) for a, b in pairs])
+    Qp = np.array([Qm[a, b] for a, b in pairs])
+    bnd = np.outer(Qp, Qp * Dp)
+    tau = float(np.quantile(bnd, 0.4))
+    skip = ~((Qp[:, None] * Qp[None, :]) * Dp[None, :] >= tau)
+    assert 0.2 < skip.mean() < 0.6
+    spf, stf = oracle.transform_spinor(s.L, None, PL, None, "LL", 0.0)
+    sps, sts = oracle.transform_spinor(s.L, None, PL, None, "LL", tau)
+    assert stf["kept"][0] == len(pairs) ** 2
+    assert sts["kept"][0] == int((~skip).sum())
+    # |skipped (mn|kl) D~_kl| <= tau, carried into (ab|cd) by the bra weights
+    w = np.zeros((len(pairs), m, m))
+    for i, (a, b) in enumerate(pairs):
+        w[i] = np.abs(_spinor_pair_density(PL, a, b))
+        if a != b:
+            w[i] += np.abs(_spinor_pair_density(PL, b, a))
+    mult = np.array([1.0 if a == b else 2.0 for a, b in pairs])
+    # each skipped ket contribution is at most tau in |re| and |im| per
+    # ordering: sqrt(2) tau in modulus
+    bound = np.sqrt(2) * tau * np.einsum("ij,iab,j->ab", skip.astype(float), w, mult)
+    diff = np.abs(sps - spf)
+    slack = 1e-13 * np.abs(spf).max()
+    assert np.all(diff <= bound[:, :, None, None] + slack)
+    assert diff.max() > 100 * slack
