@@ -137,6 +137,22 @@ typedef struct {
  * contribution into G (Dmax of the bra pair bounds |conj(C_mp) C_nq|), instead
  * of the screening bound max_b Q * max_k (Q Dmax). */
 #define QDCB_PLAN_TIER_BY_G 0x2u
+/* General (Kramers-unrestricted) two-spinor MOs, the paper's own setting
+ * (Eqs. Lspinor, Sspinor with arbitrary complex c_{mu tau, p}): n_mo counts
+ * spinors (not Kramers pairs) and qdcb_transform reads and writes
+ *   CL [4][N_L][n_mo], CS [4][N_S][n_mo]   planes alpha re, alpha im, beta re,
+ *                                          beta im of the coefficients;
+ *   G  [n][n][n][n][2]                      the complex spinor integrals
+ *                                          (pq|rs) (re, im), summed over the
+ *                                          selected classes.
+ * The first half contracts the Pauli-scalar pair densities (Coulomb) and the
+ * sigma_K-weighted L-S pair densities (Gaunt) of the spinor pairs r <= s as
+ * real and imaginary columns, screened with Dmax = the largest |re| or |im|
+ * part of the pair density over all ordered spinor pairs.  Spinor pair i
+ * (r <= s, r outer) occupies columns 4 floor(i/2) + 2 (i mod 2) (re) and + 1
+ * (im), which is also the column layout of qdcb_plan_fetch_v.  Blocked output
+ * (qdcb_transform_blocks) is not offered for these plans. */
+#define QDCB_PLAN_SPINOR 0x4u
 
 /* Plan for transforming with fixed bases and n_mo.  S must be NULL for
  * QDCB_HAM_LL and non-NULL otherwise.  Orders the pairs of each integral

@@ -166,8 +166,155 @@ __global__ void __launch_bounds__(DENS_THREADS) k_density_gaunt(DensityArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// General (Kramers-unrestricted) two-spinor MOs, Eqs. (Den), (QuaternionScatter):
+// the Pauli-scalar density of spinor pair (c, d) on the AO pair (ka, la) is
+//   D^{cd}_{ka la} = sum_tau conj(c_{ka tau c}) c_{la tau d}  (complex),
+// symmetrized over ka <-> la like the quaternion density; D^{dc}_{la ka} =
+// conj(D^{cd}_{ka la}), so pairs c <= d with both orderings cover Dmax, the
+// largest |re| or |im| part over all ordered pairs.  Gaunt (LS rows): the
+// sigma_K-weighted density of both L-S orderings,
+//   P^{K,cd} = c^L(ka, c)^dagger sigma_K c^S(la, d) + c^S(la, c)^dagger sigma_K c^L(ka, d),
+// with P^{K,dc} = conj(P^{K,cd}).
+struct Cx {
+  double re, im;
+};
+__device__ __forceinline__ Cx cmul_conj(double ar, double ai, double br, double bi) {
+  return {ar * br + ai * bi, ar * bi - ai * br};  // conj(a) b
+}
+
+// c^dagger sigma_K d for two-spinors c = (ca, cb), d = (da, db)
+__device__ __forceinline__ Cx sigma_form(int K, const double c[4], const double d[4]) {
+  const Cx aa = cmul_conj(c[0], c[1], d[0], d[1]), ab = cmul_conj(c[0], c[1], d[2], d[3]);
+  const Cx ba = cmul_conj(c[2], c[3], d[0], d[1]), bb = cmul_conj(c[2], c[3], d[2], d[3]);
+  if (K == 0) return {ab.re + ba.re, ab.im + ba.im};                   // sigma_x
+  if (K == 1) return {ab.im - ba.im, -(ab.re - ba.re)};                // sigma_y: -i ab + i ba
+  return {aa.re - bb.re, aa.im - bb.im};                               // sigma_z
+}
+
+__global__ void __launch_bounds__(DENS_THREADS) k_density_spinor(DensityArgs a) {
+  __shared__ double ck[4][MAX_N];
+  __shared__ double cl[4][MAX_N];
+  __shared__ double red[DENS_THREADS / 64];
+  const int64_t row = blockIdx.x;
+  const int cls = a.cls[row];
+  const int n = a.n;
+  const int i0 = a.bound_only ? 0 : a.i0, i1 = a.bound_only ? a.npair_mo : a.i1;
+  double *Drow = a.D + row * a.ld;
+  if (cls < 0) {
+    if (!a.bound_only)
+      for (int c = threadIdx.x; c < 4 * (i1 - i0); c += DENS_THREADS) Drow[c] = 0.0;
+    else if (threadIdx.x == 0)
+      a.Dmax[row] = 0.0;
+    return;
+  }
+  const double *C = cls == 0 ? a.CL : a.CS;
+  const int N = cls == 0 ? a.NL : a.NS;
+  const int ka = a.mu[row], la = a.nu[row];
+  for (int t = threadIdx.x; t < 4 * n; t += DENS_THREADS) {
+    int z = t / n, r = t % n;
+    ck[z][r] = C[((int64_t)z * N + ka) * n + r];
+    cl[z][r] = C[((int64_t)z * N + la) * n + r];
+  }
+  __syncthreads();
+  const bool offdiag = ka != la;
+  double mx = 0.0;
+  // one thread per spinor pair i of the groups [i0, i1)
+  for (int i = 2 * i0 + threadIdx.x; i < 2 * i1; i += DENS_THREADS) {
+    double dr = 0.0, di = 0.0;
+    if (i < a.nspair) {
+      const int rs = a.rs[i];
+      const int c = rs & 0xffff, d = rs >> 16;
+      const Cx x1 = cmul_conj(ck[0][c], ck[1][c], cl[0][d], cl[1][d]);
+      const Cx x2 = cmul_conj(ck[2][c], ck[3][c], cl[2][d], cl[3][d]);
+      dr = x1.re + x2.re;
+      di = x1.im + x2.im;
+      mx = fmax(mx, fmax(fabs(dr), fabs(di)));
+      if (offdiag) {
+        const Cx y1 = cmul_conj(cl[0][c], cl[1][c], ck[0][d], ck[1][d]);
+        const Cx y2 = cmul_conj(cl[2][c], cl[3][c], ck[2][d], ck[3][d]);
+        const double er = y1.re + y2.re, ei = y1.im + y2.im;
+        mx = fmax(mx, fmax(fabs(er), fabs(ei)));
+        dr += er;
+        di += ei;
+      }
+    }
+    if (!a.bound_only)
+      *reinterpret_cast<double2 *>(Drow + 2 * (i - 2 * i0)) = make_double2(dr, di);
+  }
+  if (a.bound_only) {
+    double m = block_max(mx, red);
+    if (threadIdx.x == 0) a.Dmax[row] = m;
+  }
+}
+
+__global__ void __launch_bounds__(DENS_THREADS) k_density_spinor_gaunt(DensityArgs a) {
+  __shared__ double ck[4][MAX_N];  // C^L row ka
+  __shared__ double cl[4][MAX_N];  // C^S row la
+  __shared__ double red[DENS_THREADS / 64];
+  const int64_t row = blockIdx.x;
+  const int cls = a.cls[row];
+  const int n = a.n;
+  const int i0 = a.bound_only ? 0 : a.i0, i1 = a.bound_only ? a.npair_mo : a.i1;
+  double *Drow = a.D + row * a.ld;
+  if (cls < 0) {
+    if (!a.bound_only) {
+      for (int K = 0; K < 3; ++K)
+        for (int c = threadIdx.x; c < 4 * (i1 - i0); c += DENS_THREADS)
+          Drow[K * a.ldK + c] = 0.0;
+    } else if (threadIdx.x == 0) {
+      a.Dmax[row] = 0.0;
+    }
+    return;
+  }
+  const int ka = a.mu[row], la = a.nu[row];
+  for (int t = threadIdx.x; t < 4 * n; t += DENS_THREADS) {
+    int z = t / n, r = t % n;
+    ck[z][r] = a.CL[((int64_t)z * a.NL + ka) * n + r];
+    cl[z][r] = a.CS[((int64_t)z * a.NS + la) * n + r];
+  }
+  __syncthreads();
+  double mx = 0.0;
+  for (int i = 2 * i0 + threadIdx.x; i < 2 * i1; i += DENS_THREADS) {
+    const bool real_pair = i < a.nspair;
+    int c = 0, d = 0;
+    if (real_pair) {
+      const int rs = a.rs[i];
+      c = rs & 0xffff;
+      d = rs >> 16;
+    }
+    const double lc[4] = {ck[0][c], ck[1][c], ck[2][c], ck[3][c]};
+    const double sc[4] = {cl[0][c], cl[1][c], cl[2][c], cl[3][c]};
+    const double ld_[4] = {ck[0][d], ck[1][d], ck[2][d], ck[3][d]};
+    const double sd[4] = {cl[0][d], cl[1][d], cl[2][d], cl[3][d]};
+    for (int K = 0; K < 3; ++K) {
+      double pr = 0.0, pi = 0.0;
+      if (real_pair) {
+        const Cx u = sigma_form(K, lc, sd), v = sigma_form(K, sc, ld_);
+        pr = u.re + v.re;
+        pi = u.im + v.im;
+        mx = fmax(mx, fmax(fabs(pr), fabs(pi)));
+      }
+      if (!a.bound_only)
+        *reinterpret_cast<double2 *>(Drow + K * a.ldK + 2 * (i - 2 * i0)) = make_double2(pr, pi);
+    }
+  }
+  if (a.bound_only) {
+    double m = block_max(mx, red);
+    if (threadIdx.x == 0) a.Dmax[row] = m;
+  }
+}
+
 void launch_density(const DensityArgs &a, hipStream_t s) {
   if (a.nrows <= 0) return;
+  if (a.spinor) {
+    if (a.gaunt)
+      hipLaunchKernelGGL(k_density_spinor_gaunt, dim3((unsigned)a.nrows), dim3(DENS_THREADS), 0,
+                         s, a);
+    else
+      hipLaunchKernelGGL(k_density_spinor, dim3((unsigned)a.nrows), dim3(DENS_THREADS), 0, s, a);
+    return;
+  }
   if (a.gaunt)
     hipLaunchKernelGGL(k_density_gaunt, dim3((unsigned)a.nrows), dim3(DENS_THREADS), 0, s, a);
   else

@@ -96,6 +96,93 @@ __global__ void k_pack(int n, const int32_t *rs, int64_t c0, int nc, const doubl
   }
 }
 
+// General two-spinor mode (planes alpha re, alpha im, beta re, beta im).
+__global__ void k_build_spinor_mats(int N, int n, const double *C, int K, double *Call,
+                                    double *Chat) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)N * n) return;
+  int mu = (int)(t / n), p = (int)(t % n);
+  double c[4];
+  for (int z = 0; z < 4; ++z) c[z] = C[((int64_t)z * N + mu) * n + p];
+  double *o = Call + (int64_t)mu * 4 * n + p;
+  if (K < 0) {
+    for (int z = 0; z < 4; ++z) o[z * n] = c[z];
+    // re: sum_tau c_re W_re + c_im W_im;  im: sum_tau c_re W_im - c_im W_re
+    const double L[4][4] = {{c[0], c[1], c[2], c[3]},
+                            {-c[1], c[0], -c[3], c[2]},
+                            {0.0, 0.0, 0.0, 0.0},
+                            {0.0, 0.0, 0.0, 0.0}};
+    for (int z = 0; z < 4; ++z)
+      for (int x = 0; x < 4; ++x) Chat[((int64_t)mu * 4 + z) * 4 * n + x * n + p] = L[x][z];
+    return;
+  }
+  // -sigma_K c: sigma_x (b, a); sigma_y (-i b, i a); sigma_z (a, -b)
+  double s[4];
+  if (K == 0) {
+    s[0] = c[2]; s[1] = c[3]; s[2] = c[0]; s[3] = c[1];
+  } else if (K == 1) {
+    s[0] = c[3]; s[1] = -c[2]; s[2] = -c[1]; s[3] = c[0];
+  } else {
+    s[0] = c[0]; s[1] = c[1]; s[2] = -c[2]; s[3] = -c[3];
+  }
+  for (int z = 0; z < 4; ++z) o[z * n] = -s[z];
+}
+
+void launch_build_spinor_mats(int N, int n, const double *C, int K, double *Call, double *Chat,
+                              hipStream_t s) {
+  int64_t tot = (int64_t)N * n;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_build_spinor_mats, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                     N, n, C, K, Call, Chat);
+}
+
+// One thread per (spinor pair of the slice, p, q).
+__global__ void k_pack_spinor(int n, const int32_t *rs, int nspair, int64_t c0, int nc,
+                              const double *Gc, double *G, int accumulate) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t npl = nc / 2;  // spinor pairs of the slice
+  if (t >= npl * n * n) return;
+  int q = (int)(t % n);
+  int p = (int)((t / n) % n);
+  int64_t jl = t / ((int64_t)n * n);  // pair within the slice
+  int64_t i = c0 / 2 + jl;            // global spinor pair
+  if (i >= nspair) return;            // empty half of the last group
+  const int rsv = rs[i];
+  const int c = rsv & 0xffff, d = rsv >> 16;
+  // planes x = 0 (re), 1 (im) of the columns of V re (2 jl) and V im (2 jl + 1)
+  const double *A = Gc + (2 * jl) * 4 * (int64_t)n * n;
+  const double *B = A + 4 * (int64_t)n * n;
+  const int64_t pq = (int64_t)p * n + q;
+  const double ar = A[pq], ai = A[(int64_t)n * n + pq];
+  const double br = B[pq], bi = B[(int64_t)n * n + pq];
+  double *o = G + ((pq * n + c) * n + d) * 2;
+  double2 v = make_double2(ar - bi, ai + br);
+  if (accumulate) {
+    const double2 old = *reinterpret_cast<double2 *>(o);
+    v.x += old.x;
+    v.y += old.y;
+  }
+  *reinterpret_cast<double2 *>(o) = v;
+  if (c != d) {
+    double *m = G + ((pq * n + d) * n + c) * 2;
+    double2 w = make_double2(ar + bi, ai - br);
+    if (accumulate) {
+      const double2 old = *reinterpret_cast<double2 *>(m);
+      w.x += old.x;
+      w.y += old.y;
+    }
+    *reinterpret_cast<double2 *>(m) = w;
+  }
+}
+
+void launch_pack_spinor(int n, const int32_t *rs, int nspair, int64_t c0, int nc,
+                        const double *Gc, double *G, int accumulate, hipStream_t s) {
+  int64_t tot = (int64_t)(nc / 2) * n * n;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_pack_spinor, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, rs,
+                     nspair, c0, nc, Gc, G, accumulate);
+}
+
 // Block output: one thread per (MO pair r <= s of the slice, p, q) writes
 // B[i][p][q][0][x][y] = G_pqrs^xy and B[i][p][q][1][x][y] = G_pqsr^xy (the same
 // entry when r = s), i the pair's index in the block (first pair b_i0).

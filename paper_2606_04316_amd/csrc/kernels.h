@@ -51,9 +51,14 @@ struct DensityArgs {
   const double *CL;       // [4][NL][n]
   const double *CS;       // [4][NS][n]
   int NL, NS;
-  const int32_t *rs;      // [npair_mo]: r | s << 16
+  const int32_t *rs;      // [npair_mo]: r | s << 16 (spinor mode: [2 npair_mo] spinor pairs)
   double *D;              // [nrows][ld]
   double *Dmax;           // [nrows]
+  // general two-spinor mode: C planes are alpha re, alpha im, beta re, beta im
+  // of n spinors; npair_mo counts groups of two spinor pairs (c <= d), nspair
+  // the spinor pairs; pair i = 2 g + h fills columns 4 g + 2 h (re) and + 1 (im)
+  int spinor = 0;
+  int nspair = 0;
 };
 void launch_density(const DensityArgs &a, hipStream_t s);
 
@@ -203,6 +208,19 @@ void launch_gather_gemm(const GatherGemmArgs &a, hipStream_t s);
 // unit = 0, 1, 2) and L(a) the matrix of left multiplication by a.
 void launch_build_coef_mats(int N, int n, const double *C, int unit, double *Call,
                             double *Chat, hipStream_t s);
+// General two-spinor mode.  K < 0: Call[nu][z*n + q] = C[z][nu][q] and Chat, the
+// matrix of the conjugated left factor with two output planes (re, im):
+// G_c[(x, p)][q] = sum_(mu, z) Chat[(mu, z)][(x, p)] W_c[(mu, z)][q] is
+// sum_tau conj(c_{mu tau p}) W_{mu tau q} (planes x = 2, 3 are zero).
+// K = 0, 1, 2: Call = the planes of -sigma_K c (sigma_x, sigma_y, sigma_z),
+// Chat untouched.
+void launch_build_spinor_mats(int N, int n, const double *C, int K, double *Call, double *Chat,
+                              hipStream_t s);
+// Scatter the slice's spinor columns into G[p][q][c][d][re, im]: for pair
+// i = 2 g + h (c <= d) of group g, columns 4 g + 2 h (V re) and + 1 (V im) give
+// A and B (complex, planes x = 0, 1 of Gc), (pq|cd) = A + iB and (pq|dc) = A - iB.
+void launch_pack_spinor(int n, const int32_t *rs, int nspair, int64_t c0, int nc,
+                        const double *Gc, double *G, int accumulate, hipStream_t s);
 // Scatter Gc[c][(x,p)][q] for MO-pair columns c of [c0, c0+nc) (c = 4 idx + y)
 // into G[p][q][r][s][x][y] and its mirror G[p][q][s][r][x][y] = mirror * s_y * v,
 // s = (+1,-1,-1,-1); accumulate = 1 adds to G instead of storing.

@@ -136,7 +136,7 @@ double dv_bytes(const qdcb_plan &p, int64_t ci) {
 }
 
 size_t g_stage_bytes(const qdcb_plan &p) {
-  return sizeof(double) * (size_t)p.n * p.n * p.n * p.n * 16;
+  return sizeof(double) * (size_t)p.n * p.n * p.n * p.n * (p.spinor ? 2 : 16);
 }
 
 // (Re)allocate the sized buffers: D~ and V of the column chunk, the
@@ -272,7 +272,8 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
       fail(QDCB_E_INVALID, "S must be NULL exactly for QDCB_HAM_LL");
     if (desc->n_mo < 1 || desc->n_mo > 512) fail(QDCB_E_INVALID, "n_mo must be in [1, 512]");
     if (!std::isfinite(desc->tau) || desc->tau < 0) fail(QDCB_E_INVALID, "tau must be >= 0");
-    if (desc->flags & ~(int32_t)(QDCB_PLAN_DIRECTED_TILES | QDCB_PLAN_TIER_BY_G))
+    if (desc->flags &
+        ~(int32_t)(QDCB_PLAN_DIRECTED_TILES | QDCB_PLAN_TIER_BY_G | QDCB_PLAN_SPINOR))
       fail(QDCB_E_INVALID, "unknown plan flag");
     // bases may belong to another context (resident, shared) on the same device
     if (L->ctx->device != ctx->device || (S && S->ctx->device != ctx->device))
@@ -288,7 +289,13 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
     p.NL = L->nfunc;
     p.NS = S ? S->nfunc : 0;
     p.gaunt = desc->ham == QDCB_HAM_DCG;
-    p.npair_mo = p.n * (p.n + 1) / 2;
+    p.spinor = desc->flags & QDCB_PLAN_SPINOR;
+    if (p.spinor) {  // pairs of spinors c <= d, two pairs per four-column group
+      p.npair_s = p.n * (p.n + 1) / 2;
+      p.npair_mo = (p.npair_s + 1) / 2;
+    } else {
+      p.npair_mo = p.n * (p.n + 1) / 2;
+    }
     p.ncol = 4LL * p.npair_mo;
 
     // --- Coulomb space: LL pairs, then SS pairs
@@ -349,7 +356,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
     }
 
     // --- index tables
-    std::vector<int32_t> rs(p.npair_mo);
+    std::vector<int32_t> rs(p.spinor ? 2 * (size_t)p.npair_mo : (size_t)p.npair_mo, -1);
     {
       int k = 0;
       for (int r = 0; r < p.n; ++r)
@@ -424,8 +431,10 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
       int kS = S ? *std::max_element(S->nprim.begin(), S->nprim.end()) : 0;
       char key[256];
       std::snprintf(key, sizeof key,
-                    "v1 ham=%d prec=%d n=%d NL=%d NS=%d kL=%d kS=%d tau=%.3e tC=%d tG=%d cu=%d",
-                    (int)desc->ham, (int)desc->prec, p.n, p.NL, p.NS, kL, kS, desc->tau,
+                    "v1 ham=%d prec=%d fl=%d n=%d NL=%d NS=%d kL=%d kS=%d tau=%.3e tC=%d "
+                    "tG=%d cu=%d",
+                    (int)desc->ham, (int)desc->prec, (int)desc->flags, p.n, p.NL, p.NS, kL, kS,
+                    desc->tau,
                     p.C.ntiles, p.gaunt ? p.G.ntiles : 0, p.n_cu);
       p.tune_key = key;
     }
@@ -457,7 +466,9 @@ qdcb_status qdcb_plan_estimate(const qdcb_basis *L, const qdcb_basis *S,
     if (desc->n_mo < 1 || desc->n_mo > 512) fail(QDCB_E_INVALID, "n_mo must be in [1, 512]");
     const bool gaunt = desc->ham == QDCB_HAM_DCG;
     const double n = desc->n_mo, NL = L->nfunc, NS = S ? S->nfunc : 0;
-    const double npair = n * (n + 1) / 2;
+    const bool spinor = desc->flags & QDCB_PLAN_SPINOR;
+    // MO-pair columns: 4 per quaternion pair, 2 per spinor pair (in groups of two)
+    const double npair = spinor ? std::ceil(n * (n + 1) / 4) : n * (n + 1) / 2;
     const double ldK = (double)round_up((int64_t)(4 * npair), 128);
     const double PC = (double)round_up(L->npairs + (S ? S->npairs : 0), TILE);
     const double PG = gaunt ? (double)round_up((int64_t)(NL * NS), TILE) : 0.0;
@@ -473,7 +484,7 @@ qdcb_status qdcb_plan_estimate(const qdcb_basis *L, const qdcb_basis *S,
     b += 8.0 * 20.0 * (NL + NS) * n * 4;                  // coefficient matrices
     auto slots = [](double nt) { return std::min(nt * nt, std::max(nt, 65536.0)); };
     b += 8.0 * TILE * TILE * (slots(ntC) + (gaunt ? slots(ntG) : 0.0));  // integral panels
-    b += 8.0 * 16.0 * n * n * n * n;                      // host-path G staging
+    b += 8.0 * (spinor ? 2.0 : 16.0) * n * n * n * n;     // host-path G staging
     *bytes = (size_t)(b * 1.05);
   });
 }

@@ -111,6 +111,8 @@ void density(qdcb_plan &p, Space &sp, const double *dCL, const double *dCS, int 
   da.rs = p.rs.p;
   da.D = sp.D.p;
   da.Dmax = sp.Dmax.p;
+  da.spinor = p.spinor ? 1 : 0;
+  da.nspair = p.npair_s;
   launch_density(da, s);
   HIPC(hipGetLastError());
 }
@@ -408,13 +410,14 @@ void gather_quarter(const qdcb_plan &p, const Space &sp, const int32_t *rowmap, 
 void second_quarter(const qdcb_plan &p, const double *Ahat, int N, bool accumulate, int nc,
                     hipStream_t s) {
   const int n = p.n;
+  const int M = (p.spinor ? 2 : 4) * n;  // output planes: re, im (spinors) or x = 0..3
   if (p.tune.sq_tile == 128) {
     GatherGemmArgs g{};
     g.V = Ahat;
     g.ld = 4 * n;
     g.col0 = 0;
     g.rowmap = nullptr;
-    g.nc = 4 * n;
+    g.nc = M;
     g.K = 4 * N;
     g.J = n;
     g.nb = nc;
@@ -427,7 +430,7 @@ void second_quarter(const qdcb_plan &p, const double *Ahat, int N, bool accumula
     g.accumulate = accumulate ? 1 : 0;
     launch_gather_gemm(g, s);
   } else {
-    launch_dgemm_batched(1, 4 * n, n, 4 * N, 1.0, Ahat, 4 * n, 0, p.W.p, n, (int64_t)N * 4 * n,
+    launch_dgemm_batched(1, M, n, 4 * N, 1.0, Ahat, 4 * n, 0, p.W.p, n, (int64_t)N * 4 * n,
                          accumulate ? 1.0 : 0.0, p.Gc.p, n, (int64_t)4 * n * n, nc, s);
   }
 }
@@ -466,7 +469,9 @@ void second_half(qdcb_plan &p, int i0, int i1, double *dG, hipStream_t s,
     const int nc = (int)std::min<int64_t>(step, cend - c0);
     const int64_t lc0 = c0 - 4LL * i0;
     auto pack = [&](double mirror, int accumulate) {
-      if (sink)
+      if (p.spinor)  // (pq|dc) = A - iB for both classes; blocks are not offered
+        launch_pack_spinor(n, p.rs.p, p.npair_s, c0, nc, p.Gc.p, dG, accumulate, s);
+      else if (sink)
         launch_pack_block(n, p.rs.p, c0, nc, p.Gc.p, p.Gb.p, c0 / 4, mirror, accumulate, s);
       else
         launch_pack(n, p.rs.p, c0, nc, p.Gc.p, dG, mirror, accumulate, s);
@@ -484,6 +489,16 @@ void second_half(qdcb_plan &p, int i0, int i1, double *dG, hipStream_t s,
       const int NL = p.NL, NS = p.NS;
       for (int K = 0; K < 3; ++K) {
         const int64_t col0 = K * p.G.ldK + lc0;
+        if (p.spinor) {
+          // -c^L(mu)^dagger (V sigma_K c^S): batches mu in L, sum over nu in S
+          // (AhatK / BhatK hold the planes of -sigma_K c^L / -sigma_K c^S)
+          gather_quarter(p, p.G, p.rowmapLS.p, NS, 1, NL, NS, p.BhatK[K].p, col0, nc, s);
+          second_quarter(p, p.ChatL.p, NL, K != 0, nc, s);
+          // -c^S(nu)^dagger (V^T sigma_K c^L): batches nu in S, sum over mu in L
+          gather_quarter(p, p.G, p.rowmapLS.p, 1, NS, NS, NL, p.AhatK[K].p, col0, nc, s);
+          second_quarter(p, p.ChatS.p, NS, true, nc, s);
+          continue;
+        }
         // conj(C^L) e_K (V C^S): batches mu in L, sum over nu in S
         gather_quarter(p, p.G, p.rowmapLS.p, NS, 1, NL, NS, p.CallS.p, col0, nc, s);
         second_quarter(p, p.AhatK[K].p, NL, K != 0, nc, s);
@@ -525,13 +540,23 @@ void enqueue(qdcb_plan &p, const double *dCL, const double *dCS, double *dG, boo
       sp->sym = !(p.desc.flags & QDCB_PLAN_DIRECTED_TILES) && sp->total <= sp->panel_slots;
   }
   if (tm.probe_only) return;
-  launch_build_coef_mats(p.NL, p.n, dCL, -1, p.CallL.p, p.ChatL.p, s);
-  if (p.NS) launch_build_coef_mats(p.NS, p.n, dCS, -1, p.CallS.p, p.ChatS.p, s);
-  if (p.gaunt)
-    for (int K = 0; K < 3; ++K) {
-      launch_build_coef_mats(p.NL, p.n, dCL, K, p.CallL.p, p.AhatK[K].p, s);
-      launch_build_coef_mats(p.NS, p.n, dCS, K, p.CallS.p, p.BhatK[K].p, s);
-    }
+  if (p.spinor) {
+    launch_build_spinor_mats(p.NL, p.n, dCL, -1, p.CallL.p, p.ChatL.p, s);
+    if (p.NS) launch_build_spinor_mats(p.NS, p.n, dCS, -1, p.CallS.p, p.ChatS.p, s);
+    if (p.gaunt)
+      for (int K = 0; K < 3; ++K) {
+        launch_build_spinor_mats(p.NL, p.n, dCL, K, p.AhatK[K].p, nullptr, s);
+        launch_build_spinor_mats(p.NS, p.n, dCS, K, p.BhatK[K].p, nullptr, s);
+      }
+  } else {
+    launch_build_coef_mats(p.NL, p.n, dCL, -1, p.CallL.p, p.ChatL.p, s);
+    if (p.NS) launch_build_coef_mats(p.NS, p.n, dCS, -1, p.CallS.p, p.ChatS.p, s);
+    if (p.gaunt)
+      for (int K = 0; K < 3; ++K) {
+        launch_build_coef_mats(p.NL, p.n, dCL, K, p.CallL.p, p.AhatK[K].p, s);
+        launch_build_coef_mats(p.NS, p.n, dCS, K, p.CallS.p, p.BhatK[K].p, s);
+      }
+  }
   HIPC(hipGetLastError());
   for (int i0 = 0, k = 0; i0 < p.npair_mo && (tm.max_chunks <= 0 || k < tm.max_chunks);
        i0 += p.ci, ++k) {
@@ -588,12 +613,14 @@ void fill_stats(qdcb_plan &p, qdcb_stats *stats, StageTimer *tm, double ms_total
                                                           : 0);
   stats->flops_first_half = 2.0 * (double)p.ncol * ktot + 6.0 * (double)p.ncol * (double)kg[0];
   double f2 = 0;
+  // second quarter: 2 (4n or 2n output rows) (4N) n per column
+  const double sq = p.spinor ? 16.0 : 32.0;
   for (int cls = 0; (p.classes & CLS_COULOMB) && cls < (p.NS ? 2 : 1); ++cls) {
     double N = cls ? p.NS : p.NL;
-    f2 += (8.0 * N * N * n + 32.0 * N * n * n) * (double)p.ncol;
+    f2 += (8.0 * N * N * n + sq * N * n * n) * (double)p.ncol;
   }
   if (p.gaunt && (p.classes & CLS_GAUNT))
-    f2 += 3.0 * (16.0 * p.NL * (double)p.NS * n + 32.0 * (p.NL + p.NS) * (double)n * n) *
+    f2 += 3.0 * (16.0 * p.NL * (double)p.NS * n + sq * (p.NL + p.NS) * (double)n * n) *
           (double)p.ncol;
   stats->flops_second_half = f2;
   const int nchunks = (p.npair_mo + p.ci - 1) / p.ci;
@@ -669,7 +696,7 @@ struct DevIO {
 DevIO device_io(qdcb_plan &p, const double *CL, const double *CS, double *G, bool dev,
                 hipStream_t s) {
   if (dev) return {CL, CS, G};
-  const size_t nG = (size_t)p.n * p.n * p.n * p.n * 16;
+  const size_t nG = (size_t)p.n * p.n * p.n * p.n * (p.spinor ? 2 : 16);
   check_finite_host(CL, (size_t)4 * p.NL * p.n, "CL");
   if (p.NS) check_finite_host(CS, (size_t)4 * p.NS * p.n, "CS");
   HIPC(hipMemcpyAsync(p.CLd.p, CL, p.CLd.bytes(), hipMemcpyHostToDevice, s));
@@ -775,7 +802,7 @@ qdcb_status qdcb_transform(qdcb_plan *plan, const double *CL, const double *CS, 
     const bool dev = flags & QDCB_PTR_DEVICE;
     const int classes = class_mask(p, flags);
     const int n = p.n;
-    const size_t nG = (size_t)n * n * n * n * 16;
+    const size_t nG = (size_t)n * n * n * n * (p.spinor ? 2 : 16);
     const DevIO io = device_io(p, CL, CS, G, dev, s);
     double *dG = io.G;
     run_eager(p, io.CL, io.CS, dG, s, stats, classes);
@@ -794,6 +821,7 @@ qdcb_status qdcb_transform_blocks(qdcb_plan *plan, const double *CL, const doubl
     qdcb_plan &p = *plan;
     PlanUse use(p);
     if (p.NS && !CS) fail(QDCB_E_INVALID, "CS is required for this Hamiltonian");
+    if (p.spinor) fail(QDCB_E_UNSUPPORTED, "blocked output is offered for quaternion plans");
     DeviceGuard g(p.ctx->device);
     hipStream_t s = (hipStream_t)hip_stream;
     const bool dev = flags & QDCB_PTR_DEVICE;

@@ -26,6 +26,7 @@ CLASSES = {None: 0, "all": 0, "coulomb": CLASS_COULOMB, "gaunt": CLASS_GAUNT}
 FETCH_DMAX, FETCH_Q, FETCH_DMAX_GAUNT, FETCH_Q_GAUNT = 1, 2, 3, 4
 PLAN_DIRECTED_TILES = 0x1
 PLAN_TIER_BY_G = 0x2
+PLAN_SPINOR = 0x4
 
 STATUS = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_UNSUPPORTED",
           -5: "E_BUSY", -6: "E_ABORTED"}
@@ -243,12 +244,17 @@ class Plan:
         self.ctx, self.L, self.S = ctx, L, S
         self.n = int(n_mo)
         self.ham = ham
+        self.spinor = bool(flags & PLAN_SPINOR)  # n_mo spinors, complex G [n]^4 x 2
         desc = PlanDesc(HAM[ham], PREC[prec], self.n, int(flags), float(tau), float(tier_fp32),
                         float(tier_bf16))
         h = _P()
         _check(lib().qdcb_plan_create(ctx.h, L.h, S.h if S is not None else None,
                                       ctypes.byref(desc), ctypes.byref(h)))
         self.h = h
+
+    def g_shape(self):
+        n = self.n
+        return (n, n, n, n, 2) if self.spinor else (n, n, n, n, 4, 4)
 
     def footprint(self) -> int:
         b = ctypes.c_size_t(0)
@@ -274,7 +280,7 @@ class Plan:
         if _is_torch_cuda(CL):
             import torch
             if G is None:
-                G = torch.empty((n, n, n, n, 4, 4), dtype=torch.float64, device=CL.device)
+                G = torch.empty(self.g_shape(), dtype=torch.float64, device=CL.device)
             for t in (CL, CS, G):
                 if t is not None and (t.dtype != torch.float64 or not t.is_contiguous()):
                     raise ValueError("device tensors must be contiguous float64")
@@ -287,7 +293,7 @@ class Plan:
         CLh = _f64(CL)
         CSh = _f64(CS) if CS is not None else None
         if G is None:
-            G = np.empty((n, n, n, n, 4, 4))
+            G = np.empty(self.g_shape())
         _check(lib().qdcb_transform(self.h, CLh.ctypes.data,
                                     CSh.ctypes.data if CSh is not None else None,
                                     G.ctypes.data, cf, stream, ctypes.byref(st)))
@@ -366,7 +372,7 @@ class Plan:
         if _is_torch_cuda(CL):
             import torch
             if G is None:
-                G = torch.empty((n, n, n, n, 4, 4), dtype=torch.float64, device=CL.device)
+                G = torch.empty(self.g_shape(), dtype=torch.float64, device=CL.device)
             if stream is None:
                 stream = torch.cuda.current_stream(CL.device).cuda_stream
             _check(lib().qdcb_plan_autotune(self.h, CL.data_ptr(),
@@ -377,7 +383,7 @@ class Plan:
         CLh = _f64(CL)
         CSh = _f64(CS) if CS is not None else None
         if G is None:
-            G = np.empty((n, n, n, n, 4, 4))
+            G = np.empty(self.g_shape())
         _check(lib().qdcb_plan_autotune(self.h, CLh.ctypes.data,
                                         CSh.ctypes.data if CSh is not None else None,
                                         G.ctypes.data, 0, stream, path, ctypes.byref(rep)))
