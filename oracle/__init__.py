@@ -85,6 +85,9 @@ def lib():
         L.orc_transform_spinor_direct.restype = ctypes.c_int
         L.orc_transform_spinor_direct.argtypes = [bp, bp, dp, dp, ctypes.c_int, ctypes.c_int,
                                                   ctypes.c_double, dp, ctypes.POINTER(Stats)]
+        L.orc_transform_direct_dmax.restype = ctypes.c_int
+        L.orc_transform_direct_dmax.argtypes = [bp, bp, dp, dp, ctypes.c_int, ctypes.c_int,
+                                                ctypes.c_double, dp, dp, ctypes.POINTER(Stats)]
         L.orc_num_bra_pairs.restype = ctypes.c_int64
         L.orc_num_bra_pairs.argtypes = [bp, bp, ctypes.c_int]
         _lib = L
@@ -260,3 +263,95 @@ def num_bra_pairs(L, S, ham: str) -> int:
     bl = _B(L)
     bs = _B(S) if S is not None else None
     return int(lib().orc_num_bra_pairs(bl.ref, bs.ref if bs else None, HAMS[ham]))
+
+
+# --------------------------------------------------------------------------
+# MO-driven variant: per-batch density bound
+# --------------------------------------------------------------------------
+
+def _qconj_mul(a, b):
+    """conj(a) b for quaternion arrays with the component on the first axis."""
+    a0, a1, a2, a3 = a[0], -a[1], -a[2], -a[3]
+    b0, b1, b2, b3 = b
+    return np.array([a0 * b0 - a1 * b1 - a2 * b2 - a3 * b3,
+                     a0 * b1 + a1 * b0 + a2 * b3 - a3 * b2,
+                     a0 * b2 - a1 * b3 + a2 * b0 + a3 * b1,
+                     a0 * b3 + a1 * b2 - a2 * b1 + a3 * b0])
+
+
+_UNITS = {0: np.array([0.0, 0.0, 0.0, 1.0]),   # e_x = k
+          1: np.array([0.0, 0.0, 1.0, 0.0]),   # e_y = j
+          2: np.array([0.0, 1.0, 0.0, 0.0])}   # e_z = i
+
+
+def _qmul(a, b):
+    return _qconj_mul(a * np.array([1.0, -1.0, -1.0, -1.0]).reshape((4,) + (1,) * (a.ndim - 1)), b)
+
+
+def dmax_batch(L, S, CL, CS, ham: str, mo_pairs) -> np.ndarray:
+    """Density bound of one batch of quaternion MO pairs (r <= t), per pair of
+    the concatenated bra list: for Coulomb pairs the largest |component| of
+    conj(C_kr) C_lt and conj(C_lr) C_kt over the batch; for Gaunt (L-S) pairs
+    of conj(C^L_mr) e_K C^S_nt + conj(C^S_nr) e_K C^L_mt over K and the batch
+    (Eq. SchwarzDen restricted to the batch's MO pairs)."""
+    out = []
+    coul = ham != "GAUNT"
+    gaunt = ham in ("DCG", "GAUNT")
+
+    def coul_block(C):
+        N = C.shape[1]
+        M = np.zeros((N, N))
+        for r, t in mo_pairs:
+            d = _qconj_mul(C[:, :, r][:, :, None], C[:, :, t][:, None, :])  # [4][k][l]
+            a = np.abs(d).max(axis=0)
+            M = np.maximum(M, np.maximum(a, a.T))
+        return np.array([M[mu, nu] for nu in range(N) for mu in range(nu + 1)])
+
+    if coul:
+        out.append(coul_block(CL))
+        if ham != "LL":
+            out.append(coul_block(CS))
+    if gaunt:
+        NL, NS = CL.shape[1], CS.shape[1]
+        M = np.zeros((NL, NS))
+        for r, t in mo_pairs:
+            for K in range(3):
+                e = _UNITS[K].reshape(4, 1, 1)
+                lr = CL[:, :, r][:, :, None]
+                st = CS[:, :, t][:, None, :]
+                sr = CS[:, :, r][:, None, :]
+                lt = CL[:, :, t][:, :, None]
+                d = _qmul(_qconj_mul(lr, e), st) + _qmul(_qconj_mul(sr, e), lt)
+                M = np.maximum(M, np.abs(d).max(axis=0))
+        out.append(M.reshape(-1))
+    return np.concatenate(out)
+
+
+def transform_direct_mo(L, S, CL, CS, ham: str, tau: float, batch: int):
+    """MO-driven variant of the direct route: the MO pairs (r <= t, r outer) in
+    batches of ``batch``, each screened with its own density bound
+    (dmax_batch); G of each batch's pairs (and their t, r mirrors) comes from
+    that batch's screened transform.  Returns (G, stats with kept summed over
+    the batches)."""
+    bl, bs, CL, CS = _prep(L, S, CL, CS)
+    n = CL.shape[2]
+    pairs = [(r, t) for r in range(n) for t in range(r, n)]
+    G = np.zeros((n, n, n, n, 4, 4))
+    kept = np.zeros(4, dtype=np.int64)
+    kept_g = 0
+    for b0 in range(0, len(pairs), batch):
+        bp = pairs[b0:b0 + batch]
+        dm = np.ascontiguousarray(dmax_batch(L, S, CL, CS, ham, bp))
+        Gb = np.zeros_like(G)
+        st = Stats()
+        rc = lib().orc_transform_direct_dmax(bl.ref, bs.ref if bs else None, _dp(CL),
+                                             _dp(CS) if CS is not None else None, n, HAMS[ham],
+                                             float(tau), _dp(dm), _dp(Gb), ctypes.byref(st))
+        if rc != 0:
+            raise ValueError("orc_transform_direct_dmax rejected the problem")
+        for r, t in bp:
+            G[:, :, r, t] = Gb[:, :, r, t]
+            G[:, :, t, r] = Gb[:, :, t, r]
+        kept += np.array(st.kept)
+        kept_g += st.kept_gaunt
+    return G, {"kept": [int(x) for x in kept], "kept_gaunt": int(kept_g)}

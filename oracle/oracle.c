@@ -549,14 +549,22 @@ static cplx dens_gaunt(const cplx *cl, const cplx *cs, int m, int K, int ka, int
 static int direct_impl(const orc_basis *L, const orc_basis *S, const double *CL,
                        const double *CS, int n, int ham, double tau, const int64_t *rows,
                        int64_t nrows_sel, int do_second, double *G, orc_stats *st, double *Vq,
-                       int general, double *sp_out);
+                       int general, double *sp_out, const double *dmax_in);
+
+int orc_transform_direct_dmax(const orc_basis *L, const orc_basis *S, const double *CL,
+                              const double *CS, int n, int ham, double tau,
+                              const double *dmax_in, double *G, orc_stats *st)
+{
+    if (!dmax_in) return -1;
+    return direct_impl(L, S, CL, CS, n, ham, tau, NULL, 0, 1, G, st, NULL, 0, NULL, dmax_in);
+}
 
 int orc_transform_direct(const orc_basis *L, const orc_basis *S, const double *CL,
                          const double *CS, int n, int ham, double tau, const int64_t *rows,
                          int64_t nrows_sel, int do_second, double *G, orc_stats *st)
 {
     return direct_impl(L, S, CL, CS, n, ham, tau, rows, nrows_sel, do_second, G, st, NULL, 0,
-                       NULL);
+                       NULL, NULL);
 }
 
 int orc_first_half_rows(const orc_basis *L, const orc_basis *S, const double *CL,
@@ -564,7 +572,7 @@ int orc_first_half_rows(const orc_basis *L, const orc_basis *S, const double *CL
                         int64_t nrows, double *Vq)
 {
     if (!rows || nrows <= 0 || !Vq) return -1;
-    return direct_impl(L, S, CL, CS, n, ham, tau, rows, nrows, 0, NULL, NULL, Vq, 0, NULL);
+    return direct_impl(L, S, CL, CS, n, ham, tau, rows, nrows, 0, NULL, NULL, Vq, 0, NULL, NULL);
 }
 
 int orc_transform_spinor_direct(const orc_basis *L, const orc_basis *S, const double *CL,
@@ -572,7 +580,8 @@ int orc_transform_spinor_direct(const orc_basis *L, const orc_basis *S, const do
                                 double *spinor_out, orc_stats *st)
 {
     if (!spinor_out) return -1;
-    return direct_impl(L, S, CL, CS, m, ham, tau, NULL, 0, 1, NULL, st, NULL, 1, spinor_out);
+    return direct_impl(L, S, CL, CS, m, ham, tau, NULL, 0, 1, NULL, st, NULL, 1, spinor_out,
+                       NULL);
 }
 
 /* n: Kramers pairs (quaternion C, m = 2n spinors, output G projected onto the
@@ -581,7 +590,7 @@ int orc_transform_spinor_direct(const orc_basis *L, const orc_basis *S, const do
 static int direct_impl(const orc_basis *L, const orc_basis *S, const double *CL,
                        const double *CS, int n, int ham, double tau, const int64_t *rows,
                        int64_t nrows_sel, int do_second, double *G, orc_stats *st, double *Vq,
-                       int general, double *sp_out)
+                       int general, double *sp_out, const double *dmax_in)
 {
     int with_S = (ham != 0);
     if (with_S && (!S || !CS)) return -1;
@@ -645,7 +654,10 @@ static int direct_impl(const orc_basis *L, const orc_basis *S, const double *CL,
      * Kramers block (Coulomb: D_s; Gaunt: the sigma_K densities, which equal
      * -i Q(D^K)). */
     double *Dmax = (double *)malloc(sizeof(double) * (size_t)(np > 0 ? np : 1));
-    if (general) {
+    if (dmax_in) {
+        /* a bound given by the caller (the MO-driven variant's per-batch bound) */
+        for (int64_t i = 0; i < np; ++i) Dmax[i] = dmax_in[i];
+    } else if (general) {
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < np; ++i) {
         /* general spinors: the largest |real| or |imaginary| part of the

@@ -136,6 +136,13 @@ int orc_transform_spinor_direct(const orc_basis *L, const orc_basis *S, const do
                                 const double *CS, int m, int ham, double tau,
                                 double *spinor_out, orc_stats *st);
 
+/* The direct route with the density bound given per pair of the
+ * concatenated list (dmax_in[np], same order as the bra pairs), for the
+ * MO-driven variant whose bound covers one batch of MO pairs. */
+int orc_transform_direct_dmax(const orc_basis *L, const orc_basis *S, const double *CL,
+                              const double *CS, int n, int ham, double tau,
+                              const double *dmax_in, double *G, orc_stats *st);
+
 /* Number of bra pairs of the concatenated list for this ham. */
 int64_t orc_num_bra_pairs(const orc_basis *L, const orc_basis *S, int ham);
 

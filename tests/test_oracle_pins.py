@@ -497,3 +497,58 @@ def test_general_spinor_screening_counts_and_certificate():
     slack = 1e-13 * np.abs(spf).max()
     assert np.all(diff <= bound[:, :, None, None] + slack)
     assert diff.max() > 100 * slack
+
+
+# --------------------------------------------------------------------------
+# MO-driven variant (per-batch density bound)
+# --------------------------------------------------------------------------
+
+def test_mo_driven_reduces_to_ao_driven():
+    # tau = 0 keeps everything in every batch; one batch of all MO pairs is
+    # the AO-driven bound itself (kept counts equal the C route's)
+    s = wl.linear_chain(seed=55, n_atoms=5, spacing=3.0, nl_per_atom=3, ns_per_atom=4, n=4,
+                        tau=1e-9, ham="DCG")
+    G0, _ = oracle.transform_direct(s.L, s.S, s.CL, s.CS, "DCG", 0.0)
+    Gm0, _ = oracle.transform_direct_mo(s.L, s.S, s.CL, s.CS, "DCG", 0.0, 3)
+    assert np.array_equal(Gm0, G0)
+    tau = 1e-6
+    Ga, sta = oracle.transform_direct(s.L, s.S, s.CL, s.CS, "DCG", tau)
+    Gall, stall = oracle.transform_direct_mo(s.L, s.S, s.CL, s.CS, "DCG", tau, 10)
+    assert np.array_equal(Gall, Ga)
+    assert stall["kept"] == sta["kept"] and stall["kept_gaunt"] == sta["kept_gaunt"]
+
+
+def test_mo_driven_batch_bounds_counts_and_certificate():
+    s = wl.small_ll(seed=13, n_atoms=6, nfunc=12, n=3, edge=14.0)
+    C = wl.quat_qr_plus(np.random.default_rng(2).standard_normal((4, 12, 3)))
+    N, n, batch = 12, 3, 2
+    Qm = oracle.schwarz(s.L)
+    pairs = [(mu, nu) for nu in range(N) for mu in range(nu + 1)]
+    mo = [(r, t) for r in range(n) for t in range(r, n)]
+    Qp = np.array([Qm[a, b] for a, b in pairs])
+    pd = {(a, b): np.abs(qalg.pair_density(C, a, b)) for a in range(N) for b in range(N)}
+    Gf, _ = oracle.transform_direct(s.L, None, C, None, "LL", 0.0)
+    tau = 3e-3
+    Gm, stm = oracle.transform_direct_mo(s.L, None, C, None, "LL", tau, batch)
+    Dall = np.array([max(pd[a, b].max(), pd[b, a].max()) for a, b in pairs])
+    kept = 0
+    w = np.zeros((len(pairs), n, n, 4))
+    for i, (a, b) in enumerate(pairs):
+        w[i] = pd[a, b].transpose(1, 2, 0) + (pd[b, a].transpose(1, 2, 0) if a != b else 0)
+    mult = np.array([1.0 if a == b else 2.0 for a, b in pairs])
+    slack = 1e-13 * np.abs(Gf).max()
+    for b0 in range(0, len(mo), batch):
+        bp = mo[b0:b0 + batch]
+        Db = np.array([max(max(pd[a, b][:, r, t].max(), pd[b, a][:, r, t].max()) for r, t in bp)
+                       for a, b in pairs])
+        assert np.all(Db <= Dall)  # a batch bound never exceeds the all-pairs bound
+        keep = (Qp[:, None] * Qp[None, :]) * Db[None, :] >= tau
+        kept += int(keep.sum())
+        bound = tau * np.einsum("ij,ipqx,j->pqx", (~keep).astype(float), w, mult)
+        for r, t in bp:
+            for a_, b_ in ((r, t), (t, r)):
+                d = np.abs(Gm[:, :, a_, b_] - Gf[:, :, a_, b_])
+                assert np.all(d <= bound[:, :, :, None] + slack)
+    assert stm["kept"][0] == kept
+    assert 0 < kept < len(pairs) ** 2 * (len(mo) + batch - 1) // batch
+    assert np.abs(Gm - Gf).max() > 100 * slack  # screening changed the result
