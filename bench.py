@@ -17,6 +17,12 @@ The JSON line also carries
                 committed rocprofv3 counter summary when it matches.
   cpu_baseline  the FP64 oracle on a seeded sample of bra pairs (first half
                 only), scaled to the whole transformation.
+  mfma_util     the first half's algorithmic FP64 flop rate over the MFMA peak.
+  mixed_vs_fp64 the same transformation with reduced-precision tiers (1e-6 /
+                1e-9, bound including the bra side), its speedup and its
+                max |G_mixed - G_fp64| (Eh).
+  serving       the request stream (256 requests, 20 ms mean gap), p50/p99.
+The last two legs are skipped with --no-legs (profiling runs).
 """
 import argparse
 import json
@@ -28,6 +34,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_MFMA = 78.6  # TFLOP/s, MI355X dense FP64 matrix
+BASELINE_METRIC = ("MO integrals/s & MFMA util, mixed vs FP64 at <=1e-10 Eh err; "
+                   "serving p99 ms")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "first_half_chain40_traffic.json")
 
 
@@ -48,12 +56,17 @@ def parse():
                          "(2 n general two-spinor MOs); replay: cluster24 (default), "
                          "chain40_dcg, chain40")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="transform: skip the mixed-precision and serving legs of the line")
     ap.add_argument("--cpu-rows", type=int, default=96)
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--serving-prec", default="fp64,mixed",
                     help="serving: precisions to serve the stream in, one run each "
                          "(mixed: tiers 1e-6 / 1e-9 with the G-bound rule)")
     ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--mo-batch", type=int, default=0,
+                    help="transform: run the MO-driven variant with batches of this many MO "
+                         "pairs, each screened with its own density bound (0: AO-driven)")
     ap.add_argument("--tune", default="auto", choices=["auto", "default"],
                     help="transform / replay: pick the plan's launch choices with the "
                          "autotuner before the untimed warm-up (auto), or keep the defaults")
@@ -138,6 +151,8 @@ def main_transform(args):
     S = qdcb.Basis(ctx, sysm.S) if sysm.S is not None else None
     plan = qdcb.Plan(ctx, L, S, sysm.ham, n, sysm.tau,
                      flags=qdcb.PLAN_SPINOR if spinor else 0)
+    if args.mo_batch:
+        plan.set_mo_batch(args.mo_batch)
     if args.copy_calibration_mib:
         src = torch.ones(args.copy_calibration_mib << 17, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -175,8 +190,9 @@ def main_transform(args):
             traffic = tr.get("bytes_per_launch")
     st0 = stats[-1]
     kind = "complex spinor" if spinor else "quaternion"
+    headline = not spinor and not args.mo_batch
     line = {
-        "metric": f"MO integrals/s ({kind} (pq|rs), FP64)",
+        "metric": BASELINE_METRIC if headline else f"MO integrals/s ({kind} (pq|rs), FP64)",
         "value": value,
         "unit": f"{kind} MO integrals (pq|rs)/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -186,7 +202,9 @@ def main_transform(args):
                    "n_atoms": int(sysm.atoms.shape[0]),
                    "N_L": sysm.L.nfunc, "N_S": sysm.S.nfunc if sysm.S is not None else 0,
                    "n_mo": n, "mo_kind": "general spinors" if spinor else "Kramers pairs",
-                   "ham": sysm.ham, "tau": sysm.tau},
+                   "ham": sysm.ham, "tau": sysm.tau,
+                   "algorithm": f"MO-driven, {args.mo_batch} MO pairs per batch"
+                   if args.mo_batch else "AO-driven"},
         "spinor_integrals_per_s": (n if spinor else 2 * n) ** 4 * args.steps / elapsed,
         "stages_ms": {k: st0[k] for k in ("ms_density", "ms_screen", "ms_eri", "ms_first_half",
                                           "ms_second_half", "ms_total")},
@@ -198,9 +216,41 @@ def main_transform(args):
                      "traffic": traffic, "launches": fh_launch,
                      "avg_launch_ms": fh_ms / max(1, fh_launch)},
     }
+    line["mfma_util"] = {"first_half": achieved / PEAK_FP64_MFMA,
+                         "basis": "algorithmic FP64 flops of k_first_half over its launch time, "
+                                  "against the dense FP64 MFMA peak"}
+    if headline and not args.no_legs:
+        # mixed precision vs FP64 on the same inputs, at tiers that meet 1e-10 Eh here
+        t32, t16 = 1e-6, 1e-9
+        mp = qdcb.Plan(ctx, L, S, sysm.ham, n, sysm.tau, prec="mixed", tier_fp32=t32,
+                       tier_bf16=t16, flags=qdcb.PLAN_TIER_BY_G)
+        mp.tune = plan.tune
+        G2 = torch.empty_like(G)
+        mp.transform(CL, CS, G2)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            _, stm = mp.transform(CL, CS, G2)
+        torch.cuda.synchronize()
+        ms_mixed = 1e3 * (time.perf_counter() - t1) / args.steps
+        err = max(float((G2[p] - G[p]).abs().max()) for p in range(n))
+        line["mixed_vs_fp64"] = {"tier_fp32": t32, "tier_bf16": t16, "rule": "g",
+                                 "ms_fp64": ms, "ms_mixed": ms_mixed, "speedup": ms / ms_mixed,
+                                 "max_abs_err_Eh": err, "meets_1e-10": err <= 1e-10,
+                                 "tiles_tier": stm["tiles_tier"]}
+        print(f"mixed leg: {ms_mixed:.1f} ms, max|dG| {err:.2e}", file=sys.stderr, flush=True)
+        mp.close()
+        del G2
     if not args.no_cpu_baseline and not spinor:
         print("cpu baseline: oracle sample ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(sysm, args.cpu_rows, n)
+    if headline and not args.no_legs:
+        # the serving stream (FP64), after this run's plan has released its memory
+        plan.close()
+        ctx.close()
+        del G
+        torch.cuda.empty_cache()
+        line["serving"] = serving_run(args, "fp64")
     print(json.dumps(line), flush=True)
 
 
@@ -336,39 +386,42 @@ def main_mixed(args):
                    "n_mo": n, "ham": sysm.ham, "tau": sysm.tau}}), flush=True)
 
 
+def serving_run(args, prec):
+    """One run of the request stream (256 requests, mean gap 20 ms, reduced
+    sizes) in one precision; eight requests re-run alone and compared bitwise."""
+    import torch
+    from paper_2606_04316_amd import serving
+    reqs = serving.request_stream(args.requests, seed=5, mean_gap_s=0.02, pool=12,
+                                  atoms=(10, 40), nl=(40, 160), n_mo=(8, 32),
+                                  radius_scale=20.0)
+    ex = serving.GpuExecutor(slots=args.slots, prec=prec)
+    budget = int(0.5 * torch.cuda.mem_get_info()[0])
+    srv = serving.Server(ex, ex.reserve, slots=args.slots, budget_bytes=budget)
+    out = srv.run(reqs)
+    ex.drain()
+    summ = serving.summarize(out)
+    print(f"serving {prec}: {summ}", file=sys.stderr, flush=True)
+    alone = serving.GpuExecutor(slots=1, prec=prec)
+    same = 0
+    for r in [r for r in out if r.error is None][:: max(1, len(out) // 8)][:8]:
+        solo = serving.Request(rid=r.rid, system=r.system, arrival=0.0)
+        solo.reserve = alone.reserve(solo)
+        same += alone(solo, 0)["digest"] == r.result["digest"]
+    alone.drain()
+    summ.update({"slots": args.slots, "max_concurrency": srv.max_concurrency,
+                 "peak_reserved_GB": srv.peak_in_use / 2 ** 30,
+                 "alone_equals_mix": f"{same}/8"})
+    if prec == "mixed":
+        summ["tiers"] = {"tier_fp32": ex.tiers[0], "tier_bf16": ex.tiers[1], "rule": "g"}
+    return summ
+
+
 def main_serving(args):
     """The request loop on a seeded Poisson stream (mean gap 20 ms); each
     request is a cluster drawn from a pool, with its own active-space size and
     Hamiltonian (DC or DCG).  Sizes are the stream recipe's reduced ranges
     (see the design doc); eight requests are re-run alone and compared bitwise."""
-    from paper_2606_04316_amd import serving
-
-    import torch
-    runs = {}
-    for prec in args.serving_prec.split(","):
-        reqs = serving.request_stream(args.requests, seed=5, mean_gap_s=0.02, pool=12,
-                                      atoms=(10, 40), nl=(40, 160), n_mo=(8, 32),
-                                      radius_scale=20.0)
-        ex = serving.GpuExecutor(slots=args.slots, prec=prec)
-        budget = int(0.5 * torch.cuda.mem_get_info()[0])
-        srv = serving.Server(ex, ex.reserve, slots=args.slots, budget_bytes=budget)
-        out = srv.run(reqs)
-        ex.drain()
-        summ = serving.summarize(out)
-        print(f"serving {prec}: {summ}", file=sys.stderr, flush=True)
-        alone = serving.GpuExecutor(slots=1, prec=prec)
-        same = 0
-        for r in [r for r in out if r.error is None][:: max(1, len(out) // 8)][:8]:
-            solo = serving.Request(rid=r.rid, system=r.system, arrival=0.0)
-            solo.reserve = alone.reserve(solo)
-            same += alone(solo, 0)["digest"] == r.result["digest"]
-        alone.drain()
-        summ.update({"max_concurrency": srv.max_concurrency,
-                     "peak_reserved_GB": srv.peak_in_use / 2 ** 30,
-                     "alone_equals_mix": f"{same}/8"})
-        if prec == "mixed":
-            summ["tiers"] = {"tier_fp32": ex.tiers[0], "tier_bf16": ex.tiers[1], "rule": "g"}
-        runs[prec] = summ
+    runs = {prec: serving_run(args, prec) for prec in args.serving_prec.split(",")}
     first = runs[next(iter(runs))]
     line = {"metric": "serving p99 latency", "mode": "serving", "value": first["p99_ms"],
             "unit": "ms", "higher_is_better": False, "slots": args.slots,

@@ -301,6 +301,17 @@ typedef struct {
 qdcb_status qdcb_plan_set_tune(qdcb_plan *plan, const qdcb_tune *tune);
 qdcb_status qdcb_plan_get_tune(const qdcb_plan *plan, qdcb_tune *tune);
 
+/* MO-driven variant, for comparison with the AO-driven transformation (the
+ * paper's Fig. 2 algorithms), quaternion plans only (QDCB_E_UNSUPPORTED for
+ * spinor plans): pairs > 0 processes the MO pairs (r <= s in the canonical
+ * order) in batches of that many, each with the density bound Dmax of its own pairs, its own
+ * screening and task lists, and its own integral tiles; the results agree
+ * with the AO-driven ones to rounding at tau = 0 and differ by what each
+ * batch's tighter bound screens at tau > 0.  stats->kept sums the batches.
+ * 0 (default) is the AO-driven transformation: one bound over all MO pairs
+ * and integral tiles computed once.  Captures are not offered for pairs > 0. */
+qdcb_status qdcb_plan_set_mo_batch(qdcb_plan *plan, int32_t pairs);
+
 /* Shape key of a plan for the tuning cache: the Hamiltonian, precision,
  * n_mo, basis sizes, largest contraction depths, tau, tile counts and the
  * device's compute-unit count, as one line of text (no quotes or newlines).

@@ -18,7 +18,8 @@
 //
 // One workgroup per pair row; the coefficient rows are staged in LDS, threads
 // stride over MO pairs and write 32 contiguous bytes each; a block reduction
-// forms Dmax.  Bound-only launches compute Dmax over all MO pairs without
+// forms Dmax.  Bound-only launches compute Dmax over a range of MO pairs (all of
+// them for the AO-driven transform, one batch for the MO-driven one) without
 // writing D; write launches fill the columns of MO pairs [i0, i1).
 #include "kernels.h"
 
@@ -62,7 +63,7 @@ __global__ void __launch_bounds__(DENS_THREADS) k_density(DensityArgs a) {
   const int64_t row = blockIdx.x;
   const int cls = a.cls[row];
   const int n = a.n;
-  const int i0 = a.bound_only ? 0 : a.i0, i1 = a.bound_only ? a.npair_mo : a.i1;
+  const int i0 = a.i0, i1 = a.i1;
   double *Drow = a.D + row * a.ld;
   if (cls < 0) {  // padding row: zero density, zero bound
     if (!a.bound_only)
@@ -118,7 +119,7 @@ __global__ void __launch_bounds__(DENS_THREADS) k_density_gaunt(DensityArgs a) {
   const int64_t row = blockIdx.x;
   const int cls = a.cls[row];
   const int n = a.n;
-  const int i0 = a.bound_only ? 0 : a.i0, i1 = a.bound_only ? a.npair_mo : a.i1;
+  const int i0 = a.i0, i1 = a.i1;
   double *Drow = a.D + row * a.ld;
   if (cls < 0) {
     if (!a.bound_only) {
@@ -199,7 +200,7 @@ __global__ void __launch_bounds__(DENS_THREADS) k_density_spinor(DensityArgs a) 
   const int64_t row = blockIdx.x;
   const int cls = a.cls[row];
   const int n = a.n;
-  const int i0 = a.bound_only ? 0 : a.i0, i1 = a.bound_only ? a.npair_mo : a.i1;
+  const int i0 = a.i0, i1 = a.i1;
   double *Drow = a.D + row * a.ld;
   if (cls < 0) {
     if (!a.bound_only)
@@ -255,7 +256,7 @@ __global__ void __launch_bounds__(DENS_THREADS) k_density_spinor_gaunt(DensityAr
   const int64_t row = blockIdx.x;
   const int cls = a.cls[row];
   const int n = a.n;
-  const int i0 = a.bound_only ? 0 : a.i0, i1 = a.bound_only ? a.npair_mo : a.i1;
+  const int i0 = a.i0, i1 = a.i1;
   double *Drow = a.D + row * a.ld;
   if (cls < 0) {
     if (!a.bound_only) {

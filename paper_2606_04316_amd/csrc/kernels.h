@@ -38,11 +38,11 @@ void launch_eri_list(int64_t nq, const int64_t *a_first, const int64_t *b_first,
 // ---- densities (k_density.hip)
 struct DensityArgs {
   int gaunt;              // 0: Coulomb rows (LL/SS), 1: Gaunt rows (LS)
-  int bound_only;         // 1: Dmax over all MO pairs, no D writes
+  int bound_only;         // 1: Dmax over the MO pairs [i0, i1), no D writes
   int64_t nrows;          // padded pair rows
   int n;                  // MOs
   int npair_mo;           // n(n+1)/2
-  int i0, i1;             // MO-pair range written (write launches)
+  int i0, i1;             // MO-pair range written (or bounded)
   int64_t ld;             // row stride of D
   int64_t ldK;            // Gaunt: stride between the K blocks of a row
   const int32_t *cls;     // [nrows] 0 = L, 1 = S (Gaunt: 0), -1 = padding

@@ -182,6 +182,7 @@ void size_plan(qdcb_plan &p, int64_t slotsC, int64_t slotsG) {
     if (sp == &p.G && !p.gaunt) continue;
     sp->ldK = round_up(4 * ci, 128);
     sp->ld = sp->nK * sp->ldK;
+    sp->ld_cap = sp->ld;
     sp->D.alloc(ctx, (size_t)sp->Ppad * sp->ld);
     HIPC(hipMemset(sp->D.p, 0, sp->D.bytes()));
     sp->V.alloc(ctx, (size_t)sp->Ppad * sp->ld);

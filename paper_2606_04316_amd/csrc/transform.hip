@@ -121,7 +121,7 @@ void density(qdcb_plan &p, Space &sp, const double *dCL, const double *dCS, int 
 // Captured: device-side scan, one batch of at most panel_slots tiles.  When
 // every directed tile fits the panel (and the plan allows it), the unique
 // tile pairs are listed as well, each with its two directed slots.
-void screen(qdcb_plan &p, Space &sp, bool captured, hipStream_t s) {
+void screen(qdcb_plan &p, Space &sp, bool captured, hipStream_t s, bool zero_kept = true) {
   const bool want_sym = !(p.desc.flags & QDCB_PLAN_DIRECTED_TILES);
   launch_tile_bounds(sp.ntiles, sp.Q.p, sp.Dmax.p, sp.Qmax.p, sp.Bmax.p, sp.Dtmax.p, s);
   launch_screen_count(sp.ntiles, sp.Qmax.p, sp.Bmax.p, p.desc.tau, sp.count.p, s);
@@ -146,7 +146,7 @@ void screen(qdcb_plan &p, Space &sp, bool captured, hipStream_t s) {
   }
   launch_screen_fill(0, sp.ntiles, sp.ntiles, sp.Qmax.p, sp.Bmax.p, p.desc.tau, sp.slot_base.p,
                      sp.tasks.p, sp.task_bra.p, s);
-  launch_zero_u64(sp.kept.p, 4, s);
+  if (zero_kept) launch_zero_u64(sp.kept.p, 4, s);
   HIPC(hipGetLastError());
   if (p.desc.prec == QDCB_PREC_MIXED) {
     launch_tier_split(sp.ntiles, sp.Qmax.p, sp.Bmax.p,
@@ -558,18 +558,40 @@ void enqueue(qdcb_plan &p, const double *dCL, const double *dCS, double *dG, boo
       }
   }
   HIPC(hipGetLastError());
+  // MO-driven variant: batches of mo_batch MO pairs, each screened with the
+  // density bound of its own pairs and with its own integral tiles (the
+  // panels, sized for the all-pairs bound above, hold every batch's subset)
+  const bool mo = p.mo_batch > 0 && !captured;
+  const int step = mo ? std::min(p.ci, p.mo_batch) : p.ci;
   for (int i0 = 0, k = 0; i0 < p.npair_mo && (tm.max_chunks <= 0 || k < tm.max_chunks);
-       i0 += p.ci, ++k) {
-    const int i1 = std::min(p.npair_mo, i0 + p.ci);
+       i0 += step, ++k) {
+    const int i1 = std::min(p.npair_mo, i0 + step);
     p.v_i0 = i0;
     p.v_i1 = i1;
+    // D~ and V rows packed to this chunk's width: a narrower chunk (the last
+    // one, or an MO-driven batch) contracts only its own column tiles
+    for (Space *sp : spaces) {
+      sp->ldK = round_up(4LL * (i1 - i0), 128);
+      sp->ld = sp->nK * sp->ldK;
+      if (sp->ld > sp->ld_cap) fail(QDCB_E_DEVICE, "column chunk wider than its buffers");
+    }
+    if (mo)
+      for (Space *sp : spaces) {
+        tm.begin(ST_DENS);
+        density(p, *sp, dCL, dCS, 1, i0, i1, s);
+        tm.end();
+        tm.begin(ST_SCREEN);
+        screen(p, *sp, false, s, false);  // kept counts add up over the batches
+        tm.end();
+        sp->sym = !(p.desc.flags & QDCB_PLAN_DIRECTED_TILES) && sp->total <= sp->panel_slots;
+      }
     for (Space *sp : spaces) {
       tm.begin(ST_DENS);
       density(p, *sp, dCL, dCS, 0, i0, i1, s);
       tm.end();
       // captured mode keeps the tiles of the first chunk (one batch, resident)
       const bool resident = captured || sp->sym || sp->total <= sp->panel_slots;
-      first_half(p, *sp, !resident || i0 == 0, i0 == 0, captured, tm, s);
+      first_half(p, *sp, mo || !resident || i0 == 0, mo || i0 == 0, captured, tm, s);
     }
     tm.begin(ST_SH);
     second_half(p, i0, i1, dG, s, classes, sink);
@@ -866,6 +888,7 @@ qdcb_status qdcb_plan_capture(qdcb_plan *plan, const double *CL, const double *C
     if (!plan || !CL || !G || !hip_stream) fail(QDCB_E_INVALID, "NULL argument");
     qdcb_plan &p = *plan;
     PlanUse use(p);
+    if (p.mo_batch > 0) fail(QDCB_E_UNSUPPORTED, "the MO-driven variant is not captured");
     if (p.NS && !CS) fail(QDCB_E_INVALID, "CS is required for this Hamiltonian");
     DeviceGuard g(p.ctx->device);
     hipStream_t s = (hipStream_t)hip_stream;

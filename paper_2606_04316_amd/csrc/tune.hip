@@ -58,6 +58,16 @@ qdcb_status qdcb_plan_get_tune(const qdcb_plan *p, qdcb_tune *t) {
   });
 }
 
+qdcb_status qdcb_plan_set_mo_batch(qdcb_plan *p, int32_t pairs) {
+  return guarded([&] {
+    if (!p) fail(QDCB_E_INVALID, "NULL argument");
+    PlanUse use(*p);
+    if (pairs < 0) fail(QDCB_E_INVALID, "pairs must be >= 0");
+    if (pairs > 0 && p->spinor) fail(QDCB_E_UNSUPPORTED, "the MO-driven variant is for quaternion plans");
+    p->mo_batch = pairs;
+  });
+}
+
 qdcb_status qdcb_plan_tune_key(const qdcb_plan *p, char *buf, size_t len) {
   return guarded([&] {
     if (!p || !buf) fail(QDCB_E_INVALID, "NULL argument");

@@ -131,6 +131,7 @@ def lib():
         L.qdcb_plan_fetch_v.argtypes = [_P, _P, ctypes.c_int64, _P]
         L.qdcb_transform_blocks.argtypes = [_P, _P, _P, BLOCK_CB, _P, ctypes.c_uint32, _P,
                                             ctypes.POINTER(Stats)]
+        L.qdcb_plan_set_mo_batch.argtypes = [_P, ctypes.c_int32]
         L.qdcb_plan_set_tune.argtypes = [_P, ctypes.POINTER(Tune)]
         L.qdcb_plan_get_tune.argtypes = [_P, ctypes.POINTER(Tune)]
         L.qdcb_plan_tune_key.argtypes = [_P, ctypes.c_char_p, ctypes.c_size_t]
@@ -146,7 +147,7 @@ def lib():
                   "qdcb_plan_capture", "qdcb_plan_replay", "qdcb_plan_fetch_v",
                   "qdcb_plan_set_tune", "qdcb_plan_get_tune", "qdcb_plan_tune_key",
                   "qdcb_tune_cache_lookup", "qdcb_tune_cache_store", "qdcb_plan_autotune",
-                  "qdcb_transform_blocks"):
+                  "qdcb_transform_blocks", "qdcb_plan_set_mo_batch"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -357,6 +358,11 @@ class Plan:
         cur.update(d)
         t = Tune(int(cur["eri_sched"]), int(cur["fh_order"]), int(cur["sq_tile"]), 0)
         _check(lib().qdcb_plan_set_tune(self.h, ctypes.byref(t)))
+
+    def set_mo_batch(self, pairs: int):
+        """MO-driven variant: batches of ``pairs`` MO pairs, each screened with
+        its own density bound (0: the AO-driven transformation)."""
+        _check(lib().qdcb_plan_set_mo_batch(self.h, int(pairs)))
 
     def tune_key(self) -> str:
         buf = ctypes.create_string_buffer(512)
