@@ -190,9 +190,10 @@ typedef struct {
     int64_t tiles_total;
     double flops_first_half; /* algorithmic: 2 * columns * kept contributions */
     double flops_second_half;
-    double flops_mfma;       /* MFMA flops issued by the first-half kernel (incl. masked) */
+    double flops_mfma;       /* MFMA flops issued by the first-half kernel (incl. masked
+                                elements of kept tiles), summed over the column chunks */
     int32_t n_batches;       /* first-half kernel launches */
-    int32_t n_chunks;        /* MO-pair column chunks */
+    int32_t n_chunks;        /* MO-pair column chunks (MO-driven variant: batches) */
     int32_t graph_replay;    /* 1: produced by qdcb_plan_replay */
     int32_t graph_fallback;  /* 1: the replay's kept tiles outgrew the panel; redone eagerly */
     int64_t tiles_made;      /* integral tiles generated (unique or directed, all chunks) */

@@ -86,6 +86,11 @@ struct qdcb_plan {
   int npair_s = 0;
   int ci = 0;        // MO pairs (spinor mode: groups) per column chunk of the first half
   int mo_batch = 0;  // > 0: MO-driven variant, batches of that many MO pairs
+  // first-half MFMA work of the last enqueued transform: row widths summed over
+  // the chunks per space, and (MO-driven) width x kept tiles summed per batch
+  double ld_sum[2] = {0.0, 0.0};
+  double mo_work = 0.0;
+  int chunks_run = 0;  // column chunks (MO-driven: batches) of the last transform
   int sc = 0;        // columns per second-half slice
   bool gaunt = false;
   qdcb_tune tune{};       // launch choices (tile shapes, schedules)

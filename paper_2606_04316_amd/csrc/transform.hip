@@ -563,11 +563,15 @@ void enqueue(qdcb_plan &p, const double *dCL, const double *dCS, double *dG, boo
   // panels, sized for the all-pairs bound above, hold every batch's subset)
   const bool mo = p.mo_batch > 0 && !captured;
   const int step = mo ? std::min(p.ci, p.mo_batch) : p.ci;
+  p.ld_sum[0] = p.ld_sum[1] = 0.0;
+  p.mo_work = 0.0;
+  p.chunks_run = 0;
   for (int i0 = 0, k = 0; i0 < p.npair_mo && (tm.max_chunks <= 0 || k < tm.max_chunks);
        i0 += step, ++k) {
     const int i1 = std::min(p.npair_mo, i0 + step);
     p.v_i0 = i0;
     p.v_i1 = i1;
+    ++p.chunks_run;
     // D~ and V rows packed to this chunk's width: a narrower chunk (the last
     // one, or an MO-driven batch) contracts only its own column tiles
     for (Space *sp : spaces) {
@@ -586,6 +590,8 @@ void enqueue(qdcb_plan &p, const double *dCL, const double *dCS, double *dG, boo
         sp->sym = !(p.desc.flags & QDCB_PLAN_DIRECTED_TILES) && sp->total <= sp->panel_slots;
       }
     for (Space *sp : spaces) {
+      p.ld_sum[sp == &p.G ? 1 : 0] += (double)sp->ld;
+      if (mo) p.mo_work += (double)sp->ld * (double)sp->total;
       tm.begin(ST_DENS);
       density(p, *sp, dCL, dCS, 0, i0, i1, s);
       tm.end();
@@ -645,10 +651,13 @@ void fill_stats(qdcb_plan &p, qdcb_stats *stats, StageTimer *tm, double ms_total
     f2 += 3.0 * (16.0 * p.NL * (double)p.NS * n + sq * (p.NL + p.NS) * (double)n * n) *
           (double)p.ncol;
   stats->flops_second_half = f2;
-  const int nchunks = (p.npair_mo + p.ci - 1) / p.ci;
-  stats->n_chunks = nchunks;
-  stats->flops_mfma = 2.0 * TILE * TILE * nchunks *
-                      ((double)p.C.ld * tiles_c + (p.gaunt ? (double)p.G.ld * tiles_g : 0.0));
+  stats->n_chunks = p.chunks_run;
+  // MFMA flops issued by the first half: every kept directed tile times the
+  // row width of each chunk (per batch for the MO-driven variant)
+  stats->flops_mfma = 2.0 * TILE * TILE *
+                      (p.mo_batch > 0 && tm ? p.mo_work
+                                            : p.ld_sum[0] * (double)tiles_c +
+                                                  p.ld_sum[1] * (double)tiles_g);
   stats->classes = p.classes;
   if (p.desc.prec == QDCB_PREC_MIXED) {
     for (Space *sp : {&p.C, &p.G}) {
