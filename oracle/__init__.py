@@ -15,7 +15,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-HAMS = {"LL": 0, "DC": 1, "DCG": 2, "GAUNT": 3}
+HAMS = {"LL": 0, "DC": 1, "DCG": 2, "GAUNT": 3, "DCB": 4, "GAUGE": 5}
+# hams with L-S (Gaunt-class) rows
+LS_HAMS = ("DCG", "GAUNT", "DCB", "GAUGE")
 
 
 def build(verbose: bool = False) -> str:
@@ -64,6 +66,10 @@ def lib():
         bp = ctypes.POINTER(_Basis)
         L.orc_boys0.restype = ctypes.c_double
         L.orc_boys0.argtypes = [ctypes.c_double]
+        L.orc_boys.restype = ctypes.c_double
+        L.orc_boys.argtypes = [ctypes.c_int, ctypes.c_double]
+        L.orc_eri3.argtypes = [bp, ctypes.c_int, bp, ctypes.c_int, bp, ctypes.c_int, bp,
+                               ctypes.c_int, dp]
         L.orc_norm_coefs.argtypes = [bp, dp]
         L.orc_eri.restype = ctypes.c_double
         L.orc_eri.argtypes = [bp, ctypes.c_int, ctypes.c_int, bp, ctypes.c_int, ctypes.c_int]
@@ -117,6 +123,18 @@ class _B:
 
 def boys0(T: float) -> float:
     return lib().orc_boys0(float(T))
+
+
+def boys(m: int, T: float) -> float:
+    return lib().orc_boys(int(m), float(T))
+
+
+def eri3(A, mu, B, nu, C, ka, D, la) -> np.ndarray:
+    """(mu^A nu^B | r_K r_L / r^3 | ka^C la^D) as a 3 x 3 array [K][L]."""
+    a, b, c, d = _B(A), _B(B), _B(C), _B(D)
+    out = np.zeros(9)
+    lib().orc_eri3(a.ref, int(mu), b.ref, int(nu), c.ref, int(ka), d.ref, int(la), _dp(out))
+    return out.reshape(3, 3)
 
 
 def norm_coefs(b) -> np.ndarray:
@@ -249,7 +267,7 @@ def first_half_rows(L, S, CL, CS, ham: str, tau: float, rows) -> np.ndarray:
     sel = np.ascontiguousarray(rows, dtype=np.int64)
     n = CL.shape[2]
     npair = n * (n + 1) // 2
-    width = (3 if ham in ("DCG", "GAUNT") else 1) * 4 * npair
+    width = (3 if ham in LS_HAMS else 1) * 4 * npair
     Vq = np.zeros((sel.shape[0], width))
     rc = lib().orc_first_half_rows(bl.ref, bs.ref if bs else None, _dp(CL),
                                    _dp(CS) if CS is not None else None, n, HAMS[ham],
@@ -295,8 +313,8 @@ def dmax_batch(L, S, CL, CS, ham: str, mo_pairs) -> np.ndarray:
     of conj(C^L_mr) e_K C^S_nt + conj(C^S_nr) e_K C^L_mt over K and the batch
     (Eq. SchwarzDen restricted to the batch's MO pairs)."""
     out = []
-    coul = ham != "GAUNT"
-    gaunt = ham in ("DCG", "GAUNT")
+    coul = ham in ("LL", "DC", "DCG", "DCB")
+    gaunt = ham in LS_HAMS
 
     def coul_block(C):
         N = C.shape[1]

@@ -3,15 +3,17 @@
 An independent second implementation for tiny bases: its own primitive
 normalization, its own ERIs (scipy's erf rather than the C library's), and
 the MO integrals as one unfactored sum over all AO and spinor indices of the
-definitions in Eqs. (AOtoMO), (DCInt), (GauntInt) with the four-spinor
-operators of Eq. (breit) and the alpha/Pauli matrices as printed in Sec. 2.
+definitions in Eqs. (AOtoMO), (DCInt), (GauntInt), (gaugeInt) with the
+four-spinor operators of Eq. (breit) and the alpha/Pauli matrices as printed
+in Sec. 2.  The gauge term's r r^T / r^3 integrals take the Boys functions
+F1, F2 from scipy's regularized incomplete gamma function.
 """
 from __future__ import annotations
 
 import math
 
 import numpy as np
-from scipy.special import erf
+from scipy.special import erf, gamma, gammainc
 
 PAULI = [np.array([[0, 1], [1, 0]], dtype=complex),
          np.array([[0, -1j], [1j, 0]], dtype=complex),
@@ -50,9 +52,22 @@ def _boys0(T):
     return out
 
 
-def eri_tensor(funcs) -> np.ndarray:
+def _boys(m, T):
+    """F_m(T) = Gamma(m + 1/2) P(m + 1/2, T) / (2 T^(m + 1/2)), 1 / (2m + 1) at 0."""
+    T = np.asarray(T, dtype=float)
+    out = np.full_like(T, 1.0 / (2 * m + 1))
+    big = T > 1e-13
+    a = m + 0.5
+    out[big] = gamma(a) * gammainc(a, T[big]) / (2 * T[big] ** a)
+    return out
+
+
+def eri_tensor(funcs, kernel3: bool = False) -> np.ndarray:
+    """Contracted (ij|kl); kernel3: the r_K r_L / r^3 integrals [K][L][i][j][k][l]
+    = 2 pi^{5/2} / (p q sqrt(p+q)) K_ab K_cd (delta_KL F1 + 2 rho R_K R_L (F1 - F2))
+    summed over primitives, R = P - Q."""
     n = len(funcs)
-    out = np.zeros((n, n, n, n))
+    out = np.zeros((3, 3, n, n, n, n) if kernel3 else (n, n, n, n))
     for i in range(n):
         A, a, ca = funcs[i]
         for j in range(n):
@@ -71,11 +86,25 @@ def eri_tensor(funcs) -> np.ndarray:
                     ccd = cc[:, None] * cd[None, :] * Kcd
                     pp = p[:, :, None, None]
                     qq = q[None, None, :, :]
-                    R2 = np.sum((P[:, :, None, None, :] - Qc[None, None, :, :, :]) ** 2, axis=-1)
-                    T = pp * qq / (pp + qq) * R2
-                    val = 2 * math.pi ** 2.5 / (pp * qq * np.sqrt(pp + qq)) * _boys0(T)
-                    out[i, j, k, l] = np.sum(cab[:, :, None, None] * ccd[None, None] * val)
+                    Rv = P[:, :, None, None, :] - Qc[None, None, :, :, :]
+                    R2 = np.sum(Rv ** 2, axis=-1)
+                    rho = pp * qq / (pp + qq)
+                    T = rho * R2
+                    pref = 2 * math.pi ** 2.5 / (pp * qq * np.sqrt(pp + qq))
+                    w = cab[:, :, None, None] * ccd[None, None]
+                    if not kernel3:
+                        out[i, j, k, l] = np.sum(w * pref * _boys0(T))
+                        continue
+                    F1, F2 = _boys(1, T), _boys(2, T)
+                    for K in range(3):
+                        for L in range(3):
+                            v = (K == L) * F1 + 2 * rho * Rv[..., K] * Rv[..., L] * (F1 - F2)
+                            out[K, L, i, j, k, l] = np.sum(w * pref * v)
     return out
+
+
+def levi(i, j, k) -> int:
+    return (i - j) * (j - k) * (k - i) // 2
 
 
 def spinor4(CL, CS):
@@ -117,9 +146,22 @@ def spinor_integrals(L, S, CL, CS, ham: str, general: bool = False) -> np.ndarra
     c4 = make(CL, CS if ham != "LL" else None)
     cc = c4.conj()
     out = 0
-    if ham in ("LL", "DC", "DCG"):
+    if ham in ("LL", "DC", "DCG", "DCB"):
         out = out + np.einsum("iwa,jwb,ijkl,kvc,lvd->abcd", cc, c4, eri, cc, c4, optimize=False)
-    if ham in ("DCG", "GAUNT"):
+    if ham in ("DCB", "GAUGE"):
+        # (alpha_1 x r) . (alpha_2 x r) / (2 r^3), the cross products by components
+        e3 = eri_tensor(funcs, kernel3=True)
+        for j in range(3):
+            for l in range(3):
+                N = 0
+                for i in range(3):
+                    for k in range(3):
+                        for k2 in range(3):
+                            if levi(i, j, k) and levi(i, l, k2):
+                                N = N + 0.5 * levi(i, j, k) * levi(i, l, k2) * e3[k, k2]
+                out = out + np.einsum("iwa,wu,jub,ijkl,kvc,vt,ltd->abcd", cc, alpha(j), c4, N,
+                                      cc, alpha(l), c4, optimize=False)
+    if ham in ("DCG", "GAUNT", "DCB"):
         for K in range(3):
             aK = alpha(K)
             out = out - np.einsum("iwa,wu,jub,ijkl,kvc,vt,ltd->abcd", cc, aK, c4, eri, cc, aK,

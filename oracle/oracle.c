@@ -8,7 +8,11 @@
  * Paper references (arXiv 2606.04316):
  *   Sec. 2, notation           alpha_K = [[0, sigma_K], [sigma_K, 0]] and the
  *                              Pauli matrices as printed.
- *   Eq. (breit)                Gaunt (magnetic) term -alpha_1 . alpha_2 / r12.
+ *   Eq. (breit)                Gaunt (magnetic) term -alpha_1 . alpha_2 / r12
+ *                              and the gauge term
+ *                              (alpha_1 x r12) . (alpha_2 x r12) / (2 r12^3).
+ *   Eq. (gaugeInt)             the gauge integrals: L/S classes of the
+ *                              r12 r12^T / r12^3 kernel.
  *   Eqs. (Lspinor), (Sspinor)  two-spinor expansions of the L and S parts.
  *   Eq. (AOtoMO), (DCInt),     the MO integrals as sums over AO integrals and
  *   (GauntInt)                 the L/S class decomposition.
@@ -48,6 +52,27 @@ double orc_boys0(double T)
 {
     if (T < 1e-12) return 1.0 - T / 3.0;
     return 0.5 * sqrt(M_PI / T) * erf(sqrt(T));
+}
+
+/* F_m(T) = int_0^1 u^{2m} exp(-T u^2) du.  Below T = 30 from the series of
+ * positive terms F_m(T) = exp(-T) sum_k (2T)^k / ((2m+1)(2m+3)...(2m+2k+1));
+ * from T = 30 on, upward from the erf form of F0 by
+ * F_{j+1} = ((2j+1) F_j - exp(-T)) / (2T), where exp(-T) is negligible next
+ * to the terms it is subtracted from. */
+double orc_boys(int m, double T)
+{
+    if (T < 30.0) {
+        double term = 1.0 / (2 * m + 1), sum = term;
+        for (int k = 1; k < 400; ++k) {
+            term *= 2.0 * T / (2 * m + 2 * k + 1);
+            sum += term;
+            if (term < 1e-18 * sum) break;
+        }
+        return exp(-T) * sum;
+    }
+    double f = orc_boys0(T), e = exp(-T);
+    for (int j = 0; j < m; ++j) f = ((2 * j + 1) * f - e) / (2.0 * T);
+    return f;
 }
 
 static int64_t *prim_offsets(const orc_basis *b)
@@ -97,6 +122,37 @@ static double prim_eri(double a, const double *A, double b, const double *B, dou
            exp(-c * d / q * rcd2) * orc_boys0(T);
 }
 
+/* Primitive integrals of the kernel r12_K r12_L / r12^3 (the gauge
+ * integrals' kernel, Eq. (gaugeInt)) over unnormalized s Gaussians:
+ *   [ab|K L|cd] = 2 pi^{5/2} / (p q sqrt(p+q)) K_ab K_cd
+ *                 (delta_KL F1(T) + 2 rho R_K R_L (F1(T) - F2(T))),
+ * R = P - Q, rho = p q / (p + q), T = rho R^2.  Derivation: write
+ * 1/r^3 = (4/sqrt(pi)) int_0^inf s^2 exp(-s^2 r^2) ds, integrate the
+ * Gaussian product over the electron coordinates, and substitute
+ * t^2 = s^2 / (rho + s^2), which turns the s integral into Boys functions.
+ * The trace over K = L is the Coulomb integral (3 F1 + 2T (F1 - F2) = F0). */
+static void prim_eri3(double a, const double *A, double b, const double *B, double c,
+                      const double *C, double d, const double *D, double out[9])
+{
+    double p = a + b, q = c + d, R[3];
+    double rab2 = 0, rcd2 = 0, rpq2 = 0;
+    for (int k = 0; k < 3; ++k) {
+        double P = (a * A[k] + b * B[k]) / p;
+        double Q = (c * C[k] + d * D[k]) / q;
+        rab2 += (A[k] - B[k]) * (A[k] - B[k]);
+        rcd2 += (C[k] - D[k]) * (C[k] - D[k]);
+        R[k] = P - Q;
+        rpq2 += R[k] * R[k];
+    }
+    double rho = p * q / (p + q), T = rho * rpq2;
+    double pre = 2.0 * pow(M_PI, 2.5) / (p * q * sqrt(p + q)) * exp(-a * b / p * rab2) *
+                 exp(-c * d / q * rcd2);
+    double F1 = orc_boys(1, T), F2 = orc_boys(2, T);
+    for (int K = 0; K < 3; ++K)
+        for (int L = 0; L < 3; ++L)
+            out[K * 3 + L] = pre * ((K == L ? F1 : 0.0) + 2.0 * rho * R[K] * R[L] * (F1 - F2));
+}
+
 /* Contracted ERI with per-basis normalized coefficient arrays. */
 static double eri4(const orc_basis *A, const double *nA, const int64_t *oA, int i,
                    const orc_basis *B, const double *nB, const int64_t *oB, int j,
@@ -113,6 +169,25 @@ static double eri4(const orc_basis *A, const double *nA, const int64_t *oA, int 
                                   B->centers + 3 * j, C->exps[pk], C->centers + 3 * k,
                                   D->exps[pl], D->centers + 3 * l);
     return s;
+}
+
+/* Contracted r12 r12^T / r12^3 integrals, out[K * 3 + L]. */
+static void eri4_3(const orc_basis *A, const double *nA, const int64_t *oA, int i,
+                   const orc_basis *B, const double *nB, const int64_t *oB, int j,
+                   const orc_basis *C, const double *nC, const int64_t *oC, int k,
+                   const orc_basis *D, const double *nD, const int64_t *oD, int l, double out[9])
+{
+    for (int c = 0; c < 9; ++c) out[c] = 0.0;
+    for (int64_t pi = oA[i]; pi < oA[i + 1]; ++pi)
+        for (int64_t pj = oB[j]; pj < oB[j + 1]; ++pj)
+            for (int64_t pk = oC[k]; pk < oC[k + 1]; ++pk)
+                for (int64_t pl = oD[l]; pl < oD[l + 1]; ++pl) {
+                    double t[9], w = nA[pi] * nB[pj] * nC[pk] * nD[pl];
+                    prim_eri3(A->exps[pi], A->centers + 3 * i, B->exps[pj], B->centers + 3 * j,
+                              C->exps[pk], C->centers + 3 * k, D->exps[pl], D->centers + 3 * l,
+                              t);
+                    for (int c = 0; c < 9; ++c) out[c] += w * t[c];
+                }
 }
 
 typedef struct {
@@ -143,6 +218,24 @@ static double nb_eri(const nbasis *A, int i, const nbasis *B, int j, const nbasi
 {
     return eri4(A->b, A->nc, A->off, i, B->b, B->nc, B->off, j, C->b, C->nc, C->off, k, D->b,
                 D->nc, D->off, l);
+}
+
+static void nb_eri3(const nbasis *A, int i, const nbasis *B, int j, const nbasis *C, int k,
+                    const nbasis *D, int l, double out[9])
+{
+    eri4_3(A->b, A->nc, A->off, i, B->b, B->nc, B->off, j, C->b, C->nc, C->off, k, D->b, D->nc,
+           D->off, l, out);
+}
+
+void orc_eri3(const orc_basis *A, int mu, const orc_basis *B, int nu, const orc_basis *C, int ka,
+              const orc_basis *D, int la, double out[9])
+{
+    nbasis a = nb_make(A), b = nb_make(B), c = nb_make(C), d = nb_make(D);
+    nb_eri3(&a, mu, &b, nu, &c, ka, &d, la, out);
+    nb_free(&a);
+    nb_free(&b);
+    nb_free(&c);
+    nb_free(&d);
 }
 
 double orc_eri(const orc_basis *A, int mu, int nu, const orc_basis *B, int ka, int la)
@@ -182,6 +275,16 @@ void orc_schwarz(const orc_basis *A, const orc_basis *B, double *Q)
     nb_free(&a);
     nb_free(&b);
 }
+
+/* Terms of each ham code: 0 LL, 1 DC, 2 DCG, 3 Gaunt alone, 4 DCB (DC + Gaunt
+ * + gauge), 5 gauge alone. */
+static int ham_coulomb(int ham) { return ham == 0 || ham == 1 || ham == 2 || ham == 4; }
+static int ham_ls(int ham) { return ham >= 2 && ham <= 5; }
+static int ham_gaunt(int ham) { return ham == 2 || ham == 3 || ham == 4; }
+static int ham_gauge(int ham) { return ham == 4 || ham == 5; }
+
+/* Levi-Civita symbol over {0, 1, 2} = {x, y, z}. */
+static int levi(int i, int j, int k) { return (i - j) * (j - k) * (k - i) / 2; }
 
 /* ------------------------------------------------------------------------ */
 /* Quaternions, the 2x2 spinor representation and Pauli matrices              */
@@ -383,9 +486,11 @@ static int def_impl(const orc_basis *L, const orc_basis *S, const double *CL, co
                     double *imag_max)
 {
     int with_S = (ham != 0);
+    if (ham < 0 || ham > 5) return -1;
     if (with_S && (!S || !CS)) return -1;
     int NL = L->nfunc, NS = with_S ? S->nfunc : 0, NF = NL + NS, m = general ? n : 2 * n;
     if (NF > 64 || m > 64 || n <= 0) return -1;
+    if (ham_gauge(ham) && NF > 32) return -1;
 
     /* combined scalar basis */
     nbasis bl = nb_make(L), bs;
@@ -423,12 +528,12 @@ static int def_impl(const orc_basis *L, const orc_basis *S, const double *CL, co
     cplx ops[4][4][4];
     double w[4];
     int nops = 0;
-    if (ham != 3) { /* Coulomb: identity */
+    if (ham_coulomb(ham)) { /* Coulomb: identity */
         memset(ops[nops], 0, sizeof(ops[nops]));
         for (int d = 0; d < 4; ++d) ops[nops][d][d] = 1;
         w[nops++] = 1.0;
     }
-    if (ham >= 2) { /* Gaunt: -sum_K alpha_K x alpha_K */
+    if (ham_gaunt(ham)) { /* Gaunt: -sum_K alpha_K x alpha_K */
         for (int K = 0; K < 3; ++K) {
             const cplx *sg = pauli(K);
             memset(ops[nops], 0, sizeof(ops[nops]));
@@ -476,6 +581,84 @@ static int def_impl(const orc_basis *L, const orc_basis *S, const double *CL, co
                 for (size_t cd = 0; cd < m2; ++cd) sp[ab * m2 + cd] += t * X[ij * m2 + cd];
             }
     }
+    if (ham_gauge(ham)) {
+        /* Gauge term, Eq. (breit): (alpha_1 x r) . (alpha_2 x r) / (2 r^3)
+         *   = sum_{j,l} alpha_1j alpha_2l N_jl,
+         *   N_jl = (1/2) sum_{i,k,k'} eps_ijk eps_ilk' r_k r_k' / r^3,
+         * the cross products written out component by component; the AO
+         * integrals of r_k r_k' / r^3 are those of Eq. (gaugeInt). */
+        double *e3 = (double *)malloc(sizeof(double) * 9 * nf2 * nf2);
+#pragma omp parallel for schedule(dynamic)
+        for (int i = 0; i < NF; ++i)
+            for (int j = 0; j < NF; ++j)
+                for (int k = 0; k < NF; ++k)
+                    for (int l = 0; l < NF; ++l) {
+                        double t[9];
+                        nb_eri3(fb[i], fi[i], fb[j], fi[j], fb[k], fi[k], fb[l], fi[l], t);
+                        size_t q = ((size_t)i * NF + j) * nf2 + (size_t)k * NF + l;
+                        for (int c = 0; c < 9; ++c) e3[(size_t)c * nf2 * nf2 + q] = t[c];
+                    }
+        /* alpha_K densities T^K_{ij,ab} of each electron */
+        cplx *TA = (cplx *)malloc(sizeof(cplx) * 3 * nf2 * m2);
+        for (int K = 0; K < 3; ++K) {
+            const cplx *sg = pauli(K);
+            cplx al[4][4];
+            memset(al, 0, sizeof(al));
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                    al[a][2 + b] = sg[a * 2 + b];
+                    al[2 + a][b] = sg[a * 2 + b];
+                }
+            cplx *TK = TA + (size_t)K * nf2 * m2;
+#pragma omp parallel for schedule(static)
+            for (int i = 0; i < NF; ++i)
+                for (int j = 0; j < NF; ++j)
+                    for (int a = 0; a < m; ++a)
+                        for (int b = 0; b < m; ++b) {
+                            cplx v = 0;
+                            for (int u = 0; u < 4; ++u)
+                                for (int w2 = 0; w2 < 4; ++w2)
+                                    v += conj(c4[((size_t)i * 4 + u) * m + a]) * al[u][w2] *
+                                         c4[((size_t)j * 4 + w2) * m + b];
+                            TK[((size_t)i * NF + j) * m2 + (size_t)a * m + b] = v;
+                        }
+        }
+        double *N = (double *)malloc(sizeof(double) * nf2 * nf2);
+        for (int j = 0; j < 3; ++j)
+            for (int l = 0; l < 3; ++l) {
+                double wt[9];
+                for (int k = 0; k < 3; ++k)
+                    for (int k2 = 0; k2 < 3; ++k2) {
+                        wt[k * 3 + k2] = 0.0;
+                        for (int i = 0; i < 3; ++i)
+                            wt[k * 3 + k2] += 0.5 * levi(i, j, k) * levi(i, l, k2);
+                    }
+                for (size_t q = 0; q < nf2 * nf2; ++q) {
+                    double v = 0.0;
+                    for (int c = 0; c < 9; ++c)
+                        if (wt[c] != 0.0) v += wt[c] * e3[(size_t)c * nf2 * nf2 + q];
+                    N[q] = v;
+                }
+                const cplx *Tj = TA + (size_t)j * nf2 * m2, *Tl = TA + (size_t)l * nf2 * m2;
+#pragma omp parallel for schedule(static)
+                for (size_t ij = 0; ij < nf2; ++ij) {
+                    for (size_t cd = 0; cd < m2; ++cd) X[ij * m2 + cd] = 0;
+                    for (size_t kl = 0; kl < nf2; ++kl) {
+                        double e = N[ij * nf2 + kl];
+                        for (size_t cd = 0; cd < m2; ++cd) X[ij * m2 + cd] += e * Tl[kl * m2 + cd];
+                    }
+                }
+#pragma omp parallel for schedule(static)
+                for (size_t ab = 0; ab < m2; ++ab)
+                    for (size_t ij = 0; ij < nf2; ++ij) {
+                        cplx t = Tj[ij * m2 + ab];
+                        for (size_t cd = 0; cd < m2; ++cd) sp[ab * m2 + cd] += t * X[ij * m2 + cd];
+                    }
+            }
+        free(N);
+        free(TA);
+        free(e3);
+    }
     if (G) project_G(n, sp, G, imag_max);
     if (spinor_out) memcpy(spinor_out, sp, sizeof(cplx) * m2 * m2);
 
@@ -513,8 +696,8 @@ int64_t orc_num_bra_pairs(const orc_basis *L, const orc_basis *S, int ham)
 {
     int64_t NL = L->nfunc, NS = (S && ham != 0) ? S->nfunc : 0;
     int64_t np = 0;
-    if (ham != 3) np += NL * (NL + 1) / 2 + NS * (NS + 1) / 2;
-    if (ham >= 2) np += NL * NS;
+    if (ham_coulomb(ham)) np += NL * (NL + 1) / 2 + NS * (NS + 1) / 2;
+    if (ham_ls(ham)) np += NL * NS;
     return np;
 }
 
@@ -594,11 +777,13 @@ static int direct_impl(const orc_basis *L, const orc_basis *S, const double *CL,
 {
     int with_S = (ham != 0);
     if (with_S && (!S || !CS)) return -1;
-    if (n <= 0 || tau < 0 || ham < 0 || ham > 3) return -1;
+    if (n <= 0 || tau < 0 || ham < 0 || ham > 5) return -1;
     if (general && Vq) return -1;
     int NL = L->nfunc, NS = with_S ? S->nfunc : 0, m = general ? n : 2 * n;
     size_t m2 = (size_t)m * m;
-    int coul = (ham != 3), gaunt = (ham >= 2);
+    /* gaunt: L-S rows present (Gaunt and/or gauge term) */
+    int coul = ham_coulomb(ham), gaunt = ham_ls(ham);
+    int gaunt_term = ham_gaunt(ham), gauge_term = ham_gauge(ham);
 
     nbasis bl = nb_make(L), bs;
     if (with_S) bs = nb_make(S);
@@ -753,11 +938,31 @@ static int direct_impl(const orc_basis *L, const orc_basis *S, const double *CL,
                 const nbasis *kB = Kp.cls == 0 ? &bl : &bs;
                 double e = nb_eri(bA, B.mu, bB, B.nu, kA, Kp.mu, kB, Kp.nu);
                 if (Kp.cls == 2) {
-                    for (int K = 0; K < 3; ++K)
+                    /* weight of the sigma_L density in V^K.  Gaunt: (mn|kl)
+                     * delta_KL.  Gauge: the second half below applies -sigma_K
+                     * (the sign of -alpha.alpha), and the gauge operator is
+                     * +sum_KL alpha_1K alpha_2L N_KL with
+                     * N_KL = (delta_KL / r - r_K r_L / r^3) / 2, so V^K takes
+                     * -N_KL = ((mn|K L|kl) - delta_KL (mn|kl)) / 2. */
+                    double wKL[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+                    if (gaunt_term)
+                        for (int K = 0; K < 3; ++K) wKL[K * 3 + K] += e;
+                    if (gauge_term) {
+                        double t3[9];
+                        nb_eri3(bA, B.mu, bB, B.nu, kA, Kp.mu, kB, Kp.nu, t3);
+                        for (int K = 0; K < 3; ++K)
+                            for (int L2 = 0; L2 < 3; ++L2)
+                                wKL[K * 3 + L2] += 0.5 * (t3[K * 3 + L2] - (K == L2 ? e : 0.0));
+                    }
+                    for (int L2 = 0; L2 < 3; ++L2)
                         for (int c = 0; c < m; ++c)
-                            for (int d = 0; d < m; ++d)
-                                Vi[(size_t)K * m2 + (size_t)c * m + d] +=
-                                    e * dens_gaunt(cl, cs, m, K, Kp.mu, Kp.nu, c, d);
+                            for (int d = 0; d < m; ++d) {
+                                cplx D = dens_gaunt(cl, cs, m, L2, Kp.mu, Kp.nu, c, d);
+                                for (int K = 0; K < 3; ++K)
+                                    if (wKL[K * 3 + L2] != 0.0)
+                                        Vi[(size_t)K * m2 + (size_t)c * m + d] +=
+                                            wKL[K * 3 + L2] * D;
+                            }
                 } else {
                     const cplx *cx = Kp.cls == 0 ? cl : cs;
                     for (int c = 0; c < m; ++c)

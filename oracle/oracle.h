@@ -19,7 +19,10 @@
  *             Q(q) = [[q0 + i q1, q2 + i q3], [-q2 + i q3, q0 - i q1]]
  *             with rows alpha, beta.
  *   ham       0 = LL (large-component Coulomb only), 1 = DC (all four L/S
- *             Coulomb classes), 2 = DCG (DC + Gaunt), 3 = Gaunt term alone.
+ *             Coulomb classes), 2 = DCG (DC + Gaunt), 3 = Gaunt term alone,
+ *             4 = DCB (DC + Gaunt + the gauge term of the Breit operator),
+ *             5 = gauge term alone.  The gauge term enters as
+ *             (alpha_1 x r12) . (alpha_2 x r12) / (2 r12^3), Eq. (breit).
  */
 #ifndef QDCB_ORACLE_H
 #define QDCB_ORACLE_H
@@ -52,6 +55,9 @@ typedef struct {
 /* Boys function F0(T) = int_0^1 exp(-T u^2) du. */
 double orc_boys0(double T);
 
+/* Boys function F_m(T) = int_0^1 u^{2m} exp(-T u^2) du, m >= 0. */
+double orc_boys(int m, double T);
+
 /* Coefficients multiplying the unnormalized primitives exp(-a r^2) so that
  * each contracted function has unit norm; out has sum(nprim) entries. */
 void orc_norm_coefs(const orc_basis *b, double *out);
@@ -59,6 +65,12 @@ void orc_norm_coefs(const orc_basis *b, double *out);
 /* Contracted ERI (mu nu | ka la) in chemists' notation; mu, nu index basis A,
  * ka, la index basis B. */
 double orc_eri(const orc_basis *A, int mu, int nu, const orc_basis *B, int ka, int la);
+
+/* Contracted integrals of the kernel r12_K r12_L / r12^3 (K, L = x, y, z),
+ * out[K * 3 + L] = (mu^A nu^B | K L | ka^C la^D), the kernel of the gauge
+ * integrals, Eq. (gaugeInt). */
+void orc_eri3(const orc_basis *A, int mu, const orc_basis *B, int nu, const orc_basis *C, int ka,
+              const orc_basis *D, int la, double out[9]);
 
 /* Full tensor out[i][j][k][l] = (i^A j^B | k^C l^D). */
 void orc_eri_tensor(const orc_basis *A, const orc_basis *B, const orc_basis *C,

@@ -34,6 +34,22 @@ def test_boys_against_library_and_quadrature(T):
         assert f == pytest.approx(0.5 * math.sqrt(math.pi / T), rel=1e-15)
 
 
+@pytest.mark.parametrize("m", [0, 1, 2, 3])
+@pytest.mark.parametrize("T", [0.0, 1e-9, 0.3, 2.0, 10.0, 29.9, 30.0, 45.0, 120.0])
+def test_boys_fm_against_quadrature_and_library(m, T):
+    # F_m(T) = int_0^1 u^{2m} exp(-T u^2) du = 1F1(m + 1/2; m + 3/2; -T) / (2m + 1)
+    f = oracle.boys(m, T)
+    quad = integrate.quad(lambda u: u ** (2 * m) * math.exp(-T * u * u), 0.0, 1.0, epsabs=0,
+                          epsrel=1e-13, limit=200)[0]
+    ref = special.hyp1f1(m + 0.5, m + 1.5, -T) / (2 * m + 1)
+    assert f == pytest.approx(quad, rel=2e-13, abs=0)
+    assert f == pytest.approx(ref, rel=1e-13, abs=0)
+    if T == 0.0:
+        assert f == 1.0 / (2 * m + 1)
+    if m == 0:
+        assert f == pytest.approx(oracle.boys0(T), rel=2e-15)
+
+
 # --------------------------------------------------------------------------
 # Basis normalization and AO integrals
 # --------------------------------------------------------------------------
@@ -101,6 +117,55 @@ def test_four_center_eri_as_charge_distribution_energy():
         assert v == pytest.approx(ref, rel=1e-13)
 
 
+def test_gauge_kernel_integrals_closed_form():
+    # The r_K r_L / r^3 kernel of the gauge integrals, Eq. (gaugeInt), equals
+    # delta_KL / r - d_K d_L r.  Between two s charge distributions (exponents
+    # p, q, centres P, Q) the Gaussian-smeared |r| is, with rho = pq/(p+q),
+    #   h(R) = exp(-rho R^2) / sqrt(pi rho) + (R + 1/(2 rho R)) erf(sqrt(rho) R)
+    # and the smeared 1/r is erf(sqrt(rho) R) / R, both with the same charge
+    # factor as the Coulomb integral.  So (mn|K L|kl) / (mn|kl) =
+    # (delta_KL Phi - d_K d_L h) / Phi, the second derivatives taken
+    # numerically at 40 digits -- an expression that never forms F1 or F2.
+    import mpmath as mp
+    mp.mp.dps = 40
+    rng = np.random.default_rng(21)
+    for it in range(8):
+        ex = 10 ** rng.uniform(-1, 1, 4)
+        cen = rng.uniform(-2, 2, (4, 3))
+        if it == 7:
+            cen[2:] += np.array([25.0, 0.0, 0.0])  # far apart: R_K R_L / R^3 times the charges
+        B = _one_prim_basis(ex, cen)
+        T3 = oracle.eri3(B, 0, B, 1, B, 2, B, 3)
+        e = oracle.eri(B, 0, 1, B, 2, 3)
+        p, q = ex[0] + ex[1], ex[2] + ex[3]
+        R = (ex[0] * cen[0] + ex[1] * cen[1]) / p - (ex[2] * cen[2] + ex[3] * cen[3]) / q
+        r = mp.mpf(p * q / (p + q))
+
+        def h(x, y, z):
+            RR = mp.sqrt(x * x + y * y + z * z)
+            return (mp.exp(-r * RR ** 2) / mp.sqrt(mp.pi * r)
+                    + (RR + 1 / (2 * r * RR)) * mp.erf(mp.sqrt(r) * RR))
+
+        Rm = [mp.mpf(float(v)) for v in R]
+        RR = mp.sqrt(sum(v * v for v in Rm))
+        Phi = mp.erf(mp.sqrt(r) * RR) / RR
+        for K in range(3):
+            for L in range(3):
+                o = [0, 0, 0]
+                o[K] += 1
+                o[L] += 1
+                ref = float(((1 if K == L else 0) * Phi - mp.diff(h, Rm, tuple(o))) / Phi)
+                assert T3[K, L] / e == pytest.approx(ref, rel=1e-12, abs=1e-14)
+        # trace = the Coulomb integral; symmetric in K, L and under bra <-> ket
+        assert np.trace(T3) == pytest.approx(e, rel=1e-14)
+        assert np.abs(T3 - T3.T).max() <= 1e-15 * abs(e)
+        assert np.abs(oracle.eri3(B, 2, B, 3, B, 0, B, 1) - T3).max() <= 1e-15 * abs(e)
+        # positive charge distributions: |r_K r_L / r^3| <= 1/r bounds every element
+        assert np.abs(T3).max() <= e * (1 + 1e-14)
+        if it == 7:
+            assert np.abs(T3 / e - np.outer(R, R) / R.dot(R)).max() < 5e-3
+
+
 def test_eri_tensor_symmetry_schwarz_and_positive_definite():
     s = wl.config("ll24")
     E = oracle.eri_tensor(s.L)
@@ -154,7 +219,7 @@ def _tiny(ham):
     return wl.linear_chain(seed=7, n_atoms=2, nl_per_atom=2, ns_per_atom=2, n=2, tau=0.0)
 
 
-@pytest.mark.parametrize("ham", ["LL", "DC", "DCG", "GAUNT"])
+@pytest.mark.parametrize("ham", ["LL", "DC", "DCG", "GAUNT", "GAUGE", "DCB"])
 def test_brute_force_vs_definition_vs_direct(ham):
     s = _tiny(ham)
     Gb, sp = brute.transform(s.L, s.S, s.CL, s.CS, ham)
@@ -229,7 +294,7 @@ def test_unitary_invariance_of_occupied_J_and_K(ham):
     assert np.abs(G1 - G0).max() > 1e-3 * np.abs(G0).max()
 
 
-@pytest.mark.parametrize("ham,sign", [("DC", 1.0), ("GAUNT", -1.0)])
+@pytest.mark.parametrize("ham,sign", [("DC", 1.0), ("GAUNT", -1.0), ("GAUGE", -1.0)])
 def test_mo_symmetries_kramers_and_hermiticity(ham, sign):
     s = wl.linear_chain(seed=5, n_atoms=2, nl_per_atom=2, ns_per_atom=3, n=3, tau=0.0)
     G, sp, _ = oracle.transform_def(s.L, s.S, s.CL, s.CS, ham, return_spinor=True)
