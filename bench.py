@@ -190,7 +190,7 @@ def main_transform(args):
             traffic = tr.get("bytes_per_launch")
     st0 = stats[-1]
     kind = "complex spinor" if spinor else "quaternion"
-    headline = not spinor and not args.mo_batch
+    headline = not spinor and not args.mo_batch and sysm.ham != "DCB"
     line = {
         "metric": BASELINE_METRIC if headline else f"MO integrals/s ({kind} (pq|rs), FP64)",
         "value": value,

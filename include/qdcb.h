@@ -9,7 +9,8 @@
  * QuaternionScatter) and with the MO coefficients in the second half
  * (Sec. 2.4.2, Eq. secondhalf).  The result is the quaternion MO integral
  * tensor (pq|rs) of the Dirac-Coulomb classes of Eq. (DCInt) and, for the
- * DCG Hamiltonian, the Gaunt classes of Eq. (GauntInt).
+ * DCG Hamiltonian, the Gaunt classes of Eq. (GauntInt); the DCB Hamiltonian
+ * adds the gauge classes of Eq. (gaugeInt).
  *
  * Conventions
  *   - All functions return a qdcb_status; 0 is success, negative is an error.
@@ -59,20 +60,27 @@ typedef enum {
 typedef enum {
     QDCB_HAM_LL = 0,  /* (LL|LL) only: the nonrelativistic-like large-component block */
     QDCB_HAM_DC = 1,  /* Dirac-Coulomb, Eq. (DCInt): LL|LL + LL|SS + SS|LL + SS|SS */
-    QDCB_HAM_DCG = 2  /* DC plus the Gaunt term, Eqs. (breit) and (GauntInt) */
+    QDCB_HAM_DCG = 2, /* DC plus the Gaunt term, Eqs. (breit) and (GauntInt) */
+    QDCB_HAM_DCB = 3  /* DC plus the whole Breit term: Gaunt and the gauge term
+                         (alpha_1 x r12) . (alpha_2 x r12) / (2 r12^3) of Eq. (breit),
+                         whose integrals, Eq. (gaugeInt), carry the kernel
+                         r12 r12^T / r12^3 over the same L-S products as Gaunt */
 } qdcb_ham;
 
 typedef enum { QDCB_PREC_FP64 = 0, QDCB_PREC_MIXED = 1 } qdcb_prec;
 
 /* transform flags */
 #define QDCB_PTR_DEVICE 0x1u /* CL, CS and G are device pointers (else host) */
-/* Integral classes to include (neither bit: every class of the plan's
+/* Integral classes to include (no class bit: every class of the plan's
  * Hamiltonian).  QDCB_CLASS_COULOMB: the Dirac-Coulomb classes of Eq. (DCInt)
  * (LL|LL for QDCB_HAM_LL); QDCB_CLASS_GAUNT: the Gaunt classes of Eq.
- * (GauntInt), DCG plans only.  The output holds the sum of the selected
- * classes, so a DCG transform equals the sum of its two single-class ones. */
+ * (GauntInt), DCG and DCB plans; QDCB_CLASS_GAUGE: the gauge classes of Eq.
+ * (gaugeInt), DCB plans only.  The output holds the sum of the selected
+ * classes, so a transform with every class equals the sum of the
+ * single-class ones (to rounding). */
 #define QDCB_CLASS_COULOMB 0x2u
 #define QDCB_CLASS_GAUNT 0x4u
+#define QDCB_CLASS_GAUGE 0x8u
 
 typedef struct qdcb_ctx qdcb_ctx;
 typedef struct qdcb_basis qdcb_basis;
@@ -184,11 +192,12 @@ typedef struct {
     double ms_second_half;   /* MO-coefficient contraction and output */
     int64_t kept[4];         /* kept directed pair contributions LL<-LL, LL<-SS, SS<-LL, SS<-SS */
     int64_t total[4];        /* all directed pair contributions of the same class pairs */
-    int64_t kept_gaunt;      /* LS<-LS (DCG) */
+    int64_t kept_gaunt;      /* LS<-LS (DCG, DCB: the Gaunt and gauge terms share them) */
     int64_t total_gaunt;
     int64_t tiles_kept;      /* kept (bra tile, ket tile) pairs */
     int64_t tiles_total;
-    double flops_first_half; /* algorithmic: 2 * columns * kept contributions */
+    double flops_first_half; /* algorithmic: 2 * columns * kept contributions (Gaunt: 3
+                                columns per MO-pair column, gauge: 9) */
     double flops_second_half;
     double flops_mfma;       /* MFMA flops issued by the first-half kernel (incl. masked
                                 elements of kept tiles), summed over the column chunks */
@@ -200,7 +209,7 @@ typedef struct {
     int64_t tiles_tier[3];   /* mixed: kept directed tiles contracted in FP64, FP32, BF16
                                 (eager transforms) */
     double ms_tier[3];       /* mixed: first-half time per tier (eager transforms) */
-    int32_t classes;         /* integral classes included: 1 Coulomb, 2 Gaunt, 3 both */
+    int32_t classes;         /* integral classes included, bits: 1 Coulomb, 2 Gaunt, 4 gauge */
     int32_t reserved;
 } qdcb_stats;
 

@@ -24,6 +24,10 @@
 // across its lanes, so its primitive data comes through scalar loads.  Stores
 // are one 512-byte row of 64 bra values per ket row (coalesced).
 //
+// Gauge tiles (Eq. gaugeInt): the same loops with six accumulators per element,
+// B_KL = ((mn| r_K r_L / r^3 |kl) - delta_KL (mn|kl)) / 2 for (K, L) = xx, xy,
+// xz, yy, yz, zz, from F0, F1 and F2 of one Taylor table (see gauge_kernel_tab).
+//
 // Schedules: one workgroup per tile in list order (k_eri_tiles), or a
 // persistent grid of a few workgroups per compute unit that pull tiles from a
 // device queue ordered by decreasing primitive-quartet count
@@ -127,16 +131,135 @@ __device__ __forceinline__ void eri_tile_body(const EriTileArgs &a, const EriLds
   }
 }
 
+// The gauge kernel of one primitive quartet without its charge factors: with
+// g_m = (2 / sqrt(pi)) sqrt(rho) F_m(T), T = rho R^2, R = P - Q,
+//   B_KL = ga delta_KL + gb R_K R_L,  ga = (g1 - g0) / 2,  gb = rho (g1 - g2),
+// or with ga = (g1 + g0) / 2 the Breit tiles (Gaunt's (mn|kl) delta_KL added)
+// when diag = +1/2 instead of -1/2.
+// Near field (T < 36): F0, F1, F2 from one table of F_k(T_i), k = 0 .. 9, by
+// their Taylor series F_m(T_i + d) = sum_k F_{m+k}(T_i) (-d)^k / k! (k <= 7,
+// nested).  Far field: F0 = (1/2) sqrt(pi / T) (erf = 1) and the upward
+// recursion F_{m+1} = ((2m + 1) F_m - exp(-T)) / (2T), exact there.
+__device__ __forceinline__ void gauge_kernel_tab(const double *tab, double ip, double px,
+                                                 double py, double pz, double iq, double qx,
+                                                 double qy, double qz, double diag, double &ga,
+                                                 double &gb, double &dx, double &dy, double &dz) {
+  const double t = ip + iq;  // 1/rho
+  const double sr = rsqrt_pos(t);
+  dx = px - qx;
+  dy = py - qy;
+  dz = pz - qz;
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double rho = sr * sr;
+  const double T = r2 * rho;
+  double g0, g1, g2;
+  if (T < BOYS_TMAX) {
+    const int i = (int)fma(T, 8.0, 0.5);
+    const double nd = fma(0.125, (double)i, -T);  // -(T - T_i)
+    const double *c = tab + BOYS_LD * i;
+    g0 = c[7];
+    g1 = c[8];
+    g2 = c[9];
+#pragma unroll
+    for (int k = 7; k >= 1; --k) {
+      const double h = nd * (1.0 / k);
+      g0 = fma(g0, h, c[k - 1]);
+      g1 = fma(g1, h, c[k]);
+      g2 = fma(g2, h, c[k + 1]);
+    }
+    g0 *= sr;
+    g1 *= sr;
+    g2 *= sr;
+  } else {
+    g0 = rsqrt(r2);
+    const double e = TWO_OVER_SQRTPI * sr * exp(-T);
+    const double h = 0.5 / T;
+    g1 = (g0 - e) * h;
+    g2 = fma(3.0, g1, -e) * h;
+  }
+  ga = fma(0.5, g1, diag * g0);
+  gb = rho * (g1 - g2);
+}
+
+// Gauge counterpart of eri_tile_body: six tiles per slot (stride TILE^2).
+__device__ __forceinline__ void eri_gauge_tile_body(const EriTileArgs &a, const EriLds &L, int kt,
+                                                    int bt, int lane, int w, double *out,
+                                                    double *outT, long long kept[4]) {
+  const int64_t brow = (int64_t)bt * TILE + lane;
+  const double qb = a.Q[brow];
+  const double db = a.Dmax[brow];
+  const int cb = a.cls[brow];
+  const int64_t bfirst = a.row_first[brow];
+  const int bcount = (int)(a.row_first[brow + 1] - bfirst);
+  const int nl = min(bcount, ERI_LDS_ROWPRIMS);
+  for (int i = 0; i < TILE / ERI_WAVES; ++i) {
+    const int j = w + ERI_WAVES * i;
+    const int64_t krow = (int64_t)kt * TILE + j;
+    const double qk = a.Q[krow], dk = a.Dmax[krow];
+    const int ck = a.cls[krow];
+    const int64_t kf0 = a.row_first[krow], kf1 = a.row_first[krow + 1];
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const bool keep_bk = out && (qb * qk) * dk >= a.tau;
+    const bool keep_kb = outT && (qk * qb) * db >= a.tau;
+    if (keep_bk || keep_kb) {
+      for (int64_t k = kf0; k < kf1; ++k) {
+        const double iq = a.pp.ip[k], qx = a.pp.x[k], qy = a.pp.y[k], qz = a.pp.z[k];
+        const double ek = a.pp.e[k];
+        double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        auto add = [&](double eb, double ip, double px, double py, double pz) {
+          double ga, gb, dx, dy, dz;
+          gauge_kernel_tab(L.tab, ip, px, py, pz, iq, qx, qy, qz, a.gauge_diag, ga, gb, dx, dy,
+                           dz);
+          const double ea = eb * ga, ebb = eb * gb;
+          const double bx = ebb * dx, by = ebb * dy, bz = ebb * dz;
+          s[0] += fma(bx, dx, ea);
+          s[1] = fma(bx, dy, s[1]);
+          s[2] = fma(bx, dz, s[2]);
+          s[3] += fma(by, dy, ea);
+          s[4] = fma(by, dz, s[4]);
+          s[5] += fma(bz, dz, ea);
+        };
+        for (int t = 0; t < nl; ++t) {
+          const int b = t * TILE + lane;
+          add(L.se[b], L.sip[b], L.sx[b], L.sy[b], L.sz[b]);
+        }
+        for (int t = nl; t < bcount; ++t) {
+          const int64_t b = bfirst + t;
+          add(a.pp.e[b], a.pp.ip[b], a.pp.x[b], a.pp.y[b], a.pp.z[b]);
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] = fma(ek, s[c], v[c]);
+      }
+      if (cb >= 0 && ck >= 0) {
+        if (keep_bk) kept[cb * 2 + ck] += 1;
+        if (keep_kb) kept[ck * 2 + cb] += 1;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      if (out) out[c * TILE * TILE + j * TILE + lane] = keep_bk ? v[c] : 0.0;
+      if (outT) outT[c * TILE * TILE + lane * TILE + j] = keep_kb ? v[c] : 0.0;
+    }
+  }
+}
+
+template <bool GAUGE>
 __device__ __forceinline__ void eri_stage_table(const EriTileArgs &a, EriLds &L) {
-  for (int t = threadIdx.x; t < BOYS_N * 8; t += ERI_THREADS)
-    L.tab[(t >> 3) * BOYS_LD + (t & 7)] = a.boys[t];
+  if constexpr (GAUGE) {
+    for (int t = threadIdx.x; t < BOYS_N * BOYS_LD; t += ERI_THREADS) L.tab[t] = a.boys3[t];
+  } else {
+    for (int t = threadIdx.x; t < BOYS_N * 8; t += ERI_THREADS)
+      L.tab[(t >> 3) * BOYS_LD + (t & 7)] = a.boys[t];
+  }
 }
 
 // One tile: task `slot` of the lists, written to its panel slot(s).  Opens
 // with a barrier-separated staging phase, so consecutive calls of one
 // workgroup may reuse the LDS (the table must have been staged before).
+template <bool GAUGE>
 __device__ __forceinline__ void eri_one_tile(const EriTileArgs &a, EriLds &L, int64_t slot,
                                              long long kept[4]) {
+  constexpr int64_t SLOT = (GAUGE ? 6 : 1) * TILE * TILE;  // doubles per panel slot
   const int kt = a.tasks[slot];
   const int bt = a.task_bra[slot];
   const int lane = threadIdx.x & 63;
@@ -144,10 +267,10 @@ __device__ __forceinline__ void eri_one_tile(const EriTileArgs &a, EriLds &L, in
   double *out, *outT = nullptr;
   if (a.uslot_bk) {
     const int32_t s1 = a.uslot_bk[slot], s2 = a.uslot_kb[slot];
-    out = s1 >= 0 ? a.panel + (int64_t)s1 * TILE * TILE : nullptr;
-    outT = s2 >= 0 ? a.panel + (int64_t)s2 * TILE * TILE : nullptr;
+    out = s1 >= 0 ? a.panel + (int64_t)s1 * SLOT : nullptr;
+    outT = s2 >= 0 ? a.panel + (int64_t)s2 * SLOT : nullptr;
   } else {
-    out = a.panel + (slot - a.slot0) * TILE * TILE;
+    out = a.panel + (slot - a.slot0) * SLOT;
   }
   // largest primitive count of the tile's bra rows
   if (threadIdx.x < 64) {
@@ -173,7 +296,10 @@ __device__ __forceinline__ void eri_one_tile(const EriTileArgs &a, EriLds &L, in
     }
   }
   __syncthreads();
-  eri_tile_body(a, L, kt, bt, lane, w, out, outT, kept);
+  if constexpr (GAUGE)
+    eri_gauge_tile_body(a, L, kt, bt, lane, w, out, outT, kept);
+  else
+    eri_tile_body(a, L, kt, bt, lane, w, out, outT, kept);
 }
 
 __device__ __forceinline__ void eri_count(const EriTileArgs &a, const long long kept[4]) {
@@ -186,13 +312,14 @@ __device__ __forceinline__ void eri_count(const EriTileArgs &a, const long long 
 }
 
 // One workgroup per tile, in list order.
+template <bool GAUGE>
 __global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles(EriTileArgs a) {
   __shared__ EriLds L;
   if (a.overflow && *a.overflow) return;  // uniform: the panel cannot hold the tiles
   if (a.d_total && (int64_t)blockIdx.x >= min(*a.d_total, a.cap)) return;  // uniform exit
   long long kept[4] = {0, 0, 0, 0};
-  eri_stage_table(a, L);
-  eri_one_tile(a, L, a.slot0 + blockIdx.x, kept);
+  eri_stage_table<GAUGE>(a, L);
+  eri_one_tile<GAUGE>(a, L, a.slot0 + blockIdx.x, kept);
   eri_count(a, kept);
 }
 
@@ -201,6 +328,7 @@ __global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles(EriTileArgs a) {
 // workgroup's last fetch returns an index past the end, so all of them exit.
 // The Boys table is staged once per workgroup.  Which workgroup computes a
 // tile does not change its values.
+template <bool GAUGE>
 __global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles_queue(EriTileArgs a,
                                                                  const int32_t *order,
                                                                  unsigned long long *qctr,
@@ -210,28 +338,41 @@ __global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles_queue(EriTileArgs a,
   if (a.overflow && *a.overflow) return;  // uniform
   const int64_t n = a.d_total ? min(*a.d_total, a.cap) : n_host;
   long long kept[4] = {0, 0, 0, 0};
-  eri_stage_table(a, L);
+  eri_stage_table<GAUGE>(a, L);
   for (;;) {
     __syncthreads();  // the previous tile's LDS reads (and s_next's) are done
     if (threadIdx.x == 0) s_next = (int64_t)atomicAdd(qctr, 1ull);
     __syncthreads();
     const int64_t i = s_next;
     if (i >= n) break;  // uniform
-    eri_one_tile(a, L, order[i], kept);
+    eri_one_tile<GAUGE>(a, L, order[i], kept);
   }
   eri_count(a, kept);
 }
 
 void launch_eri_tiles(const EriTileArgs &a, int64_t nslots, hipStream_t s) {
   if (nslots <= 0) return;
-  hipLaunchKernelGGL(k_eri_tiles, dim3((unsigned)nslots), dim3(ERI_THREADS), 0, s, a);
+  hipLaunchKernelGGL(k_eri_tiles<false>, dim3((unsigned)nslots), dim3(ERI_THREADS), 0, s, a);
 }
 
 void launch_eri_tiles_queue(const EriTileArgs &a, const int32_t *order, unsigned long long *qctr,
                             int64_t n_host, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return;
-  hipLaunchKernelGGL(k_eri_tiles_queue, dim3((unsigned)nblocks), dim3(ERI_THREADS), 0, s, a,
-                     order, qctr, n_host);
+  hipLaunchKernelGGL(k_eri_tiles_queue<false>, dim3((unsigned)nblocks), dim3(ERI_THREADS), 0, s,
+                     a, order, qctr, n_host);
+}
+
+void launch_eri_gauge_tiles(const EriTileArgs &a, int64_t nslots, hipStream_t s) {
+  if (nslots <= 0) return;
+  hipLaunchKernelGGL(k_eri_tiles<true>, dim3((unsigned)nslots), dim3(ERI_THREADS), 0, s, a);
+}
+
+void launch_eri_gauge_tiles_queue(const EriTileArgs &a, const int32_t *order,
+                                  unsigned long long *qctr, int64_t n_host, int nblocks,
+                                  hipStream_t s) {
+  if (nblocks <= 0) return;
+  hipLaunchKernelGGL(k_eri_tiles_queue<true>, dim3((unsigned)nblocks), dim3(ERI_THREADS), 0, s,
+                     a, order, qctr, n_host);
 }
 
 }  // namespace qdcb

@@ -144,8 +144,21 @@ __device__ __forceinline__ void fh_mfma(const double *Ac, const double *Bc, int 
   }
 }
 
-template <int KH, int PREC>
-__global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, int nct, int ncx) {
+// Gauge panel slot of the symmetric pair (K, L): xx, xy, xz, yy, yz, zz.
+__device__ __forceinline__ int gauge_sym_index(int K, int L) {
+  const int lo = K < L ? K : L, hi = K < L ? L : K;
+  return lo * 3 - lo * (lo + 1) / 2 + hi;
+}
+
+// TENSOR (gauge term, FP64): workgroup (bp, ct, K = blockIdx.y) accumulates
+// V^K over the kept ket tiles and, per ket tile, over L = x, y, z: each task
+// is three runs of TILE / KH steps, the L-th reading panel tile (K, L) of the
+// slot and the density rows' L-th column block.
+template <int KH, int PREC, bool TENSOR = false>
+__global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, int nct, int ncx,
+                                                    int64_t ldK, int accumulate) {
+  constexpr int NSTEP = (TENSOR ? 3 : 1) * (TILE / KH);  // staged steps per task
+  constexpr int64_t SLOT = (TENSOR ? 6 : 1) * TILE * TILE;  // doubles per panel slot
   // two staging buffers as distinct objects, so that the compiler can tell
   // the loads into one from the reads of the other
   __shared__ __attribute__((aligned(16))) double As0[KH * AS_LD], As1[KH * AS_LD];
@@ -174,9 +187,20 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
   const int wr = w >> 1, wc = w & 1;  // wave's 64-row half (bra tile) and 64-column half
   const int64_t c0 = (int64_t)ct * FH_COLS;
   const int lr = lane & 15, lk = lane >> 4;
+  const int Kt = TENSOR ? (int)blockIdx.y : 0;
   FhAcc<PREC> f;
   for (int r = 0; r < 4; ++r)
     for (int c = 0; c < 4; ++c) f.acc[r][c] = (typename FhAcc<PREC>::V){0, 0, 0, 0};
+  const int64_t vc0 = (TENSOR ? Kt * ldK : 0) + c0;  // this workgroup's first V column
+  if (TENSOR && accumulate && (wr == 0 || two)) {
+    // adding to V: the accumulators start from it (loaded before the loop,
+    // where registers are free, instead of read-modify-writes at the end)
+    const int64_t row0 = (int64_t)(bt0 + wr) * TILE;
+    for (int r = 0; r < 4; ++r)
+      for (int c = 0; c < 4; ++c)
+        for (int i = 0; i < 4; ++i)
+          f.acc[r][c][i] = a.V[(row0 + r * 16 + lk + 4 * i) * a.ld + vc0 + wc * 64 + c * 16 + lr];
+  }
   if constexpr (PREC != PREC_F64)
     for (int r = 0; r < 4; ++r)
       for (int c = 0; c < 4; ++c) f.part[r][c] = (typename FhAcc<PREC>::V){0, 0, 0, 0};
@@ -185,7 +209,7 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
   int i0 = 0, i1 = 0;
   // step state: current task's ket tile and tiles, sub-step h within the task
   const double *P0 = nullptr, *P1 = nullptr;
-  int kt = 0, h = TILE / KH;
+  int kt = 0, h = NSTEP;
   bool has0 = false, has1 = false;
   int eI = 0, eD = 0;  // block-scale exponents of the current task (this wave's half)
   // heads of the two ordered lists, read one task ahead so that the list
@@ -197,7 +221,7 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
   int nr1 = n1 > 0 && a.rank ? a.rank[l1] : 0;
   // advance to the next step; false when the merged lists are exhausted
   auto advance = [&]() -> bool {
-    if (++h < TILE / KH) return true;
+    if (++h < NSTEP) return true;
     const int k0 = __builtin_amdgcn_readfirstlane(nk0), k1 = __builtin_amdgcn_readfirstlane(nk1);
     if (k0 == INT_MAX && k1 == INT_MAX) return false;
     kt = k0 < k1 ? k0 : k1;
@@ -205,7 +229,7 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
     has1 = k1 == kt;
     if (has0) {
       const int64_t r0 = a.rank ? __builtin_amdgcn_readfirstlane(nr0) : i0;
-      P0 = a.panel + (s0 + r0 - a.slot0) * (TILE * TILE);
+      P0 = a.panel + (s0 + r0 - a.slot0) * SLOT;
       ++i0;
       nk0 = i0 < n0 ? a.tasks[l0 + i0] : INT_MAX;
       if (a.rank && i0 < n0) nr0 = a.rank[l0 + i0];
@@ -214,7 +238,7 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
     }
     if (has1) {
       const int64_t r1 = a.rank ? __builtin_amdgcn_readfirstlane(nr1) : i1;
-      P1 = a.panel + (s1 + r1 - a.slot0) * (TILE * TILE);
+      P1 = a.panel + (s1 + r1 - a.slot0) * SLOT;
       ++i1;
       nk1 = i1 < n1 ? a.tasks[l1 + i1] : INT_MAX;
       if (a.rank && i1 < n1) nr1 = a.rank[l1 + i1];
@@ -232,13 +256,21 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
   // integral slice (lanes 0-31: tile of bra tile bt0, lanes 32-63: of bt0+1)
   // and of the density slice
   auto issue = [&](double *A, double *B) {
+    int hh = h;
+    int64_t poff = 0, doff = 0;
+    if constexpr (TENSOR) {
+      const int Lc = h / (TILE / KH);
+      hh = h - Lc * (TILE / KH);
+      poff = (int64_t)gauge_sym_index(Kt, Lc) * (TILE * TILE);
+      doff = Lc * ldK;
+    }
     const double *P = lane < 32 ? P0 : P1;
 #pragma unroll
     for (int q = 0; q < KH / 4; ++q) {
       const int jj = w + 4 * q;
-      if (P) load_row_lds(P + (h * KH + jj) * TILE + 2 * (lane & 31), A + jj * AS_LD);
+      if (P) load_row_lds(P + poff + (hh * KH + jj) * TILE + 2 * (lane & 31), A + jj * AS_LD);
     }
-    const double *Dr = a.D + ((int64_t)kt * TILE + h * KH) * a.ld + c0 + 2 * lane;
+    const double *Dr = a.D + ((int64_t)kt * TILE + hh * KH) * a.ld + doff + c0 + 2 * lane;
 #pragma unroll
     for (int q = 0; q < KH / 4; ++q) {
       const int r = w + 4 * q;
@@ -251,7 +283,7 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
     int eI, eD;
   };
   auto desc = [&]() -> StepDesc {
-    return StepDesc{wr == 0 ? has0 : has1, h == TILE / KH - 1, eI, eD};
+    return StepDesc{wr == 0 ? has0 : has1, h == NSTEP - 1, eI, eD};
   };
   // one staged step: MFMAs when this wave's bra tile keeps the task; at the
   // task's last step the reduced tiers fold the scaled partial into the sum
@@ -306,7 +338,7 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
       for (int i = 0; i < 4; ++i) {
         if constexpr (PREC == PREC_F64) {
           const int64_t row = row0 + r * 16 + lk + 4 * i;
-          a.V[row * a.ld + c0 + wc * 64 + c * 16 + lr] = f.acc[r][c][i];
+          a.V[row * a.ld + vc0 + wc * 64 + c * 16 + lr] = f.acc[r][c][i];
         } else {
           const int64_t row = row0 + r * 16 + 4 * lk + i;
           a.V[row * a.ld + c0 + wc * 64 + c * 16 + lr] += (double)f.acc[r][c][i];
@@ -321,7 +353,17 @@ void launch_first_half(const FirstHalfArgs &a, hipStream_t s) {
   // at most 32768 bra pairs x (ncol / 128 + 8) slices: well inside the grid limit
   const int64_t grid = ncx ? (int64_t)N_XCD * ncx * nbp : (int64_t)nbp * nct;
   hipLaunchKernelGGL((k_first_half<FH_KH, PREC_F64>), dim3((unsigned)grid), dim3(256), 0, s, a,
-                     nbp, nct, ncx);
+                     nbp, nct, ncx, (int64_t)0, 0);
+}
+
+void launch_first_half_gauge(const FirstHalfArgs &a, int64_t ldK, int accumulate,
+                             hipStream_t s) {
+  if (a.b1 <= a.b0 || a.ncol_tiles <= 0) return;
+  const int nbp = (a.b1 - a.b0 + 1) / 2, nct = a.ncol_tiles;
+  const int ncx = !a.plain_order && nct >= N_XCD ? (nct + N_XCD - 1) / N_XCD : 0;
+  const int64_t grid = ncx ? (int64_t)N_XCD * ncx * nbp : (int64_t)nbp * nct;
+  hipLaunchKernelGGL((k_first_half<FH_KH, PREC_F64, true>), dim3((unsigned)grid, 3), dim3(256),
+                     0, s, a, nbp, nct, ncx, ldK, accumulate);
 }
 
 void launch_first_half_lp(const FirstHalfArgs &a, int tier, hipStream_t s) {
@@ -331,10 +373,10 @@ void launch_first_half_lp(const FirstHalfArgs &a, int tier, hipStream_t s) {
   const int64_t grid = ncx ? (int64_t)N_XCD * ncx * nbp : (int64_t)nbp * nct;
   if (tier == 2)
     hipLaunchKernelGGL((k_first_half<FH_KH, PREC_BF16>), dim3((unsigned)grid), dim3(256), 0, s,
-                       a, nbp, nct, ncx);
+                       a, nbp, nct, ncx, (int64_t)0, 0);
   else
     hipLaunchKernelGGL((k_first_half<FH_KH, PREC_F32>), dim3((unsigned)grid), dim3(256), 0, s,
-                       a, nbp, nct, ncx);
+                       a, nbp, nct, ncx, (int64_t)0, 0);
 }
 
 }  // namespace qdcb

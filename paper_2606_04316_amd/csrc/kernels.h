@@ -127,8 +127,14 @@ struct EriTileArgs {
   const double *Dmax;         // [nrows]
   const int32_t *cls;         // [nrows]
   double tau;
-  double *panel;              // [slots][64 ket][64 bra]
+  double *panel;              // [slots][64 ket][64 bra] ([slots][6][64][64] for gauge tiles)
   unsigned long long *kept;   // [4] kept directed contributions per class pair, or NULL
+  // gauge tiles (launch_eri_gauge_tiles*): boys3 = [BOYS_N][BOYS_LD] table of
+  // (2 / sqrt(pi)) F_k(T_i), k = 0 .. 9; gauge_diag = -1/2 makes the gauge
+  // tiles B_KL below, +1/2 the Breit tiles B_KL + delta_KL (mn|kl) (Gaunt and
+  // gauge terms in one)
+  const double *boys3 = nullptr;
+  double gauge_diag = -0.5;
 };
 void launch_eri_tiles(const EriTileArgs &a, int64_t nslots, hipStream_t s);
 // Persistent integral launch of nblocks workgroups over the tasks order[i],
@@ -136,6 +142,14 @@ void launch_eri_tiles(const EriTileArgs &a, int64_t nslots, hipStream_t s);
 // queue counter *qctr must be 0 at launch.
 void launch_eri_tiles_queue(const EriTileArgs &a, const int32_t *order, unsigned long long *qctr,
                             int64_t n_host, int nblocks, hipStream_t s);
+// Gauge-term tiles of the L-S space, same task lists and masks as the Gaunt
+// tiles: panel slot s holds the six tiles (K, L) = xx, xy, xz, yy, yz, zz of
+//   B_KL(mn, kl) = ((mn| r_K r_L / r^3 |kl) - delta_KL (mn|kl)) / 2
+// (symmetric in K, L and under bra <-> ket), each [64 ket][64 bra].
+void launch_eri_gauge_tiles(const EriTileArgs &a, int64_t nslots, hipStream_t s);
+void launch_eri_gauge_tiles_queue(const EriTileArgs &a, const int32_t *order,
+                                  unsigned long long *qctr, int64_t n_host, int nblocks,
+                                  hipStream_t s);
 // Longest-first order of n unique tile tasks (n as for launch_eri_tiles_queue,
 // from d_total/cap or n_host): order lists the task indices by decreasing
 // floor(log2(bra primitive pairs x ket primitive pairs)) of their tiles (order
@@ -170,6 +184,12 @@ struct FirstHalfArgs {
   int plain_order = 0;
 };
 void launch_first_half(const FirstHalfArgs &a, hipStream_t s);
+// Gauge term (FP64): V[mn][K ldK + col] (+)= sum_L sum_kl B_KL(mn, kl)
+// D~[kl][L ldK + col] with the six-tile gauge panel slots (ld = 3 ldK,
+// ncol_tiles = ldK / 128); accumulate = 1 adds to V (after the Gaunt term),
+// 0 stores.
+void launch_first_half_gauge(const FirstHalfArgs &a, int64_t ldK, int accumulate,
+                             hipStream_t s);
 // Reduced-precision tiers: V += the tier's contributions, computed with FP32
 // (tier 1) or BF16 (tier 2) MFMA operands and FP32 accumulation.
 void launch_first_half_lp(const FirstHalfArgs &a, int tier, hipStream_t s);

@@ -31,7 +31,12 @@ struct Space {
   DBuf<int32_t> count, tasks, task_bra;
   DBuf<int64_t> slot_base;
   DBuf<double> panel;
+  DBuf<double> panel3;  // gauge tiles, six per slot (L-S space of DCB plans)
   int64_t panel_slots = 0;
+  // panel of the plain integral tiles: FP64 DCB plans have none of their own
+  // and use the gauge panel's memory (the fused Breit tiles replace them; a
+  // Gaunt-only transform regenerates its tiles there)
+  double *pan() const { return panel.p ? panel.p : panel3.p; }
   DBuf<unsigned long long> kept;
   DBuf<int64_t> dtotal;     // device copy of the kept-tile total (graph mode)
   DBuf<int32_t> overflow;   // set when the kept tiles exceed the panel (graph mode)
@@ -54,7 +59,7 @@ struct Space {
     return cls.bytes() + mu.bytes() + nu.bytes() + row_first.bytes() + Q.bytes() + pp.bytes() +
            D.bytes() + V.bytes() + Dmax.bytes() + Qmax.bytes() + Bmax.bytes() + Dtmax.bytes() +
            ttasks.bytes() + trank.bytes() + tcount.bytes() + toff.bytes() + count.bytes() +
-           tasks.bytes() + task_bra.bytes() + slot_base.bytes() + panel.bytes() + kept.bytes() +
+           tasks.bytes() + task_bra.bytes() + slot_base.bytes() + panel.bytes() + panel3.bytes() + kept.bytes() +
            dtotal.bytes() + overflow.bytes() + ucount.bytes() + utask_k.bytes() +
            utask_b.bytes() + uslot_bk.bytes() + uslot_kb.bytes() + dmap.bytes() + ubase.bytes() + udtotal.bytes() +
            uoverflow.bytes() + uorder.bytes() + lpt.bytes();
@@ -92,7 +97,9 @@ struct qdcb_plan {
   double mo_work = 0.0;
   int chunks_run = 0;  // column chunks (MO-driven: batches) of the last transform
   int sc = 0;        // columns per second-half slice
-  bool gaunt = false;
+  bool gaunt = false;      // L-S space (Gaunt term; DCG and DCB)
+  bool gauge = false;      // gauge term of the Breit operator (DCB)
+  bool fused_breit = false;  // FP64 DCB: Gaunt + gauge from one set of Breit tiles
   qdcb_tune tune{};       // launch choices (tile shapes, schedules)
   int n_cu = 0;           // compute units of the device
   std::string tune_key;   // shape key of the tuning cache
@@ -104,9 +111,11 @@ struct qdcb_plan {
   qdcb::DBuf<double> W, Gc;
   qdcb::DBuf<double> Gb;         // block output of qdcb_transform_blocks (made on first use)
   std::vector<double> h_Gb;      // its host copy (host-pointer mode)
-  int classes = 3;               // integral classes of the last transform (1 Coulomb, 2 Gaunt)
+  int classes = 3;               // integral classes of the last transform (1 Coulomb, 2 Gaunt,
+                                 // 4 gauge)
   std::atomic<int> busy{0};      // a call is using the plan
-  qdcb::DBuf<double> boys;  // Taylor table of the Boys function F0
+  qdcb::DBuf<double> boys;   // Taylor table of the Boys function F0
+  qdcb::DBuf<double> boys3;  // F0 .. F9 on the same grid (gauge tiles)
   bool have_last = false;
   int64_t tiles_made = 0;  // integral tiles generated by the last eager transform
   int v_i0 = 0, v_i1 = 0;  // MO pairs whose first-half columns V holds (last chunk)

@@ -126,6 +126,27 @@ std::vector<double> boys_table() {
   return tab;
 }
 
+// Table of the gauge tiles: tab[BOYS_LD i + k] = (2/sqrt(pi)) F_k(T_i), k = 0 .. 9,
+// T_i = i / 8, by the same series and downward recursion (long double).
+std::vector<double> boys_table3() {
+  std::vector<double> tab((size_t)BOYS_N * BOYS_LD);
+  const long double two_over_sqrtpi = 2.0L / sqrtl(3.14159265358979323846264338327950288L);
+  for (int i = 0; i < BOYS_N; ++i) {
+    const long double T = (long double)i / 8.0L, eT = expl(-T);
+    long double term = 1.0L / 19.0L, sum = term;  // m = 9
+    for (int j = 1; j < 400; ++j) {
+      term *= 2.0L * T / (19.0L + 2.0L * j);
+      sum += term;
+      if (term < 1e-22L * sum) break;
+    }
+    long double F[10];
+    F[9] = eT * sum;
+    for (int m = 9; m >= 1; --m) F[m - 1] = (2.0L * T * F[m] + eT) / (2.0L * m - 1.0L);
+    for (int k = 0; k < 10; ++k) tab[(size_t)BOYS_LD * i + k] = (double)(two_over_sqrtpi * F[k]);
+  }
+  return tab;
+}
+
 }  // namespace
 
 namespace qdcb {
@@ -151,6 +172,7 @@ void size_plan(qdcb_plan &p, int64_t slotsC, int64_t slotsG) {
     sp->D.free();
     sp->V.free();
     sp->panel.free();
+    sp->panel3.free();
     sp->panel_slots = 0;
   }
   p.W.free();
@@ -163,8 +185,11 @@ void size_plan(qdcb_plan &p, int64_t slotsC, int64_t slotsG) {
   const size_t slot_bytes = sizeof(double) * TILE * TILE;
   const int64_t wmax = (int64_t)std::max(p.NL, p.NS) * 4 * p.n;
   const size_t per_col = sizeof(double) * (size_t)(wmax + (int64_t)4 * p.n * p.n);
+  // an L-S slot of a DCB plan holds six gauge (or Breit) tiles, and the Gaunt
+  // tile too when the two terms are contracted apart (mixed precision)
+  const int gmul = p.gauge ? (p.fused_breit ? 6 : 7) : 1;
   const bool fixed = slotsC > 0;
-  const double panels = fixed ? (double)slot_bytes * (slotsC + slotsG) : 0.0;
+  const double panels = fixed ? (double)slot_bytes * (slotsC + gmul * slotsG) : 0.0;
   // --- first-half column chunk
   int64_t ci = p.npair_mo;
   const double room0 = (double)room();
@@ -208,12 +233,13 @@ void size_plan(qdcb_plan &p, int64_t slotsC, int64_t slotsG) {
       slots = sp == &p.G ? slotsG : slotsC;
     } else {
       slots = (int64_t)(room() / 4 / nsp / slot_bytes);
-      if (sp == &p.G) slots = (int64_t)(room() / 4 / slot_bytes);
+      if (sp == &p.G) slots = (int64_t)(room() / 4 / (gmul * slot_bytes));
     }
     slots = std::min<int64_t>(slots, (int64_t)1 << 23);
     if (slots < sp->ntiles) fail(QDCB_E_NOMEM, "no room for one bra row of integral tiles");
     sp->panel_slots = slots;
-    sp->panel.alloc(ctx, (size_t)slots * TILE * TILE);
+    if (!(sp == &p.G && p.fused_breit)) sp->panel.alloc(ctx, (size_t)slots * TILE * TILE);
+    if (sp == &p.G && p.gauge) sp->panel3.alloc(ctx, (size_t)slots * 6 * TILE * TILE);
   }
 }
 
@@ -228,7 +254,8 @@ bool ensure_residency(qdcb_plan &p, double slack) {
   if (needC > ((int64_t)1 << 23) || needG > ((int64_t)1 << 23)) return false;
   // memory the resizable buffers may use: what they hold now plus the free room
   size_t held = p.W.bytes() + p.Gc.bytes();
-  for (const Space *sp : {&p.C, &p.G}) held += sp->D.bytes() + sp->V.bytes() + sp->panel.bytes();
+  for (const Space *sp : {&p.C, &p.G})
+    held += sp->D.bytes() + sp->V.bytes() + sp->panel.bytes() + sp->panel3.bytes();
   const size_t g_stage = g_stage_bytes(p);
   // within the context budget and within what the device has free now (other
   // allocations of the process, such as the caller's G, count against it)
@@ -236,7 +263,8 @@ bool ensure_residency(qdcb_plan &p, double slack) {
   HIPC(hipMemGetInfo(&fr, &tot));
   const double room0 = std::min((double)p.ctx->room(), 0.95 * (double)fr) + (double)held -
                        (double)g_stage;
-  const double panels = (double)sizeof(double) * TILE * TILE * (needC + needG);
+  const double panels = (double)sizeof(double) * TILE * TILE *
+                        (needC + (p.gauge ? (p.fused_breit ? 6 : 7) : 1) * needG);
   const int64_t wmax = (int64_t)std::max(p.NL, p.NS) * 4 * p.n;
   const double per_col = (double)sizeof(double) * (wmax + 4.0 * p.n * p.n);
   if (panels + dv_bytes(p, 32) + 64.0 * per_col > 0.85 * room0) return false;
@@ -261,7 +289,8 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
                              const qdcb_plan_desc *desc, qdcb_plan **out) {
   return guarded([&] {
     if (!ctx || !L || !desc || !out) fail(QDCB_E_INVALID, "NULL argument");
-    if (desc->ham != QDCB_HAM_LL && desc->ham != QDCB_HAM_DC && desc->ham != QDCB_HAM_DCG)
+    if (desc->ham != QDCB_HAM_LL && desc->ham != QDCB_HAM_DC && desc->ham != QDCB_HAM_DCG &&
+        desc->ham != QDCB_HAM_DCB)
       fail(QDCB_E_INVALID, "unknown Hamiltonian");
     if (desc->prec != QDCB_PREC_FP64 && desc->prec != QDCB_PREC_MIXED)
       fail(QDCB_E_INVALID, "unknown precision mode");
@@ -289,7 +318,9 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
     p.n = desc->n_mo;
     p.NL = L->nfunc;
     p.NS = S ? S->nfunc : 0;
-    p.gaunt = desc->ham == QDCB_HAM_DCG;
+    p.gaunt = desc->ham == QDCB_HAM_DCG || desc->ham == QDCB_HAM_DCB;
+    p.gauge = desc->ham == QDCB_HAM_DCB;
+    p.fused_breit = p.gauge && desc->prec == QDCB_PREC_FP64;
     p.spinor = desc->flags & QDCB_PLAN_SPINOR;
     if (p.spinor) {  // pairs of spinors c <= d, two pairs per four-column group
       p.npair_s = p.n * (p.n + 1) / 2;
@@ -441,6 +472,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
     }
     size_plan(p, 0, 0);
     p.boys.upload(ctx, boys_table());
+    if (p.gauge) p.boys3.upload(ctx, boys_table3());
     HIPC(hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking));
     ctx->retain();
     *out = pl.release();
@@ -465,7 +497,10 @@ qdcb_status qdcb_plan_estimate(const qdcb_basis *L, const qdcb_basis *S,
     if ((desc->ham == QDCB_HAM_LL) != (S == nullptr))
       fail(QDCB_E_INVALID, "S must be NULL exactly for QDCB_HAM_LL");
     if (desc->n_mo < 1 || desc->n_mo > 512) fail(QDCB_E_INVALID, "n_mo must be in [1, 512]");
-    const bool gaunt = desc->ham == QDCB_HAM_DCG;
+    const bool gaunt = desc->ham == QDCB_HAM_DCG || desc->ham == QDCB_HAM_DCB;
+    // gauge (or fused Breit) tiles: six per slot, plus the Gaunt tile when mixed
+    const double gmul =
+        desc->ham == QDCB_HAM_DCB ? (desc->prec == QDCB_PREC_MIXED ? 7.0 : 6.0) : 1.0;
     const double n = desc->n_mo, NL = L->nfunc, NS = S ? S->nfunc : 0;
     const bool spinor = desc->flags & QDCB_PLAN_SPINOR;
     // MO-pair columns: 4 per quaternion pair, 2 per spinor pair (in groups of two)
@@ -484,7 +519,7 @@ qdcb_status qdcb_plan_estimate(const qdcb_basis *L, const qdcb_basis *S,
     b += 8.0 * 256 * (std::max(NL, NS) * 4 * n + 4 * n * n);  // second-half slice
     b += 8.0 * 20.0 * (NL + NS) * n * 4;                  // coefficient matrices
     auto slots = [](double nt) { return std::min(nt * nt, std::max(nt, 65536.0)); };
-    b += 8.0 * TILE * TILE * (slots(ntC) + (gaunt ? slots(ntG) : 0.0));  // integral panels
+    b += 8.0 * TILE * TILE * (slots(ntC) + (gaunt ? gmul * slots(ntG) : 0.0));  // integral panels
     b += 8.0 * (spinor ? 2.0 : 16.0) * n * n * n * n;     // host-path G staging
     *bytes = (size_t)(b * 1.05);
   });
@@ -495,7 +530,7 @@ qdcb_status qdcb_plan_footprint(const qdcb_plan *p, size_t *bytes) {
     if (!p || !bytes) fail(QDCB_E_INVALID, "NULL argument");
     size_t b = p->C.bytes() + p->G.bytes();
     for (auto *x : {&p->CLd, &p->CSd, &p->Gd, &p->CallL, &p->CallS, &p->ChatL, &p->ChatS, &p->boys,
-                    &p->W, &p->Gc})
+                    &p->boys3, &p->W, &p->Gc})
       b += x->bytes();
     for (int K = 0; K < 3; ++K) b += p->AhatK[K].bytes() + p->BhatK[K].bytes();
     b += p->rs.bytes() + p->rowmapL.bytes() + p->rowmapS.bytes() + p->rowmapLS.bytes();

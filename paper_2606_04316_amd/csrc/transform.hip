@@ -201,7 +201,10 @@ void screen(qdcb_plan &p, Space &sp, bool captured, hipStream_t s, bool zero_kep
   sp.sym = captured || sp.total <= sp.panel_slots;
 }
 
-EriTileArgs eri_args(qdcb_plan &p, Space &sp, int64_t slot0, bool count) {
+// gauge: the six-tile gauge panel and its table instead of the integral panel
+// (breit: the fused Breit tiles)
+EriTileArgs eri_args(qdcb_plan &p, Space &sp, int64_t slot0, bool count, bool gauge = false,
+                     bool breit = false) {
   EriTileArgs ea;
   ea.tasks = sp.tasks.p;
   ea.task_bra = sp.task_bra.p;
@@ -212,13 +215,16 @@ EriTileArgs eri_args(qdcb_plan &p, Space &sp, int64_t slot0, bool count) {
   ea.Dmax = sp.Dmax.p;
   ea.cls = sp.cls.p;
   ea.tau = p.desc.tau;
-  ea.panel = sp.panel.p;
+  ea.panel = gauge ? sp.panel3.p : sp.pan();
   ea.kept = count ? sp.kept.p : nullptr;
   ea.boys = p.boys.p;
+  ea.boys3 = gauge ? p.boys3.p : nullptr;
+  ea.gauge_diag = breit ? 0.5 : -0.5;
+  if (gauge && !ea.boys3) fail(QDCB_E_DEVICE, "gauge tiles without their table");
   return ea;
 }
 
-FirstHalfArgs fh_args(Space &sp, int b0, int b1, int64_t slot0) {
+FirstHalfArgs fh_args(Space &sp, int b0, int b1, int64_t slot0, bool gauge = false) {
   FirstHalfArgs fa;
   fa.b0 = b0;
   fa.b1 = b1;
@@ -226,19 +232,29 @@ FirstHalfArgs fh_args(Space &sp, int b0, int b1, int64_t slot0) {
   fa.count = sp.count.p;
   fa.tasks = sp.tasks.p;
   fa.slot0 = slot0;
-  fa.panel = sp.panel.p;
+  fa.panel = gauge ? sp.panel3.p : sp.pan();
   fa.D = sp.D.p;
   fa.V = sp.V.p;
   fa.ld = sp.ld;
-  fa.ncol_tiles = (int)(sp.ld / 128);
+  fa.ncol_tiles = (int)((gauge ? sp.ldK : sp.ld) / 128);  // gauge: per K block
   return fa;
 }
 
 // First-half contraction of bra tiles [fa.b0, fa.b1): FP64 plans in one
 // launch; mixed plans as the FP64 tier (which stores V) followed by the FP32
-// and BF16 tiers (which add to it).
-void contract(qdcb_plan &p, Space &sp, FirstHalfArgs fa, StageTimer &tm, hipStream_t s) {
+// and BF16 tiers (which add to it).  Gauge term (gauge >= 0): one FP64
+// launch over the directed lists in every precision mode, adding to V when
+// gauge = 1 (after the Gaunt term) and storing when gauge = 0.
+void contract(qdcb_plan &p, Space &sp, FirstHalfArgs fa, StageTimer &tm, hipStream_t s,
+              int gauge = -1) {
   fa.plain_order = p.tune.fh_order;
+  if (gauge >= 0) {
+    tm.begin(ST_FH);
+    launch_first_half_gauge(fa, sp.ldK, gauge, s);
+    tm.end();
+    HIPC(hipGetLastError());
+    return;
+  }
   if (p.desc.prec != QDCB_PREC_MIXED) {
     tm.begin(ST_FH);
     launch_first_half(fa, s);
@@ -270,55 +286,70 @@ void contract(qdcb_plan &p, Space &sp, FirstHalfArgs fa, StageTimer &tm, hipStre
 int eri_queue_blocks(const qdcb_plan &p) { return 2 * std::max(p.n_cu, 1); }
 
 // Integral tiles + first half of one space over its current column chunk.
+// gauge >= 0: the gauge term of the L-S space (its six-tile panel, same task
+// lists and batches), adding to V when gauge = 1; breit: the Gaunt and gauge
+// terms together from the fused Breit tiles (gauge = 0).
 void first_half(qdcb_plan &p, Space &sp, bool make_tiles, bool count, bool captured,
-                StageTimer &tm, hipStream_t s) {
+                StageTimer &tm, hipStream_t s, int gauge = -1, bool breit = false) {
+  const bool g3 = gauge >= 0;
+  const int64_t slot_elems = (g3 ? 6 : 1) * (int64_t)(TILE * TILE);
   if (sp.sym) {
     // every directed tile is resident: the unique tiles are computed once
     // (first chunk) and written to both of their directed slots; then all bra
     // tiles are contracted in one launch
     if (make_tiles) {
-      EriTileArgs ea = eri_args(p, sp, 0, count);
+      EriTileArgs ea = eri_args(p, sp, 0, count, g3, breit);
       ea.tasks = sp.utask_k.p;
       ea.task_bra = sp.utask_b.p;
       ea.uslot_bk = sp.uslot_bk.p;
       ea.uslot_kb = sp.uslot_kb.p;
       const bool queue = p.tune.eri_sched == 1;
-      unsigned long long *qctr = sp.lpt.p + 2 * LPT_CLASSES;  // zeroed with the order
+      // the queue counter is zeroed with the order; a second persistent launch
+      // over the same order (the gauge tiles) zeroes it again first
+      unsigned long long *qctr = sp.lpt.p + 2 * LPT_CLASSES;
+      if (queue && g3) launch_zero_u64(qctr, 1, s);
+      auto tiles = [&](int64_t n_host, int nblocks, int64_t nlist) {
+        if (queue && g3)
+          launch_eri_gauge_tiles_queue(ea, sp.uorder.p, qctr, n_host, nblocks, s);
+        else if (queue)
+          launch_eri_tiles_queue(ea, sp.uorder.p, qctr, n_host, nblocks, s);
+        else if (g3)
+          launch_eri_gauge_tiles(ea, nlist, s);
+        else
+          launch_eri_tiles(ea, nlist, s);
+      };
       if (captured) {
         ea.overflow = sp.overflow.p;
         ea.d_total = sp.udtotal.p;
         ea.cap = sp.panel_slots;
-        if (queue)
-          launch_eri_tiles_queue(ea, sp.uorder.p, qctr, 0, eri_queue_blocks(p), s);
-        else
-          launch_eri_tiles(ea, std::min<int64_t>(sp.panel_slots, (int64_t)sp.utask_k.n), s);
+        tiles(0, eri_queue_blocks(p), std::min<int64_t>(sp.panel_slots, (int64_t)sp.utask_k.n));
       } else {
         tm.begin(ST_ERI);
-        if (queue)
-          launch_eri_tiles_queue(ea, sp.uorder.p, qctr, sp.utotal,
-                                 (int)std::min<int64_t>(eri_queue_blocks(p), sp.utotal), s);
-        else
-          launch_eri_tiles(ea, sp.utotal, s);
+        tiles(sp.utotal, (int)std::min<int64_t>(eri_queue_blocks(p), sp.utotal), sp.utotal);
         tm.end();
-        p.tiles_made += sp.utotal;
+        if (!g3) p.tiles_made += sp.utotal;
       }
       HIPC(hipGetLastError());
     }
-    FirstHalfArgs fa = fh_args(sp, 0, sp.ntiles, 0);
+    FirstHalfArgs fa = fh_args(sp, 0, sp.ntiles, 0, g3);
     if (captured) fa.overflow = sp.overflow.p;
-    contract(p, sp, fa, tm, s);
+    contract(p, sp, fa, tm, s, gauge);
     return;
   }
   if (captured) {
     if (make_tiles) {
-      EriTileArgs ea = eri_args(p, sp, 0, count);
+      EriTileArgs ea = eri_args(p, sp, 0, count, g3, breit);
       ea.d_total = sp.dtotal.p;
       ea.cap = sp.panel_slots;
-      launch_eri_tiles(ea, std::min<int64_t>(sp.panel_slots, (int64_t)sp.ntiles * sp.ntiles), s);
+      const int64_t n = std::min<int64_t>(sp.panel_slots, (int64_t)sp.ntiles * sp.ntiles);
+      if (g3)
+        launch_eri_gauge_tiles(ea, n, s);
+      else
+        launch_eri_tiles(ea, n, s);
     }
-    FirstHalfArgs fa = fh_args(sp, 0, sp.ntiles, 0);
+    FirstHalfArgs fa = fh_args(sp, 0, sp.ntiles, 0, g3);
     fa.overflow = sp.overflow.p;
-    contract(p, sp, fa, tm, s);
+    contract(p, sp, fa, tm, s, gauge);
     return;
   }
   // Batches of consecutive bra tiles.  When the tiles are generated here, the
@@ -353,18 +384,21 @@ void first_half(qdcb_plan &p, Space &sp, bool make_tiles, bool count, bool captu
   std::vector<hipEvent_t> made(batches.size()), done(batches.size());
   for (size_t i = 0; i < batches.size(); ++i) {
     const Batch &B = batches[i];
-    double *panel = sp.panel.p + B.off * (int64_t)(TILE * TILE);
+    double *panel = (g3 ? sp.panel3.p : sp.pan()) + B.off * slot_elems;
     if (make_tiles) {
       hipStream_t es = pipe ? p.side : s;
       if (pipe) {
         HIPC(hipStreamWaitEvent(es, ready, 0));
         if (!resident_all && i >= 2) HIPC(hipStreamWaitEvent(es, done[i - 2], 0));
       }
-      EriTileArgs ea = eri_args(p, sp, sp.base[B.b0], count);
+      EriTileArgs ea = eri_args(p, sp, sp.base[B.b0], count, g3, breit);
       ea.panel = panel;
       tm.begin(ST_ERI, es);
-      launch_eri_tiles(ea, B.used, es);
-      p.tiles_made += B.used;
+      if (g3)
+        launch_eri_gauge_tiles(ea, B.used, es);
+      else
+        launch_eri_tiles(ea, B.used, es);
+      if (!g3) p.tiles_made += B.used;
       tm.end(es);
       HIPC(hipGetLastError());
       if (pipe) {
@@ -372,9 +406,9 @@ void first_half(qdcb_plan &p, Space &sp, bool make_tiles, bool count, bool captu
         HIPC(hipStreamWaitEvent(s, made[i], 0));
       }
     }
-    FirstHalfArgs fa = fh_args(sp, B.b0, B.b1, sp.base[B.b0]);
+    FirstHalfArgs fa = fh_args(sp, B.b0, B.b1, sp.base[B.b0], g3);
     fa.panel = panel;
-    contract(p, sp, fa, tm, s);
+    contract(p, sp, fa, tm, s, gauge);
     if (pipe && !resident_all) done[i] = tm.record(s);
   }
 }
@@ -456,13 +490,20 @@ struct BlockSink {
   }
 };
 
-enum { CLS_COULOMB = 1, CLS_GAUNT = 2 };
+enum { CLS_COULOMB = 1, CLS_GAUNT = 2, CLS_GAUGE = 4, CLS_LS = CLS_GAUNT | CLS_GAUGE };
 
-void second_half(qdcb_plan &p, int i0, int i1, double *dG, hipStream_t s,
-                 int classes = CLS_COULOMB | CLS_GAUNT, BlockSink *sink = nullptr) {
+// Every integral class of the plan's Hamiltonian.
+int all_classes(const qdcb_plan &p) {
+  return CLS_COULOMB | (p.gaunt ? CLS_GAUNT : 0) | (p.gauge ? CLS_GAUGE : 0);
+}
+
+// classes: the V of the L-S space holds the Gaunt and / or gauge terms, whose
+// second halves are the same.
+void second_half(qdcb_plan &p, int i0, int i1, double *dG, hipStream_t s, int classes,
+                 BlockSink *sink = nullptr) {
   const int n = p.n;
   const int64_t cend = 4LL * i1;
-  const bool do_c = classes & CLS_COULOMB, do_g = p.gaunt && (classes & CLS_GAUNT);
+  const bool do_c = classes & CLS_COULOMB, do_g = p.gaunt && (classes & CLS_LS);
   // slices of whole MO pairs; with blocked output, of at most one block
   const int64_t step = sink ? std::min<int64_t>(p.sc, 4 * sink->pairs) : p.sc;
   for (int64_t c0 = 4LL * i0; c0 < cend; c0 += step) {
@@ -515,13 +556,15 @@ void second_half(qdcb_plan &p, int i0, int i1, double *dG, hipStream_t s,
 
 // Enqueue one whole transformation of device inputs into device G.
 void enqueue(qdcb_plan &p, const double *dCL, const double *dCS, double *dG, bool captured,
-             StageTimer &tm, hipStream_t s, int classes = CLS_COULOMB | CLS_GAUNT,
-             BlockSink *sink = nullptr) {
+             StageTimer &tm, hipStream_t s, int classes = -1, BlockSink *sink = nullptr) {
+  if (classes < 0) classes = all_classes(p);
   std::vector<Space *> spaces;
   if (classes & CLS_COULOMB) spaces.push_back(&p.C);
   else launch_zero_u64(p.C.kept.p, 4, s);
-  if (p.gaunt && (classes & CLS_GAUNT)) spaces.push_back(&p.G);
+  if (p.gaunt && (classes & CLS_LS)) spaces.push_back(&p.G);
   else if (p.gaunt) launch_zero_u64(p.G.kept.p, 4, s);
+  const bool gaunt_term = classes & CLS_GAUNT, gauge_term = p.gauge && (classes & CLS_GAUGE);
+  const bool fused = p.fused_breit && gaunt_term && gauge_term;
   p.classes = classes;
   p.tiles_made = 0;
   for (Space *sp : spaces) {
@@ -597,7 +640,17 @@ void enqueue(qdcb_plan &p, const double *dCL, const double *dCS, double *dG, boo
       tm.end();
       // captured mode keeps the tiles of the first chunk (one batch, resident)
       const bool resident = captured || sp->sym || sp->total <= sp->panel_slots;
-      first_half(p, *sp, mo || !resident || i0 == 0, mo || i0 == 0, captured, tm, s);
+      const bool make = mo || !resident || i0 == 0, count = mo || i0 == 0;
+      if (sp == &p.G && fused) {
+        // Gaunt + gauge: one pass over the Breit tiles B_KL + delta_KL (mn|kl)
+        first_half(p, *sp, make, count, captured, tm, s, 0, true);
+        continue;
+      }
+      if (sp != &p.G || gaunt_term) first_half(p, *sp, make, count, captured, tm, s);
+      // gauge term: its own tiles and contraction over the same lists, added
+      // to the Gaunt term's V (counted here only without the Gaunt term)
+      if (sp == &p.G && gauge_term)
+        first_half(p, *sp, make, count && !gaunt_term, captured, tm, s, gaunt_term ? 1 : 0);
     }
     tm.begin(ST_SH);
     second_half(p, i0, i1, dG, s, classes, sink);
@@ -633,13 +686,18 @@ void fill_stats(qdcb_plan &p, qdcb_stats *stats, StageTimer *tm, double ms_total
     stats->total[2] = p.nSS * p.nLL;
     stats->total[3] = p.nSS * p.nSS;
   }
+  const bool ls = p.gaunt && (p.classes & CLS_LS);
+  // first-half products per kept L-S contribution and MO-pair column: 3 (Gaunt,
+  // one per K) and 9 (gauge, K x L)
+  const bool gt = p.classes & CLS_GAUNT, gg = p.gauge && (p.classes & CLS_GAUGE);
+  const double ls_mult = p.fused_breit && gt && gg ? 9.0 : (gt ? 3.0 : 0.0) + (gg ? 9.0 : 0.0);
   stats->kept_gaunt = (int64_t)kg[0];
-  stats->total_gaunt = p.gaunt && (p.classes & CLS_GAUNT) ? p.G.P * p.G.P : 0;
+  stats->total_gaunt = ls ? p.G.P * p.G.P : 0;
   stats->tiles_kept = tiles_c + tiles_g;
   stats->tiles_total = ((p.classes & CLS_COULOMB) ? (int64_t)p.C.ntiles * p.C.ntiles : 0) +
-                       (p.gaunt && (p.classes & CLS_GAUNT) ? (int64_t)p.G.ntiles * p.G.ntiles
-                                                          : 0);
-  stats->flops_first_half = 2.0 * (double)p.ncol * ktot + 6.0 * (double)p.ncol * (double)kg[0];
+                       (ls ? (int64_t)p.G.ntiles * p.G.ntiles : 0);
+  stats->flops_first_half =
+      2.0 * (double)p.ncol * ktot + 2.0 * ls_mult * (double)p.ncol * (double)kg[0];
   double f2 = 0;
   // second quarter: 2 (4n or 2n output rows) (4N) n per column
   const double sq = p.spinor ? 16.0 : 32.0;
@@ -647,21 +705,24 @@ void fill_stats(qdcb_plan &p, qdcb_stats *stats, StageTimer *tm, double ms_total
     double N = cls ? p.NS : p.NL;
     f2 += (8.0 * N * N * n + sq * N * n * n) * (double)p.ncol;
   }
-  if (p.gaunt && (p.classes & CLS_GAUNT))
+  if (ls)
     f2 += 3.0 * (16.0 * p.NL * (double)p.NS * n + sq * (p.NL + p.NS) * (double)n * n) *
           (double)p.ncol;
   stats->flops_second_half = f2;
   stats->n_chunks = p.chunks_run;
   // MFMA flops issued by the first half: every kept directed tile times the
-  // row width of each chunk (per batch for the MO-driven variant)
+  // row width of each chunk (per batch for the MO-driven variant); the L-S
+  // row width (3 K blocks) counts once for Gaunt and three times for the gauge
+  // term (three L blocks per K block)
+  const double gw = ls_mult / 3.0;
   stats->flops_mfma = 2.0 * TILE * TILE *
                       (p.mo_batch > 0 && tm ? p.mo_work
                                             : p.ld_sum[0] * (double)tiles_c +
-                                                  p.ld_sum[1] * (double)tiles_g);
+                                                  gw * p.ld_sum[1] * (double)tiles_g);
   stats->classes = p.classes;
   if (p.desc.prec == QDCB_PREC_MIXED) {
     for (Space *sp : {&p.C, &p.G}) {
-      if (sp == &p.G && !(p.gaunt && (p.classes & CLS_GAUNT))) continue;
+      if (sp == &p.G && !(p.gaunt && (p.classes & CLS_GAUNT))) continue;  // tiers: Gaunt only
       if (sp == &p.C && !(p.classes & CLS_COULOMB)) continue;
       if (sp->h_tcount.size() != 3 * (size_t)sp->ntiles) continue;
       for (int t = 0; t < 3; ++t)
@@ -681,8 +742,8 @@ void read_counters(qdcb_plan &p, hipStream_t s, unsigned long long kc[4],
 }
 
 void run_eager(qdcb_plan &p, const double *dCL, const double *dCS, double *dG, hipStream_t s,
-               qdcb_stats *stats, int classes = CLS_COULOMB | CLS_GAUNT,
-               BlockSink *sink = nullptr) {
+               qdcb_stats *stats, int classes = -1, BlockSink *sink = nullptr) {
+  if (classes < 0) classes = all_classes(p);
   StageTimer tm(s, true);
   hipEvent_t e0, e1;
   HIPC(hipEventCreate(&e0));
@@ -700,22 +761,27 @@ void run_eager(qdcb_plan &p, const double *dCL, const double *dCS, double *dG, h
   p.have_last = true;
   if (stats) {
     fill_stats(p, stats, &tm, ms, kc, kg, (classes & CLS_COULOMB) ? p.C.total : 0,
-               p.gaunt && (classes & CLS_GAUNT) ? p.G.total : 0);
+               p.gaunt && (classes & CLS_LS) ? p.G.total : 0);
     stats->tiles_made = p.tiles_made;
   }
 }
 
 // Integral classes selected by transform flags.
 int class_mask(const qdcb_plan &p, uint32_t flags) {
-  if (flags & ~(uint32_t)(QDCB_PTR_DEVICE | QDCB_CLASS_COULOMB | QDCB_CLASS_GAUNT))
+  if (flags &
+      ~(uint32_t)(QDCB_PTR_DEVICE | QDCB_CLASS_COULOMB | QDCB_CLASS_GAUNT | QDCB_CLASS_GAUGE))
     fail(QDCB_E_INVALID, "unknown transform flag");
   int m = 0;
   if (flags & QDCB_CLASS_COULOMB) m |= CLS_COULOMB;
   if (flags & QDCB_CLASS_GAUNT) m |= CLS_GAUNT;
-  if (!m) m = CLS_COULOMB | CLS_GAUNT;
-  if ((m & CLS_GAUNT) && !(m & CLS_COULOMB) && !p.gaunt)
-    fail(QDCB_E_INVALID, "QDCB_CLASS_GAUNT needs a DCG plan");
-  return m;
+  if (flags & QDCB_CLASS_GAUGE) m |= CLS_GAUGE;
+  const int all = all_classes(p);
+  if (!m) return all;
+  // classes the plan lacks are ignored beside one it has
+  if (!(m & all))
+    fail(QDCB_E_INVALID, (m & CLS_GAUGE) ? "QDCB_CLASS_GAUGE needs a DCB plan"
+                                         : "QDCB_CLASS_GAUNT needs a DCG or DCB plan");
+  return m & all;
 }
 
 // Device copies of host inputs (QDCB_PTR_DEVICE unset): CL, CS into the

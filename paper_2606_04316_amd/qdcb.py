@@ -17,12 +17,14 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqdcb.so")
 
-HAM = {"LL": 0, "DC": 1, "DCG": 2}
+HAM = {"LL": 0, "DC": 1, "DCG": 2, "DCB": 3}
 PREC = {"fp64": 0, "mixed": 1}
 PTR_DEVICE = 0x1
 CLASS_COULOMB = 0x2
 CLASS_GAUNT = 0x4
-CLASSES = {None: 0, "all": 0, "coulomb": CLASS_COULOMB, "gaunt": CLASS_GAUNT}
+CLASS_GAUGE = 0x8
+CLASSES = {None: 0, "all": 0, "coulomb": CLASS_COULOMB, "gaunt": CLASS_GAUNT,
+           "gauge": CLASS_GAUGE, "breit": CLASS_GAUNT | CLASS_GAUGE}
 FETCH_DMAX, FETCH_Q, FETCH_DMAX_GAUNT, FETCH_Q_GAUNT = 1, 2, 3, 4
 PLAN_DIRECTED_TILES = 0x1
 PLAN_TIER_BY_G = 0x2
@@ -274,7 +276,7 @@ class Plan:
     def transform(self, CL, CS=None, G=None, stream=None, classes=None):
         """Returns (G, stats).  numpy inputs use the host path; torch CUDA
         tensors the device path (G must then be a CUDA float64 tensor or None).
-        classes: None (all), "coulomb" or "gaunt"."""
+        classes: None (all), "coulomb", "gaunt", "gauge" or "breit" (Gaunt + gauge)."""
         n = self.n
         st = Stats()
         cf = CLASSES[classes]
@@ -421,7 +423,7 @@ class Plan:
         (concatenated LL, SS, LS indexing), quaternion components."""
         idx = np.ascontiguousarray(pairs, dtype=np.int64)
         npair = self.n * (self.n + 1) // 2
-        out = np.empty((idx.shape[0], (3 if self.ham == "DCG" else 1) * 4 * npair))
+        out = np.empty((idx.shape[0], (3 if self.ham in ("DCG", "DCB") else 1) * 4 * npair))
         _check(lib().qdcb_plan_fetch_v(self.h, idx.ctypes.data, int(idx.shape[0]),
                                        out.ctypes.data))
         return out

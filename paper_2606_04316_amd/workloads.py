@@ -321,6 +321,8 @@ def config(name: str) -> System:
     ``chain40`` 40-atom chain (2.5 bohr), N_L = 400, N_S = 800, n = 64, DC, tau 1e-10.
     ``cluster60`` 60-atom cluster (20 bohr ball), N_L = 600, N_S = 1200,
                K in 1..6, n = 128, DC + Gaunt, tau 1e-10.
+    ``chain40_dcg``, ``chain40_dcb``, ``cluster60_dcb``  the same systems with
+               the Gaunt term, or the whole Breit term (Gaunt + gauge).
     """
     if name == "ll24":
         return small_ll(seed=1)
@@ -328,8 +330,12 @@ def config(name: str) -> System:
         return linear_chain(seed=2)
     if name == "chain40_dcg":
         return linear_chain(seed=2, ham="DCG")
+    if name == "chain40_dcb":
+        return linear_chain(seed=2, ham="DCB")
     if name == "cluster60":
         return cluster(seed=3)
+    if name == "cluster60_dcb":
+        return cluster(seed=3, ham="DCB")
     if name == "cluster24":
         # the cluster recipe at 24 atoms (radius scaled by (24/60)^(1/3)), n = 64
         return cluster(seed=3, n_atoms=24, radius=20.0 * (24 / 60) ** (1 / 3), n=64)
