@@ -210,3 +210,19 @@ def test_mo_driven_dcb_matches_oracle(q, ctx):
     Go, so = oracle.transform_direct_mo(s.L, s.S, s.CL, s.CS, "DCB", s.tau, 4)
     assert st["kept"] == so["kept"] and st["kept_gaunt"] == so["kept_gaunt"]
     assert np.abs(G - Go).max() <= 1e-12 * _scale(s)
+
+
+def test_degenerate_cases(q, ctx):
+    # nothing kept: G is zero and no tile is made
+    s = _chain(67, n=3, tau=1e30)
+    L, S = q.Basis(ctx, s.L), q.Basis(ctx, s.S)
+    G, st = q.Plan(ctx, L, S, "DCB", s.n_mo, 1e30).transform(s.CL, s.CS)
+    assert not np.any(G) and st["kept_gaunt"] == 0 and st["tiles_kept"] == 0
+    # one MO (a single MO pair, one column group) and a single-atom basis
+    s1 = wl.linear_chain(seed=68, n_atoms=1, spacing=3.0, nl_per_atom=3, ns_per_atom=4, n=1,
+                         tau=0.0, ham="DCB")
+    L1, S1 = q.Basis(ctx, s1.L), q.Basis(ctx, s1.S)
+    G1, st1 = q.Plan(ctx, L1, S1, "DCB", 1, 0.0).transform(s1.CL, s1.CS)
+    Go, so = oracle.transform_direct(s1.L, s1.S, s1.CL, s1.CS, "DCB", 0.0)
+    assert st1["kept_gaunt"] == so["kept_gaunt"] == (3 * 4) ** 2
+    assert np.abs(G1 - Go).max() <= 1e-12 * _scale(s1)

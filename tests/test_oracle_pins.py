@@ -390,6 +390,55 @@ def test_screening_certificate_and_counts():
     assert diff.max() > 100 * slack  # screening did change the result
 
 
+def _gaunt_pair_densities(s):
+    """D^{K,pq}_{mn} = conj(C^L_mp) e_K C^S_nq + conj(C^S_np) e_K C^L_mq, [K][4][NL][NS][n][n]."""
+    NL, NS, n = s.L.nfunc, s.S.nfunc, s.n_mo
+    unit = {0: np.array([0, 0, 0, 1.0]), 1: np.array([0, 0, 1.0, 0]), 2: np.array([0, 1.0, 0, 0])}
+    out = np.zeros((3, 4, NL, NS, n, n))
+    for K in range(3):
+        e = unit[K].reshape(4, 1, 1)
+        for m_ in range(NL):
+            for n_ in range(NS):
+                a = qalg.qmul(qalg.qconj(s.CL[:, m_, :])[:, :, None] * np.ones((1, 1, n)),
+                              e * np.ones((1, n, n)))
+                t1 = qalg.qmul(a, s.CS[:, n_, :][:, None, :] * np.ones((1, n, 1)))
+                b = qalg.qmul(qalg.qconj(s.CS[:, n_, :])[:, :, None] * np.ones((1, 1, n)),
+                              e * np.ones((1, n, n)))
+                t2 = qalg.qmul(b, s.CL[:, m_, :][:, None, :] * np.ones((1, n, 1)))
+                out[K, :, m_, n_] = t1 + t2
+    return out
+
+
+def test_gauge_screening_certificate_and_counts():
+    # The gauge classes take the Gaunt predicate Q_mn Q_kl Dmax_kl >= tau.  For
+    # non-negative s pair distributions |B_KL| = |(T_KL - delta_KL / r)| / 2 is
+    # at most (mn|kl) / 2 <= Q_mn Q_kl / 2, so a skipped contribution adds at
+    # most (3/2) tau sum_K |[D^{K,pq}_mn]_x| to G^{xy}_{pqrs}.
+    s = wl.linear_chain(seed=17, n_atoms=3, spacing=2.0, nl_per_atom=2, ns_per_atom=3, n=2,
+                        tau=0.0, ham="GAUGE")
+    NL, NS, n = s.L.nfunc, s.S.nfunc, s.n_mo
+    Qp = oracle.schwarz(s.L, s.S).reshape(-1)
+    Dp = oracle.dmax_gaunt(s.CL, s.CS).reshape(-1)
+    bnd = np.outer(Qp, Qp * Dp)
+    tau = float(np.quantile(bnd, 0.5))
+    skip = ~((Qp[:, None] * Qp[None, :]) * Dp[None, :] >= tau)
+    assert 0.3 < skip.mean() < 0.7
+    Gf, stf = oracle.transform_direct(s.L, s.S, s.CL, s.CS, "GAUGE", 0.0)
+    Gs, sts = oracle.transform_direct(s.L, s.S, s.CL, s.CS, "GAUGE", tau)
+    assert sts["total_gaunt"] == (NL * NS) ** 2 and stf["kept_gaunt"] == (NL * NS) ** 2
+    assert sts["kept_gaunt"] == int((~skip).sum())
+    # the gauge route keeps exactly what the Gaunt route keeps
+    assert oracle.transform_direct(s.L, s.S, s.CL, s.CS, "GAUNT", tau)[1]["kept_gaunt"] == \
+        sts["kept_gaunt"]
+    D = _gaunt_pair_densities(s)
+    w = np.abs(D).sum(axis=0).reshape(4, NL * NS, n, n).transpose(1, 2, 3, 0)  # [pair][p][q][x]
+    bound = 1.5 * tau * np.einsum("ij,ipqx->pqx", skip.astype(float), w)
+    diff = np.abs(Gs - Gf)
+    slack = 1e-13 * np.abs(Gf).max()
+    assert np.all(diff <= bound[:, :, None, None, :, None] + slack)
+    assert diff.max() > 100 * slack  # screening did change the result
+
+
 def test_zero_threshold_keeps_everything_including_zeros():
     s = wl.small_ll(seed=4, n_atoms=3, nfunc=6, n=2)
     C = np.zeros((4, 6, 2))
