@@ -64,6 +64,8 @@ def parse():
                     help="serving: precisions to serve the stream in, one run each "
                          "(mixed: tiers 1e-6 / 1e-9 with the G-bound rule)")
     ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--prim-bands", action="store_true",
+                    help="plans with QDCB_PLAN_PRIM_BANDS (rows grouped by primitive count)")
     ap.add_argument("--mo-batch", type=int, default=0,
                     help="transform: run the MO-driven variant with batches of this many MO "
                          "pairs, each screened with its own density bound (0: AO-driven)")
@@ -150,7 +152,8 @@ def main_transform(args):
     L = qdcb.Basis(ctx, sysm.L)
     S = qdcb.Basis(ctx, sysm.S) if sysm.S is not None else None
     plan = qdcb.Plan(ctx, L, S, sysm.ham, n, sysm.tau,
-                     flags=qdcb.PLAN_SPINOR if spinor else 0)
+                     flags=(qdcb.PLAN_SPINOR if spinor else 0) |
+                     (qdcb.PLAN_PRIM_BANDS if args.prim_bands else 0))
     if args.mo_batch:
         plan.set_mo_batch(args.mo_batch)
     if args.copy_calibration_mib:
@@ -204,7 +207,8 @@ def main_transform(args):
                    "n_mo": n, "mo_kind": "general spinors" if spinor else "Kramers pairs",
                    "ham": sysm.ham, "tau": sysm.tau,
                    "algorithm": f"MO-driven, {args.mo_batch} MO pairs per batch"
-                   if args.mo_batch else "AO-driven"},
+                   if args.mo_batch else "AO-driven",
+                   "row_order": "primitive bands" if args.prim_bands else "Schwarz"},
         "spinor_integrals_per_s": (n if spinor else 2 * n) ** 4 * args.steps / elapsed,
         "stages_ms": {k: st0[k] for k in ("ms_density", "ms_screen", "ms_eri", "ms_first_half",
                                           "ms_second_half", "ms_total")},
@@ -394,14 +398,15 @@ def serving_run(args, prec):
     reqs = serving.request_stream(args.requests, seed=5, mean_gap_s=0.02, pool=12,
                                   atoms=(10, 40), nl=(40, 160), n_mo=(8, 32),
                                   radius_scale=20.0)
-    ex = serving.GpuExecutor(slots=args.slots, prec=prec)
+    pf = 0x8 if args.prim_bands else 0  # QDCB_PLAN_PRIM_BANDS
+    ex = serving.GpuExecutor(slots=args.slots, prec=prec, plan_flags=pf)
     budget = int(0.5 * torch.cuda.mem_get_info()[0])
     srv = serving.Server(ex, ex.reserve, slots=args.slots, budget_bytes=budget)
     out = srv.run(reqs)
     ex.drain()
     summ = serving.summarize(out)
     print(f"serving {prec}: {summ}", file=sys.stderr, flush=True)
-    alone = serving.GpuExecutor(slots=1, prec=prec)
+    alone = serving.GpuExecutor(slots=1, prec=prec, plan_flags=pf)
     same = 0
     for r in [r for r in out if r.error is None][:: max(1, len(out) // 8)][:8]:
         solo = serving.Request(rid=r.rid, system=r.system, arrival=0.0)
@@ -409,6 +414,7 @@ def serving_run(args, prec):
         same += alone(solo, 0)["digest"] == r.result["digest"]
     alone.drain()
     summ.update({"slots": args.slots, "max_concurrency": srv.max_concurrency,
+                 "prim_bands": bool(args.prim_bands),
                  "peak_reserved_GB": srv.peak_in_use / 2 ** 30,
                  "alone_equals_mix": f"{same}/8"})
     if prec == "mixed":

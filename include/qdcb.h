@@ -161,11 +161,19 @@ typedef struct {
  * (im), which is also the column layout of qdcb_plan_fetch_v.  Blocked output
  * (qdcb_transform_blocks) is not offered for these plans. */
 #define QDCB_PLAN_SPINOR 0x4u
+/* Row order for uneven contraction depths: the pairs of each space, ordered
+ * by Schwarz factor, are regrouped in bands of 8 x 64 rows by their primitive
+ * pair count (decreasing), so that the 64 rows of an integral tile have
+ * similar primitive loops (lanes of the integral kernel idle less).  The tile
+ * bounds get looser (a tile spans the band's Schwarz range), so more tile
+ * pairs are kept; worth it when the integral tiles dominate (deep
+ * contractions, few MO pairs).  Results agree to rounding. */
+#define QDCB_PLAN_PRIM_BANDS 0x8u
 
 /* Plan for transforming with fixed bases and n_mo.  S must be NULL for
  * QDCB_HAM_LL and non-NULL otherwise.  Orders the pairs of each integral
  * class space (Coulomb: LL and SS pairs; Gaunt, for DCG: ordered LS pairs) by
- * their Schwarz factor and allocates the per-transform device buffers; the
+ * their Schwarz factor (see QDCB_PLAN_PRIM_BANDS) and allocates the per-transform device buffers; the
  * MO-pair columns are processed in chunks when they do not fit at once.
  * QDCB_E_NOMEM if even the smallest chunk does not fit the context budget. */
 qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basis *S,

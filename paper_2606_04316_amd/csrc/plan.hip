@@ -24,10 +24,17 @@ struct RowSrc {
   int which;  // which source store
 };
 
+// Rows ordered by Schwarz factor; band_rows > 0: within each band of that many
+// rows, by primitive-pair count (decreasing, Schwarz order among equals).
 void build_space(qdcb_ctx *ctx, Space &sp, std::vector<RowSrc> &rows,
-                 const std::vector<const PairStore *> &stores) {
+                 const std::vector<const PairStore *> &stores, int64_t band_rows) {
   std::stable_sort(rows.begin(), rows.end(),
                    [](const RowSrc &a, const RowSrc &b) { return a.Q > b.Q; });
+  for (int64_t b0 = 0; band_rows > 0 && b0 < (int64_t)rows.size(); b0 += band_rows) {
+    const int64_t b1 = std::min<int64_t>((int64_t)rows.size(), b0 + band_rows);
+    std::stable_sort(rows.begin() + b0, rows.begin() + b1,
+                     [](const RowSrc &a, const RowSrc &b) { return a.cnt > b.cnt; });
+  }
   sp.P = (int64_t)rows.size();
   sp.Ppad = std::max<int64_t>(round_up(sp.P, TILE), TILE);
   // unique-tile slot numbers are int32: ntiles (ntiles + 1) / 2 < 2^31
@@ -303,7 +310,8 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
     if (desc->n_mo < 1 || desc->n_mo > 512) fail(QDCB_E_INVALID, "n_mo must be in [1, 512]");
     if (!std::isfinite(desc->tau) || desc->tau < 0) fail(QDCB_E_INVALID, "tau must be >= 0");
     if (desc->flags &
-        ~(int32_t)(QDCB_PLAN_DIRECTED_TILES | QDCB_PLAN_TIER_BY_G | QDCB_PLAN_SPINOR))
+        ~(int32_t)(QDCB_PLAN_DIRECTED_TILES | QDCB_PLAN_TIER_BY_G | QDCB_PLAN_SPINOR |
+                   QDCB_PLAN_PRIM_BANDS))
       fail(QDCB_E_INVALID, "unknown plan flag");
     // bases may belong to another context (resident, shared) on the same device
     if (L->ctx->device != ctx->device || (S && S->ctx->device != ctx->device))
@@ -329,6 +337,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
       p.npair_mo = p.n * (p.n + 1) / 2;
     }
     p.ncol = 4LL * p.npair_mo;
+    const int64_t bands = (desc->flags & QDCB_PLAN_PRIM_BANDS) ? 8 * TILE : 0;
 
     // --- Coulomb space: LL pairs, then SS pairs
     {
@@ -350,7 +359,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
       }
       p.C.gaunt = 0;
       p.C.nK = 1;
-      build_space(ctx, p.C, rows, stores);
+      build_space(ctx, p.C, rows, stores, bands);
     }
     // --- Gaunt space: ordered LS pairs (mu in L, nu in S), key mu*NS + nu
     if (p.gaunt) {
@@ -384,7 +393,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
         rows[i] = RowSrc{hQ[i], 0, pm[i], pn[i], i, pf[i], (int32_t)(pf[i + 1] - pf[i]), 0};
       p.G.gaunt = 1;
       p.G.nK = 3;
-      build_space(ctx, p.G, rows, {&ls});
+      build_space(ctx, p.G, rows, {&ls}, bands);
     }
 
     // --- index tables

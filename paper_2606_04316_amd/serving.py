@@ -172,7 +172,8 @@ class GpuExecutor:
     one HIP stream (torch) per request, the plan created in a context whose
     budget is the request's reservation.  ``prec="mixed"`` runs every plan
     with the reduced-precision tiers (``tiers`` = tier_fp32, tier_bf16, plan
-    flags).
+    flags); ``plan_flags`` are added to every plan's flags (for instance
+    PLAN_PRIM_BANDS for integral-dominated request mixes).
 
     G comes to the host through a pinned staging buffer per slot (reused, so
     a result is delivered as the digest of that copy, or as the device tensor
@@ -182,7 +183,7 @@ class GpuExecutor:
     slots' transforms finish.  ``drain()`` waits for those releases."""
 
     def __init__(self, slots: int, device: int = 0, keep_outputs: bool = False,
-                 prec: str = "fp64", tiers=(1e-6, 1e-9, 0x2)):
+                 prec: str = "fp64", tiers=(1e-6, 1e-9, 0x2), plan_flags: int = 0):
         import torch
         from paper_2606_04316_amd import qdcb
         self.torch = torch
@@ -196,6 +197,7 @@ class GpuExecutor:
         self.keep_outputs = keep_outputs
         self.prec = prec
         self.tiers = tiers
+        self.plan_flags = int(plan_flags)
         self.staging = [None] * slots  # pinned host buffers for G, per slot
         self._retire: "queue.Queue" = queue.Queue()
         self._reaper = threading.Thread(target=self._reap, daemon=True)
@@ -265,9 +267,9 @@ class GpuExecutor:
             if self.prec == "mixed":
                 t32, t16, flags = self.tiers
                 plan = qdcb.Plan(ctx, L, S, s.ham, s.n_mo, s.tau, prec="mixed",
-                                 tier_fp32=t32, tier_bf16=t16, flags=flags)
+                                 tier_fp32=t32, tier_bf16=t16, flags=flags | self.plan_flags)
             else:
-                plan = qdcb.Plan(ctx, L, S, s.ham, s.n_mo, s.tau)
+                plan = qdcb.Plan(ctx, L, S, s.ham, s.n_mo, s.tau, flags=self.plan_flags)
             held["plan"] = plan
             CL = torch.from_numpy(s.CL).to(self.dev, non_blocking=False)
             CS = torch.from_numpy(s.CS).to(self.dev) if s.CS is not None else None
