@@ -161,10 +161,11 @@ typedef struct {
  * (im), which is also the column layout of qdcb_plan_fetch_v.  Blocked output
  * (qdcb_transform_blocks) is not offered for these plans. */
 #define QDCB_PLAN_SPINOR 0x4u
-/* Row order for uneven contraction depths: the pairs of each space, ordered
- * by Schwarz factor, are regrouped in bands of 8 x 64 rows by their primitive
- * pair count (decreasing), so that the 64 rows of an integral tile have
- * similar primitive loops (lanes of the integral kernel idle less).  The tile
+/* Row order for uneven primitive loops: the pairs of each space, ordered by
+ * Schwarz factor, are regrouped in bands of 8 x 64 rows by the number of
+ * primitive pairs that survive primitive screening (decreasing), so that the
+ * 64 rows of an integral tile have similar primitive loops (lanes of the
+ * integral kernel idle less).  The tile
  * bounds get looser (a tile spans the band's Schwarz range), so more tile
  * pairs are kept; worth it when the integral tiles dominate (deep
  * contractions, few MO pairs).  Results agree to rounding. */

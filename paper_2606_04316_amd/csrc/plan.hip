@@ -21,19 +21,44 @@ struct RowSrc {
   int64_t key;
   int64_t src_first;
   int32_t cnt;
-  int which;  // which source store
+  int which;        // which source store
+  int32_t kept = 0;  // primitive pairs kept by primitive screening
 };
 
 // Rows ordered by Schwarz factor; band_rows > 0: within each band of that many
-// rows, by primitive-pair count (decreasing, Schwarz order among equals).
+// rows, by the number of primitive pairs kept by primitive screening
+// (decreasing, Schwarz order among equals).
 void build_space(qdcb_ctx *ctx, Space &sp, std::vector<RowSrc> &rows,
                  const std::vector<const PairStore *> &stores, int64_t band_rows) {
+  // primitive pairs kept per row (rows in their input order)
+  for (size_t w = 0; w < stores.size(); ++w) {
+    std::vector<int64_t> idx, first;
+    std::vector<int32_t> cnt;
+    for (size_t i = 0; i < rows.size(); ++i)
+      if (rows[i].which == (int)w) {
+        idx.push_back((int64_t)i);
+        first.push_back(rows[i].src_first);
+        cnt.push_back(rows[i].cnt);
+      }
+    if (idx.empty()) continue;
+    DBuf<int64_t> dfirst;
+    DBuf<int32_t> dcnt, dk;
+    dfirst.upload(ctx, first);
+    dcnt.upload(ctx, cnt);
+    dk.alloc(ctx, idx.size());
+    launch_prim_count((int64_t)idx.size(), dfirst.p, dcnt.p, stores[w]->cview(), PRIM_EPS, dk.p,
+                      nullptr);
+    HIPC(hipGetLastError());
+    std::vector<int32_t> k(idx.size());
+    HIPC(hipMemcpy(k.data(), dk.p, k.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < idx.size(); ++i) rows[idx[i]].kept = k[i];
+  }
   std::stable_sort(rows.begin(), rows.end(),
                    [](const RowSrc &a, const RowSrc &b) { return a.Q > b.Q; });
   for (int64_t b0 = 0; band_rows > 0 && b0 < (int64_t)rows.size(); b0 += band_rows) {
     const int64_t b1 = std::min<int64_t>((int64_t)rows.size(), b0 + band_rows);
     std::stable_sort(rows.begin() + b0, rows.begin() + b1,
-                     [](const RowSrc &a, const RowSrc &b) { return a.cnt > b.cnt; });
+                     [](const RowSrc &a, const RowSrc &b) { return a.kept > b.kept; });
   }
   sp.P = (int64_t)rows.size();
   sp.Ppad = std::max<int64_t>(round_up(sp.P, TILE), TILE);
@@ -63,18 +88,11 @@ void build_space(qdcb_ctx *ctx, Space &sp, std::vector<RowSrc> &rows,
   std::vector<DBuf<int64_t>> dsrc(ns);
   std::vector<DBuf<int32_t>> dcnt(ns);
   std::vector<int32_t> kept_prims(sp.Ppad, 0);
+  for (int64_t r = 0; r < sp.P; ++r) kept_prims[r] = rows[r].kept;
   for (size_t w = 0; w < ns; ++w) {
     if (src[w].empty()) continue;
     dsrc[w].upload(ctx, src[w]);
     dcnt[w].upload(ctx, cnt[w]);
-    DBuf<int32_t> dk;
-    dk.alloc(ctx, src[w].size());
-    launch_prim_count((int64_t)src[w].size(), dsrc[w].p, dcnt[w].p, stores[w]->cview(),
-                      PRIM_EPS, dk.p, nullptr);
-    HIPC(hipGetLastError());
-    std::vector<int32_t> k(src[w].size());
-    HIPC(hipMemcpy(k.data(), dk.p, k.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
-    for (size_t i = 0; i < k.size(); ++i) kept_prims[rowidx[w][i]] = k[i];
   }
   std::vector<int64_t> rf(sp.Ppad + 1, 0);
   for (int64_t r = 0; r < sp.Ppad; ++r) rf[r + 1] = rf[r] + kept_prims[r];
