@@ -35,7 +35,8 @@ class _Basis(ctypes.Structure):
                 ("centers", ctypes.POINTER(ctypes.c_double)),
                 ("nprim", ctypes.POINTER(ctypes.c_int32)),
                 ("exps", ctypes.POINTER(ctypes.c_double)),
-                ("coefs", ctypes.POINTER(ctypes.c_double))]
+                ("coefs", ctypes.POINTER(ctypes.c_double)),
+                ("cart", ctypes.POINTER(ctypes.c_int32))]
 
 
 class Stats(ctypes.Structure):
@@ -71,6 +72,8 @@ def lib():
         L.orc_eri3.argtypes = [bp, ctypes.c_int, bp, ctypes.c_int, bp, ctypes.c_int, bp,
                                ctypes.c_int, dp]
         L.orc_norm_coefs.argtypes = [bp, dp]
+        L.orc_prim_eri_cart.restype = ctypes.c_double
+        L.orc_prim_eri_cart.argtypes = [ctypes.c_double, dp, ctypes.c_int] * 4
         L.orc_eri.restype = ctypes.c_double
         L.orc_eri.argtypes = [bp, ctypes.c_int, ctypes.c_int, bp, ctypes.c_int, ctypes.c_int]
         L.orc_eri_tensor.argtypes = [bp, bp, bp, bp, dp]
@@ -112,9 +115,12 @@ class _B:
         self.nprim = np.ascontiguousarray(b.nprim, dtype=np.int32)
         self.exps = np.ascontiguousarray(b.exps, dtype=np.float64)
         self.coefs = np.ascontiguousarray(b.coefs, dtype=np.float64)
+        cart = getattr(b, "cart", None)
+        self.cart = None if cart is None else np.ascontiguousarray(cart, dtype=np.int32)
+        ip = ctypes.POINTER(ctypes.c_int32)
         self.s = _Basis(int(self.nprim.shape[0]), _dp(self.centers),
-                        self.nprim.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                        _dp(self.exps), _dp(self.coefs))
+                        self.nprim.ctypes.data_as(ip), _dp(self.exps), _dp(self.coefs),
+                        self.cart.ctypes.data_as(ip) if self.cart is not None else ip())
 
     @property
     def ref(self):
@@ -127,6 +133,21 @@ def boys0(T: float) -> float:
 
 def boys(m: int, T: float) -> float:
     return lib().orc_boys(int(m), float(T))
+
+
+def prim_eri_cart(a, A, ca, b, B, cb, c, C, cc, d, D, cd) -> float:
+    """[ab|cd] over unnormalized Cartesian primitives (centre, exponent,
+    code 0 = s, 1..3 = p_x, p_y, p_z), by the Obara-Saika recursion."""
+    args = []
+    for e, X, k in ((a, A, ca), (b, B, cb), (c, C, cc), (d, D, cd)):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        args += [float(e), _dp(X), int(k)]
+        args.append(X)  # keep alive
+    keep = args[3::4]
+    call = [x for i, x in enumerate(args) if i % 4 != 3]
+    v = lib().orc_prim_eri_cart(*call)
+    del keep
+    return v
 
 
 def eri3(A, mu, B, nu, C, ka, D, la) -> np.ndarray:

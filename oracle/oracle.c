@@ -42,7 +42,7 @@
 typedef double complex cplx;
 
 /* ------------------------------------------------------------------------ */
-/* Boys function and AO integrals over s-type Gaussians                      */
+/* Boys function and AO integrals over s- and p-type Gaussians              */
 /* ------------------------------------------------------------------------ */
 
 /* F0(T) = int_0^1 exp(-T u^2) du = (1/2) sqrt(pi/T) erf(sqrt(T)); the first
@@ -83,23 +83,153 @@ static int64_t *prim_offsets(const orc_basis *b)
     return off;
 }
 
-/* Normalized primitive: (2a/pi)^{3/4} exp(-a r^2).  Overlap of two
- * unnormalized s primitives on one centre: (pi/(a+b))^{3/2}. */
+static int cart_of(const orc_basis *b, int f) { return b->cart ? b->cart[f] : 0; }
+
+static int has_p(const orc_basis *b)
+{
+    for (int f = 0; b && f < b->nfunc; ++f)
+        if (cart_of(b, f)) return 1;
+    return 0;
+}
+
+/* Normalized primitives: (2a/pi)^{3/4} exp(-a r^2) for s and
+ * (2a/pi)^{3/4} 2 sqrt(a) (x - A_x) exp(-a r^2) for p_x (the square of
+ * x exp(-a r^2) integrates to pi^{3/2} / (2 (2a)^{5/2})).  Overlap of two
+ * unnormalized primitives of one function (same centre, same Cartesian
+ * factor): (pi/(a+b))^{3/2} for s, (pi/(a+b))^{3/2} / (2 (a+b)) for p. */
+static double prim_norm(double a, int cart)
+{
+    double n = pow(2.0 * a / M_PI, 0.75);
+    return cart ? n * 2.0 * sqrt(a) : n;
+}
+
 void orc_norm_coefs(const orc_basis *b, double *out)
 {
     int64_t *off = prim_offsets(b);
     for (int f = 0; f < b->nfunc; ++f) {
+        int c = cart_of(b, f);
         double s = 0.0;
         for (int64_t i = off[f]; i < off[f + 1]; ++i)
             for (int64_t j = off[f]; j < off[f + 1]; ++j) {
-                double di = b->coefs[i] * pow(2.0 * b->exps[i] / M_PI, 0.75);
-                double dj = b->coefs[j] * pow(2.0 * b->exps[j] / M_PI, 0.75);
-                s += di * dj * pow(M_PI / (b->exps[i] + b->exps[j]), 1.5);
+                double di = b->coefs[i] * prim_norm(b->exps[i], c);
+                double dj = b->coefs[j] * prim_norm(b->exps[j], c);
+                double pq = b->exps[i] + b->exps[j];
+                double ov = pow(M_PI / pq, 1.5);
+                if (c) ov /= 2.0 * pq;
+                s += di * dj * ov;
             }
         for (int64_t i = off[f]; i < off[f + 1]; ++i)
-            out[i] = b->coefs[i] * pow(2.0 * b->exps[i] / M_PI, 0.75) / sqrt(s);
+            out[i] = b->coefs[i] * prim_norm(b->exps[i], c) / sqrt(s);
     }
     free(off);
+}
+
+/* Primitive ERIs over unnormalized Cartesian Gaussians
+ * (x-A_x)^{a_x} (y-A_y)^{a_y} (z-A_z)^{a_z} exp(-a|r-A|^2), by the recursion
+ * of Obara and Saika (J. Chem. Phys. 84, 3963 (1986)): the vertical relation
+ * builds [a0|c0]^(m) from the auxiliary integrals
+ * [00|00]^(m) = 2 pi^{5/2} / (p q sqrt(p+q)) K_ab K_cd F_m(T), and the
+ * horizontal relations [a, b+1_i | cd] = [a+1_i, b | cd] + (A-B)_i [ab|cd]
+ * (likewise on the ket) move angular momentum onto the second centre of
+ * each pair.  Notation: p = a+b, P = (aA+bB)/p, q = c+d, Q = (cC+dD)/q,
+ * W = (pP+qQ)/(p+q), rho = pq/(p+q), T = rho |P-Q|^2. */
+typedef struct {
+    double p, q, rho;
+    double PA[3], QC[3], WP[3], WQ[3], AB[3], CD[3];
+    double aux[9]; /* [00|00]^(m), m = 0..8 */
+} os_data;
+
+static double os_vrr(const os_data *o, const int a[3], const int c[3], int m)
+{
+    int i;
+    for (i = 0; i < 3; ++i)
+        if (a[i] > 0) break;
+    if (i < 3) {
+        int a1[3] = {a[0], a[1], a[2]};
+        a1[i] -= 1;
+        double v = o->PA[i] * os_vrr(o, a1, c, m) + o->WP[i] * os_vrr(o, a1, c, m + 1);
+        if (a1[i] > 0) {
+            int a2[3] = {a1[0], a1[1], a1[2]};
+            a2[i] -= 1;
+            v += a1[i] / (2.0 * o->p) *
+                 (os_vrr(o, a2, c, m) - o->rho / o->p * os_vrr(o, a2, c, m + 1));
+        }
+        if (c[i] > 0) {
+            int c1[3] = {c[0], c[1], c[2]};
+            c1[i] -= 1;
+            v += c[i] / (2.0 * (o->p + o->q)) * os_vrr(o, a1, c1, m + 1);
+        }
+        return v;
+    }
+    for (i = 0; i < 3; ++i)
+        if (c[i] > 0) break;
+    if (i < 3) {
+        int c1[3] = {c[0], c[1], c[2]};
+        c1[i] -= 1;
+        double v = o->QC[i] * os_vrr(o, a, c1, m) + o->WQ[i] * os_vrr(o, a, c1, m + 1);
+        if (c1[i] > 0) {
+            int c2[3] = {c1[0], c1[1], c1[2]};
+            c2[i] -= 1;
+            v += c1[i] / (2.0 * o->q) *
+                 (os_vrr(o, a, c2, m) - o->rho / o->q * os_vrr(o, a, c2, m + 1));
+        }
+        return v;
+    }
+    return o->aux[m];
+}
+
+static double os_eri(const os_data *o, const int a[3], const int b[3], const int c[3],
+                     const int d[3])
+{
+    for (int i = 0; i < 3; ++i)
+        if (b[i] > 0) {
+            int a1[3] = {a[0], a[1], a[2]}, b1[3] = {b[0], b[1], b[2]};
+            a1[i] += 1;
+            b1[i] -= 1;
+            return os_eri(o, a1, b1, c, d) + o->AB[i] * os_eri(o, a, b1, c, d);
+        }
+    for (int i = 0; i < 3; ++i)
+        if (d[i] > 0) {
+            int c1[3] = {c[0], c[1], c[2]}, d1[3] = {d[0], d[1], d[2]};
+            c1[i] += 1;
+            d1[i] -= 1;
+            return os_eri(o, a, b, c1, d1) + o->CD[i] * os_eri(o, a, b, c, d1);
+        }
+    return os_vrr(o, a, c, 0);
+}
+
+double orc_prim_eri_cart(double a, const double *A, int ca, double b, const double *B, int cb,
+                         double c, const double *C, int cc, double d, const double *D, int cd)
+{
+    os_data o;
+    double p = a + b, q = c + d, rab2 = 0, rcd2 = 0, rpq2 = 0;
+    o.p = p;
+    o.q = q;
+    o.rho = p * q / (p + q);
+    for (int k = 0; k < 3; ++k) {
+        double P = (a * A[k] + b * B[k]) / p;
+        double Q = (c * C[k] + d * D[k]) / q;
+        double W = (p * P + q * Q) / (p + q);
+        o.PA[k] = P - A[k];
+        o.QC[k] = Q - C[k];
+        o.WP[k] = W - P;
+        o.WQ[k] = W - Q;
+        o.AB[k] = A[k] - B[k];
+        o.CD[k] = C[k] - D[k];
+        rab2 += o.AB[k] * o.AB[k];
+        rcd2 += o.CD[k] * o.CD[k];
+        rpq2 += (P - Q) * (P - Q);
+    }
+    double pre = 2.0 * pow(M_PI, 2.5) / (p * q * sqrt(p + q)) * exp(-a * b / p * rab2) *
+                 exp(-c * d / q * rcd2);
+    double T = o.rho * rpq2;
+    for (int m = 0; m < 9; ++m) o.aux[m] = pre * orc_boys(m, T);
+    int la[3] = {0, 0, 0}, lb[3] = {0, 0, 0}, lc[3] = {0, 0, 0}, ld[3] = {0, 0, 0};
+    if (ca) la[ca - 1] = 1;
+    if (cb) lb[cb - 1] = 1;
+    if (cc) lc[cc - 1] = 1;
+    if (cd) ld[cd - 1] = 1;
+    return os_eri(&o, la, lb, lc, ld);
 }
 
 /* Primitive ERI over unnormalized s Gaussians exp(-a|r-A|^2) ... :
@@ -153,21 +283,31 @@ static void prim_eri3(double a, const double *A, double b, const double *B, doub
             out[K * 3 + L] = pre * ((K == L ? F1 : 0.0) + 2.0 * rho * R[K] * R[L] * (F1 - F2));
 }
 
-/* Contracted ERI with per-basis normalized coefficient arrays. */
+/* Contracted ERI with per-basis normalized coefficient arrays; s-type
+ * quartets take the closed form, quartets with a p function the recursion. */
 static double eri4(const orc_basis *A, const double *nA, const int64_t *oA, int i,
                    const orc_basis *B, const double *nB, const int64_t *oB, int j,
                    const orc_basis *C, const double *nC, const int64_t *oC, int k,
                    const orc_basis *D, const double *nD, const int64_t *oD, int l)
 {
+    int ca = cart_of(A, i), cb = cart_of(B, j), cc = cart_of(C, k), cd = cart_of(D, l);
+    int ang = ca || cb || cc || cd;
     double s = 0.0;
     for (int64_t pi = oA[i]; pi < oA[i + 1]; ++pi)
         for (int64_t pj = oB[j]; pj < oB[j + 1]; ++pj)
             for (int64_t pk = oC[k]; pk < oC[k + 1]; ++pk)
-                for (int64_t pl = oD[l]; pl < oD[l + 1]; ++pl)
-                    s += nA[pi] * nB[pj] * nC[pk] * nD[pl] *
-                         prim_eri(A->exps[pi], A->centers + 3 * i, B->exps[pj],
-                                  B->centers + 3 * j, C->exps[pk], C->centers + 3 * k,
-                                  D->exps[pl], D->centers + 3 * l);
+                for (int64_t pl = oD[l]; pl < oD[l + 1]; ++pl) {
+                    double w = nA[pi] * nB[pj] * nC[pk] * nD[pl];
+                    if (ang)
+                        s += w * orc_prim_eri_cart(A->exps[pi], A->centers + 3 * i, ca,
+                                                   B->exps[pj], B->centers + 3 * j, cb,
+                                                   C->exps[pk], C->centers + 3 * k, cc,
+                                                   D->exps[pl], D->centers + 3 * l, cd);
+                    else
+                        s += w * prim_eri(A->exps[pi], A->centers + 3 * i, B->exps[pj],
+                                          B->centers + 3 * j, C->exps[pk], C->centers + 3 * k,
+                                          D->exps[pl], D->centers + 3 * l);
+                }
     return s;
 }
 
@@ -491,6 +631,7 @@ static int def_impl(const orc_basis *L, const orc_basis *S, const double *CL, co
     int NL = L->nfunc, NS = with_S ? S->nfunc : 0, NF = NL + NS, m = general ? n : 2 * n;
     if (NF > 64 || m > 64 || n <= 0) return -1;
     if (ham_gauge(ham) && NF > 32) return -1;
+    if (ham_gauge(ham) && (has_p(L) || (with_S && has_p(S)))) return -1;
 
     /* combined scalar basis */
     nbasis bl = nb_make(L), bs;
@@ -779,6 +920,7 @@ static int direct_impl(const orc_basis *L, const orc_basis *S, const double *CL,
     if (with_S && (!S || !CS)) return -1;
     if (n <= 0 || tau < 0 || ham < 0 || ham > 5) return -1;
     if (general && Vq) return -1;
+    if (ham_gauge(ham) && (has_p(L) || (with_S && has_p(S)))) return -1;
     int NL = L->nfunc, NS = with_S ? S->nfunc : 0, m = general ? n : 2 * n;
     size_t m2 = (size_t)m * m;
     /* gaunt: L-S rows present (Gaunt and/or gauge term) */

@@ -7,9 +7,11 @@
  * load it.  Nothing in the product path calls it.
  *
  * Conventions (all arrays C-contiguous, FP64 unless stated):
- *   basis     s-type contracted Gaussians; coefs multiply normalized
- *             primitives (2a/pi)^{3/4} exp(-a r^2); each contracted function
- *             is rescaled to unit self-overlap.
+ *   basis     contracted Cartesian Gaussians of s or p type; coefs multiply
+ *             normalized primitives (2a/pi)^{3/4} exp(-a r^2) (s) or
+ *             (2a/pi)^{3/4} 2 sqrt(a) (x - A_x) exp(-a r^2) (p_x, likewise
+ *             p_y, p_z); each contracted function is rescaled to unit
+ *             self-overlap.  Gauge-term hams (4, 5) take s functions only.
  *   C         quaternion MO coefficients, planar [4][N][n]:
  *             C = C0 + i C1 + j C2 + k C3.
  *   G         quaternion MO integrals [n][n][n][n][4][4] = G^{xy}_{pqrs}
@@ -39,6 +41,7 @@ typedef struct {
     const int32_t *nprim;  /* [nfunc] */
     const double *exps;    /* [sum nprim] */
     const double *coefs;   /* [sum nprim] */
+    const int32_t *cart;   /* [nfunc] 0 = s, 1, 2, 3 = p_x, p_y, p_z; NULL = all s */
 } orc_basis;
 
 typedef struct {
@@ -61,6 +64,10 @@ double orc_boys(int m, double T);
 /* Coefficients multiplying the unnormalized primitives exp(-a r^2) so that
  * each contracted function has unit norm; out has sum(nprim) entries. */
 void orc_norm_coefs(const orc_basis *b, double *out);
+/* Primitive ERI over unnormalized Cartesian Gaussians: centre X, exponent x,
+ * cartesian code cx (0 = s, 1..3 = p_x, p_y, p_z), Obara-Saika recursion. */
+double orc_prim_eri_cart(double a, const double *A, int ca, double b, const double *B, int cb,
+                         double c, const double *C, int cc, double d, const double *D, int cd);
 
 /* Contracted ERI (mu nu | ka la) in chemists' notation; mu, nu index basis A,
  * ka, la index basis B. */

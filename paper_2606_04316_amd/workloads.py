@@ -33,12 +33,16 @@ SPEED_OF_LIGHT = 137.035999074  # a.u., the value quoted in Sec. 3
 
 @dataclasses.dataclass
 class Basis:
-    """s-type contracted Gaussian basis (all arrays float64/int32, C-contiguous)."""
+    """Contracted Cartesian Gaussian basis (all arrays float64/int32,
+    C-contiguous).  ``cart`` gives each function's type: 0 = s, 1, 2, 3 =
+    p_x, p_y, p_z (None: every function is s).  A p shell is three functions
+    with the same centre, exponents and coefficients."""
 
     centers: np.ndarray  # (nfunc, 3) bohr
     nprim: np.ndarray  # (nfunc,) int32
     exps: np.ndarray  # (sum nprim,)
     coefs: np.ndarray  # (sum nprim,)
+    cart: Optional[np.ndarray] = None  # (nfunc,) int32
 
     @property
     def nfunc(self) -> int:
@@ -59,7 +63,9 @@ class Basis:
         return Basis(np.ascontiguousarray(self.centers[idx]),
                      np.ascontiguousarray(self.nprim[idx]).astype(np.int32),
                      np.ascontiguousarray(np.concatenate(e)) if e else np.zeros(0),
-                     np.ascontiguousarray(np.concatenate(c)) if c else np.zeros(0))
+                     np.ascontiguousarray(np.concatenate(c)) if c else np.zeros(0),
+                     None if self.cart is None
+                     else np.ascontiguousarray(self.cart[idx]).astype(np.int32))
 
 
 @dataclasses.dataclass
@@ -295,6 +301,60 @@ def cluster(seed: int = 3, n_atoms: int = 60, radius: float = 20.0, min_sep: flo
     return System(f"cluster{n_atoms}_{ham}_{n}", ham, L, S, CL, CS, tau, atoms)
 
 
+def make_sp_basis(rng: np.random.Generator, atoms: np.ndarray, s_per_atom: int,
+                  p_shells_per_atom: int, nprim, exp_lo: float, exp_hi: float,
+                  exp_scale: float = 1.0) -> Basis:
+    """Per atom ``s_per_atom`` s functions and ``p_shells_per_atom`` p shells
+    (p_x, p_y, p_z with one shared set of exponents and coefficients), drawn
+    as in make_basis; functions are listed atom by atom."""
+    centers, nprim_l, exps, coefs, cart = [], [], [], [], []
+
+    def draw():
+        return int(rng.integers(nprim[0], nprim[1] + 1)) if isinstance(nprim, (tuple, list)) \
+            else int(nprim)
+
+    for a in atoms:
+        for _ in range(s_per_atom):
+            k = draw()
+            e = exp_scale * 10.0 ** rng.uniform(math.log10(exp_lo), math.log10(exp_hi), size=k)
+            c = rng.uniform(0.1, 1.0, size=k)
+            centers.append(a); nprim_l.append(k); exps.append(e); coefs.append(c); cart.append(0)
+        for _ in range(p_shells_per_atom):
+            k = draw()
+            e = exp_scale * 10.0 ** rng.uniform(math.log10(exp_lo), math.log10(exp_hi), size=k)
+            c = rng.uniform(0.1, 1.0, size=k)
+            for comp in (1, 2, 3):
+                centers.append(a); nprim_l.append(k); exps.append(e); coefs.append(c)
+                cart.append(comp)
+    return Basis(np.ascontiguousarray(np.array(centers, dtype=np.float64)),
+                 np.array(nprim_l, dtype=np.int32),
+                 np.ascontiguousarray(np.concatenate(exps)),
+                 np.ascontiguousarray(np.concatenate(coefs)),
+                 np.array(cart, dtype=np.int32))
+
+
+def sp_cluster(seed: int = 5, n_atoms: int = 8, edge: float = 6.0, s_per_atom: int = 1,
+               p_shells_per_atom: int = 1, ns_per_atom: int = 1, nsp_per_atom: int = 1,
+               nprim=(1, 3), n: int = 8, tau: float = 0.0, ham: str = "DC") -> System:
+    """Atoms uniform in a cube with s and p shells on every atom (L: exponents
+    10^U(-1, 1); S: the same recipe with exponents x4).  The MO coefficients
+    are a quaternion-orthonormal n-column matrix (positive-diagonal QR of a
+    Gaussian quaternion matrix) over the L and S functions together, not
+    orthonormalized in the AO metric: the transformation does not need it."""
+    ra, rb, rc, _ = _streams(seed)
+    atoms = cube(ra, n_atoms, edge)
+    L = make_sp_basis(rb, atoms, s_per_atom, p_shells_per_atom, nprim, 0.1, 10.0)
+    S = None
+    if ham != "LL":
+        S = make_sp_basis(rb, atoms, ns_per_atom, nsp_per_atom, nprim, 0.1, 10.0,
+                          exp_scale=4.0)
+    NL, NS = L.nfunc, (S.nfunc if S is not None else 0)
+    Q = quat_qr_plus(gaussian_quat(rc, NL + NS, n))
+    CL = np.ascontiguousarray(Q[:, :NL])
+    CS = np.ascontiguousarray(Q[:, NL:]) if S is not None else None
+    return System(f"sp{n_atoms}_{ham}_{n}", ham, L, S, CL, CS, tau, atoms)
+
+
 def perturbed_coefficients(system: System, k: int, eps: float = 1e-2):
     """Re-transform input k: the system's quaternion-orthonormal Q0
     (C = X Q0) is perturbed by eps * G_k (G_k Gaussian, seed 3000 + k) and
@@ -323,6 +383,8 @@ def config(name: str) -> System:
                K in 1..6, n = 128, DC + Gaunt, tau 1e-10.
     ``chain40_dcg``, ``chain40_dcb``, ``cluster60_dcb``  the same systems with
                the Gaunt term, or the whole Breit term (Gaunt + gauge).
+    ``sp8``    8 atoms in a 6 bohr cube with one s function and one p shell per
+               atom in L and in S (N_L = N_S = 32), K in 1..3, n = 8, DC.
     """
     if name == "ll24":
         return small_ll(seed=1)
@@ -336,6 +398,8 @@ def config(name: str) -> System:
         return cluster(seed=3)
     if name == "cluster60_dcb":
         return cluster(seed=3, ham="DCB")
+    if name == "sp8":
+        return sp_cluster(seed=5)
     if name == "cluster24":
         # the cluster recipe at 24 atoms (radius scaled by (24/60)^(1/3)), n = 64
         return cluster(seed=3, n_atoms=24, radius=20.0 * (24 / 60) ** (1 / 3), n=64)

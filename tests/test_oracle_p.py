@@ -1,0 +1,162 @@
+"""Pins of the oracle's p-type (Cartesian l = 1) integrals (CPU only).
+
+The oracle evaluates integrals with p functions by the Obara-Saika
+recursion.  These tests tie that recursion to facts it does not compute
+itself:
+
+* a p primitive is a derivative of an s primitive with respect to its centre,
+  (x - A_x) exp(-a|r-A|^2) = (1/(2a)) d/dA_x exp(-a|r-A|^2), so every integral
+  with a p function in one slot equals a centred finite difference of the
+  same integral with an s function there (chained slot by slot from the
+  closed-form s integral, every slot, every direction);
+* the normalized contracted p function has unit self-overlap (Gauss-Hermite
+  quadrature from numpy, not the oracle's overlap formula);
+* the Coulomb operator is invariant under rotations: a quarter turn about z
+  maps p_x to p_y and p_y to -p_x, so the MO integrals of the rotated system,
+  with the coefficient rows of the p_y functions negated, are those of the
+  original system (a wrong index or sign in the recursion breaks this);
+* the Schwarz inequality holds for the contracted p-type integrals.
+
+A dropped term of the recursion (the a_i/(2p) or c_i/(2(p+q)) terms, the
+horizontal transfer) changes the value at the first order the finite
+difference resolves.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_04316_amd import workloads as wl
+
+
+def _pe(ex, cen, cs):
+    args = []
+    for i in range(4):
+        args += [ex[i], cen[i], cs[i]]
+    return oracle.prim_eri_cart(*args)
+
+
+def test_recursion_all_s_equals_closed_form():
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        ex = rng.uniform(0.1, 5.0, 4)
+        cen = [rng.uniform(-2, 2, 3) for _ in range(4)]
+        # one-primitive normalized basis functions: the oracle's closed-form s route
+        b = wl.Basis(np.array(cen), np.ones(4, np.int32), ex.copy(), np.ones(4))
+        norm = (2 * ex / math.pi) ** 0.75
+        ref = oracle.eri_tensor(b)[0, 1, 2, 3] / norm.prod()
+        assert _pe(ex, cen, [0, 0, 0, 0]) == pytest.approx(ref, rel=1e-13, abs=0)
+
+
+@pytest.mark.parametrize("geom", ["generic", "shared_centres", "one_centre"])
+def test_p_integrals_are_centre_derivatives(geom):
+    rng = np.random.default_rng({"generic": 1, "shared_centres": 2, "one_centre": 3}[geom])
+    h = 1e-4
+    worst = 0.0
+    checked = 0
+    for trial in range(300):
+        ex = list(rng.uniform(0.2, 3.0, 4))
+        if geom == "generic":
+            cen = [rng.uniform(-1.5, 1.5, 3) for _ in range(4)]
+        elif geom == "shared_centres":
+            A, C = rng.uniform(-1.5, 1.5, 3), rng.uniform(-1.5, 1.5, 3)
+            cen = [A, A.copy(), C, C.copy()]
+        else:
+            A = rng.uniform(-1, 1, 3)
+            cen = [A.copy() for _ in range(4)]
+        cs = [int(x) for x in rng.integers(0, 4, 4)]
+        slot = int(rng.integers(0, 4))
+        if cs[slot] == 0:
+            cs[slot] = int(rng.integers(1, 4))
+        comp = cs[slot] - 1
+        lower = list(cs)
+        lower[slot] = 0
+
+        def shifted(d):
+            c2 = [x.copy() for x in cen]
+            c2[slot][comp] += d
+            return _pe(ex, c2, lower)
+
+        fd = (shifted(h) - shifted(-h)) / (2 * h) / (2 * ex[slot])
+        an = _pe(ex, cen, cs)
+        scale = max(abs(_pe(ex, cen, [0, 0, 0, 0])), abs(an))
+        worst = max(worst, abs(fd - an) / scale)
+        checked += 1
+    assert checked > 200
+    assert worst < 1e-6, worst
+
+
+def test_p_normalization_by_quadrature():
+    # numpy Gauss-Hermite nodes integrate x^2 exp(-s x^2) exactly:
+    # int x^2 e^{-s x^2} dx = s^{-3/2} sum_k w_k t_k^2 with t = sqrt(s) x
+    t, w = np.polynomial.hermite.hermgauss(20)
+    rng = np.random.default_rng(5)
+    b = wl.make_sp_basis(rng, np.zeros((1, 3)), 1, 2, (1, 4), 0.1, 10.0)
+    nc = oracle.norm_coefs(b)
+    off = b.offsets()
+    for f in range(b.nfunc):
+        e = b.exps[off[f]:off[f + 1]]
+        c = nc[off[f]:off[f + 1]]
+        tot = 0.0
+        for i in range(len(e)):
+            for j in range(len(e)):
+                s = e[i] + e[j]
+                one = (w.sum() / math.sqrt(s))            # int e^{-s y^2} dy
+                two = (w * t * t).sum() / s ** 1.5        # int y^2 e^{-s y^2} dy
+                tot += c[i] * c[j] * (two * one * one if b.cart[f] else one ** 3)
+        assert tot == pytest.approx(1.0, rel=1e-13)
+
+
+def _rotated(system):
+    """Quarter turn about z: r -> (-y, x, z).  The rotated image of p_x on A
+    is p_y on RA, of p_y is -p_x, of p_z is p_z."""
+    R = np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    newcart = np.array([0, 2, 1, 3], np.int32)
+    sign = np.array([1.0, 1.0, -1.0, 1.0])
+
+    def rot_basis(b, C):
+        b2 = wl.Basis(np.ascontiguousarray(b.centers @ R.T), b.nprim.copy(), b.exps.copy(),
+                      b.coefs.copy(), newcart[b.cart])
+        return b2, np.ascontiguousarray(C * sign[b.cart][None, :, None])
+
+    L2, CL2 = rot_basis(system.L, system.CL)
+    if system.S is None:
+        return L2, None, CL2, None
+    S2, CS2 = rot_basis(system.S, system.CS)
+    return L2, S2, CL2, CS2
+
+
+@pytest.mark.parametrize("ham", ["LL", "DC", "DCG"])
+def test_transform_invariant_under_rotation(ham):
+    sy = wl.sp_cluster(seed=7, n_atoms=3, edge=4.0, nprim=(1, 2), n=4, ham=ham)
+    G = oracle.transform_direct(sy.L, sy.S, sy.CL, sy.CS, ham=ham)[0]
+    L2, S2, CL2, CS2 = _rotated(sy)
+    G2 = oracle.transform_direct(L2, S2, CL2, CS2, ham=ham)[0]
+    scale = np.abs(G).max()
+    assert scale > 0
+    assert np.abs(G2 - G).max() <= 1e-12 * scale
+    # the p functions matter: dropping the sign flip breaks the invariance
+    bad = oracle.transform_direct(L2, S2, sy.CL, sy.CS, ham=ham)[0]
+    assert np.abs(bad - G).max() > 1e-3 * scale
+
+
+def test_schwarz_inequality_with_p():
+    sy = wl.sp_cluster(seed=8, n_atoms=2, edge=3.0, nprim=(1, 3), n=2, ham="LL")
+    I = oracle.eri_tensor(sy.L)
+    N = sy.L.nfunc
+    diag = np.array([[I[m, n, m, n] for n in range(N)] for m in range(N)])
+    assert (diag >= 0).all()
+    Q = np.sqrt(diag)
+    bound = Q[:, :, None, None] * Q[None, None, :, :]
+    assert (np.abs(I) <= bound * (1 + 1e-12) + 1e-15).all()
+    # permutational symmetry of real functions
+    assert np.allclose(I, I.transpose(1, 0, 2, 3), rtol=0, atol=1e-14 * np.abs(I).max())
+    assert np.allclose(I, I.transpose(2, 3, 0, 1), rtol=0, atol=1e-14 * np.abs(I).max())
+    np.testing.assert_allclose(oracle.schwarz(sy.L), Q, rtol=1e-13, atol=0)
+
+
+def test_gauge_hams_refuse_p_functions():
+    sy = wl.sp_cluster(seed=9, n_atoms=2, edge=3.0, nprim=(1, 1), n=2, ham="DC")
+    with pytest.raises(ValueError):
+        oracle.transform_direct(sy.L, sy.S, sy.CL, sy.CS, ham="DCB")
