@@ -105,6 +105,26 @@ void qdcb_ctx_destroy(qdcb_ctx *ctx);
 qdcb_status qdcb_basis_create(qdcb_ctx *ctx, int32_t nfunc, const double *centers,
                               const int32_t *nprim, const double *exps, const double *coefs,
                               qdcb_basis **out);
+
+/* Basis of contracted Cartesian Gaussians of s or p type (the angular
+ * momenta of the paper's basis sets, Sec. 2.5; each Cartesian component is a
+ * function of its own).  Arguments as for qdcb_basis_create, plus cart
+ * [nfunc] (host, copied): 0 = s, 1, 2, 3 = p_x, p_y, p_z, i.e.
+ * (x - A_x) exp(-a |r - A|^2) and likewise; NULL = all s (the call is then
+ * qdcb_basis_create).  coefs multiply normalized primitives
+ * (2a/pi)^{3/4} 2 sqrt(a) (x - A_x) exp(-a r^2) for p functions, and each
+ * contracted function is rescaled to unit self-overlap.  A p shell is three
+ * functions with one centre, exponent set and coefficient set.  Integrals
+ * with p functions are generated in McMurchie-Davidson form; Schwarz
+ * factors are per function pair, and primitive-pair screening is not
+ * applied to pairs with a p function.  Plans over such bases support
+ * QDCB_HAM_LL, QDCB_HAM_DC and QDCB_HAM_DCG (QDCB_HAM_DCB returns
+ * QDCB_E_UNSUPPORTED: its gauge integrals take s functions only).
+ * QDCB_E_INVALID for a code outside [0, 3]. */
+qdcb_status qdcb_basis_create_cart(qdcb_ctx *ctx, int32_t nfunc, const double *centers,
+                                   const int32_t *nprim, const double *exps,
+                                   const double *coefs, const int32_t *cart,
+                                   qdcb_basis **out);
 void qdcb_basis_destroy(qdcb_basis *basis);
 
 /* Schwarz factors of the basis's own function pairs: Q[mu][nu] (host,

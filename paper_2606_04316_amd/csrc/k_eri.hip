@@ -28,6 +28,12 @@
 // B_KL = ((mn| r_K r_L / r^3 |kl) - delta_KL (mn|kl)) / 2 for (K, L) = xx, xy,
 // xz, yy, yz, zz, from F0, F1 and F2 of one Taylor table (see gauge_kernel_tab).
 //
+// Cartesian tiles (bases with p functions, k_eri_tiles_cart*): the same
+// layout and masks; each primitive quartet is evaluated in McMurchie-Davidson
+// form (Hermite expansion of each pair, derivatives of the Boys kernel up to
+// fourth order, common.h) with F_0 .. F_4 from one Taylor table; bra
+// primitives are read from global memory (no LDS staging).
+//
 // Schedules: one workgroup per tile in list order (k_eri_tiles), or a
 // persistent grid of a few workgroups per compute unit that pull tiles from a
 // device queue ordered by decreasing primitive-quartet count
@@ -350,16 +356,170 @@ __global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles_queue(EriTileArgs a,
   eri_count(a, kept);
 }
 
+// ---- Cartesian (s/p) tiles
+
+// g_n = (2/sqrt(pi)) sqrt(rho) F_n(T), n = 0..4: near field from the table
+// tab[BOYS_LDC i + k] = (2/sqrt(pi)) F_k(T_i) by the Taylor series
+// F_m(T_i + d) = sum_k F_{m+k}(T_i) (-d)^k / k! (k <= 7, nested); far field
+// (T >= 36) from 1/R and the upward recursion.
+__device__ __forceinline__ void boys_g_tab(const double *tab, double T, double r2, double sr,
+                                           double g[5]) {
+  if (T < BOYS_TMAX) {
+    const int i = (int)fma(T, 8.0, 0.5);
+    const double nd = fma(0.125, (double)i, -T);
+    const double *c = tab + BOYS_LDC * i;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) g[m] = c[m + 7];
+#pragma unroll
+    for (int k = 7; k >= 1; --k) {
+      const double h = nd * (1.0 / k);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) g[m] = fma(g[m], h, c[m + k - 1]);
+    }
+#pragma unroll
+    for (int m = 0; m < 5; ++m) g[m] *= sr;
+  } else {
+    g[0] = rsqrt(r2);
+    const double e = TWO_OVER_SQRTPI * sr * exp(-T);
+    const double h = 0.5 / T;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) g[m + 1] = fma(2.0 * m + 1.0, g[m], -e) * h;
+  }
+}
+
+__device__ __forceinline__ double cart_quartet_tab(const double *tab, double ip, double px,
+                                                   double py, double pz, double pa, double pb,
+                                                   int cb, double iq, double qx, double qy,
+                                                   double qz, double qa, double qb, int ck) {
+  const double sr = rsqrt_pos(ip + iq);
+  const double rho = sr * sr;
+  const double X[3] = {px - qx, py - qy, pz - qz};
+  const double r2 = X[0] * X[0] + X[1] * X[1] + X[2] * X[2];
+  const double T = r2 * rho;
+  double g[5];
+  boys_g_tab(tab, T, r2, sr, g);
+  double G[5];
+  double f = 1.0;
+#pragma unroll
+  for (int n = 0; n < 5; ++n) {
+    G[n] = f * g[n];
+    f *= -2.0 * rho;
+  }
+  double hb[4], hk[4];
+  int a, b, c, d;
+  herm_side(cb, pa, pb, 0.5 * ip, hb, a, b);
+  herm_side(ck, qa, qb, 0.5 * iq, hk, c, d);
+  return herm_contract(hb, a, b, hk, c, d, X, G);
+}
+
+__device__ __forceinline__ void eri_cart_tile_body(const EriTileArgs &a, const double *tab,
+                                                   int kt, int bt, int lane, int w, double *out,
+                                                   double *outT, long long kept[4]) {
+  const int64_t brow = (int64_t)bt * TILE + lane;
+  const double qb = a.Q[brow];
+  const double db = a.Dmax[brow];
+  const int cb = a.cls[brow];
+  const int bcode = a.code[brow];
+  const int64_t bfirst = a.row_first[brow];
+  const int64_t blast = a.row_first[brow + 1];
+  for (int i = 0; i < TILE / ERI_WAVES; ++i) {
+    const int j = w + ERI_WAVES * i;
+    const int64_t krow = (int64_t)kt * TILE + j;
+    const double qk = a.Q[krow], dk = a.Dmax[krow];
+    const int ck = a.cls[krow];
+    const int kcode = a.code[krow];
+    const int64_t kf0 = a.row_first[krow], kf1 = a.row_first[krow + 1];
+    double v = 0.0;
+    const bool keep_bk = out && (qb * qk) * dk >= a.tau;
+    const bool keep_kb = outT && (qk * qb) * db >= a.tau;
+    if (keep_bk || keep_kb) {
+      for (int64_t k = kf0; k < kf1; ++k) {
+        const double iq = a.pp.ip[k], qx = a.pp.x[k], qy = a.pp.y[k], qz = a.pp.z[k];
+        const double qa = a.pp.pa[k], qbb = a.pp.pb[k], ek = a.pp.e[k];
+        double s = 0.0;
+        for (int64_t b = bfirst; b < blast; ++b)
+          s += a.pp.e[b] * cart_quartet_tab(tab, a.pp.ip[b], a.pp.x[b], a.pp.y[b], a.pp.z[b],
+                                            a.pp.pa[b], a.pp.pb[b], bcode, iq, qx, qy, qz, qa,
+                                            qbb, kcode);
+        v = fma(ek, s, v);
+      }
+      if (cb >= 0 && ck >= 0) {
+        if (keep_bk) kept[cb * 2 + ck] += 1;
+        if (keep_kb) kept[ck * 2 + cb] += 1;
+      }
+    }
+    if (out) out[j * TILE + lane] = keep_bk ? v : 0.0;
+    if (outT) outT[lane * TILE + j] = keep_kb ? v : 0.0;
+  }
+}
+
+__device__ __forceinline__ void eri_cart_one_tile(const EriTileArgs &a, const double *tab,
+                                                  int64_t slot, long long kept[4]) {
+  const int kt = a.tasks[slot];
+  const int bt = a.task_bra[slot];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double *out, *outT = nullptr;
+  if (a.uslot_bk) {
+    const int32_t s1 = a.uslot_bk[slot], s2 = a.uslot_kb[slot];
+    out = s1 >= 0 ? a.panel + (int64_t)s1 * TILE * TILE : nullptr;
+    outT = s2 >= 0 ? a.panel + (int64_t)s2 * TILE * TILE : nullptr;
+  } else {
+    out = a.panel + (slot - a.slot0) * TILE * TILE;
+  }
+  eri_cart_tile_body(a, tab, kt, bt, lane, w, out, outT, kept);
+}
+
+__global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles_cart(EriTileArgs a) {
+  __shared__ double tab[BOYS_N * BOYS_LDC];
+  if (a.overflow && *a.overflow) return;  // uniform
+  if (a.d_total && (int64_t)blockIdx.x >= min(*a.d_total, a.cap)) return;  // uniform
+  for (int t = threadIdx.x; t < BOYS_N * BOYS_LDC; t += ERI_THREADS) tab[t] = a.boysc[t];
+  __syncthreads();
+  long long kept[4] = {0, 0, 0, 0};
+  eri_cart_one_tile(a, tab, a.slot0 + blockIdx.x, kept);
+  eri_count(a, kept);
+}
+
+// Persistent variant; same queue protocol as k_eri_tiles_queue.
+__global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles_queue_cart(EriTileArgs a,
+                                                                      const int32_t *order,
+                                                                      unsigned long long *qctr,
+                                                                      int64_t n_host) {
+  __shared__ double tab[BOYS_N * BOYS_LDC];
+  __shared__ int64_t s_next;
+  if (a.overflow && *a.overflow) return;  // uniform
+  const int64_t n = a.d_total ? min(*a.d_total, a.cap) : n_host;
+  for (int t = threadIdx.x; t < BOYS_N * BOYS_LDC; t += ERI_THREADS) tab[t] = a.boysc[t];
+  long long kept[4] = {0, 0, 0, 0};
+  for (;;) {
+    __syncthreads();  // table staged; the previous s_next read by every thread
+    if (threadIdx.x == 0) s_next = (int64_t)atomicAdd(qctr, 1ull);
+    __syncthreads();
+    const int64_t i = s_next;
+    if (i >= n) break;  // uniform
+    eri_cart_one_tile(a, tab, order[i], kept);
+  }
+  eri_count(a, kept);
+}
+
 void launch_eri_tiles(const EriTileArgs &a, int64_t nslots, hipStream_t s) {
   if (nslots <= 0) return;
-  hipLaunchKernelGGL(k_eri_tiles<false>, dim3((unsigned)nslots), dim3(ERI_THREADS), 0, s, a);
+  if (a.code)
+    hipLaunchKernelGGL(k_eri_tiles_cart, dim3((unsigned)nslots), dim3(ERI_THREADS), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_eri_tiles<false>, dim3((unsigned)nslots), dim3(ERI_THREADS), 0, s, a);
 }
 
 void launch_eri_tiles_queue(const EriTileArgs &a, const int32_t *order, unsigned long long *qctr,
                             int64_t n_host, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return;
-  hipLaunchKernelGGL(k_eri_tiles_queue<false>, dim3((unsigned)nblocks), dim3(ERI_THREADS), 0, s,
-                     a, order, qctr, n_host);
+  if (a.code)
+    hipLaunchKernelGGL(k_eri_tiles_queue_cart, dim3((unsigned)nblocks), dim3(ERI_THREADS), 0, s,
+                       a, order, qctr, n_host);
+  else
+    hipLaunchKernelGGL(k_eri_tiles_queue<false>, dim3((unsigned)nblocks), dim3(ERI_THREADS), 0,
+                       s, a, order, qctr, n_host);
 }
 
 void launch_eri_gauge_tiles(const EriTileArgs &a, int64_t nslots, hipStream_t s) {

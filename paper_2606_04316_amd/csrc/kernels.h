@@ -9,31 +9,36 @@
 namespace qdcb {
 
 // ---- basis: normalization, primitive pairs, Schwarz factors (k_basis.hip)
+// cart: per function 0 = s, 1..3 = p_x, p_y, p_z (NULL: all s).
 void launch_norm_coefs(int nfunc, const int32_t *prim_first, const double *exps,
-                       const double *coefs, double *nc, hipStream_t s);
-// Primitive-pair data of pairs (mu[i] in A, nu[i] in B), written at pair_first[i].
+                       const double *coefs, const int32_t *cart, double *nc, hipStream_t s);
+// Primitive-pair data of pairs (mu[i] in A, nu[i] in B), written at pair_first[i]
+// (out.pa / out.pb too when set; cartA, cartB as for launch_norm_coefs).
 void launch_pair_data(int64_t npairs, const int32_t *mu, const int32_t *nu,
                       const int64_t *pair_first, const double *centA, const int32_t *firstA,
-                      const double *expA, const double *ncA, const double *centB,
-                      const int32_t *firstB, const double *expB, const double *ncB,
-                      PrimPairs out, hipStream_t s);
+                      const double *expA, const double *ncA, const int32_t *cartA,
+                      const double *centB, const int32_t *firstB, const double *expB,
+                      const double *ncB, const int32_t *cartB, PrimPairs out, hipStream_t s);
 // Q[i] = sqrt((i|i)) over the primitive pairs [pair_first[i], pair_first[i+1]).
-void launch_schwarz(int64_t npairs, const int64_t *pair_first, PrimPairsC pp, double *Q,
-                    hipStream_t s);
+// code: per pair cf | (cg << 2) for bases with p functions, else NULL.
+void launch_schwarz(int64_t npairs, const int64_t *pair_first, PrimPairsC pp,
+                    const int32_t *code, double *Q, hipStream_t s);
 // Primitive-pair screening: kept[r] = number of the cnt[r] primitive pairs of
 // row r (starting at src_first[r]) whose Schwarz weight exceeds eps times the
-// row's mean weight.
+// row's mean weight; rows with code[r] != 0 (a p function) keep all.
 void launch_prim_count(int64_t nrows, const int64_t *src_first, const int32_t *cnt,
-                       PrimPairsC src, double eps, int32_t *kept, hipStream_t s);
+                       const int32_t *code, PrimPairsC src, double eps, int32_t *kept,
+                       hipStream_t s);
 // Gather pair rows into a new order: row r takes its kept primitive pairs
 // (same criterion) from src_first[r] and stores them from dst_first[r] on.
 void launch_gather_pairs(int64_t nrows, const int64_t *src_first, const int32_t *cnt,
-                         const int64_t *dst_first, PrimPairsC src, PrimPairs dst, double eps,
-                         hipStream_t s);
-// ERIs of explicit quartets (test entry point): out[q] = (pair a[q] | pair b[q]).
+                         const int32_t *code, const int64_t *dst_first, PrimPairsC src,
+                         PrimPairs dst, double eps, hipStream_t s);
+// ERIs of explicit quartets (test entry point): out[q] = (pair a[q] | pair b[q]);
+// codes[2q], codes[2q+1]: the two pair codes (NULL for s-only bases).
 void launch_eri_list(int64_t nq, const int64_t *a_first, const int64_t *b_first,
-                     const int32_t *a_cnt, const int32_t *b_cnt, PrimPairsC A,
-                     PrimPairsC B, double *out, hipStream_t s);
+                     const int32_t *a_cnt, const int32_t *b_cnt, const int32_t *codes,
+                     PrimPairsC A, PrimPairsC B, double *out, hipStream_t s);
 
 // ---- densities (k_density.hip)
 struct DensityArgs {
@@ -118,6 +123,11 @@ struct EriTileArgs {
   // are counted
   const int32_t *uslot_bk = nullptr, *uslot_kb = nullptr;
   const double *boys = nullptr;  // [BOYS_N][8] Taylor table of F0 (see common.h)
+  // bases with p functions: per sorted row its pair code (see common.h), and
+  // the table [BOYS_N][BOYS_LDC] of (2/sqrt(pi)) F_k(T_i), k < BOYS_LDC; the
+  // integral launches then run the Cartesian tile kernels
+  const int32_t *code = nullptr;
+  const double *boysc = nullptr;
   const int32_t *tasks;       // [slots] ket tile per slot
   const int32_t *task_bra;    // [slots] bra tile per slot
   int64_t slot0;              // slot index of the panel buffer's first entry

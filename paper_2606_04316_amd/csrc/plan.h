@@ -20,6 +20,7 @@ struct Space {
   DBuf<int64_t> row_first;
   DBuf<double> Q;
   PairStore pp;
+  DBuf<int32_t> code;  // per row: pair code of bases with p functions (else empty)
   int nK = 1;
   // row layout of D~ and V for the current column chunk: nK blocks of ldK
   // columns (ld = nK ldK), packed to the chunk's width; ld_cap = the allocation
@@ -57,6 +58,7 @@ struct Space {
 
   size_t bytes() const {
     return cls.bytes() + mu.bytes() + nu.bytes() + row_first.bytes() + Q.bytes() + pp.bytes() +
+           code.bytes() +
            D.bytes() + V.bytes() + Dmax.bytes() + Qmax.bytes() + Bmax.bytes() + Dtmax.bytes() +
            ttasks.bytes() + trank.bytes() + tcount.bytes() + toff.bytes() + count.bytes() +
            tasks.bytes() + task_bra.bytes() + slot_base.bytes() + panel.bytes() + panel3.bytes() + kept.bytes() +
@@ -116,6 +118,8 @@ struct qdcb_plan {
   std::atomic<int> busy{0};      // a call is using the plan
   qdcb::DBuf<double> boys;   // Taylor table of the Boys function F0
   qdcb::DBuf<double> boys3;  // F0 .. F9 on the same grid (gauge tiles)
+  bool cart = false;         // a basis has p functions: Cartesian integral tiles
+  qdcb::DBuf<double> boysc;  // F0 .. F11 on the same grid (Cartesian tiles)
   bool have_last = false;
   int64_t tiles_made = 0;  // integral tiles generated by the last eager transform
   int v_i0 = 0, v_i1 = 0;  // MO pairs whose first-half columns V holds (last chunk)

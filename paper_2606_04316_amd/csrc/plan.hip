@@ -23,6 +23,7 @@ struct RowSrc {
   int32_t cnt;
   int which;        // which source store
   int32_t kept = 0;  // primitive pairs kept by primitive screening
+  int32_t code = 0;  // pair code cf | (cg << 2) of bases with p functions (0: s s)
 };
 
 // Rows ordered by Schwarz factor; band_rows > 0: within each band of that many
@@ -33,21 +34,23 @@ void build_space(qdcb_ctx *ctx, Space &sp, std::vector<RowSrc> &rows,
   // primitive pairs kept per row (rows in their input order)
   for (size_t w = 0; w < stores.size(); ++w) {
     std::vector<int64_t> idx, first;
-    std::vector<int32_t> cnt;
+    std::vector<int32_t> cnt, code;
     for (size_t i = 0; i < rows.size(); ++i)
       if (rows[i].which == (int)w) {
         idx.push_back((int64_t)i);
         first.push_back(rows[i].src_first);
         cnt.push_back(rows[i].cnt);
+        code.push_back(rows[i].code);
       }
     if (idx.empty()) continue;
     DBuf<int64_t> dfirst;
-    DBuf<int32_t> dcnt, dk;
+    DBuf<int32_t> dcnt, dk, dcode;
     dfirst.upload(ctx, first);
     dcnt.upload(ctx, cnt);
+    dcode.upload(ctx, code);
     dk.alloc(ctx, idx.size());
-    launch_prim_count((int64_t)idx.size(), dfirst.p, dcnt.p, stores[w]->cview(), PRIM_EPS, dk.p,
-                      nullptr);
+    launch_prim_count((int64_t)idx.size(), dfirst.p, dcnt.p, dcode.p, stores[w]->cview(),
+                      PRIM_EPS, dk.p, nullptr);
     HIPC(hipGetLastError());
     std::vector<int32_t> k(idx.size());
     HIPC(hipMemcpy(k.data(), dk.p, k.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -70,9 +73,11 @@ void build_space(qdcb_ctx *ctx, Space &sp, std::vector<RowSrc> &rows,
   sp.h_nu.assign(sp.Ppad, 0);
   sp.h_key.assign(sp.Ppad, -1);
   std::vector<double> hQ(sp.Ppad, 0.0);
+  std::vector<int32_t> hcode(sp.Ppad, 0);
   const size_t ns = stores.size();
   std::vector<std::vector<int64_t>> src(ns), dst(ns), rowidx(ns);
-  std::vector<std::vector<int32_t>> cnt(ns);
+  std::vector<std::vector<int32_t>> cnt(ns), scode(ns);
+  bool cart = false;
   for (int64_t r = 0; r < sp.P; ++r) {
     const RowSrc &s = rows[r];
     sp.h_cls[r] = s.cls;
@@ -80,19 +85,25 @@ void build_space(qdcb_ctx *ctx, Space &sp, std::vector<RowSrc> &rows,
     sp.h_nu[r] = s.nu;
     sp.h_key[r] = s.key;
     hQ[r] = s.Q;
+    hcode[r] = s.code;
+    cart = cart || s.code != 0;
     src[s.which].push_back(s.src_first);
     cnt[s.which].push_back(s.cnt);
+    scode[s.which].push_back(s.code);
     rowidx[s.which].push_back(r);
   }
+  for (const PairStore *st : stores) cart = cart || st->pa.p;
+  if (cart) sp.code.upload(ctx, hcode);
   // primitive pairs kept per row after primitive screening
   std::vector<DBuf<int64_t>> dsrc(ns);
-  std::vector<DBuf<int32_t>> dcnt(ns);
+  std::vector<DBuf<int32_t>> dcnt(ns), dscode(ns);
   std::vector<int32_t> kept_prims(sp.Ppad, 0);
   for (int64_t r = 0; r < sp.P; ++r) kept_prims[r] = rows[r].kept;
   for (size_t w = 0; w < ns; ++w) {
     if (src[w].empty()) continue;
     dsrc[w].upload(ctx, src[w]);
     dcnt[w].upload(ctx, cnt[w]);
+    dscode[w].upload(ctx, scode[w]);
   }
   std::vector<int64_t> rf(sp.Ppad + 1, 0);
   for (int64_t r = 0; r < sp.Ppad; ++r) rf[r + 1] = rf[r] + kept_prims[r];
@@ -103,13 +114,13 @@ void build_space(qdcb_ctx *ctx, Space &sp, std::vector<RowSrc> &rows,
   sp.nu.upload(ctx, sp.h_nu);
   sp.Q.upload(ctx, hQ);
   sp.row_first.upload(ctx, rf);
-  sp.pp.alloc(ctx, (size_t)std::max<int64_t>(rf[sp.Ppad], 1));
+  sp.pp.alloc(ctx, (size_t)std::max<int64_t>(rf[sp.Ppad], 1), cart);
   for (size_t w = 0; w < ns; ++w) {
     if (src[w].empty()) continue;
     DBuf<int64_t> dd;
     dd.upload(ctx, dst[w]);
-    launch_gather_pairs((int64_t)src[w].size(), dsrc[w].p, dcnt[w].p, dd.p, stores[w]->cview(),
-                        sp.pp.view(), PRIM_EPS, nullptr);
+    launch_gather_pairs((int64_t)src[w].size(), dsrc[w].p, dcnt[w].p, dscode[w].p, dd.p,
+                        stores[w]->cview(), sp.pp.view(), PRIM_EPS, nullptr);
     HIPC(hipGetLastError());
     HIPC(hipDeviceSynchronize());
   }
@@ -168,6 +179,29 @@ std::vector<double> boys_table3() {
     F[9] = eT * sum;
     for (int m = 9; m >= 1; --m) F[m - 1] = (2.0L * T * F[m] + eT) / (2.0L * m - 1.0L);
     for (int k = 0; k < 10; ++k) tab[(size_t)BOYS_LD * i + k] = (double)(two_over_sqrtpi * F[k]);
+  }
+  return tab;
+}
+
+// Table of the Cartesian (s/p) tiles: tab[BOYS_LDC i + k] = (2/sqrt(pi)) F_k(T_i),
+// k = 0 .. 11, T_i = i / 8, by the same series and downward recursion (long double).
+std::vector<double> boys_table_cart() {
+  std::vector<double> tab((size_t)BOYS_N * BOYS_LDC);
+  const long double two_over_sqrtpi = 2.0L / sqrtl(3.14159265358979323846264338327950288L);
+  constexpr int M = BOYS_LDC - 1;
+  for (int i = 0; i < BOYS_N; ++i) {
+    const long double T = (long double)i / 8.0L, eT = expl(-T);
+    long double term = 1.0L / (2.0L * M + 1.0L), sum = term;
+    for (int j = 1; j < 400; ++j) {
+      term *= 2.0L * T / (2.0L * M + 1.0L + 2.0L * j);
+      sum += term;
+      if (term < 1e-22L * sum) break;
+    }
+    long double F[BOYS_LDC];
+    F[M] = eT * sum;
+    for (int m = M; m >= 1; --m) F[m - 1] = (2.0L * T * F[m] + eT) / (2.0L * m - 1.0L);
+    for (int k = 0; k < BOYS_LDC; ++k)
+      tab[(size_t)BOYS_LDC * i + k] = (double)(two_over_sqrtpi * F[k]);
   }
   return tab;
 }
@@ -347,6 +381,9 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
     p.gaunt = desc->ham == QDCB_HAM_DCG || desc->ham == QDCB_HAM_DCB;
     p.gauge = desc->ham == QDCB_HAM_DCB;
     p.fused_breit = p.gauge && desc->prec == QDCB_PREC_FP64;
+    p.cart = L->has_p() || (S && S->has_p());
+    if (p.cart && p.gauge)
+      fail(QDCB_E_UNSUPPORTED, "the gauge term takes s functions only");
     p.spinor = desc->flags & QDCB_PLAN_SPINOR;
     if (p.spinor) {  // pairs of spinors c <= d, two pairs per four-column group
       p.npair_s = p.n * (p.n + 1) / 2;
@@ -365,8 +402,10 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
         for (int nu = 0; nu < B->nfunc; ++nu)
           for (int mu = 0; mu <= nu; ++mu) {
             int64_t c = qdcb_basis::canon(mu, nu);
-            rows.push_back(RowSrc{B->Q[c], cls, mu, nu, c, B->pair_first[c],
-                                  (int32_t)(B->pair_first[c + 1] - B->pair_first[c]), which});
+            RowSrc r{B->Q[c], cls, mu, nu, c, B->pair_first[c],
+                     (int32_t)(B->pair_first[c + 1] - B->pair_first[c]), which};
+            r.code = B->cart_of(mu) | (B->cart_of(nu) << 2);
+            rows.push_back(r);
           }
       };
       add(L, 0, 0);
@@ -398,17 +437,25 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
       dm.upload(ctx, pm);
       dn.upload(ctx, pn);
       dpf.upload(ctx, pf);
-      ls.alloc(ctx, (size_t)pf[nls]);
+      ls.alloc(ctx, (size_t)pf[nls], p.cart);
       launch_pair_data(nls, dm.p, dn.p, dpf.p, L->cent.p, L->dfirst.p, L->exps.p, L->nc.p,
-                       S->cent.p, S->dfirst.p, S->exps.p, S->nc.p, ls.view(), nullptr);
+                       L->dcart.p, S->cent.p, S->dfirst.p, S->exps.p, S->nc.p, S->dcart.p,
+                       ls.view(), nullptr);
+      std::vector<int32_t> lcode(p.cart ? nls : 0);
+      for (int64_t i = 0; p.cart && i < nls; ++i)
+        lcode[i] = L->cart_of(pm[i]) | (S->cart_of(pn[i]) << 2);
+      DBuf<int32_t> dlcode;
+      if (p.cart) dlcode.upload(ctx, lcode);
       dQ.alloc(ctx, nls);
-      launch_schwarz(nls, dpf.p, ls.cview(), dQ.p, nullptr);
+      launch_schwarz(nls, dpf.p, ls.cview(), dlcode.p, dQ.p, nullptr);
       HIPC(hipGetLastError());
       std::vector<double> hQ(nls);
       HIPC(hipMemcpy(hQ.data(), dQ.p, nls * sizeof(double), hipMemcpyDeviceToHost));
       std::vector<RowSrc> rows(nls);
-      for (int64_t i = 0; i < nls; ++i)
+      for (int64_t i = 0; i < nls; ++i) {
         rows[i] = RowSrc{hQ[i], 0, pm[i], pn[i], i, pf[i], (int32_t)(pf[i + 1] - pf[i]), 0};
+        rows[i].code = p.cart ? lcode[i] : 0;
+      }
       p.G.gaunt = 1;
       p.G.nK = 3;
       build_space(ctx, p.G, rows, {&ls}, bands);
@@ -491,15 +538,16 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
       char key[256];
       std::snprintf(key, sizeof key,
                     "v1 ham=%d prec=%d fl=%d n=%d NL=%d NS=%d kL=%d kS=%d tau=%.3e tC=%d "
-                    "tG=%d cu=%d",
+                    "tG=%d cu=%d%s",
                     (int)desc->ham, (int)desc->prec, (int)desc->flags, p.n, p.NL, p.NS, kL, kS,
                     desc->tau,
-                    p.C.ntiles, p.gaunt ? p.G.ntiles : 0, p.n_cu);
+                    p.C.ntiles, p.gaunt ? p.G.ntiles : 0, p.n_cu, p.cart ? " p=1" : "");
       p.tune_key = key;
     }
     size_plan(p, 0, 0);
     p.boys.upload(ctx, boys_table());
     if (p.gauge) p.boys3.upload(ctx, boys_table3());
+    if (p.cart) p.boysc.upload(ctx, boys_table_cart());
     HIPC(hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking));
     ctx->retain();
     *out = pl.release();
@@ -538,7 +586,10 @@ qdcb_status qdcb_plan_estimate(const qdcb_basis *L, const qdcb_basis *S,
     const double ntC = PC / TILE, ntG = PG / TILE;
     double prims = (double)L->pair_first.back() + (S ? (double)S->pair_first.back() : 0.0);
     if (gaunt) prims += 2.0 * (double)L->first.back() * (double)S->first.back();
-    double b = 40.0 * prims;                              // primitive-pair data
+    const bool cart = L->has_p() || (S && S->has_p());
+    if (cart && desc->ham == QDCB_HAM_DCB)
+      fail(QDCB_E_UNSUPPORTED, "the gauge term takes s functions only");
+    double b = (cart ? 56.0 : 40.0) * prims;              // primitive-pair data
     b += 48.0 * (PC + PG);                                // row metadata
     b += 16.0 * (PC * ldK + 3.0 * PG * ldK);              // D~ and V, all columns
     b += 22.0 * (ntC * ntC + ntG * ntG);                  // task lists, unique pairs, slot map
@@ -557,7 +608,7 @@ qdcb_status qdcb_plan_footprint(const qdcb_plan *p, size_t *bytes) {
     if (!p || !bytes) fail(QDCB_E_INVALID, "NULL argument");
     size_t b = p->C.bytes() + p->G.bytes();
     for (auto *x : {&p->CLd, &p->CSd, &p->Gd, &p->CallL, &p->CallS, &p->ChatL, &p->ChatS, &p->boys,
-                    &p->boys3, &p->W, &p->Gc})
+                    &p->boys3, &p->boysc, &p->W, &p->Gc})
       b += x->bytes();
     for (int K = 0; K < 3; ++K) b += p->AhatK[K].bytes() + p->BhatK[K].bytes();
     b += p->rs.bytes() + p->rowmapL.bytes() + p->rowmapS.bytes() + p->rowmapLS.bytes();

@@ -131,23 +131,33 @@ struct DBuf {
 
 struct PairStore {
   DBuf<double> p, x, y, z, e;
-  void alloc(qdcb_ctx *c, size_t n) {
+  DBuf<double> pa, pb;  // bases with p functions only (see PrimPairs)
+  void alloc(qdcb_ctx *c, size_t n, bool cart = false) {
     p.alloc(c, n);
     x.alloc(c, n);
     y.alloc(c, n);
     z.alloc(c, n);
     e.alloc(c, n);
+    if (cart) {
+      pa.alloc(c, n);
+      pb.alloc(c, n);
+    } else {
+      pa.free();
+      pb.free();
+    }
   }
-  PrimPairs view() { return PrimPairs{p.p, x.p, y.p, z.p, e.p}; }
-  PrimPairsC cview() const { return PrimPairsC(PrimPairs{p.p, x.p, y.p, z.p, e.p}); }
+  PrimPairs view() { return PrimPairs{p.p, x.p, y.p, z.p, e.p, pa.p, pb.p}; }
+  PrimPairsC cview() const { return PrimPairsC(PrimPairs{p.p, x.p, y.p, z.p, e.p, pa.p, pb.p}); }
   void free() {
     p.free();
     x.free();
     y.free();
     z.free();
     e.free();
+    pa.free();
+    pb.free();
   }
-  size_t bytes() const { return p.bytes() * 5; }
+  size_t bytes() const { return p.bytes() * 5 + pa.bytes() + pb.bytes(); }
 };
 
 }  // namespace qdcb
@@ -159,9 +169,12 @@ struct qdcb_basis {
   std::vector<int32_t> nprim;       // [nfunc]
   std::vector<int64_t> pair_first;  // canonical pairs (mu <= nu, nu-major) [npairs+1]
   std::vector<double> Q;            // host copy of the Schwarz factors
+  std::vector<int32_t> cart;        // [nfunc] 0 = s, 1..3 = p_x, p_y, p_z (empty: all s)
   int64_t npairs = 0;
+  bool has_p() const { return !cart.empty(); }
+  int32_t cart_of(int f) const { return cart.empty() ? 0 : cart[f]; }
   qdcb::DBuf<double> cent, exps, coefs, nc;
-  qdcb::DBuf<int32_t> dfirst;
+  qdcb::DBuf<int32_t> dfirst, dcart;
   qdcb::DBuf<int64_t> dpair_first;
   qdcb::PairStore pp;
   qdcb::DBuf<double> dQ;

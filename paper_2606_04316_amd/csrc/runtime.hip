@@ -38,6 +38,13 @@ void qdcb_ctx_destroy(qdcb_ctx *ctx) { qdcb_ctx::release_ref(ctx); }
 qdcb_status qdcb_basis_create(qdcb_ctx *ctx, int32_t nfunc, const double *centers,
                               const int32_t *nprim, const double *exps, const double *coefs,
                               qdcb_basis **out) {
+  return qdcb_basis_create_cart(ctx, nfunc, centers, nprim, exps, coefs, nullptr, out);
+}
+
+qdcb_status qdcb_basis_create_cart(qdcb_ctx *ctx, int32_t nfunc, const double *centers,
+                                   const int32_t *nprim, const double *exps,
+                                   const double *coefs, const int32_t *cart,
+                                   qdcb_basis **out) {
   return guarded([&] {
     if (!ctx || !out || !centers || !nprim || !exps || !coefs)
       fail(QDCB_E_INVALID, "NULL argument");
@@ -53,19 +60,28 @@ qdcb_status qdcb_basis_create(qdcb_ctx *ctx, int32_t nfunc, const double *center
       if (!std::isfinite(exps[i]) || !(exps[i] > 0)) fail(QDCB_E_INVALID, "exponent <= 0");
       if (!std::isfinite(coefs[i])) fail(QDCB_E_INVALID, "non-finite coefficient");
     }
+    bool any_p = false;
+    for (int f = 0; cart && f < nfunc; ++f) {
+      if (cart[f] < 0 || cart[f] > 3) fail(QDCB_E_INVALID, "cart codes must be in [0, 3]");
+      any_p = any_p || cart[f] != 0;
+    }
     DeviceGuard g(ctx->device);
     std::unique_ptr<qdcb_basis> b(new qdcb_basis());
     b->ctx = ctx;
     b->nfunc = nfunc;
     b->first = first;
     b->nprim.assign(nprim, nprim + nfunc);
+    if (any_p) {
+      b->cart.assign(cart, cart + nfunc);
+      b->dcart.upload(ctx, b->cart);
+    }
     int np = first[nfunc];
     b->cent.upload(ctx, std::vector<double>(centers, centers + 3 * nfunc));
     b->exps.upload(ctx, std::vector<double>(exps, exps + np));
     b->coefs.upload(ctx, std::vector<double>(coefs, coefs + np));
     b->dfirst.upload(ctx, first);
     b->nc.alloc(ctx, np);
-    launch_norm_coefs(nfunc, b->dfirst.p, b->exps.p, b->coefs.p, b->nc.p, nullptr);
+    launch_norm_coefs(nfunc, b->dfirst.p, b->exps.p, b->coefs.p, b->dcart.p, b->nc.p, nullptr);
     HIPC(hipGetLastError());
     // canonical pairs mu <= nu, index nu(nu+1)/2 + mu
     int64_t npairs = (int64_t)nfunc * (nfunc + 1) / 2;
@@ -85,12 +101,19 @@ qdcb_status qdcb_basis_create(qdcb_ctx *ctx, int32_t nfunc, const double *center
     dm.upload(ctx, pm);
     dn.upload(ctx, pn);
     b->dpair_first.upload(ctx, pf);
-    b->pp.alloc(ctx, (size_t)pf[npairs]);
+    b->pp.alloc(ctx, (size_t)pf[npairs], any_p);
     launch_pair_data(npairs, dm.p, dn.p, b->dpair_first.p, b->cent.p, b->dfirst.p, b->exps.p,
-                     b->nc.p, b->cent.p, b->dfirst.p, b->exps.p, b->nc.p, b->pp.view(), nullptr);
+                     b->nc.p, b->dcart.p, b->cent.p, b->dfirst.p, b->exps.p, b->nc.p,
+                     b->dcart.p, b->pp.view(), nullptr);
     HIPC(hipGetLastError());
+    DBuf<int32_t> dcode;
+    if (any_p) {
+      std::vector<int32_t> code(npairs);
+      for (int64_t i = 0; i < npairs; ++i) code[i] = b->cart[pm[i]] | (b->cart[pn[i]] << 2);
+      dcode.upload(ctx, code);
+    }
     b->dQ.alloc(ctx, npairs);
-    launch_schwarz(npairs, b->dpair_first.p, b->pp.cview(), b->dQ.p, nullptr);
+    launch_schwarz(npairs, b->dpair_first.p, b->pp.cview(), dcode.p, b->dQ.p, nullptr);
     HIPC(hipGetLastError());
     b->Q.resize(npairs);
     HIPC(hipMemcpy(b->Q.data(), b->dQ.p, npairs * sizeof(double), hipMemcpyDeviceToHost));
@@ -127,6 +150,8 @@ qdcb_status qdcb_eri_quartets(const qdcb_basis *A, const qdcb_basis *B, int64_t 
     if (nq <= 0) return;
     std::vector<int64_t> af(nq), bf(nq);
     std::vector<int32_t> ac(nq), bc(nq);
+    const bool cart = A->has_p() || B->has_p();
+    std::vector<int32_t> codes(cart ? 2 * nq : 0);
     for (int64_t q = 0; q < nq; ++q) {
       const int32_t *i4 = idx + 4 * q;
       if (i4[0] < 0 || i4[1] < 0 || i4[0] >= A->nfunc || i4[1] >= A->nfunc || i4[2] < 0 ||
@@ -137,6 +162,13 @@ qdcb_status qdcb_eri_quartets(const qdcb_basis *A, const qdcb_basis *B, int64_t 
       ac[q] = (int32_t)(A->pair_first[pa + 1] - af[q]);
       bf[q] = B->pair_first[pb];
       bc[q] = (int32_t)(B->pair_first[pb + 1] - bf[q]);
+      if (cart) {
+        // canonical pair (mu <= nu): first function mu, second nu
+        const int a0 = std::min(i4[0], i4[1]), a1 = std::max(i4[0], i4[1]);
+        const int b0 = std::min(i4[2], i4[3]), b1 = std::max(i4[2], i4[3]);
+        codes[2 * q] = A->cart_of(a0) | (A->cart_of(a1) << 2);
+        codes[2 * q + 1] = B->cart_of(b0) | (B->cart_of(b1) << 2);
+      }
     }
     qdcb_ctx *ctx = A->ctx;
     DeviceGuard g(ctx->device);
@@ -147,8 +179,11 @@ qdcb_status qdcb_eri_quartets(const qdcb_basis *A, const qdcb_basis *B, int64_t 
     dbf.upload(ctx, bf);
     dac.upload(ctx, ac);
     dbc.upload(ctx, bc);
+    DBuf<int32_t> dcodes;
+    if (cart) dcodes.upload(ctx, codes);
     dout.alloc(ctx, nq);
-    launch_eri_list(nq, daf.p, dbf.p, dac.p, dbc.p, A->pp.cview(), B->pp.cview(), dout.p, nullptr);
+    launch_eri_list(nq, daf.p, dbf.p, dac.p, dbc.p, dcodes.p, A->pp.cview(), B->pp.cview(),
+                    dout.p, nullptr);
     HIPC(hipGetLastError());
     HIPC(hipMemcpy(out, dout.p, nq * sizeof(double), hipMemcpyDeviceToHost));
   });

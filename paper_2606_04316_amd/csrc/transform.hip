@@ -219,6 +219,10 @@ EriTileArgs eri_args(qdcb_plan &p, Space &sp, int64_t slot0, bool count, bool ga
   ea.kept = count ? sp.kept.p : nullptr;
   ea.boys = p.boys.p;
   ea.boys3 = gauge ? p.boys3.p : nullptr;
+  ea.code = p.cart ? sp.code.p : nullptr;
+  ea.boysc = p.cart ? p.boysc.p : nullptr;
+  if (p.cart && (!ea.code || !ea.boysc || !sp.pp.pa.p || gauge))
+    fail(QDCB_E_DEVICE, "Cartesian tiles without their codes, table or pair data");
   ea.gauge_diag = breit ? 0.5 : -0.5;
   if (gauge && !ea.boys3) fail(QDCB_E_DEVICE, "gauge tiles without their table");
   return ea;

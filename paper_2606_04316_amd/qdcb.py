@@ -116,6 +116,8 @@ def lib():
         L.qdcb_ctx_destroy.argtypes = [_P]
         L.qdcb_ctx_destroy.restype = None
         L.qdcb_basis_create.argtypes = [_P, ctypes.c_int32, _DP, _IP, _DP, _DP, ctypes.POINTER(_P)]
+        L.qdcb_basis_create_cart.argtypes = [_P, ctypes.c_int32, _DP, _IP, _DP, _DP, _IP,
+                                             ctypes.POINTER(_P)]
         L.qdcb_basis_destroy.argtypes = [_P]
         L.qdcb_basis_destroy.restype = None
         L.qdcb_basis_schwarz.argtypes = [_P, _DP]
@@ -144,7 +146,8 @@ def lib():
                                             ctypes.POINTER(Tune)]
         L.qdcb_plan_autotune.argtypes = [_P, _P, _P, _P, ctypes.c_uint32, _P, ctypes.c_char_p,
                                          ctypes.POINTER(TuneReport)]
-        for f in ("qdcb_ctx_create", "qdcb_basis_create", "qdcb_basis_schwarz",
+        for f in ("qdcb_ctx_create", "qdcb_basis_create", "qdcb_basis_create_cart",
+                  "qdcb_basis_schwarz",
                   "qdcb_eri_quartets", "qdcb_plan_create", "qdcb_plan_footprint",
                   "qdcb_transform", "qdcb_plan_fetch", "qdcb_plan_estimate",
                   "qdcb_plan_capture", "qdcb_plan_replay", "qdcb_plan_fetch_v",
@@ -189,7 +192,8 @@ class Context:
 
 
 class Basis:
-    """Device-resident s-type basis: ``basis`` has centers, nprim, exps, coefs."""
+    """Device-resident basis: ``basis`` has centers, nprim, exps, coefs and
+    optionally cart (0 = s, 1..3 = p_x, p_y, p_z; qdcb_basis_create_cart)."""
 
     def __init__(self, ctx: Context, basis):
         self.ctx = ctx
@@ -198,10 +202,18 @@ class Basis:
         k = np.ascontiguousarray(basis.nprim, dtype=np.int32)
         e = _f64(basis.exps)
         d = _f64(basis.coefs)
+        cart = getattr(basis, "cart", None)
         h = _P()
-        _check(lib().qdcb_basis_create(ctx.h, self.nfunc, c.ctypes.data_as(_DP),
-                                       k.ctypes.data_as(_IP), e.ctypes.data_as(_DP),
-                                       d.ctypes.data_as(_DP), ctypes.byref(h)))
+        if cart is None:
+            _check(lib().qdcb_basis_create(ctx.h, self.nfunc, c.ctypes.data_as(_DP),
+                                           k.ctypes.data_as(_IP), e.ctypes.data_as(_DP),
+                                           d.ctypes.data_as(_DP), ctypes.byref(h)))
+        else:
+            ct = np.ascontiguousarray(cart, dtype=np.int32)
+            _check(lib().qdcb_basis_create_cart(ctx.h, self.nfunc, c.ctypes.data_as(_DP),
+                                                k.ctypes.data_as(_IP), e.ctypes.data_as(_DP),
+                                                d.ctypes.data_as(_DP), ct.ctypes.data_as(_IP),
+                                                ctypes.byref(h)))
         self.h = h
 
     def schwarz(self) -> np.ndarray:
