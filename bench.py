@@ -193,7 +193,8 @@ def main_transform(args):
             traffic = tr.get("bytes_per_launch")
     st0 = stats[-1]
     kind = "complex spinor" if spinor else "quaternion"
-    headline = not spinor and not args.mo_batch and sysm.ham != "DCB"
+    headline = (not spinor and not args.mo_batch and sysm.ham != "DCB"
+                and getattr(sysm.L, "cart", None) is None)
     line = {
         "metric": BASELINE_METRIC if headline else f"MO integrals/s ({kind} (pq|rs), FP64)",
         "value": value,
@@ -208,7 +209,8 @@ def main_transform(args):
                    "ham": sysm.ham, "tau": sysm.tau,
                    "algorithm": f"MO-driven, {args.mo_batch} MO pairs per batch"
                    if args.mo_batch else "AO-driven",
-                   "row_order": "primitive bands" if args.prim_bands else "Schwarz"},
+                   "row_order": "primitive bands" if args.prim_bands else "Schwarz",
+                   "shells": "s, p" if getattr(sysm.L, "cart", None) is not None else "s"},
         "spinor_integrals_per_s": (n if spinor else 2 * n) ** 4 * args.steps / elapsed,
         "stages_ms": {k: st0[k] for k in ("ms_density", "ms_screen", "ms_eri", "ms_first_half",
                                           "ms_second_half", "ms_total")},

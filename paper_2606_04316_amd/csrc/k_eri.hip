@@ -358,58 +358,135 @@ __global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles_queue(EriTileArgs a,
 
 // ---- Cartesian (s/p) tiles
 
-// g_n = (2/sqrt(pi)) sqrt(rho) F_n(T), n = 0..4: near field from the table
+// Directions of one (bra row, ket row) pair of a Cartesian tile: a, b of the
+// bra functions (lane), c, d of the ket functions (wavefront-uniform); an
+// absent direction (s function) has a zero Hermite coefficient, so its index
+// only needs to be valid (0).  The Kronecker deltas between the directions
+// are fixed for the pair, so they are formed once, outside the primitive
+// loops.
+struct CartDirs {
+  int a, b, c;            // ket: c = the direction of a one-p ket (either function)
+  int d;                  // second ket direction (two-p kets)
+  bool ha, hb;            // bra functions of p type
+  double dab, dac, dad, dbc, dbd, dcd;
+};
+
+// g_n = (2/sqrt(pi)) sqrt(rho) F_n(T), n < NG: near field from the table
 // tab[BOYS_LDC i + k] = (2/sqrt(pi)) F_k(T_i) by the Taylor series
 // F_m(T_i + d) = sum_k F_{m+k}(T_i) (-d)^k / k! (k <= 7, nested); far field
 // (T >= 36) from 1/R and the upward recursion.
-__device__ __forceinline__ void boys_g_tab(const double *tab, double T, double r2, double sr,
-                                           double g[5]) {
+template <int NG>
+__device__ __forceinline__ void boys_g_tab_n(const double *tab, double T, double r2, double sr,
+                                             double g[NG]) {
   if (T < BOYS_TMAX) {
     const int i = (int)fma(T, 8.0, 0.5);
     const double nd = fma(0.125, (double)i, -T);
     const double *c = tab + BOYS_LDC * i;
 #pragma unroll
-    for (int m = 0; m < 5; ++m) g[m] = c[m + 7];
+    for (int m = 0; m < NG; ++m) g[m] = c[m + 7];
 #pragma unroll
     for (int k = 7; k >= 1; --k) {
       const double h = nd * (1.0 / k);
 #pragma unroll
-      for (int m = 0; m < 5; ++m) g[m] = fma(g[m], h, c[m + k - 1]);
+      for (int m = 0; m < NG; ++m) g[m] = fma(g[m], h, c[m + k - 1]);
     }
 #pragma unroll
-    for (int m = 0; m < 5; ++m) g[m] *= sr;
+    for (int m = 0; m < NG; ++m) g[m] *= sr;
   } else {
     g[0] = rsqrt(r2);
     const double e = TWO_OVER_SQRTPI * sr * exp(-T);
     const double h = 0.5 / T;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) g[m + 1] = fma(2.0 * m + 1.0, g[m], -e) * h;
+    for (int m = 0; m + 1 < NG; ++m) g[m + 1] = fma(2.0 * m + 1.0, g[m], -e) * h;
   }
 }
 
-__device__ __forceinline__ double cart_quartet_tab(const double *tab, double ip, double px,
-                                                   double py, double pz, double pa, double pb,
-                                                   int cb, double iq, double qx, double qy,
-                                                   double qz, double qa, double qb, int ck) {
-  const double sr = rsqrt_pos(ip + iq);
-  const double rho = sr * sr;
-  const double X[3] = {px - qx, py - qy, pz - qz};
-  const double r2 = X[0] * X[0] + X[1] * X[1] + X[2] * X[2];
-  const double T = r2 * rho;
-  double g[5];
-  boys_g_tab(tab, T, r2, sr, g);
-  double G[5];
-  double f = 1.0;
-#pragma unroll
-  for (int n = 0; n < 5; ++n) {
-    G[n] = f * g[n];
-    f *= -2.0 * rho;
+__device__ __forceinline__ double sel3(int i, double x, double y, double z) {
+  return i == 0 ? x : (i == 1 ? y : z);
+}
+
+// Contracted value of one (bra row, ket row) pair of a Cartesian tile.  KT is
+// the ket's number of p functions (0, 1, 2); the bra side is branch-free
+// (its absent terms have zero coefficients).  With W_u the bra-contracted
+// Hermite integral sum_t h_t R_{t+u} for the ket Hermite index u:
+//   KT = 0: h0 W_0;  KT = 1: h0 W_0 - h1 W_c;
+//   KT = 2: h0 W_0 - h1 W_c - h2 W_d + h3 W_cd  (ket coefficients h).
+template <int KT>
+__device__ __forceinline__ double cart_row_pair(const EriTileArgs &A, const double *tab,
+                                                int64_t kf0, int64_t kf1, int64_t b0, int64_t b1,
+                                                const CartDirs &r, int kcode) {
+  constexpr int NG = 3 + KT;  // G_0 .. G_{2 + KT}
+  const int kc = (kcode & 3) - 1;
+  double v = 0.0;
+  for (int64_t k = kf0; k < kf1; ++k) {
+    const double iq = A.pp.ip[k], qx = A.pp.x[k], qy = A.pp.y[k], qz = A.pp.z[k];
+    const double ek = A.pp.e[k];
+    // ket Hermite coefficients
+    double k0 = 1.0, k1 = 0.0, k2 = 0.0, k3 = 0.0;
+    if constexpr (KT == 1) {
+      const double half = 0.5 * iq;
+      k0 = kc >= 0 ? A.pp.pa[k] : A.pp.pb[k];
+      k1 = half;
+    } else if constexpr (KT == 2) {
+      const double half = 0.5 * iq, qa = A.pp.pa[k], qb = A.pp.pb[k];
+      k0 = fma(qa, qb, r.dcd * half);
+      k1 = qb * half;
+      k2 = qa * half;
+      k3 = half * half;
+    }
+    double s = 0.0;
+    for (int64_t b = b0; b < b1; ++b) {
+      const double ip = A.pp.ip[b];
+      const double X0 = A.pp.x[b] - qx, X1 = A.pp.y[b] - qy, X2 = A.pp.z[b] - qz;
+      // bra Hermite coefficients (zero for absent functions)
+      const double half = 0.5 * ip;
+      const double fa = r.ha ? A.pp.pa[b] : 1.0, fb = r.hb ? A.pp.pb[b] : 1.0;
+      const double h0 = fma(fa, fb, r.dab * half);
+      const double h1 = r.ha ? fb * half : 0.0;
+      const double h2 = r.hb ? fa * half : 0.0;
+      const double h3 = (r.ha && r.hb) ? half * half : 0.0;
+      const double sr = rsqrt_pos(ip + iq);
+      const double rho = sr * sr;
+      const double r2 = X0 * X0 + X1 * X1 + X2 * X2;
+      double g[NG];
+      boys_g_tab_n<NG>(tab, r2 * rho, r2, sr, g);
+      const double m2r = -2.0 * rho;
+      const double G1 = g[1] * m2r, G2 = g[2] * (m2r * m2r);
+      const double xa = sel3(r.a, X0, X1, X2), xb = sel3(r.b, X0, X1, X2);
+      // W_0 = h0 R_0 + h1 R_a + h2 R_b + h3 R_ab
+      const double w0 = h0 * g[0] + (h1 * xa + h2 * xb) * G1 + h3 * fma(xa * xb, G2, r.dab * G1);
+      double val = k0 * w0;
+      if constexpr (KT >= 1) {
+        const double G3 = g[3] * (m2r * m2r * m2r);
+        const double xc = sel3(r.c, X0, X1, X2);
+        // W_c = h0 R_c + h1 R_ac + h2 R_bc + h3 R_abc
+        const double wc = h0 * xc * G1 + h1 * fma(xa * xc, G2, r.dac * G1) +
+                          h2 * fma(xb * xc, G2, r.dbc * G1) +
+                          h3 * fma(r.dab * xc + r.dac * xb + r.dbc * xa, G2, xa * xb * xc * G3);
+        val -= k1 * wc;
+        if constexpr (KT == 2) {
+          const double G4 = g[4] * ((m2r * m2r) * (m2r * m2r));
+          const double xd = sel3(r.d, X0, X1, X2);
+          const double wd = h0 * xd * G1 + h1 * fma(xa * xd, G2, r.dad * G1) +
+                            h2 * fma(xb * xd, G2, r.dbd * G1) +
+                            h3 * fma(r.dab * xd + r.dad * xb + r.dbd * xa, G2, xa * xb * xd * G3);
+          // W_cd = h0 R_cd + h1 R_acd + h2 R_bcd + h3 R_abcd
+          const double rcd = fma(xc * xd, G2, r.dcd * G1);
+          const double racd = fma(r.dac * xd + r.dad * xc + r.dcd * xa, G2, xa * xc * xd * G3);
+          const double rbcd = fma(r.dbc * xd + r.dbd * xc + r.dcd * xb, G2, xb * xc * xd * G3);
+          const double d2 = r.dab * r.dcd + r.dac * r.dbd + r.dad * r.dbc;
+          const double d1 = r.dab * xc * xd + r.dac * xb * xd + r.dad * xb * xc +
+                            r.dbc * xa * xd + r.dbd * xa * xc + r.dcd * xa * xb;
+          const double rabcd = d2 * G2 + d1 * G3 + (xa * xb) * (xc * xd) * G4;
+          const double wcd = h0 * rcd + h1 * racd + h2 * rbcd + h3 * rabcd;
+          val = fma(-k2, wd, fma(k3, wcd, val));
+        }
+      }
+      s = fma(A.pp.e[b], val, s);
+    }
+    v = fma(ek, s, v);
   }
-  double hb[4], hk[4];
-  int a, b, c, d;
-  herm_side(cb, pa, pb, 0.5 * ip, hb, a, b);
-  herm_side(ck, qa, qb, 0.5 * iq, hk, c, d);
-  return herm_contract(hb, a, b, hk, c, d, X, G);
+  return v;
 }
 
 __device__ __forceinline__ void eri_cart_tile_body(const EriTileArgs &a, const double *tab,
@@ -422,27 +499,41 @@ __device__ __forceinline__ void eri_cart_tile_body(const EriTileArgs &a, const d
   const int bcode = a.code[brow];
   const int64_t bfirst = a.row_first[brow];
   const int64_t blast = a.row_first[brow + 1];
+  const int ba = (bcode & 3) - 1, bb = ((bcode >> 2) & 3) - 1;
   for (int i = 0; i < TILE / ERI_WAVES; ++i) {
     const int j = w + ERI_WAVES * i;
     const int64_t krow = (int64_t)kt * TILE + j;
     const double qk = a.Q[krow], dk = a.Dmax[krow];
     const int ck = a.cls[krow];
-    const int kcode = a.code[krow];
+    const int kcode = __builtin_amdgcn_readfirstlane(a.code[krow]);
     const int64_t kf0 = a.row_first[krow], kf1 = a.row_first[krow + 1];
     double v = 0.0;
     const bool keep_bk = out && (qb * qk) * dk >= a.tau;
     const bool keep_kb = outT && (qk * qb) * db >= a.tau;
     if (keep_bk || keep_kb) {
-      for (int64_t k = kf0; k < kf1; ++k) {
-        const double iq = a.pp.ip[k], qx = a.pp.x[k], qy = a.pp.y[k], qz = a.pp.z[k];
-        const double qa = a.pp.pa[k], qbb = a.pp.pb[k], ek = a.pp.e[k];
-        double s = 0.0;
-        for (int64_t b = bfirst; b < blast; ++b)
-          s += a.pp.e[b] * cart_quartet_tab(tab, a.pp.ip[b], a.pp.x[b], a.pp.y[b], a.pp.z[b],
-                                            a.pp.pa[b], a.pp.pb[b], bcode, iq, qx, qy, qz, qa,
-                                            qbb, kcode);
-        v = fma(ek, s, v);
-      }
+      const int kc = (kcode & 3) - 1, kd = ((kcode >> 2) & 3) - 1;
+      const int kt_p = (kc >= 0) + (kd >= 0);
+      CartDirs r;
+      r.ha = ba >= 0;
+      r.hb = bb >= 0;
+      r.a = max(ba, 0);
+      r.b = max(bb, 0);
+      r.c = kc >= 0 ? kc : max(kd, 0);  // one-p kets: their direction
+      r.d = max(kd, 0);
+      auto del = [](int x, int y) { return (x >= 0 && x == y) ? 1.0 : 0.0; };
+      r.dab = del(ba, bb);
+      r.dcd = del(kc, kd);
+      const int c1 = kt_p == 1 ? r.c : kc;  // the first ket direction
+      r.dac = del(ba, c1);
+      r.dbc = del(bb, c1);
+      r.dad = del(ba, kd);
+      r.dbd = del(bb, kd);
+      if (kt_p == 0)
+        v = cart_row_pair<0>(a, tab, kf0, kf1, bfirst, blast, r, kcode);
+      else if (kt_p == 1)
+        v = cart_row_pair<1>(a, tab, kf0, kf1, bfirst, blast, r, kcode);
+      else
+        v = cart_row_pair<2>(a, tab, kf0, kf1, bfirst, blast, r, kcode);
       if (cb >= 0 && ck >= 0) {
         if (keep_bk) kept[cb * 2 + ck] += 1;
         if (keep_kb) kept[ck * 2 + cb] += 1;

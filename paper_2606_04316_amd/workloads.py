@@ -355,6 +355,22 @@ def sp_cluster(seed: int = 5, n_atoms: int = 8, edge: float = 6.0, s_per_atom: i
     return System(f"sp{n_atoms}_{ham}_{n}", ham, L, S, CL, CS, tau, atoms)
 
 
+def sp_chain(seed: int = 6, n_atoms: int = 40, spacing: float = 2.5, l_s: int = 4,
+             l_p: int = 2, s_s: int = 8, s_p: int = 4, nprim=3, n: int = 64,
+             tau: float = 1e-10, ham: str = "DC") -> System:
+    """The linear-chain recipe with p shells: per atom l_s s functions and l_p
+    p shells in L (10 functions by default, N_L = 400 for 40 atoms) and
+    s_s + 3 s_p in S (20, exponents x4).  MO coefficients as in sp_cluster."""
+    ra, rb, rc, _ = _streams(seed)
+    atoms = chain(n_atoms, spacing)
+    L = make_sp_basis(rb, atoms, l_s, l_p, nprim, 0.1, 10.0)
+    S = make_sp_basis(rb, atoms, s_s, s_p, nprim, 0.1, 10.0, exp_scale=4.0)
+    Q = quat_qr_plus(gaussian_quat(rc, L.nfunc + S.nfunc, n))
+    return System(f"chain{n_atoms}_sp_{ham}_{n}", ham, L, S,
+                  np.ascontiguousarray(Q[:, :L.nfunc]), np.ascontiguousarray(Q[:, L.nfunc:]),
+                  tau, atoms)
+
+
 def perturbed_coefficients(system: System, k: int, eps: float = 1e-2):
     """Re-transform input k: the system's quaternion-orthonormal Q0
     (C = X Q0) is perturbed by eps * G_k (G_k Gaussian, seed 3000 + k) and
@@ -383,6 +399,9 @@ def config(name: str) -> System:
                K in 1..6, n = 128, DC + Gaunt, tau 1e-10.
     ``chain40_dcg``, ``chain40_dcb``, ``cluster60_dcb``  the same systems with
                the Gaunt term, or the whole Breit term (Gaunt + gauge).
+    ``chain40_sp`` the chain40 shape with p shells: per atom 4 s + 2 p shells in
+               L (N_L = 400) and 8 s + 4 p shells in S (N_S = 800), K = 3, n = 64,
+               DC, tau 1e-10.
     ``sp8``    8 atoms in a 6 bohr cube with one s function and one p shell per
                atom in L and in S (N_L = N_S = 32), K in 1..3, n = 8, DC.
     """
@@ -400,6 +419,8 @@ def config(name: str) -> System:
         return cluster(seed=3, ham="DCB")
     if name == "sp8":
         return sp_cluster(seed=5)
+    if name == "chain40_sp":
+        return sp_chain(seed=6)
     if name == "cluster24":
         # the cluster recipe at 24 atoms (radius scaled by (24/60)^(1/3)), n = 64
         return cluster(seed=3, n_atoms=24, radius=20.0 * (24 / 60) ** (1 / 3), n=64)
