@@ -411,40 +411,55 @@ __device__ __forceinline__ double sel3(int i, double x, double y, double z) {
 // Hermite integral sum_t h_t R_{t+u} for the ket Hermite index u:
 //   KT = 0: h0 W_0;  KT = 1: h0 W_0 - h1 W_c;
 //   KT = 2: h0 W_0 - h1 W_c - h2 W_d + h3 W_cd  (ket coefficients h).
+// Read-only view of pair data in the constant address space: the pair data
+// are not written while an integral kernel runs, so wavefront-uniform reads
+// through it become scalar loads.
+typedef const __attribute__((address_space(4))) double *cdptr;
+__device__ __forceinline__ cdptr as_const(const double *p) { return (cdptr)p; }
+
+// Contracted value of one (bra row, ket row) pair of a Cartesian tile.  KT is
+// the ket's number of p functions (0, 1, 2); the bra side is branch-free
+// (its absent terms have zero coefficients).  With W_u the bra-contracted
+// Hermite integral sum_t h_t R_{t+u} for the ket Hermite index u:
+//   KT = 0: h0 W_0;  KT = 1: h0 W_0 - h1 W_c;
+//   KT = 2: h0 W_0 - h1 W_c - h2 W_d + h3 W_cd  (ket coefficients h).
+// Loop order: the lane's bra primitive outside (held in registers), the
+// wavefront-uniform ket primitives inside (scalar loads).
 template <int KT>
 __device__ __forceinline__ double cart_row_pair(const EriTileArgs &A, const double *tab,
                                                 int64_t kf0, int64_t kf1, int64_t b0, int64_t b1,
                                                 const CartDirs &r, int kcode) {
   constexpr int NG = 3 + KT;  // G_0 .. G_{2 + KT}
   const int kc = (kcode & 3) - 1;
+  const cdptr kip = as_const(A.pp.ip), kx = as_const(A.pp.x), ky = as_const(A.pp.y),
+              kz = as_const(A.pp.z), ke = as_const(A.pp.e), kpa = as_const(A.pp.pa),
+              kpb = as_const(A.pp.pb);
   double v = 0.0;
-  for (int64_t k = kf0; k < kf1; ++k) {
-    const double iq = A.pp.ip[k], qx = A.pp.x[k], qy = A.pp.y[k], qz = A.pp.z[k];
-    const double ek = A.pp.e[k];
-    // ket Hermite coefficients
-    double k0 = 1.0, k1 = 0.0, k2 = 0.0, k3 = 0.0;
-    if constexpr (KT == 1) {
-      const double half = 0.5 * iq;
-      k0 = kc >= 0 ? A.pp.pa[k] : A.pp.pb[k];
-      k1 = half;
-    } else if constexpr (KT == 2) {
-      const double half = 0.5 * iq, qa = A.pp.pa[k], qb = A.pp.pb[k];
-      k0 = fma(qa, qb, r.dcd * half);
-      k1 = qb * half;
-      k2 = qa * half;
-      k3 = half * half;
-    }
+  for (int64_t b = b0; b < b1; ++b) {
+    const double ip = A.pp.ip[b], px = A.pp.x[b], py = A.pp.y[b], pz = A.pp.z[b];
+    // bra Hermite coefficients (zero for absent functions)
+    const double half = 0.5 * ip;
+    const double fa = r.ha ? A.pp.pa[b] : 1.0, fb = r.hb ? A.pp.pb[b] : 1.0;
+    const double h0 = fma(fa, fb, r.dab * half);
+    const double h1 = r.ha ? fb * half : 0.0;
+    const double h2 = r.hb ? fa * half : 0.0;
+    const double h3 = (r.ha && r.hb) ? half * half : 0.0;
     double s = 0.0;
-    for (int64_t b = b0; b < b1; ++b) {
-      const double ip = A.pp.ip[b];
-      const double X0 = A.pp.x[b] - qx, X1 = A.pp.y[b] - qy, X2 = A.pp.z[b] - qz;
-      // bra Hermite coefficients (zero for absent functions)
-      const double half = 0.5 * ip;
-      const double fa = r.ha ? A.pp.pa[b] : 1.0, fb = r.hb ? A.pp.pb[b] : 1.0;
-      const double h0 = fma(fa, fb, r.dab * half);
-      const double h1 = r.ha ? fb * half : 0.0;
-      const double h2 = r.hb ? fa * half : 0.0;
-      const double h3 = (r.ha && r.hb) ? half * half : 0.0;
+    for (int64_t k = kf0; k < kf1; ++k) {
+      const double iq = kip[k];
+      // ket Hermite coefficients
+      double k0 = 1.0, k1 = 0.0, k2 = 0.0, k3 = 0.0;
+      if constexpr (KT == 1) {
+        k0 = kc >= 0 ? kpa[k] : kpb[k];
+        k1 = 0.5 * iq;
+      } else if constexpr (KT == 2) {
+        const double hq = 0.5 * iq, qa = kpa[k], qb = kpb[k];
+        k0 = fma(qa, qb, r.dcd * hq);
+        k1 = qb * hq;
+        k2 = qa * hq;
+        k3 = hq * hq;
+      }
+      const double X0 = px - kx[k], X1 = py - ky[k], X2 = pz - kz[k];
       const double sr = rsqrt_pos(ip + iq);
       const double rho = sr * sr;
       const double r2 = X0 * X0 + X1 * X1 + X2 * X2;
@@ -482,9 +497,9 @@ __device__ __forceinline__ double cart_row_pair(const EriTileArgs &A, const doub
           val = fma(-k2, wd, fma(k3, wcd, val));
         }
       }
-      s = fma(A.pp.e[b], val, s);
+      s = fma(ke[k], val, s);
     }
-    v = fma(ek, s, v);
+    v = fma(A.pp.e[b], s, v);
   }
   return v;
 }
