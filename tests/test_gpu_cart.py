@@ -125,3 +125,65 @@ def test_cart_refuses_gauge(q, ctx):
     with pytest.raises(q.QdcbError):
         q.Basis(ctx, wl.Basis(s.L.centers, s.L.nprim, s.L.exps, s.L.coefs,
                               np.full(s.L.nfunc, 4, np.int32)))
+
+
+def test_cart_spinor_plan_matches_oracle(q, ctx):
+    # general (Kramers-unrestricted) two-spinor plan over s and p functions
+    s = _sys("DCG", 1e-10, seed=47, n_atoms=5, n=4)
+    m = 6
+    PL, PS, _ = wl.general_spinors(s, m, seed=12)
+    L, S = q.Basis(ctx, s.L), q.Basis(ctx, s.S)
+    plan = q.Plan(ctx, L, S, "DCG", m, 1e-10, flags=q.PLAN_SPINOR)
+    G, st = plan.transform(PL, PS)
+    Gc = G[..., 0] + 1j * G[..., 1]
+    Go, so = oracle.transform_spinor(s.L, s.S, PL, PS, "DCG", 1e-10)
+    assert so["tie_band"] == 0
+    assert st["kept"] == so["kept"] and st["kept_gaunt"] == so["kept_gaunt"]
+    assert np.abs(Gc - Go).max() <= 1e-12 * np.abs(Go).max()
+
+
+def test_cart_mixed_and_mo_driven(q, ctx):
+    s = _sys("DC", 1e-10, seed=48)
+    L, S = q.Basis(ctx, s.L), q.Basis(ctx, s.S)
+    ref = q.Plan(ctx, L, S, "DC", s.n_mo, 1e-10)
+    G0, st0 = ref.transform(s.CL, s.CS)
+    # every kept tile in the FP32 tier: FP32 operands, FP32 accumulation
+    mp = q.Plan(ctx, L, S, "DC", s.n_mo, 1e-10, prec="mixed", tier_fp32=1e300, tier_bf16=0.0)
+    G1, st1 = mp.transform(s.CL, s.CS)
+    assert st1["tiles_tier"][1] == st1["tiles_kept"]
+    err = np.abs(G1 - G0).max()
+    assert 0.0 < err <= 2e-6 * np.abs(G0).max()
+    # MO-driven variant: batches of MO pairs, same integrals and results
+    mo = q.Plan(ctx, L, S, "DC", s.n_mo, 1e-10)
+    mo.set_mo_batch(4)
+    G2, st2 = mo.transform(s.CL, s.CS)
+    Go, _ = oracle.transform_direct_mo(s.L, s.S, s.CL, s.CS, "DC", 1e-10, 4)
+    assert np.abs(G2 - Go).max() <= 1e-12 * np.abs(Go).max()
+
+
+def test_cart_graph_replays_equal_eager(q, ctx):
+    import torch
+    s = _sys("DCG", 1e-10, seed=49, n_atoms=5, n=6)
+    L, S = q.Basis(ctx, s.L), q.Basis(ctx, s.S)
+    plan = q.Plan(ctx, L, S, "DCG", s.n_mo, 1e-10)
+    dev = torch.device("cuda:0")
+    CL = torch.from_numpy(s.CL).to(dev)
+    CS = torch.from_numpy(s.CS).to(dev)
+    n = s.n_mo
+    G = torch.empty((n, n, n, n, 4, 4), dtype=torch.float64, device=dev)
+    stream = torch.cuda.Stream()
+    plan.capture(CL, CS, G, stream)
+    rng = np.random.default_rng(50)
+    for k in range(3):
+        cl = s.CL if k == 0 else s.CL + 1e-2 * rng.standard_normal(s.CL.shape)
+        cs = s.CS if k == 0 else s.CS + 1e-2 * rng.standard_normal(s.CS.shape)
+        CL.copy_(torch.from_numpy(cl))
+        CS.copy_(torch.from_numpy(cs))
+        torch.cuda.synchronize()
+        st = plan.replay(stream)
+        assert st["graph_replay"] or st["graph_fallback"]
+        Gr = G.clone()
+        Ge, ste = plan.transform(torch.from_numpy(cl).to(dev), torch.from_numpy(cs).to(dev))
+        torch.cuda.synchronize()
+        assert st["kept"] == ste["kept"]
+        assert torch.equal(Gr, Ge)
