@@ -133,7 +133,22 @@ struct qdcb_plan {
   // previous batch (default priority)
   hipStream_t side = nullptr;
 
+  // an event after the last work a call enqueued on each stream the plan used
+  // (destruction waits for these instead of the whole device)
+  std::vector<std::pair<hipStream_t, hipEvent_t>> stream_events;
+  void mark_stream(hipStream_t s) {
+    for (auto &se : stream_events)
+      if (se.first == s) {
+        (void)hipEventRecord(se.second, s);
+        return;
+      }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return;
+    (void)hipEventRecord(e, s);
+    stream_events.emplace_back(s, e);
+  }
   ~qdcb_plan() {
+    for (auto &se : stream_events) (void)hipEventDestroy(se.second);
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (side) (void)hipStreamDestroy(side);
@@ -141,6 +156,13 @@ struct qdcb_plan {
 };
 
 namespace qdcb {
+// Records the plan's stream event when the scope ends (after the work a call
+// enqueued on s).
+struct StreamMark {
+  qdcb_plan &p;
+  hipStream_t s;
+  ~StreamMark() { p.mark_stream(s); }
+};
 // Exclusive use of a plan for the duration of one call: a second call on the
 // same plan meanwhile (another thread, or a callback of the first) fails with
 // QDCB_E_BUSY instead of racing.

@@ -8,6 +8,10 @@
 //            Pauli components K per MO-pair column.
 // Rows of a space are ordered by decreasing Schwarz factor and padded to a
 // multiple of 64.  The transformation itself is driven by transform.hip.
+#include <chrono>
+#include <deque>
+#include <cstdlib>
+
 #include "plan.h"
 
 using namespace qdcb;
@@ -43,8 +47,8 @@ void build_space(qdcb_ctx *ctx, Space &sp, std::vector<RowSrc> &rows,
         code.push_back(rows[i].code);
       }
     if (idx.empty()) continue;
-    DBuf<int64_t> dfirst;
-    DBuf<int32_t> dcnt, dk, dcode;
+    DBuf<int64_t> dfirst(POOLED);
+    DBuf<int32_t> dcnt(POOLED), dk(POOLED), dcode(POOLED);
     dfirst.upload(ctx, first);
     dcnt.upload(ctx, cnt);
     dcode.upload(ctx, code);
@@ -95,8 +99,13 @@ void build_space(qdcb_ctx *ctx, Space &sp, std::vector<RowSrc> &rows,
   for (const PairStore *st : stores) cart = cart || st->pa.p;
   if (cart) sp.code.upload(ctx, hcode);
   // primitive pairs kept per row after primitive screening
-  std::vector<DBuf<int64_t>> dsrc(ns);
-  std::vector<DBuf<int32_t>> dcnt(ns), dscode(ns);
+  std::deque<DBuf<int64_t>> dsrc;  // deque: its elements never move
+  std::deque<DBuf<int32_t>> dcnt, dscode;
+  for (size_t w = 0; w < ns; ++w) {
+    dsrc.emplace_back(POOLED);
+    dcnt.emplace_back(POOLED);
+    dscode.emplace_back(POOLED);
+  }
   std::vector<int32_t> kept_prims(sp.Ppad, 0);
   for (int64_t r = 0; r < sp.P; ++r) kept_prims[r] = rows[r].kept;
   for (size_t w = 0; w < ns; ++w) {
@@ -117,12 +126,12 @@ void build_space(qdcb_ctx *ctx, Space &sp, std::vector<RowSrc> &rows,
   sp.pp.alloc(ctx, (size_t)std::max<int64_t>(rf[sp.Ppad], 1), cart);
   for (size_t w = 0; w < ns; ++w) {
     if (src[w].empty()) continue;
-    DBuf<int64_t> dd;
+    DBuf<int64_t> dd(POOLED);
     dd.upload(ctx, dst[w]);
     launch_gather_pairs((int64_t)src[w].size(), dsrc[w].p, dcnt[w].p, dscode[w].p, dd.p,
                         stores[w]->cview(), sp.pp.view(), PRIM_EPS, nullptr);
     HIPC(hipGetLastError());
-    HIPC(hipDeviceSynchronize());
+    HIPC(hipStreamSynchronize(nullptr));
   }
   sp.Dmax.alloc(ctx, sp.Ppad);
   sp.Qmax.alloc(ctx, sp.ntiles);
@@ -133,6 +142,27 @@ void build_space(qdcb_ctx *ctx, Space &sp, std::vector<RowSrc> &rows,
   sp.dtotal.alloc(ctx, 1);
   sp.overflow.alloc(ctx, 1);
 }
+
+// Stage times of plan creation on stderr when QDCB_TRACE_PLAN is set (host
+// wall clock, after a device synchronization at each mark).
+struct PlanTrace {
+  bool on = std::getenv("QDCB_TRACE_PLAN") != nullptr;
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  std::string line;
+  void mark(const char *what) {
+    if (!on) return;
+    (void)hipDeviceSynchronize();
+    const auto now = std::chrono::steady_clock::now();
+    char b[96];
+    std::snprintf(b, sizeof b, " %s %.2f", what,
+                  std::chrono::duration<double, std::milli>(now - t).count());
+    line += b;
+    t = now;
+  }
+  ~PlanTrace() {
+    if (on && !line.empty()) std::fprintf(stderr, "qdcb plan ms:%s\n", line.c_str());
+  }
+};
 
 // Taylor table of the Boys function, tab[8 i + k] = (2/sqrt(pi)) (-1)^k F_k(T_i) / k! at
 // T_i = i / 8: F_7 from its series e^-T sum_j (2T)^j / ((2m+1)(2m+3)...(2m+2j+1)),
@@ -320,6 +350,7 @@ bool ensure_residency(qdcb_plan &p, double slack) {
   // allocations of the process, such as the caller's G, count against it)
   size_t fr = 0, tot = 0;
   HIPC(hipMemGetInfo(&fr, &tot));
+  fr += dev_cached(p.ctx->device);  // cached blocks are reusable
   const double room0 = std::min((double)p.ctx->room(), 0.95 * (double)fr) + (double)held -
                        (double)g_stage;
   const double panels = (double)sizeof(double) * TILE * TILE *
@@ -369,6 +400,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
     if (L->ctx->device != ctx->device || (S && S->ctx->device != ctx->device))
       fail(QDCB_E_INVALID, "basis on another device");
     DeviceGuard g(ctx->device);
+    PlanTrace trace;
     std::unique_ptr<qdcb_plan> pl(new qdcb_plan());
     qdcb_plan &p = *pl;
     p.ctx = ctx;
@@ -417,6 +449,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
       p.C.gaunt = 0;
       p.C.nK = 1;
       build_space(ctx, p.C, rows, stores, bands);
+      trace.mark("coulomb_space");
     }
     // --- Gaunt space: ordered LS pairs (mu in L, nu in S), key mu*NS + nu
     if (p.gaunt) {
@@ -430,10 +463,10 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
           pn[i] = nu;
           pf[i + 1] = pf[i] + (int64_t)L->nprim[mu] * S->nprim[nu];
         }
-      PairStore ls;
-      DBuf<int32_t> dm, dn;
-      DBuf<int64_t> dpf;
-      DBuf<double> dQ;
+      PairStore ls(POOLED);
+      DBuf<int32_t> dm(POOLED), dn(POOLED);
+      DBuf<int64_t> dpf(POOLED);
+      DBuf<double> dQ(POOLED);
       dm.upload(ctx, pm);
       dn.upload(ctx, pn);
       dpf.upload(ctx, pf);
@@ -444,7 +477,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
       std::vector<int32_t> lcode(p.cart ? nls : 0);
       for (int64_t i = 0; p.cart && i < nls; ++i)
         lcode[i] = L->cart_of(pm[i]) | (S->cart_of(pn[i]) << 2);
-      DBuf<int32_t> dlcode;
+      DBuf<int32_t> dlcode(POOLED);
       if (p.cart) dlcode.upload(ctx, lcode);
       dQ.alloc(ctx, nls);
       launch_schwarz(nls, dpf.p, ls.cview(), dlcode.p, dQ.p, nullptr);
@@ -459,6 +492,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
       p.G.gaunt = 1;
       p.G.nK = 3;
       build_space(ctx, p.G, rows, {&ls}, bands);
+      trace.mark("gaunt_space");
     }
 
     // --- index tables
@@ -486,6 +520,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
         p.rowmapLS.upload(ctx, mLS);
       }
     }
+    trace.mark("index_tables");
     // --- coefficient buffers
     p.CLd.alloc(ctx, (size_t)4 * p.NL * p.n);
     p.CallL.alloc(ctx, (size_t)p.NL * 4 * p.n);
@@ -527,6 +562,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
       sp->uorder.alloc(ctx, ucap);
       sp->lpt.alloc(ctx, LPT_WORK);
     }
+    trace.mark("coef_and_task_buffers");
     // --- launch choices and the shape key of the tuning cache
     HIPC(hipDeviceGetAttribute(&p.n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
     p.tune.eri_sched = 1;  // faster or equal on every workload measured
@@ -545,10 +581,13 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
       p.tune_key = key;
     }
     size_plan(p, 0, 0);
+    trace.mark("size_plan");
     p.boys.upload(ctx, boys_table());
     if (p.gauge) p.boys3.upload(ctx, boys_table3());
     if (p.cart) p.boysc.upload(ctx, boys_table_cart());
+    trace.mark("tables");
     HIPC(hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking));
+    trace.mark("stream");
     ctx->retain();
     *out = pl.release();
   });
@@ -560,7 +599,19 @@ void qdcb_plan_destroy(qdcb_plan *p) {
   int prev = -1;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(ctx->device);
-  delete p;
+  // wait only for this plan's own work (the last enqueued call on each stream
+  // it used, and its side stream); its buffers then go to the allocator's
+  // cache without the device-wide wait of hipFree
+  bool idle = true;
+  for (auto &se : p->stream_events) idle = idle && hipEventSynchronize(se.second) == hipSuccess;
+  if (p->side) idle = idle && hipStreamSynchronize(p->side) == hipSuccess;
+  if (idle) {
+    CacheReleases cache;
+    delete p;
+  } else {
+    (void)hipGetLastError();
+    delete p;  // hipFree: waits for the whole device
+  }
   if (prev >= 0) (void)hipSetDevice(prev);
   qdcb_ctx::release_ref(ctx);
 }

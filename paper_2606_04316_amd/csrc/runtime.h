@@ -12,6 +12,7 @@
 #include <numeric>
 #include <stdexcept>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/qdcb.h"
@@ -64,6 +65,25 @@ struct DeviceGuard {
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// Device memory of contexts.  Blocks are rounded up (powers of two to 1 MiB,
+// then eighths of a power of two).  dev_release returns a block with hipFree,
+// or, while the calling thread is inside a CacheReleases scope, to a
+// per-device cache that dev_alloc takes blocks from (the smallest cached
+// block of at least the rounded size, if it is at most twice that).  hipFree synchronizes the whole device, so a plan that is
+// destroyed while other plans' transforms run would otherwise wait for them
+// at every buffer.  A scope may cache only blocks no stream still uses.  The
+// cache keeps at most a quarter of the device's memory; it is emptied when
+// hipMalloc fails.
+void *dev_alloc(int device, size_t bytes);
+void dev_release(int device, void *p);
+size_t dev_cached(int device);  // bytes held by the cache
+struct CacheReleases {
+  CacheReleases();
+  ~CacheReleases();
+  CacheReleases(const CacheReleases &) = delete;
+  CacheReleases &operator=(const CacheReleases &) = delete;
+};
+
 }  // namespace qdcb
 
 // A context lives until it has been destroyed by its owner and every basis
@@ -84,16 +104,13 @@ struct qdcb_ctx {
     if (used + bytes > budget)
       qdcb::fail(QDCB_E_NOMEM, "device memory budget exceeded (" + std::to_string(used + bytes) +
                                    " > " + std::to_string(budget) + " bytes)");
-    void *p = nullptr;
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess)
-      qdcb::fail(QDCB_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    void *p = qdcb::dev_alloc(device, bytes);
     used += bytes;
     return p;
   }
   void release(void *p, size_t bytes) {
     if (!p) return;
-    (void)hipFree(p);
+    qdcb::dev_release(device, p);
     used -= bytes;
   }
   size_t room() const { return budget > used ? budget - used : 0; }
@@ -101,13 +118,29 @@ struct qdcb_ctx {
 
 namespace qdcb {
 
-// Device buffer owned by a context.
+// Device scratch of set-up work (basis and plan creation, test entries).  A
+// freed block goes back to a per-device cache instead of hipFree, whose
+// implicit device-wide synchronization would wait for every stream of the
+// process, the transforms of other plans included.  Set-up work runs on the
+// null stream, so a block is cached only after that stream has drained.
+// Blocks are rounded up to a power of two (>= 4 KiB); the cache keeps at most
+// 1 GiB per device and frees beyond that.  Not counted in context budgets.
+void *tmp_alloc(int device, size_t bytes, size_t *rounded);
+void tmp_release(int device, void *p, size_t rounded);
+
+struct Pooled {};
+constexpr Pooled POOLED{};
+
+// Device buffer owned by a context (or, pooled, a set-up scratch block).
 template <class T>
 struct DBuf {
   qdcb_ctx *ctx = nullptr;
   T *p = nullptr;
   size_t n = 0;
+  bool pooled = false;
+  size_t cap_bytes = 0;  // pooled: the block's rounded size
   DBuf() = default;
+  explicit DBuf(Pooled) : pooled(true) {}
   DBuf(const DBuf &) = delete;
   DBuf &operator=(const DBuf &) = delete;
   ~DBuf() { free(); }
@@ -115,14 +148,24 @@ struct DBuf {
     free();
     ctx = c;
     n = count;
-    p = static_cast<T *>(c->alloc(count * sizeof(T)));
+    if (pooled)
+      p = count ? static_cast<T *>(tmp_alloc(c->device, count * sizeof(T), &cap_bytes)) : nullptr;
+    else
+      p = static_cast<T *>(c->alloc(count * sizeof(T)));
   }
   void upload(qdcb_ctx *c, const std::vector<T> &v) {
     alloc(c, v.size());
     if (!v.empty()) HIPC(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
   }
   void free() {
-    if (ctx && p) ctx->release(p, n * sizeof(T));
+    if (ctx && p) {
+      if (pooled) {
+        (void)hipStreamSynchronize(nullptr);  // set-up kernels that read it are done
+        tmp_release(ctx->device, p, cap_bytes);
+      } else {
+        ctx->release(p, n * sizeof(T));
+      }
+    }
     p = nullptr;
     n = 0;
   }
@@ -132,6 +175,9 @@ struct DBuf {
 struct PairStore {
   DBuf<double> p, x, y, z, e;
   DBuf<double> pa, pb;  // bases with p functions only (see PrimPairs)
+  PairStore() = default;
+  explicit PairStore(Pooled)
+      : p(POOLED), x(POOLED), y(POOLED), z(POOLED), e(POOLED), pa(POOLED), pb(POOLED) {}
   void alloc(qdcb_ctx *c, size_t n, bool cart = false) {
     p.alloc(c, n);
     x.alloc(c, n);

@@ -3,6 +3,10 @@
 // A basis owns the device primitive-pair (Gaussian product) data of all its
 // function pairs and their Schwarz factors; both stay resident for the
 // basis's lifetime and are shared by every plan built on it.
+#include <map>
+#include <mutex>
+#include <unordered_map>
+
 #include "runtime.h"
 
 using namespace qdcb;
@@ -10,6 +14,166 @@ using namespace qdcb;
 namespace qdcb {
 thread_local std::string g_err;
 }
+
+namespace qdcb {
+
+namespace {
+struct TmpPool {
+  std::mutex m;
+  std::multimap<size_t, void *> free_blocks;  // rounded size -> block
+  size_t cached = 0;
+};
+constexpr size_t TMP_CACHE_MAX = (size_t)1 << 30;
+TmpPool &tmp_pool(int device) {
+  static std::mutex m;
+  static std::map<int, std::unique_ptr<TmpPool>> pools;
+  std::lock_guard<std::mutex> g(m);
+  auto &slot = pools[device];
+  if (!slot) slot.reset(new TmpPool());
+  return *slot;
+}
+}  // namespace
+
+void *tmp_alloc(int device, size_t bytes, size_t *rounded) {
+  size_t r = 4096;
+  while (r < bytes) r <<= 1;
+  *rounded = r;
+  TmpPool &tp = tmp_pool(device);
+  {
+    std::lock_guard<std::mutex> g(tp.m);
+    auto it = tp.free_blocks.find(r);
+    if (it != tp.free_blocks.end()) {
+      void *p = it->second;
+      tp.free_blocks.erase(it);
+      tp.cached -= r;
+      return p;
+    }
+  }
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, r);
+  if (e != hipSuccess) fail(QDCB_E_NOMEM, std::string("hipMalloc (set-up scratch): ") +
+                                              hipGetErrorString(e));
+  return p;
+}
+
+void tmp_release(int device, void *p, size_t rounded) {
+  if (!p) return;
+  TmpPool &tp = tmp_pool(device);
+  {
+    std::lock_guard<std::mutex> g(tp.m);
+    if (tp.cached + rounded <= TMP_CACHE_MAX) {
+      tp.free_blocks.emplace(rounded, p);
+      tp.cached += rounded;
+      return;
+    }
+  }
+  (void)hipFree(p);
+}
+
+namespace {
+struct DevCache {
+  std::mutex m;
+  std::multimap<size_t, void *> free_blocks;    // size -> cached block
+  std::unordered_map<void *, size_t> size_of;  // every live or cached block
+  size_t cached = 0;
+  size_t cap = 0;
+};
+thread_local int t_cache_releases = 0;
+DevCache &dev_cache(int device) {
+  static std::mutex m;
+  static std::map<int, std::unique_ptr<DevCache>> caches;
+  std::lock_guard<std::mutex> g(m);
+  auto &slot = caches[device];
+  if (!slot) {
+    slot.reset(new DevCache());
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess) slot->cap = tot / 4;
+  }
+  return *slot;
+}
+size_t round_block(size_t bytes) {
+  constexpr size_t MB = (size_t)1 << 20;
+  if (bytes > MB) {
+    // eighths of the power of two below: at most 12.5% more
+    size_t top = MB;
+    while (top * 2 <= bytes) top <<= 1;
+    const size_t step = top / 8;
+    return (bytes + step - 1) / step * step;
+  }
+  size_t r = 256;
+  while (r < bytes) r <<= 1;
+  return r;
+}
+}  // namespace
+
+CacheReleases::CacheReleases() { ++t_cache_releases; }
+CacheReleases::~CacheReleases() { --t_cache_releases; }
+
+void *dev_alloc(int device, size_t bytes) {
+  const size_t r = round_block(bytes);
+  DevCache &dc = dev_cache(device);
+  {
+    std::lock_guard<std::mutex> g(dc.m);
+    auto it = dc.free_blocks.lower_bound(r);
+    if (it != dc.free_blocks.end() && it->first <= 2 * r) {
+      void *p = it->second;
+      dc.cached -= it->first;
+      dc.free_blocks.erase(it);
+      return p;
+    }
+  }
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, r);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    // give the cached blocks back and try once more
+    std::vector<void *> blocks;
+    {
+      std::lock_guard<std::mutex> g(dc.m);
+      for (auto &b : dc.free_blocks) {
+        blocks.push_back(b.second);
+        dc.size_of.erase(b.second);
+      }
+      dc.free_blocks.clear();
+      dc.cached = 0;
+    }
+    for (void *b : blocks) (void)hipFree(b);
+    p = nullptr;
+    e = hipMalloc(&p, r);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      fail(QDCB_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+  }
+  std::lock_guard<std::mutex> g(dc.m);
+  dc.size_of[p] = r;
+  return p;
+}
+
+void dev_release(int device, void *p) {
+  if (!p) return;
+  DevCache &dc = dev_cache(device);
+  {
+    std::lock_guard<std::mutex> g(dc.m);
+    auto it = dc.size_of.find(p);
+    const size_t sz = it != dc.size_of.end() ? it->second : 0;
+    if (t_cache_releases > 0 && sz && dc.cached + sz <= dc.cap) {
+      dc.free_blocks.emplace(sz, p);
+      dc.cached += sz;
+      return;
+    }
+    if (it != dc.size_of.end()) dc.size_of.erase(it);
+  }
+  (void)hipFree(p);
+}
+
+size_t dev_cached(int device) {
+  DevCache &dc = dev_cache(device);
+  std::lock_guard<std::mutex> g(dc.m);
+  return dc.cached;
+}
+
+}  // namespace qdcb
 
 extern "C" {
 
@@ -28,7 +192,8 @@ qdcb_status qdcb_ctx_create(int device, size_t budget, qdcb_ctx **out) {
     HIPC(hipMemGetInfo(&fr, &tot));
     auto *c = new qdcb_ctx();
     c->device = device;
-    c->budget = budget ? budget : (size_t)(0.9 * (double)fr);
+    // blocks held by the allocator's cache are free for this context too
+    c->budget = budget ? budget : (size_t)(0.9 * (double)(fr + dev_cached(device)));
     *out = c;
   });
 }
@@ -97,7 +262,7 @@ qdcb_status qdcb_basis_create_cart(qdcb_ctx *ctx, int32_t nfunc, const double *c
     for (int64_t i = 0; i < npairs; ++i)
       pf[i + 1] = pf[i] + (int64_t)nprim[pm[i]] * nprim[pn[i]];
     b->pair_first = pf;
-    DBuf<int32_t> dm, dn;
+    DBuf<int32_t> dm(POOLED), dn(POOLED);
     dm.upload(ctx, pm);
     dn.upload(ctx, pn);
     b->dpair_first.upload(ctx, pf);
@@ -106,7 +271,7 @@ qdcb_status qdcb_basis_create_cart(qdcb_ctx *ctx, int32_t nfunc, const double *c
                      b->nc.p, b->dcart.p, b->cent.p, b->dfirst.p, b->exps.p, b->nc.p,
                      b->dcart.p, b->pp.view(), nullptr);
     HIPC(hipGetLastError());
-    DBuf<int32_t> dcode;
+    DBuf<int32_t> dcode(POOLED);
     if (any_p) {
       std::vector<int32_t> code(npairs);
       for (int64_t i = 0; i < npairs; ++i) code[i] = b->cart[pm[i]] | (b->cart[pn[i]] << 2);
@@ -172,14 +337,14 @@ qdcb_status qdcb_eri_quartets(const qdcb_basis *A, const qdcb_basis *B, int64_t 
     }
     qdcb_ctx *ctx = A->ctx;
     DeviceGuard g(ctx->device);
-    DBuf<int64_t> daf, dbf;
-    DBuf<int32_t> dac, dbc;
-    DBuf<double> dout;
+    DBuf<int64_t> daf(POOLED), dbf(POOLED);
+    DBuf<int32_t> dac(POOLED), dbc(POOLED);
+    DBuf<double> dout(POOLED);
     daf.upload(ctx, af);
     dbf.upload(ctx, bf);
     dac.upload(ctx, ac);
     dbc.upload(ctx, bc);
-    DBuf<int32_t> dcodes;
+    DBuf<int32_t> dcodes(POOLED);
     if (cart) dcodes.upload(ctx, codes);
     dout.alloc(ctx, nq);
     launch_eri_list(nq, daf.p, dbf.p, dac.p, dbc.p, dcodes.p, A->pp.cview(), B->pp.cview(),

@@ -843,6 +843,7 @@ qdcb_status qdcb_plan_autotune(qdcb_plan *plan, const double *CL, const double *
     }
     DeviceGuard g(p.ctx->device);
     hipStream_t s = (hipStream_t)hip_stream;
+    StreamMark mark{p, s};  // after this call's work on s
     const DevIO io = device_io(p, CL, CS, G, flags & QDCB_PTR_DEVICE, s);
     const qdcb_tune saved = p.tune;
     // the two candidates differ in every choice; alternating them gives each
@@ -900,6 +901,7 @@ qdcb_status qdcb_transform(qdcb_plan *plan, const double *CL, const double *CS, 
     if (p.NS && !CS) fail(QDCB_E_INVALID, "CS is required for this Hamiltonian");
     DeviceGuard g(p.ctx->device);
     hipStream_t s = (hipStream_t)hip_stream;
+    StreamMark mark{p, s};  // after this call's work on s
     const bool dev = flags & QDCB_PTR_DEVICE;
     const int classes = class_mask(p, flags);
     const int n = p.n;
@@ -925,6 +927,7 @@ qdcb_status qdcb_transform_blocks(qdcb_plan *plan, const double *CL, const doubl
     if (p.spinor) fail(QDCB_E_UNSUPPORTED, "blocked output is offered for quaternion plans");
     DeviceGuard g(p.ctx->device);
     hipStream_t s = (hipStream_t)hip_stream;
+    StreamMark mark{p, s};  // after this call's work on s
     const bool dev = flags & QDCB_PTR_DEVICE;
     const int classes = class_mask(p, flags);
     // block buffer: at most one second-half slice of MO pairs, both (r, s)
@@ -1015,6 +1018,7 @@ qdcb_status qdcb_plan_replay(qdcb_plan *plan, void *hip_stream, qdcb_stats *stat
     if (!p.graph_exec) fail(QDCB_E_INVALID, "no captured transform (call qdcb_plan_capture)");
     DeviceGuard g(p.ctx->device);
     hipStream_t s = (hipStream_t)hip_stream;
+    StreamMark mark{p, s};  // after this call's work on s
     hipEvent_t e0, e1;
     HIPC(hipEventCreate(&e0));
     HIPC(hipEventCreate(&e1));

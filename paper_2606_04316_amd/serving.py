@@ -177,13 +177,14 @@ class GpuExecutor:
 
     G comes to the host through a pinned staging buffer per slot (reused, so
     a result is delivered as the digest of that copy, or as the device tensor
-    with keep_outputs).  Finished plans and their contexts are destroyed by a
+    with keep_outputs; ``digest_ids`` limits the hashing to those requests).  Finished plans and their contexts are destroyed by a
     background thread: freeing device memory waits for the work of every
     stream on the device, which would otherwise hold the slot until the other
     slots' transforms finish.  ``drain()`` waits for those releases."""
 
     def __init__(self, slots: int, device: int = 0, keep_outputs: bool = False,
-                 prec: str = "fp64", tiers=(1e-6, 1e-9, 0x2), plan_flags: int = 0):
+                 prec: str = "fp64", tiers=(1e-6, 1e-9, 0x2), plan_flags: int = 0,
+                 digest_ids=None):
         import torch
         from paper_2606_04316_amd import qdcb
         self.torch = torch
@@ -198,6 +199,9 @@ class GpuExecutor:
         self.prec = prec
         self.tiers = tiers
         self.plan_flags = int(plan_flags)
+        # requests whose G is hashed for the alone-vs-mix comparison (None:
+        # every request); the hash runs after delivery but holds the slot
+        self.digest_ids = None if digest_ids is None else set(digest_ids)
         self.staging = [None] * slots  # pinned host buffers for G, per slot
         self._retire: "queue.Queue" = queue.Queue()
         self._reaper = threading.Thread(target=self._reap, daemon=True)
@@ -261,6 +265,7 @@ class GpuExecutor:
         s = r.system
         L = self.basis(s.L)
         S = self.basis(s.S) if s.S is not None else None
+        t_start = time.perf_counter()
         ctx = held["ctx"] = qdcb.Context(self.device, budget_bytes=r.reserve)
         stream = self.streams[slot]
         with torch.cuda.stream(stream):
@@ -271,16 +276,23 @@ class GpuExecutor:
             else:
                 plan = qdcb.Plan(ctx, L, S, s.ham, s.n_mo, s.tau, flags=self.plan_flags)
             held["plan"] = plan
+            t_plan = time.perf_counter()
             CL = torch.from_numpy(s.CL).to(self.dev, non_blocking=False)
             CS = torch.from_numpy(s.CS).to(self.dev) if s.CS is not None else None
             n = s.n_mo
             G = torch.empty((n, n, n, n, 4, 4), dtype=torch.float64, device=self.dev)
             G, st = plan.transform(CL, CS, G, stream=stream.cuda_stream)
+        t_tr = time.perf_counter()
         Gh = self._host_copy(G, slot, stream)
         t_result = time.perf_counter()  # G is on the host: the request is served
-        digest = hashlib.sha1(Gh.tobytes()).hexdigest()
+        digest = None
+        if self.digest_ids is None or r.rid in self.digest_ids:
+            digest = hashlib.sha1(Gh.tobytes()).hexdigest()
         out = {"digest": digest, "n": n, "ms_gpu": st["ms_total"], "t_result": t_result,
-               "flops": st["flops_first_half"] + st["flops_second_half"]}
+               "flops": st["flops_first_half"] + st["flops_second_half"],
+               "ms_plan": 1e3 * (t_plan - t_start), "ms_transform_call": 1e3 * (t_tr - t_plan),
+               "ms_copy": 1e3 * (t_result - t_tr),
+               "ms_digest": 1e3 * (time.perf_counter() - t_result)}
         if self.keep_outputs:
             out["G"] = G
         return out
@@ -327,6 +339,10 @@ def summarize(reqs: List[Request]) -> dict:
     serve = np.array([1e3 * (r.t_done - r.t_admit) for r in done])
     gpu = np.array([r.result["ms_gpu"] for r in done
                     if isinstance(r.result, dict) and "ms_gpu" in r.result])
+
+    def mean_of(k):
+        v = [r.result[k] for r in done if isinstance(r.result, dict) and k in r.result]
+        return float(np.mean(v)) if v else None
     return {"requests": len(reqs), "failed": sum(r.error is not None for r in reqs),
             "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
             "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
@@ -334,5 +350,7 @@ def summarize(reqs: List[Request]) -> dict:
             "mean_wait_ms": float(wait.mean()) if wait.size else None,
             "mean_service_ms": float(serve.mean()) if serve.size else None,
             "mean_transform_ms": float(gpu.mean()) if gpu.size else None,
+            "mean_parts_ms": {k: mean_of("ms_" + k) for k in ("plan", "transform_call", "copy",
+                                                                 "digest")},
             "span_s": span, "mo_integrals_per_s": mo / span if span > 0 else None,
             "errors": errors}
