@@ -34,7 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_MFMA = 78.6  # TFLOP/s, MI355X dense FP64 matrix
-BASELINE_METRIC = ("MO integrals/s & MFMA util, mixed vs FP64 at <=1e-10 Eh err; "
+HEADLINE_METRIC = ("MO integrals/s & MFMA util, mixed vs FP64 at <=1e-10 Eh err; "
                    "serving p99 ms")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "first_half_chain40_traffic.json")
 
@@ -196,7 +196,7 @@ def main_transform(args):
     headline = (not spinor and not args.mo_batch and sysm.ham != "DCB"
                 and getattr(sysm.L, "cart", None) is None)
     line = {
-        "metric": BASELINE_METRIC if headline else f"MO integrals/s ({kind} (pq|rs), FP64)",
+        "metric": HEADLINE_METRIC if headline else f"MO integrals/s ({kind} (pq|rs), FP64)",
         "value": value,
         "unit": f"{kind} MO integrals (pq|rs)/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -433,8 +433,9 @@ def serving_run(args, prec):
 def main_serving(args):
     """The request loop on a seeded Poisson stream (mean gap 20 ms); each
     request is a cluster drawn from a pool, with its own active-space size and
-    Hamiltonian (DC or DCG).  Sizes are the stream recipe's reduced ranges
-    (see the design doc); eight requests are re-run alone and compared bitwise."""
+    Hamiltonian (DC or DCG).  Sizes are reduced ranges of the stream recipe
+    (10-40 atoms, N_L 40-160, n 8-32, so that every G fits a host staging
+    buffer); eight requests are re-run alone and compared bitwise."""
     runs = {prec: serving_run(args, prec) for prec in args.serving_prec.split(",")}
     first = runs[next(iter(runs))]
     line = {"metric": "serving p99 latency", "mode": "serving", "value": first["p99_ms"],
