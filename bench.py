@@ -65,7 +65,11 @@ def parse():
                          "(mixed: tiers 1e-6 / 1e-9 with the G-bound rule)")
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--prim-bands", action="store_true",
-                    help="plans with QDCB_PLAN_PRIM_BANDS (rows grouped by primitive count)")
+                    help="transform: plans with QDCB_PLAN_PRIM_BANDS (rows grouped by the "
+                         "primitive pairs they keep)")
+    ap.add_argument("--serving-rows", default="bands", choices=["bands", "schwarz"],
+                    help="serving: row order of the request plans (bands: "
+                         "QDCB_PLAN_PRIM_BANDS; the requests' contraction depths are uneven)")
     ap.add_argument("--mo-batch", type=int, default=0,
                     help="transform: run the MO-driven variant with batches of this many MO "
                          "pairs, each screened with its own density bound (0: AO-driven)")
@@ -400,7 +404,7 @@ def serving_run(args, prec):
     reqs = serving.request_stream(args.requests, seed=5, mean_gap_s=0.02, pool=12,
                                   atoms=(10, 40), nl=(40, 160), n_mo=(8, 32),
                                   radius_scale=20.0)
-    pf = 0x8 if args.prim_bands else 0  # QDCB_PLAN_PRIM_BANDS
+    pf = 0x8 if args.serving_rows == "bands" else 0  # QDCB_PLAN_PRIM_BANDS
     # the eight requests re-run alone below (every len/8-th by arrival) are the
     # only ones hashed
     step = max(1, len(reqs) // 8)
@@ -422,7 +426,7 @@ def serving_run(args, prec):
                  alone(solo, 0)["digest"] == r.result["digest"])
     alone.drain()
     summ.update({"slots": args.slots, "max_concurrency": srv.max_concurrency,
-                 "prim_bands": bool(args.prim_bands),
+                 "prim_bands": args.serving_rows == "bands",
                  "peak_reserved_GB": srv.peak_in_use / 2 ** 30,
                  "alone_equals_mix": f"{same}/8"})
     if prec == "mixed":
