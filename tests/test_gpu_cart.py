@@ -7,7 +7,7 @@ Schwarz factors and single integrals (normwise 1e-13), kept contribution
 counts (exact) and the MO integrals of LL, DC and DCG transforms
 (max|G_gpu - G_oracle| <= 1e-12 max|G_oracle|), on systems whose pair spaces
 span several 64-pair tiles with a ragged last tile, under both integral
-schedules and with directed and unique tiles.  DCB plans with p functions
+schedules, with directed and unique tiles and in the primitive-band row order.  DCB plans with p functions
 are refused (the gauge integrals take s functions only).
 """
 import numpy as np
@@ -97,7 +97,8 @@ def test_cart_transform(q, ctx, ham, tau):
 
 
 @pytest.mark.parametrize("eri_sched", [0, 1])
-@pytest.mark.parametrize("flags", [0, 1])  # 1: directed tiles (no unique-pair mirroring)
+# 1: directed tiles (no unique-pair mirroring); 8: primitive-band row order
+@pytest.mark.parametrize("flags", [0, 1, 8])
 def test_cart_schedules(q, ctx, eri_sched, flags):
     s = _sys("DC", 1e-10, seed=43)
     _check(q, ctx, s, 1e-10, flags=flags,
