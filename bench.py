@@ -438,8 +438,9 @@ def main_serving(args):
     """The request loop on a seeded Poisson stream (mean gap 20 ms); each
     request is a cluster drawn from a pool, with its own active-space size and
     Hamiltonian (DC or DCG).  Sizes are reduced ranges of the stream recipe
-    (10-40 atoms, N_L 40-160, n 8-32, so that every G fits a host staging
-    buffer); eight requests are re-run alone and compared bitwise."""
+    (10-40 atoms, N_L 40-160, n 8-32: at the recipe's full sizes one GPU is
+    saturated and the latencies would measure the queue only); eight requests
+    are re-run alone and compared bitwise."""
     runs = {prec: serving_run(args, prec) for prec in args.serving_prec.split(",")}
     first = runs[next(iter(runs))]
     line = {"metric": "serving p99 latency", "mode": "serving", "value": first["p99_ms"],
