@@ -85,6 +85,13 @@ static int64_t *prim_offsets(const orc_basis *b)
 
 static int cart_of(const orc_basis *b, int f) { return b->cart ? b->cart[f] : 0; }
 
+static int carts_valid(const orc_basis *b)
+{
+    for (int f = 0; b && b->cart && f < b->nfunc; ++f)
+        if (b->cart[f] < 0 || b->cart[f] > 9) return 0;
+    return 1;
+}
+
 static int has_p(const orc_basis *b)
 {
     for (int f = 0; b && f < b->nfunc; ++f)
@@ -92,15 +99,40 @@ static int has_p(const orc_basis *b)
     return 0;
 }
 
-/* Normalized primitives: (2a/pi)^{3/4} exp(-a r^2) for s and
- * (2a/pi)^{3/4} 2 sqrt(a) (x - A_x) exp(-a r^2) for p_x (the square of
- * x exp(-a r^2) integrates to pi^{3/2} / (2 (2a)^{5/2})).  Overlap of two
- * unnormalized primitives of one function (same centre, same Cartesian
- * factor): (pi/(a+b))^{3/2} for s, (pi/(a+b))^{3/2} / (2 (a+b)) for p. */
+/* Cartesian exponents of a function code: 0 = s; 1, 2, 3 = p_x, p_y, p_z;
+ * 4 .. 9 = d_xx, d_yy, d_zz, d_xy, d_xz, d_yz. */
+static void cart_powers(int code, int l[3])
+{
+    static const int tab[10][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {2, 0, 0},
+                                   {0, 2, 0}, {0, 0, 2}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
+    for (int k = 0; k < 3; ++k) l[k] = tab[code][k];
+}
+
+/* (2l - 1)!! for l = 0, 1, 2 */
+static double dfact(int l) { return l == 2 ? 3.0 : 1.0; }
+
+/* Normalized primitive (x-A_x)^lx (y-A_y)^ly (z-A_z)^lz exp(-a r^2) with
+ * N = (2a/pi)^{3/4} (4a)^{L/2} / sqrt((2lx-1)!! (2ly-1)!! (2lz-1)!!),
+ * L = lx + ly + lz: the square of the unnormalized primitive integrates to
+ * (pi/(2a))^{3/2} prod_k (2l_k-1)!! / (4a)^{l_k}.  Overlap of two
+ * unnormalized primitives of one function (same centre and factor),
+ * exponents a, b, p = a + b: (pi/p)^{3/2} prod_k (2l_k-1)!! / (2p)^{l_k}. */
 static double prim_norm(double a, int cart)
 {
+    int l[3];
+    cart_powers(cart, l);
     double n = pow(2.0 * a / M_PI, 0.75);
-    return cart ? n * 2.0 * sqrt(a) : n;
+    for (int k = 0; k < 3; ++k) n *= pow(4.0 * a, 0.5 * l[k]) / sqrt(dfact(l[k]));
+    return n;
+}
+
+static double prim_overlap_same(double p, int cart)
+{
+    int l[3];
+    cart_powers(cart, l);
+    double ov = pow(M_PI / p, 1.5);
+    for (int k = 0; k < 3; ++k) ov *= dfact(l[k]) / pow(2.0 * p, l[k]);
+    return ov;
 }
 
 void orc_norm_coefs(const orc_basis *b, double *out)
@@ -113,10 +145,7 @@ void orc_norm_coefs(const orc_basis *b, double *out)
             for (int64_t j = off[f]; j < off[f + 1]; ++j) {
                 double di = b->coefs[i] * prim_norm(b->exps[i], c);
                 double dj = b->coefs[j] * prim_norm(b->exps[j], c);
-                double pq = b->exps[i] + b->exps[j];
-                double ov = pow(M_PI / pq, 1.5);
-                if (c) ov /= 2.0 * pq;
-                s += di * dj * ov;
+                s += di * dj * prim_overlap_same(b->exps[i] + b->exps[j], c);
             }
         for (int64_t i = off[f]; i < off[f + 1]; ++i)
             out[i] = b->coefs[i] * prim_norm(b->exps[i], c) / sqrt(s);
@@ -224,11 +253,11 @@ double orc_prim_eri_cart(double a, const double *A, int ca, double b, const doub
                  exp(-c * d / q * rcd2);
     double T = o.rho * rpq2;
     for (int m = 0; m < 9; ++m) o.aux[m] = pre * orc_boys(m, T);
-    int la[3] = {0, 0, 0}, lb[3] = {0, 0, 0}, lc[3] = {0, 0, 0}, ld[3] = {0, 0, 0};
-    if (ca) la[ca - 1] = 1;
-    if (cb) lb[cb - 1] = 1;
-    if (cc) lc[cc - 1] = 1;
-    if (cd) ld[cd - 1] = 1;
+    int la[3], lb[3], lc[3], ld[3];
+    cart_powers(ca, la);
+    cart_powers(cb, lb);
+    cart_powers(cc, lc);
+    cart_powers(cd, ld);
     return os_eri(&o, la, lb, lc, ld);
 }
 
@@ -631,6 +660,7 @@ static int def_impl(const orc_basis *L, const orc_basis *S, const double *CL, co
     int NL = L->nfunc, NS = with_S ? S->nfunc : 0, NF = NL + NS, m = general ? n : 2 * n;
     if (NF > 64 || m > 64 || n <= 0) return -1;
     if (ham_gauge(ham) && NF > 32) return -1;
+    if (!carts_valid(L) || (with_S && !carts_valid(S))) return -1;
     if (ham_gauge(ham) && (has_p(L) || (with_S && has_p(S)))) return -1;
 
     /* combined scalar basis */
@@ -920,6 +950,7 @@ static int direct_impl(const orc_basis *L, const orc_basis *S, const double *CL,
     if (with_S && (!S || !CS)) return -1;
     if (n <= 0 || tau < 0 || ham < 0 || ham > 5) return -1;
     if (general && Vq) return -1;
+    if (!carts_valid(L) || (with_S && !carts_valid(S))) return -1;
     if (ham_gauge(ham) && (has_p(L) || (with_S && has_p(S)))) return -1;
     int NL = L->nfunc, NS = with_S ? S->nfunc : 0, m = general ? n : 2 * n;
     size_t m2 = (size_t)m * m;

@@ -7,11 +7,12 @@
  * load it.  Nothing in the product path calls it.
  *
  * Conventions (all arrays C-contiguous, FP64 unless stated):
- *   basis     contracted Cartesian Gaussians of s or p type; coefs multiply
- *             normalized primitives (2a/pi)^{3/4} exp(-a r^2) (s) or
- *             (2a/pi)^{3/4} 2 sqrt(a) (x - A_x) exp(-a r^2) (p_x, likewise
- *             p_y, p_z); each contracted function is rescaled to unit
- *             self-overlap.  Gauge-term hams (4, 5) take s functions only.
+ *   basis     contracted Cartesian Gaussians of s, p or d type; coefs
+ *             multiply normalized primitives N x^lx y^ly z^lz exp(-a r^2)
+ *             (coordinates relative to the centre), N = (2a/pi)^{3/4}
+ *             (4a)^{L/2} / sqrt((2lx-1)!! (2ly-1)!! (2lz-1)!!); each
+ *             contracted function is rescaled to unit self-overlap.
+ *             Gauge-term hams (4, 5) take s functions only.
  *   C         quaternion MO coefficients, planar [4][N][n]:
  *             C = C0 + i C1 + j C2 + k C3.
  *   G         quaternion MO integrals [n][n][n][n][4][4] = G^{xy}_{pqrs}
@@ -41,7 +42,8 @@ typedef struct {
     const int32_t *nprim;  /* [nfunc] */
     const double *exps;    /* [sum nprim] */
     const double *coefs;   /* [sum nprim] */
-    const int32_t *cart;   /* [nfunc] 0 = s, 1, 2, 3 = p_x, p_y, p_z; NULL = all s */
+    const int32_t *cart;   /* [nfunc] 0 = s, 1, 2, 3 = p_x, p_y, p_z, 4 .. 9 = d_xx,
+                              d_yy, d_zz, d_xy, d_xz, d_yz; NULL = all s */
 } orc_basis;
 
 typedef struct {
@@ -65,7 +67,7 @@ double orc_boys(int m, double T);
  * each contracted function has unit norm; out has sum(nprim) entries. */
 void orc_norm_coefs(const orc_basis *b, double *out);
 /* Primitive ERI over unnormalized Cartesian Gaussians: centre X, exponent x,
- * cartesian code cx (0 = s, 1..3 = p_x, p_y, p_z), Obara-Saika recursion. */
+ * cartesian code cx (as in orc_basis.cart), Obara-Saika recursion. */
 double orc_prim_eri_cart(double a, const double *A, int ca, double b, const double *B, int cb,
                          double c, const double *C, int cc, double d, const double *D, int cd);
 

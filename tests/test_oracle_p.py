@@ -1,4 +1,4 @@
-"""Pins of the oracle's p-type (Cartesian l = 1) integrals (CPU only).
+"""Pins of the oracle's p- and d-type (Cartesian l = 1, 2) integrals (CPU only).
 
 The oracle evaluates integrals with p functions by the Obara-Saika
 recursion.  These tests tie that recursion to facts it does not compute
@@ -15,7 +15,11 @@ itself:
   maps p_x to p_y and p_y to -p_x, so the MO integrals of the rotated system,
   with the coefficient rows of the p_y functions negated, are those of the
   original system (a wrong index or sign in the recursion breaks this);
-* the Schwarz inequality holds for the contracted p-type integrals.
+* the Schwarz inequality holds for the contracted p-type integrals;
+* d functions likewise: a d primitive is a centre derivative of a p primitive
+  ((x-A_x)(y-A_y) e = (1/2a) d/dA_y [(x-A_x) e], and (x-A_x)^2 e adds the s
+  term), unit self-overlap by quadrature, and rotation invariance of LL and DC
+  transforms over s, p and d functions.
 
 A dropped term of the recursion (the a_i/(2p) or c_i/(2(p+q)) terms, the
 horizontal transfer) changes the value at the first order the finite
@@ -160,3 +164,127 @@ def test_gauge_hams_refuse_p_functions():
     sy = wl.sp_cluster(seed=9, n_atoms=2, edge=3.0, nprim=(1, 1), n=2, ham="DC")
     with pytest.raises(ValueError):
         oracle.transform_direct(sy.L, sy.S, sy.CL, sy.CS, ham="DCB")
+
+
+# --------------------------------------------------------------------------
+# d functions (codes 4..9 = d_xx, d_yy, d_zz, d_xy, d_xz, d_yz)
+# --------------------------------------------------------------------------
+
+# d code -> (p code it comes from, derivative direction, adds the s term):
+# (x-A_x)(y-A_y) e = (1/2a) d/dA_y [(x-A_x) e];
+# (x-A_x)^2 e = (1/2a) (d/dA_x [(x-A_x) e] + e)
+D_FROM_P = {4: (1, 0, True), 5: (2, 1, True), 6: (3, 2, True),
+            7: (1, 1, False), 8: (1, 2, False), 9: (2, 2, False)}
+
+
+@pytest.mark.parametrize("geom", ["generic", "shared_centres"])
+def test_d_integrals_are_centre_derivatives_of_p(geom):
+    rng = np.random.default_rng({"generic": 21, "shared_centres": 22}[geom])
+    h = 1e-4
+    worst = 0.0
+    for trial in range(240):
+        ex = list(rng.uniform(0.3, 2.5, 4))
+        if geom == "generic":
+            cen = [rng.uniform(-1.2, 1.2, 3) for _ in range(4)]
+        else:
+            A, C = rng.uniform(-1.2, 1.2, 3), rng.uniform(-1.2, 1.2, 3)
+            cen = [A, A.copy(), C, C.copy()]
+        cs = [int(x) for x in rng.integers(0, 10, 4)]
+        slot = int(rng.integers(0, 4))
+        if cs[slot] < 4:
+            cs[slot] = int(rng.integers(4, 10))
+        pcode, comp, add_s = D_FROM_P[cs[slot]]
+        lower = list(cs)
+        lower[slot] = pcode
+
+        def shifted(d):
+            c2 = [x.copy() for x in cen]
+            c2[slot][comp] += d
+            return _pe(ex, c2, lower)
+
+        fd = (shifted(h) - shifted(-h)) / (2 * h)
+        if add_s:
+            s_codes = list(cs)
+            s_codes[slot] = 0
+            fd += _pe(ex, cen, s_codes)
+        fd /= 2 * ex[slot]
+        an = _pe(ex, cen, cs)
+        scale = max(abs(_pe(ex, cen, [0, 0, 0, 0])), abs(an))
+        worst = max(worst, abs(fd - an) / scale)
+    assert worst < 1e-6, worst
+
+
+def test_d_normalization_by_quadrature():
+    t, w = np.polynomial.hermite.hermgauss(20)
+    powers = {4: (2, 0, 0), 5: (0, 2, 0), 6: (0, 0, 2), 7: (1, 1, 0), 8: (1, 0, 1), 9: (0, 1, 1)}
+    rng = np.random.default_rng(23)
+    k = 3
+    exps = np.tile(10.0 ** rng.uniform(-1, 1, k), 6)
+    coefs = np.tile(rng.uniform(0.1, 1.0, k), 6)
+    b = wl.Basis(np.zeros((6, 3)), np.full(6, k, np.int32), exps, coefs,
+                 np.arange(4, 10, dtype=np.int32))
+    nc = oracle.norm_coefs(b)
+    off = b.offsets()
+    for f in range(6):
+        e, c = b.exps[off[f]:off[f + 1]], nc[off[f]:off[f + 1]]
+        tot = 0.0
+        for i in range(k):
+            for j in range(k):
+                s = e[i] + e[j]
+                # int y^(2l) e^{-s y^2} dy = s^{-(2l+1)/2} sum_k w_k t_k^(2l)
+                tot += c[i] * c[j] * np.prod([(w * t ** (2 * l)).sum() / s ** (l + 0.5)
+                                              for l in powers[4 + f]])
+        assert tot == pytest.approx(1.0, rel=1e-13)
+
+
+def _rotated_spd(L, C):
+    """Quarter turn about z: the image of x^lx y^ly z^lz on A is
+    (-1)^ly x^ly y^lx z^lz on RA."""
+    R = np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    pw = {0: (0, 0, 0), 1: (1, 0, 0), 2: (0, 1, 0), 3: (0, 0, 1), 4: (2, 0, 0), 5: (0, 2, 0),
+          6: (0, 0, 2), 7: (1, 1, 0), 8: (1, 0, 1), 9: (0, 1, 1)}
+    code_of = {v: k for k, v in pw.items()}
+    new = np.array([code_of[(pw[c][1], pw[c][0], pw[c][2])] for c in L.cart], np.int32)
+    sign = np.array([(-1.0) ** pw[c][1] for c in L.cart])
+    L2 = wl.Basis(np.ascontiguousarray(L.centers @ R.T), L.nprim.copy(), L.exps.copy(),
+                  L.coefs.copy(), new)
+    return L2, np.ascontiguousarray(C * sign[None, :, None])
+
+
+def _spd_basis(rng, atoms, nprim):
+    cen, npr, ex, co, cart = [], [], [], [], []
+    for a in atoms:
+        for codes in ((0,), (1, 2, 3), (4, 5, 6, 7, 8, 9)):
+            e = 10.0 ** rng.uniform(-1, 1, nprim)
+            c = rng.uniform(0.1, 1.0, nprim)
+            for code in codes:
+                cen.append(a); npr.append(nprim); ex.append(e); co.append(c); cart.append(code)
+    return wl.Basis(np.array(cen), np.array(npr, np.int32), np.concatenate(ex),
+                    np.concatenate(co), np.array(cart, np.int32))
+
+
+@pytest.mark.parametrize("ham", ["LL", "DC"])
+def test_spd_transform_invariant_under_rotation(ham):
+    rng = np.random.default_rng(24)
+    atoms = rng.uniform(0, 3.0, (2, 3))
+    L = _spd_basis(rng, atoms, 1)
+    S = _spd_basis(rng, atoms, 1) if ham == "DC" else None
+    NL, NS = L.nfunc, (S.nfunc if S is not None else 0)
+    Q = wl.quat_qr_plus(rng.standard_normal((4, NL + NS, 3)))
+    CL = np.ascontiguousarray(Q[:, :NL])
+    CS = np.ascontiguousarray(Q[:, NL:]) if S is not None else None
+    G = oracle.transform_direct(L, S, CL, CS, ham=ham)[0]
+    L2, CL2 = _rotated_spd(L, CL)
+    S2, CS2 = _rotated_spd(S, CS) if S is not None else (None, None)
+    G2 = oracle.transform_direct(L2, S2, CL2, CS2, ham=ham)[0]
+    scale = np.abs(G).max()
+    assert np.abs(G2 - G).max() <= 1e-12 * scale
+    bad = oracle.transform_direct(L2, S2, CL, CS, ham=ham)[0]
+    assert np.abs(bad - G).max() > 1e-3 * scale
+
+
+def test_invalid_cart_codes_are_refused():
+    b = wl.Basis(np.zeros((1, 3)), np.ones(1, np.int32), np.ones(1), np.ones(1),
+                 np.array([10], np.int32))
+    with pytest.raises(ValueError):
+        oracle.transform_direct(b, None, np.ones((4, 1, 1)), None, ham="LL")
