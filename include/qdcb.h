@@ -127,6 +127,28 @@ qdcb_status qdcb_basis_create_cart(qdcb_ctx *ctx, int32_t nfunc, const double *c
                                    qdcb_basis **out);
 void qdcb_basis_destroy(qdcb_basis *basis);
 
+/* Restricted kinetic balance (Eq. RKB): chi^S_{mu tau} = (1/2c) (sigma . p)
+ * chi^L_{mu tau}, so the small component of a two-spinor is, per spin
+ * component, a combination of the 3 N gradient functions d_K chi_mu
+ * (K = x, y, z), which are p functions for s-type chi_mu.
+ * qdcb_basis_create_rkb builds them as a basis of 3 nfunc(L) normalized
+ * Cartesian p functions (function 3 mu + K on chi_mu's centre), with
+ * norms[3 mu + K] = ||d_K chi_mu|| (host, caller-owned, may be NULL).  L must
+ * be s-only (QDCB_E_UNSUPPORTED otherwise); 3 nfunc <= 65535.  A general
+ * two-spinor DC plan (QDCB_PLAN_SPINOR) with L and this basis as S then gives
+ * the four-component Dirac-Coulomb integrals of RKB spinors (all classes of
+ * Eq. DCInt, with their 1/(2c^2) and 1/(8c^4) factors). */
+qdcb_status qdcb_basis_create_rkb(qdcb_ctx *ctx, const qdcb_basis *L, double *norms,
+                                  qdcb_basis **out);
+/* Small-component planes over that gradient basis: out [4][3 nfunc][m]
+ * (alpha re, alpha im, beta re, beta im; function 3 mu + K) from the RKB
+ * coefficients PS [4][nfunc][m] of m two-spinors (same plane layout), the
+ * norms of qdcb_basis_create_rkb and the speed of light c:
+ * out_{(mu K) u} = (-i / 2c) norms[3 mu + K] sum_tau (sigma_K)_{u tau} PS_{mu tau}.
+ * Host arrays, host arithmetic (no device work). */
+qdcb_status qdcb_rkb_small_planes(int32_t nfunc, int32_t m, const double *PS,
+                                  const double *norms, double c, double *out);
+
 /* Schwarz factors of the basis's own function pairs: Q[mu][nu] (host,
  * [nfunc][nfunc], symmetric). */
 qdcb_status qdcb_basis_schwarz(const qdcb_basis *basis, double *Q);

@@ -20,12 +20,32 @@ evaluates an integral itself.
 """
 from __future__ import annotations
 
+import dataclasses
+
 import numpy as np
 
 import oracle
-from paper_2606_04316_amd import workloads as wl
 
-SPEED_OF_LIGHT = wl.SPEED_OF_LIGHT
+SPEED_OF_LIGHT = 137.035999074  # a.u., the value the paper's Sec. 3 quotes
+
+
+@dataclasses.dataclass
+class _Basis:
+    """Basis record in the layout the oracle's ctypes wrapper reads."""
+    centers: np.ndarray
+    nprim: np.ndarray
+    exps: np.ndarray
+    coefs: np.ndarray
+    cart: np.ndarray
+
+    @property
+    def nfunc(self) -> int:
+        return int(self.nprim.shape[0])
+
+    def offsets(self) -> np.ndarray:
+        off = np.zeros(self.nfunc + 1, dtype=np.int64)
+        np.cumsum(self.nprim, out=off[1:])
+        return off
 
 # Pauli matrices as printed in the paper's notation section
 PAULI = (np.array([[0, 1], [1, 0]], dtype=complex),
@@ -40,7 +60,8 @@ def gradient_basis(L):
     if getattr(L, "cart", None) is not None and np.any(np.asarray(L.cart) != 0):
         raise ValueError("RKB gradients are built for s functions")
     nc = oracle.norm_coefs(L)  # chi_mu = sum_i nc_i exp(-a_i r^2)
-    off = L.offsets()
+    off = np.zeros(L.nfunc + 1, dtype=np.int64)
+    np.cumsum(np.asarray(L.nprim), out=off[1:])
     cen, npr, ex, co, cart = [], [], [], [], []
     for mu in range(L.nfunc):
         a = L.exps[off[mu]:off[mu + 1]]
@@ -52,9 +73,9 @@ def gradient_basis(L):
             ex.append(a)
             co.append(w / pnorm)
             cart.append(K + 1)
-    G = wl.Basis(np.ascontiguousarray(np.array(cen)), np.array(npr, np.int32),
-                 np.ascontiguousarray(np.concatenate(ex)),
-                 np.ascontiguousarray(np.concatenate(co)), np.array(cart, np.int32))
+    G = _Basis(np.ascontiguousarray(np.array(cen)), np.array(npr, np.int32),
+               np.ascontiguousarray(np.concatenate(ex)),
+               np.ascontiguousarray(np.concatenate(co)), np.array(cart, np.int32))
     ncg = oracle.norm_coefs(G)
     offg = G.offsets()
     norms = np.array([G.coefs[offg[f]] * (2 * G.exps[offg[f]] / np.pi) ** 0.75 *
@@ -77,10 +98,11 @@ def small_component_planes(PS: np.ndarray, norms: np.ndarray, c: float) -> np.nd
 
 
 def transform_rkb(L, PL: np.ndarray, PS: np.ndarray, c: float = SPEED_OF_LIGHT,
-                  tau: float = 0.0):
-    """Four-component Dirac-Coulomb MO integrals (ab|cd) [m]^4 (complex) of
-    general two-spinors with large-component planes PL [4][N][m] over L and
-    RKB small-component planes PS [4][N][m] (N_S = N_L)."""
+                  tau: float = 0.0, ham: str = "DC"):
+    """Four-component MO integrals (ab|cd) [m]^4 (complex) of general
+    two-spinors with large-component planes PL [4][N][m] over L and RKB
+    small-component planes PS [4][N][m] (N_S = N_L): Dirac-Coulomb (ham "DC")
+    or with the Gaunt term ("DCG")."""
     G, norms = gradient_basis(L)
     PG = small_component_planes(PS, norms, c)
-    return oracle.transform_spinor(L, G, PL, PG, "DC", tau)[0]
+    return oracle.transform_spinor(L, G, PL, PG, ham, tau)[0]

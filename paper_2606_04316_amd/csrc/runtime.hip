@@ -298,6 +298,81 @@ void qdcb_basis_destroy(qdcb_basis *b) {
   qdcb_ctx::release_ref(ctx);
 }
 
+qdcb_status qdcb_basis_create_rkb(qdcb_ctx *ctx, const qdcb_basis *L, double *norms,
+                                  qdcb_basis **out) {
+  return guarded([&] {
+    if (!ctx || !L || !out) fail(QDCB_E_INVALID, "NULL argument");
+    if (L->has_p()) fail(QDCB_E_UNSUPPORTED, "gradient bases are built for s functions");
+    if (3LL * L->nfunc > 65535) fail(QDCB_E_INVALID, "3 nfunc must be at most 65535");
+    DeviceGuard g(L->ctx->device);
+    const int N = L->nfunc, np = L->first[N];
+    std::vector<double> cent(3 * (size_t)N), a(np), nc(np);
+    HIPC(hipMemcpy(cent.data(), L->cent.p, cent.size() * sizeof(double), hipMemcpyDeviceToHost));
+    HIPC(hipMemcpy(a.data(), L->exps.p, np * sizeof(double), hipMemcpyDeviceToHost));
+    HIPC(hipMemcpy(nc.data(), L->nc.p, np * sizeof(double), hipMemcpyDeviceToHost));
+    // d/dr_K chi_mu = sum_i w_i (r_K - A_K) exp(-a_i r^2), w_i = -2 a_i nc_i; as
+    // coefficients of normalized p primitives (2a/pi)^{3/4} 2 sqrt(a) (r_K - A_K) ...
+    std::vector<double> gc(9 * (size_t)N), ge(3 * (size_t)np), gco(3 * (size_t)np);
+    std::vector<int32_t> gn(3 * (size_t)N), gcart(3 * (size_t)N);
+    std::vector<double> nrm(3 * (size_t)N);
+    size_t o = 0;
+    for (int mu = 0; mu < N; ++mu) {
+      const int i0 = L->first[mu], i1 = L->first[mu + 1];
+      // ||d_K chi_mu||^2 = sum_ij w_i w_j (pi/(a_i+a_j))^{3/2} / (2 (a_i+a_j))
+      double n2 = 0.0;
+      for (int i = i0; i < i1; ++i)
+        for (int j = i0; j < i1; ++j) {
+          const double p = a[i] + a[j];
+          n2 += 4.0 * a[i] * nc[i] * a[j] * nc[j] * std::pow(PI / p, 1.5) / (2.0 * p);
+        }
+      for (int K = 0; K < 3; ++K) {
+        const int f = 3 * mu + K;
+        for (int k = 0; k < 3; ++k) gc[3 * (size_t)f + k] = cent[3 * (size_t)mu + k];
+        gn[f] = i1 - i0;
+        gcart[f] = K + 1;
+        nrm[f] = std::sqrt(n2);
+        for (int i = i0; i < i1; ++i, ++o) {
+          ge[o] = a[i];
+          const double pn = std::pow(2.0 * a[i] / PI, 0.75) * 2.0 * std::sqrt(a[i]);
+          gco[o] = -2.0 * a[i] * nc[i] / pn;
+        }
+      }
+    }
+    const qdcb_status st = qdcb_basis_create_cart(ctx, 3 * N, gc.data(), gn.data(), ge.data(),
+                                                  gco.data(), gcart.data(), out);
+    if (st != QDCB_OK) fail(st, g_err);
+    if (norms) std::copy(nrm.begin(), nrm.end(), norms);
+  });
+}
+
+qdcb_status qdcb_rkb_small_planes(int32_t nfunc, int32_t m, const double *PS,
+                                  const double *norms, double c, double *out) {
+  return guarded([&] {
+    if (!PS || !norms || !out) fail(QDCB_E_INVALID, "NULL argument");
+    if (nfunc < 1 || m < 1) fail(QDCB_E_INVALID, "nfunc and m must be positive");
+    if (!(c > 0) || !std::isfinite(c)) fail(QDCB_E_INVALID, "c must be positive");
+    const size_t N = nfunc, M = m, G = 3 * N;
+    auto at = [&](int plane, size_t f, size_t a) { return PS[(plane * N + f) * M + a]; };
+    const double h = 0.5 / c;  // the factor -i / 2c is applied as h * (-i)
+    for (size_t mu = 0; mu < N; ++mu)
+      for (size_t a = 0; a < M; ++a) {
+        const double ar = at(0, mu, a), ai = at(1, mu, a);  // C^S_{mu alpha}
+        const double br = at(2, mu, a), bi = at(3, mu, a);  // C^S_{mu beta}
+        // sigma_K (C_alpha, C_beta): x -> (C_b, C_a); y -> (-i C_b, i C_a); z -> (C_a, -C_b)
+        const double sr[3][2] = {{br, ar}, {bi, -ai}, {ar, -br}};   // real parts
+        const double si[3][2] = {{bi, ai}, {-br, ar}, {ai, -bi}};   // imaginary parts
+        for (int K = 0; K < 3; ++K) {
+          const double w = h * norms[3 * mu + K];
+          for (int u = 0; u < 2; ++u) {
+            // (-i)(x + i y) = y - i x
+            out[((2 * u) * G + 3 * mu + K) * M + a] = w * si[K][u];
+            out[((2 * u + 1) * G + 3 * mu + K) * M + a] = -w * sr[K][u];
+          }
+        }
+      }
+  });
+}
+
 qdcb_status qdcb_basis_schwarz(const qdcb_basis *b, double *Q) {
   return guarded([&] {
     if (!b || !Q) fail(QDCB_E_INVALID, "NULL argument");

@@ -118,6 +118,9 @@ def lib():
         L.qdcb_basis_create.argtypes = [_P, ctypes.c_int32, _DP, _IP, _DP, _DP, ctypes.POINTER(_P)]
         L.qdcb_basis_create_cart.argtypes = [_P, ctypes.c_int32, _DP, _IP, _DP, _DP, _IP,
                                              ctypes.POINTER(_P)]
+        L.qdcb_basis_create_rkb.argtypes = [_P, _P, _DP, ctypes.POINTER(_P)]
+        L.qdcb_rkb_small_planes.argtypes = [ctypes.c_int32, ctypes.c_int32, _DP, _DP,
+                                            ctypes.c_double, _DP]
         L.qdcb_basis_destroy.argtypes = [_P]
         L.qdcb_basis_destroy.restype = None
         L.qdcb_basis_schwarz.argtypes = [_P, _DP]
@@ -147,6 +150,7 @@ def lib():
         L.qdcb_plan_autotune.argtypes = [_P, _P, _P, _P, ctypes.c_uint32, _P, ctypes.c_char_p,
                                          ctypes.POINTER(TuneReport)]
         for f in ("qdcb_ctx_create", "qdcb_basis_create", "qdcb_basis_create_cart",
+                  "qdcb_basis_create_rkb", "qdcb_rkb_small_planes",
                   "qdcb_basis_schwarz",
                   "qdcb_eri_quartets", "qdcb_plan_create", "qdcb_plan_footprint",
                   "qdcb_transform", "qdcb_plan_fetch", "qdcb_plan_estimate",
@@ -231,6 +235,31 @@ class Basis:
             self.close()
         except Exception:
             pass
+
+
+def rkb_basis(ctx: Context, L: "Basis"):
+    """(gradient basis of 3 nfunc p functions, norms) for RKB small components
+    (qdcb_basis_create_rkb)."""
+    b = Basis.__new__(Basis)
+    b.ctx = ctx
+    b.nfunc = 3 * L.nfunc
+    norms = np.empty(3 * L.nfunc)
+    h = _P()
+    _check(lib().qdcb_basis_create_rkb(ctx.h, L.h, norms.ctypes.data_as(_DP), ctypes.byref(h)))
+    b.h = h
+    return b, norms
+
+
+def rkb_small_planes(PS: np.ndarray, norms: np.ndarray, c: float) -> np.ndarray:
+    """Small-component planes [4][3 N][m] over the gradient basis from RKB
+    planes PS [4][N][m] (qdcb_rkb_small_planes)."""
+    PS = _f64(PS)
+    N, m = PS.shape[1], PS.shape[2]
+    norms = _f64(norms)
+    out = np.empty((4, 3 * N, m))
+    _check(lib().qdcb_rkb_small_planes(N, m, PS.ctypes.data_as(_DP), norms.ctypes.data_as(_DP),
+                                       float(c), out.ctypes.data_as(_DP)))
+    return out
 
 
 def tune_cache_lookup(path: str, key: str) -> Optional[dict]:
