@@ -137,14 +137,28 @@ def main_transform(args):
 
     args.workload = args.workload or "chain40"
     # "<name>_spinor": the same basis with 2 n general two-spinor MOs (the
-    # system's Kramers pairs mixed by a seeded unitary), a QDCB_PLAN_SPINOR plan
-    spinor = args.workload.endswith("_spinor")
-    sysm = wl.config(args.workload[:-len("_spinor")] if spinor else args.workload)
-    n = 2 * sysm.n_mo if spinor else sysm.n_mo
+    # system's Kramers pairs mixed by a seeded unitary), a QDCB_PLAN_SPINOR plan.
+    # "<name>_rkb": the system's L basis with RKB small components (its
+    # gradient basis as S) and n general two-spinors, a QDCB_PLAN_SPINOR plan
+    rkb = args.workload.endswith("_rkb")
+    spinor = args.workload.endswith("_spinor") or rkb
+    base = args.workload[:-len("_spinor")] if args.workload.endswith("_spinor") else \
+        args.workload[:-len("_rkb")] if rkb else args.workload
+    sysm = wl.config(base)
+    n = sysm.n_mo if rkb else 2 * sysm.n_mo if spinor else sysm.n_mo
     dev = torch.device("cuda:0")
     # output and inputs first: the context's default budget is a share of
     # what is free when it is created
-    if spinor:
+    if rkb:
+        # n orthonormal general two-spinors over the L and RKB S coefficients
+        # (QR of a Gaussian quaternion matrix, its Kramers pairs mixed)
+        NLr = sysm.L.nfunc
+        Q = wl.quat_qr_plus(wl.gaussian_quat(np.random.default_rng(8000), 2 * NLr, n // 2))
+        U = wl.random_unitary(np.random.default_rng(8001), n, n)
+        PL = wl.mix_spinors(wl.quat_to_spinor_planes(np.ascontiguousarray(Q[:, :NLr])), U)
+        PS = wl.mix_spinors(wl.quat_to_spinor_planes(np.ascontiguousarray(Q[:, NLr:])), U)
+        G = torch.empty((n, n, n, n, 2), dtype=torch.float64, device=dev)
+    elif spinor:
         PL, PS, _ = wl.general_spinors(sysm, n, seed=0)
         G = torch.empty((n, n, n, n, 2), dtype=torch.float64, device=dev)
     else:
@@ -154,7 +168,11 @@ def main_transform(args):
     CS = torch.from_numpy(PS).to(dev) if PS is not None else None
     ctx = qdcb.Context(0)
     L = qdcb.Basis(ctx, sysm.L)
-    S = qdcb.Basis(ctx, sysm.S) if sysm.S is not None else None
+    if rkb:
+        S, norms = qdcb.rkb_basis(ctx, L)
+        CS = torch.from_numpy(qdcb.rkb_small_planes(PS, norms, wl.SPEED_OF_LIGHT)).to(dev)
+    else:
+        S = qdcb.Basis(ctx, sysm.S) if sysm.S is not None else None
     plan = qdcb.Plan(ctx, L, S, sysm.ham, n, sysm.tau,
                      flags=(qdcb.PLAN_SPINOR if spinor else 0) |
                      (qdcb.PLAN_PRIM_BANDS if args.prim_bands else 0))
@@ -206,15 +224,18 @@ def main_transform(args):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": sysm.name + ("_spinor" if spinor else ""),
+        "config": {"workload": sysm.name + ("_rkb" if rkb else "_spinor" if spinor else ""),
                    "n_atoms": int(sysm.atoms.shape[0]),
-                   "N_L": sysm.L.nfunc, "N_S": sysm.S.nfunc if sysm.S is not None else 0,
+                   "N_L": sysm.L.nfunc,
+                   "N_S": 3 * sysm.L.nfunc if rkb else
+                   sysm.S.nfunc if sysm.S is not None else 0,
                    "n_mo": n, "mo_kind": "general spinors" if spinor else "Kramers pairs",
                    "ham": sysm.ham, "tau": sysm.tau,
                    "algorithm": f"MO-driven, {args.mo_batch} MO pairs per batch"
                    if args.mo_batch else "AO-driven",
                    "row_order": "primitive bands" if args.prim_bands else "Schwarz",
-                   "shells": "s, p" if getattr(sysm.L, "cart", None) is not None else "s"},
+                   "shells": "s, p" if getattr(sysm.L, "cart", None) is not None else "s",
+                   "small_components": "RKB (gradient basis)" if rkb else "stand-in basis"},
         "spinor_integrals_per_s": (n if spinor else 2 * n) ** 4 * args.steps / elapsed,
         "stages_ms": {k: st0[k] for k in ("ms_density", "ms_screen", "ms_eri", "ms_first_half",
                                           "ms_second_half", "ms_total")},
