@@ -134,7 +134,8 @@ void qdcb_basis_destroy(qdcb_basis *basis);
  * qdcb_basis_create_rkb builds them as a basis of 3 nfunc(L) normalized
  * Cartesian p functions (function 3 mu + K on chi_mu's centre), with
  * norms[3 mu + K] = ||d_K chi_mu|| (host, caller-owned, may be NULL).  L must
- * be s-only (QDCB_E_UNSUPPORTED otherwise); 3 nfunc <= 65535.  A general
+ * be s-only (QDCB_E_UNSUPPORTED otherwise) and on ctx's device
+ * (QDCB_E_INVALID otherwise); 3 nfunc <= 65535.  A general
  * two-spinor DC plan (QDCB_PLAN_SPINOR) with L and this basis as S then gives
  * the four-component Dirac-Coulomb integrals of RKB spinors (all classes of
  * Eq. DCInt, with their 1/(2c^2) and 1/(8c^4) factors). */

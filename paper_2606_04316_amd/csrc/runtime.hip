@@ -302,6 +302,7 @@ qdcb_status qdcb_basis_create_rkb(qdcb_ctx *ctx, const qdcb_basis *L, double *no
                                   qdcb_basis **out) {
   return guarded([&] {
     if (!ctx || !L || !out) fail(QDCB_E_INVALID, "NULL argument");
+    if (L->ctx->device != ctx->device) fail(QDCB_E_INVALID, "basis on another device");
     if (L->has_p()) fail(QDCB_E_UNSUPPORTED, "gradient bases are built for s functions");
     if (3LL * L->nfunc > 65535) fail(QDCB_E_INVALID, "3 nfunc must be at most 65535");
     DeviceGuard g(L->ctx->device);
