@@ -2,8 +2,9 @@
  * two-electron integral transformation (arXiv 2606.04316).
  *
  * The library implements the paper's AO-driven direct transformation
- * (Sec. 2.4): scalar AO two-electron integrals over s-type contracted
- * Gaussians are generated on the GPU, filtered by the quaternion-density-
+ * (Sec. 2.4): scalar AO two-electron integrals over contracted Cartesian
+ * Gaussians (s and p functions; restricted-kinetic-balance gradient functions
+ * for the small component, Eq. RKB) are generated on the GPU, filtered by the quaternion-density-
  * weighted Cauchy-Schwarz bound (Sec. 2.5, Eq. SchwarzDen), contracted with
  * quaternion MO-pair densities in the first half (Eq. firsthalf, Eqs. Den and
  * QuaternionScatter) and with the MO coefficients in the second half
@@ -17,8 +18,11 @@
  *     On error no output buffer has been written and qdcb_last_error()
  *     returns a message for the calling thread.  No C++ exception crosses
  *     this boundary.
- *   - Basis: s-type contracted Gaussians.  coefs multiply normalized
- *     primitives (2a/pi)^{3/4} exp(-a r^2); the library rescales every
+ *   - Basis: contracted Gaussians, s type (qdcb_basis_create) or Cartesian s
+ *     and p components (qdcb_basis_create_cart), and the gradient functions of
+ *     an s basis as the restricted-kinetic-balance small-component basis
+ *     (qdcb_basis_create_rkb).  coefs multiply normalized primitives
+ *     ((2a/pi)^{3/4} exp(-a r^2) for s); the library rescales every
  *     contracted function to unit self-overlap.  Bohr units.
  *   - MO coefficients (Eqs. Lspinor, Sspinor in the Kramers-paired quaternion
  *     form): planar float64 [4][N][n_mo], C = C0 + i C1 + j C2 + k C3.

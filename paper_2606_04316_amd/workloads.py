@@ -154,32 +154,39 @@ def make_basis(rng: np.random.Generator, atoms: np.ndarray, nfunc: int,
     return Basis(centers, k, np.ascontiguousarray(exps), np.ascontiguousarray(coefs))
 
 
-def overlap_matrix(A: Basis, B: Basis) -> np.ndarray:
-    """Overlap of the normalized contracted s functions of A and B (input
-    construction only: Loewdin orthonormalization of the MO coefficients)."""
-    def normalized_coefs(b: Basis):
-        off = b.offsets()
-        out = np.empty_like(b.coefs)
-        for f in range(b.nfunc):
-            a = b.exps[off[f]:off[f + 1]]
-            d = b.coefs[off[f]:off[f + 1]] * (2.0 * a / math.pi) ** 0.75
-            s = (d[:, None] * d[None, :] * (math.pi / (a[:, None] + a[None, :])) ** 1.5).sum()
-            out[off[f]:off[f + 1]] = d / math.sqrt(s)
-        return out
+def _normalized_coefs(b: Basis) -> np.ndarray:
+    """Contraction coefficients of normalized primitives (2a/pi)^{3/4} e^{-a r^2}
+    rescaled so that each contracted s function has unit self-overlap."""
+    off = b.offsets()
+    out = np.empty_like(b.coefs)
+    for f in range(b.nfunc):
+        a = b.exps[off[f]:off[f + 1]]
+        d = b.coefs[off[f]:off[f + 1]] * (2.0 * a / math.pi) ** 0.75
+        s = (d[:, None] * d[None, :] * (math.pi / (a[:, None] + a[None, :])) ** 1.5).sum()
+        out[off[f]:off[f + 1]] = d / math.sqrt(s)
+    return out
 
-    ca, cb = normalized_coefs(A), normalized_coefs(B)
+
+def overlap_matrix(A: Basis, B: Basis, block: int = 2048) -> np.ndarray:
+    """Overlap of the normalized contracted s functions of A and B (input
+    construction only: Loewdin orthonormalization of the MO coefficients):
+    primitive overlaps d_i d_j (pi/p)^{3/2} exp(-a_i b_j R^2 / p), summed over
+    each function's primitives (blocks of A's primitives at a time)."""
+    ca, cb = _normalized_coefs(A), _normalized_coefs(B)
     oa, ob = A.offsets(), B.offsets()
-    S = np.empty((A.nfunc, B.nfunc))
-    for i in range(A.nfunc):
-        ai = A.exps[oa[i]:oa[i + 1]]
-        di = ca[oa[i]:oa[i + 1]]
-        for j in range(B.nfunc):
-            bj = B.exps[ob[j]:ob[j + 1]]
-            dj = cb[ob[j]:ob[j + 1]]
-            r2 = float(((A.centers[i] - B.centers[j]) ** 2).sum())
-            p = ai[:, None] + bj[None, :]
-            S[i, j] = (di[:, None] * dj[None, :] * (math.pi / p) ** 1.5
-                       * np.exp(-ai[:, None] * bj[None, :] / p * r2)).sum()
+    fa = np.repeat(np.arange(A.nfunc), np.diff(oa))  # function of each primitive
+    fb = np.repeat(np.arange(B.nfunc), np.diff(ob))
+    PA, PB = A.centers[fa], B.centers[fb]
+    S = np.zeros((A.nfunc, B.nfunc))
+    for i0 in range(0, fa.shape[0], block):
+        i1 = min(fa.shape[0], i0 + block)
+        a = A.exps[i0:i1, None]
+        p = a + B.exps[None, :]
+        r2 = ((PA[i0:i1, None, :] - PB[None, :, :]) ** 2).sum(-1)
+        prim = (ca[i0:i1, None] * cb[None, :] * (math.pi / p) ** 1.5
+                * np.exp(-a * B.exps[None, :] / p * r2))
+        byfunc = np.add.reduceat(prim, ob[:-1], axis=1) if B.nfunc else prim[:, :0]
+        np.add.at(S, fa[i0:i1], byfunc)
     return S
 
 
@@ -260,44 +267,71 @@ def ball(rng, n_atoms: int, radius: float, min_sep: float) -> np.ndarray:
 # named workloads
 # ----------------------------------------------------------------------------
 
+def qr_coefficients(rng: np.random.Generator, L: Basis, S: Optional[Basis], n: int):
+    """C = QR+(G): a random quaternion-orthonormal (N_L + N_S) x n matrix (the
+    positive-diagonal quaternion QR of a Gaussian quaternion matrix), split
+    into its L and S rows; not orthonormal in the AO metric, which the
+    transformation does not need.  |C_mu p| <= 1, so the MO integrals are
+    not small differences of large terms (well-conditioned inputs)."""
+    NL = L.nfunc
+    NS = S.nfunc if S is not None else 0
+    Q = quat_qr_plus(gaussian_quat(rng, NL + NS, n))
+    CL = np.ascontiguousarray(Q[:, :NL])
+    CS = np.ascontiguousarray(Q[:, NL:]) if S is not None else None
+    return CL, CS
+
+
+def _coefficients(kind: str, rng, L, S, n):
+    if kind == "loewdin":
+        return loewdin_coefficients(rng, L, S, n)
+    if kind == "qr":
+        return qr_coefficients(rng, L, S, n)
+    raise ValueError(f"coefficient kind {kind!r} (loewdin or qr)")
+
+
 def _streams(seed: int):
     ss = np.random.SeedSequence(seed).spawn(4)
     return [np.random.default_rng(s) for s in ss]  # atoms, basis, C, perturbations
 
 
 def small_ll(seed: int = 1, n_atoms: int = 8, nfunc: int = 24, n: int = 12,
-             nprim: int = 3, edge: float = 6.0, tau: float = 0.0) -> System:
+             nprim: int = 3, edge: float = 6.0, tau: float = 0.0,
+             coefs: str = "loewdin") -> System:
     """Large-component-only system: ``nfunc`` s functions (3 per atom by
-    default) on atoms uniform in a cube."""
+    default) on atoms uniform in a cube.  coefs: "loewdin" (orthonormal in
+    the AO metric) or "qr" (quaternion-orthonormal, see qr_coefficients)."""
     ra, rb, rc, _ = _streams(seed)
     atoms = cube(ra, n_atoms, edge)
     L = make_basis(rb, atoms, nfunc, nprim, 0.1, 10.0)
-    CL, _ = loewdin_coefficients(rc, L, None, n)
+    CL, _ = _coefficients(coefs, rc, L, None, n)
     return System(f"ll_{nfunc}_{n}", "LL", L, None, CL, None, tau, atoms)
 
 
 def linear_chain(seed: int = 2, n_atoms: int = 40, spacing: float = 2.5,
                  nl_per_atom: int = 10, ns_per_atom: int = 20, n: int = 64,
-                 nprim=3, tau: float = 1e-10, ham: str = "DC") -> System:
+                 nprim=3, tau: float = 1e-10, ham: str = "DC",
+                 coefs: str = "loewdin") -> System:
     """Linear chain with a large-component basis and a tighter (exponents x4)
-    stand-in small-component basis of twice the size."""
+    stand-in small-component basis of twice the size (coefs as in small_ll)."""
     ra, rb, rc, _ = _streams(seed)
     atoms = chain(n_atoms, spacing)
     L = make_basis(rb, atoms, nl_per_atom * n_atoms, nprim, 0.1, 10.0)
     S = make_basis(rb, atoms, ns_per_atom * n_atoms, nprim, 0.1, 10.0, exp_scale=4.0)
-    CL, CS = loewdin_coefficients(rc, L, S, n)
+    CL, CS = _coefficients(coefs, rc, L, S, n)
     return System(f"chain{n_atoms}_{ham}_{n}", ham, L, S, CL, CS, tau, atoms)
 
 
 def cluster(seed: int = 3, n_atoms: int = 60, radius: float = 20.0, min_sep: float = 2.0,
             nl_per_atom: int = 10, ns_per_atom: int = 20, n: int = 128,
-            nprim=(1, 6), tau: float = 1e-10, ham: str = "DCG") -> System:
-    """Compact 3-D cluster with mixed contraction depth 1..6."""
+            nprim=(1, 6), tau: float = 1e-10, ham: str = "DCG",
+            coefs: str = "loewdin") -> System:
+    """Compact 3-D cluster with mixed contraction depth 1..6 (coefs as in
+    small_ll)."""
     ra, rb, rc, _ = _streams(seed)
     atoms = ball(ra, n_atoms, radius, min_sep)
     L = make_basis(rb, atoms, nl_per_atom * n_atoms, nprim, 0.1, 10.0)
     S = make_basis(rb, atoms, ns_per_atom * n_atoms, nprim, 0.1, 10.0, exp_scale=4.0)
-    CL, CS = loewdin_coefficients(rc, L, S, n)
+    CL, CS = _coefficients(coefs, rc, L, S, n)
     return System(f"cluster{n_atoms}_{ham}_{n}", ham, L, S, CL, CS, tau, atoms)
 
 

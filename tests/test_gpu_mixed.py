@@ -1,21 +1,26 @@
 """GPU tests of the mixed-precision first half (FP64 / FP32 / BF16 tiers).
 
-Tiles are assigned to a tier by their screening bound B = max Q (bra tile) x
-max Q Dmax (ket tile).  Forcing every tile into one tier checks each kernel
-path on its own: the FP64 tier run through the tier lists must equal the
-FP64 plan bitwise (same tasks, same order), the FP32 and BF16 tiers must agree
-with the FP64 result to their operand precision (relative rounding 2^-24 and
-2^-9 of each operand, FP32 accumulation), measured against the Schwarz
-magnitude bound of the sums (the same scale as the parity tests).  With the
-default tiers the error is reported and must stay within the a-priori budget
-of the low tiers.  The oracle pins the FP64 tier.
+Tiles are assigned to a tier by their bound: the screening bound
+B = max Q (bra tile) x max Q Dmax (ket tile), or with QDCB_PLAN_TIER_BY_G the
+bound B_G = max Q Dmax (bra tile) x max Q Dmax (ket tile) of a contribution's
+effect on G.  The FP64 tier run through the tier lists must equal the FP64
+plan bitwise (same tasks, same order).  The reduced tiers are checked element
+by element against an a-priori bound (tests/mixed_bound.py): the contribution
+bound decides the worst tier a contribution can land in, its rounding error is
+at most eps_tier |I| |D~| (operand unit roundoff and FP32 accumulation), and
+the second half carries it into G through the bra pair densities; the FP64
+oracle is the reference, on well-conditioned (QR) coefficients where the FP64
+part of the error is below 1e-12 of max|G|.  On the chain recipe with Loewdin
+coefficients, the tiers the benchmark reports (G rule, 1e-6 / 1e-9) must keep
+the reduced tiers' error (against the FP64 transform) below 1e-10 Eh, and on QR
+coefficients max|G - G_oracle| <= 1e-10 Eh.
 """
 import numpy as np
 import pytest
 
 import oracle
 from paper_2606_04316_amd import workloads as wl
-from tests import qalg
+from tests import mixed_bound, qalg
 
 pytestmark = pytest.mark.gpu
 
@@ -45,20 +50,6 @@ def _run(q, ctx, s, prec="fp64", t32=1e-4, t16=1e-7, flags=0):
     return G, st
 
 
-def _scale(s):
-    Qs, Cs = [oracle.schwarz(s.L)], [s.CL]
-    if s.S is not None:
-        Qs.append(oracle.schwarz(s.S))
-        Cs.append(s.CS)
-    sc = qalg.schwarz_scale(Qs, Cs)
-    if s.ham == "DCG":
-        nL = np.sqrt((s.CL ** 2).sum(0))
-        nS = np.sqrt((s.CS ** 2).sum(0))
-        a = nL.T @ oracle.schwarz(s.L, s.S) @ nS
-        sc += 3 * float(np.max(a + a.T)) ** 2
-    return sc
-
-
 def _j_occ(G):
     # occupied-block Coulomb sum over the first n/2 Kramers pairs
     occ = range(G.shape[0] // 2)
@@ -83,45 +74,97 @@ def test_fp64_tier_equals_fp64_plan(q, ctx, ham):
     assert np.array_equal(G0, G1)
 
 
+QR_SYSTEMS = {
+    "DC": lambda: wl.linear_chain(seed=60, n_atoms=8, spacing=3.0, nl_per_atom=3,
+                                  ns_per_atom=6, n=6, tau=1e-10, coefs="qr"),
+    "DCG": lambda: wl.linear_chain(seed=61, n_atoms=6, spacing=3.2, nl_per_atom=3,
+                                   ns_per_atom=4, n=5, tau=1e-10, ham="DCG", coefs="qr"),
+}
+
+
+def _check_bound(s, G, st, rule, t32, t16, what):
+    Go, so = oracle.transform_direct(s.L, s.S, s.CL, s.CS, s.ham, s.tau)
+    assert st["kept"] == so["kept"] and st["kept_gaunt"] == so["kept_gaunt"]
+    B = mixed_bound.bound(s, s.CL, s.CS, s.tau, rule, t32, t16)
+    gmax = float(np.abs(Go).max())
+    err = np.abs(mixed_bound.upper_part(G) - mixed_bound.upper_part(Go))
+    ratio = float((err / (B + 1e-12 * gmax)).max())
+    print(f"{what}: tiles {st['tiles_tier']}, max|dG| {err.max():.3e}, bound max "
+          f"{B.max():.3e}, max|G| {gmax:.3e}, worst error / bound {ratio:.3f}")
+    assert np.all(err <= B + 1e-12 * gmax), what
+    return float(err.max()), float(B.max())
+
+
 @pytest.mark.parametrize("ham", ["DC", "DCG"])
-@pytest.mark.parametrize("tier,tol", [(1, 2e-6), (2, 2e-2)])
-def test_single_low_tier_within_operand_precision(q, ctx, ham, tier, tol):
-    s = SYSTEMS[ham]()
-    G0, _ = _run(q, ctx, s)
+@pytest.mark.parametrize("tier", [1, 2])
+def test_single_low_tier_within_a_priori_bound(q, ctx, ham, tier):
+    s = QR_SYSTEMS[ham]()
     t32, t16 = (HUGE, 0.0) if tier == 1 else (HUGE, HUGE)
     G1, st = _run(q, ctx, s, prec="mixed", t32=t32, t16=t16)
     assert st["tiles_tier"][tier] == st["tiles_kept"]
-    err = np.abs(G1 - G0).max()
-    scale = _scale(s)
-    print(f"{ham} tier {tier}: max|dG| {err:.3e}, scale {scale:.3e}, rel {err / scale:.2e}")
-    assert err <= tol * scale
+    err, bmax = _check_bound(s, G1, st, "screen", t32, t16, f"{ham} all tiles in tier {tier}")
     # not trivially equal: the reduced operands do change the result
     assert err > 0.0
 
 
 @pytest.mark.parametrize("ham", ["DC", "DCG"])
 @pytest.mark.parametrize("rule", ["screen", "g"])
-def test_default_tiers_error(q, ctx, ham, rule):
-    # Tiers 1e-4 / 1e-7.  The screening-bound rule ignores the bra-side
-    # coefficients that carry a V error into G (|conj(C_mp) C_nq| up to the
-    # bra pair's Dmax, large for Loewdin coefficients of a near-dependent basis);
-    # the G rule includes them.  Reported, with the budgets: FP32 operands are
-    # rounded to 2^-24 relative, BF16 to 2^-9, so with the G rule each low-tier
-    # contribution moves G by at most ~1e-4 * 2^-23 or ~1e-7 * 2^-8.
-    s = SYSTEMS[ham]()
-    G0, st0 = _run(q, ctx, s)
+def test_specified_tiers_within_a_priori_bound(q, ctx, ham, rule):
+    # the mixed configuration's tiers, 1e-4 (FP32) and 1e-7 (BF16)
+    s = QR_SYSTEMS[ham]()
     flags = q.PLAN_TIER_BY_G if rule == "g" else 0
+    G0, st0 = _run(q, ctx, s)
     G1, st1 = _run(q, ctx, s, prec="mixed", flags=flags)
-    Go, _ = oracle.transform_direct(s.L, s.S, s.CL, s.CS, ham, s.tau)
     assert st1["kept"] == st0["kept"]
     assert sum(st1["tiles_tier"]) == st1["tiles_kept"]
-    err = np.abs(G1 - G0).max()
-    derr = np.abs(G1 - Go).max()
+    assert st1["tiles_tier"][1] > 0 and st1["tiles_tier"][2] > 0
+    _check_bound(s, G1, st1, rule, 1e-4, 1e-7, f"{ham} rule {rule} tiers 1e-4 / 1e-7")
     dj = abs(_j_occ(G1) - _j_occ(G0))
-    print(f"{ham} rule {rule} tiers {st1['tiles_tier']}: max|dG| vs FP64 {err:.3e}, vs oracle "
-          f"{derr:.3e}, |dJ_occ| {dj:.3e}, max|G| {np.abs(G0).max():.3e}")
-    assert err <= 1e-6 * _scale(s)
-    assert derr <= err + 1e-12 * _scale(s)
+    print(f"  |dJ_occ| vs FP64 {dj:.3e}")
+
+
+@pytest.mark.parametrize("ham", ["DC", "DCG"])
+@pytest.mark.parametrize("coefs", ["qr", "loewdin"])
+def test_benchmark_tiers_meet_1e10_hartree(q, ctx, ham, coefs):
+    # the tiers the benchmark reports: G rule, FP32 below 1e-6, BF16 below
+    # 1e-9.  QR coefficients: max|G_mixed - G_oracle| <= 1e-10 Eh directly.
+    # Loewdin coefficients (the benchmark's inputs, at test size): there the
+    # FP64 path and the oracle already differ at the 1e-10 level (the MO
+    # integrals are small differences of large terms, summed in different
+    # orders), so the reduced tiers' part of the error is measured against
+    # the FP64 GPU transform (identical except for the low-tier tiles), and
+    # the FP64 transform is held to the oracle at the parity tolerance.
+    s = (QR_SYSTEMS if coefs == "qr" else SYSTEMS)[ham]()
+    G0, st0 = _run(q, ctx, s)
+    G1, st1 = _run(q, ctx, s, prec="mixed", t32=1e-6, t16=1e-9, flags=q.PLAN_TIER_BY_G)
+    Go, so = oracle.transform_direct(s.L, s.S, s.CL, s.CS, ham, s.tau)
+    assert st1["kept"] == so["kept"] and st1["kept_gaunt"] == so["kept_gaunt"]
+    assert st1["tiles_tier"][1] > 0
+    err_o = float(np.abs(G1 - Go).max())
+    err_64 = float(np.abs(G1 - G0).max())
+    fp64_o = float(np.abs(G0 - Go).max())
+    dj = abs(_j_occ(G1) - _j_occ(G0))
+    print(f"{ham} {coefs} G rule 1e-6 / 1e-9: tiles {st1['tiles_tier']}, max|G - G_FP64| "
+          f"{err_64:.3e} Eh, max|G - G_oracle| {err_o:.3e} Eh (FP64 vs oracle {fp64_o:.3e}), "
+          f"|dJ_occ| {dj:.3e}, max|G| {np.abs(Go).max():.3e}")
+    assert err_64 <= 1e-10
+    if coefs == "qr":
+        assert err_o <= 1e-10 and fp64_o <= 1e-12 * np.abs(Go).max()
+    else:
+        assert fp64_o <= 1e-12 * _schwarz_scale(s)
+
+
+def _schwarz_scale(s):
+    # the Schwarz magnitude bound of the sums (the parity tolerance scale of
+    # Loewdin-coefficient tests, see test_gpu_parity.py)
+    Qs, Cs = [oracle.schwarz(s.L), oracle.schwarz(s.S)], [s.CL, s.CS]
+    sc = qalg.schwarz_scale(Qs, Cs)
+    if s.ham == "DCG":
+        nL = np.sqrt((s.CL ** 2).sum(0))
+        nS = np.sqrt((s.CS ** 2).sum(0))
+        a = nL.T @ oracle.schwarz(s.L, s.S) @ nS
+        sc += 3 * float(np.max(a + a.T)) ** 2
+    return sc
 
 
 def test_mixed_graph_replay_equals_eager(q):

@@ -55,7 +55,9 @@ def test_graph_replays_equal_eager(q, ham, budget_mb):
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_served_requests_equal_alone(q, prec):
     from paper_2606_04316_amd import serving
-    reqs = serving.request_stream(12, seed=7, mean_gap_s=0.005, pool=4, atoms=(3, 6),
+    # arrivals 1 ms apart on average, far below a request's service time
+    # (plan creation alone takes milliseconds), so requests must overlap
+    reqs = serving.request_stream(12, seed=7, mean_gap_s=0.001, pool=4, atoms=(3, 6),
                                   nl=(6, 24), n_mo=(2, 6), radius_scale=8.0)
     # mixed: every tile in a reduced tier (FP32, BF16 below 1e-3), so that the
     # reduced-precision kernels run in the mix
@@ -67,6 +69,13 @@ def test_served_requests_equal_alone(q, prec):
     assert all(r.error is None for r in out), [r.error for r in out if r.error]
     summ = serving.summarize(out)
     assert summ["failed"] == 0 and summ["p99_ms"] >= summ["p50_ms"] > 0
+    # continuous batching, not a queue: requests were admitted while others
+    # ran, and their admission-to-result intervals overlap in time
+    assert srv.max_concurrency > 1, srv.max_concurrency
+    iv = sorted((r.t_admit, r.t_done) for r in out)
+    overlaps = sum(1 for a, b in zip(iv, iv[1:]) if b[0] < a[1])
+    print(f"max concurrency {srv.max_concurrency}, overlapping neighbours {overlaps}")
+    assert overlaps > 0
     # the same requests one at a time, nothing else on the device
     alone_ex = serving.GpuExecutor(slots=1, prec=prec, tiers=tiers)
     for r in out[:8]:
