@@ -89,6 +89,11 @@ def lib():
         L.orc_first_half_rows.restype = ctypes.c_int
         L.orc_first_half_rows.argtypes = [bp, bp, dp, dp, ctypes.c_int, ctypes.c_int,
                                           ctypes.c_double, ctypes.c_void_p, ctypes.c_int64, dp]
+        L.orc_first_half_rows_cols.restype = ctypes.c_int
+        L.orc_first_half_rows_cols.argtypes = [bp, bp, dp, dp, ctypes.c_int, ctypes.c_int,
+                                               ctypes.c_double, ctypes.c_void_p, ctypes.c_int64,
+                                               ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                               dp]
         L.orc_transform_spinor_def.restype = ctypes.c_int
         L.orc_transform_spinor_def.argtypes = [bp, bp, dp, dp, ctypes.c_int, ctypes.c_int, dp]
         L.orc_transform_spinor_direct.restype = ctypes.c_int
@@ -296,6 +301,46 @@ def first_half_rows(L, S, CL, CS, ham: str, tau: float, rows) -> np.ndarray:
     if rc != 0:
         raise ValueError("orc_first_half_rows rejected its arguments")
     return Vq
+
+
+def first_half_rows_cols(L, S, CL, CS, ham: str, tau: float, rows, cols,
+                         dmax=None) -> np.ndarray:
+    """first_half_rows for the MO pairs ``cols`` (indices of p <= q, p outer)
+    only: columns K * 4 * len(cols) + 4 * j + y.  ``dmax`` (optional) is the
+    density bound per pair of the concatenated LL, SS, LS list
+    (pair_density_bounds); without it the bound is computed here."""
+    bl, bs, CL, CS = _prep(L, S, CL, CS)
+    sel = np.ascontiguousarray(rows, dtype=np.int64)
+    cl = np.ascontiguousarray(cols, dtype=np.int64)
+    width = (3 if ham in LS_HAMS else 1) * 4 * cl.shape[0]
+    Vq = np.zeros((sel.shape[0], width))
+    dm = None if dmax is None else np.ascontiguousarray(dmax, dtype=np.float64)
+    rc = lib().orc_first_half_rows_cols(bl.ref, bs.ref if bs else None, _dp(CL),
+                                        _dp(CS) if CS is not None else None, CL.shape[2],
+                                        HAMS[ham], float(tau), sel.ctypes.data,
+                                        int(sel.shape[0]), cl.ctypes.data, int(cl.shape[0]),
+                                        dm.ctypes.data if dm is not None else None, _dp(Vq))
+    if rc != 0:
+        raise ValueError("orc_first_half_rows_cols rejected its arguments")
+    return Vq
+
+
+def pair_density_bounds(L, S, CL, CS, ham: str) -> np.ndarray:
+    """Density bound Dmax of every pair of the concatenated bra pair list
+    (LL pairs mu <= nu, nu-major, then SS pairs, then LS pairs mu-major) from
+    the quaternion-route bounds dmax_coulomb and dmax_gaunt."""
+    parts = []
+    if ham not in ("GAUNT", "GAUGE"):
+        for C in ((CL,) if ham == "LL" else (CL, CS)):
+            D = dmax_coulomb(C)
+            N = D.shape[0]
+            iu = np.triu_indices(N)  # (mu, nu) with mu <= nu
+            v = np.empty(N * (N + 1) // 2)
+            v[iu[1] * (iu[1] + 1) // 2 + iu[0]] = D[iu[0], iu[1]]
+            parts.append(v)
+    if ham in LS_HAMS:
+        parts.append(dmax_gaunt(CL, CS).reshape(-1))
+    return np.concatenate(parts)
 
 
 def num_bra_pairs(L, S, ham: str) -> int:

@@ -573,22 +573,35 @@ static void qmul(const double a[4], const double b[4], double r[4])
     r[3] = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
 }
 
+/* Both bounds loop over MO pairs (r, t) with t innermost; the t loop is a
+ * max reduction (order-independent), written for SIMD. */
 void orc_dmax_coulomb(int NA, const double *CA, int n, double *Dmax)
 {
+    const size_t pl = (size_t)NA * n;  /* plane stride */
+#pragma omp parallel for schedule(dynamic, 4)
     for (int k = 0; k < NA; ++k)
         for (int l = 0; l < NA; ++l) {
             double m = 0.0;
-            for (int r = 0; r < n; ++r)
+            const double *b0 = CA + (size_t)l * n, *b1 = b0 + pl, *b2 = b1 + pl, *b3 = b2 + pl;
+            for (int r = 0; r < n; ++r) {
+                /* a = conj(C_kr) */
+                const double a0 = CA[(size_t)k * n + r], a1 = -CA[pl + (size_t)k * n + r];
+                const double a2 = -CA[2 * pl + (size_t)k * n + r];
+                const double a3 = -CA[3 * pl + (size_t)k * n + r];
+#pragma omp simd reduction(max : m)
                 for (int t = 0; t < n; ++t) {
-                    double a[4], b[4], d[4];
-                    for (int z = 0; z < 4; ++z) {
-                        a[z] = CA[((size_t)z * NA + k) * n + r] * (z ? -1.0 : 1.0);
-                        b[z] = CA[((size_t)z * NA + l) * n + t];
-                    }
-                    qmul(a, b, d);
-                    for (int z = 0; z < 4; ++z)
-                        if (fabs(d[z]) > m) m = fabs(d[z]);
+                    /* d = a * C_lt, the quaternion product written out */
+                    double d0 = a0 * b0[t] - a1 * b1[t] - a2 * b2[t] - a3 * b3[t];
+                    double d1 = a0 * b1[t] + a1 * b0[t] + a2 * b3[t] - a3 * b2[t];
+                    double d2 = a0 * b2[t] - a1 * b3[t] + a2 * b0[t] + a3 * b1[t];
+                    double d3 = a0 * b3[t] + a1 * b2[t] - a2 * b1[t] + a3 * b0[t];
+                    d0 = fabs(d0); d1 = fabs(d1); d2 = fabs(d2); d3 = fabs(d3);
+                    m = m > d0 ? m : d0;
+                    m = m > d1 ? m : d1;
+                    m = m > d2 ? m : d2;
+                    m = m > d3 ? m : d3;
                 }
+            }
             Dmax[(size_t)k * NA + l] = m;
         }
 }
@@ -597,27 +610,39 @@ void orc_dmax_gaunt(int NL, const double *CL, int NS, const double *CS, int n, d
 {
     /* e_K for K = x, y, z: the quaternion units with sigma_K = -i Q(e_K) */
     const double unit[3][4] = {{0, 0, 0, 1}, {0, 0, 1, 0}, {0, 1, 0, 0}};
+    const size_t pL = (size_t)NL * n, pS = (size_t)NS * n;
+#pragma omp parallel for schedule(dynamic, 1)
     for (int mu = 0; mu < NL; ++mu)
         for (int nu = 0; nu < NS; ++nu) {
             double m = 0.0;
+            const double *l0 = CL + (size_t)mu * n, *l1 = l0 + pL, *l2 = l1 + pL, *l3 = l2 + pL;
+            const double *s0 = CS + (size_t)nu * n, *s1 = s0 + pS, *s2 = s1 + pS, *s3 = s2 + pS;
             for (int K = 0; K < 3; ++K)
-                for (int r = 0; r < n; ++r)
+                for (int r = 0; r < n; ++r) {
+                    /* a = conj(C^L_mu r) e_K, b = conj(C^S_nu r) e_K */
+                    double lr[4] = {l0[r], -l1[r], -l2[r], -l3[r]};
+                    double sr[4] = {s0[r], -s1[r], -s2[r], -s3[r]};
+                    double a[4], b[4];
+                    qmul(lr, unit[K], a);
+                    qmul(sr, unit[K], b);
+#pragma omp simd reduction(max : m)
                     for (int t = 0; t < n; ++t) {
-                        double lr[4], sr[4], lt[4], st[4], a[4], b[4], d1[4], d2[4];
-                        for (int z = 0; z < 4; ++z) {
-                            double sg = z ? -1.0 : 1.0;
-                            lr[z] = sg * CL[((size_t)z * NL + mu) * n + r];
-                            sr[z] = sg * CS[((size_t)z * NS + nu) * n + r];
-                            lt[z] = CL[((size_t)z * NL + mu) * n + t];
-                            st[z] = CS[((size_t)z * NS + nu) * n + t];
-                        }
-                        qmul(lr, unit[K], a);
-                        qmul(a, st, d1);
-                        qmul(sr, unit[K], b);
-                        qmul(b, lt, d2);
-                        for (int z = 0; z < 4; ++z)
-                            if (fabs(d1[z] + d2[z]) > m) m = fabs(d1[z] + d2[z]);
+                        /* a * C^S_nu t + b * C^L_mu t */
+                        double d0 = a[0] * s0[t] - a[1] * s1[t] - a[2] * s2[t] - a[3] * s3[t]
+                                  + (b[0] * l0[t] - b[1] * l1[t] - b[2] * l2[t] - b[3] * l3[t]);
+                        double d1 = a[0] * s1[t] + a[1] * s0[t] + a[2] * s3[t] - a[3] * s2[t]
+                                  + (b[0] * l1[t] + b[1] * l0[t] + b[2] * l3[t] - b[3] * l2[t]);
+                        double d2 = a[0] * s2[t] - a[1] * s3[t] + a[2] * s0[t] + a[3] * s1[t]
+                                  + (b[0] * l2[t] - b[1] * l3[t] + b[2] * l0[t] + b[3] * l1[t]);
+                        double d3 = a[0] * s3[t] + a[1] * s2[t] - a[2] * s1[t] + a[3] * s0[t]
+                                  + (b[0] * l3[t] + b[1] * l2[t] - b[2] * l1[t] + b[3] * l0[t]);
+                        d0 = fabs(d0); d1 = fabs(d1); d2 = fabs(d2); d3 = fabs(d3);
+                        m = m > d0 ? m : d0;
+                        m = m > d1 ? m : d1;
+                        m = m > d2 ? m : d2;
+                        m = m > d3 ? m : d3;
                     }
+                }
             Dmax[(size_t)mu * NS + nu] = m;
         }
 }
@@ -903,14 +928,16 @@ static cplx dens_gaunt(const cplx *cl, const cplx *cs, int m, int K, int ka, int
 static int direct_impl(const orc_basis *L, const orc_basis *S, const double *CL,
                        const double *CS, int n, int ham, double tau, const int64_t *rows,
                        int64_t nrows_sel, int do_second, double *G, orc_stats *st, double *Vq,
-                       int general, double *sp_out, const double *dmax_in);
+                       int general, double *sp_out, const double *dmax_in,
+                       const int64_t *cols, int64_t ncols);
 
 int orc_transform_direct_dmax(const orc_basis *L, const orc_basis *S, const double *CL,
                               const double *CS, int n, int ham, double tau,
                               const double *dmax_in, double *G, orc_stats *st)
 {
     if (!dmax_in) return -1;
-    return direct_impl(L, S, CL, CS, n, ham, tau, NULL, 0, 1, G, st, NULL, 0, NULL, dmax_in);
+    return direct_impl(L, S, CL, CS, n, ham, tau, NULL, 0, 1, G, st, NULL, 0, NULL, dmax_in,
+                       NULL, 0);
 }
 
 int orc_transform_direct(const orc_basis *L, const orc_basis *S, const double *CL,
@@ -918,7 +945,7 @@ int orc_transform_direct(const orc_basis *L, const orc_basis *S, const double *C
                          int64_t nrows_sel, int do_second, double *G, orc_stats *st)
 {
     return direct_impl(L, S, CL, CS, n, ham, tau, rows, nrows_sel, do_second, G, st, NULL, 0,
-                       NULL, NULL);
+                       NULL, NULL, NULL, 0);
 }
 
 int orc_first_half_rows(const orc_basis *L, const orc_basis *S, const double *CL,
@@ -926,7 +953,18 @@ int orc_first_half_rows(const orc_basis *L, const orc_basis *S, const double *CL
                         int64_t nrows, double *Vq)
 {
     if (!rows || nrows <= 0 || !Vq) return -1;
-    return direct_impl(L, S, CL, CS, n, ham, tau, rows, nrows, 0, NULL, NULL, Vq, 0, NULL, NULL);
+    return direct_impl(L, S, CL, CS, n, ham, tau, rows, nrows, 0, NULL, NULL, Vq, 0, NULL, NULL,
+                       NULL, 0);
+}
+
+int orc_first_half_rows_cols(const orc_basis *L, const orc_basis *S, const double *CL,
+                             const double *CS, int n, int ham, double tau, const int64_t *rows,
+                             int64_t nrows, const int64_t *cols, int64_t ncols,
+                             const double *dmax_in, double *Vq)
+{
+    if (!rows || nrows <= 0 || !Vq || !cols || ncols <= 0) return -1;
+    return direct_impl(L, S, CL, CS, n, ham, tau, rows, nrows, 0, NULL, NULL, Vq, 0, NULL,
+                       dmax_in, cols, ncols);
 }
 
 int orc_transform_spinor_direct(const orc_basis *L, const orc_basis *S, const double *CL,
@@ -935,7 +973,7 @@ int orc_transform_spinor_direct(const orc_basis *L, const orc_basis *S, const do
 {
     if (!spinor_out) return -1;
     return direct_impl(L, S, CL, CS, m, ham, tau, NULL, 0, 1, NULL, st, NULL, 1, spinor_out,
-                       NULL);
+                       NULL, NULL, 0);
 }
 
 /* n: Kramers pairs (quaternion C, m = 2n spinors, output G projected onto the
@@ -944,7 +982,8 @@ int orc_transform_spinor_direct(const orc_basis *L, const orc_basis *S, const do
 static int direct_impl(const orc_basis *L, const orc_basis *S, const double *CL,
                        const double *CS, int n, int ham, double tau, const int64_t *rows,
                        int64_t nrows_sel, int do_second, double *G, orc_stats *st, double *Vq,
-                       int general, double *sp_out, const double *dmax_in)
+                       int general, double *sp_out, const double *dmax_in,
+                       const int64_t *cols, int64_t ncols)
 {
     int with_S = (ham != 0);
     if (with_S && (!S || !CS)) return -1;
@@ -954,6 +993,39 @@ static int direct_impl(const orc_basis *L, const orc_basis *S, const double *CL,
     if (ham_gauge(ham) && (has_p(L) || (with_S && has_p(S)))) return -1;
     int NL = L->nfunc, NS = with_S ? S->nfunc : 0, m = general ? n : 2 * n;
     size_t m2 = (size_t)m * m;
+    /* spinor pairs (c, d) of the first half: all m^2, or (cols: first-half
+     * rows only) the four of each selected MO pair p <= q, c in {2p, 2p+1},
+     * d in {2q, 2q+1}; the MO pair index counts p <= q with p outer */
+    if (cols && (general || !Vq || do_second)) return -1;
+    const int64_t npair_mo = (int64_t)n * (n + 1) / 2;
+    int64_t ncd = cols ? 4 * ncols : (int64_t)m2;
+    int *cd_c = (int *)malloc(sizeof(int) * (size_t)ncd), *cd_d = (int *)malloc(sizeof(int) * (size_t)ncd);
+    int64_t *col_p = cols ? (int64_t *)malloc(sizeof(int64_t) * (size_t)ncols) : NULL;
+    int64_t *col_q = cols ? (int64_t *)malloc(sizeof(int64_t) * (size_t)ncols) : NULL;
+    if (cols) {
+        for (int64_t j = 0; j < ncols; ++j) {
+            if (cols[j] < 0 || cols[j] >= npair_mo) {
+                free(cd_c); free(cd_d); free(col_p); free(col_q);
+                return -1;
+            }
+            int p = 0;
+            int64_t rest = cols[j];
+            while (rest >= n - p) { rest -= n - p; ++p; }
+            col_p[j] = p;
+            col_q[j] = p + rest;
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                    cd_c[4 * j + 2 * a + b] = (int)(2 * col_p[j] + a);
+                    cd_d[4 * j + 2 * a + b] = (int)(2 * col_q[j] + b);
+                }
+        }
+    } else {
+        for (int c = 0; c < m; ++c)
+            for (int d = 0; d < m; ++d) {
+                cd_c[(size_t)c * m + d] = c;
+                cd_d[(size_t)c * m + d] = d;
+            }
+    }
     /* gaunt: L-S rows present (Gaunt and/or gauge term) */
     int coul = ham_coulomb(ham), gaunt = ham_ls(ham);
     int gaunt_term = ham_gaunt(ham), gauge_term = ham_gauge(ham);
@@ -985,6 +1057,10 @@ static int direct_impl(const orc_basis *L, const orc_basis *S, const double *CL,
     for (int64_t r = 0; r < nrow; ++r) {
         int64_t i = rows ? rows[r] : r;
         if (i < 0 || i >= np || (rows && slot[i] >= 0)) {
+            free(cd_c);
+            free(cd_d);
+            free(col_p);
+            free(col_q);
             free(slot);
             free(sel);
             free(pl);
@@ -1128,8 +1204,8 @@ static int direct_impl(const orc_basis *L, const orc_basis *S, const double *CL,
                                 wKL[K * 3 + L2] += 0.5 * (t3[K * 3 + L2] - (K == L2 ? e : 0.0));
                     }
                     for (int L2 = 0; L2 < 3; ++L2)
-                        for (int c = 0; c < m; ++c)
-                            for (int d = 0; d < m; ++d) {
+                        for (int64_t t = 0; t < ncd; ++t) {
+                                int c = cd_c[t], d = cd_d[t];
                                 cplx D = dens_gaunt(cl, cs, m, L2, Kp.mu, Kp.nu, c, d);
                                 for (int K = 0; K < 3; ++K)
                                     if (wKL[K * 3 + L2] != 0.0)
@@ -1138,8 +1214,8 @@ static int direct_impl(const orc_basis *L, const orc_basis *S, const double *CL,
                             }
                 } else {
                     const cplx *cx = Kp.cls == 0 ? cl : cs;
-                    for (int c = 0; c < m; ++c)
-                        for (int d = 0; d < m; ++d) {
+                    for (int64_t t = 0; t < ncd; ++t) {
+                            int c = cd_c[t], d = cd_d[t];
                             cplx D = dens_s(cx, m, Kp.mu, Kp.nu, c, d);
                             if (Kp.mu != Kp.nu) D += dens_s(cx, m, Kp.nu, Kp.mu, c, d);
                             Vi[(size_t)c * m + d] += e * D;
@@ -1166,27 +1242,35 @@ static int direct_impl(const orc_basis *L, const orc_basis *S, const double *CL,
          * a Coulomb row is Q(V^{rs}) and of a Gaunt row -i Q(V^{K,rs}); columns
          * (K, r <= s, y) at K * 4 * npair + 4 * idx(r, s) + y, idx counting the
          * pairs r <= s with r outer. */
-        const int64_t npair = (int64_t)n * (n + 1) / 2, width = (int64_t)nvK * 4 * npair;
+        const int64_t npair = cols ? ncols : npair_mo, width = (int64_t)nvK * 4 * npair;
         for (int64_t r = 0; r < nrow; ++r) {
             const opair B = pl[sel[r]];
             const cplx *Vr = V + (size_t)r * nvK * m2;
             double *out = Vq + (size_t)r * width;
             for (int64_t c = 0; c < width; ++c) out[c] = 0.0;
             int nK = B.cls == 2 ? 3 : 1;
-            for (int K = 0; K < nK; ++K) {
-                int64_t idx = 0;
-                for (int p = 0; p < n; ++p)
-                    for (int q = p; q < n; ++q, ++idx) {
-                        cplx blk[2][2];
-                        for (int a = 0; a < 2; ++a)
-                            for (int b = 0; b < 2; ++b) {
-                                cplx v = Vr[(size_t)K * m2 + (size_t)(2 * p + a) * m + 2 * q + b];
-                                blk[a][b] = B.cls == 2 ? I * v : v;
-                            }
-                        for (int y = 0; y < 4; ++y)
-                            out[(int64_t)K * 4 * npair + 4 * idx + y] = qproject(y, blk, NULL);
+            for (int K = 0; K < nK; ++K)
+                for (int64_t idx = 0; idx < npair; ++idx) {
+                    /* MO pair idx (p <= q, p outer), or the idx-th selected one */
+                    int p, q;
+                    if (cols) {
+                        p = (int)col_p[idx];
+                        q = (int)col_q[idx];
+                    } else {
+                        p = 0;
+                        int64_t rest = idx;
+                        while (rest >= n - p) { rest -= n - p; ++p; }
+                        q = p + (int)rest;
                     }
-            }
+                    cplx blk[2][2];
+                    for (int a = 0; a < 2; ++a)
+                        for (int b = 0; b < 2; ++b) {
+                            cplx v = Vr[(size_t)K * m2 + (size_t)(2 * p + a) * m + 2 * q + b];
+                            blk[a][b] = B.cls == 2 ? I * v : v;
+                        }
+                    for (int y = 0; y < 4; ++y)
+                        out[(int64_t)K * 4 * npair + 4 * idx + y] = qproject(y, blk, NULL);
+                }
         }
     }
 
@@ -1294,6 +1378,10 @@ static int direct_impl(const orc_basis *L, const orc_basis *S, const double *CL,
         st->threads = nthreads;
     }
     free(V);
+    free(cd_c);
+    free(cd_d);
+    free(col_p);
+    free(col_q);
     free(Q);
     free(Dmax);
     free(slot);

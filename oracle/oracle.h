@@ -139,6 +139,16 @@ int orc_first_half_rows(const orc_basis *L, const orc_basis *S, const double *CL
                         const double *CS, int n, int ham, double tau, const int64_t *rows,
                         int64_t nrows, double *Vq);
 
+/* orc_first_half_rows for a subset of the MO-pair columns and, optionally,
+ * a density bound given per pair of the concatenated list (dmax_in[np], as
+ * for orc_transform_direct_dmax; NULL: computed here).  cols[ncols] are MO
+ * pair indices idx(p <= q) (p outer); Vq[r][K * 4 * ncols + 4 * j + y] holds
+ * MO pair cols[j].  Returns 0, or -1 on invalid arguments. */
+int orc_first_half_rows_cols(const orc_basis *L, const orc_basis *S, const double *CL,
+                             const double *CS, int n, int ham, double tau, const int64_t *rows,
+                             int64_t nrows, const int64_t *cols, int64_t ncols,
+                             const double *dmax_in, double *Vq);
+
 /* Kramers-unrestricted (general) two-spinor input, the paper's own setting:
  * m spinors with coefficients c_{mu tau, a} given as planes C[4][N][m] (alpha
  * re, alpha im, beta re, beta im).  Output: the complex spinor MO integrals

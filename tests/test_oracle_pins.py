@@ -666,3 +666,26 @@ def test_mo_driven_batch_bounds_counts_and_certificate():
     assert stm["kept"][0] == kept
     assert 0 < kept < len(pairs) ** 2 * (len(mo) + batch - 1) // batch
     assert np.abs(Gm - Gf).max() > 100 * slack  # screening changed the result
+
+
+@pytest.mark.parametrize("ham", ["DC", "DCG", "DCB"])
+def test_first_half_rows_for_a_column_subset(ham):
+    # the column-subset form (used at full size, where all MO-pair columns
+    # would not fit) equals the corresponding columns of the full rows, with
+    # the density bound computed inside or given from the quaternion-route
+    # bounds (the same predicate)
+    s = wl.linear_chain(seed=70, n_atoms=5, spacing=3.0, nl_per_atom=3, ns_per_atom=4, n=5,
+                        tau=1e-9, ham=ham, coefs="qr")
+    P = oracle.num_bra_pairs(s.L, s.S, ham)
+    rows = np.array([0, 5, P // 2, P - 1, P - 7])
+    V = oracle.first_half_rows(s.L, s.S, s.CL, s.CS, ham, s.tau, rows)
+    cols = np.array([14, 0, 3, 9])
+    dm = oracle.pair_density_bounds(s.L, s.S, s.CL, s.CS, ham)
+    nK, npair = (3 if ham != "DC" else 1), 15
+    ref = np.concatenate([V[:, K * 4 * npair:(K + 1) * 4 * npair]
+                          .reshape(len(rows), npair, 4)[:, cols].reshape(len(rows), -1)
+                          for K in range(nK)], axis=1)
+    for d in (None, dm):
+        Vc = oracle.first_half_rows_cols(s.L, s.S, s.CL, s.CS, ham, s.tau, rows, cols, d)
+        assert np.array_equal(Vc, ref)
+    assert np.abs(ref).max() > 0
