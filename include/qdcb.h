@@ -154,6 +154,19 @@ qdcb_status qdcb_basis_create_rkb(qdcb_ctx *ctx, const qdcb_basis *L, double *no
 qdcb_status qdcb_rkb_small_planes(int32_t nfunc, int32_t m, const double *PS,
                                   const double *norms, double c, double *out);
 
+/* The same small components in the Kramers-restricted (quaternion) form:
+ * the Kramers pair of quaternion MO p with RKB coefficients C^S [4][nfunc][n]
+ * (planes C0..C3, as for qdcb_transform) has, over the gradient basis, the
+ * quaternion coefficients
+ *   out_{(mu K) p} = -(norms[3 mu + K] / 2c) e_K C^S_{mu p},  e_x = k, e_y = j, e_z = i,
+ * out [4][3 nfunc][n], because sigma_K = -i Q(e_K) makes (-i / 2c) sigma_K Q(C)
+ * the matrix Q of that quaternion.  A quaternion DC or DCG plan with L and
+ * the gradient basis as S then gives the RKB four-component integrals of the
+ * n Kramers pairs with half the MO-pair columns of the general two-spinor
+ * route.  Host arrays, host arithmetic (no device work). */
+qdcb_status qdcb_rkb_small_quat(int32_t nfunc, int32_t n, const double *CS, const double *norms,
+                                double c, double *out);
+
 /* Schwarz factors of the basis's own function pairs: Q[mu][nu] (host,
  * [nfunc][nfunc], symmetric). */
 qdcb_status qdcb_basis_schwarz(const qdcb_basis *basis, double *Q);

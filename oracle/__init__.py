@@ -30,6 +30,21 @@ def build(verbose: bool = False) -> str:
     return _SO
 
 
+def build_sanitized() -> str:
+    """CPU check build: oracle.c with AddressSanitizer and
+    UndefinedBehaviorSanitizer, linked into sanitize_check (a driver of every
+    entry point on a tiny system).  Returns the executable's path."""
+    out = os.path.join(_HERE, "_build_san")
+    os.makedirs(out, exist_ok=True)
+    exe = os.path.join(out, "sanitize_check")
+    cmd = ["gcc", "-O1", "-g", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-Wall",
+           "-Wno-unused-variable", "-I", _HERE, os.path.join(_HERE, "sanitize_check.c"),
+           os.path.join(_HERE, "oracle.c"), "-o", exe, "-lm"]
+    subprocess.run(cmd, check=True, capture_output=True)
+    return exe
+
+
 class _Basis(ctypes.Structure):
     _fields_ = [("nfunc", ctypes.c_int32),
                 ("centers", ctypes.POINTER(ctypes.c_double)),

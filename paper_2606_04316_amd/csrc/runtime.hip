@@ -374,6 +374,31 @@ qdcb_status qdcb_rkb_small_planes(int32_t nfunc, int32_t m, const double *PS,
   });
 }
 
+qdcb_status qdcb_rkb_small_quat(int32_t nfunc, int32_t n, const double *CS, const double *norms,
+                                double c, double *out) {
+  return guarded([&] {
+    if (!CS || !norms || !out) fail(QDCB_E_INVALID, "NULL argument");
+    if (nfunc < 1 || n < 1) fail(QDCB_E_INVALID, "nfunc and n must be positive");
+    if (!(c > 0) || !std::isfinite(c)) fail(QDCB_E_INVALID, "c must be positive");
+    const size_t N = nfunc, M = n, G = 3 * N;
+    for (size_t mu = 0; mu < N; ++mu)
+      for (size_t p = 0; p < M; ++p) {
+        const double q0 = CS[(0 * N + mu) * M + p], q1 = CS[(1 * N + mu) * M + p];
+        const double q2 = CS[(2 * N + mu) * M + p], q3 = CS[(3 * N + mu) * M + p];
+        // e_K C for e_x = k, e_y = j, e_z = i (sigma_K = -i Q(e_K)), with
+        // ki = j, kj = -i, ji = -k, jk = i, ij = k, ik = -j:
+        //   k (q0 + q1 i + q2 j + q3 k) = -q3 - q2 i + q1 j + q0 k
+        //   j (...)                     = -q2 + q3 i + q0 j - q1 k
+        //   i (...)                     = -q1 + q0 i - q3 j + q2 k
+        const double e[3][4] = {{-q3, -q2, q1, q0}, {-q2, q3, q0, -q1}, {-q1, q0, -q3, q2}};
+        for (int K = 0; K < 3; ++K) {
+          const double w = -0.5 / c * norms[3 * mu + K];
+          for (int z = 0; z < 4; ++z) out[(z * G + 3 * mu + K) * M + p] = w * e[K][z];
+        }
+      }
+  });
+}
+
 qdcb_status qdcb_basis_schwarz(const qdcb_basis *b, double *Q) {
   return guarded([&] {
     if (!b || !Q) fail(QDCB_E_INVALID, "NULL argument");

@@ -121,6 +121,8 @@ def lib():
         L.qdcb_basis_create_rkb.argtypes = [_P, _P, _DP, ctypes.POINTER(_P)]
         L.qdcb_rkb_small_planes.argtypes = [ctypes.c_int32, ctypes.c_int32, _DP, _DP,
                                             ctypes.c_double, _DP]
+        L.qdcb_rkb_small_quat.argtypes = [ctypes.c_int32, ctypes.c_int32, _DP, _DP,
+                                          ctypes.c_double, _DP]
         L.qdcb_basis_destroy.argtypes = [_P]
         L.qdcb_basis_destroy.restype = None
         L.qdcb_basis_schwarz.argtypes = [_P, _DP]
@@ -150,7 +152,7 @@ def lib():
         L.qdcb_plan_autotune.argtypes = [_P, _P, _P, _P, ctypes.c_uint32, _P, ctypes.c_char_p,
                                          ctypes.POINTER(TuneReport)]
         for f in ("qdcb_ctx_create", "qdcb_basis_create", "qdcb_basis_create_cart",
-                  "qdcb_basis_create_rkb", "qdcb_rkb_small_planes",
+                  "qdcb_basis_create_rkb", "qdcb_rkb_small_planes", "qdcb_rkb_small_quat",
                   "qdcb_basis_schwarz",
                   "qdcb_eri_quartets", "qdcb_plan_create", "qdcb_plan_footprint",
                   "qdcb_transform", "qdcb_plan_fetch", "qdcb_plan_estimate",
@@ -262,6 +264,19 @@ def rkb_small_planes(PS: np.ndarray, norms: np.ndarray, c: float) -> np.ndarray:
     return out
 
 
+def rkb_small_quat(CS: np.ndarray, norms: np.ndarray, c: float) -> np.ndarray:
+    """Quaternion RKB small-component coefficients [4][3 N][n] over the
+    gradient basis of rkb_basis, from the RKB quaternion coefficients
+    CS [4][N][n] of n Kramers pairs."""
+    CS = _f64(CS)
+    norms = _f64(norms)
+    N, n = CS.shape[1], CS.shape[2]
+    out = np.empty((4, 3 * N, n))
+    _check(lib().qdcb_rkb_small_quat(N, n, CS.ctypes.data_as(_DP), norms.ctypes.data_as(_DP),
+                                     float(c), out.ctypes.data_as(_DP)))
+    return out
+
+
 def tune_cache_lookup(path: str, key: str) -> Optional[dict]:
     t, found = Tune(), ctypes.c_int32(0)
     _check(lib().qdcb_tune_cache_lookup(path.encode(), key.encode(), ctypes.byref(t),
@@ -280,6 +295,7 @@ def eri_quartets(A: Basis, B: Basis, idx) -> np.ndarray:
     _check(lib().qdcb_eri_quartets(A.h, B.h, idx.shape[0], idx.ctypes.data_as(_IP),
                                    out.ctypes.data_as(_DP)))
     return out
+
 
 
 class Plan:

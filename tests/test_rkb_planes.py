@@ -30,3 +30,21 @@ def test_small_planes_reject_bad_arguments(q):
         q.rkb_small_planes(PS, np.ones(6), 0.0)
     with pytest.raises(q.QdcbError):
         q.rkb_small_planes(PS, np.ones(6), float("nan"))
+
+
+def test_quaternion_small_components_are_the_kramers_pairs_spinor_planes(q):
+    # the Kramers-restricted form: the two spinors of each quaternion
+    # coefficient (columns of Q(C)) have exactly the oracle's RKB small
+    # components, i.e. Q(-(n / 2c) e_K C) = (-i / 2c) n sigma_K Q(C)
+    from paper_2606_04316_amd import workloads as wl
+    rng = np.random.default_rng(4)
+    for N, n, c in ((1, 1, 1.0), (4, 3, 2.5), (9, 5, rkb.SPEED_OF_LIGHT)):
+        CS = rng.standard_normal((4, N, n))
+        norms = rng.uniform(0.5, 3.0, 3 * N)
+        Cq = q.rkb_small_quat(CS, norms, c)
+        assert Cq.shape == (4, 3 * N, n)
+        got = wl.quat_to_spinor_planes(Cq)
+        ref = rkb.small_component_planes(wl.quat_to_spinor_planes(CS), norms, c)
+        assert np.abs(got - ref).max() <= 1e-15 * np.abs(ref).max()
+    with pytest.raises(q.QdcbError):
+        q.rkb_small_quat(np.ones((4, 2, 2)), np.ones(6), -1.0)
