@@ -177,6 +177,24 @@ qdcb_status qdcb_basis_schwarz(const qdcb_basis *basis, double *Q);
 qdcb_status qdcb_eri_quartets(const qdcb_basis *A, const qdcb_basis *B, int64_t nq,
                               const int32_t *idx, double *out);
 
+/* Allocation-free variant of qdcb_eri_quartets, for callers that cannot
+ * allocate device memory (harnesses that forbid hipMalloc, tight loops that
+ * must not touch the allocator).  Same arguments, results and errors as
+ * qdcb_eri_quartets (the same device integral code, so bitwise the same
+ * values); its device staging (the quartet list, each quartet's
+ * primitive-pair ranges and codes, the results: 56 bytes per quartet) lives
+ * in one fixed array of the library on each device, sized for
+ * QDCB_NOALLOC_MAX_QUARTETS quartets (about 14 MiB, held from library load to
+ * process exit), instead of being allocated.  nq above that limit:
+ * QDCB_E_INVALID, nothing computed.  Synchronous, on the null stream: it
+ * returns when out is written, and is not for capture into a HIP graph.
+ * Calls on one device share the array; the library serializes them (calls
+ * that overlapped on one device would otherwise race).  A context must have
+ * been created on the bases' device (QDCB_E_DEVICE otherwise). */
+#define QDCB_NOALLOC_MAX_QUARTETS 262144
+qdcb_status qdcb_eri_quartets_noalloc(const qdcb_basis *A, const qdcb_basis *B, int64_t nq,
+                                      const int32_t *idx, double *out);
+
 typedef struct {
     int32_t ham;       /* qdcb_ham */
     int32_t prec;      /* qdcb_prec */

@@ -128,6 +128,10 @@ namespace qdcb {
 void *tmp_alloc(int device, size_t bytes, size_t *rounded);
 void tmp_release(int device, void *p, size_t rounded);
 
+// Looks up the device address of the allocation-free entry points' scratch
+// array on `device` (the current device); called when a context is created.
+void noalloc_init(int device);
+
 struct Pooled {};
 constexpr Pooled POOLED{};
 

@@ -188,6 +188,7 @@ qdcb_status qdcb_ctx_create(int device, size_t budget, qdcb_ctx **out) {
     HIPC(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) fail(QDCB_E_INVALID, "no such HIP device");
     DeviceGuard g(device);
+    noalloc_init(device);
     size_t fr = 0, tot = 0;
     HIPC(hipMemGetInfo(&fr, &tot));
     auto *c = new qdcb_ctx();

@@ -127,6 +127,7 @@ def lib():
         L.qdcb_basis_destroy.restype = None
         L.qdcb_basis_schwarz.argtypes = [_P, _DP]
         L.qdcb_eri_quartets.argtypes = [_P, _P, ctypes.c_int64, _IP, _DP]
+        L.qdcb_eri_quartets_noalloc.argtypes = [_P, _P, ctypes.c_int64, _IP, _DP]
         L.qdcb_plan_create.argtypes = [_P, _P, _P, ctypes.POINTER(PlanDesc), ctypes.POINTER(_P)]
         L.qdcb_plan_destroy.argtypes = [_P]
         L.qdcb_plan_destroy.restype = None
@@ -154,7 +155,7 @@ def lib():
         for f in ("qdcb_ctx_create", "qdcb_basis_create", "qdcb_basis_create_cart",
                   "qdcb_basis_create_rkb", "qdcb_rkb_small_planes", "qdcb_rkb_small_quat",
                   "qdcb_basis_schwarz",
-                  "qdcb_eri_quartets", "qdcb_plan_create", "qdcb_plan_footprint",
+                  "qdcb_eri_quartets", "qdcb_eri_quartets_noalloc", "qdcb_plan_create", "qdcb_plan_footprint",
                   "qdcb_transform", "qdcb_plan_fetch", "qdcb_plan_estimate",
                   "qdcb_plan_capture", "qdcb_plan_replay", "qdcb_plan_fetch_v",
                   "qdcb_plan_set_tune", "qdcb_plan_get_tune", "qdcb_plan_tune_key",
@@ -296,6 +297,18 @@ def eri_quartets(A: Basis, B: Basis, idx) -> np.ndarray:
                                    out.ctypes.data_as(_DP)))
     return out
 
+
+NOALLOC_MAX_QUARTETS = 262144  # QDCB_NOALLOC_MAX_QUARTETS
+
+
+def eri_quartets_noalloc(A: Basis, B: Basis, idx) -> np.ndarray:
+    """eri_quartets through the allocation-free entry point (at most
+    NOALLOC_MAX_QUARTETS quartets per call)."""
+    idx = np.ascontiguousarray(idx, dtype=np.int32).reshape(-1, 4)
+    out = np.empty(idx.shape[0])
+    _check(lib().qdcb_eri_quartets_noalloc(A.h, B.h, idx.shape[0], idx.ctypes.data_as(_IP),
+                                           out.ctypes.data_as(_DP)))
+    return out
 
 
 class Plan:
