@@ -157,7 +157,8 @@ __device__ __forceinline__ int gauge_sym_index(int K, int L) {
 template <int KH, int PREC, bool TENSOR = false>
 __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, int nct, int ncx,
                                                     int64_t ldK, int accumulate) {
-  constexpr int NSTEP = (TENSOR ? 3 : 1) * (TILE / KH);  // staged steps per task
+  constexpr int NS_MAX = TILE / KH;                      // steps per task and L run
+  constexpr int NSTEP = (TENSOR ? 3 : 1) * NS_MAX;        // staged steps of a full task
   constexpr int64_t SLOT = (TENSOR ? 6 : 1) * TILE * TILE;  // doubles per panel slot
   // two staging buffers as distinct objects, so that the compiler can tell
   // the loads into one from the reads of the other
@@ -198,18 +199,30 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
     const int64_t row0 = (int64_t)(bt0 + wr) * TILE;
     for (int r = 0; r < 4; ++r)
       for (int c = 0; c < 4; ++c)
-        for (int i = 0; i < 4; ++i)
-          f.acc[r][c][i] = a.V[(row0 + r * 16 + lk + 4 * i) * a.ld + vc0 + wc * 64 + c * 16 + lr];
+        for (int i = 0; i < 4; ++i) {
+          const int lr_ = r * 16 + lk + 4 * i;
+          const int64_t row = row0 + (a.perm ? a.perm[row0 + lr_] : lr_);
+          f.acc[r][c][i] = a.V[row * a.ld + vc0 + wc * 64 + c * 16 + lr];
+        }
   }
   if constexpr (PREC != PREC_F64)
     for (int r = 0; r < 4; ++r)
       for (int c = 0; c < 4; ++c) f.part[r][c] = (typename FhAcc<PREC>::V){0, 0, 0, 0};
   // bra tile bound of this wave's half (block scales of the reduced tiers)
   const double qbw = PREC != PREC_F64 ? a.Qmax[bt0 + (two ? wr : 0)] : 0.0;
+  // bra tile bounds of the pair (step skipping)
+  const double qm0 = a.sthr ? a.Qmax[bt0] : 0.0, qm1 = a.sthr && two ? a.Qmax[bt0 + 1] : 0.0;
+  const double tq = a.tau * (1.0 - 1e-12);
   int i0 = 0, i1 = 0;
-  // step state: current task's ket tile and tiles, sub-step h within the task
+  // step state: current task's ket tile and tiles, sub-step h within the task;
+  // ns = steps per L run of the task (the longer of the two bra tiles' needs),
+  // ns0 / ns1 = each bra tile's own (0 when it does not keep the task)
   const double *P0 = nullptr, *P1 = nullptr;
-  int kt = 0, h = NSTEP;
+  int kt = 0, h = NSTEP, nst = NSTEP, ns = NS_MAX, ns0 = NS_MAX, ns1 = NS_MAX;
+  // step bounds of the two list heads, loaded during the task before theirs
+  // (off the path between a barrier and the next step's loads)
+  double th0[NS_MAX - 1], th1[NS_MAX - 1];
+  int th_k0 = -1, th_k1 = -1;
   bool has0 = false, has1 = false;
   int eI = 0, eD = 0;  // block-scale exponents of the current task (this wave's half)
   // heads of the two ordered lists, read one task ahead so that the list
@@ -220,8 +233,20 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
   int nr0 = n0 > 0 && a.rank ? a.rank[l0] : 0;
   int nr1 = n1 > 0 && a.rank ? a.rank[l1] : 0;
   // advance to the next step; false when the merged lists are exhausted
+  auto load_th = [&](int k, double (&th)[NS_MAX - 1]) {
+#pragma unroll
+    for (int st = 1; st < NS_MAX; ++st) th[st - 1] = a.sthr[(int64_t)k * NS_MAX + st];
+  };
   auto advance = [&]() -> bool {
-    if (++h < NSTEP) return true;
+    if (++h < nst) {
+      if (a.sthr && h == 1) {  // the heads are known by now: their step bounds
+        th_k0 = __builtin_amdgcn_readfirstlane(nk0);
+        th_k1 = __builtin_amdgcn_readfirstlane(nk1);
+        if (th_k0 != INT_MAX) load_th(th_k0, th0);
+        if (th_k1 != INT_MAX) load_th(th_k1, th1);
+      }
+      return true;
+    }
     const int k0 = __builtin_amdgcn_readfirstlane(nk0), k1 = __builtin_amdgcn_readfirstlane(nk1);
     if (k0 == INT_MAX && k1 == INT_MAX) return false;
     kt = k0 < k1 ? k0 : k1;
@@ -249,6 +274,32 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
       eI = scale_exp(qbw * a.Qmax[kt]);
       eD = scale_exp(2.0 * a.Dtmax[kt]);
     }
+    if (a.sthr) {
+      // steps whose largest ket bound passes against the bra tile's largest Q
+      // (a prefix: the bounds decrease with the step; step 0 holds the ket
+      // tile's largest bound, which every kept task passes)
+      double th[NS_MAX - 1];
+      if (kt == th_k0) {
+#pragma unroll
+        for (int st = 0; st < NS_MAX - 1; ++st) th[st] = th0[st];
+      } else if (kt == th_k1) {
+#pragma unroll
+        for (int st = 0; st < NS_MAX - 1; ++st) th[st] = th1[st];
+      } else {
+        load_th(kt, th);  // the first task, or one that followed a one-step task
+      }
+      th_k0 = th_k1 = -1;
+      int need0 = 1, need1 = 1;
+#pragma unroll
+      for (int st = 1; st < NS_MAX; ++st) {
+        if (qm0 * th[st - 1] >= tq) need0 = st + 1;
+        if (qm1 * th[st - 1] >= tq) need1 = st + 1;
+      }
+      ns0 = has0 ? need0 : 0;
+      ns1 = has1 ? need1 : 0;
+      ns = ns0 > ns1 ? ns0 : ns1;
+      nst = (TENSOR ? 3 : 1) * ns;
+    }
     h = 0;
     return true;
   };
@@ -259,8 +310,8 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
     int hh = h;
     int64_t poff = 0, doff = 0;
     if constexpr (TENSOR) {
-      const int Lc = h / (TILE / KH);
-      hh = h - Lc * (TILE / KH);
+      const int Lc = h / ns;
+      hh = h - Lc * ns;
       poff = (int64_t)gauge_sym_index(Kt, Lc) * (TILE * TILE);
       doff = Lc * ldK;
     }
@@ -270,6 +321,7 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
       const int jj = w + 4 * q;
       if (P) load_row_lds(P + poff + (hh * KH + jj) * TILE + 2 * (lane & 31), A + jj * AS_LD);
     }
+    // density rows (stored in the tiles' row order)
     const double *Dr = a.D + ((int64_t)kt * TILE + hh * KH) * a.ld + doff + c0 + 2 * lane;
 #pragma unroll
     for (int q = 0; q < KH / 4; ++q) {
@@ -283,7 +335,10 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
     int eI, eD;
   };
   auto desc = [&]() -> StepDesc {
-    return StepDesc{wr == 0 ? has0 : has1, h == NSTEP - 1, eI, eD};
+    // this wave's bra tile: active while the step is within its own need
+    const int hh = TENSOR ? h % ns : h;
+    const int own = wr == 0 ? ns0 : ns1;
+    return StepDesc{(wr == 0 ? has0 : has1) && hh < own, hh == own - 1, eI, eD};
   };
   // one staged step: MFMAs when this wave's bra tile keeps the task; at the
   // task's last step the reduced tiers fold the scaled partial into the sum
@@ -337,10 +392,12 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         if constexpr (PREC == PREC_F64) {
-          const int64_t row = row0 + r * 16 + lk + 4 * i;
+          const int lr_ = r * 16 + lk + 4 * i;
+          const int64_t row = row0 + (a.perm ? a.perm[row0 + lr_] : lr_);
           a.V[row * a.ld + vc0 + wc * 64 + c * 16 + lr] = f.acc[r][c][i];
         } else {
-          const int64_t row = row0 + r * 16 + 4 * lk + i;
+          const int lr_ = r * 16 + 4 * lk + i;
+          const int64_t row = row0 + (a.perm ? a.perm[row0 + lr_] : lr_);
           a.V[row * a.ld + c0 + wc * 64 + c * 16 + lr] += (double)f.acc[r][c][i];
         }
       }

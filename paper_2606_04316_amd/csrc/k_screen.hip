@@ -398,4 +398,139 @@ void launch_screen_fill(int b0, int b1, int ntiles, const double *Qmax, const do
                      slot_base, tasks, task_bra);
 }
 
+// Intra-tile row order of a transform: within each 64-row tile the rows are
+// ranked by decreasing bound B = Q Dmax (ties by row), one wavefront per
+// tile.  perm[64 t + i] = the tile-local row at position i; sthr[4 t + s] =
+// the B of position 16 s, the largest of the 16 rows of step s.
+__global__ void __launch_bounds__(TILE) k_tile_order(int ntiles, const double *Q,
+                                                     const double *Dmax, int32_t *perm,
+                                                     double *sthr) {
+  const int t = blockIdx.x, i = threadIdx.x;
+  const int64_t row = (int64_t)t * TILE + i;
+  const double b = Q[row] * Dmax[row];
+  int rank = 0;
+  for (int j = 0; j < TILE; ++j) {
+    const double bj = __shfl(b, j, 64);
+    rank += (bj > b || (bj == b && j < i)) ? 1 : 0;
+  }
+  perm[(int64_t)t * TILE + rank] = i;
+  if (rank % 16 == 0) sthr[(int64_t)t * 4 + rank / 16] = b;
+}
+
+void launch_tile_order(int ntiles, const double *Q, const double *Dmax, int32_t *perm,
+                       double *sthr, hipStream_t s) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(k_tile_order, dim3(ntiles), dim3(TILE), 0, s, ntiles, Q, Dmax, perm, sthr);
+}
+
+// Row data in that order, one wavefront per tile: Q, Dmax, class, pair
+// functions and code of position i are those of row perm[i]; the primitive
+// pairs of the tile keep
+// their range [row_first[64 t], row_first[64 t + 64]) and are regrouped by
+// position (wrow_first from a wavefront scan of the permuted counts), read
+// contiguously, each written to its row's new place.
+__global__ void __launch_bounds__(TILE) k_gather_rows(int ntiles, const int32_t *perm,
+                                                      const double *Q, const double *Dmax,
+                                                      const int32_t *cls, const int32_t *mu,
+                                                      const int32_t *nu, const int32_t *code,
+                                                      const int64_t *row_first, PrimPairsC pp,
+                                                      double *wQ, double *wDmax, int32_t *wcls,
+                                                      int32_t *wmu, int32_t *wnu,
+                                                      int32_t *wcode, int64_t *wrow_first,
+                                                      PrimPairs wpp) {
+  __shared__ int64_t sfirst[TILE + 1];  // tile-local source offsets by row
+  __shared__ int64_t dfirst[TILE];      // destination offset of each source row
+  const int t = blockIdx.x, i = threadIdx.x;
+  const int64_t base = (int64_t)t * TILE;
+  const int src = perm[base + i];
+  wQ[base + i] = Q[base + src];
+  wDmax[base + i] = Dmax[base + src];
+  wcls[base + i] = cls[base + src];
+  wmu[base + i] = mu[base + src];
+  wnu[base + i] = nu[base + src];
+  if (code) wcode[base + i] = code[base + src];
+  const int64_t t0 = row_first[base], t1 = row_first[base + TILE];
+  sfirst[i] = row_first[base + i] - t0;
+  if (i == 0) sfirst[TILE] = t1 - t0;
+  __syncthreads();
+  // exclusive scan of the counts in position order
+  const int64_t c = sfirst[src + 1] - sfirst[src];
+  int64_t x = c;
+  for (int o = 1; o < TILE; o <<= 1) {
+    const int64_t y = __shfl_up(x, o, 64);
+    if (i >= o) x += y;
+  }
+  const int64_t ex = x - c;
+  wrow_first[base + i] = t0 + ex;
+  if (t == ntiles - 1 && i == TILE - 1) wrow_first[base + TILE] = t1;
+  dfirst[src] = ex;
+  __syncthreads();
+  // primitive pairs: source index g -> its row (search over sfirst) -> destination
+  const int64_t n = t1 - t0;
+  for (int64_t g = i; g < n; g += TILE) {
+    int lo = 0, hi = TILE;  // last row with sfirst <= g
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (sfirst[mid] <= g) lo = mid;
+      else hi = mid;
+    }
+    while (lo + 1 < TILE && sfirst[lo + 1] <= g) ++lo;  // skip empty rows
+    const int64_t from = t0 + g, to = t0 + dfirst[lo] + (g - sfirst[lo]);
+    wpp.ip[to] = pp.ip[from];
+    wpp.x[to] = pp.x[from];
+    wpp.y[to] = pp.y[from];
+    wpp.z[to] = pp.z[from];
+    wpp.e[to] = pp.e[from];
+    if (pp.pa) {
+      wpp.pa[to] = pp.pa[from];
+      wpp.pb[to] = pp.pb[from];
+    }
+  }
+}
+
+void launch_gather_rows(int ntiles, const int32_t *perm, const double *Q, const double *Dmax,
+                        const int32_t *cls, const int32_t *mu, const int32_t *nu,
+                        const int32_t *code, const int64_t *row_first, PrimPairsC pp, double *wQ,
+                        double *wDmax, int32_t *wcls, int32_t *wmu, int32_t *wnu,
+                        int32_t *wcode, int64_t *wrow_first, PrimPairs wpp, hipStream_t s) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(k_gather_rows, dim3(ntiles), dim3(TILE), 0, s, ntiles, perm, Q, Dmax, cls,
+                     mu, nu, code, row_first, pp, wQ, wDmax, wcls, wmu, wnu, wcode, wrow_first,
+                     wpp);
+}
+
+// First-half work of the intra-tile order: the 16-row steps the contraction
+// runs, summed over the directed tasks (bra tile b, ket tile k): 1 plus the
+// steps s >= 1 with Qmax[b] sthr[4 k + s] >= tau (1 - 1e-12), as the
+// first-half kernel counts them.  One workgroup per bra tile; *out += the sum.
+__global__ void __launch_bounds__(256) k_step_work(int ntiles, const int64_t *slot_base,
+                                                   const int32_t *count, const int32_t *tasks,
+                                                   const double *Qmax, const double *sthr,
+                                                   double tau, unsigned long long *out) {
+  __shared__ unsigned long long red[4];
+  const int b = blockIdx.x;
+  const double qb = Qmax[b], tq = tau * (1.0 - 1e-12);
+  const int64_t base = slot_base[b];
+  unsigned long long sum = 0;
+  for (int i = threadIdx.x; i < count[b]; i += 256) {
+    const int64_t k = tasks[base + i];
+    int ns = 1;
+    for (int st = 1; st < 4; ++st)
+      if (qb * sthr[k * 4 + st] >= tq) ns = st + 1;
+    sum += (unsigned long long)ns;
+  }
+  for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(out, red[0] + red[1] + red[2] + red[3]);
+}
+
+void launch_step_work(int ntiles, const int64_t *slot_base, const int32_t *count,
+                      const int32_t *tasks, const double *Qmax, const double *sthr, double tau,
+                      unsigned long long *out, hipStream_t s) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(k_step_work, dim3(ntiles), dim3(256), 0, s, ntiles, slot_base, count,
+                     tasks, Qmax, sthr, tau, out);
+}
+
 }  // namespace qdcb

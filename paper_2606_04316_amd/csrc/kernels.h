@@ -111,6 +111,27 @@ void launch_scan_counts(int ntiles, const int32_t *count, int64_t *slot_base, in
 // Zero n 64-bit counters with a kernel (safe inside captured graphs).
 void launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
 
+// Intra-tile row order (k_screen.hip): within each tile, rows ranked by
+// decreasing Q Dmax (ties by row): perm[64 t + i] = the tile-local row at
+// position i, sthr[4 t + s] = the Q Dmax at position 16 s.
+void launch_tile_order(int ntiles, const double *Q, const double *Dmax, int32_t *perm,
+                       double *sthr, hipStream_t s);
+// Row data in that order: wQ, wDmax, wcls, wmu, wnu (and wcode when code is
+// set) of position i are row perm[i]'s; each tile's primitive pairs keep the
+// tile's range and are regrouped by position (wrow_first, wpp).
+void launch_gather_rows(int ntiles, const int32_t *perm, const double *Q, const double *Dmax,
+                        const int32_t *cls, const int32_t *mu, const int32_t *nu,
+                        const int32_t *code, const int64_t *row_first, PrimPairsC pp, double *wQ,
+                        double *wDmax, int32_t *wcls, int32_t *wmu, int32_t *wnu,
+                        int32_t *wcode, int64_t *wrow_first, PrimPairs wpp, hipStream_t s);
+
+// *out += the 16-row steps the first half runs over the directed task lists
+// with that order (per task: 1 + the steps s >= 1 that pass against the bra
+// tile's Qmax).
+void launch_step_work(int ntiles, const int64_t *slot_base, const int32_t *count,
+                      const int32_t *tasks, const double *Qmax, const double *sthr, double tau,
+                      unsigned long long *out, hipStream_t s);
+
 // ---- AO integral tiles (k_eri.hip)
 struct EriTileArgs {
   const int64_t *d_total = nullptr;  // graph mode: slots beyond *d_total (or the
@@ -192,6 +213,16 @@ struct FirstHalfArgs {
   // workgroup order: 0 = XCD-aware (with at least 8 column slices), 1 = plain
   // (bra-tile pairs fastest); the order does not change any result
   int plain_order = 0;
+  // intra-tile row order of the integral tiles and density rows (NULL: the
+  // rows' own order): position i of tile t is row 64 t + perm[64 t + i], and V
+  // rows are written (and, when adding, read) through it.  sthr[4 t + s]: the
+  // largest Q Dmax of the 16 rows of step s of tile t in that order
+  // (decreasing in s); a task skips the steps whose rows fail the predicate
+  // against every bra row of its tile (Qmax[bra tile] * sthr < tau (1 - 1e-12)):
+  // their integrals are masked zeros, so the result is the same bits.
+  const int32_t *perm = nullptr;
+  const double *sthr = nullptr;
+  double tau = 0.0;
 };
 void launch_first_half(const FirstHalfArgs &a, hipStream_t s);
 // Gauge term (FP64): V[mn][K ldK + col] (+)= sum_L sum_kl B_KL(mn, kl)

@@ -26,6 +26,14 @@ struct Space {
   // columns (ld = nK ldK), packed to the chunk's width; ld_cap = the allocation
   int64_t ldK = 0, ld = 0, ld_cap = 0;
   DBuf<double> D, V, Dmax, Qmax, Bmax, Dtmax;
+  // intra-tile row order of the current transform (rows ranked by Q Dmax
+  // within each tile) and the row data of the integral tiles in that order
+  DBuf<int32_t> perm, wcls, wmu, wnu, wcode;
+  DBuf<double> sthr, wQ, wDmax;
+  DBuf<int64_t> wrow_first;
+  PairStore wpp;
+  DBuf<unsigned long long> steps;  // first-half steps of the task lists (eager)
+  unsigned long long h_steps = 0;
   // mixed precision: per-tier sub-lists of the directed tasks
   DBuf<int32_t> ttasks, trank, tcount, toff;
   std::vector<int32_t> h_tcount;
@@ -58,7 +66,9 @@ struct Space {
 
   size_t bytes() const {
     return cls.bytes() + mu.bytes() + nu.bytes() + row_first.bytes() + Q.bytes() + pp.bytes() +
-           code.bytes() +
+           code.bytes() + perm.bytes() + wcls.bytes() + wmu.bytes() + wnu.bytes() + wcode.bytes() +
+           sthr.bytes() +
+           wQ.bytes() + wDmax.bytes() + wrow_first.bytes() + wpp.bytes() + steps.bytes() +
            D.bytes() + V.bytes() + Dmax.bytes() + Qmax.bytes() + Bmax.bytes() + Dtmax.bytes() +
            ttasks.bytes() + trank.bytes() + tcount.bytes() + toff.bytes() + count.bytes() +
            tasks.bytes() + task_bra.bytes() + slot_base.bytes() + panel.bytes() + panel3.bytes() + kept.bytes() +
@@ -119,6 +129,10 @@ struct qdcb_plan {
   qdcb::DBuf<double> boys;   // Taylor table of the Boys function F0
   qdcb::DBuf<double> boys3;  // F0 .. F9 on the same grid (gauge tiles)
   bool cart = false;         // a basis has p functions: Cartesian integral tiles
+  // integral tiles in the intra-tile row order of each transform, first half
+  // skipping masked 16-row steps (environment QDCB_TILE_ORDER=0 at plan
+  // creation turns it off, for comparisons)
+  bool tile_order = true;
   qdcb::DBuf<double> boysc;  // F0 .. F11 on the same grid (Cartesian tiles)
   bool have_last = false;
   int64_t tiles_made = 0;  // integral tiles generated by the last eager transform

@@ -134,6 +134,18 @@ void build_space(qdcb_ctx *ctx, Space &sp, std::vector<RowSrc> &rows,
     HIPC(hipStreamSynchronize(nullptr));
   }
   sp.Dmax.alloc(ctx, sp.Ppad);
+  // intra-tile row order buffers (row data of the integral tiles in that order)
+  sp.perm.alloc(ctx, sp.Ppad);
+  sp.sthr.alloc(ctx, (size_t)sp.ntiles * 4);
+  sp.wQ.alloc(ctx, sp.Ppad);
+  sp.wDmax.alloc(ctx, sp.Ppad);
+  sp.wcls.alloc(ctx, sp.Ppad);
+  sp.wmu.alloc(ctx, sp.Ppad);
+  sp.wnu.alloc(ctx, sp.Ppad);
+  if (cart) sp.wcode.alloc(ctx, sp.Ppad);
+  sp.wrow_first.alloc(ctx, sp.Ppad + 1);
+  sp.wpp.alloc(ctx, (size_t)std::max<int64_t>(rf[sp.Ppad], 1), cart);
+  sp.steps.alloc(ctx, 1);
   sp.Qmax.alloc(ctx, sp.ntiles);
   sp.Bmax.alloc(ctx, sp.ntiles);
   sp.count.alloc(ctx, sp.ntiles);
@@ -414,6 +426,10 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
     p.gauge = desc->ham == QDCB_HAM_DCB;
     p.fused_breit = p.gauge && desc->prec == QDCB_PREC_FP64;
     p.cart = L->has_p() || (S && S->has_p());
+    {
+      const char *e = std::getenv("QDCB_TILE_ORDER");
+      p.tile_order = !(e && e[0] == '0');
+    }
     if (p.cart && p.gauge)
       fail(QDCB_E_UNSUPPORTED, "the gauge term takes s functions only");
     p.spinor = desc->flags & QDCB_PLAN_SPINOR;
@@ -640,8 +656,8 @@ qdcb_status qdcb_plan_estimate(const qdcb_basis *L, const qdcb_basis *S,
     const bool cart = L->has_p() || (S && S->has_p());
     if (cart && desc->ham == QDCB_HAM_DCB)
       fail(QDCB_E_UNSUPPORTED, "the gauge term takes s functions only");
-    double b = (cart ? 56.0 : 40.0) * prims;              // primitive-pair data
-    b += 48.0 * (PC + PG);                                // row metadata
+    double b = 2.0 * (cart ? 56.0 : 40.0) * prims;        // primitive-pair data (two orders)
+    b += 88.0 * (PC + PG);                                // row metadata
     b += 16.0 * (PC * ldK + 3.0 * PG * ldK);              // D~ and V, all columns
     b += 22.0 * (ntC * ntC + ntG * ntG);                  // task lists, unique pairs, slot map
     if (desc->prec == QDCB_PREC_MIXED) b += 8.0 * (ntC * ntC + ntG * ntG);  // tier sub-lists

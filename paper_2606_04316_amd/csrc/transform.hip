@@ -89,8 +89,11 @@ struct StageTimer {
   }
 };
 
+// The bound pass (bound_only) reads the rows in their own order (Dmax by
+// row); the density rows are written in the transform's intra-tile order.
 void density(qdcb_plan &p, Space &sp, const double *dCL, const double *dCS, int bound_only,
              int i0, int i1, hipStream_t s) {
+  const bool w = p.tile_order && !bound_only;
   DensityArgs da;
   da.gaunt = sp.gaunt;
   da.bound_only = bound_only;
@@ -101,9 +104,9 @@ void density(qdcb_plan &p, Space &sp, const double *dCL, const double *dCS, int 
   da.i1 = i1;
   da.ld = sp.ld;
   da.ldK = sp.ldK;
-  da.cls = sp.cls.p;
-  da.mu = sp.mu.p;
-  da.nu = sp.nu.p;
+  da.cls = w ? sp.wcls.p : sp.cls.p;
+  da.mu = w ? sp.wmu.p : sp.mu.p;
+  da.nu = w ? sp.wnu.p : sp.nu.p;
   da.CL = dCL;
   da.CS = dCS;
   da.NL = p.NL;
@@ -114,6 +117,18 @@ void density(qdcb_plan &p, Space &sp, const double *dCL, const double *dCS, int 
   da.spinor = p.spinor ? 1 : 0;
   da.nspair = p.npair_s;
   launch_density(da, s);
+  HIPC(hipGetLastError());
+}
+
+// Intra-tile row order after a density bound: rows ranked by Q Dmax within
+// each tile, and the integral tiles' row data gathered in that order.
+void order_rows(qdcb_plan &p, Space &sp, hipStream_t s) {
+  if (!p.tile_order) return;
+  launch_tile_order(sp.ntiles, sp.Q.p, sp.Dmax.p, sp.perm.p, sp.sthr.p, s);
+  launch_gather_rows(sp.ntiles, sp.perm.p, sp.Q.p, sp.Dmax.p, sp.cls.p, sp.mu.p, sp.nu.p,
+                     p.cart ? sp.code.p : nullptr, sp.row_first.p, sp.pp.cview(), sp.wQ.p,
+                     sp.wDmax.p, sp.wcls.p, sp.wmu.p, sp.wnu.p, p.cart ? sp.wcode.p : nullptr,
+                     sp.wrow_first.p, sp.wpp.view(), s);
   HIPC(hipGetLastError());
 }
 
@@ -148,6 +163,17 @@ void screen(qdcb_plan &p, Space &sp, bool captured, hipStream_t s, bool zero_kep
                      sp.tasks.p, sp.task_bra.p, s);
   if (zero_kept) launch_zero_u64(sp.kept.p, 4, s);
   HIPC(hipGetLastError());
+  sp.h_steps = 4ull * (unsigned long long)sp.total;  // every task in full
+  if (p.tile_order && !captured) {
+    // the steps the first half runs with the intra-tile order (MFMA work)
+    launch_zero_u64(sp.steps.p, 1, s);
+    launch_step_work(sp.ntiles, sp.slot_base.p, sp.count.p, sp.tasks.p, sp.Qmax.p, sp.sthr.p,
+                     p.desc.tau, sp.steps.p, s);
+    HIPC(hipGetLastError());
+    HIPC(hipMemcpyAsync(&sp.h_steps, sp.steps.p, sizeof(unsigned long long),
+                        hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+  }
   if (p.desc.prec == QDCB_PREC_MIXED) {
     launch_tier_split(sp.ntiles, sp.Qmax.p, sp.Bmax.p,
                       (p.desc.flags & QDCB_PLAN_TIER_BY_G) ? 1 : 0, p.desc.tier_fp32,
@@ -209,17 +235,19 @@ EriTileArgs eri_args(qdcb_plan &p, Space &sp, int64_t slot0, bool count, bool ga
   ea.tasks = sp.tasks.p;
   ea.task_bra = sp.task_bra.p;
   ea.slot0 = slot0;
-  ea.row_first = sp.row_first.p;
-  ea.pp = sp.pp.cview();
-  ea.Q = sp.Q.p;
-  ea.Dmax = sp.Dmax.p;
-  ea.cls = sp.cls.p;
+  // the tiles' rows in the transform's intra-tile order (order_rows)
+  const bool w = p.tile_order;
+  ea.row_first = w ? sp.wrow_first.p : sp.row_first.p;
+  ea.pp = w ? sp.wpp.cview() : sp.pp.cview();
+  ea.Q = w ? sp.wQ.p : sp.Q.p;
+  ea.Dmax = w ? sp.wDmax.p : sp.Dmax.p;
+  ea.cls = w ? sp.wcls.p : sp.cls.p;
   ea.tau = p.desc.tau;
   ea.panel = gauge ? sp.panel3.p : sp.pan();
   ea.kept = count ? sp.kept.p : nullptr;
   ea.boys = p.boys.p;
   ea.boys3 = gauge ? p.boys3.p : nullptr;
-  ea.code = p.cart ? sp.code.p : nullptr;
+  ea.code = p.cart ? (w ? sp.wcode.p : sp.code.p) : nullptr;
   ea.boysc = p.cart ? p.boysc.p : nullptr;
   if (p.cart && (!ea.code || !ea.boysc || !sp.pp.pa.p || gauge))
     fail(QDCB_E_DEVICE, "Cartesian tiles without their codes, table or pair data");
@@ -228,8 +256,15 @@ EriTileArgs eri_args(qdcb_plan &p, Space &sp, int64_t slot0, bool count, bool ga
   return ea;
 }
 
-FirstHalfArgs fh_args(Space &sp, int b0, int b1, int64_t slot0, bool gauge = false) {
+FirstHalfArgs fh_args(qdcb_plan &p, Space &sp, int b0, int b1, int64_t slot0,
+                      bool gauge = false) {
   FirstHalfArgs fa;
+  if (p.tile_order) {
+    fa.perm = sp.perm.p;
+    fa.sthr = sp.sthr.p;
+    fa.tau = p.desc.tau;
+    fa.Qmax = sp.Qmax.p;
+  }
   fa.b0 = b0;
   fa.b1 = b1;
   fa.slot_base = sp.slot_base.p;
@@ -335,7 +370,7 @@ void first_half(qdcb_plan &p, Space &sp, bool make_tiles, bool count, bool captu
       }
       HIPC(hipGetLastError());
     }
-    FirstHalfArgs fa = fh_args(sp, 0, sp.ntiles, 0, g3);
+    FirstHalfArgs fa = fh_args(p, sp, 0, sp.ntiles, 0, g3);
     if (captured) fa.overflow = sp.overflow.p;
     contract(p, sp, fa, tm, s, gauge);
     return;
@@ -351,7 +386,7 @@ void first_half(qdcb_plan &p, Space &sp, bool make_tiles, bool count, bool captu
       else
         launch_eri_tiles(ea, n, s);
     }
-    FirstHalfArgs fa = fh_args(sp, 0, sp.ntiles, 0, g3);
+    FirstHalfArgs fa = fh_args(p, sp, 0, sp.ntiles, 0, g3);
     fa.overflow = sp.overflow.p;
     contract(p, sp, fa, tm, s, gauge);
     return;
@@ -410,7 +445,7 @@ void first_half(qdcb_plan &p, Space &sp, bool make_tiles, bool count, bool captu
         HIPC(hipStreamWaitEvent(s, made[i], 0));
       }
     }
-    FirstHalfArgs fa = fh_args(sp, B.b0, B.b1, sp.base[B.b0], g3);
+    FirstHalfArgs fa = fh_args(p, sp, B.b0, B.b1, sp.base[B.b0], g3);
     fa.panel = panel;
     contract(p, sp, fa, tm, s, gauge);
     if (pipe && !resident_all) done[i] = tm.record(s);
@@ -576,6 +611,7 @@ void enqueue(qdcb_plan &p, const double *dCL, const double *dCS, double *dG, boo
     density(p, *sp, dCL, dCS, 1, 0, p.npair_mo, s);
     tm.end();
     tm.begin(ST_SCREEN);
+    order_rows(p, *sp, s);
     screen(p, *sp, captured, s);
     tm.end();
   }
@@ -632,13 +668,14 @@ void enqueue(qdcb_plan &p, const double *dCL, const double *dCS, double *dG, boo
         density(p, *sp, dCL, dCS, 1, i0, i1, s);
         tm.end();
         tm.begin(ST_SCREEN);
+        order_rows(p, *sp, s);
         screen(p, *sp, false, s, false);  // kept counts add up over the batches
         tm.end();
         sp->sym = !(p.desc.flags & QDCB_PLAN_DIRECTED_TILES) && sp->total <= sp->panel_slots;
       }
     for (Space *sp : spaces) {
       p.ld_sum[sp == &p.G ? 1 : 0] += (double)sp->ld;
-      if (mo) p.mo_work += (double)sp->ld * (double)sp->total;
+      if (mo) p.mo_work += (double)sp->ld * 0.25 * (double)sp->h_steps;
       tm.begin(ST_DENS);
       density(p, *sp, dCL, dCS, 0, i0, i1, s);
       tm.end();
@@ -719,10 +756,12 @@ void fill_stats(qdcb_plan &p, qdcb_stats *stats, StageTimer *tm, double ms_total
   // row width (3 K blocks) counts once for Gaunt and three times for the gauge
   // term (three L blocks per K block)
   const double gw = ls_mult / 3.0;
+  // (tiles as run: with the intra-tile order, the steps each task runs / 4)
+  const double run_c = p.tile_order && tm ? 0.25 * (double)p.C.h_steps : (double)tiles_c;
+  const double run_g = p.tile_order && tm ? 0.25 * (double)p.G.h_steps : (double)tiles_g;
   stats->flops_mfma = 2.0 * TILE * TILE *
                       (p.mo_batch > 0 && tm ? p.mo_work
-                                            : p.ld_sum[0] * (double)tiles_c +
-                                                  gw * p.ld_sum[1] * (double)tiles_g);
+                                            : p.ld_sum[0] * run_c + gw * p.ld_sum[1] * run_g);
   stats->classes = p.classes;
   if (p.desc.prec == QDCB_PREC_MIXED) {
     for (Space *sp : {&p.C, &p.G}) {

@@ -3,8 +3,8 @@ oracle's MO-driven route: each batch of MO pairs is screened with the density
 bound of its own pairs, so the kept contributions (exact counts, summed over
 the batches) and G (parity tolerance of test_gpu_parity.py) follow the
 oracle's batches.  At tau = 0 every batch keeps everything and the variant
-equals the AO-driven transformation bitwise (same tiles, same per-column
-summation order).
+equals the AO-driven transformation to rounding (same tiles and products;
+each batch orders a tile's rows by its own bound).
 """
 import numpy as np
 import pytest
@@ -60,14 +60,19 @@ def test_mo_driven_matches_oracle(q, ctx, ham, batch, tau):
 
 
 def test_mo_driven_at_zero_threshold_is_the_ao_transform(q, ctx):
+    # at tau = 0 every batch keeps every contribution: the same integrals and
+    # products as the AO-driven transform, summed in another order within a
+    # tile (each batch ranks a tile's rows by its own bound), so equal to
+    # rounding (well-conditioned coefficients: relative to max|G|)
     s = wl.linear_chain(seed=57, n_atoms=5, spacing=3.0, nl_per_atom=3, ns_per_atom=4, n=6,
-                        tau=0.0, ham="DCG")
+                        tau=0.0, ham="DCG", coefs="qr")
     L, S = q.Basis(ctx, s.L), q.Basis(ctx, s.S)
-    Ga, _ = q.Plan(ctx, L, S, "DCG", s.n_mo, 0.0).transform(s.CL, s.CS)
+    Ga, sa = q.Plan(ctx, L, S, "DCG", s.n_mo, 0.0).transform(s.CL, s.CS)
     plan = q.Plan(ctx, L, S, "DCG", s.n_mo, 0.0)
     plan.set_mo_batch(5)
     G, st = plan.transform(s.CL, s.CS)
-    assert np.array_equal(G, Ga)
+    assert st["n_chunks"] > 1
+    assert np.abs(G - Ga).max() <= 1e-13 * np.abs(Ga).max()
     # not offered: captures of the variant, spinor plans
     import torch
     dev = torch.device("cuda:0")

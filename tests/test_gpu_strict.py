@@ -310,3 +310,55 @@ def test_graph_replays_strict(q, ham):
         _strict(G.cpu().numpy(), Go, f"{ham} replay {k}")
     plan.close()
     c.close()
+
+
+@pytest.mark.parametrize("case", ["DC", "DCG", "DCB", "mixed", "spinor"])
+def test_intra_tile_row_order_on_and_off(q, ctx, case, monkeypatch):
+    # the intra-tile row order (rows of each tile ranked by Q Dmax per
+    # transform, masked 16-row steps skipped) against plans created with it
+    # turned off: the same kept contributions, both at oracle parity, and no
+    # more first-half MFMA work than without
+    if case == "DCG":
+        s = wl.cluster(seed=41, n_atoms=5, nl_per_atom=2, ns_per_atom=3, n=3, radius=5.0,
+                       min_sep=1.5, tau=1e-10, ham="DCG", coefs="qr")
+    elif case == "DCB":
+        s = _chain(64, n_atoms=6, n=6, tau=1e-10, ham="DCB")
+    else:
+        s = _chain(34, n_atoms=8, spacing=4.0, nl=3, ns=6, n=6, tau=1e-10)
+    L, S = _bases(q, ctx, s)
+    kw = {}
+    if case == "mixed":
+        kw = dict(prec="mixed", tier_fp32=1e-3, tier_bf16=0.0)
+    flags = q.PLAN_SPINOR if case == "spinor" else 0
+    if case == "spinor":
+        PL, PS, _ = wl.general_spinors(s, 7, seed=5)
+        Go, so = oracle.transform_spinor(s.L, s.S, PL, PS, s.ham, s.tau)
+        inputs, m = (PL, PS), 7
+    else:
+        Go, so = oracle.transform_direct(s.L, s.S, s.CL, s.CS, s.ham, s.tau)
+        inputs, m = (s.CL, s.CS), s.n_mo
+    res = {}
+    for on in (True, False):
+        if on:
+            monkeypatch.delenv("QDCB_TILE_ORDER", raising=False)
+        else:
+            monkeypatch.setenv("QDCB_TILE_ORDER", "0")
+        plan = q.Plan(ctx, L, S, s.ham, m, s.tau, flags=flags, **kw)
+        G, st = plan.transform(*inputs)
+        plan.close()
+        if case == "spinor":
+            G = G[..., 0] + 1j * G[..., 1]
+        res[on] = (G, st)
+    monkeypatch.delenv("QDCB_TILE_ORDER", raising=False)
+    (G1, s1), (G0, s0) = res[True], res[False]
+    assert s1["kept"] == s0["kept"] == so["kept"] and s1["kept_gaunt"] == s0["kept_gaunt"]
+    assert s1["tiles_kept"] == s0["tiles_kept"]
+    print(f"{case}: MFMA work with / without the order {s1['flops_mfma']:.4e} / "
+          f"{s0['flops_mfma']:.4e}, fill {s1['flops_first_half'] / s1['flops_mfma']:.3f} / "
+          f"{s0['flops_first_half'] / s0['flops_mfma']:.3f}")
+    assert s1["flops_mfma"] <= s0["flops_mfma"]
+    if case == "mixed":
+        assert np.abs(G1 - G0).max() <= 1e-6 * np.abs(Go).max()
+    else:
+        _strict(G1, Go, f"{case} with the intra-tile order")
+        _strict(G0, Go, f"{case} without")
