@@ -18,11 +18,19 @@ The JSON line also carries
   cpu_baseline  the FP64 oracle on a seeded sample of bra pairs (first half
                 only), scaled to the whole transformation.
   mfma_util     the first half's algorithmic FP64 flop rate over the MFMA peak.
-  mixed_vs_fp64 the same transformation with reduced-precision tiers (1e-6 /
-                1e-9, bound including the bra side), its speedup and its
-                max |G_mixed - G_fp64| (Eh).
-  serving       the request stream (256 requests, 20 ms mean gap), p50/p99.
-The last two legs are skipped with --no-legs (profiling runs).
+  cluster       the compact-cluster configuration (60 atoms, N_L 600, N_S 1200,
+                contraction depths 1..6, n 128, Dirac-Coulomb + Gaunt): FP64
+                transforms with their own roofline, and the mixed-precision
+                transform of the same inputs at the specified tiers (1e-4 /
+                1e-7, screening bound) and at tiers that meet 1e-10 Eh
+                (1e-6 / 1e-9, bound including the bra side): speedup, max
+                |G_mixed - G_FP64 GPU| and the occupied Coulomb sum change.
+  serving       the request stream (256 requests, 20 ms mean gap), p50/p99,
+                with the size ranges it draws from.
+The cluster and serving legs are skipped with --no-legs (profiling runs).
+The headline value is the chain's: one cluster transform takes about 33 s,
+so the 25 transforms of the default warm-up and timed steps do not fit the
+run's time; the cluster leg times two.
 """
 import argparse
 import json
@@ -36,7 +44,6 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_MFMA = 78.6  # TFLOP/s, MI355X dense FP64 matrix
 HEADLINE_METRIC = ("MO integrals/s & MFMA util, mixed vs FP64 at <=1e-10 Eh err; "
                    "serving p99 ms")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "first_half_chain40_traffic.json")
 
 
 def parse():
@@ -53,12 +60,16 @@ def parse():
                          "(rule screen = screening bound, g = bound including the bra side)")
     ap.add_argument("--workload", default=None,
                     help="transform: chain40 (default), cluster60, ll24, or <name>_spinor "
-                         "(2 n general two-spinor MOs); replay: cluster24 (default), "
-                         "chain40_dcg, chain40")
+                         "(2 n general two-spinor MOs), <name>_rkb (RKB small components, "
+                         "n general two-spinors), <name>_rkbq (RKB small components, n / 2 "
+                         "Kramers pairs through a quaternion plan); replay: cluster24 "
+                         "(default), chain40_dcg, chain40")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-legs", action="store_true",
                     help="transform: skip the mixed-precision and serving legs of the line")
     ap.add_argument("--cpu-rows", type=int, default=96)
+    ap.add_argument("--cluster-steps", type=int, default=2,
+                    help="transform: timed FP64 transforms of the cluster leg")
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--serving-prec", default="fp64,mixed",
                     help="serving: precisions to serve the stream in, one run each "
@@ -84,6 +95,37 @@ def parse():
     return ap.parse_args()
 
 
+def cpu_model():
+    """The host CPU's model name (Linux), for the baseline's record."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# The paper's own timings (all on CPUs, none on GPUs), quoted as context with
+# their hardware; none is on this build's synthetic workloads.
+PAPER_TIMINGS = {
+    "source": "arXiv 2606.04316, Sec. 3.3",
+    "Au6_DCB": {"system": "planar Au6, dyall-ae2z, 1278 basis functions, 48 MO spinors, DCB",
+                "wall_time_h": 14.0,
+                "hardware": "2048 CPU cores (16 nodes x 128 AMD EPYC 7742)",
+                "spinor_MO_integrals_per_s_derived": 48 ** 4 / (14.0 * 3600)},
+    "Pu3_stage_s": {"system": "Pu3 chain, dyall-v2z (846 basis functions), 16 orbitals per "
+                              "atom, tau 1e-12",
+                    "columns": ["DC-SSSS", "DC", "Gaunt", "gauge"],
+                    "AO_integrals": [9.13, 21.89, 18.68, 253.4],
+                    "density": [61.49, 31.1, 61.88, 60.67],
+                    "first_half": [2969.0, 804.8, 9215.0, 9556.0],
+                    "second_half": [24.85, 17.48, 35.22, 34.91],
+                    "hardware": "CPU cluster nodes (Hyak / Bridges-2), core count not stated"},
+}
+
+
 def cpu_baseline(sysm, n_rows, n):
     import numpy as np
     import oracle
@@ -94,7 +136,7 @@ def cpu_baseline(sysm, n_rows, n):
     t_sample = st["seconds_first_half"]
     t_full = t_sample * P / len(rows)
     return {"value": n ** 4 / t_full, "unit": "quaternion MO integrals (pq|rs)/s",
-            "cores": st["threads"], "kind": "oracle",
+            "cores": st["threads"], "cpu_model": cpu_model(), "kind": "oracle",
             "sample": (f"oracle first half (screened ERIs + density contraction, all "
                        f"{4 * n * n} spinor-pair columns) for {len(rows)} of {P} bra pairs "
                        f"drawn with seed 0, {t_sample:.2f} s, scaled by {P}/{len(rows)} to "
@@ -140,12 +182,18 @@ def main_transform(args):
     # system's Kramers pairs mixed by a seeded unitary), a QDCB_PLAN_SPINOR plan.
     # "<name>_rkb": the system's L basis with RKB small components (its
     # gradient basis as S) and n general two-spinors, a QDCB_PLAN_SPINOR plan
+    # "<name>_rkbq": the same RKB small components in Kramers-restricted form,
+    # n_mo / 2 quaternion MOs (the same number of spinors as "<name>_rkb")
+    # through a quaternion plan
     rkb = args.workload.endswith("_rkb")
+    rkbq = args.workload.endswith("_rkbq")
     spinor = args.workload.endswith("_spinor") or rkb
     base = args.workload[:-len("_spinor")] if args.workload.endswith("_spinor") else \
-        args.workload[:-len("_rkb")] if rkb else args.workload
+        args.workload[:-len("_rkb")] if rkb else \
+        args.workload[:-len("_rkbq")] if rkbq else args.workload
     sysm = wl.config(base)
-    n = sysm.n_mo if rkb else 2 * sysm.n_mo if spinor else sysm.n_mo
+    n = sysm.n_mo if rkb else 2 * sysm.n_mo if spinor else \
+        sysm.n_mo // 2 if rkbq else sysm.n_mo
     dev = torch.device("cuda:0")
     # output and inputs first: the context's default budget is a share of
     # what is free when it is created
@@ -161,6 +209,12 @@ def main_transform(args):
     elif spinor:
         PL, PS, _ = wl.general_spinors(sysm, n, seed=0)
         G = torch.empty((n, n, n, n, 2), dtype=torch.float64, device=dev)
+    elif rkbq:
+        # n quaternion-orthonormal MOs over the L and RKB S coefficients
+        NLr = sysm.L.nfunc
+        Q = wl.quat_qr_plus(wl.gaussian_quat(np.random.default_rng(8000), 2 * NLr, n))
+        PL, PS = np.ascontiguousarray(Q[:, :NLr]), np.ascontiguousarray(Q[:, NLr:])
+        G = torch.empty((n, n, n, n, 4, 4), dtype=torch.float64, device=dev)
     else:
         PL, PS = sysm.CL, sysm.CS
         G = torch.empty((n, n, n, n, 4, 4), dtype=torch.float64, device=dev)
@@ -171,6 +225,9 @@ def main_transform(args):
     if rkb:
         S, norms = qdcb.rkb_basis(ctx, L)
         CS = torch.from_numpy(qdcb.rkb_small_planes(PS, norms, wl.SPEED_OF_LIGHT)).to(dev)
+    elif rkbq:
+        S, norms = qdcb.rkb_basis(ctx, L)
+        CS = torch.from_numpy(qdcb.rkb_small_quat(PS, norms, wl.SPEED_OF_LIGHT)).to(dev)
     else:
         S = qdcb.Basis(ctx, sysm.S) if sysm.S is not None else None
     plan = qdcb.Plan(ctx, L, S, sysm.ham, n, sysm.tau,
@@ -206,16 +263,10 @@ def main_transform(args):
     fh_launch = sum(s["n_batches"] for s in stats)
     fh_flops = sum(s["flops_first_half"] for s in stats)
     achieved = fh_flops / (fh_ms * 1e-3) / 1e12
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as f:
-            tr = json.load(f)
-        if (tr.get("workload") == args.workload and tr.get("kernel_rev") == qdcb_kernel_rev()
-                and tr.get("fh_order") == plan.tune["fh_order"]):
-            traffic = tr.get("bytes_per_launch")
+    traffic = committed_traffic(args.workload, plan.tune)
     st0 = stats[-1]
     kind = "complex spinor" if spinor else "quaternion"
-    headline = (not spinor and not args.mo_batch and sysm.ham != "DCB"
+    headline = (not spinor and not rkbq and not args.mo_batch and sysm.ham != "DCB"
                 and getattr(sysm.L, "cart", None) is None)
     line = {
         "metric": HEADLINE_METRIC if headline else f"MO integrals/s ({kind} (pq|rs), FP64)",
@@ -224,10 +275,11 @@ def main_transform(args):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": sysm.name + ("_rkb" if rkb else "_spinor" if spinor else ""),
+        "config": {"workload": sysm.name + ("_rkb" if rkb else "_rkbq" if rkbq else
+                                            "_spinor" if spinor else ""),
                    "n_atoms": int(sysm.atoms.shape[0]),
                    "N_L": sysm.L.nfunc,
-                   "N_S": 3 * sysm.L.nfunc if rkb else
+                   "N_S": 3 * sysm.L.nfunc if rkb or rkbq else
                    sysm.S.nfunc if sysm.S is not None else 0,
                    "n_mo": n, "mo_kind": "general spinors" if spinor else "Kramers pairs",
                    "ham": sysm.ham, "tau": sysm.tau,
@@ -235,7 +287,8 @@ def main_transform(args):
                    if args.mo_batch else "AO-driven",
                    "row_order": "primitive bands" if args.prim_bands else "Schwarz",
                    "shells": "s, p" if getattr(sysm.L, "cart", None) is not None else "s",
-                   "small_components": "RKB (gradient basis)" if rkb else "stand-in basis"},
+                   "small_components": "RKB (gradient basis)" if rkb else
+                   "RKB (gradient basis), Kramers-restricted" if rkbq else "stand-in basis"},
         "spinor_integrals_per_s": (n if spinor else 2 * n) ** 4 * args.steps / elapsed,
         "stages_ms": {k: st0[k] for k in ("ms_density", "ms_screen", "ms_eri", "ms_first_half",
                                           "ms_second_half", "ms_total")},
@@ -251,37 +304,21 @@ def main_transform(args):
                          "basis": "algorithmic FP64 flops of k_first_half over its launch time, "
                                   "against the dense FP64 MFMA peak"}
     if headline and not args.no_legs:
-        # mixed precision vs FP64 on the same inputs, at tiers that meet 1e-10 Eh here
-        t32, t16 = 1e-6, 1e-9
-        mp = qdcb.Plan(ctx, L, S, sysm.ham, n, sysm.tau, prec="mixed", tier_fp32=t32,
-                       tier_bf16=t16, flags=qdcb.PLAN_TIER_BY_G)
-        mp.tune = plan.tune
-        G2 = torch.empty_like(G)
-        mp.transform(CL, CS, G2)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(args.steps):
-            _, stm = mp.transform(CL, CS, G2)
-        torch.cuda.synchronize()
-        ms_mixed = 1e3 * (time.perf_counter() - t1) / args.steps
-        err = max(float((G2[p] - G[p]).abs().max()) for p in range(n))
-        line["mixed_vs_fp64"] = {"tier_fp32": t32, "tier_bf16": t16, "rule": "g",
-                                 "ms_fp64": ms, "ms_mixed": ms_mixed, "speedup": ms / ms_mixed,
-                                 "max_abs_err_Eh": err, "meets_1e-10": err <= 1e-10,
-                                 "tiles_tier": stm["tiles_tier"]}
-        print(f"mixed leg: {ms_mixed:.1f} ms, max|dG| {err:.2e}", file=sys.stderr, flush=True)
-        mp.close()
-        del G2
-    if not args.no_cpu_baseline and not spinor:
-        print("cpu baseline: oracle sample ...", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(sysm, args.cpu_rows, n)
-    if headline and not args.no_legs:
-        # the serving stream (FP64), after this run's plan has released its memory
+        # the compact-cluster configuration (FP64 and mixed precision), after
+        # this run's plan has released its memory
         plan.close()
         ctx.close()
         del G
         torch.cuda.empty_cache()
+        line["cluster"] = cluster_leg(args)
+    if not args.no_cpu_baseline and not spinor and not rkbq:
+        print("cpu baseline: oracle sample ...", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(sysm, args.cpu_rows, n)
+    if headline and not args.no_legs:
+        # the serving stream (FP64)
         line["serving"] = serving_run(args, "fp64")
+    if headline:
+        line["paper_timings"] = PAPER_TIMINGS
     print(json.dumps(line), flush=True)
 
 
@@ -446,7 +483,12 @@ def serving_run(args, prec):
         same += (r.error is None and
                  alone(solo, 0)["digest"] == r.result["digest"])
     alone.drain()
-    summ.update({"slots": args.slots, "max_concurrency": srv.max_concurrency,
+    summ.update({"stream": {"arrivals": "Poisson, mean gap 20 ms", "atoms": [10, 40],
+                            "N_L": [40, 160], "N_S": "2 N_L", "n_mo": [8, 32],
+                            "contraction_depths": [1, 6], "ham": "DC or DCG, 50/50",
+                            "tau": 1e-10, "pool": 12,
+                            "note": "reduced from 10-80 atoms, N_L 100-800, n_mo 16-128"},
+                 "slots": args.slots, "max_concurrency": srv.max_concurrency,
                  "prim_bands": args.serving_rows == "bands",
                  "peak_reserved_GB": srv.peak_in_use / 2 ** 30,
                  "alone_equals_mix": f"{same}/8"})
@@ -472,6 +514,128 @@ def main_serving(args):
         line["mixed_vs_fp64_throughput"] = (runs["mixed"]["mo_integrals_per_s"]
                                             / runs["fp64"]["mo_integrals_per_s"])
     print(json.dumps(line), flush=True)
+
+
+def committed_traffic(workload, tune):
+    """HBM bytes per first-half launch from the committed counter summary of
+    this workload, when it was taken from the current kernel source in the
+    same workgroup order (else None)."""
+    path = os.path.join(ROOT, "profiles", f"first_half_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        tr = json.load(f)
+    if tr.get("kernel_rev") == qdcb_kernel_rev() and tr.get("fh_order") == tune["fh_order"]:
+        return tr.get("bytes_per_launch")
+    return None
+
+
+def cluster_leg(args):
+    """The compact-cluster configuration: 60 atoms in a 20 bohr ball, N_L 600,
+    N_S 1200, contraction depths 1..6, n = 128, Dirac-Coulomb + Gaunt, tau
+    1e-10, Loewdin coefficients.  FP64: autotuned launch choices (the tuner's
+    warm-up sizes the integral panels), then args.cluster_steps timed
+    transforms with the first half's roofline.  Mixed precision on the same
+    inputs: the specified tiers (FP32 below 1e-4, BF16 below 1e-7, screening
+    bound) and tiers that meet 1e-10 Eh here (1e-6 / 1e-9, bound including the
+    bra side); each plan autotuned (its warm-up), one timed transform, its
+    max |G_mixed - G_FP64| against the FP64 GPU result of the same inputs (the
+    FP64 path is held to the oracle by the parity tests) and the change of the
+    occupied-block Coulomb sum J_occ = 4 sum_{p,r < 64} G^00_pprr."""
+    import torch
+    from paper_2606_04316_amd import qdcb, workloads as wl
+
+    t_start = time.perf_counter()
+    sysm = wl.config("cluster60")
+    n = sysm.n_mo
+    dev = torch.device("cuda:0")
+    G = torch.empty((n, n, n, n, 4, 4), dtype=torch.float64, device=dev)
+    Gm = torch.empty_like(G)
+    CL = torch.from_numpy(sysm.CL).to(dev)
+    CS = torch.from_numpy(sysm.CS).to(dev)
+    ctx = qdcb.Context(0)
+    L, S = qdcb.Basis(ctx, sysm.L), qdcb.Basis(ctx, sysm.S)
+    plan = qdcb.Plan(ctx, L, S, sysm.ham, n, sysm.tau)
+    print(f"cluster leg: {sysm.name} ready", file=sys.stderr, flush=True)
+    tune = autotune(args, plan, CL, CS, G)
+    if not tune.get("autotuned") or tune.get("from_cache"):
+        plan.transform(CL, CS, G)  # warm-up: sizes the integral panels
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for i in range(args.cluster_steps):
+        _, st = plan.transform(CL, CS, G)
+        stats.append(st)
+        print(f"cluster step {i + 1}/{args.cluster_steps}: {st['ms_total']:.1f} ms",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms = 1e3 * elapsed / args.cluster_steps
+    fh_ms = sum(x["ms_first_half"] for x in stats)
+    fh_launch = sum(x["n_batches"] for x in stats)
+    achieved = sum(x["flops_first_half"] for x in stats) / (fh_ms * 1e-3) / 1e12
+    sh_ms = sum(x["ms_second_half"] for x in stats)
+    sh_rate = sum(x["flops_second_half"] for x in stats) / (sh_ms * 1e-3) / 1e12
+    st0 = stats[-1]
+    occ = torch.arange(n // 2, device=dev)
+
+    def j_occ(X):
+        return 4.0 * float(sum(X[p, p][occ, occ, 0, 0].sum() for p in range(n // 2)))
+
+    j0 = j_occ(G)
+    # the mixed plans below need the integral panels' memory
+    plan.close()
+    out = {
+        "workload": sysm.name, "n_atoms": int(sysm.atoms.shape[0]), "N_L": sysm.L.nfunc,
+        "N_S": sysm.S.nfunc, "n_mo": n, "ham": sysm.ham, "tau": sysm.tau,
+        "contraction_depths": "1..6", "steps": args.cluster_steps, "ms_per_transform": ms,
+        "value": n ** 4 / (ms * 1e-3), "unit": "quaternion MO integrals (pq|rs)/s",
+        "spinor_integrals_per_s": (2 * n) ** 4 / (ms * 1e-3),
+        "stages_ms": {k: st0[k] for k in ("ms_density", "ms_screen", "ms_eri", "ms_first_half",
+                                          "ms_second_half", "ms_total")},
+        "chunks": st0["n_chunks"], "tune": tune,
+        "kept_fraction": (sum(st0["kept"]) + st0["kept_gaunt"])
+        / max(1, sum(st0["total"]) + st0["total_gaunt"]),
+        "tile_fill": st0["flops_first_half"] / max(1.0, st0["flops_mfma"]),
+        "roofline": {"kernel": "k_first_half", "bound": "mfma", "achieved": achieved,
+                     "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_MFMA,
+                     "traffic": committed_traffic("cluster60", tune["chosen"]),
+                     "launches": fh_launch, "avg_launch_ms": fh_ms / max(1, fh_launch)},
+        "second_half": {"achieved": sh_rate, "frac": sh_rate / PEAK_FP64_MFMA,
+                        "unit": "TFLOP/s"},
+    }
+    print(f"cluster leg fp64: {ms:.1f} ms per transform", file=sys.stderr, flush=True)
+    mixed = []
+    for t32, t16, rule in ((1e-4, 1e-7, "screen"), (1e-6, 1e-9, "g")):
+        mp = qdcb.Plan(ctx, L, S, sysm.ham, n, sysm.tau, prec="mixed", tier_fp32=t32,
+                       tier_bf16=t16, flags=qdcb.PLAN_TIER_BY_G if rule == "g" else 0)
+        print(f"cluster leg mixed {t32}/{t16} {rule}: plan ready", file=sys.stderr, flush=True)
+        mtune = autotune(args, mp, CL, CS, Gm)
+        if not mtune.get("autotuned") or mtune.get("from_cache"):
+            mp.transform(CL, CS, Gm)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, stm = mp.transform(CL, CS, Gm)
+        torch.cuda.synchronize()
+        ms_m = 1e3 * (time.perf_counter() - t1)
+        err = max(float((Gm[p] - G[p]).abs().max()) for p in range(n))
+        mixed.append({"tier_fp32": t32, "tier_bf16": t16,
+                      "rule": "screening bound" if rule == "screen" else "G bound",
+                      "ms_mixed": ms_m, "speedup": ms / ms_m,
+                      "max_abs_err_vs_fp64_gpu_Eh": err, "meets_1e-10": err <= 1e-10,
+                      "abs_err_J_occ_Eh": abs(j_occ(Gm) - j0),
+                      "tiles_tier": stm["tiles_tier"], "ms_tier": stm["ms_tier"]})
+        print(f"cluster leg mixed {t32}/{t16} {rule}: {ms_m:.1f} ms, max|dG| {err:.2e}",
+              file=sys.stderr, flush=True)
+        mp.close()
+    out["mixed_vs_fp64"] = mixed
+    out["J_occ"] = j0
+    ctx.close()
+    del G, Gm
+    torch.cuda.empty_cache()
+    out["wall_s"] = time.perf_counter() - t_start
+    return out
 
 
 def qdcb_kernel_rev():

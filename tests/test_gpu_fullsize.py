@@ -1,5 +1,9 @@
-"""GPU parity at the benchmark's full size (chain40: 40 atoms, N_L = 400,
-N_S = 800, n = 64, tau = 1e-10), in the plan configuration bench.py times.
+"""GPU parity at the benchmark's full sizes, in the plan configuration
+bench.py times: the chain (40 atoms, N_L = 400, N_S = 800, n = 64, DC and DCG,
+tau = 1e-10) and the compact cluster (60 atoms in a 20 bohr ball, N_L = 600,
+N_S = 1200, contraction depths 1..6, n = 128, DCG, tau = 1e-10: 33 MO-pair
+column chunks, integral panels resized at transform time, 128-wide
+second-quarter tiles).
 
 The oracle cannot finish the whole transform at this size, so it is compared
 on sampled outputs it can compute one by one: the first-half rows V of
@@ -143,6 +147,89 @@ def test_full_size_first_half_rows_and_pq_symmetry(q, name):
               flush=True)
         assert d <= 1e-12 * gscale
         assert d <= 1e-10 * gmax
+    assert torch.isfinite(G).all().item()
+    plan.close()
+    ctx.close()
+
+
+def test_cluster60_full_size_rows_and_second_half(q):
+    """The cluster configuration at full size with well-conditioned
+    coefficients (a random quaternion-orthonormal (N_L + N_S) x n matrix):
+    sampled LL, SS and LS first-half rows over the MO pairs of the last
+    column chunk against the oracle at 1e-12 of each row's largest element
+    (the oracle takes its density bounds from its quaternion-route routines
+    for speed; kept decisions are then exact unless a bound ties the
+    threshold, which the oracle counts); and the second half of the whole
+    output through the p <-> q rules, which the kernels never impose:
+    G_qprs = s_x G_pqrs for the Coulomb classes and -s_x G_pqrs for the Gaunt
+    classes (the Coulomb classes transformed alone, the Gaunt classes as the
+    DCG result minus them)."""
+    import torch
+    s = wl.cluster(seed=3, coefs="qr")  # the cluster recipe (N_L 600, N_S 1200, n 128, DCG)
+    n = s.n_mo
+    dev = torch.device("cuda:0")
+    # two outputs of 34 GB each, allocated before the context takes its share
+    G = torch.empty((n, n, n, n, 4, 4), dtype=torch.float64, device=dev)
+    Gc = torch.empty_like(G)
+    CL = torch.from_numpy(s.CL).to(dev)
+    CS = torch.from_numpy(s.CS).to(dev)
+    ctx = q.Context(0)
+    L, S = q.Basis(ctx, s.L), q.Basis(ctx, s.S)
+    plan = q.Plan(ctx, L, S, "DCG", n, s.tau)
+    _, st = plan.transform(CL, CS, G)
+    torch.cuda.synchronize()
+    print(f"cluster60_qr: {st['ms_total']:.1f} ms, chunks {st['n_chunks']}, tune {plan.tune}",
+          flush=True)
+    assert st["n_chunks"] > 1 and plan.tune["sq_tile"] == 128
+
+    # sampled rows: the largest Schwarz factor of each class and one drawn
+    # from the upper fifth of each class
+    QL, QS = oracle.schwarz(s.L), oracle.schwarz(s.S)
+    QLc, QSc = _tri(QL), _tri(QS)
+    QLS = oracle.schwarz(s.L, s.S).reshape(-1)
+    rng = np.random.default_rng(23)
+    nLL, nSS = QLc.shape[0], QSc.shape[0]
+    rows = []
+    for base, Qc in ((0, QLc), (nLL, QSc), (nLL + nSS, QLS)):
+        order = np.argsort(-Qc)
+        rows += [base + int(order[0]), base + int(rng.choice(order[:Qc.shape[0] // 5]))]
+    rows = np.array(sorted(set(rows)), dtype=np.int64)
+    Vg = plan.fetch_v(rows)
+    npair = n * (n + 1) // 2
+    have = np.isfinite(Vg[0, :4 * npair])
+    cols = np.unique(np.nonzero(have)[0] // 4)
+    assert 0 < cols.shape[0] < npair
+    dm = oracle.pair_density_bounds(s.L, s.S, s.CL, s.CS, "DCG")
+    Vo = oracle.first_half_rows_cols(s.L, s.S, s.CL, s.CS, "DCG", s.tau, rows, cols, dm)
+    # columns K * 4 npair + 4 idx + y of the selected MO pairs, in the
+    # oracle's order (K, selected pair, y)
+    sel = np.concatenate([(K * 4 * npair + 4 * cols[:, None] + np.arange(4)).reshape(-1)
+                          for K in range(3)])
+    Vgs = Vg[:, sel]
+    assert np.isfinite(Vgs).all()
+    err = np.abs(Vgs - Vo).max(axis=1)
+    vmax = np.abs(Vo).max(axis=1)
+    print(f"cluster60_qr: rows {rows.tolist()}, MO pairs {cols.shape[0]} (last chunk)\n"
+          "  per row max|dV| / max|V_row|: " +
+          " ".join(f"{x:.1e}" for x in err / np.maximum(vmax, 1e-300)), flush=True)
+    # a sampled row may keep nothing in these columns (then it must be exactly 0)
+    assert int((vmax > 0).sum()) >= len(rows) - 1
+    assert np.all(err <= 1e-12 * vmax)
+
+    # second half: p <-> q rules per class, on the device, one p slice at a
+    # time: the Coulomb classes alone, and the Gaunt classes as the DCG result
+    # minus the Coulomb classes
+    sign = torch.tensor(qalg.SIGNS, device=dev, dtype=torch.float64).view(1, 1, 1, 4, 1)
+    plan.transform(CL, CS, Gc, classes="coulomb")
+    torch.cuda.synchronize()
+    gmax = dc = dg = 0.0
+    for p in range(n):
+        gmax = max(gmax, G[p].abs().max().item())
+        dc = max(dc, (Gc[:, p] - sign * Gc[p]).abs().max().item())
+        dg = max(dg, ((G[:, p] - Gc[:, p]) + sign * (G[p] - Gc[p])).abs().max().item())
+    print(f"cluster60_qr: max|G| {gmax:.3e}; p<->q deviation Coulomb {dc:.2e}, Gaunt {dg:.2e}",
+          flush=True)
+    assert dc <= 1e-12 * gmax and dg <= 1e-12 * gmax
     assert torch.isfinite(G).all().item()
     plan.close()
     ctx.close()
