@@ -75,12 +75,12 @@ def parse():
                     help="serving: precisions to serve the stream in, one run each "
                          "(mixed: tiers 1e-6 / 1e-9 with the G-bound rule)")
     ap.add_argument("--slots", type=int, default=4)
-    ap.add_argument("--prim-bands", action="store_true",
-                    help="transform: plans with QDCB_PLAN_PRIM_BANDS (rows grouped by the "
-                         "primitive pairs they keep)")
+    ap.add_argument("--schwarz-rows", action="store_true",
+                    help="transform: plans with QDCB_PLAN_SCHWARZ_ROWS (plain Schwarz row "
+                         "order instead of the default primitive bands)")
     ap.add_argument("--serving-rows", default="bands", choices=["bands", "schwarz"],
-                    help="serving: row order of the request plans (bands: "
-                         "QDCB_PLAN_PRIM_BANDS; the requests' contraction depths are uneven)")
+                    help="serving: row order of the request plans (bands: the library "
+                         "default; schwarz: QDCB_PLAN_SCHWARZ_ROWS)")
     ap.add_argument("--mo-batch", type=int, default=0,
                     help="transform: run the MO-driven variant with batches of this many MO "
                          "pairs, each screened with its own density bound (0: AO-driven)")
@@ -232,7 +232,7 @@ def main_transform(args):
         S = qdcb.Basis(ctx, sysm.S) if sysm.S is not None else None
     plan = qdcb.Plan(ctx, L, S, sysm.ham, n, sysm.tau,
                      flags=(qdcb.PLAN_SPINOR if spinor else 0) |
-                     (qdcb.PLAN_PRIM_BANDS if args.prim_bands else 0))
+                     (qdcb.PLAN_SCHWARZ_ROWS if args.schwarz_rows else 0))
     if args.mo_batch:
         plan.set_mo_batch(args.mo_batch)
     if args.copy_calibration_mib:
@@ -263,7 +263,8 @@ def main_transform(args):
     fh_launch = sum(s["n_batches"] for s in stats)
     fh_flops = sum(s["flops_first_half"] for s in stats)
     achieved = fh_flops / (fh_ms * 1e-3) / 1e12
-    traffic = committed_traffic(args.workload, plan.tune)
+    traffic = committed_traffic(args.workload, plan.tune,
+                                "Schwarz" if args.schwarz_rows else "primitive bands")
     st0 = stats[-1]
     kind = "complex spinor" if spinor else "quaternion"
     headline = (not spinor and not rkbq and not args.mo_batch and sysm.ham != "DCB"
@@ -285,7 +286,7 @@ def main_transform(args):
                    "ham": sysm.ham, "tau": sysm.tau,
                    "algorithm": f"MO-driven, {args.mo_batch} MO pairs per batch"
                    if args.mo_batch else "AO-driven",
-                   "row_order": "primitive bands" if args.prim_bands else "Schwarz",
+                   "row_order": "Schwarz" if args.schwarz_rows else "primitive bands",
                    "shells": "s, p" if getattr(sysm.L, "cart", None) is not None else "s",
                    "small_components": "RKB (gradient basis)" if rkb else
                    "RKB (gradient basis), Kramers-restricted" if rkbq else "stand-in basis"},
@@ -458,11 +459,11 @@ def serving_run(args, prec):
     """One run of the request stream (256 requests, mean gap 20 ms, reduced
     sizes) in one precision; eight requests re-run alone and compared bitwise."""
     import torch
-    from paper_2606_04316_amd import serving
+    from paper_2606_04316_amd import qdcb, serving
     reqs = serving.request_stream(args.requests, seed=5, mean_gap_s=0.02, pool=12,
                                   atoms=(10, 40), nl=(40, 160), n_mo=(8, 32),
                                   radius_scale=20.0)
-    pf = 0x8 if args.serving_rows == "bands" else 0  # QDCB_PLAN_PRIM_BANDS
+    pf = 0 if args.serving_rows == "bands" else qdcb.PLAN_SCHWARZ_ROWS
     # the eight requests re-run alone below (every len/8-th by arrival) are the
     # only ones hashed
     step = max(1, len(reqs) // 8)
@@ -489,7 +490,7 @@ def serving_run(args, prec):
                             "tau": 1e-10, "pool": 12,
                             "note": "reduced from 10-80 atoms, N_L 100-800, n_mo 16-128"},
                  "slots": args.slots, "max_concurrency": srv.max_concurrency,
-                 "prim_bands": args.serving_rows == "bands",
+                 "row_order": "primitive bands" if args.serving_rows == "bands" else "Schwarz",
                  "peak_reserved_GB": srv.peak_in_use / 2 ** 30,
                  "alone_equals_mix": f"{same}/8"})
     if prec == "mixed":
@@ -516,16 +517,17 @@ def main_serving(args):
     print(json.dumps(line), flush=True)
 
 
-def committed_traffic(workload, tune):
+def committed_traffic(workload, tune, row_order):
     """HBM bytes per first-half launch from the committed counter summary of
     this workload, when it was taken from the current kernel source in the
-    same workgroup order (else None)."""
+    same workgroup order and row order (else None)."""
     path = os.path.join(ROOT, "profiles", f"first_half_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         tr = json.load(f)
-    if tr.get("kernel_rev") == qdcb_kernel_rev() and tr.get("fh_order") == tune["fh_order"]:
+    if (tr.get("kernel_rev") == qdcb_kernel_rev() and tr.get("fh_order") == tune["fh_order"]
+            and tr.get("row_order") == row_order):
         return tr.get("bytes_per_launch")
     return None
 
@@ -588,7 +590,8 @@ def cluster_leg(args):
     out = {
         "workload": sysm.name, "n_atoms": int(sysm.atoms.shape[0]), "N_L": sysm.L.nfunc,
         "N_S": sysm.S.nfunc, "n_mo": n, "ham": sysm.ham, "tau": sysm.tau,
-        "contraction_depths": "1..6", "steps": args.cluster_steps, "ms_per_transform": ms,
+        "contraction_depths": "1..6", "row_order": "primitive bands",
+        "steps": args.cluster_steps, "ms_per_transform": ms,
         "value": n ** 4 / (ms * 1e-3), "unit": "quaternion MO integrals (pq|rs)/s",
         "spinor_integrals_per_s": (2 * n) ** 4 / (ms * 1e-3),
         "stages_ms": {k: st0[k] for k in ("ms_density", "ms_screen", "ms_eri", "ms_first_half",
@@ -600,7 +603,7 @@ def cluster_leg(args):
         "roofline": {"kernel": "k_first_half", "bound": "mfma", "achieved": achieved,
                      "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_MFMA,
-                     "traffic": committed_traffic("cluster60", tune["chosen"]),
+                     "traffic": committed_traffic("cluster60", tune["chosen"], "primitive bands"),
                      "launches": fh_launch, "avg_launch_ms": fh_ms / max(1, fh_launch)},
         "second_half": {"achieved": sh_rate, "frac": sh_rate / PEAK_FP64_MFMA,
                         "unit": "TFLOP/s"},

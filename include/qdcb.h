@@ -239,20 +239,24 @@ typedef struct {
  * (im), which is also the column layout of qdcb_plan_fetch_v.  Blocked output
  * (qdcb_transform_blocks) is not offered for these plans. */
 #define QDCB_PLAN_SPINOR 0x4u
-/* Row order for uneven primitive loops: the pairs of each space, ordered by
- * Schwarz factor, are regrouped in bands of 8 x 64 rows by the number of
+/* Row order of the pair spaces.  By default the pairs of each space, ordered
+ * by Schwarz factor, are regrouped in bands of 8 x 64 rows by the number of
  * primitive pairs that survive primitive screening (decreasing), so that the
  * 64 rows of an integral tile have similar primitive loops (lanes of the
- * integral kernel idle less).  The tile
- * bounds get looser (a tile spans the band's Schwarz range), so more tile
- * pairs are kept; worth it when the integral tiles dominate (deep
- * contractions, few MO pairs).  Results agree to rounding. */
+ * integral kernel idle less).  A tile's bound then spans its band's Schwarz
+ * range, so somewhat more tile pairs are kept; on uneven contraction depths
+ * the integral tiles gain more than the first half loses.
+ * QDCB_PLAN_SCHWARZ_ROWS keeps the plain order by decreasing Schwarz factor
+ * (tightest tile bounds; even contraction depths gain nothing from bands).
+ * QDCB_PLAN_PRIM_BANDS names the default explicitly; setting both is
+ * QDCB_E_INVALID.  Results agree to rounding across the orders. */
 #define QDCB_PLAN_PRIM_BANDS 0x8u
+#define QDCB_PLAN_SCHWARZ_ROWS 0x10u
 
 /* Plan for transforming with fixed bases and n_mo.  S must be NULL for
  * QDCB_HAM_LL and non-NULL otherwise.  Orders the pairs of each integral
  * class space (Coulomb: LL and SS pairs; Gaunt, for DCG: ordered LS pairs) by
- * their Schwarz factor (see QDCB_PLAN_PRIM_BANDS) and allocates the per-transform device buffers; the
+ * their Schwarz factor (regrouped in primitive bands unless QDCB_PLAN_SCHWARZ_ROWS) and allocates the per-transform device buffers; the
  * MO-pair columns are processed in chunks when they do not fit at once.
  * QDCB_E_NOMEM if even the smallest chunk does not fit the context budget. */
 qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basis *S,

@@ -406,8 +406,10 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
     if (!std::isfinite(desc->tau) || desc->tau < 0) fail(QDCB_E_INVALID, "tau must be >= 0");
     if (desc->flags &
         ~(int32_t)(QDCB_PLAN_DIRECTED_TILES | QDCB_PLAN_TIER_BY_G | QDCB_PLAN_SPINOR |
-                   QDCB_PLAN_PRIM_BANDS))
+                   QDCB_PLAN_PRIM_BANDS | QDCB_PLAN_SCHWARZ_ROWS))
       fail(QDCB_E_INVALID, "unknown plan flag");
+    if ((desc->flags & QDCB_PLAN_PRIM_BANDS) && (desc->flags & QDCB_PLAN_SCHWARZ_ROWS))
+      fail(QDCB_E_INVALID, "QDCB_PLAN_PRIM_BANDS and QDCB_PLAN_SCHWARZ_ROWS exclude each other");
     // bases may belong to another context (resident, shared) on the same device
     if (L->ctx->device != ctx->device || (S && S->ctx->device != ctx->device))
       fail(QDCB_E_INVALID, "basis on another device");
@@ -440,7 +442,8 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
       p.npair_mo = p.n * (p.n + 1) / 2;
     }
     p.ncol = 4LL * p.npair_mo;
-    const int64_t bands = (desc->flags & QDCB_PLAN_PRIM_BANDS) ? 8 * TILE : 0;
+    // row order: primitive bands of 8 tiles (default), or plain Schwarz order
+    const int64_t bands = (desc->flags & QDCB_PLAN_SCHWARZ_ROWS) ? 0 : 8 * TILE;
 
     // --- Coulomb space: LL pairs, then SS pairs
     {

@@ -30,6 +30,7 @@ PLAN_DIRECTED_TILES = 0x1
 PLAN_TIER_BY_G = 0x2
 PLAN_SPINOR = 0x4
 PLAN_PRIM_BANDS = 0x8
+PLAN_SCHWARZ_ROWS = 0x10
 
 STATUS = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_UNSUPPORTED",
           -5: "E_BUSY", -6: "E_ABORTED"}

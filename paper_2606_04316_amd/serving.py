@@ -173,7 +173,7 @@ class GpuExecutor:
     budget is the request's reservation.  ``prec="mixed"`` runs every plan
     with the reduced-precision tiers (``tiers`` = tier_fp32, tier_bf16, plan
     flags); ``plan_flags`` are added to every plan's flags (for instance
-    PLAN_PRIM_BANDS for integral-dominated request mixes).
+    PLAN_SCHWARZ_ROWS for plain Schwarz row order).
 
     G comes to the host through a pinned staging buffer per slot (reused, so
     a result is delivered as the digest of that copy, or as the device tensor

@@ -112,7 +112,7 @@ def test_uneven_depth_cluster_strict(q, ctx, ham):
         s = wl.cluster(seed=41, n_atoms=5, nl_per_atom=2, ns_per_atom=3, n=3, radius=5.0,
                        min_sep=1.5, tau=1e-10, ham="DCG", coefs="qr")
     Go, so = oracle.transform_direct(s.L, s.S, s.CL, s.CS, ham, s.tau)
-    for flags in (0, q.PLAN_PRIM_BANDS):
+    for flags in (0, q.PLAN_SCHWARZ_ROWS):  # primitive bands (default) and Schwarz rows
         G, st = _run(q, ctx, s, flags=flags)
         _same_counts(st, so)
         _strict(G, Go, f"{ham} cluster flags {flags}")

@@ -185,16 +185,19 @@ def test_autotune_times_every_choice_and_caches(q, ctx, tmp_path, monkeypatch):
 
 @pytest.mark.parametrize("ham", ["DC", "DCB"])
 def test_primitive_band_row_order_matches_the_oracle(q, ctx, ham):
-    # QDCB_PLAN_PRIM_BANDS regroups the Schwarz-ordered rows by primitive count
-    # within bands of 512 rows: the tiles change, the kept contributions and
-    # the integrals do not (exact kept counts, parity tolerance)
+    # the default row order regroups the Schwarz-ordered rows by primitive
+    # count within bands of 512 rows (QDCB_PLAN_SCHWARZ_ROWS keeps the plain
+    # order): the tiles change, the kept contributions and the integrals do
+    # not (exact kept counts, parity tolerance); both flags at once are refused
     s = wl.cluster(seed=69, n_atoms=9, nl_per_atom=3, ns_per_atom=4, n=5, radius=7.0,
                    min_sep=1.5, tau=1e-10, ham=ham)
     assert (s.L.nfunc * (s.L.nfunc + 1) + s.S.nfunc * (s.S.nfunc + 1)) // 2 > 2 * 512
     Go, sto = oracle.transform_direct(s.L, s.S, s.CL, s.CS, ham, s.tau)
     L, S = q.Basis(ctx, s.L), q.Basis(ctx, s.S)
     res = {}
-    for flags in (0, q.PLAN_PRIM_BANDS):
+    with pytest.raises(q.QdcbError):
+        q.Plan(ctx, L, S, ham, s.n_mo, s.tau, flags=q.PLAN_SCHWARZ_ROWS | q.PLAN_PRIM_BANDS)
+    for flags in (q.PLAN_SCHWARZ_ROWS, 0, q.PLAN_PRIM_BANDS):
         plan = q.Plan(ctx, L, S, ham, s.n_mo, s.tau, flags=flags)
         G, st = plan.transform(s.CL, s.CS)
         plan.close()
@@ -206,6 +209,7 @@ def test_primitive_band_row_order_matches_the_oracle(q, ctx, ham):
             sc += 3 * 6.25 * float(np.max(a + a.T)) ** 2
         assert np.abs(G - Go).max() <= 1e-12 * sc, flags
         res[flags] = (G, st)
-    (G0, st0), (G1, st1) = res[0], res[q.PLAN_PRIM_BANDS]
+    (G0, st0), (G1, st1) = res[q.PLAN_SCHWARZ_ROWS], res[0]
+    assert np.array_equal(res[q.PLAN_PRIM_BANDS][0], G1)  # the default, named
     print(f"{ham}: kept tiles {st0['tiles_kept']} (Schwarz order) vs {st1['tiles_kept']} (bands)")
     assert st0["tiles_kept"] != st1["tiles_kept"]  # the row order did change the tiles

@@ -549,8 +549,10 @@ def test_general_spinors_brute_force_vs_definition_vs_direct(ham):
 def test_general_spinor_route_equals_unitary_mixing_of_kramers_route(ham):
     # (a'b'|c'd') = sum U*_{aa'} U_{bb'} U*_{cc'} U_{dd'} (ab|cd): the general
     # route on mixed spinors against the quaternion route's spinor integrals
+    # well-conditioned (QR) coefficients: the four-index mixing of Loewdin
+    # coefficients amplifies their rounding to the size of the bound itself
     s = wl.linear_chain(seed=9, n_atoms=3, spacing=2.8, nl_per_atom=2, ns_per_atom=3, n=3,
-                        tau=0.0, ham=ham)
+                        tau=0.0, ham=ham, coefs="qr")
     _, sp, _ = oracle.transform_def(s.L, s.S, s.CL, s.CS, ham, return_spinor=True)
     PL, PS, U = wl.general_spinors(s, 5, seed=2)
     mixed = np.einsum("aA,bB,cC,dD,abcd->ABCD", U.conj(), U, U.conj(), U, sp)
