@@ -99,13 +99,19 @@ void launch_dgemm_batched(int transA, int M, int N, int K, double alpha, const d
 // direct global->LDS loads, double-buffered so that the loads of step t+1
 // run under step t's MFMAs.  Rows k >= K are zero-filled; lanes past the V
 // row or past J load nothing (they only feed outputs that are not stored).
+// Two workgroups per compute unit (the register budget is held to that).
+//
+// Workgroup order: the chip's 8 XCDs take workgroups round-robin; workgroup
+// L runs on XCD L % 8, whose consecutive workgroups cover the tiles of one
+// sharing group (the tiles that read the same A or B tile), so that the
+// shared tile is fetched into that XCD's L2 once.
 constexpr int GG_KH = 16;
 constexpr int GG_LD = 130;  // LDS row stride (doubles): 16-byte rows, padded
 
 typedef __attribute__((address_space(3))) void *gg_lds_ptr;
 
 __device__ __forceinline__ void gg_mfma(const double *A, const double *B, int wr, int wc, int lr,
-                                        int lk, dbl4 (&acc)[4][4]) {
+                                        int lk, unsigned skip, dbl4 (&acc)[4][4]) {
 #pragma unroll
   for (int kk = 0; kk < GG_KH / 4; ++kk) {
     const int j = kk * 4 + lk;
@@ -117,18 +123,52 @@ __device__ __forceinline__ void gg_mfma(const double *A, const double *B, int wr
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[r][c] = MFMA_F64(av[r], bv[c], acc[r][c]);
+      for (int c = 0; c < 4; ++c)
+        if (!(skip >> (r * 4 + c) & 1u)) acc[r][c] = MFMA_F64(av[r], bv[c], acc[r][c]);
   }
 }
 
-__global__ void __launch_bounds__(256) k_gather_gemm(GatherGemmArgs a) {
+constexpr int GG_XCD = 8;
+
+__global__ void __launch_bounds__(256, 2) k_gather_gemm(GatherGemmArgs a, int nct, int njt) {
   __shared__ __attribute__((aligned(16))) double As0[GG_KH * GG_LD], As1[GG_KH * GG_LD];
   __shared__ __attribute__((aligned(16))) double Bs0[GG_KH * GG_LD], Bs1[GG_KH * GG_LD];
-  const int ct = blockIdx.x, jt = blockIdx.y, b = blockIdx.z;
+  int ct, jt, b;
+  {
+    const int L = blockIdx.x, loc = L / GG_XCD;
+    const int inner = a.share_b ? nct : njt;  // tiles of one sharing group
+    const int64_t g = (int64_t)GG_XCD * (loc / inner) + L % GG_XCD;
+    const int t = loc % inner;
+    if (a.share_b) {  // group (jt, b)
+      if (g >= (int64_t)njt * a.nb) return;  // uniform: ragged last groups
+      ct = t;
+      jt = (int)(g % njt);
+      b = (int)(g / njt);
+    } else {  // group (ct, b)
+      if (g >= (int64_t)nct * a.nb) return;
+      jt = t;
+      ct = (int)(g % nct);
+      b = (int)(g / nct);
+    }
+  }
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = w >> 1, wc = w & 1;
   const int lr = lane & 15, lk = lane >> 4;
+  // triangle: skip[r][c] for this wave's 16 x 16 blocks (p of every row above
+  // q of every column); a workgroup whose blocks are all skipped exits
+  unsigned skip = 0;
+  if (a.tri_n > 0) {
+    const int qw = jt * 128 + wc * 64;
+    for (int r = 0; r < 4; ++r) {
+      // first p of block r (a 16-row block never spans two x: 16 divides tri_n)
+      const int pr = (int)(((int64_t)ct * 128 + wr * 64 + r * 16) % a.tri_n);
+      for (int c = 0; c < 4; ++c)
+        if (pr >= qw + c * 16 + 16) skip |= 1u << (r * 4 + c);
+    }
+    const int pg = (int)(((int64_t)ct * 128) % a.tri_n);
+    if (pg + 128 <= a.tri_n && pg >= jt * 128 + 128) return;  // uniform: every p > every q
+  }
   const int64_t c0 = (int64_t)ct * 128 + 2 * lane;  // this lane's two columns
   const int j0 = jt * 128 + 2 * lane;
   const bool c_ok = a.col0 + c0 + 1 < a.ld;
@@ -165,7 +205,7 @@ __global__ void __launch_bounds__(256) k_gather_gemm(GatherGemmArgs a) {
       }
     }
   };
-  auto mfma = [&](const double *A, const double *B) { gg_mfma(A, B, wr, wc, lr, lk, acc); };
+  auto mfma = [&](const double *A, const double *B) { gg_mfma(A, B, wr, wc, lr, lk, skip, acc); };
   fetch_rows(0);
   __builtin_amdgcn_s_waitcnt(0x0F70);
   bool more = nsteps > 0;
@@ -202,7 +242,7 @@ __global__ void __launch_bounds__(256) k_gather_gemm(GatherGemmArgs a) {
       for (int i = 0; i < 4; ++i) {
         const int64_t cc = (int64_t)ct * 128 + wr * 64 + r * 16 + lk + 4 * i;
         const int jj = jt * 128 + wc * 64 + c * 16 + lr;
-        if (cc < a.nc && jj < a.J) {
+        if (cc < a.nc && jj < a.J && !(skip >> (r * 4 + c) & 1u)) {
           double *o = a.C + cc * a.ldc_c + (int64_t)b * a.ldc_b + jj;
           *o = a.accumulate ? *o + acc[r][c][i] : acc[r][c][i];
         }
@@ -211,8 +251,12 @@ __global__ void __launch_bounds__(256) k_gather_gemm(GatherGemmArgs a) {
 
 void launch_gather_gemm(const GatherGemmArgs &a, hipStream_t s) {
   if (a.nc <= 0 || a.J <= 0 || a.nb <= 0) return;
-  dim3 grid((a.nc + 127) / 128, (a.J + 127) / 128, a.nb);
-  hipLaunchKernelGGL(k_gather_gemm, grid, dim3(256), 0, s, a);
+  const int nct = (a.nc + 127) / 128, njt = (a.J + 127) / 128;
+  const int inner = a.share_b ? nct : njt;
+  const int64_t groups = (int64_t)(a.share_b ? njt : nct) * a.nb;
+  // at most (65532 / 128) x 32 x 2^16 tiles: inside the grid limit
+  const int64_t grid = (int64_t)GG_XCD * inner * ((groups + GG_XCD - 1) / GG_XCD);
+  hipLaunchKernelGGL(k_gather_gemm, dim3((unsigned)grid), dim3(256), 0, s, a, nct, njt);
 }
 
 }  // namespace qdcb

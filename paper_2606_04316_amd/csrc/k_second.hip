@@ -51,6 +51,17 @@ void launch_build_coef_mats(int N, int n, const double *C, int unit, double *Cal
                      n, C, unit, Call, Chat);
 }
 
+// G_c entry (x, p, q) of slice column il * 4 + y for p <= q, and for p > q
+// from (x, q, p) by the bra-pair rule G_pq^x = mirror s_x G_qp^x (s_0 = +1,
+// s_1,2,3 = -1; mirror = +1 Coulomb, -1 Gaunt): the second quarter need not
+// compute the p > q half.
+__device__ __forceinline__ double gc_entry(const double *Gc, int n, int64_t il, int y, int x,
+                                           int p, int q, double mirror) {
+  if (p <= q) return Gc[((il * 4 + y) * 4 * n + (int64_t)x * n + p) * n + q];
+  const double v = Gc[((il * 4 + y) * 4 * n + (int64_t)x * n + q) * n + p];
+  return x == 0 ? mirror * v : -mirror * v;
+}
+
 // One thread per (MO pair r <= s of the slice, p, q): 16 contiguous outputs.
 __global__ void k_pack(int n, const int32_t *rs, int64_t c0, int nc, const double *Gc,
                        double *G, double mirror, int accumulate) {
@@ -65,8 +76,7 @@ __global__ void k_pack(int n, const int32_t *rs, int64_t c0, int nc, const doubl
   int r = rsv & 0xffff, s = rsv >> 16;
   double v[4][4];
   for (int y = 0; y < 4; ++y)
-    for (int x = 0; x < 4; ++x)
-      v[x][y] = Gc[((il * 4 + y) * 4 * n + (int64_t)x * n + p) * n + q];
+    for (int x = 0; x < 4; ++x) v[x][y] = gc_entry(Gc, n, il, y, x, p, q, mirror);
   double *o = G + ((((int64_t)p * n + q) * n + r) * n + s) * 16;
   for (int x = 0; x < 4; ++x)
     for (int y = 0; y < 4; y += 2) {
@@ -200,7 +210,7 @@ __global__ void k_pack_block(int n, const int32_t *rs, int64_t c0, int nc, const
   double *o = B + ((i * n + p) * n + q) * 32;
   for (int x = 0; x < 4; ++x)
     for (int y = 0; y < 4; ++y) {
-      const double v = Gc[((il * 4 + y) * 4 * n + (int64_t)x * n + p) * n + q];
+      const double v = gc_entry(Gc, n, il, y, x, p, q, mirror);
       // s_y = +1 for y = 0, -1 otherwise
       const double m = diag ? v : mirror * (y == 0 ? v : -v);
       o[x * 4 + y] = accumulate ? o[x * 4 + y] + v : v;

@@ -260,6 +260,15 @@ struct GatherGemmArgs {
   double *C;
   int64_t ldc_c, ldc_b;
   int accumulate;
+  // workgroup order: the tiles that share one operand tile run consecutively
+  // on one XCD (one L2): the J tiles of an (nc tile, batch) share the A tile
+  // (share_b = 0), the nc tiles of a (J tile, batch) share the B tile
+  // (share_b = 1)
+  int share_b = 0;
+  // tri_n > 0 (a multiple of 16): output row c is (x, p) = (c / tri_n,
+  // c % tri_n) and column j is q; 16 x 16 blocks whose every p exceeds every q
+  // are neither computed nor stored (the p > q half is filled from p < q)
+  int tri_n = 0;
 };
 void launch_gather_gemm(const GatherGemmArgs &a, hipStream_t s);
 

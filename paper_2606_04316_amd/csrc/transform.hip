@@ -473,13 +473,15 @@ void gather_quarter(const qdcb_plan &p, const Space &sp, const int32_t *rowmap, 
   g.C = p.W.p;
   g.ldc_c = (int64_t)nb * 4 * p.n;
   g.ldc_b = 4 * p.n;
+  g.share_b = 0;  // the J tiles of a batch read the same V rows
   launch_gather_gemm(g, s);
 }
 
 // Second quarter for nc columns: Gc[c] (+)= Ahat^T W[c], Ahat [4N][4n] (rows
 // (mu, z), columns (x, p)), W[c] [4N][n], Gc[c] [4n][n].  Tile 128: the
 // gathered-GEMM kernel with identity rows (A^T rows are Ahat's rows, one
-// W block per batch); tile 64: the batched GEMM.
+// W block per batch; quaternion plans compute only p <= q when 16 divides n);
+// tile 64: the batched GEMM.
 void second_quarter(const qdcb_plan &p, const double *Ahat, int N, bool accumulate, int nc,
                     hipStream_t s) {
   const int n = p.n;
@@ -501,6 +503,9 @@ void second_quarter(const qdcb_plan &p, const double *Ahat, int N, bool accumula
     g.ldc_c = n;
     g.ldc_b = (int64_t)4 * n * n;
     g.accumulate = accumulate ? 1 : 0;
+    g.share_b = 1;  // the (x, p) tiles of a column read the same W_c
+    // quaternion plans: only p <= q (the pack fills p > q by the bra-pair rule)
+    g.tri_n = !p.spinor && n % 16 == 0 ? n : 0;
     launch_gather_gemm(g, s);
   } else {
     launch_dgemm_batched(1, M, n, 4 * N, 1.0, Ahat, 4 * n, 0, p.W.p, n, (int64_t)N * 4 * n,
