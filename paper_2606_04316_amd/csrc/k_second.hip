@@ -51,15 +51,19 @@ void launch_build_coef_mats(int N, int n, const double *C, int unit, double *Cal
                      n, C, unit, Call, Chat);
 }
 
-// G_c entry (x, p, q) of slice column il * 4 + y for p <= q, and for p > q
-// from (x, q, p) by the bra-pair rule G_pq^x = mirror s_x G_qp^x (s_0 = +1,
-// s_1,2,3 = -1; mirror = +1 Coulomb, -1 Gaunt): the second quarter need not
-// compute the p > q half.
+// G_pq^x of slice column il * 4 + y (s_0 = +1, s_1,2,3 = -1).
+//   Coulomb (mirror = +1): Gc holds G_pq for p <= q; for p > q the bra-pair
+//     rule G_pq^x = s_x G_qp^x (the symmetric V of an unordered pair).
+//   Gaunt (mirror = -1): Gc holds T_pq, the term of the bra density
+//     conj(C^L_mu p) e_K C^S_nu q, for every (p, q).  The other term,
+//     conj(C^S_nu p) e_K C^L_mu q, is minus the conjugate of the first one at
+//     (q, p), so G_pq^x = T_pq^x - s_x T_qp^x.
 __device__ __forceinline__ double gc_entry(const double *Gc, int n, int64_t il, int y, int x,
                                            int p, int q, double mirror) {
-  if (p <= q) return Gc[((il * 4 + y) * 4 * n + (int64_t)x * n + p) * n + q];
-  const double v = Gc[((il * 4 + y) * 4 * n + (int64_t)x * n + q) * n + p];
-  return x == 0 ? mirror * v : -mirror * v;
+  const double *P = Gc + (il * 4 + y) * 4 * n * (int64_t)n + (int64_t)x * n * n;
+  const double sx = x == 0 ? 1.0 : -1.0;
+  if (mirror > 0) return p <= q ? P[(int64_t)p * n + q] : sx * P[(int64_t)q * n + p];
+  return P[(int64_t)p * n + q] - sx * P[(int64_t)q * n + p];
 }
 
 // One thread per (MO pair r <= s of the slice, p, q): 16 contiguous outputs.

@@ -293,7 +293,10 @@ void launch_pack_spinor(int n, const int32_t *rs, int nspair, int64_t c0, int nc
                         const double *Gc, double *G, int accumulate, hipStream_t s);
 // Scatter Gc[c][(x,p)][q] for MO-pair columns c of [c0, c0+nc) (c = 4 idx + y)
 // into G[p][q][r][s][x][y] and its mirror G[p][q][s][r][x][y] = mirror * s_y * v,
-// s = (+1,-1,-1,-1); accumulate = 1 adds to G instead of storing.
+// s = (+1,-1,-1,-1); accumulate = 1 adds to G instead of storing.  Coulomb
+// (mirror = +1): Gc holds p <= q (p > q by G_pq^x = s_x G_qp^x); Gaunt
+// (mirror = -1): Gc holds the first bra-density term T for every (p, q) and
+// G_pq^x = T_pq^x - s_x T_qp^x.
 void launch_pack(int n, const int32_t *rs, int64_t c0, int nc, const double *Gc, double *G,
                  double mirror, int accumulate, hipStream_t s);
 // Block output of the same slice: B[i][p][q][0][x][y] = v, B[i][p][q][1][x][y] =

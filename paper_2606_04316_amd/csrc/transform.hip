@@ -483,7 +483,7 @@ void gather_quarter(const qdcb_plan &p, const Space &sp, const int32_t *rowmap, 
 // W block per batch; quaternion plans compute only p <= q when 16 divides n);
 // tile 64: the batched GEMM.
 void second_quarter(const qdcb_plan &p, const double *Ahat, int N, bool accumulate, int nc,
-                    hipStream_t s) {
+                    hipStream_t s, bool upper = true) {
   const int n = p.n;
   const int M = (p.spinor ? 2 : 4) * n;  // output planes: re, im (spinors) or x = 0..3
   if (p.tune.sq_tile == 128) {
@@ -505,7 +505,7 @@ void second_quarter(const qdcb_plan &p, const double *Ahat, int N, bool accumula
     g.accumulate = accumulate ? 1 : 0;
     g.share_b = 1;  // the (x, p) tiles of a column read the same W_c
     // quaternion plans: only p <= q (the pack fills p > q by the bra-pair rule)
-    g.tri_n = !p.spinor && n % 16 == 0 ? n : 0;
+    g.tri_n = upper && !p.spinor && n % 16 == 0 ? n : 0;
     launch_gather_gemm(g, s);
   } else {
     launch_dgemm_batched(1, M, n, 4 * N, 1.0, Ahat, 4 * n, 0, p.W.p, n, (int64_t)N * 4 * n,
@@ -584,12 +584,10 @@ void second_half(qdcb_plan &p, int i0, int i1, double *dG, hipStream_t s, int cl
           second_quarter(p, p.ChatS.p, NS, true, nc, s);
           continue;
         }
-        // conj(C^L) e_K (V C^S): batches mu in L, sum over nu in S
+        // T = conj(C^L) e_K (V C^S): batches mu in L, sum over nu in S, every
+        // (p, q); the term conj(C^S) e_K C^L follows from T in the pack
         gather_quarter(p, p.G, p.rowmapLS.p, NS, 1, NL, NS, p.CallS.p, col0, nc, s);
-        second_quarter(p, p.AhatK[K].p, NL, K != 0, nc, s);
-        // conj(C^S) e_K (V^T C^L): batches nu in S, sum over mu in L
-        gather_quarter(p, p.G, p.rowmapLS.p, 1, NS, NS, NL, p.CallL.p, col0, nc, s);
-        second_quarter(p, p.BhatK[K].p, NS, true, nc, s);
+        second_quarter(p, p.AhatK[K].p, NL, K != 0, nc, s, false);
       }
       pack(-1.0, do_c ? 1 : 0);
     }
@@ -745,14 +743,18 @@ void fill_stats(qdcb_plan &p, qdcb_stats *stats, StageTimer *tm, double ms_total
   stats->flops_first_half =
       2.0 * (double)p.ncol * ktot + 2.0 * ls_mult * (double)p.ncol * (double)kg[0];
   double f2 = 0;
-  // second quarter: 2 (4n or 2n output rows) (4N) n per column
-  const double sq = p.spinor ? 16.0 : 32.0;
+  // per column: first quarter 2 N N 4n, second quarter 2 (4n or 2n output
+  // rows) (4N) n; quaternion plans take the Coulomb second quarter over p <= q
+  // and one of the two Gaunt chains (the other follows from it)
   for (int cls = 0; (p.classes & CLS_COULOMB) && cls < (p.NS ? 2 : 1); ++cls) {
     double N = cls ? p.NS : p.NL;
-    f2 += (8.0 * N * N * n + sq * N * n * n) * (double)p.ncol;
+    const double sq = p.spinor ? 16.0 * N * n * n : 16.0 * N * n * (n + 1.0);
+    f2 += (8.0 * N * N * n + sq) * (double)p.ncol;
   }
   if (ls)
-    f2 += 3.0 * (16.0 * p.NL * (double)p.NS * n + sq * (p.NL + p.NS) * (double)n * n) *
+    f2 += 3.0 *
+          (p.spinor ? 16.0 * p.NL * (double)p.NS * n + 16.0 * (p.NL + p.NS) * (double)n * n
+                    : 8.0 * p.NL * (double)p.NS * n + 32.0 * p.NL * (double)n * n) *
           (double)p.ncol;
   stats->flops_second_half = f2;
   stats->n_chunks = p.chunks_run;
