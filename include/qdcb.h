@@ -203,7 +203,9 @@ typedef struct {
     double tau;        /* Schwarz threshold: a directed contribution (mn <- kl) is
                           kept iff (Q_mn * Q_kl) * Dmax_kl >= tau, Eq. (SchwarzDen) */
     double tier_fp32;  /* QDCB_PREC_MIXED: a kept directed tile (b, k) with bound
-                          B = max_b Q * max_k (Q Dmax) is contracted in FP64 when
+                          B = max_b' Q * max_k (Q Dmax), b' over the bra tile and
+                          its pair partner (tiles 2i, 2i + 1; the first half
+                          contracts them together), is contracted in FP64 when
                           B >= tier_fp32, with FP32 MFMA operands when
                           tier_bf16 <= B < tier_fp32, else with BF16 operands (FP32
                           accumulation, power-of-2 block scales, V and the second

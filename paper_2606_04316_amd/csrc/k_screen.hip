@@ -207,7 +207,12 @@ __global__ void __launch_bounds__(256) k_tier_split(int ntiles, const double *Qm
                                                     int32_t *tcount, int32_t *toff) {
   __shared__ int wsum[4];
   const int b = blockIdx.x;
-  const double qb = gbound ? Bmax[b] : Qmax[b];
+  // the bra tile's bound, raised to its pair partner's (tiles 2i and 2i + 1,
+  // which the first half contracts in one workgroup): both tiles of a pair
+  // then take every ket tile in the same tier, so the per-tier launches keep
+  // the pair's shared staging
+  const int bp = (b ^ 1) < ntiles ? (b ^ 1) : b;
+  const double qb = gbound ? fmax(Bmax[b], Bmax[bp]) : fmax(Qmax[b], Qmax[bp]);
   const int64_t base = slot_base[b];
   const int n = count[b];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;

@@ -73,8 +73,10 @@ void launch_density(const DensityArgs &a, hipStream_t s);
 void launch_tile_bounds(int ntiles, const double *Q, const double *Dmax, double *Qmax,
                         double *Bmax, double *Dtmax, hipStream_t s);
 // Precision tiers of the directed tasks: tier 0 (FP64) when the tile bound
-// B = Qmax[b] * Bmax[k] >= t32, tier 1 (FP32) when >= t16, else tier 2 (BF16);
-// gbound = 1 uses B = Bmax[b] * Bmax[k] instead (bra-side density included).  Each
+// B = max(Qmax[b], Qmax[b ^ 1]) * Bmax[k] >= t32, tier 1 (FP32) when >= t16,
+// else tier 2 (BF16); gbound = 1 uses max(Bmax[b], Bmax[b ^ 1]) * Bmax[k]
+// instead (bra-side density included).  The bra bound is the larger of the
+// pair (b, b ^ 1), which the first half contracts together.  Each
 // bra tile's ordered list tasks[slot_base[b] + i] (i < count[b]) is split into
 // three ordered sub-lists stored in its own segment: ttasks[slot_base[b] +
 // toff[t*ntiles + b] + i] for i < tcount[t*ntiles + b], with trank = the
