@@ -54,9 +54,7 @@ __device__ __forceinline__ void wait_loads() {
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt, lgkmcnt unchanged (max)
 }
 
-// Precision of a first-half launch: FP64 (stores V) or a reduced tier (adds
-// to V).  The reduced tiers read the same FP64 staging buffers and round each
-// operand as it is loaded for the MFMA:
+// Reduced-precision tiers (k_first_half_lp): V += the tier's contributions.
 //   FP32: v_mfma_f32_16x16x4f32, lane l supplies A[l%16][l/16] and B[l/16][l%16];
 //   BF16: v_mfma_f32_16x16x16bf16_1k, lane l supplies A[l%16][4(l/16)..+3] and
 //         B[4(l/16)..+3][l%16];
@@ -64,83 +62,31 @@ __device__ __forceinline__ void wait_loads() {
 // tile (b, k) is multiplied by 2^-eI with 2^eI above the Cauchy-Schwarz bound
 // Qmax_b Qmax_k of its elements and the density rows of ket tile k by 2^-eD
 // with 2^eD above 2 max Dmax (the symmetrized density is a sum of two terms),
-// so every rounded operand is at most 1 in magnitude; each task's products
-// go to a scaled FP32 partial that is multiplied back by the exact
+// so every rounded operand is at most 1 in magnitude.  The density rows come
+// from an FP32 copy made with those scales (k_density_lo); each task's
+// products go to a scaled FP32 partial that is multiplied back by the exact
 // 2^(eI+eD) into the FP32 running sum, and V (FP64) receives the sum once.
 enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };
 
 typedef float flt4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ int scale_exp(double bound) {
-  int e = 0;
-  (void)frexp(bound, &e);  // bound < 2^e
-  return bound > 0.0 ? e : 0;
-}
-
-template <int PREC>
-struct FhAcc {
-  typedef typename std::conditional<PREC == PREC_F64, dbl4, flt4>::type V;
-  V acc[4][4];
-  V part[PREC == PREC_F64 ? 1 : 4][PREC == PREC_F64 ? 1 : 4];
-};
-
-// One step's MFMAs from staged FP64 buffers A (KH x AS_LD) and B (KH x BS_LD).
-template <int KH, int PREC>
+// One step's FP64 MFMAs from staged buffers A (KH x AS_LD) and B (KH x BS_LD).
+template <int KH>
 __device__ __forceinline__ void fh_mfma(const double *Ac, const double *Bc, int wr, int wc, int lr,
-                                        int lk, double sI, double sD, FhAcc<PREC> &f) {
-  if constexpr (PREC == PREC_F64) {
+                                        int lk, dbl4 (&acc)[4][4]) {
 #pragma unroll
-    for (int kk = 0; kk < KH / 4; ++kk) {
-      const int j = kk * 4 + lk;
-      double av[4], bv[4];
+  for (int kk = 0; kk < KH / 4; ++kk) {
+    const int j = kk * 4 + lk;
+    double av[4], bv[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) av[r] = Ac[j * AS_LD + wr * 64 + r * 16 + lr];
+    for (int r = 0; r < 4; ++r) av[r] = Ac[j * AS_LD + wr * 64 + r * 16 + lr];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) bv[c] = Bc[j * BS_LD + wc * 64 + c * 16 + lr];
+    for (int c = 0; c < 4; ++c) bv[c] = Bc[j * BS_LD + wc * 64 + c * 16 + lr];
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-          f.acc[r][c] = MFMA_F64(av[r], bv[c], f.acc[r][c]);
-    }
-  } else if constexpr (PREC == PREC_F32) {
-#pragma unroll
-    for (int kk = 0; kk < KH / 4; ++kk) {
-      const int j = kk * 4 + lk;
-      float av[4], bv[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) av[r] = (float)(Ac[j * AS_LD + wr * 64 + r * 16 + lr] * sI);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) bv[c] = (float)(Bc[j * BS_LD + wc * 64 + c * 16 + lr] * sD);
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-          f.part[r][c] =
-              __builtin_amdgcn_mfma_f32_16x16x4f32(av[r], bv[c], f.part[r][c], 0, 0, 0);
-    }
-  } else {
-#pragma unroll
-    for (int kk = 0; kk < KH / 16; ++kk) {
-      bf16x4 av[4], bv[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int j = kk * 16 + 4 * lk + t;
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          av[r][t] = (__bf16)(float)(Ac[j * AS_LD + wr * 64 + r * 16 + lr] * sI);
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-          bv[c][t] = (__bf16)(float)(Bc[j * BS_LD + wc * 64 + c * 16 + lr] * sD);
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-          f.part[r][c] =
-              __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[r], bv[c], f.part[r][c], 0, 0, 0);
-    }
+      for (int c = 0; c < 4; ++c) acc[r][c] = MFMA_F64(av[r], bv[c], acc[r][c]);
   }
 }
 
@@ -157,6 +103,7 @@ __device__ __forceinline__ int gauge_sym_index(int K, int L) {
 template <int KH, int PREC, bool TENSOR = false>
 __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, int nct, int ncx,
                                                     int64_t ldK, int accumulate) {
+  static_assert(PREC == PREC_F64, "the reduced tiers run in k_first_half_lp");
   constexpr int NS_MAX = TILE / KH;                      // steps per task and L run
   constexpr int NSTEP = (TENSOR ? 3 : 1) * NS_MAX;        // staged steps of a full task
   constexpr int64_t SLOT = (TENSOR ? 6 : 1) * TILE * TILE;  // doubles per panel slot
@@ -182,16 +129,17 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
   const int64_t l0 = s0 + (a.toff ? a.toff[bt0] : 0);
   const int64_t l1 = two ? s1 + (a.toff ? a.toff[bt0 + 1] : 0) : 0;
   const int n0 = a.count[bt0], n1 = two ? a.count[bt0 + 1] : 0;
-  if (PREC != PREC_F64 && n0 + n1 == 0) return;  // uniform: nothing to add in this tier
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = w >> 1, wc = w & 1;  // wave's 64-row half (bra tile) and 64-column half
   const int64_t c0 = (int64_t)ct * FH_COLS;
   const int lr = lane & 15, lk = lane >> 4;
   const int Kt = TENSOR ? (int)blockIdx.y : 0;
-  FhAcc<PREC> f;
+  struct {
+    dbl4 acc[4][4];
+  } f;
   for (int r = 0; r < 4; ++r)
-    for (int c = 0; c < 4; ++c) f.acc[r][c] = (typename FhAcc<PREC>::V){0, 0, 0, 0};
+    for (int c = 0; c < 4; ++c) f.acc[r][c] = (dbl4){0, 0, 0, 0};
   const int64_t vc0 = (TENSOR ? Kt * ldK : 0) + c0;  // this workgroup's first V column
   if (TENSOR && accumulate && (wr == 0 || two)) {
     // adding to V: the accumulators start from it (loaded before the loop,
@@ -205,11 +153,6 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
           f.acc[r][c][i] = a.V[row * a.ld + vc0 + wc * 64 + c * 16 + lr];
         }
   }
-  if constexpr (PREC != PREC_F64)
-    for (int r = 0; r < 4; ++r)
-      for (int c = 0; c < 4; ++c) f.part[r][c] = (typename FhAcc<PREC>::V){0, 0, 0, 0};
-  // bra tile bound of this wave's half (block scales of the reduced tiers)
-  const double qbw = PREC != PREC_F64 ? a.Qmax[bt0 + (two ? wr : 0)] : 0.0;
   // bra tile bounds of the pair (step skipping)
   const double qm0 = a.sthr ? a.Qmax[bt0] : 0.0, qm1 = a.sthr && two ? a.Qmax[bt0 + 1] : 0.0;
   const double tq = a.tau * (1.0 - 1e-12);
@@ -224,7 +167,6 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
   double th0[NS_MAX - 1], th1[NS_MAX - 1];
   int th_k0 = -1, th_k1 = -1;
   bool has0 = false, has1 = false;
-  int eI = 0, eD = 0;  // block-scale exponents of the current task (this wave's half)
   // heads of the two ordered lists, read one task ahead so that the list
   // reads are off the path between a barrier and the next step's loads
   // (with their panel ranks when the lists are tier sub-lists)
@@ -269,10 +211,6 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
       if (a.rank && i1 < n1) nr1 = a.rank[l1 + i1];
     } else {
       P1 = nullptr;
-    }
-    if (PREC != PREC_F64) {
-      eI = scale_exp(qbw * a.Qmax[kt]);
-      eD = scale_exp(2.0 * a.Dtmax[kt]);
     }
     if (a.sthr) {
       // steps whose largest ket bound passes against the bra tile's largest Q
@@ -330,42 +268,26 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
     }
   };
   // what the MFMAs of a staged step need, taken when the step is issued
-  struct StepDesc {
-    bool act, last;
-    int eI, eD;
-  };
-  auto desc = [&]() -> StepDesc {
+  auto desc = [&]() -> int {
     // this wave's bra tile: active while the step is within its own need
     const int hh = TENSOR ? h % ns : h;
     const int own = wr == 0 ? ns0 : ns1;
-    return StepDesc{(wr == 0 ? has0 : has1) && hh < own, hh == own - 1, eI, eD};
+    return (wr == 0 ? has0 : has1) && hh < own;
   };
-  // one staged step: MFMAs when this wave's bra tile keeps the task; at the
-  // task's last step the reduced tiers fold the scaled partial into the sum
-  auto run = [&](const double *A, const double *B, const StepDesc &d) {
-    if (!d.act) return;
-    fh_mfma<KH, PREC>(A, B, wr, wc, lr, lk, ldexp(1.0, -d.eI), ldexp(1.0, -d.eD), f);
-    if constexpr (PREC != PREC_F64) {
-      if (!d.last) return;
-      const float sc = ldexpf(1.0f, d.eI + d.eD);
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          f.acc[r][c] += f.part[r][c] * sc;
-          f.part[r][c] = (typename FhAcc<PREC>::V){0, 0, 0, 0};
-        }
-    }
+  // one staged step: MFMAs when this wave's bra tile keeps the task
+  auto run = [&](const double *A, const double *B, int act) {
+    if (!act) return;
+    fh_mfma<KH>(A, B, wr, wc, lr, lk, f.acc);
   };
 
   // steps alternate between the two buffers: even steps in 0, odd in 1
   bool more = advance();
-  StepDesc nxt = desc();
+  int nxt = desc();
   if (more) issue(As0, Bs0);
   while (more) {
     wait_loads();
     __syncthreads();  // even step staged by every wave; buffer 1's readers are done
-    StepDesc cur = nxt;
+    int cur = nxt;
     more = advance();
     if (more) {
       nxt = desc();
@@ -391,16 +313,264 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
     for (int c = 0; c < 4; ++c)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        if constexpr (PREC == PREC_F64) {
-          const int lr_ = r * 16 + lk + 4 * i;
-          const int64_t row = row0 + (a.perm ? a.perm[row0 + lr_] : lr_);
-          a.V[row * a.ld + vc0 + wc * 64 + c * 16 + lr] = f.acc[r][c][i];
-        } else {
-          const int lr_ = r * 16 + 4 * lk + i;
-          const int64_t row = row0 + (a.perm ? a.perm[row0 + lr_] : lr_);
-          a.V[row * a.ld + c0 + wc * 64 + c * 16 + lr] += (double)f.acc[r][c][i];
-        }
+        const int lr_ = r * 16 + lk + 4 * i;
+        const int64_t row = row0 + (a.perm ? a.perm[row0 + lr_] : lr_);
+        a.V[row * a.ld + vc0 + wc * 64 + c * 16 + lr] = f.acc[r][c][i];
       }
+}
+
+// ---------------------------------------------------------------------------
+// Reduced tiers.  Same workgroup and list structure as k_first_half, over the
+// tier's sub-lists: FP64 integral rows, density rows from the scaled FP32 copy
+// (16 + 8 KB per step), and three steps in flight, the loads of step t + 2
+// issued when step t starts (a reduced-precision step is too short to cover
+// the latency of loads issued one step ahead).  The list reads go through the
+// scalar cache, so the vector memory counter holds only the staging loads:
+// eight per wave and step (four integral rows, four density rows).
+constexpr int BL_LD = FH_COLS + 4;  // FP32 density row stride (floats; 16-byte rows, padded)
+
+typedef const __attribute__((address_space(4))) int32_t *ci32p;
+typedef const __attribute__((address_space(4))) int64_t *ci64p;
+typedef const __attribute__((address_space(4))) double *cdblp;
+
+// One step of a reduced tier into the per-task partial: A (KH x AS_LD, FP64
+// integrals, scaled by sI as they are rounded), B (KH x BL_LD, scaled FP32
+// densities).
+template <int TIER>
+__device__ __forceinline__ void lp_mfma(const double *Ac, const float *Bc, int wr, int wc, int lr,
+                                        int lk, double sI, flt4 (&part)[4][4]) {
+  constexpr int KH = FH_KH;
+  if constexpr (TIER == PREC_F32) {
+#pragma unroll
+    for (int kk = 0; kk < KH / 4; ++kk) {
+      const int j = kk * 4 + lk;
+      float av[4], bv[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) av[r] = (float)(Ac[j * AS_LD + wr * 64 + r * 16 + lr] * sI);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bv[c] = Bc[j * BL_LD + wc * 64 + c * 16 + lr];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          part[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[r], bv[c], part[r][c], 0, 0, 0);
+    }
+  } else {
+#pragma unroll
+    for (int kk = 0; kk < KH / 16; ++kk) {
+      bf16x4 av[4], bv[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int j = kk * 16 + 4 * lk + t;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          av[r][t] = (__bf16)(float)(Ac[j * AS_LD + wr * 64 + r * 16 + lr] * sI);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) bv[c][t] = (__bf16)Bc[j * BL_LD + wc * 64 + c * 16 + lr];
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          part[r][c] =
+              __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[r], bv[c], part[r][c], 0, 0, 0);
+    }
+  }
+}
+
+// Task descriptor of a reduced-tier list entry (k_tier_split): the steps its
+// bra tile needs (1..4), and the block-scale exponents eI, eD.
+__device__ __forceinline__ int lp_steps(int d) { return d & 7; }
+__device__ __forceinline__ int lp_eI(int d) { return ((d >> 3) & 2047) - 1024; }
+__device__ __forceinline__ int lp_eD(int d) { return ((d >> 14) & 2047) - 1024; }
+
+template <int TIER>
+__global__ void __launch_bounds__(256, 2) k_first_half_lp(FirstHalfArgs a, int nbp, int nct,
+                                                          int ncx) {
+  constexpr int KH = FH_KH;
+  constexpr int64_t SLOT = TILE * TILE;
+  // three staging buffers as distinct objects (so that the compiler can tell
+  // the loads into one from the reads of another)
+  __shared__ __attribute__((aligned(16))) double A0[KH * AS_LD], A1[KH * AS_LD], A2[KH * AS_LD];
+  __shared__ __attribute__((aligned(16))) float B0[KH * BL_LD], B1[KH * BL_LD], B2[KH * BL_LD];
+  if (a.overflow && *a.overflow) return;  // uniform: the task lists did not fit
+  int bp, ct;
+  if (ncx > 0) {  // XCD-aware order (as k_first_half)
+    const int L = blockIdx.x, x = L % N_XCD, loc = L / N_XCD;
+    bp = loc / ncx;
+    ct = x + N_XCD * (loc % ncx);
+    if (ct >= nct) return;  // uniform: ragged column slices
+  } else {
+    bp = blockIdx.x % nbp;
+    ct = blockIdx.x / nbp;
+  }
+  const ci32p tasks = (ci32p)a.tasks, rank = (ci32p)a.rank, tdesc = (ci32p)a.tdesc;
+  const ci32p count = (ci32p)a.count, toff = (ci32p)a.toff;
+  const ci64p slot_base = (ci64p)a.slot_base;
+  const int bt0 = a.b0 + 2 * bp;
+  const bool two = bt0 + 1 < a.b1;
+  const int64_t s0 = slot_base[bt0], s1 = two ? slot_base[bt0 + 1] : 0;
+  const int64_t l0 = s0 + toff[bt0], l1 = two ? s1 + toff[bt0 + 1] : 0;
+  const int n0 = count[bt0], n1 = two ? count[bt0 + 1] : 0;
+  if (n0 + n1 == 0) return;  // uniform: nothing to add in this tier
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = w >> 1, wc = w & 1;
+  const int64_t c0 = (int64_t)ct * FH_COLS;
+  const int lr = lane & 15, lk = lane >> 4;
+  flt4 acc[4][4], part[4][4];
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) acc[r][c] = part[r][c] = (flt4){0, 0, 0, 0};
+  // merged walk over the two lists (heads read one task ahead)
+  int i0 = 0, i1 = 0;
+  int nk0 = n0 > 0 ? tasks[l0] : INT_MAX, nk1 = n1 > 0 ? tasks[l1] : INT_MAX;
+  int nr0 = n0 > 0 ? rank[l0] : 0, nr1 = n1 > 0 ? rank[l1] : 0;
+  int nd0 = n0 > 0 ? tdesc[l0] : 0, nd1 = n1 > 0 ? tdesc[l1] : 0;
+  const double *P0 = nullptr, *P1 = nullptr;
+  int kt = 0, h = 0, nst = 0, ns0 = 0, ns1 = 0, d0 = 0, d1 = 0;
+  auto advance = [&]() -> bool {
+    if (++h < nst) return true;
+    if (nk0 == INT_MAX && nk1 == INT_MAX) return false;
+    kt = nk0 < nk1 ? nk0 : nk1;
+    const bool has0 = nk0 == kt, has1 = nk1 == kt;
+    P0 = P1 = nullptr;
+    ns0 = ns1 = 0;
+    if (has0) {
+      P0 = a.panel + (s0 + nr0 - a.slot0) * SLOT;
+      d0 = nd0;
+      ns0 = lp_steps(d0);
+      ++i0;
+      nk0 = i0 < n0 ? tasks[l0 + i0] : INT_MAX;
+      nr0 = i0 < n0 ? rank[l0 + i0] : 0;
+      nd0 = i0 < n0 ? tdesc[l0 + i0] : 0;
+    }
+    if (has1) {
+      P1 = a.panel + (s1 + nr1 - a.slot0) * SLOT;
+      d1 = nd1;
+      ns1 = lp_steps(d1);
+      ++i1;
+      nk1 = i1 < n1 ? tasks[l1 + i1] : INT_MAX;
+      nr1 = i1 < n1 ? rank[l1 + i1] : 0;
+      nd1 = i1 < n1 ? tdesc[l1 + i1] : 0;
+    }
+    nst = ns0 > ns1 ? ns0 : ns1;
+    h = 0;
+    return true;
+  };
+  // the current step's loads into stage st: wave w stages integral rows w,
+  // w+4, ... (lanes 0-31 bra tile bt0, 32-63 bt0+1; a lane half whose tile
+  // does not keep the task reads the other tile's row, unused) and density
+  // rows w, w+4, ... (lanes 0-31, 16 bytes each)
+  auto issue = [&](double *A, float *B) {
+    const double *P = lane < 32 ? (P0 ? P0 : P1) : (P1 ? P1 : P0);
+#pragma unroll
+    for (int q = 0; q < KH / 4; ++q) {
+      const int jj = w + 4 * q;
+      __builtin_amdgcn_global_load_lds(P + (h * KH + jj) * TILE + 2 * (lane & 31),
+                                       (lds_ptr)(A + jj * AS_LD), 16, 0, 0);
+    }
+    const float *Dr = a.Dlo + ((int64_t)kt * TILE + h * KH) * a.ld + c0 + 4 * lane;
+#pragma unroll
+    for (int q = 0; q < KH / 4; ++q) {
+      const int r = w + 4 * q;
+      if (lane < 32)
+        __builtin_amdgcn_global_load_lds(Dr + r * a.ld, (lds_ptr)(B + r * BL_LD), 16, 0, 0);
+    }
+  };
+  struct StepDesc {
+    bool act, last;
+    int eI, eD;
+  };
+  auto desc = [&]() -> StepDesc {
+    const int own = wr == 0 ? ns0 : ns1, d = wr == 0 ? d0 : d1;
+    return StepDesc{h < own, h == own - 1, lp_eI(d), lp_eD(d)};
+  };
+  auto run = [&](const double *A, const float *B, StepDesc d) {
+    if (!d.act) return;
+    lp_mfma<TIER>(A, B, wr, wc, lr, lk, ldexp(1.0, -d.eI), part);
+    if (!d.last) return;
+    const float sc = ldexpf(1.0f, d.eI + d.eD);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        acc[r][c] += part[r][c] * sc;
+        part[r][c] = (flt4){0, 0, 0, 0};
+      }
+  };
+  // three stages: step t in buffer t % 3.  Before step t runs, its loads
+  // (every wave's) are complete while step t + 1's may still be in flight;
+  // then step t + 2 is staged into the buffer step t - 1 was read from.  The
+  // barrier carries no memory fence: a fence would wait for every staging
+  // load, including step t + 1's.
+  bool more0 = advance();
+  StepDesc da = desc();
+  if (more0) issue(A0, B0);
+  bool more1 = more0 && advance();
+  StepDesc db = desc();
+  if (more1) issue(A1, B1);
+  auto step = [&](const double *Ar, const float *Br, double *Ai, float *Bi) {
+    if (more1)
+      __builtin_amdgcn_s_waitcnt(0x0F78);  // vmcnt(8): the next step's loads may be pending
+    else
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __asm__ volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    __asm__ volatile("" ::: "memory");
+    const bool more2 = more1 && advance();
+    const StepDesc dc = desc();
+    if (more2) issue(Ai, Bi);
+    run(Ar, Br, da);
+    da = db;
+    db = dc;
+    more0 = more1;
+    more1 = more2;
+  };
+  while (more0) {
+    step(A0, B0, A2, B2);
+    if (!more0) break;
+    step(A1, B1, A0, B0);
+    if (!more0) break;
+    step(A2, B2, A1, B1);
+  }
+  if (wr == 1 && !two) return;
+  const int64_t row0 = (int64_t)(bt0 + wr) * TILE;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int lr_ = r * 16 + 4 * lk + i;
+        const int64_t row = row0 + (a.perm ? a.perm[row0 + lr_] : lr_);
+        a.V[row * a.ld + c0 + wc * 64 + c * 16 + lr] += (double)acc[r][c][i];
+      }
+}
+
+// The reduced tiers' density operand: Dlo[r][c] = D~[r][c] 2^-eD (rounded to
+// FP32), eD = scale_exp(2 Dtmax[tile of r]), over rows [0, rows) of stride ld
+// (a multiple of 4).
+__global__ void __launch_bounds__(256) k_density_lo(int64_t rows, int64_t ld, const double *D,
+                                                    const double *Dtmax, float *Dlo) {
+  const int64_t n4 = rows * ld / 4;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = 4 * i, r = e / ld;
+    const double sc = ldexp(1.0, -scale_exp(2.0 * Dtmax[r / TILE]));
+    const double2 x = *reinterpret_cast<const double2 *>(D + e);
+    const double2 y = *reinterpret_cast<const double2 *>(D + e + 2);
+    *reinterpret_cast<float4 *>(Dlo + e) =
+        make_float4((float)(x.x * sc), (float)(x.y * sc), (float)(y.x * sc), (float)(y.y * sc));
+  }
+}
+
+void launch_density_lo(int64_t rows, int64_t ld, const double *D, const double *Dtmax, float *Dlo,
+                       hipStream_t s) {
+  const int64_t n4 = rows * ld / 4;
+  if (n4 <= 0) return;
+  const int64_t blocks = std::min<int64_t>((n4 + 255) / 256, 1 << 16);
+  hipLaunchKernelGGL(k_density_lo, dim3((unsigned)blocks), dim3(256), 0, s, rows, ld, D, Dtmax,
+                     Dlo);
 }
 
 void launch_first_half(const FirstHalfArgs &a, hipStream_t s) {
@@ -429,11 +599,11 @@ void launch_first_half_lp(const FirstHalfArgs &a, int tier, hipStream_t s) {
   const int ncx = !a.plain_order && nct >= N_XCD ? (nct + N_XCD - 1) / N_XCD : 0;
   const int64_t grid = ncx ? (int64_t)N_XCD * ncx * nbp : (int64_t)nbp * nct;
   if (tier == 2)
-    hipLaunchKernelGGL((k_first_half<FH_KH, PREC_BF16>), dim3((unsigned)grid), dim3(256), 0, s,
-                       a, nbp, nct, ncx, (int64_t)0, 0);
+    hipLaunchKernelGGL(k_first_half_lp<PREC_BF16>, dim3((unsigned)grid), dim3(256), 0, s, a, nbp,
+                       nct, ncx);
   else
-    hipLaunchKernelGGL((k_first_half<FH_KH, PREC_F32>), dim3((unsigned)grid), dim3(256), 0, s,
-                       a, nbp, nct, ncx, (int64_t)0, 0);
+    hipLaunchKernelGGL(k_first_half_lp<PREC_F32>, dim3((unsigned)grid), dim3(256), 0, s, a, nbp,
+                       nct, ncx);
 }
 
 }  // namespace qdcb

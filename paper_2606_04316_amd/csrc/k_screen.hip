@@ -198,13 +198,11 @@ void launch_screen_fill_u(int ntiles, const double *Qmax, const double *Bmax, do
 
 // Tier split: one workgroup per bra tile, three ordered compactions of its
 // task list (one per tier) into the same segment.
-__global__ void __launch_bounds__(256) k_tier_split(int ntiles, const double *Qmax,
-                                                    const double *Bmax, int gbound, double t32,
-                                                    double t16,
-                                                    const int64_t *slot_base,
-                                                    const int32_t *count, const int32_t *tasks,
-                                                    int32_t *ttasks, int32_t *trank,
-                                                    int32_t *tcount, int32_t *toff) {
+__global__ void __launch_bounds__(256) k_tier_split(
+    int ntiles, const double *Qmax, const double *Bmax, const double *Dtmax, const double *sthr,
+    double tau, int gbound, double t32, double t16, const int64_t *slot_base,
+    const int32_t *count, const int32_t *tasks, int32_t *ttasks, int32_t *trank, int32_t *tdesc,
+    int32_t *tcount, int32_t *toff) {
   __shared__ int wsum[4];
   const int b = blockIdx.x;
   // the bra tile's bound, raised to its pair partner's (tiles 2i and 2i + 1,
@@ -213,6 +211,7 @@ __global__ void __launch_bounds__(256) k_tier_split(int ntiles, const double *Qm
   // the pair's shared staging
   const int bp = (b ^ 1) < ntiles ? (b ^ 1) : b;
   const double qb = gbound ? fmax(Bmax[b], Bmax[bp]) : fmax(Qmax[b], Qmax[bp]);
+  const double qs = Qmax[b], tq = tau * (1.0 - 1e-12);
   const int64_t base = slot_base[b];
   const int n = count[b];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -237,8 +236,17 @@ __global__ void __launch_bounds__(256) k_tier_split(int ntiles, const double *Qm
       for (int j = 0; j < w; ++j) off += wsum[j];
       const int total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
       if (keep) {
-        ttasks[base + out + off + before] = k;
-        trank[base + out + off + before] = i;
+        const int64_t e = base + out + off + before;
+        ttasks[e] = k;
+        trank[e] = i;
+        int need = 4;
+        if (sthr) {
+          need = 1;
+          for (int st = 1; st < 4; ++st)
+            if (qs * sthr[(int64_t)k * 4 + st] >= tq) need = st + 1;
+        }
+        tdesc[e] = need | (scale_exp(qs * Qmax[k]) + 1024) << 3 |
+                   (scale_exp(2.0 * Dtmax[k]) + 1024) << 14;
       }
       out += total;
       __syncthreads();
@@ -250,14 +258,15 @@ __global__ void __launch_bounds__(256) k_tier_split(int ntiles, const double *Qm
   }
 }
 
-void launch_tier_split(int ntiles, const double *Qmax, const double *Bmax, int gbound,
-                       double t32, double t16, const int64_t *slot_base, const int32_t *count,
-                       const int32_t *tasks, int32_t *ttasks, int32_t *trank, int32_t *tcount,
+void launch_tier_split(int ntiles, const double *Qmax, const double *Bmax, const double *Dtmax,
+                       const double *sthr, double tau, int gbound, double t32, double t16,
+                       const int64_t *slot_base, const int32_t *count, const int32_t *tasks,
+                       int32_t *ttasks, int32_t *trank, int32_t *tdesc, int32_t *tcount,
                        int32_t *toff, hipStream_t s) {
   if (ntiles <= 0) return;
-  hipLaunchKernelGGL(k_tier_split, dim3(ntiles), dim3(256), 0, s, ntiles, Qmax, Bmax, gbound,
-                     t32, t16,
-                     slot_base, count, tasks, ttasks, trank, tcount, toff);
+  hipLaunchKernelGGL(k_tier_split, dim3(ntiles), dim3(256), 0, s, ntiles, Qmax, Bmax, Dtmax, sthr,
+                     tau, gbound, t32, t16, slot_base, count, tasks, ttasks, trank, tdesc, tcount,
+                     toff);
 }
 
 // Device-side exclusive scan of the per-bra-tile counts (one workgroup of

@@ -72,6 +72,14 @@ void launch_density(const DensityArgs &a, hipStream_t s);
 // and (when Dtmax is not NULL) Dtmax[t] = max Dmax.
 void launch_tile_bounds(int ntiles, const double *Q, const double *Dmax, double *Qmax,
                         double *Bmax, double *Dtmax, hipStream_t s);
+// Block-scale exponent of the reduced tiers: the e with bound < 2^e (0 for a
+// zero bound).
+__device__ __forceinline__ int scale_exp(double bound) {
+  int e = 0;
+  (void)frexp(bound, &e);
+  return bound > 0.0 ? e : 0;
+}
+
 // Precision tiers of the directed tasks: tier 0 (FP64) when the tile bound
 // B = max(Qmax[b], Qmax[b ^ 1]) * Bmax[k] >= t32, tier 1 (FP32) when >= t16,
 // else tier 2 (BF16); gbound = 1 uses max(Bmax[b], Bmax[b ^ 1]) * Bmax[k]
@@ -80,10 +88,15 @@ void launch_tile_bounds(int ntiles, const double *Q, const double *Dmax, double 
 // bra tile's ordered list tasks[slot_base[b] + i] (i < count[b]) is split into
 // three ordered sub-lists stored in its own segment: ttasks[slot_base[b] +
 // toff[t*ntiles + b] + i] for i < tcount[t*ntiles + b], with trank = the
-// task's rank i in the full list (its panel slot is slot_base[b] + rank).
-void launch_tier_split(int ntiles, const double *Qmax, const double *Bmax, int gbound,
-                       double t32, double t16, const int64_t *slot_base, const int32_t *count,
-                       const int32_t *tasks, int32_t *ttasks, int32_t *trank, int32_t *tcount,
+// task's rank i in the full list (its panel slot is slot_base[b] + rank) and
+// tdesc = the entry's descriptor for the reduced tiers: the 16-row steps bra
+// tile b needs (1 + the steps s >= 1 with Qmax[b] sthr[4 k + s] >= tau (1 -
+// 1e-12); 4 without sthr) | (eI + 1024) << 3 | (eD + 1024) << 14, with eI =
+// scale_exp(Qmax[b] Qmax[k]) and eD = scale_exp(2 Dtmax[k]).
+void launch_tier_split(int ntiles, const double *Qmax, const double *Bmax, const double *Dtmax,
+                       const double *sthr, double tau, int gbound, double t32, double t16,
+                       const int64_t *slot_base, const int32_t *count, const int32_t *tasks,
+                       int32_t *ttasks, int32_t *trank, int32_t *tdesc, int32_t *tcount,
                        int32_t *toff, hipStream_t s);
 // count[b] = number of ket tiles k with Qmax[b]*Bmax[k] >= tau*(1-1e-12).
 void launch_screen_count(int ntiles, const double *Qmax, const double *Bmax, double tau,
@@ -200,8 +213,11 @@ struct FirstHalfArgs {
   // tier sub-lists (NULL: the full directed lists): bra tile b's list starts at
   // slot_base[b] + toff[b], and entry e's panel slot is slot_base[b] + rank[e]
   const int32_t *toff = nullptr, *rank = nullptr;
-  // FP32 / BF16 tiers: per-tile bounds that set the power-of-2 block scales
-  const double *Qmax = nullptr, *Dtmax = nullptr;
+  // per-tile bounds Qmax (step skipping); reduced tiers: the entries'
+  // descriptors (launch_tier_split) and the scaled FP32 density rows
+  const double *Qmax = nullptr;
+  const int32_t *tdesc = nullptr;
+  const float *Dlo = nullptr;
   int b0, b1;
   const int64_t *slot_base;
   const int32_t *count;
@@ -234,8 +250,13 @@ void launch_first_half(const FirstHalfArgs &a, hipStream_t s);
 void launch_first_half_gauge(const FirstHalfArgs &a, int64_t ldK, int accumulate,
                              hipStream_t s);
 // Reduced-precision tiers: V += the tier's contributions, computed with FP32
-// (tier 1) or BF16 (tier 2) MFMA operands and FP32 accumulation.
+// (tier 1) or BF16 (tier 2) MFMA operands and FP32 accumulation, over the
+// tier sub-lists (toff, rank, tdesc) with the density rows of Dlo.
 void launch_first_half_lp(const FirstHalfArgs &a, int tier, hipStream_t s);
+// Dlo[r][c] = D[r][c] 2^-scale_exp(2 Dtmax[r / 64]) in FP32 for rows [0, rows)
+// of stride ld (a multiple of 4): the reduced tiers' density operand.
+void launch_density_lo(int64_t rows, int64_t ld, const double *D, const double *Dtmax, float *Dlo,
+                       hipStream_t s);
 
 // Batched FP64 GEMM, row-major: C[b] = alpha * op(A[b]) * B[b] + beta * C[b].
 // op(A) = A (transA = 0, A[m][k] at m*lda + k) or A^T (transA = 1, A[k][m] at k*lda + m).

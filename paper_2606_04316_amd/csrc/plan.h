@@ -35,7 +35,8 @@ struct Space {
   DBuf<unsigned long long> steps;  // first-half steps of the task lists (eager)
   unsigned long long h_steps = 0;
   // mixed precision: per-tier sub-lists of the directed tasks
-  DBuf<int32_t> ttasks, trank, tcount, toff;
+  DBuf<int32_t> ttasks, trank, tdesc, tcount, toff;
+  DBuf<float> Dlo;  // scaled FP32 copy of D~ (the reduced tiers' density operand)
   std::vector<int32_t> h_tcount;
   DBuf<int32_t> count, tasks, task_bra;
   DBuf<int64_t> slot_base;
@@ -70,7 +71,8 @@ struct Space {
            sthr.bytes() +
            wQ.bytes() + wDmax.bytes() + wrow_first.bytes() + wpp.bytes() + steps.bytes() +
            D.bytes() + V.bytes() + Dmax.bytes() + Qmax.bytes() + Bmax.bytes() + Dtmax.bytes() +
-           ttasks.bytes() + trank.bytes() + tcount.bytes() + toff.bytes() + count.bytes() +
+           ttasks.bytes() + trank.bytes() + tdesc.bytes() + tcount.bytes() + toff.bytes() +
+           Dlo.bytes() + count.bytes() +
            tasks.bytes() + task_bra.bytes() + slot_base.bytes() + panel.bytes() + panel3.bytes() + kept.bytes() +
            dtotal.bytes() + overflow.bytes() + ucount.bytes() + utask_k.bytes() +
            utask_b.bytes() + uslot_bk.bytes() + uslot_kb.bytes() + dmap.bytes() + ubase.bytes() + udtotal.bytes() +

@@ -254,7 +254,9 @@ namespace qdcb {
 
 double dv_bytes(const qdcb_plan &p, int64_t ci) {
   const int64_t ldK = round_up(4 * ci, 128);
-  return 16.0 * ((double)p.C.Ppad * ldK + (p.gaunt ? 3.0 * p.G.Ppad * ldK : 0.0));
+  // D~ and V in FP64, and (mixed precision) the FP32 copy of D~
+  const double per = p.desc.prec == QDCB_PREC_MIXED ? 20.0 : 16.0;
+  return per * ((double)p.C.Ppad * ldK + (p.gaunt ? 3.0 * p.G.Ppad * ldK : 0.0));
 }
 
 size_t g_stage_bytes(const qdcb_plan &p) {
@@ -271,6 +273,7 @@ void size_plan(qdcb_plan &p, int64_t slotsC, int64_t slotsG) {
   qdcb_ctx *ctx = p.ctx;
   for (Space *sp : {&p.C, &p.G}) {
     sp->D.free();
+    sp->Dlo.free();
     sp->V.free();
     sp->panel.free();
     sp->panel3.free();
@@ -311,6 +314,7 @@ void size_plan(qdcb_plan &p, int64_t slotsC, int64_t slotsG) {
     sp->ld_cap = sp->ld;
     sp->D.alloc(ctx, (size_t)sp->Ppad * sp->ld);
     HIPC(hipMemset(sp->D.p, 0, sp->D.bytes()));
+    if (p.desc.prec == QDCB_PREC_MIXED) sp->Dlo.alloc(ctx, (size_t)sp->Ppad * sp->ld);
     sp->V.alloc(ctx, (size_t)sp->Ppad * sp->ld);
   }
   // --- second-half slice: W and G slices
@@ -356,7 +360,8 @@ bool ensure_residency(qdcb_plan &p, double slack) {
   // memory the resizable buffers may use: what they hold now plus the free room
   size_t held = p.W.bytes() + p.Gc.bytes();
   for (const Space *sp : {&p.C, &p.G})
-    held += sp->D.bytes() + sp->V.bytes() + sp->panel.bytes() + sp->panel3.bytes();
+    held += sp->D.bytes() + sp->Dlo.bytes() + sp->V.bytes() + sp->panel.bytes() +
+            sp->panel3.bytes();
   const size_t g_stage = g_stage_bytes(p);
   // within the context budget and within what the device has free now (other
   // allocations of the process, such as the caller's G, count against it)
@@ -570,6 +575,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
       if (desc->prec == QDCB_PREC_MIXED) {
         sp->ttasks.alloc(ctx, cap);
         sp->trank.alloc(ctx, cap);
+        sp->tdesc.alloc(ctx, cap);
         sp->tcount.alloc(ctx, 3 * (size_t)sp->ntiles);
         sp->toff.alloc(ctx, 3 * (size_t)sp->ntiles);
       }
@@ -661,9 +667,10 @@ qdcb_status qdcb_plan_estimate(const qdcb_basis *L, const qdcb_basis *S,
       fail(QDCB_E_UNSUPPORTED, "the gauge term takes s functions only");
     double b = 2.0 * (cart ? 56.0 : 40.0) * prims;        // primitive-pair data (two orders)
     b += 88.0 * (PC + PG);                                // row metadata
-    b += 16.0 * (PC * ldK + 3.0 * PG * ldK);              // D~ and V, all columns
+    b += (desc->prec == QDCB_PREC_MIXED ? 20.0 : 16.0) *
+         (PC * ldK + 3.0 * PG * ldK);                     // D~, V (and FP32 D~), all columns
     b += 22.0 * (ntC * ntC + ntG * ntG);                  // task lists, unique pairs, slot map
-    if (desc->prec == QDCB_PREC_MIXED) b += 8.0 * (ntC * ntC + ntG * ntG);  // tier sub-lists
+    if (desc->prec == QDCB_PREC_MIXED) b += 12.0 * (ntC * ntC + ntG * ntG);  // tier sub-lists
     b += 8.0 * 256 * (std::max(NL, NS) * 4 * n + 4 * n * n);  // second-half slice
     b += 8.0 * 20.0 * (NL + NS) * n * 4;                  // coefficient matrices
     auto slots = [](double nt) { return std::min(nt * nt, std::max(nt, 65536.0)); };

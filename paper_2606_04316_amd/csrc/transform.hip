@@ -175,11 +175,11 @@ void screen(qdcb_plan &p, Space &sp, bool captured, hipStream_t s, bool zero_kep
     HIPC(hipStreamSynchronize(s));
   }
   if (p.desc.prec == QDCB_PREC_MIXED) {
-    launch_tier_split(sp.ntiles, sp.Qmax.p, sp.Bmax.p,
+    launch_tier_split(sp.ntiles, sp.Qmax.p, sp.Bmax.p, sp.Dtmax.p,
+                      p.tile_order ? sp.sthr.p : nullptr, p.desc.tau,
                       (p.desc.flags & QDCB_PLAN_TIER_BY_G) ? 1 : 0, p.desc.tier_fp32,
-                      p.desc.tier_bf16,
-                      sp.slot_base.p, sp.count.p, sp.tasks.p, sp.ttasks.p, sp.trank.p,
-                      sp.tcount.p, sp.toff.p, s);
+                      p.desc.tier_bf16, sp.slot_base.p, sp.count.p, sp.tasks.p, sp.ttasks.p,
+                      sp.trank.p, sp.tdesc.p, sp.tcount.p, sp.toff.p, s);
     HIPC(hipGetLastError());
     if (!captured) {
       sp.h_tcount.resize(3 * (size_t)sp.ntiles);
@@ -304,7 +304,8 @@ void contract(qdcb_plan &p, Space &sp, FirstHalfArgs fa, StageTimer &tm, hipStre
   fa.tasks = sp.ttasks.p;
   fa.rank = sp.trank.p;
   fa.Qmax = sp.Qmax.p;
-  fa.Dtmax = sp.Dtmax.p;
+  fa.tdesc = sp.tdesc.p;
+  fa.Dlo = sp.Dlo.p;
   const int stage[3] = {ST_FH, ST_FH32, ST_FH16};
   for (int t = 0; t < 3; ++t) {
     fa.count = sp.tcount.p + (size_t)t * sp.ntiles;
@@ -681,6 +682,9 @@ void enqueue(qdcb_plan &p, const double *dCL, const double *dCS, double *dG, boo
       if (mo) p.mo_work += (double)sp->ld * 0.25 * (double)sp->h_steps;
       tm.begin(ST_DENS);
       density(p, *sp, dCL, dCS, 0, i0, i1, s);
+      // the reduced tiers' scaled FP32 copy of the density rows
+      if (p.desc.prec == QDCB_PREC_MIXED)
+        launch_density_lo(sp->Ppad, sp->ld, sp->D.p, sp->Dtmax.p, sp->Dlo.p, s);
       tm.end();
       // captured mode keeps the tiles of the first chunk (one batch, resident)
       const bool resident = captured || sp->sym || sp->total <= sp->panel_slots;
