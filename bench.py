@@ -312,6 +312,15 @@ def main_transform(args):
         del G
         torch.cuda.empty_cache()
         line["cluster"] = cluster_leg(args)
+        # the metric's mixed-precision part: the best mixed leg on the cluster
+        # inputs that meets 1e-10 Eh (against the FP64 GPU transform)
+        ok = [m for m in line["cluster"]["mixed_vs_fp64"] if m["meets_1e-10"]]
+        best = max(ok, key=lambda m: m["speedup"]) if ok else None
+        line["mixed_vs_fp64_at_1e-10_Eh"] = {
+            "workload": line["cluster"]["workload"],
+            "speedup": best["speedup"] if best else None,
+            "tiers": [best["tier_fp32"], best["tier_bf16"], best["rule"]] if best else None,
+            "max_abs_err_Eh": best["max_abs_err_vs_fp64_gpu_Eh"] if best else None}
     if not args.no_cpu_baseline and not spinor and not rkbq:
         print("cpu baseline: oracle sample ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(sysm, args.cpu_rows, n)

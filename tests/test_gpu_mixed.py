@@ -1,9 +1,10 @@
 """GPU tests of the mixed-precision first half (FP64 / FP32 / BF16 tiers).
 
 Tiles are assigned to a tier by their bound: the screening bound
-B = max Q (bra tile) x max Q Dmax (ket tile), or with QDCB_PLAN_TIER_BY_G the
-bound B_G = max Q Dmax (bra tile) x max Q Dmax (ket tile) of a contribution's
-effect on G.  The FP64 tier run through the tier lists must equal the FP64
+B = max Q (bra tile pair) x max Q Dmax (ket tile), or with QDCB_PLAN_TIER_BY_G
+the bound B_G = max Q Dmax (bra tile pair) x max Q Dmax (ket tile) of a
+contribution's effect on G; the bra factor is taken over the pair of bra
+tiles (2i, 2i + 1) that one first-half workgroup contracts.  The FP64 tier run through the tier lists must equal the FP64
 plan bitwise (same tasks, same order).  The reduced tiers are checked element
 by element against an a-priori bound (tests/mixed_bound.py): the contribution
 bound decides the worst tier a contribution can land in, its rounding error is
@@ -152,6 +153,38 @@ def test_benchmark_tiers_meet_1e10_hartree(q, ctx, ham, coefs):
         assert err_o <= 1e-10 and fp64_o <= 1e-12 * np.abs(Go).max()
     else:
         assert fp64_o <= 1e-12 * _schwarz_scale(s)
+
+
+@pytest.mark.parametrize("budget_mb", [40, 24])
+def test_tiers_in_chunks_and_batches_within_a_priori_bound(q, budget_mb):
+    # small budgets: several MO-pair column chunks (each with its FP32 density
+    # copy) and bra-tile batches of the integral panels, so tier sub-lists
+    # start at odd bra tiles and the reduced-tier launches run per batch
+    s = wl.linear_chain(seed=42, n_atoms=6, spacing=3.0, nl_per_atom=3, ns_per_atom=5, n=16,
+                        tau=1e-10, ham="DCG", coefs="qr")
+    small = q.Context(0, budget_bytes=budget_mb << 20)
+    G1, st1 = _run(q, small, s, prec="mixed")
+    small.close()
+    print(f"budget {budget_mb} MB: chunks {st1['n_chunks']}, launches {st1['n_batches']}")
+    assert st1["n_chunks"] > 1
+    assert st1["tiles_tier"][1] > 0 and st1["tiles_tier"][2] > 0
+    _check_bound(s, G1, st1, "screen", 1e-4, 1e-7, f"DCG {budget_mb} MB tiers 1e-4 / 1e-7")
+
+
+def test_dcb_reduced_gaunt_tiers_match_fp64_within_operand_error(q, ctx):
+    # DCB mixed plans: the Gaunt term in tiers, the gauge term in FP64 over the
+    # same lists.  With every Gaunt tile in FP32 the result stays within the
+    # FP32 operand error of the FP64 plan.
+    s = wl.linear_chain(seed=63, n_atoms=5, spacing=3.0, nl_per_atom=3, ns_per_atom=4, n=5,
+                        tau=1e-10, ham="DCB", coefs="qr")
+    G0, st0 = _run(q, ctx, s)
+    G1, st1 = _run(q, ctx, s, prec="mixed", t32=HUGE, t16=0.0)
+    assert st1["tiles_tier"][1] == st1["tiles_kept"] > 0
+    assert st1["kept"] == st0["kept"] and st1["kept_gaunt"] == st0["kept_gaunt"]
+    err = float(np.abs(G1 - G0).max())
+    gmax = float(np.abs(G0).max())
+    print(f"DCB all Gaunt tiles FP32: max|G - G_FP64| {err:.3e}, max|G| {gmax:.3e}")
+    assert 0.0 < err <= 1e-5 * gmax
 
 
 def _schwarz_scale(s):
