@@ -19,7 +19,8 @@ __global__ void __launch_bounds__(256) k_dgemm_batched(int transA, int M, int N,
                                                        double alpha, const double *A,
                                                        int64_t lda, int64_t sA, const double *B,
                                                        int64_t ldb, int64_t sB, double beta,
-                                                       double *C, int64_t ldc, int64_t sC) {
+                                                       double *C, int64_t ldc, int64_t sC,
+                                                       int tri_n) {
   __shared__ double As[GB_K][GB_M + 2];
   __shared__ double Bs[GB_K][GB_N + 2];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -30,32 +31,30 @@ __global__ void __launch_bounds__(256) k_dgemm_batched(int transA, int M, int N,
   C += bz * sC;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   const int lr = lane & 15, lk = lane >> 4;
+  // triangle (tri_n > 0, a multiple of 16): row m is (x, p) = (m / tri_n,
+  // m % tri_n) and column n is q; 16 x 16 blocks whose every p exceeds every
+  // q are neither computed nor stored
+  unsigned skip = 0;
+  if (tri_n > 0)
+    for (int r = 0; r < 2; ++r)
+      for (int c = 0; c < 2; ++c)
+        if ((m0 + wr + r * 16) % tri_n >= n0 + wc + c * 16 + 16) skip |= 1u << (r * 2 + c);
   dbl4 acc[2][2];
   for (int r = 0; r < 2; ++r)
     for (int c = 0; c < 2; ++c) acc[r][c] = (dbl4){0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < K; k0 += GB_K) {
-    if (!transA) {  // A[m][k]: thread -> (m = tid/4, 4 consecutive k)
-      int m = tid >> 2, kq = (tid & 3) * 4;
+    // staging: lane l of each wave takes column l of its k rows, so that the
+    // 64 lanes of a wave write 64 consecutive doubles of one LDS row (no bank
+    // conflicts) and read consecutive m (op(A) = A^T) and n columns
+    const int col = tid & 63, kr = tid >> 6;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        int gm = m0 + m, gk = k0 + kq + i;
-        As[kq + i][m] = (gm < M && gk < K) ? A[(int64_t)gm * lda + gk] : 0.0;
-      }
-    } else {  // A[k][m]: thread -> (k = tid/16, 4 consecutive m)
-      int k = tid >> 4, mq = (tid & 15) * 4;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        int gm = m0 + mq + i, gk = k0 + k;
-        As[k][mq + i] = (gm < M && gk < K) ? A[(int64_t)gk * lda + gm] : 0.0;
-      }
-    }
-    {
-      int k = tid >> 4, nq = (tid & 15) * 4;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        int gn = n0 + nq + i, gk = k0 + k;
-        Bs[k][nq + i] = (gn < N && gk < K) ? B[(int64_t)gk * ldb + gn] : 0.0;
-      }
+    for (int i = 0; i < GB_K / 4; ++i) {
+      const int k = kr + 4 * i, gk = k0 + k;
+      const int gm = m0 + col, gn = n0 + col;
+      As[k][col] = (gm < M && gk < K)
+                       ? (transA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk])
+                       : 0.0;
+      Bs[k][col] = (gn < N && gk < K) ? B[(int64_t)gk * ldb + gn] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -65,7 +64,8 @@ __global__ void __launch_bounds__(256) k_dgemm_batched(int transA, int M, int N,
       for (int r = 0; r < 2; ++r) av[r] = As[k][wr + r * 16 + lr];
       for (int c = 0; c < 2; ++c) bv[c] = Bs[k][wc + c * 16 + lr];
       for (int r = 0; r < 2; ++r)
-        for (int c = 0; c < 2; ++c) acc[r][c] = MFMA_F64(av[r], bv[c], acc[r][c]);
+        for (int c = 0; c < 2; ++c)
+          if (!(skip >> (r * 2 + c) & 1u)) acc[r][c] = MFMA_F64(av[r], bv[c], acc[r][c]);
     }
     __syncthreads();
   }
@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(256) k_dgemm_batched(int transA, int M, int N,
     for (int c = 0; c < 2; ++c)
       for (int i = 0; i < 4; ++i) {
         int gm = m0 + wr + r * 16 + lk + 4 * i, gn = n0 + wc + c * 16 + lr;
-        if (gm < M && gn < N) {
+        if (gm < M && gn < N && !(skip >> (r * 2 + c) & 1u)) {
           double *p = C + (int64_t)gm * ldc + gn;
           double v = alpha * acc[r][c][i];
           *p = beta == 0.0 ? v : v + beta * *p;
@@ -84,11 +84,11 @@ __global__ void __launch_bounds__(256) k_dgemm_batched(int transA, int M, int N,
 void launch_dgemm_batched(int transA, int M, int N, int K, double alpha, const double *A,
                           int64_t lda, int64_t strideA, const double *B, int64_t ldb,
                           int64_t strideB, double beta, double *C, int64_t ldc, int64_t strideC,
-                          int batch, hipStream_t s) {
+                          int batch, hipStream_t s, int tri_n) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
   dim3 grid((M + GB_M - 1) / GB_M, (N + GB_N - 1) / GB_N, batch);
   hipLaunchKernelGGL(k_dgemm_batched, grid, dim3(256), 0, s, transA, M, N, K, alpha, A, lda,
-                     strideA, B, ldb, strideB, beta, C, ldc, strideC);
+                     strideA, B, ldb, strideB, beta, C, ldc, strideC, tri_n);
 }
 
 // ---------------------------------------------------------------------------

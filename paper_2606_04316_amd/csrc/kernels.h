@@ -260,10 +260,12 @@ void launch_density_lo(int64_t rows, int64_t ld, const double *D, const double *
 
 // Batched FP64 GEMM, row-major: C[b] = alpha * op(A[b]) * B[b] + beta * C[b].
 // op(A) = A (transA = 0, A[m][k] at m*lda + k) or A^T (transA = 1, A[k][m] at k*lda + m).
+// tri_n > 0 (a multiple of 16): row m is (x, p) = (m / tri_n, m % tri_n) and
+// column n is q; 16 x 16 blocks whose every p exceeds every q are skipped.
 void launch_dgemm_batched(int transA, int M, int N, int K, double alpha, const double *A,
                           int64_t lda, int64_t strideA, const double *B, int64_t ldb,
                           int64_t strideB, double beta, double *C, int64_t ldc,
-                          int64_t strideC, int batch, hipStream_t s);
+                          int64_t strideC, int batch, hipStream_t s, int tri_n = 0);
 
 // Gathered GEMM, 128 x 128 tiles: for every batch b < nb, c < nc and j < J,
 //   C[c * ldc_c + b * ldc_b + j] (+)= sum_{k < K} V[row(b, k) * ld + col0 + c] * B[b * sbB + k * ldb + j]

@@ -487,6 +487,8 @@ void second_quarter(const qdcb_plan &p, const double *Ahat, int N, bool accumula
                     hipStream_t s, bool upper = true) {
   const int n = p.n;
   const int M = (p.spinor ? 2 : 4) * n;  // output planes: re, im (spinors) or x = 0..3
+  // quaternion plans: only p <= q (the pack fills p > q by the bra-pair rule)
+  const int tri_n = upper && !p.spinor && n % 16 == 0 ? n : 0;
   if (p.tune.sq_tile == 128) {
     GatherGemmArgs g{};
     g.V = Ahat;
@@ -505,12 +507,11 @@ void second_quarter(const qdcb_plan &p, const double *Ahat, int N, bool accumula
     g.ldc_b = (int64_t)4 * n * n;
     g.accumulate = accumulate ? 1 : 0;
     g.share_b = 1;  // the (x, p) tiles of a column read the same W_c
-    // quaternion plans: only p <= q (the pack fills p > q by the bra-pair rule)
-    g.tri_n = upper && !p.spinor && n % 16 == 0 ? n : 0;
+    g.tri_n = tri_n;
     launch_gather_gemm(g, s);
   } else {
     launch_dgemm_batched(1, M, n, 4 * N, 1.0, Ahat, 4 * n, 0, p.W.p, n, (int64_t)N * 4 * n,
-                         accumulate ? 1.0 : 0.0, p.Gc.p, n, (int64_t)4 * n * n, nc, s);
+                         accumulate ? 1.0 : 0.0, p.Gc.p, n, (int64_t)4 * n * n, nc, s, tri_n);
   }
 }
 
