@@ -98,9 +98,9 @@ __device__ __forceinline__ double coulomb_kernel_tab(const double *tab, double i
     for (int k = 6; k >= 0; --k) f = fma(f, d, c[k]);
     return sr * f;  // the table carries the factor 2 / sqrt(pi)
   }
-  // far field, 1/R: the library rsqrt, whose longer sequence the compiler
-  // keeps behind a branch that wavefronts without such lanes skip
-  return rsqrt(r2);
+  // far field, 1/R (r2 > 0 here): the refined hardware estimate, a short
+  // branch for the lanes of a wavefront that take it
+  return rsqrt_pos(r2);
 }
 
 __device__ __forceinline__ double prim_quartet(double ip, double px, double py, double pz,

@@ -321,34 +321,49 @@ __global__ void __launch_bounds__(256) k_first_half(FirstHalfArgs a, int nbp, in
 
 // ---------------------------------------------------------------------------
 // Reduced tiers.  Same workgroup and list structure as k_first_half, over the
-// tier's sub-lists: FP64 integral rows, density rows from the scaled FP32 copy
-// (16 + 8 KB per step), and three steps in flight, the loads of step t + 2
-// issued when step t starts (a reduced-precision step is too short to cover
-// the latency of loads issued one step ahead).  The list reads go through the
-// scalar cache, so the vector memory counter holds only the staging loads:
-// eight per wave and step (four integral rows, four density rows).
-constexpr int BL_LD = FH_COLS + 4;  // FP32 density row stride (floats; 16-byte rows, padded)
+// tier's sub-lists.  The integral tiles of these entries were rounded once,
+// in their own panel slots, after they were made (k_panel_lo): FP32 tiles
+// [ket j][bra m] (16 KB) and BF16 tiles in groups of four ket rows
+// ([j / 4][m][j % 4], 8 KB), both already scaled by 2^-eI.  A step stages 8
+// (FP32) or 4 KB (BF16) of integrals and 8 KB of scaled FP32 densities, and
+// three steps are in flight, the loads of step t + 2 issued when step t
+// starts (a reduced-precision step is too short to cover the latency of
+// loads issued one step ahead).  The list reads go through the scalar cache,
+// so the vector memory counter holds only the staging loads: LP_LOADS per
+// wave and step.
+//
+// LDS row strides (4-byte words): FP32 integral and density rows 144 (rows
+// j and j + 1, read by lane groups lk and lk + 1, start 16 banks apart); BF16
+// integral blocks 288 (blocks lk and lk + 1 start 32 banks apart) and BF16
+// density rows 132 (rows 4 lk + t of lane groups lk and lk + 1 start 16
+// banks apart).
+constexpr int A32_LD = FH_COLS + 16;       // FP32 integral row (floats)
+constexpr int A16_LD = 2 * (FH_COLS + 16);  // BF16 block of four ket rows (words)
+template <int TIER> constexpr int lp_bl_ld() { return TIER == PREC_F32 ? FH_COLS + 16 : FH_COLS + 4; }
+template <int TIER> constexpr int lp_a_words() {
+  return TIER == PREC_F32 ? FH_KH * A32_LD : (FH_KH / 4) * A16_LD;
+}
+template <int TIER> constexpr int lp_loads() { return TIER == PREC_F32 ? 8 : 5; }
 
 typedef const __attribute__((address_space(4))) int32_t *ci32p;
 typedef const __attribute__((address_space(4))) int64_t *ci64p;
 typedef const __attribute__((address_space(4))) double *cdblp;
 
-// One step of a reduced tier into the per-task partial: A (KH x AS_LD, FP64
-// integrals, scaled by sI as they are rounded), B (KH x BL_LD, scaled FP32
-// densities).
+// One step of a reduced tier into the per-task partial: A (the step's
+// rounded integral rows, layout above), B (KH rows of scaled FP32 densities).
 template <int TIER>
-__device__ __forceinline__ void lp_mfma(const double *Ac, const float *Bc, int wr, int wc, int lr,
-                                        int lk, double sI, flt4 (&part)[4][4]) {
-  constexpr int KH = FH_KH;
+__device__ __forceinline__ void lp_mfma(const float *Ac, const float *Bc, int wr, int wc, int lr,
+                                        int lk, flt4 (&part)[4][4]) {
+  constexpr int KH = FH_KH, BL = lp_bl_ld<TIER>();
   if constexpr (TIER == PREC_F32) {
 #pragma unroll
     for (int kk = 0; kk < KH / 4; ++kk) {
       const int j = kk * 4 + lk;
       float av[4], bv[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) av[r] = (float)(Ac[j * AS_LD + wr * 64 + r * 16 + lr] * sI);
+      for (int r = 0; r < 4; ++r) av[r] = Ac[j * A32_LD + wr * 64 + r * 16 + lr];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) bv[c] = Bc[j * BL_LD + wc * 64 + c * 16 + lr];
+      for (int c = 0; c < 4; ++c) bv[c] = Bc[j * BL + wc * 64 + c * 16 + lr];
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -356,25 +371,22 @@ __device__ __forceinline__ void lp_mfma(const double *Ac, const float *Bc, int w
           part[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[r], bv[c], part[r][c], 0, 0, 0);
     }
   } else {
+    static_assert(KH == 16, "one BF16 MFMA step of 16 ket rows");
+    bf16x4 av[4], bv[4];
 #pragma unroll
-    for (int kk = 0; kk < KH / 16; ++kk) {
-      bf16x4 av[4], bv[4];
+    for (int r = 0; r < 4; ++r)
+      av[r] = *reinterpret_cast<const bf16x4 *>(Ac + lk * A16_LD + 2 * (wr * 64 + r * 16 + lr));
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int j = kk * 16 + 4 * lk + t;
+    for (int t = 0; t < 4; ++t) {
+      const int j = 4 * lk + t;
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          av[r][t] = (__bf16)(float)(Ac[j * AS_LD + wr * 64 + r * 16 + lr] * sI);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) bv[c][t] = (__bf16)Bc[j * BL_LD + wc * 64 + c * 16 + lr];
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-          part[r][c] =
-              __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[r], bv[c], part[r][c], 0, 0, 0);
+      for (int c = 0; c < 4; ++c) bv[c][t] = (__bf16)Bc[j * BL + wc * 64 + c * 16 + lr];
     }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        part[r][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[r], bv[c], part[r][c], 0, 0, 0);
   }
 }
 
@@ -387,12 +399,12 @@ __device__ __forceinline__ int lp_eD(int d) { return ((d >> 14) & 2047) - 1024; 
 template <int TIER>
 __global__ void __launch_bounds__(256, 2) k_first_half_lp(FirstHalfArgs a, int nbp, int nct,
                                                           int ncx) {
-  constexpr int KH = FH_KH;
+  constexpr int KH = FH_KH, BL = lp_bl_ld<TIER>(), AW = lp_a_words<TIER>();
   constexpr int64_t SLOT = TILE * TILE;
   // three staging buffers as distinct objects (so that the compiler can tell
   // the loads into one from the reads of another)
-  __shared__ __attribute__((aligned(16))) double A0[KH * AS_LD], A1[KH * AS_LD], A2[KH * AS_LD];
-  __shared__ __attribute__((aligned(16))) float B0[KH * BL_LD], B1[KH * BL_LD], B2[KH * BL_LD];
+  __shared__ __attribute__((aligned(16))) float A0[AW], A1[AW], A2[AW];
+  __shared__ __attribute__((aligned(16))) float B0[KH * BL], B1[KH * BL], B2[KH * BL];
   if (a.overflow && *a.overflow) return;  // uniform: the task lists did not fit
   int bp, ct;
   if (ncx > 0) {  // XCD-aware order (as k_first_half)
@@ -457,24 +469,34 @@ __global__ void __launch_bounds__(256, 2) k_first_half_lp(FirstHalfArgs a, int n
     h = 0;
     return true;
   };
-  // the current step's loads into stage st: wave w stages integral rows w,
-  // w+4, ... (lanes 0-31 bra tile bt0, 32-63 bt0+1; a lane half whose tile
-  // does not keep the task reads the other tile's row, unused) and density
-  // rows w, w+4, ... (lanes 0-31, 16 bytes each)
-  auto issue = [&](double *A, float *B) {
-    const double *P = lane < 32 ? (P0 ? P0 : P1) : (P1 ? P1 : P0);
+  // the current step's loads into stage st (a lane group whose tile does not
+  // keep the task reads the other tile's rows, unused).  FP32: wave w stages
+  // integral rows w, w+4, ... (lanes 0-15 bra tile bt0, 16-31 bt0+1);
+  // BF16: wave w stages the block of ket rows 4w..4w+3 (lanes 0-31 bt0, 32-63
+  // bt0+1).  Density rows w, w+4, ... (lanes 0-31, 16 bytes each).
+  auto issue = [&](float *A, float *B) {
+    if constexpr (TIER == PREC_F32) {
+      const float *P = reinterpret_cast<const float *>(lane < 16 ? (P0 ? P0 : P1)
+                                                                 : (P1 ? P1 : P0));
 #pragma unroll
-    for (int q = 0; q < KH / 4; ++q) {
-      const int jj = w + 4 * q;
-      __builtin_amdgcn_global_load_lds(P + (h * KH + jj) * TILE + 2 * (lane & 31),
-                                       (lds_ptr)(A + jj * AS_LD), 16, 0, 0);
+      for (int q = 0; q < KH / 4; ++q) {
+        const int jj = w + 4 * q;
+        if (lane < 32)
+          __builtin_amdgcn_global_load_lds(P + (h * KH + jj) * TILE + 4 * (lane & 15),
+                                           (lds_ptr)(A + jj * A32_LD), 16, 0, 0);
+      }
+    } else {
+      const __bf16 *P = reinterpret_cast<const __bf16 *>(lane < 32 ? (P0 ? P0 : P1)
+                                                                    : (P1 ? P1 : P0));
+      __builtin_amdgcn_global_load_lds(P + ((h * KH) / 4 + w) * (4 * TILE) + 8 * (lane & 31),
+                                       (lds_ptr)(A + w * A16_LD), 16, 0, 0);
     }
     const float *Dr = a.Dlo + ((int64_t)kt * TILE + h * KH) * a.ld + c0 + 4 * lane;
 #pragma unroll
     for (int q = 0; q < KH / 4; ++q) {
       const int r = w + 4 * q;
       if (lane < 32)
-        __builtin_amdgcn_global_load_lds(Dr + r * a.ld, (lds_ptr)(B + r * BL_LD), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(Dr + r * a.ld, (lds_ptr)(B + r * BL), 16, 0, 0);
     }
   };
   struct StepDesc {
@@ -485,9 +507,9 @@ __global__ void __launch_bounds__(256, 2) k_first_half_lp(FirstHalfArgs a, int n
     const int own = wr == 0 ? ns0 : ns1, d = wr == 0 ? d0 : d1;
     return StepDesc{h < own, h == own - 1, lp_eI(d), lp_eD(d)};
   };
-  auto run = [&](const double *A, const float *B, StepDesc d) {
+  auto run = [&](const float *A, const float *B, StepDesc d) {
     if (!d.act) return;
-    lp_mfma<TIER>(A, B, wr, wc, lr, lk, ldexp(1.0, -d.eI), part);
+    lp_mfma<TIER>(A, B, wr, wc, lr, lk, part);
     if (!d.last) return;
     const float sc = ldexpf(1.0f, d.eI + d.eD);
 #pragma unroll
@@ -509,9 +531,9 @@ __global__ void __launch_bounds__(256, 2) k_first_half_lp(FirstHalfArgs a, int n
   bool more1 = more0 && advance();
   StepDesc db = desc();
   if (more1) issue(A1, B1);
-  auto step = [&](const double *Ar, const float *Br, double *Ai, float *Bi) {
-    if (more1)
-      __builtin_amdgcn_s_waitcnt(0x0F78);  // vmcnt(8): the next step's loads may be pending
+  auto step = [&](const float *Ar, const float *Br, float *Ai, float *Bi) {
+    if (more1)  // vmcnt(LP_LOADS): the next step's loads may be pending
+      __builtin_amdgcn_s_waitcnt(0x0F70 | lp_loads<TIER>());
     else
       __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     __asm__ volatile("" ::: "memory");
@@ -547,6 +569,53 @@ __global__ void __launch_bounds__(256, 2) k_first_half_lp(FirstHalfArgs a, int n
       }
 }
 
+// Rounding of the reduced-tier integral tiles, in place, after they are
+// made: workgroup (b - b0, y) takes entries y, y + gridDim.y, ... of the
+// FP32 and BF16 sub-lists of bra tile b, reads the entry's whole FP64 tile,
+// and writes its scaled copy x 2^-eI into the start of the same slot (FP32
+// [j][m]; BF16 [j / 4][m][j % 4]).  Every value is read before any is written
+// (loads complete, then a barrier); slots of different entries are disjoint.
+__global__ void __launch_bounds__(256) k_panel_lo(PanelLoArgs a) {
+  if (a.overflow && *a.overflow) return;  // uniform: the task lists did not fit
+  constexpr int64_t SLOT = TILE * TILE;
+  const int b = a.b0 + blockIdx.x, t = threadIdx.x;
+  const int n32 = a.tcount[a.ntiles + b], n16 = a.tcount[2 * a.ntiles + b];
+  const int64_t sb = a.slot_base[b];
+  for (int e = blockIdx.y; e < n32 + n16; e += gridDim.y) {
+    const bool bf = e >= n32;  // uniform
+    const int64_t l = sb + (bf ? a.toff[2 * a.ntiles + b] + (e - n32) : a.toff[a.ntiles + b] + e);
+    double *T = a.panel + (sb + a.rank[l] - a.slot0) * SLOT;
+    const double sI = ldexp(1.0, -lp_eI(a.tdesc[l]));
+    double v[16];
+    if (!bf) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = T[t + 256 * i];
+      wait_loads();
+      __syncthreads();
+      float *F = reinterpret_cast<float *>(T);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) F[t + 256 * i] = (float)(v[i] * sI);
+    } else {
+      const int m = t & 63, q = t >> 6;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[4 * i + r] = T[(4 * (q + 4 * i) + r) * TILE + m];
+      wait_loads();
+      __syncthreads();
+      bf16x4 *H = reinterpret_cast<bf16x4 *>(T);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        bf16x4 x;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[r] = (__bf16)(float)(v[4 * i + r] * sI);
+        H[(q + 4 * i) * TILE + m] = x;
+      }
+    }
+    // slots of different entries are disjoint: no barrier before the next
+  }
+}
+
 // The reduced tiers' density operand: Dlo[r][c] = D~[r][c] 2^-eD (rounded to
 // FP32), eD = scale_exp(2 Dtmax[tile of r]), over rows [0, rows) of stride ld
 // (a multiple of 4).
@@ -571,6 +640,12 @@ void launch_density_lo(int64_t rows, int64_t ld, const double *D, const double *
   const int64_t blocks = std::min<int64_t>((n4 + 255) / 256, 1 << 16);
   hipLaunchKernelGGL(k_density_lo, dim3((unsigned)blocks), dim3(256), 0, s, rows, ld, D, Dtmax,
                      Dlo);
+}
+
+void launch_panel_lo(const PanelLoArgs &a, hipStream_t s) {
+  if (a.b1 <= a.b0) return;
+  // 8 workgroups per bra tile share its entries (at most 32768 tiles)
+  hipLaunchKernelGGL(k_panel_lo, dim3((unsigned)(a.b1 - a.b0), 8), dim3(256), 0, s, a);
 }
 
 void launch_first_half(const FirstHalfArgs &a, hipStream_t s) {

@@ -251,8 +251,23 @@ void launch_first_half_gauge(const FirstHalfArgs &a, int64_t ldK, int accumulate
                              hipStream_t s);
 // Reduced-precision tiers: V += the tier's contributions, computed with FP32
 // (tier 1) or BF16 (tier 2) MFMA operands and FP32 accumulation, over the
-// tier sub-lists (toff, rank, tdesc) with the density rows of Dlo.
+// tier sub-lists (toff, rank, tdesc), from the tiles rounded by
+// launch_panel_lo and the density rows of Dlo.
 void launch_first_half_lp(const FirstHalfArgs &a, int tier, hipStream_t s);
+// Rounds the integral tiles of the FP32 and BF16 sub-lists of bra tiles
+// [b0, b1) once, in their own panel slots (after the tiles are made, before
+// any reduced-tier contraction reads them): x 2^-eI to FP32 [j][m] or to BF16
+// [j / 4][m][j % 4] at the start of the slot.  Run once per generation of a
+// tile: a second pass would read rounded bytes as FP64.
+struct PanelLoArgs {
+  const int32_t *overflow = nullptr;  // graph mode: nothing to do when set
+  int b0, b1, ntiles;
+  const int64_t *slot_base;
+  const int32_t *tcount, *toff, *rank, *tdesc;  // [3][ntiles] counts, offsets; entries
+  int64_t slot0;
+  double *panel;  // [slots][64][64]
+};
+void launch_panel_lo(const PanelLoArgs &a, hipStream_t s);
 // Dlo[r][c] = D[r][c] 2^-scale_exp(2 Dtmax[r / 64]) in FP32 for rows [0, rows)
 // of stride ld (a multiple of 4): the reduced tiers' density operand.
 void launch_density_lo(int64_t rows, int64_t ld, const double *D, const double *Dtmax, float *Dlo,

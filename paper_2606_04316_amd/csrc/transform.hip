@@ -325,6 +325,28 @@ void contract(qdcb_plan &p, Space &sp, FirstHalfArgs fa, StageTimer &tm, hipStre
 // workgroups per compute unit).
 int eri_queue_blocks(const qdcb_plan &p) { return 2 * std::max(p.n_cu, 1); }
 
+// Mixed plans: the reduced-tier tiles of bra tiles [b0, b1), just made into
+// the panel at slot0, are rounded in place once (FP32 / BF16 operands of the
+// reduced tiers).  The gauge tiles are always FP64.
+void round_reduced_tiles(const qdcb_plan &p, Space &sp, int b0, int b1, int64_t slot0,
+                         double *panel, const int32_t *overflow, hipStream_t s) {
+  if (p.desc.prec != QDCB_PREC_MIXED) return;
+  PanelLoArgs la;
+  la.overflow = overflow;
+  la.b0 = b0;
+  la.b1 = b1;
+  la.ntiles = sp.ntiles;
+  la.slot_base = sp.slot_base.p;
+  la.tcount = sp.tcount.p;
+  la.toff = sp.toff.p;
+  la.rank = sp.trank.p;
+  la.tdesc = sp.tdesc.p;
+  la.slot0 = slot0;
+  la.panel = panel;
+  launch_panel_lo(la, s);
+  HIPC(hipGetLastError());
+}
+
 // Integral tiles + first half of one space over its current column chunk.
 // gauge >= 0: the gauge term of the L-S space (its six-tile panel, same task
 // lists and batches), adding to V when gauge = 1; breit: the Gaunt and gauge
@@ -363,9 +385,11 @@ void first_half(qdcb_plan &p, Space &sp, bool make_tiles, bool count, bool captu
         ea.d_total = sp.udtotal.p;
         ea.cap = sp.panel_slots;
         tiles(0, eri_queue_blocks(p), std::min<int64_t>(sp.panel_slots, (int64_t)sp.utask_k.n));
+        if (!g3) round_reduced_tiles(p, sp, 0, sp.ntiles, 0, sp.pan(), sp.overflow.p, s);
       } else {
         tm.begin(ST_ERI);
         tiles(sp.utotal, (int)std::min<int64_t>(eri_queue_blocks(p), sp.utotal), sp.utotal);
+        if (!g3) round_reduced_tiles(p, sp, 0, sp.ntiles, 0, sp.pan(), nullptr, s);
         tm.end();
         if (!g3) p.tiles_made += sp.utotal;
       }
@@ -382,10 +406,12 @@ void first_half(qdcb_plan &p, Space &sp, bool make_tiles, bool count, bool captu
       ea.d_total = sp.dtotal.p;
       ea.cap = sp.panel_slots;
       const int64_t n = std::min<int64_t>(sp.panel_slots, (int64_t)sp.ntiles * sp.ntiles);
-      if (g3)
+      if (g3) {
         launch_eri_gauge_tiles(ea, n, s);
-      else
+      } else {
         launch_eri_tiles(ea, n, s);
+        round_reduced_tiles(p, sp, 0, sp.ntiles, 0, sp.pan(), sp.overflow.p, s);
+      }
     }
     FirstHalfArgs fa = fh_args(p, sp, 0, sp.ntiles, 0, g3);
     fa.overflow = sp.overflow.p;
@@ -434,10 +460,12 @@ void first_half(qdcb_plan &p, Space &sp, bool make_tiles, bool count, bool captu
       EriTileArgs ea = eri_args(p, sp, sp.base[B.b0], count, g3, breit);
       ea.panel = panel;
       tm.begin(ST_ERI, es);
-      if (g3)
+      if (g3) {
         launch_eri_gauge_tiles(ea, B.used, es);
-      else
+      } else {
         launch_eri_tiles(ea, B.used, es);
+        round_reduced_tiles(p, sp, B.b0, B.b1, sp.base[B.b0], panel, nullptr, es);
+      }
       if (!g3) p.tiles_made += B.used;
       tm.end(es);
       HIPC(hipGetLastError());

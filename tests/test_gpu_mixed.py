@@ -12,7 +12,7 @@ at most eps_tier |I| |D~| (operand unit roundoff and FP32 accumulation), and
 the second half carries it into G through the bra pair densities; the FP64
 oracle is the reference, on well-conditioned (QR) coefficients where the FP64
 part of the error is below 1e-12 of max|G|.  On the chain recipe with Loewdin
-coefficients, the tiers the benchmark reports (G rule, 1e-6 / 1e-9) must keep
+coefficients, the tiers the benchmark reports (G rule, 3e-6 / 1e-9) must keep
 the reduced tiers' error (against the FP64 transform) below 1e-10 Eh, and on QR
 coefficients max|G - G_oracle| <= 1e-10 Eh.
 """
@@ -127,7 +127,7 @@ def test_specified_tiers_within_a_priori_bound(q, ctx, ham, rule):
 @pytest.mark.parametrize("ham", ["DC", "DCG"])
 @pytest.mark.parametrize("coefs", ["qr", "loewdin"])
 def test_benchmark_tiers_meet_1e10_hartree(q, ctx, ham, coefs):
-    # the tiers the benchmark reports: G rule, FP32 below 1e-6, BF16 below
+    # the tiers the benchmark reports: G rule, FP32 below 3e-6, BF16 below
     # 1e-9.  QR coefficients: max|G_mixed - G_oracle| <= 1e-10 Eh directly.
     # Loewdin coefficients (the benchmark's inputs, at test size): there the
     # FP64 path and the oracle already differ at the 1e-10 level (the MO
@@ -137,7 +137,7 @@ def test_benchmark_tiers_meet_1e10_hartree(q, ctx, ham, coefs):
     # the FP64 transform is held to the oracle at the parity tolerance.
     s = (QR_SYSTEMS if coefs == "qr" else SYSTEMS)[ham]()
     G0, st0 = _run(q, ctx, s)
-    G1, st1 = _run(q, ctx, s, prec="mixed", t32=1e-6, t16=1e-9, flags=q.PLAN_TIER_BY_G)
+    G1, st1 = _run(q, ctx, s, prec="mixed", t32=3e-6, t16=1e-9, flags=q.PLAN_TIER_BY_G)
     Go, so = oracle.transform_direct(s.L, s.S, s.CL, s.CS, ham, s.tau)
     assert st1["kept"] == so["kept"] and st1["kept_gaunt"] == so["kept_gaunt"]
     assert st1["tiles_tier"][1] > 0
@@ -145,7 +145,7 @@ def test_benchmark_tiers_meet_1e10_hartree(q, ctx, ham, coefs):
     err_64 = float(np.abs(G1 - G0).max())
     fp64_o = float(np.abs(G0 - Go).max())
     dj = abs(_j_occ(G1) - _j_occ(G0))
-    print(f"{ham} {coefs} G rule 1e-6 / 1e-9: tiles {st1['tiles_tier']}, max|G - G_FP64| "
+    print(f"{ham} {coefs} G rule 3e-6 / 1e-9: tiles {st1['tiles_tier']}, max|G - G_FP64| "
           f"{err_64:.3e} Eh, max|G - G_oracle| {err_o:.3e} Eh (FP64 vs oracle {fp64_o:.3e}), "
           f"|dJ_occ| {dj:.3e}, max|G| {np.abs(Go).max():.3e}")
     assert err_64 <= 1e-10
