@@ -172,6 +172,15 @@ def main():
     return main_transform(args)
 
 
+def shell_kinds(sysm):
+    """The angular momenta present in the system's bases ("s", "s, p", "s, p, d")."""
+    codes = [c for B in (sysm.L, sysm.S) if B is not None and getattr(B, "cart", None) is not None
+             for c in B.cart]
+    if not codes:
+        return "s"
+    return "s, p, d" if max(codes) >= 4 else "s, p"
+
+
 def main_transform(args):
     import numpy as np
     import torch
@@ -287,7 +296,7 @@ def main_transform(args):
                    "algorithm": f"MO-driven, {args.mo_batch} MO pairs per batch"
                    if args.mo_batch else "AO-driven",
                    "row_order": "Schwarz" if args.schwarz_rows else "primitive bands",
-                   "shells": "s, p" if getattr(sysm.L, "cart", None) is not None else "s",
+                   "shells": shell_kinds(sysm),
                    "small_components": "RKB (gradient basis)" if rkb else
                    "RKB (gradient basis), Kramers-restricted" if rkbq else "stand-in basis"},
         "spinor_integrals_per_s": (n if spinor else 2 * n) ** 4 * args.steps / elapsed,

@@ -22,6 +22,10 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // function in its erf form F0(T) = (1/2) sqrt(pi/T) erf(sqrt T).
 // Bases with p functions add, per primitive pair of functions (f, g),
 //   pa = P_i - A_i for f = p_i on centre A (0 for s), pb = P_j - B_j for g.
+// Primitive-pair data: 1/p, P, the charge factor e, and for Cartesian bases
+// pa / pb = (P - A) and (P - B) along the direction of a p function (0 for
+// an s function) and the full vectors P - A = (ax, ay, az), P - B = (bx, by,
+// bz) (the general kernels of bases with d functions).
 struct PrimPairs {
   double *ip;
   double *x;
@@ -30,14 +34,19 @@ struct PrimPairs {
   double *e;
   double *pa = nullptr;
   double *pb = nullptr;
+  double *ax = nullptr, *ay = nullptr, *az = nullptr;
+  double *bx = nullptr, *by = nullptr, *bz = nullptr;
 };
 
 struct PrimPairsC {
   const double *ip, *x, *y, *z, *e, *pa, *pb;
+  const double *ax, *ay, *az, *bx, *by, *bz;
   __host__ __device__ PrimPairsC()
-      : ip(nullptr), x(nullptr), y(nullptr), z(nullptr), e(nullptr), pa(nullptr), pb(nullptr) {}
+      : ip(nullptr), x(nullptr), y(nullptr), z(nullptr), e(nullptr), pa(nullptr), pb(nullptr),
+        ax(nullptr), ay(nullptr), az(nullptr), bx(nullptr), by(nullptr), bz(nullptr) {}
   __host__ __device__ PrimPairsC(const PrimPairs &s)
-      : ip(s.ip), x(s.x), y(s.y), z(s.z), e(s.e), pa(s.pa), pb(s.pb) {}
+      : ip(s.ip), x(s.x), y(s.y), z(s.z), e(s.e), pa(s.pa), pb(s.pb), ax(s.ax), ay(s.ay),
+        az(s.az), bx(s.bx), by(s.by), bz(s.bz) {}
 };
 
 // erf(sqrt(rho) R) / R for one primitive quartet; two Taylor terms of
@@ -71,6 +80,9 @@ constexpr int BOYS_LD = 10;
 // Columns of the table of the Cartesian (s/p) integral tiles: F_0 .. F_11, so
 // that F_0 .. F_4 each take eight Taylor terms
 constexpr int BOYS_LDC = 12;
+// Columns of the table of the general (s, p, d) tiles: F_0 .. F_15 (F_0 .. F_8
+// with eight Taylor terms each)
+constexpr int BOYS_LDG = 16;
 
 // 1/sqrt(x) for finite x > 0: the hardware estimate y and one second-order
 // correction from the binomial series, y (1 + e/2 + 3 e^2/8), e = 1 - x y^2.
@@ -126,8 +138,8 @@ __device__ __forceinline__ double contracted_eri(const PrimPairsC &A, int64_t a0
 // ---------------------------------------------------------------------------
 // Integrals over Cartesian s and p functions (McMurchie-Davidson form).
 //
-// A function pair (f, g) has the code cf | (cg << 2), c = 0 for s and
-// 1, 2, 3 for p_x, p_y, p_z.  With Lambda_t the Hermite Gaussians
+// A function pair (f, g) has the code cf | (cg << 4), c = 0 for s and
+// 1, 2, 3 for p_x, p_y, p_z (4 .. 9 for d functions, general form below).  With Lambda_t the Hermite Gaussians
 // d^t/dP^t exp(-p|r-P|^2), a pair's product expands over at most four of
 // them: for f = p_i on A and g = p_j on B
 //   (PA_i PB_j + delta_ij / 2p) L_0 + PB_j / 2p L_{e_i} + PA_i / 2p L_{e_j}
@@ -172,8 +184,8 @@ __device__ __forceinline__ double herm_r4(int i, int j, int k, int l, const doub
 // second function, or -1 for an s function.  inv2p = 1 / (2p).
 __device__ __forceinline__ void herm_side(int code, double pa, double pb, double inv2p,
                                           double h[4], int &a, int &b) {
-  a = (code & 3) - 1;
-  b = ((code >> 2) & 3) - 1;
+  a = (code & 15) - 1;
+  b = ((code >> 4) & 15) - 1;
   const double fa = a >= 0 ? pa : 1.0, fb = b >= 0 ? pb : 1.0;
   h[0] = fa * fb + ((a >= 0 && a == b) ? inv2p : 0.0);
   h[1] = a >= 0 ? fb * inv2p : 0.0;
@@ -287,6 +299,199 @@ __device__ inline double contracted_eri_cart(const PrimPairsC &A, int64_t a0, in
       s += B.e[k] * cart_quartet_exact(A.ip[i], A.x[i], A.y[i], A.z[i], pa, pb, ca, B.ip[k],
                                        B.x[k], B.y[k], B.z[k], B.pa ? B.pa[k] : 0.0,
                                        B.pb ? B.pb[k] : 0.0, cb);
+    acc += A.e[i] * s;
+  }
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
+// Integrals over Cartesian s, p and d functions, general form (bases with d
+// functions).  Codes 4 .. 9 are d_xx, d_yy, d_zz, d_xy, d_xz, d_yz, i.e. the
+// monomial (x - A_x)^{l_x} (y - A_y)^{l_y} (z - A_z)^{l_z}.
+// McMurchie-Davidson form: per Cartesian direction the product of the two
+// functions of a pair expands in Hermite Gaussians with the coefficients
+// E^{ij}_t (t <= i + j) of the recursion
+//   E^{i+1,j}_t = E^{ij}_{t-1} / (2p) + X_PA E^{ij}_t + (t + 1) E^{ij}_{t+1}
+// (likewise j + 1 with X_PB), E^{00}_0 = 1.  The Hermite integral of orders
+// (T, U, V) is the derivative of g_0 (a function of |X|^2, X = P - Q):
+//   R_TUV = sum_{a, b, c} h_T^a(X_x) h_U^b(X_y) h_V^c(X_z) G_{T+U+V-a-b-c},
+//   h_T^a(x) = T! / (a! (T - 2a)! 2^a) x^{T-2a},   G_n = (-2 rho)^n g_n,
+// so with H_x[T] = sum_{t + u = T} Ebra_x[t] (-1)^u Eket_x[u] and
+// P_x[s] = sum_T H_x[T] h_T^{T-s}(X_x) the value of a primitive quartet is
+//   sum_{s_x, s_y, s_z} P_x[s_x] P_y[s_y] P_z[s_z] G_{s_x + s_y + s_z}
+// (the same sums, factorized by direction).
+// ---------------------------------------------------------------------------
+constexpr int GEN_T = 4;              // Hermite order of one pair per direction (two d)
+constexpr int GEN_S = 2 * GEN_T;      // Hermite order of a quartet per direction
+constexpr int GEN_NG = 2 * GEN_T + 1;  // Boys orders g_0 .. g_8 (four d functions)
+
+// a pair code with a d function (the general form)
+__host__ __device__ __forceinline__ bool gen_code(int c) {
+  return (c & 15) >= 4 || ((c >> 4) & 15) >= 4;
+}
+
+// powers (l_x, l_y, l_z) of a function code 0 .. 9, two bits each, six per code
+__device__ __forceinline__ int cart_pow(int code, int dir) {
+  constexpr unsigned long long PK =
+      (0ull) | (1ull << 6) | (4ull << 12) | (16ull << 18) | (2ull << 24) | (8ull << 30) |
+      (32ull << 36) | (5ull << 42) | (17ull << 48) | (20ull << 54);
+  return (int)((PK >> (6 * code + 2 * dir)) & 3ull);
+}
+
+// E^{ij}_t, t <= GEN_T, for i, j <= 2 (one direction of one primitive pair).
+__device__ __forceinline__ void herm_raise(double E[GEN_T + 1], double x, double h) {
+  double N[GEN_T + 1];
+#pragma unroll
+  for (int t = 0; t <= GEN_T; ++t) {
+    double v = x * E[t];
+    if (t + 1 <= GEN_T) v = fma((double)(t + 1), E[t + 1], v);
+    if (t >= 1) v = fma(h, E[t - 1], v);
+    N[t] = v;
+  }
+#pragma unroll
+  for (int t = 0; t <= GEN_T; ++t) E[t] = N[t];
+}
+__device__ __forceinline__ void herm_1d(int i, int j, double pa, double pb, double h,
+                                        double E[GEN_T + 1]) {
+  E[0] = 1.0;
+#pragma unroll
+  for (int t = 1; t <= GEN_T; ++t) E[t] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+    if (k < i) herm_raise(E, pa, h);
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+    if (k < j) herm_raise(E, pb, h);
+}
+
+// P[s] = sum_T H[T] h_T^{T-s}(x), H[T] = sum_{t+u=T} Eb[t] (-1)^u Ek[u].
+__device__ __forceinline__ void herm_dir(const double Eb[GEN_T + 1], const double Ek[GEN_T + 1],
+                                         double x, double P[GEN_S + 1]) {
+  double H[GEN_S + 1];
+#pragma unroll
+  for (int T = 0; T <= GEN_S; ++T) H[T] = 0.0;
+#pragma unroll
+  for (int t = 0; t <= GEN_T; ++t)
+#pragma unroll
+    for (int u = 0; u <= GEN_T; ++u) H[t + u] = fma(Eb[t], (u & 1) ? -Ek[u] : Ek[u], H[t + u]);
+  double xp[GEN_S + 1];
+  xp[0] = 1.0;
+#pragma unroll
+  for (int k = 1; k <= GEN_S; ++k) xp[k] = xp[k - 1] * x;
+#pragma unroll
+  for (int q = 0; q <= GEN_S; ++q) P[q] = 0.0;
+  // h_T^a = T! / (a! (T - 2a)! 2^a): products of integers, exact in double
+#pragma unroll
+  for (int T = 0; T <= GEN_S; ++T) {
+    double c = 1.0;  // h_T^0
+#pragma unroll
+    for (int a = 0; 2 * a <= T; ++a) {
+      P[T - a] = fma(H[T] * c, xp[T - 2 * a], P[T - a]);
+      // h_T^{a+1} / h_T^a = (T - 2a)(T - 2a - 1) / (2 (a + 1))
+      c = c * (double)((T - 2 * a) * (T - 2 * a - 1)) / (double)(2 * (a + 1));
+    }
+  }
+}
+
+// Sum over (s_x, s_y, s_z) of P_x P_y P_z G_{s_x+s_y+s_z} (orders above
+// GEN_S vanish: the Hermite orders of a quartet add up to at most GEN_S).
+__device__ __forceinline__ double herm_sum(const double Px[GEN_S + 1], const double Py[GEN_S + 1],
+                                           const double Pz[GEN_S + 1], const double G[GEN_NG]) {
+  double Q[GEN_S + 1];
+#pragma unroll
+  for (int n = 0; n <= GEN_S; ++n) Q[n] = 0.0;
+#pragma unroll
+  for (int a = 0; a <= GEN_S; ++a)
+#pragma unroll
+    for (int b = 0; a + b <= GEN_S; ++b) Q[a + b] = fma(Px[a], Py[b], Q[a + b]);
+  double v = 0.0;
+#pragma unroll
+  for (int m = 0; m <= GEN_S; ++m) {
+    double w = 0.0;
+#pragma unroll
+    for (int c = 0; m + c <= GEN_S; ++c) w = fma(Pz[c], G[m + c], w);
+    v = fma(Q[m], w, v);
+  }
+  return v;
+}
+
+// g_n = (2/sqrt(pi)) sqrt(rho) F_n(T), n < NG, without a table: below T = 10
+// from the series of F_{NG-1} and the downward recursion; from T = 10 on from
+// the erf form of F_0 and the upward recursion (stable there for n <= 8).
+template <int NG>
+__device__ inline void boys_g_exact_n(double T, double sr, double g[NG]) {
+  const double c = TWO_OVER_SQRTPI * sr;
+  const double eT = exp(-T);
+  if (T < 10.0) {
+    constexpr int M = NG - 1;
+    double term = 1.0 / (2.0 * M + 1.0), sum = term;
+    for (int k = 1; k < 300; ++k) {
+      term *= 2.0 * T / (2.0 * M + 1.0 + 2.0 * k);
+      sum += term;
+      if (term < 1e-18 * sum) break;
+    }
+    double f = eT * sum;
+    g[M] = c * f;
+    for (int m = M; m >= 1; --m) {
+      f = (2.0 * T * f + eT) / (2.0 * m - 1.0);
+      g[m - 1] = c * f;
+    }
+  } else {
+    double f = 0.5 * sqrt(PI / T) * erf(sqrt(T));
+    g[0] = c * f;
+    for (int m = 0; m + 1 < NG; ++m) {
+      f = ((2.0 * m + 1.0) * f - eT) / (2.0 * T);
+      g[m + 1] = c * f;
+    }
+  }
+}
+
+// One primitive quartet in the general form (no charge factors): bra pair
+// (ip = 1/p, P, P - A, P - B, codes fa, fb), ket pair likewise.
+__device__ inline double gen_quartet_exact(double ip, const double P[3], const double PA[3],
+                                           const double PB[3], int fa, int fb, double iq,
+                                           const double Q[3], const double QC[3],
+                                           const double QD[3], int fc, int fd) {
+  const double rho = 1.0 / (ip + iq);
+  const double X[3] = {P[0] - Q[0], P[1] - Q[1], P[2] - Q[2]};
+  const double T = rho * (X[0] * X[0] + X[1] * X[1] + X[2] * X[2]);
+  double g[GEN_NG];
+  boys_g_exact_n<GEN_NG>(T, sqrt(rho), g);
+  double G[GEN_NG];
+  double f = 1.0;
+  for (int n = 0; n < GEN_NG; ++n) {
+    G[n] = f * g[n];
+    f *= -2.0 * rho;
+  }
+  double Pd[3][GEN_S + 1];
+  for (int d = 0; d < 3; ++d) {
+    double Eb[GEN_T + 1], Ek[GEN_T + 1];
+    herm_1d(cart_pow(fa, d), cart_pow(fb, d), PA[d], PB[d], 0.5 * ip, Eb);
+    herm_1d(cart_pow(fc, d), cart_pow(fd, d), QC[d], QD[d], 0.5 * iq, Ek);
+    herm_dir(Eb, Ek, X[d], Pd[d]);
+  }
+  return herm_sum(Pd[0], Pd[1], Pd[2], G);
+}
+
+// Contracted integral of two pairs with codes cf | (cg << 4) in the general
+// form (the pair stores carry the P - A, P - B vectors).
+__device__ inline double contracted_eri_gen(const PrimPairsC &A, int64_t a0, int64_t a1, int ca,
+                                            const PrimPairsC &B, int64_t b0, int64_t b1,
+                                            int cb) {
+  const int fa = ca & 15, fb = (ca >> 4) & 15, fc = cb & 15, fd = (cb >> 4) & 15;
+  double acc = 0.0;
+  for (int64_t i = a0; i < a1; ++i) {
+    const double P[3] = {A.x[i], A.y[i], A.z[i]};
+    const bool va = A.ax != nullptr, vb = B.ax != nullptr;
+    const double PA[3] = {va ? A.ax[i] : 0.0, va ? A.ay[i] : 0.0, va ? A.az[i] : 0.0};
+    const double PB[3] = {va ? A.bx[i] : 0.0, va ? A.by[i] : 0.0, va ? A.bz[i] : 0.0};
+    double s = 0.0;
+    for (int64_t k = b0; k < b1; ++k) {
+      const double Q[3] = {B.x[k], B.y[k], B.z[k]};
+      const double QC[3] = {vb ? B.ax[k] : 0.0, vb ? B.ay[k] : 0.0, vb ? B.az[k] : 0.0};
+      const double QD[3] = {vb ? B.bx[k] : 0.0, vb ? B.by[k] : 0.0, vb ? B.bz[k] : 0.0};
+      s += B.e[k] * gen_quartet_exact(A.ip[i], P, PA, PB, fa, fb, B.ip[k], Q, QC, QD, fc, fd);
+    }
     acc += A.e[i] * s;
   }
   return acc;

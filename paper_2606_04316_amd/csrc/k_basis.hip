@@ -9,18 +9,23 @@
 
 namespace qdcb {
 
-// nc[i] = c_i N(a_i) / sqrt(<chi|chi>) multiplies exp(-a_i r^2) (s) or
-// (x - A_x) exp(-a_i r^2) (p_x; likewise p_y, p_z), with the primitive
-// normalization N(a) = (2a/pi)^{3/4} (s) or (2a/pi)^{3/4} 2 sqrt(a) (p).  Two
-// primitives of one p function overlap by (pi/(a+b))^{3/2} / (2(a+b)).
+// nc[i] = c_i N(a_i) / sqrt(<chi|chi>) multiplies exp(-a_i r^2) (s),
+// (x - A_x) exp(-a_i r^2) (p_x; likewise p_y, p_z) or (x - A_x)(y - A_y)
+// exp(-a_i r^2) (d_xy; likewise the other d codes), with the primitive
+// normalization N(a) = (2a/pi)^{3/4} (4a)^{L/2} / sqrt(prod_k (2 l_k - 1)!!)
+// (s: (2a/pi)^{3/4}; p: (2a/pi)^{3/4} 2 sqrt(a)).  Two primitives of one
+// function overlap by (pi/q)^{3/2} prod_k (2 l_k - 1)!! / (2q)^{l_k}, q = a + b.
 __global__ void k_norm_coefs(int nfunc, const int32_t *first, const double *exps,
                              const double *coefs, const int32_t *cart, double *nc) {
   int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= nfunc) return;
-  const bool pf = cart && cart[f] != 0;
+  const int code = cart ? cart[f] : 0;
+  const bool pf = code >= 1 && code <= 3, df = code >= 4;
+  // d: (2 l_x - 1)!! (2 l_y - 1)!! (2 l_z - 1)!! = 3 for d_xx, d_yy, d_zz, 1 otherwise
+  const double dd = code >= 4 && code <= 6 ? 3.0 : 1.0;
   auto nrm = [&](double a) {
     const double n = pow(2.0 * a / PI, 0.75);
-    return pf ? 2.0 * sqrt(a) * n : n;
+    return pf ? 2.0 * sqrt(a) * n : (df ? 4.0 * a * n / sqrt(dd) : n);
   };
   int i0 = first[f], i1 = first[f + 1];
   double s = 0.0;
@@ -31,6 +36,7 @@ __global__ void k_norm_coefs(int nfunc, const int32_t *first, const double *exps
       const double q = exps[i] + exps[j];
       double ov = pow(PI / q, 1.5);
       if (pf) ov /= 2.0 * q;
+      if (df) ov *= dd / (4.0 * q * q);
       s += di * dj * ov;
     }
   }
@@ -56,8 +62,9 @@ __global__ void k_pair_data(int64_t npairs, const int32_t *mu, const int32_t *nu
   double Ax = cA[3 * m], Ay = cA[3 * m + 1], Az = cA[3 * m + 2];
   double Bx = cB[3 * n], By = cB[3 * n + 1], Bz = cB[3 * n + 2];
   double r2 = (Ax - Bx) * (Ax - Bx) + (Ay - By) * (Ay - By) + (Az - Bz) * (Az - Bz);
-  // Cartesian direction of each function (-1: s)
-  const int da = kA ? kA[m] - 1 : -1, db = kB ? kB[n] - 1 : -1;
+  // Cartesian direction of each p function (-1: s or d)
+  const int ca = kA ? kA[m] : 0, cb = kB ? kB[n] : 0;
+  const int da = ca >= 1 && ca <= 3 ? ca - 1 : -1, db = cb >= 1 && cb <= 3 ? cb - 1 : -1;
   const double Ad = da == 0 ? Ax : (da == 1 ? Ay : Az);
   const double Bd = db == 0 ? Bx : (db == 1 ? By : Bz);
   int64_t o = pair_first[i];
@@ -77,6 +84,12 @@ __global__ void k_pair_data(int64_t npairs, const int32_t *mu, const int32_t *nu
       if (out.pa) {
         out.pa[o] = da >= 0 ? (da == 0 ? Px : (da == 1 ? Py : Pz)) - Ad : 0.0;
         out.pb[o] = db >= 0 ? (db == 0 ? Px : (db == 1 ? Py : Pz)) - Bd : 0.0;
+        out.ax[o] = Px - Ax;
+        out.ay[o] = Py - Ay;
+        out.az[o] = Pz - Az;
+        out.bx[o] = Px - Bx;
+        out.by[o] = Py - By;
+        out.bz[o] = Pz - Bz;
       }
       ++o;
     }
@@ -94,7 +107,7 @@ void launch_pair_data(int64_t npairs, const int32_t *mu, const int32_t *nu,
 }
 
 // One wavefront per pair: lanes stride over the (ij, kl) primitive quartets.
-// code: pair codes of a basis with p functions (see common.h), else NULL.
+// code: pair codes of a Cartesian basis (see common.h), else NULL.
 __global__ void __launch_bounds__(256) k_schwarz(int64_t npairs, const int64_t *pair_first,
                                                  PrimPairsC pp, const int32_t *code, double *Q) {
   int lane = threadIdx.x & 63;
@@ -104,9 +117,17 @@ __global__ void __launch_bounds__(256) k_schwarz(int64_t npairs, const int64_t *
   int k = (int)(pair_first[pair + 1] - f0);
   double acc = 0.0;
   const int c = code ? code[pair] : 0;
+  const bool gen = gen_code(c);  // uniform
   for (int t = lane; t < k * k; t += 64) {
     int64_t i = f0 + t / k, j = f0 + t % k;
-    if (c)
+    if (gen) {
+      const double Pi[3] = {pp.x[i], pp.y[i], pp.z[i]}, Pj[3] = {pp.x[j], pp.y[j], pp.z[j]};
+      const double Ai[3] = {pp.ax[i], pp.ay[i], pp.az[i]}, Aj[3] = {pp.ax[j], pp.ay[j], pp.az[j]};
+      const double Bi[3] = {pp.bx[i], pp.by[i], pp.bz[i]}, Bj[3] = {pp.bx[j], pp.by[j], pp.bz[j]};
+      acc += pp.e[i] * pp.e[j] *
+             gen_quartet_exact(pp.ip[i], Pi, Ai, Bi, c & 15, c >> 4, pp.ip[j], Pj, Aj, Bj,
+                               c & 15, c >> 4);
+    } else if (c)
       acc += pp.e[i] * pp.e[j] *
              cart_quartet_exact(pp.ip[i], pp.x[i], pp.y[i], pp.z[i], pp.pa[i], pp.pb[i], c,
                                 pp.ip[j], pp.x[j], pp.y[j], pp.z[j], pp.pa[j], pp.pb[j], c);
@@ -181,8 +202,15 @@ __global__ void k_gather_pairs(int64_t nrows, const int64_t *src_first, const in
     dst.z[d] = src.z[si];
     dst.e[d] = src.e[si];
     if (dst.pa) {  // a store of an s-only basis has no pa / pb (its codes are 0)
-      dst.pa[d] = src.pa ? src.pa[si] : 0.0;
-      dst.pb[d] = src.pb ? src.pb[si] : 0.0;
+      const bool c = src.pa != nullptr;
+      dst.pa[d] = c ? src.pa[si] : 0.0;
+      dst.pb[d] = c ? src.pb[si] : 0.0;
+      dst.ax[d] = c ? src.ax[si] : 0.0;
+      dst.ay[d] = c ? src.ay[si] : 0.0;
+      dst.az[d] = c ? src.az[si] : 0.0;
+      dst.bx[d] = c ? src.bx[si] : 0.0;
+      dst.by[d] = c ? src.by[si] : 0.0;
+      dst.bz[d] = c ? src.bz[si] : 0.0;
     }
     ++d;
   }
@@ -202,7 +230,10 @@ __global__ void k_eri_list(int64_t nq, const int64_t *af, const int64_t *bf, con
                            double *out) {
   int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nq) return;
-  if (codes)
+  if (codes && (gen_code(codes[2 * q]) || gen_code(codes[2 * q + 1])))
+    out[q] = contracted_eri_gen(A, af[q], af[q] + ac[q], codes[2 * q], B, bf[q], bf[q] + bc[q],
+                                codes[2 * q + 1]);
+  else if (codes)
     out[q] = contracted_eri_cart(A, af[q], af[q] + ac[q], codes[2 * q], B, bf[q], bf[q] + bc[q],
                                  codes[2 * q + 1]);
   else

@@ -375,13 +375,14 @@ struct CartDirs {
 // tab[BOYS_LDC i + k] = (2/sqrt(pi)) F_k(T_i) by the Taylor series
 // F_m(T_i + d) = sum_k F_{m+k}(T_i) (-d)^k / k! (k <= 7, nested); far field
 // (T >= 36) from 1/R and the upward recursion.
-template <int NG>
+template <int NG, int LD = BOYS_LDC>
 __device__ __forceinline__ void boys_g_tab_n(const double *tab, double T, double r2, double sr,
                                              double g[NG]) {
+  static_assert(NG + 7 <= LD, "eight Taylor terms per order");
   if (T < BOYS_TMAX) {
     const int i = (int)fma(T, 8.0, 0.5);
     const double nd = fma(0.125, (double)i, -T);
-    const double *c = tab + BOYS_LDC * i;
+    const double *c = tab + LD * i;
 #pragma unroll
     for (int m = 0; m < NG; ++m) g[m] = c[m + 7];
 #pragma unroll
@@ -430,7 +431,7 @@ __device__ __forceinline__ double cart_row_pair(const EriTileArgs &A, const doub
                                                 int64_t kf0, int64_t kf1, int64_t b0, int64_t b1,
                                                 const CartDirs &r, int kcode) {
   constexpr int NG = 3 + KT;  // G_0 .. G_{2 + KT}
-  const int kc = (kcode & 3) - 1;
+  const int kc = (kcode & 15) - 1;
   const cdptr kip = as_const(A.pp.ip), kx = as_const(A.pp.x), ky = as_const(A.pp.y),
               kz = as_const(A.pp.z), ke = as_const(A.pp.e), kpa = as_const(A.pp.pa),
               kpb = as_const(A.pp.pb);
@@ -514,7 +515,7 @@ __device__ __forceinline__ void eri_cart_tile_body(const EriTileArgs &a, const d
   const int bcode = a.code[brow];
   const int64_t bfirst = a.row_first[brow];
   const int64_t blast = a.row_first[brow + 1];
-  const int ba = (bcode & 3) - 1, bb = ((bcode >> 2) & 3) - 1;
+  const int ba = (bcode & 15) - 1, bb = ((bcode >> 4) & 15) - 1;
   for (int i = 0; i < TILE / ERI_WAVES; ++i) {
     const int j = w + ERI_WAVES * i;
     const int64_t krow = (int64_t)kt * TILE + j;
@@ -526,7 +527,7 @@ __device__ __forceinline__ void eri_cart_tile_body(const EriTileArgs &a, const d
     const bool keep_bk = out && (qb * qk) * dk >= a.tau;
     const bool keep_kb = outT && (qk * qb) * db >= a.tau;
     if (keep_bk || keep_kb) {
-      const int kc = (kcode & 3) - 1, kd = ((kcode >> 2) & 3) - 1;
+      const int kc = (kcode & 15) - 1, kd = ((kcode >> 4) & 15) - 1;
       const int kt_p = (kc >= 0) + (kd >= 0);
       CartDirs r;
       r.ha = ba >= 0;
@@ -609,9 +610,138 @@ __global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles_queue_cart(EriTileArg
   eri_count(a, kept);
 }
 
+// ---- general (s, p, d) tiles: bases with d functions
+
+// Contracted value of one (bra row, ket row) pair of a general tile (codes
+// cf | (cg << 4)), in the factorized McMurchie-Davidson form of common.h.  The
+// lane's bra primitive outside (its Hermite coefficients held in registers),
+// the wavefront-uniform ket primitives inside (scalar loads).
+__device__ __forceinline__ double gen_row_pair(const EriTileArgs &A, const double *tab,
+                                               int64_t kf0, int64_t kf1, int64_t b0, int64_t b1,
+                                               int bcode, int kcode) {
+  const int fa = bcode & 15, fb = (bcode >> 4) & 15, fc = kcode & 15, fd = (kcode >> 4) & 15;
+  const cdptr kip = as_const(A.pp.ip), kx = as_const(A.pp.x), ky = as_const(A.pp.y),
+              kz = as_const(A.pp.z), ke = as_const(A.pp.e), kax = as_const(A.pp.ax),
+              kay = as_const(A.pp.ay), kaz = as_const(A.pp.az), kbx = as_const(A.pp.bx),
+              kby = as_const(A.pp.by), kbz = as_const(A.pp.bz);
+  double v = 0.0;
+  for (int64_t b = b0; b < b1; ++b) {
+    const double ip = A.pp.ip[b], px = A.pp.x[b], py = A.pp.y[b], pz = A.pp.z[b];
+    const double hb = 0.5 * ip;
+    double Ebx[GEN_T + 1], Eby[GEN_T + 1], Ebz[GEN_T + 1];
+    herm_1d(cart_pow(fa, 0), cart_pow(fb, 0), A.pp.ax[b], A.pp.bx[b], hb, Ebx);
+    herm_1d(cart_pow(fa, 1), cart_pow(fb, 1), A.pp.ay[b], A.pp.by[b], hb, Eby);
+    herm_1d(cart_pow(fa, 2), cart_pow(fb, 2), A.pp.az[b], A.pp.bz[b], hb, Ebz);
+    double s = 0.0;
+    for (int64_t k = kf0; k < kf1; ++k) {
+      const double iq = kip[k], hk = 0.5 * iq;
+      const double X0 = px - kx[k], X1 = py - ky[k], X2 = pz - kz[k];
+      const double sr = rsqrt_pos(ip + iq);
+      const double rho = sr * sr;
+      const double r2 = X0 * X0 + X1 * X1 + X2 * X2;
+      double G[GEN_NG];
+      boys_g_tab_n<GEN_NG, BOYS_LDG>(tab, r2 * rho, r2, sr, G);
+      const double m2r = -2.0 * rho;
+      double f = m2r;
+#pragma unroll
+      for (int n = 1; n < GEN_NG; ++n) {
+        G[n] *= f;
+        f *= m2r;
+      }
+      double Ek[GEN_T + 1], Px[GEN_S + 1], Py[GEN_S + 1], Pz[GEN_S + 1];
+      herm_1d(cart_pow(fc, 0), cart_pow(fd, 0), kax[k], kbx[k], hk, Ek);
+      herm_dir(Ebx, Ek, X0, Px);
+      herm_1d(cart_pow(fc, 1), cart_pow(fd, 1), kay[k], kby[k], hk, Ek);
+      herm_dir(Eby, Ek, X1, Py);
+      herm_1d(cart_pow(fc, 2), cart_pow(fd, 2), kaz[k], kbz[k], hk, Ek);
+      herm_dir(Ebz, Ek, X2, Pz);
+      s = fma(ke[k], herm_sum(Px, Py, Pz, G), s);
+    }
+    v = fma(A.pp.e[b], s, v);
+  }
+  return v;
+}
+
+__device__ __forceinline__ void eri_gen_one_tile(const EriTileArgs &a, const double *tab,
+                                                 int64_t slot, long long kept[4]) {
+  const int kt = a.tasks[slot];
+  const int bt = a.task_bra[slot];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double *out, *outT = nullptr;
+  if (a.uslot_bk) {
+    const int32_t s1 = a.uslot_bk[slot], s2 = a.uslot_kb[slot];
+    out = s1 >= 0 ? a.panel + (int64_t)s1 * TILE * TILE : nullptr;
+    outT = s2 >= 0 ? a.panel + (int64_t)s2 * TILE * TILE : nullptr;
+  } else {
+    out = a.panel + (slot - a.slot0) * TILE * TILE;
+  }
+  const int64_t brow = (int64_t)bt * TILE + lane;
+  const double qb = a.Q[brow];
+  const double db = a.Dmax[brow];
+  const int cb = a.cls[brow];
+  const int bcode = a.code[brow];
+  const int64_t bfirst = a.row_first[brow], blast = a.row_first[brow + 1];
+  for (int i = 0; i < TILE / ERI_WAVES; ++i) {
+    const int j = w + ERI_WAVES * i;
+    const int64_t krow = (int64_t)kt * TILE + j;
+    const double qk = a.Q[krow], dk = a.Dmax[krow];
+    const int ck = a.cls[krow];
+    const int kcode = __builtin_amdgcn_readfirstlane(a.code[krow]);
+    const int64_t kf0 = a.row_first[krow], kf1 = a.row_first[krow + 1];
+    double v = 0.0;
+    const bool keep_bk = out && (qb * qk) * dk >= a.tau;
+    const bool keep_kb = outT && (qk * qb) * db >= a.tau;
+    if (keep_bk || keep_kb) {
+      v = gen_row_pair(a, tab, kf0, kf1, bfirst, blast, bcode, kcode);
+      if (cb >= 0 && ck >= 0) {
+        if (keep_bk) kept[cb * 2 + ck] += 1;
+        if (keep_kb) kept[ck * 2 + cb] += 1;
+      }
+    }
+    if (out) out[j * TILE + lane] = keep_bk ? v : 0.0;
+    if (outT) outT[lane * TILE + j] = keep_kb ? v : 0.0;
+  }
+}
+
+__global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles_gen(EriTileArgs a) {
+  __shared__ double tab[BOYS_N * BOYS_LDG];
+  if (a.overflow && *a.overflow) return;  // uniform
+  if (a.d_total && (int64_t)blockIdx.x >= min(*a.d_total, a.cap)) return;  // uniform
+  for (int t = threadIdx.x; t < BOYS_N * BOYS_LDG; t += ERI_THREADS) tab[t] = a.boysg[t];
+  __syncthreads();
+  long long kept[4] = {0, 0, 0, 0};
+  eri_gen_one_tile(a, tab, a.slot0 + blockIdx.x, kept);
+  eri_count(a, kept);
+}
+
+// Persistent variant; same queue protocol as k_eri_tiles_queue.
+__global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles_queue_gen(EriTileArgs a,
+                                                                     const int32_t *order,
+                                                                     unsigned long long *qctr,
+                                                                     int64_t n_host) {
+  __shared__ double tab[BOYS_N * BOYS_LDG];
+  __shared__ int64_t s_next;
+  if (a.overflow && *a.overflow) return;  // uniform
+  const int64_t n = a.d_total ? min(*a.d_total, a.cap) : n_host;
+  for (int t = threadIdx.x; t < BOYS_N * BOYS_LDG; t += ERI_THREADS) tab[t] = a.boysg[t];
+  long long kept[4] = {0, 0, 0, 0};
+  for (;;) {
+    __syncthreads();  // table staged; the previous s_next read by every thread
+    if (threadIdx.x == 0) s_next = (int64_t)atomicAdd(qctr, 1ull);
+    __syncthreads();
+    const int64_t i = s_next;
+    if (i >= n) break;  // uniform
+    eri_gen_one_tile(a, tab, order[i], kept);
+  }
+  eri_count(a, kept);
+}
+
 void launch_eri_tiles(const EriTileArgs &a, int64_t nslots, hipStream_t s) {
   if (nslots <= 0) return;
-  if (a.code)
+  if (a.boysg)
+    hipLaunchKernelGGL(k_eri_tiles_gen, dim3((unsigned)nslots), dim3(ERI_THREADS), 0, s, a);
+  else if (a.code)
     hipLaunchKernelGGL(k_eri_tiles_cart, dim3((unsigned)nslots), dim3(ERI_THREADS), 0, s, a);
   else
     hipLaunchKernelGGL(k_eri_tiles<false>, dim3((unsigned)nslots), dim3(ERI_THREADS), 0, s, a);
@@ -620,7 +750,10 @@ void launch_eri_tiles(const EriTileArgs &a, int64_t nslots, hipStream_t s) {
 void launch_eri_tiles_queue(const EriTileArgs &a, const int32_t *order, unsigned long long *qctr,
                             int64_t n_host, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return;
-  if (a.code)
+  if (a.boysg)
+    hipLaunchKernelGGL(k_eri_tiles_queue_gen, dim3((unsigned)nblocks), dim3(ERI_THREADS), 0, s,
+                       a, order, qctr, n_host);
+  else if (a.code)
     hipLaunchKernelGGL(k_eri_tiles_queue_cart, dim3((unsigned)nblocks), dim3(ERI_THREADS), 0, s,
                        a, order, qctr, n_host);
   else

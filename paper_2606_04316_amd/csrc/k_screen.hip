@@ -498,6 +498,12 @@ __global__ void __launch_bounds__(TILE) k_gather_rows(int ntiles, const int32_t 
     if (pp.pa) {
       wpp.pa[to] = pp.pa[from];
       wpp.pb[to] = pp.pb[from];
+      wpp.ax[to] = pp.ax[from];
+      wpp.ay[to] = pp.ay[from];
+      wpp.az[to] = pp.az[from];
+      wpp.bx[to] = pp.bx[from];
+      wpp.by[to] = pp.by[from];
+      wpp.bz[to] = pp.bz[from];
     }
   }
 }

@@ -20,7 +20,7 @@ void launch_pair_data(int64_t npairs, const int32_t *mu, const int32_t *nu,
                       const double *centB, const int32_t *firstB, const double *expB,
                       const double *ncB, const int32_t *cartB, PrimPairs out, hipStream_t s);
 // Q[i] = sqrt((i|i)) over the primitive pairs [pair_first[i], pair_first[i+1]).
-// code: per pair cf | (cg << 2) for bases with p functions, else NULL.
+// code: per pair cf | (cg << 4) for Cartesian bases, else NULL.
 void launch_schwarz(int64_t npairs, const int64_t *pair_first, PrimPairsC pp,
                     const int32_t *code, double *Q, hipStream_t s);
 // Primitive-pair screening: kept[r] = number of the cnt[r] primitive pairs of
@@ -164,6 +164,9 @@ struct EriTileArgs {
   // integral launches then run the Cartesian tile kernels
   const int32_t *code = nullptr;
   const double *boysc = nullptr;
+  // bases with d functions: the general tiles (codes as above) with the table
+  // [BOYS_N][BOYS_LDG] of (2/sqrt(pi)) F_k(T_i), k < BOYS_LDG
+  const double *boysg = nullptr;
   const int32_t *tasks;       // [slots] ket tile per slot
   const int32_t *task_bra;    // [slots] bra tile per slot
   int64_t slot0;              // slot index of the panel buffer's first entry

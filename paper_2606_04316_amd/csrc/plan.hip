@@ -27,7 +27,7 @@ struct RowSrc {
   int32_t cnt;
   int which;        // which source store
   int32_t kept = 0;  // primitive pairs kept by primitive screening
-  int32_t code = 0;  // pair code cf | (cg << 2) of bases with p functions (0: s s)
+  int32_t code = 0;  // pair code cf | (cg << 4) of Cartesian bases (0: s s)
 };
 
 // Rows ordered by Schwarz factor; band_rows > 0: within each band of that many
@@ -225,12 +225,14 @@ std::vector<double> boys_table3() {
   return tab;
 }
 
-// Table of the Cartesian (s/p) tiles: tab[BOYS_LDC i + k] = (2/sqrt(pi)) F_k(T_i),
-// k = 0 .. 11, T_i = i / 8, by the same series and downward recursion (long double).
+// Table of the Cartesian tiles: tab[LD i + k] = (2/sqrt(pi)) F_k(T_i), k < LD
+// (BOYS_LDC for s/p tiles, BOYS_LDG for the general tiles), T_i = i / 8, by the
+// same series and downward recursion (long double).
+template <int LD = BOYS_LDC>
 std::vector<double> boys_table_cart() {
-  std::vector<double> tab((size_t)BOYS_N * BOYS_LDC);
+  std::vector<double> tab((size_t)BOYS_N * LD);
   const long double two_over_sqrtpi = 2.0L / sqrtl(3.14159265358979323846264338327950288L);
-  constexpr int M = BOYS_LDC - 1;
+  constexpr int M = LD - 1;
   for (int i = 0; i < BOYS_N; ++i) {
     const long double T = (long double)i / 8.0L, eT = expl(-T);
     long double term = 1.0L / (2.0L * M + 1.0L), sum = term;
@@ -239,11 +241,10 @@ std::vector<double> boys_table_cart() {
       sum += term;
       if (term < 1e-22L * sum) break;
     }
-    long double F[BOYS_LDC];
+    long double F[LD];
     F[M] = eT * sum;
     for (int m = M; m >= 1; --m) F[m - 1] = (2.0L * T * F[m] + eT) / (2.0L * m - 1.0L);
-    for (int k = 0; k < BOYS_LDC; ++k)
-      tab[(size_t)BOYS_LDC * i + k] = (double)(two_over_sqrtpi * F[k]);
+    for (int k = 0; k < LD; ++k) tab[(size_t)LD * i + k] = (double)(two_over_sqrtpi * F[k]);
   }
   return tab;
 }
@@ -433,6 +434,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
     p.gauge = desc->ham == QDCB_HAM_DCB;
     p.fused_breit = p.gauge && desc->prec == QDCB_PREC_FP64;
     p.cart = L->has_p() || (S && S->has_p());
+    p.gen = L->has_d() || (S && S->has_d());
     {
       const char *e = std::getenv("QDCB_TILE_ORDER");
       p.tile_order = !(e && e[0] == '0');
@@ -460,7 +462,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
             int64_t c = qdcb_basis::canon(mu, nu);
             RowSrc r{B->Q[c], cls, mu, nu, c, B->pair_first[c],
                      (int32_t)(B->pair_first[c + 1] - B->pair_first[c]), which};
-            r.code = B->cart_of(mu) | (B->cart_of(nu) << 2);
+            r.code = B->cart_of(mu) | (B->cart_of(nu) << 4);
             rows.push_back(r);
           }
       };
@@ -500,7 +502,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
                        ls.view(), nullptr);
       std::vector<int32_t> lcode(p.cart ? nls : 0);
       for (int64_t i = 0; p.cart && i < nls; ++i)
-        lcode[i] = L->cart_of(pm[i]) | (S->cart_of(pn[i]) << 2);
+        lcode[i] = L->cart_of(pm[i]) | (S->cart_of(pn[i]) << 4);
       DBuf<int32_t> dlcode(POOLED);
       if (p.cart) dlcode.upload(ctx, lcode);
       dQ.alloc(ctx, nls);
@@ -610,6 +612,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
     p.boys.upload(ctx, boys_table());
     if (p.gauge) p.boys3.upload(ctx, boys_table3());
     if (p.cart) p.boysc.upload(ctx, boys_table_cart());
+    if (p.gen) p.boysg.upload(ctx, boys_table_cart<BOYS_LDG>());
     trace.mark("tables");
     HIPC(hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking));
     trace.mark("stream");
@@ -685,7 +688,7 @@ qdcb_status qdcb_plan_footprint(const qdcb_plan *p, size_t *bytes) {
     if (!p || !bytes) fail(QDCB_E_INVALID, "NULL argument");
     size_t b = p->C.bytes() + p->G.bytes();
     for (auto *x : {&p->CLd, &p->CSd, &p->Gd, &p->CallL, &p->CallS, &p->ChatL, &p->ChatS, &p->boys,
-                    &p->boys3, &p->boysc, &p->W, &p->Gc})
+                    &p->boys3, &p->boysc, &p->boysg, &p->W, &p->Gc})
       b += x->bytes();
     for (int K = 0; K < 3; ++K) b += p->AhatK[K].bytes() + p->BhatK[K].bytes();
     b += p->rs.bytes() + p->rowmapL.bytes() + p->rowmapS.bytes() + p->rowmapLS.bytes();

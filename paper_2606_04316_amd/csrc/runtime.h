@@ -178,36 +178,44 @@ struct DBuf {
 
 struct PairStore {
   DBuf<double> p, x, y, z, e;
-  DBuf<double> pa, pb;  // bases with p functions only (see PrimPairs)
+  DBuf<double> pa, pb;                  // Cartesian bases only (see PrimPairs)
+  DBuf<double> ax, ay, az, bx, by, bz;  // likewise
   PairStore() = default;
   explicit PairStore(Pooled)
-      : p(POOLED), x(POOLED), y(POOLED), z(POOLED), e(POOLED), pa(POOLED), pb(POOLED) {}
+      : p(POOLED), x(POOLED), y(POOLED), z(POOLED), e(POOLED), pa(POOLED), pb(POOLED),
+        ax(POOLED), ay(POOLED), az(POOLED), bx(POOLED), by(POOLED), bz(POOLED) {}
+  // cart: pa / pb and the P - A, P - B vectors (bases with p or d functions)
   void alloc(qdcb_ctx *c, size_t n, bool cart = false) {
     p.alloc(c, n);
     x.alloc(c, n);
     y.alloc(c, n);
     z.alloc(c, n);
     e.alloc(c, n);
-    if (cart) {
-      pa.alloc(c, n);
-      pb.alloc(c, n);
-    } else {
-      pa.free();
-      pb.free();
+    for (DBuf<double> *b : {&pa, &pb, &ax, &ay, &az, &bx, &by, &bz}) {
+      if (cart)
+        b->alloc(c, n);
+      else
+        b->free();
     }
   }
-  PrimPairs view() { return PrimPairs{p.p, x.p, y.p, z.p, e.p, pa.p, pb.p}; }
-  PrimPairsC cview() const { return PrimPairsC(PrimPairs{p.p, x.p, y.p, z.p, e.p, pa.p, pb.p}); }
-  void free() {
-    p.free();
-    x.free();
-    y.free();
-    z.free();
-    e.free();
-    pa.free();
-    pb.free();
+  PrimPairs view() {
+    PrimPairs v{p.p, x.p, y.p, z.p, e.p, pa.p, pb.p};
+    v.ax = ax.p;
+    v.ay = ay.p;
+    v.az = az.p;
+    v.bx = bx.p;
+    v.by = by.p;
+    v.bz = bz.p;
+    return v;
   }
-  size_t bytes() const { return p.bytes() * 5 + pa.bytes() + pb.bytes(); }
+  PrimPairsC cview() const { return PrimPairsC(const_cast<PairStore *>(this)->view()); }
+  void free() {
+    for (DBuf<double> *b : {&p, &x, &y, &z, &e, &pa, &pb, &ax, &ay, &az, &bx, &by, &bz}) b->free();
+  }
+  size_t bytes() const {
+    return p.bytes() * 5 + pa.bytes() + pb.bytes() +
+           (ax.bytes() + ay.bytes() + az.bytes() + bx.bytes() + by.bytes() + bz.bytes());
+  }
 };
 
 }  // namespace qdcb
@@ -219,9 +227,16 @@ struct qdcb_basis {
   std::vector<int32_t> nprim;       // [nfunc]
   std::vector<int64_t> pair_first;  // canonical pairs (mu <= nu, nu-major) [npairs+1]
   std::vector<double> Q;            // host copy of the Schwarz factors
-  std::vector<int32_t> cart;        // [nfunc] 0 = s, 1..3 = p_x, p_y, p_z (empty: all s)
+  // [nfunc] 0 = s, 1..3 = p_x, p_y, p_z, 4..9 = d_xx, d_yy, d_zz, d_xy, d_xz,
+  // d_yz (empty: all s)
+  std::vector<int32_t> cart;
   int64_t npairs = 0;
-  bool has_p() const { return !cart.empty(); }
+  bool has_p() const { return !cart.empty(); }  // any Cartesian function (p or d)
+  bool has_d() const {
+    for (int32_t c : cart)
+      if (c >= 4) return true;
+    return false;
+  }
   int32_t cart_of(int f) const { return cart.empty() ? 0 : cart[f]; }
   qdcb::DBuf<double> cent, exps, coefs, nc;
   qdcb::DBuf<int32_t> dfirst, dcart;

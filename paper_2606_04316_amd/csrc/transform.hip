@@ -249,6 +249,8 @@ EriTileArgs eri_args(qdcb_plan &p, Space &sp, int64_t slot0, bool count, bool ga
   ea.boys3 = gauge ? p.boys3.p : nullptr;
   ea.code = p.cart ? (w ? sp.wcode.p : sp.code.p) : nullptr;
   ea.boysc = p.cart ? p.boysc.p : nullptr;
+  ea.boysg = p.gen ? p.boysg.p : nullptr;
+  if (p.gen && !ea.boysg) fail(QDCB_E_DEVICE, "general tiles without their table");
   if (p.cart && (!ea.code || !ea.boysc || !sp.pp.pa.p || gauge))
     fail(QDCB_E_DEVICE, "Cartesian tiles without their codes, table or pair data");
   ea.gauge_diag = breit ? 0.5 : -0.5;

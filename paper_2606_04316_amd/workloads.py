@@ -337,10 +337,12 @@ def cluster(seed: int = 3, n_atoms: int = 60, radius: float = 20.0, min_sep: flo
 
 def make_sp_basis(rng: np.random.Generator, atoms: np.ndarray, s_per_atom: int,
                   p_shells_per_atom: int, nprim, exp_lo: float, exp_hi: float,
-                  exp_scale: float = 1.0) -> Basis:
-    """Per atom ``s_per_atom`` s functions and ``p_shells_per_atom`` p shells
-    (p_x, p_y, p_z with one shared set of exponents and coefficients), drawn
-    as in make_basis; functions are listed atom by atom."""
+                  exp_scale: float = 1.0, d_shells_per_atom: int = 0) -> Basis:
+    """Per atom ``s_per_atom`` s functions, ``p_shells_per_atom`` p shells
+    (p_x, p_y, p_z with one shared set of exponents and coefficients) and
+    ``d_shells_per_atom`` Cartesian d shells (codes 4..9: d_xx, d_yy, d_zz,
+    d_xy, d_xz, d_yz, shared exponents and coefficients), drawn as in
+    make_basis; functions are listed atom by atom."""
     centers, nprim_l, exps, coefs, cart = [], [], [], [], []
 
     def draw():
@@ -358,6 +360,13 @@ def make_sp_basis(rng: np.random.Generator, atoms: np.ndarray, s_per_atom: int,
             e = exp_scale * 10.0 ** rng.uniform(math.log10(exp_lo), math.log10(exp_hi), size=k)
             c = rng.uniform(0.1, 1.0, size=k)
             for comp in (1, 2, 3):
+                centers.append(a); nprim_l.append(k); exps.append(e); coefs.append(c)
+                cart.append(comp)
+        for _ in range(d_shells_per_atom):
+            k = draw()
+            e = exp_scale * 10.0 ** rng.uniform(math.log10(exp_lo), math.log10(exp_hi), size=k)
+            c = rng.uniform(0.1, 1.0, size=k)
+            for comp in range(4, 10):
                 centers.append(a); nprim_l.append(k); exps.append(e); coefs.append(c)
                 cart.append(comp)
     return Basis(np.ascontiguousarray(np.array(centers, dtype=np.float64)),
@@ -389,18 +398,39 @@ def sp_cluster(seed: int = 5, n_atoms: int = 8, edge: float = 6.0, s_per_atom: i
     return System(f"sp{n_atoms}_{ham}_{n}", ham, L, S, CL, CS, tau, atoms)
 
 
+def spd_cluster(seed: int = 7, n_atoms: int = 4, edge: float = 4.0, nprim=(1, 2), n: int = 4,
+                tau: float = 0.0, ham: str = "DC", d_l: int = 1, d_s: int = 0) -> System:
+    """Atoms uniform in a cube with one s function, one p shell and ``d_l``
+    Cartesian d shells per atom in L (10 functions per atom by default) and
+    one s function, one p shell and ``d_s`` d shells in S (exponents x4).  MO
+    coefficients as in sp_cluster (quaternion QR, |C| <= 1)."""
+    ra, rb, rc, _ = _streams(seed)
+    atoms = cube(ra, n_atoms, edge)
+    L = make_sp_basis(rb, atoms, 1, 1, nprim, 0.1, 10.0, d_shells_per_atom=d_l)
+    S = None
+    if ham != "LL":
+        S = make_sp_basis(rb, atoms, 1, 1, nprim, 0.1, 10.0, exp_scale=4.0,
+                          d_shells_per_atom=d_s)
+    NL, NS = L.nfunc, (S.nfunc if S is not None else 0)
+    Q = quat_qr_plus(gaussian_quat(rc, NL + NS, n))
+    CL = np.ascontiguousarray(Q[:, :NL])
+    CS = np.ascontiguousarray(Q[:, NL:]) if S is not None else None
+    return System(f"spd{n_atoms}_{ham}_{n}", ham, L, S, CL, CS, tau, atoms)
+
+
 def sp_chain(seed: int = 6, n_atoms: int = 40, spacing: float = 2.5, l_s: int = 4,
              l_p: int = 2, s_s: int = 8, s_p: int = 4, nprim=3, n: int = 64,
-             tau: float = 1e-10, ham: str = "DC") -> System:
-    """The linear-chain recipe with p shells: per atom l_s s functions and l_p
-    p shells in L (10 functions by default, N_L = 400 for 40 atoms) and
-    s_s + 3 s_p in S (20, exponents x4).  MO coefficients as in sp_cluster."""
+             tau: float = 1e-10, ham: str = "DC", l_d: int = 0) -> System:
+    """The linear-chain recipe with p shells: per atom l_s s functions, l_p
+    p shells and l_d Cartesian d shells in L (10 functions by default, N_L =
+    400 for 40 atoms) and s_s + 3 s_p in S (20, exponents x4).  MO
+    coefficients as in sp_cluster."""
     ra, rb, rc, _ = _streams(seed)
     atoms = chain(n_atoms, spacing)
-    L = make_sp_basis(rb, atoms, l_s, l_p, nprim, 0.1, 10.0)
+    L = make_sp_basis(rb, atoms, l_s, l_p, nprim, 0.1, 10.0, d_shells_per_atom=l_d)
     S = make_sp_basis(rb, atoms, s_s, s_p, nprim, 0.1, 10.0, exp_scale=4.0)
     Q = quat_qr_plus(gaussian_quat(rc, L.nfunc + S.nfunc, n))
-    return System(f"chain{n_atoms}_sp_{ham}_{n}", ham, L, S,
+    return System(f"chain{n_atoms}_sp{'d' if l_d else ''}_{ham}_{n}", ham, L, S,
                   np.ascontiguousarray(Q[:, :L.nfunc]), np.ascontiguousarray(Q[:, L.nfunc:]),
                   tau, atoms)
 
@@ -436,6 +466,9 @@ def config(name: str) -> System:
     ``chain40_sp`` the chain40 shape with p shells: per atom 4 s + 2 p shells in
                L (N_L = 400) and 8 s + 4 p shells in S (N_S = 800), K = 3, n = 64,
                DC, tau 1e-10.
+    ``chain40_spd`` the chain40 shape with p and d shells: per atom 4 s + 1 p +
+               1 Cartesian d shell in L (N_L = 520) and 8 s + 4 p shells in S
+               (N_S = 800), K = 3, n = 64, DC, tau 1e-10.
     ``sp8``    8 atoms in a 6 bohr cube with one s function and one p shell per
                atom in L and in S (N_L = N_S = 32), K in 1..3, n = 8, DC.
     """
@@ -455,6 +488,8 @@ def config(name: str) -> System:
         return sp_cluster(seed=5)
     if name == "chain40_sp":
         return sp_chain(seed=6)
+    if name == "chain40_spd":
+        return sp_chain(seed=6, l_p=1, l_d=1)
     if name == "cluster24":
         # the cluster recipe at 24 atoms (radius scaled by (24/60)^(1/3)), n = 64
         return cluster(seed=3, n_atoms=24, radius=20.0 * (24 / 60) ** (1 / 3), n=64)
