@@ -88,7 +88,7 @@ static int cart_of(const orc_basis *b, int f) { return b->cart ? b->cart[f] : 0;
 static int carts_valid(const orc_basis *b)
 {
     for (int f = 0; b && b->cart && f < b->nfunc; ++f)
-        if (b->cart[f] < 0 || b->cart[f] > 9) return 0;
+        if (b->cart[f] < 0 || b->cart[f] > 19) return 0;
     return 1;
 }
 
@@ -100,16 +100,19 @@ static int has_p(const orc_basis *b)
 }
 
 /* Cartesian exponents of a function code: 0 = s; 1, 2, 3 = p_x, p_y, p_z;
- * 4 .. 9 = d_xx, d_yy, d_zz, d_xy, d_xz, d_yz. */
+ * 4 .. 9 = d_xx, d_yy, d_zz, d_xy, d_xz, d_yz; 10 .. 19 = f_xxx, f_yyy, f_zzz,
+ * f_xxy, f_xxz, f_xyy, f_yyz, f_xzz, f_yzz, f_xyz. */
 static void cart_powers(int code, int l[3])
 {
-    static const int tab[10][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {2, 0, 0},
-                                   {0, 2, 0}, {0, 0, 2}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
+    static const int tab[20][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {2, 0, 0},
+                                   {0, 2, 0}, {0, 0, 2}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1},
+                                   {3, 0, 0}, {0, 3, 0}, {0, 0, 3}, {2, 1, 0}, {2, 0, 1},
+                                   {1, 2, 0}, {0, 2, 1}, {1, 0, 2}, {0, 1, 2}, {1, 1, 1}};
     for (int k = 0; k < 3; ++k) l[k] = tab[code][k];
 }
 
-/* (2l - 1)!! for l = 0, 1, 2 */
-static double dfact(int l) { return l == 2 ? 3.0 : 1.0; }
+/* (2l - 1)!! for l = 0 .. 3 */
+static double dfact(int l) { return l == 3 ? 15.0 : (l == 2 ? 3.0 : 1.0); }
 
 /* Normalized primitive (x-A_x)^lx (y-A_y)^ly (z-A_z)^lz exp(-a r^2) with
  * N = (2a/pi)^{3/4} (4a)^{L/2} / sqrt((2lx-1)!! (2ly-1)!! (2lz-1)!!),
@@ -165,7 +168,7 @@ void orc_norm_coefs(const orc_basis *b, double *out)
 typedef struct {
     double p, q, rho;
     double PA[3], QC[3], WP[3], WQ[3], AB[3], CD[3];
-    double aux[9]; /* [00|00]^(m), m = 0..8 */
+    double aux[13]; /* [00|00]^(m), m = 0..12 (four f functions) */
 } os_data;
 
 static double os_vrr(const os_data *o, const int a[3], const int c[3], int m)
@@ -252,7 +255,7 @@ double orc_prim_eri_cart(double a, const double *A, int ca, double b, const doub
     double pre = 2.0 * pow(M_PI, 2.5) / (p * q * sqrt(p + q)) * exp(-a * b / p * rab2) *
                  exp(-c * d / q * rcd2);
     double T = o.rho * rpq2;
-    for (int m = 0; m < 9; ++m) o.aux[m] = pre * orc_boys(m, T);
+    for (int m = 0; m < 13; ++m) o.aux[m] = pre * orc_boys(m, T);
     int la[3], lb[3], lc[3], ld[3];
     cart_powers(ca, la);
     cart_powers(cb, lb);

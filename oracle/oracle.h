@@ -43,7 +43,9 @@ typedef struct {
     const double *exps;    /* [sum nprim] */
     const double *coefs;   /* [sum nprim] */
     const int32_t *cart;   /* [nfunc] 0 = s, 1, 2, 3 = p_x, p_y, p_z, 4 .. 9 = d_xx,
-                              d_yy, d_zz, d_xy, d_xz, d_yz; NULL = all s */
+                              d_yy, d_zz, d_xy, d_xz, d_yz, 10 .. 19 = f_xxx, f_yyy,
+                              f_zzz, f_xxy, f_xxz, f_xyy, f_yyz, f_xzz, f_yzz, f_xyz;
+                              NULL = all s */
 } orc_basis;
 
 typedef struct {

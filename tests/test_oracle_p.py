@@ -237,12 +237,18 @@ def test_d_normalization_by_quadrature():
         assert tot == pytest.approx(1.0, rel=1e-13)
 
 
+# Cartesian powers of the codes (the library's and the oracle's table)
+POWERS = {0: (0, 0, 0), 1: (1, 0, 0), 2: (0, 1, 0), 3: (0, 0, 1), 4: (2, 0, 0), 5: (0, 2, 0),
+          6: (0, 0, 2), 7: (1, 1, 0), 8: (1, 0, 1), 9: (0, 1, 1), 10: (3, 0, 0),
+          11: (0, 3, 0), 12: (0, 0, 3), 13: (2, 1, 0), 14: (2, 0, 1), 15: (1, 2, 0),
+          16: (0, 2, 1), 17: (1, 0, 2), 18: (0, 1, 2), 19: (1, 1, 1)}
+
+
 def _rotated_spd(L, C):
     """Quarter turn about z: the image of x^lx y^ly z^lz on A is
     (-1)^ly x^ly y^lx z^lz on RA."""
     R = np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
-    pw = {0: (0, 0, 0), 1: (1, 0, 0), 2: (0, 1, 0), 3: (0, 0, 1), 4: (2, 0, 0), 5: (0, 2, 0),
-          6: (0, 0, 2), 7: (1, 1, 0), 8: (1, 0, 1), 9: (0, 1, 1)}
+    pw = POWERS
     code_of = {v: k for k, v in pw.items()}
     new = np.array([code_of[(pw[c][1], pw[c][0], pw[c][2])] for c in L.cart], np.int32)
     sign = np.array([(-1.0) ** pw[c][1] for c in L.cart])
@@ -283,8 +289,112 @@ def test_spd_transform_invariant_under_rotation(ham):
     assert np.abs(bad - G).max() > 1e-3 * scale
 
 
+# --------------------------------------------------------------------------
+# f functions (codes 10..19 = f_xxx, f_yyy, f_zzz, f_xxy, f_xxz, f_xyy, f_yyz,
+# f_xzz, f_yzz, f_xyz)
+# --------------------------------------------------------------------------
+
+def _raise_source(code):
+    """An f code as a raised d code: (d code, direction k, d power l_k) with
+    (r-A)_k^{l+1} M e = (1/2a) (d/dA_k [(r-A)_k^l M e] + l (r-A)_k^{l-1} M e)."""
+    lf = POWERS[code]
+    for k in range(3):
+        if lf[k] > 0:
+            ld = list(lf)
+            ld[k] -= 1
+            dcode = [c for c, p in POWERS.items() if p == tuple(ld)][0]
+            if 4 <= dcode <= 9:
+                return dcode, k, ld[k]
+    raise AssertionError(code)
+
+
+@pytest.mark.parametrize("geom", ["generic", "shared_centres"])
+def test_f_integrals_are_centre_derivatives_of_d(geom):
+    rng = np.random.default_rng({"generic": 31, "shared_centres": 32}[geom])
+    h = 1e-4
+    worst = 0.0
+    for trial in range(200):
+        ex = list(rng.uniform(0.3, 2.5, 4))
+        if geom == "generic":
+            cen = [rng.uniform(-1.2, 1.2, 3) for _ in range(4)]
+        else:
+            A, C = rng.uniform(-1.2, 1.2, 3), rng.uniform(-1.2, 1.2, 3)
+            cen = [A, A.copy(), C, C.copy()]
+        cs = [int(x) for x in rng.integers(0, 20, 4)]
+        slot = int(rng.integers(0, 4))
+        if cs[slot] < 10:
+            cs[slot] = int(rng.integers(10, 20))
+        dcode, k, l = _raise_source(cs[slot])
+        lower = list(cs)
+        lower[slot] = dcode
+
+        def shifted(d):
+            c2 = [x.copy() for x in cen]
+            c2[slot][k] += d
+            return _pe(ex, c2, lower)
+
+        fd = (shifted(h) - shifted(-h)) / (2 * h)
+        if l > 0:  # the power-lowered term l (r-A)_k^{l-1} M e (a p function)
+            lp = list(POWERS[dcode])
+            lp[k] -= 1
+            pcode = [c for c, p in POWERS.items() if p == tuple(lp)][0]
+            p_codes = list(cs)
+            p_codes[slot] = pcode
+            fd += l * _pe(ex, cen, p_codes)
+        fd /= 2 * ex[slot]
+        an = _pe(ex, cen, cs)
+        scale = max(abs(_pe(ex, cen, [0, 0, 0, 0])), abs(an))
+        worst = max(worst, abs(fd - an) / scale)
+    assert worst < 1e-6, worst
+
+
+def test_f_normalization_by_quadrature():
+    t, w = np.polynomial.hermite.hermgauss(20)
+    rng = np.random.default_rng(33)
+    k = 3
+    exps = np.tile(10.0 ** rng.uniform(-1, 1, k), 10)
+    coefs = np.tile(rng.uniform(0.1, 1.0, k), 10)
+    b = wl.Basis(np.zeros((10, 3)), np.full(10, k, np.int32), exps, coefs,
+                 np.arange(10, 20, dtype=np.int32))
+    nc = oracle.norm_coefs(b)
+    off = b.offsets()
+    for f in range(10):
+        e, c = b.exps[off[f]:off[f + 1]], nc[off[f]:off[f + 1]]
+        tot = 0.0
+        for i in range(k):
+            for j in range(k):
+                s = e[i] + e[j]
+                tot += c[i] * c[j] * np.prod([(w * t ** (2 * l)).sum() / s ** (l + 0.5)
+                                              for l in POWERS[10 + f]])
+        assert tot == pytest.approx(1.0, rel=1e-13)
+
+
+def test_f_integrals_invariant_under_rotation():
+    # quarter turn about z: the image of x^lx y^ly z^lz on A is
+    # (-1)^ly x^ly y^lx z^lz on RA, so every primitive integral over the
+    # images equals the product of the four signs times the original
+    R = np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    code_of = {v: k for k, v in POWERS.items()}
+    rng = np.random.default_rng(34)
+    worst, flips = 0.0, 0
+    for trial in range(300):
+        ex = list(rng.uniform(0.3, 2.5, 4))
+        cen = [rng.uniform(-1.2, 1.2, 3) for _ in range(4)]
+        cs = [int(x) for x in rng.integers(0, 20, 4)]
+        cs[int(rng.integers(0, 4))] = int(rng.integers(10, 20))
+        img = [code_of[(POWERS[c][1], POWERS[c][0], POWERS[c][2])] for c in cs]
+        sign = np.prod([(-1.0) ** POWERS[c][1] for c in cs])
+        a = _pe(ex, cen, cs)
+        b = _pe(ex, [R @ c for c in cen], img)
+        scale = max(abs(_pe(ex, cen, [0, 0, 0, 0])), abs(a))
+        worst = max(worst, abs(b - sign * a) / scale)
+        flips += sign < 0 and abs(a) > 1e-6 * scale
+    assert worst < 1e-13, worst
+    assert flips > 20  # the signs matter
+
+
 def test_invalid_cart_codes_are_refused():
     b = wl.Basis(np.zeros((1, 3)), np.ones(1, np.int32), np.ones(1), np.ones(1),
-                 np.array([10], np.int32))
+                 np.array([20], np.int32))
     with pytest.raises(ValueError):
         oracle.transform_direct(b, None, np.ones((4, 1, 1)), None, ham="LL")
