@@ -173,12 +173,13 @@ def main():
 
 
 def shell_kinds(sysm):
-    """The angular momenta present in the system's bases ("s", "s, p", "s, p, d")."""
+    """The angular momenta present in the system's bases ("s", "s, p", "s, p, d", ...)."""
     codes = [c for B in (sysm.L, sysm.S) if B is not None and getattr(B, "cart", None) is not None
              for c in B.cart]
     if not codes:
         return "s"
-    return "s, p, d" if max(codes) >= 4 else "s, p"
+    top = max(codes)
+    return "s, p, d, f" if top >= 10 else "s, p, d" if top >= 4 else "s, p"
 
 
 def main_transform(args):

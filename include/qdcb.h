@@ -19,7 +19,7 @@
  *     returns a message for the calling thread.  No C++ exception crosses
  *     this boundary.
  *   - Basis: contracted Gaussians, s type (qdcb_basis_create) or Cartesian s,
- *     p and d components (qdcb_basis_create_cart), and the gradient functions of
+ *     p, d and f components (qdcb_basis_create_cart), and the gradient functions of
  *     an s basis as the restricted-kinetic-balance small-component basis
  *     (qdcb_basis_create_rkb).  coefs multiply normalized primitives
  *     ((2a/pi)^{3/4} exp(-a r^2) for s); the library rescales every
@@ -110,24 +110,25 @@ qdcb_status qdcb_basis_create(qdcb_ctx *ctx, int32_t nfunc, const double *center
                               const int32_t *nprim, const double *exps, const double *coefs,
                               qdcb_basis **out);
 
-/* Basis of contracted Cartesian Gaussians of s, p or d type (the angular
+/* Basis of contracted Cartesian Gaussians of s, p, d or f type (the angular
  * momenta of the paper's basis sets, Sec. 2.5; each Cartesian component is a
  * function of its own).  Arguments as for qdcb_basis_create, plus cart
  * [nfunc] (host, copied): 0 = s, 1, 2, 3 = p_x, p_y, p_z, 4 .. 9 = d_xx,
- * d_yy, d_zz, d_xy, d_xz, d_yz, i.e. the monomials (x - A_x)^{l_x}
+ * d_yy, d_zz, d_xy, d_xz, d_yz, 10 .. 19 = f_xxx, f_yyy, f_zzz, f_xxy, f_xxz,
+ * f_xyy, f_yyz, f_xzz, f_yzz, f_xyz, i.e. the monomials (x - A_x)^{l_x}
  * (y - A_y)^{l_y} (z - A_z)^{l_z} times exp(-a |r - A|^2); NULL = all s (the
  * call is then qdcb_basis_create).  coefs multiply normalized primitives,
  * (2a/pi)^{3/4} (4a)^{L/2} / sqrt(prod_k (2 l_k - 1)!!) times the monomial
  * and the Gaussian (L = l_x + l_y + l_z), and each contracted function is
  * rescaled to unit self-overlap.  A shell is the functions of one centre,
- * exponent set and coefficient set (three p, six Cartesian d).  Integrals
- * with p functions are generated in McMurchie-Davidson form, and bases with
- * a d function take its general form for every integral; Schwarz factors
- * are per function pair, and primitive-pair screening is not applied to
- * pairs with a p or d function.  Plans over such bases support QDCB_HAM_LL,
+ * exponent set and coefficient set (three p, six Cartesian d, ten Cartesian
+ * f).  Integrals with p functions are generated in McMurchie-Davidson form,
+ * and bases with a d or f function take its general form for every
+ * integral; Schwarz factors are per function pair, and primitive-pair
+ * screening is not applied to pairs with a p, d or f function.  Plans over such bases support QDCB_HAM_LL,
  * QDCB_HAM_DC and QDCB_HAM_DCG (QDCB_HAM_DCB returns QDCB_E_UNSUPPORTED: its
  * gauge integrals take s functions only).  QDCB_E_INVALID for a code outside
- * [0, 9]. */
+ * [0, 19]. */
 qdcb_status qdcb_basis_create_cart(qdcb_ctx *ctx, int32_t nfunc, const double *centers,
                                    const int32_t *nprim, const double *exps,
                                    const double *coefs, const int32_t *cart,

@@ -22,6 +22,12 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // function in its erf form F0(T) = (1/2) sqrt(pi/T) erf(sqrt T).
 // Bases with p functions add, per primitive pair of functions (f, g),
 //   pa = P_i - A_i for f = p_i on centre A (0 for s), pb = P_j - B_j for g.
+// Code of a function pair (f, g) of Cartesian functions (function codes 0 .. 19:
+// s; p_x, p_y, p_z; six d; ten f) and its two function codes.
+__host__ __device__ __forceinline__ int pair_code(int cf, int cg) { return cf | (cg << 5); }
+__host__ __device__ __forceinline__ int code_f(int c) { return c & 31; }
+__host__ __device__ __forceinline__ int code_g(int c) { return (c >> 5) & 31; }
+
 // Primitive-pair data: 1/p, P, the charge factor e, and for Cartesian bases
 // pa / pb = (P - A) and (P - B) along the direction of a p function (0 for
 // an s function) and the full vectors P - A = (ax, ay, az), P - B = (bx, by,
@@ -80,9 +86,9 @@ constexpr int BOYS_LD = 10;
 // Columns of the table of the Cartesian (s/p) integral tiles: F_0 .. F_11, so
 // that F_0 .. F_4 each take eight Taylor terms
 constexpr int BOYS_LDC = 12;
-// Columns of the table of the general (s, p, d) tiles: F_0 .. F_15 (F_0 .. F_8
+// Columns of the table of the general (s .. f) tiles: F_0 .. F_19 (F_0 .. F_12
 // with eight Taylor terms each)
-constexpr int BOYS_LDG = 16;
+constexpr int BOYS_LDG = 20;
 
 // 1/sqrt(x) for finite x > 0: the hardware estimate y and one second-order
 // correction from the binomial series, y (1 + e/2 + 3 e^2/8), e = 1 - x y^2.
@@ -138,8 +144,9 @@ __device__ __forceinline__ double contracted_eri(const PrimPairsC &A, int64_t a0
 // ---------------------------------------------------------------------------
 // Integrals over Cartesian s and p functions (McMurchie-Davidson form).
 //
-// A function pair (f, g) has the code cf | (cg << 4), c = 0 for s and
-// 1, 2, 3 for p_x, p_y, p_z (4 .. 9 for d functions, general form below).  With Lambda_t the Hermite Gaussians
+// A function pair (f, g) has the code cf | (cg << 5) (pair_code), c = 0 for s
+// and 1, 2, 3 for p_x, p_y, p_z (4 .. 19 for d and f functions, general form
+// below).  With Lambda_t the Hermite Gaussians
 // d^t/dP^t exp(-p|r-P|^2), a pair's product expands over at most four of
 // them: for f = p_i on A and g = p_j on B
 //   (PA_i PB_j + delta_ij / 2p) L_0 + PB_j / 2p L_{e_i} + PA_i / 2p L_{e_j}
@@ -184,8 +191,8 @@ __device__ __forceinline__ double herm_r4(int i, int j, int k, int l, const doub
 // second function, or -1 for an s function.  inv2p = 1 / (2p).
 __device__ __forceinline__ void herm_side(int code, double pa, double pb, double inv2p,
                                           double h[4], int &a, int &b) {
-  a = (code & 15) - 1;
-  b = ((code >> 4) & 15) - 1;
+  a = code_f(code) - 1;
+  b = code_g(code) - 1;
   const double fa = a >= 0 ? pa : 1.0, fb = b >= 0 ? pb : 1.0;
   h[0] = fa * fb + ((a >= 0 && a == b) ? inv2p : 0.0);
   h[1] = a >= 0 ? fb * inv2p : 0.0;
@@ -305,9 +312,10 @@ __device__ inline double contracted_eri_cart(const PrimPairsC &A, int64_t a0, in
 }
 
 // ---------------------------------------------------------------------------
-// Integrals over Cartesian s, p and d functions, general form (bases with d
-// functions).  Codes 4 .. 9 are d_xx, d_yy, d_zz, d_xy, d_xz, d_yz, i.e. the
-// monomial (x - A_x)^{l_x} (y - A_y)^{l_y} (z - A_z)^{l_z}.
+// Integrals over Cartesian s, p, d and f functions, general form (bases with
+// d or f functions).  Codes 4 .. 9 are d_xx, d_yy, d_zz, d_xy, d_xz, d_yz and
+// 10 .. 19 f_xxx, f_yyy, f_zzz, f_xxy, f_xxz, f_xyy, f_yyz, f_xzz, f_yzz, f_xyz,
+// i.e. the monomial (x - A_x)^{l_x} (y - A_y)^{l_y} (z - A_z)^{l_z}.
 // McMurchie-Davidson form: per Cartesian direction the product of the two
 // functions of a pair expands in Hermite Gaussians with the coefficients
 // E^{ij}_t (t <= i + j) of the recursion
@@ -319,113 +327,136 @@ __device__ inline double contracted_eri_cart(const PrimPairsC &A, int64_t a0, in
 // so with H_x[T] = sum_{t + u = T} Ebra_x[t] (-1)^u Eket_x[u] and
 // P_x[s] = sum_T H_x[T] h_T^{T-s}(X_x) the value of a primitive quartet is
 //   sum_{s_x, s_y, s_z} P_x[s_x] P_y[s_y] P_z[s_z] G_{s_x + s_y + s_z}
-// (the same sums, factorized by direction).
+// (the same sums, factorized by direction).  TB, TK: bounds of the bra and
+// ket pairs' Hermite orders per direction (l_f + l_g of the pair, rounded up
+// to 2, 4 or 6), which size every array statically.
 // ---------------------------------------------------------------------------
-constexpr int GEN_T = 4;              // Hermite order of one pair per direction (two d)
-constexpr int GEN_S = 2 * GEN_T;      // Hermite order of a quartet per direction
-constexpr int GEN_NG = 2 * GEN_T + 1;  // Boys orders g_0 .. g_8 (four d functions)
+constexpr int GEN_TMAX = 6;                  // Hermite order of a pair per direction (two f)
+constexpr int GEN_NGMAX = 2 * GEN_TMAX + 1;  // Boys orders g_0 .. g_12 (four f functions)
 
-// a pair code with a d function (the general form)
+// a pair code with a d or f function (the general form)
 __host__ __device__ __forceinline__ bool gen_code(int c) {
-  return (c & 15) >= 4 || ((c >> 4) & 15) >= 4;
+  return code_f(c) >= 4 || code_g(c) >= 4;
 }
 
-// powers (l_x, l_y, l_z) of a function code 0 .. 9, two bits each, six per code
-__device__ __forceinline__ int cart_pow(int code, int dir) {
-  constexpr unsigned long long PK =
+// powers (l_x, l_y, l_z) of a function code 0 .. 19, two bits each, six bits
+// per code in two words (codes 0 .. 9, 10 .. 19)
+__host__ __device__ __forceinline__ int cart_pow(int code, int dir) {
+  constexpr unsigned long long PK0 =
       (0ull) | (1ull << 6) | (4ull << 12) | (16ull << 18) | (2ull << 24) | (8ull << 30) |
       (32ull << 36) | (5ull << 42) | (17ull << 48) | (20ull << 54);
-  return (int)((PK >> (6 * code + 2 * dir)) & 3ull);
+  constexpr unsigned long long PK1 =
+      (3ull) | (12ull << 6) | (48ull << 12) | (6ull << 18) | (18ull << 24) | (9ull << 30) |
+      (24ull << 36) | (33ull << 42) | (36ull << 48) | (21ull << 54);
+  const unsigned long long pk = code < 10 ? PK0 : PK1;
+  const int c = code < 10 ? code : code - 10;
+  return (int)((pk >> (6 * c + 2 * dir)) & 3ull);
+}
+// angular momentum of a function code
+__host__ __device__ __forceinline__ int cart_l(int code) {
+  return code == 0 ? 0 : (code < 4 ? 1 : (code < 10 ? 2 : 3));
+}
+// Hermite order bound of a pair code: l_f + l_g rounded up to 2, 4 or 6
+__host__ __device__ __forceinline__ int gen_bucket(int c) {
+  const int L = cart_l(code_f(c)) + cart_l(code_g(c));
+  return L <= 2 ? 2 : (L <= 4 ? 4 : 6);
 }
 
-// E^{ij}_t, t <= GEN_T, for i, j <= 2 (one direction of one primitive pair).
-__device__ __forceinline__ void herm_raise(double E[GEN_T + 1], double x, double h) {
-  double N[GEN_T + 1];
+// E^{ij}_t, t <= T, for i, j <= 3 with i + j <= T (one direction of one
+// primitive pair).
+template <int T>
+__device__ __forceinline__ void herm_raise(double E[T + 1], double x, double h) {
+  double N[T + 1];
 #pragma unroll
-  for (int t = 0; t <= GEN_T; ++t) {
+  for (int t = 0; t <= T; ++t) {
     double v = x * E[t];
-    if (t + 1 <= GEN_T) v = fma((double)(t + 1), E[t + 1], v);
+    if (t + 1 <= T) v = fma((double)(t + 1), E[t + 1], v);
     if (t >= 1) v = fma(h, E[t - 1], v);
     N[t] = v;
   }
 #pragma unroll
-  for (int t = 0; t <= GEN_T; ++t) E[t] = N[t];
+  for (int t = 0; t <= T; ++t) E[t] = N[t];
 }
+template <int T>
 __device__ __forceinline__ void herm_1d(int i, int j, double pa, double pb, double h,
-                                        double E[GEN_T + 1]) {
+                                        double E[T + 1]) {
   E[0] = 1.0;
 #pragma unroll
-  for (int t = 1; t <= GEN_T; ++t) E[t] = 0.0;
+  for (int t = 1; t <= T; ++t) E[t] = 0.0;
 #pragma unroll
-  for (int k = 0; k < 2; ++k)
-    if (k < i) herm_raise(E, pa, h);
+  for (int k = 0; k < 3 && k < T; ++k)
+    if (k < i) herm_raise<T>(E, pa, h);
 #pragma unroll
-  for (int k = 0; k < 2; ++k)
-    if (k < j) herm_raise(E, pb, h);
+  for (int k = 0; k < 3 && k < T; ++k)
+    if (k < j) herm_raise<T>(E, pb, h);
 }
 
 // P[s] = sum_T H[T] h_T^{T-s}(x), H[T] = sum_{t+u=T} Eb[t] (-1)^u Ek[u].
-__device__ __forceinline__ void herm_dir(const double Eb[GEN_T + 1], const double Ek[GEN_T + 1],
-                                         double x, double P[GEN_S + 1]) {
-  double H[GEN_S + 1];
+template <int TB, int TK>
+__device__ __forceinline__ void herm_dir(const double Eb[TB + 1], const double Ek[TK + 1],
+                                         double x, double P[TB + TK + 1]) {
+  constexpr int TS = TB + TK;
+  double H[TS + 1];
 #pragma unroll
-  for (int T = 0; T <= GEN_S; ++T) H[T] = 0.0;
+  for (int t = 0; t <= TS; ++t) H[t] = 0.0;
 #pragma unroll
-  for (int t = 0; t <= GEN_T; ++t)
+  for (int t = 0; t <= TB; ++t)
 #pragma unroll
-    for (int u = 0; u <= GEN_T; ++u) H[t + u] = fma(Eb[t], (u & 1) ? -Ek[u] : Ek[u], H[t + u]);
-  double xp[GEN_S + 1];
+    for (int u = 0; u <= TK; ++u) H[t + u] = fma(Eb[t], (u & 1) ? -Ek[u] : Ek[u], H[t + u]);
+  double xp[TS + 1];
   xp[0] = 1.0;
 #pragma unroll
-  for (int k = 1; k <= GEN_S; ++k) xp[k] = xp[k - 1] * x;
+  for (int k = 1; k <= TS; ++k) xp[k] = xp[k - 1] * x;
 #pragma unroll
-  for (int q = 0; q <= GEN_S; ++q) P[q] = 0.0;
+  for (int q = 0; q <= TS; ++q) P[q] = 0.0;
   // h_T^a = T! / (a! (T - 2a)! 2^a): products of integers, exact in double
 #pragma unroll
-  for (int T = 0; T <= GEN_S; ++T) {
-    double c = 1.0;  // h_T^0
+  for (int t = 0; t <= TS; ++t) {
+    double c = 1.0;  // h_t^0
 #pragma unroll
-    for (int a = 0; 2 * a <= T; ++a) {
-      P[T - a] = fma(H[T] * c, xp[T - 2 * a], P[T - a]);
-      // h_T^{a+1} / h_T^a = (T - 2a)(T - 2a - 1) / (2 (a + 1))
-      c = c * (double)((T - 2 * a) * (T - 2 * a - 1)) / (double)(2 * (a + 1));
+    for (int a = 0; 2 * a <= t; ++a) {
+      P[t - a] = fma(H[t] * c, xp[t - 2 * a], P[t - a]);
+      // h_t^{a+1} / h_t^a = (t - 2a)(t - 2a - 1) / (2 (a + 1))
+      c = c * (double)((t - 2 * a) * (t - 2 * a - 1)) / (double)(2 * (a + 1));
     }
   }
 }
 
-// Sum over (s_x, s_y, s_z) of P_x P_y P_z G_{s_x+s_y+s_z} (orders above
-// GEN_S vanish: the Hermite orders of a quartet add up to at most GEN_S).
-__device__ __forceinline__ double herm_sum(const double Px[GEN_S + 1], const double Py[GEN_S + 1],
-                                           const double Pz[GEN_S + 1], const double G[GEN_NG]) {
-  double Q[GEN_S + 1];
+// Sum over (s_x, s_y, s_z) of P_x P_y P_z G_{s_x+s_y+s_z} (orders above TS
+// vanish: the Hermite orders of a quartet add up to at most TS).
+template <int TS>
+__device__ __forceinline__ double herm_sum(const double Px[TS + 1], const double Py[TS + 1],
+                                           const double Pz[TS + 1], const double G[TS + 1]) {
+  double Q[TS + 1];
 #pragma unroll
-  for (int n = 0; n <= GEN_S; ++n) Q[n] = 0.0;
+  for (int n = 0; n <= TS; ++n) Q[n] = 0.0;
 #pragma unroll
-  for (int a = 0; a <= GEN_S; ++a)
+  for (int a = 0; a <= TS; ++a)
 #pragma unroll
-    for (int b = 0; a + b <= GEN_S; ++b) Q[a + b] = fma(Px[a], Py[b], Q[a + b]);
+    for (int b = 0; a + b <= TS; ++b) Q[a + b] = fma(Px[a], Py[b], Q[a + b]);
   double v = 0.0;
 #pragma unroll
-  for (int m = 0; m <= GEN_S; ++m) {
+  for (int m = 0; m <= TS; ++m) {
     double w = 0.0;
 #pragma unroll
-    for (int c = 0; m + c <= GEN_S; ++c) w = fma(Pz[c], G[m + c], w);
+    for (int c = 0; m + c <= TS; ++c) w = fma(Pz[c], G[m + c], w);
     v = fma(Q[m], w, v);
   }
   return v;
 }
 
-// g_n = (2/sqrt(pi)) sqrt(rho) F_n(T), n < NG, without a table: below T = 10
-// from the series of F_{NG-1} and the downward recursion; from T = 10 on from
-// the erf form of F_0 and the upward recursion (stable there for n <= 8).
+// g_n = (2/sqrt(pi)) sqrt(rho) F_n(T), n < NG, without a table: below T = 15
+// from the series of F_{NG-1} and the downward recursion; from T = 15 on
+// from the erf form of F_0 and the upward recursion (stable there for
+// n <= 12: each step multiplies an error by (2m + 1) / 2T < 1).
 template <int NG>
 __device__ inline void boys_g_exact_n(double T, double sr, double g[NG]) {
   const double c = TWO_OVER_SQRTPI * sr;
   const double eT = exp(-T);
-  if (T < 10.0) {
+  if (T < 15.0) {
     constexpr int M = NG - 1;
     double term = 1.0 / (2.0 * M + 1.0), sum = term;
-    for (int k = 1; k < 300; ++k) {
+    for (int k = 1; k < 400; ++k) {
       term *= 2.0 * T / (2.0 * M + 1.0 + 2.0 * k);
       sum += term;
       if (term < 1e-18 * sum) break;
@@ -452,33 +483,33 @@ __device__ inline double gen_quartet_exact(double ip, const double P[3], const d
                                            const double PB[3], int fa, int fb, double iq,
                                            const double Q[3], const double QC[3],
                                            const double QD[3], int fc, int fd) {
+  constexpr int T = GEN_TMAX, TS = 2 * GEN_TMAX;
   const double rho = 1.0 / (ip + iq);
   const double X[3] = {P[0] - Q[0], P[1] - Q[1], P[2] - Q[2]};
-  const double T = rho * (X[0] * X[0] + X[1] * X[1] + X[2] * X[2]);
-  double g[GEN_NG];
-  boys_g_exact_n<GEN_NG>(T, sqrt(rho), g);
-  double G[GEN_NG];
+  const double Tb = rho * (X[0] * X[0] + X[1] * X[1] + X[2] * X[2]);
+  double g[TS + 1];
+  boys_g_exact_n<TS + 1>(Tb, sqrt(rho), g);
   double f = 1.0;
-  for (int n = 0; n < GEN_NG; ++n) {
-    G[n] = f * g[n];
+  for (int n = 0; n <= TS; ++n) {
+    g[n] *= f;
     f *= -2.0 * rho;
   }
-  double Pd[3][GEN_S + 1];
+  double Pd[3][TS + 1];
   for (int d = 0; d < 3; ++d) {
-    double Eb[GEN_T + 1], Ek[GEN_T + 1];
-    herm_1d(cart_pow(fa, d), cart_pow(fb, d), PA[d], PB[d], 0.5 * ip, Eb);
-    herm_1d(cart_pow(fc, d), cart_pow(fd, d), QC[d], QD[d], 0.5 * iq, Ek);
-    herm_dir(Eb, Ek, X[d], Pd[d]);
+    double Eb[T + 1], Ek[T + 1];
+    herm_1d<T>(cart_pow(fa, d), cart_pow(fb, d), PA[d], PB[d], 0.5 * ip, Eb);
+    herm_1d<T>(cart_pow(fc, d), cart_pow(fd, d), QC[d], QD[d], 0.5 * iq, Ek);
+    herm_dir<T, T>(Eb, Ek, X[d], Pd[d]);
   }
-  return herm_sum(Pd[0], Pd[1], Pd[2], G);
+  return herm_sum<TS>(Pd[0], Pd[1], Pd[2], g);
 }
 
-// Contracted integral of two pairs with codes cf | (cg << 4) in the general
+// Contracted integral of two pairs with codes pair_code(cf, cg) in the general
 // form (the pair stores carry the P - A, P - B vectors).
 __device__ inline double contracted_eri_gen(const PrimPairsC &A, int64_t a0, int64_t a1, int ca,
                                             const PrimPairsC &B, int64_t b0, int64_t b1,
                                             int cb) {
-  const int fa = ca & 15, fb = (ca >> 4) & 15, fc = cb & 15, fd = (cb >> 4) & 15;
+  const int fa = code_f(ca), fb = code_g(ca), fc = code_f(cb), fd = code_g(cb);
   double acc = 0.0;
   for (int64_t i = a0; i < a1; ++i) {
     const double P[3] = {A.x[i], A.y[i], A.z[i]};

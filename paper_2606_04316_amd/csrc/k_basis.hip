@@ -10,9 +10,10 @@
 namespace qdcb {
 
 // nc[i] = c_i N(a_i) / sqrt(<chi|chi>) multiplies exp(-a_i r^2) (s),
-// (x - A_x) exp(-a_i r^2) (p_x; likewise p_y, p_z) or (x - A_x)(y - A_y)
-// exp(-a_i r^2) (d_xy; likewise the other d codes), with the primitive
-// normalization N(a) = (2a/pi)^{3/4} (4a)^{L/2} / sqrt(prod_k (2 l_k - 1)!!)
+// (x - A_x) exp(-a_i r^2) (p_x; likewise p_y, p_z) or the monomial
+// (x - A_x)^{l_x} (y - A_y)^{l_y} (z - A_z)^{l_z} exp(-a_i r^2) of a d or f
+// code, with the primitive normalization
+// N(a) = (2a/pi)^{3/4} (4a)^{L/2} / sqrt(prod_k (2 l_k - 1)!!)
 // (s: (2a/pi)^{3/4}; p: (2a/pi)^{3/4} 2 sqrt(a)).  Two primitives of one
 // function overlap by (pi/q)^{3/2} prod_k (2 l_k - 1)!! / (2q)^{l_k}, q = a + b.
 __global__ void k_norm_coefs(int nfunc, const int32_t *first, const double *exps,
@@ -20,12 +21,17 @@ __global__ void k_norm_coefs(int nfunc, const int32_t *first, const double *exps
   int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= nfunc) return;
   const int code = cart ? cart[f] : 0;
-  const bool pf = code >= 1 && code <= 3, df = code >= 4;
-  // d: (2 l_x - 1)!! (2 l_y - 1)!! (2 l_z - 1)!! = 3 for d_xx, d_yy, d_zz, 1 otherwise
-  const double dd = code >= 4 && code <= 6 ? 3.0 : 1.0;
+  const bool pf = code >= 1 && code <= 3, df = code >= 4 && code <= 9, ff = code >= 10;
+  // prod_k (2 l_k - 1)!! (1, 3 or 15 per direction)
+  double dd = 1.0;
+  for (int k = 0; k < 3; ++k) {
+    const int l = cart_pow(code, k);
+    dd *= l == 3 ? 15.0 : (l == 2 ? 3.0 : 1.0);
+  }
   auto nrm = [&](double a) {
     const double n = pow(2.0 * a / PI, 0.75);
-    return pf ? 2.0 * sqrt(a) * n : (df ? 4.0 * a * n / sqrt(dd) : n);
+    return pf ? 2.0 * sqrt(a) * n
+              : (df ? 4.0 * a * n / sqrt(dd) : (ff ? 8.0 * a * sqrt(a) * n / sqrt(dd) : n));
   };
   int i0 = first[f], i1 = first[f + 1];
   double s = 0.0;
@@ -37,6 +43,7 @@ __global__ void k_norm_coefs(int nfunc, const int32_t *first, const double *exps
       double ov = pow(PI / q, 1.5);
       if (pf) ov /= 2.0 * q;
       if (df) ov *= dd / (4.0 * q * q);
+      if (ff) ov *= dd / (8.0 * q * q * q);
       s += di * dj * ov;
     }
   }
@@ -125,8 +132,8 @@ __global__ void __launch_bounds__(256) k_schwarz(int64_t npairs, const int64_t *
       const double Ai[3] = {pp.ax[i], pp.ay[i], pp.az[i]}, Aj[3] = {pp.ax[j], pp.ay[j], pp.az[j]};
       const double Bi[3] = {pp.bx[i], pp.by[i], pp.bz[i]}, Bj[3] = {pp.bx[j], pp.by[j], pp.bz[j]};
       acc += pp.e[i] * pp.e[j] *
-             gen_quartet_exact(pp.ip[i], Pi, Ai, Bi, c & 15, c >> 4, pp.ip[j], Pj, Aj, Bj,
-                               c & 15, c >> 4);
+             gen_quartet_exact(pp.ip[i], Pi, Ai, Bi, code_f(c), code_g(c), pp.ip[j], Pj, Aj, Bj,
+                               code_f(c), code_g(c));
     } else if (c)
       acc += pp.e[i] * pp.e[j] *
              cart_quartet_exact(pp.ip[i], pp.x[i], pp.y[i], pp.z[i], pp.pa[i], pp.pb[i], c,

@@ -431,7 +431,7 @@ __device__ __forceinline__ double cart_row_pair(const EriTileArgs &A, const doub
                                                 int64_t kf0, int64_t kf1, int64_t b0, int64_t b1,
                                                 const CartDirs &r, int kcode) {
   constexpr int NG = 3 + KT;  // G_0 .. G_{2 + KT}
-  const int kc = (kcode & 15) - 1;
+  const int kc = code_f(kcode) - 1;
   const cdptr kip = as_const(A.pp.ip), kx = as_const(A.pp.x), ky = as_const(A.pp.y),
               kz = as_const(A.pp.z), ke = as_const(A.pp.e), kpa = as_const(A.pp.pa),
               kpb = as_const(A.pp.pb);
@@ -515,7 +515,7 @@ __device__ __forceinline__ void eri_cart_tile_body(const EriTileArgs &a, const d
   const int bcode = a.code[brow];
   const int64_t bfirst = a.row_first[brow];
   const int64_t blast = a.row_first[brow + 1];
-  const int ba = (bcode & 15) - 1, bb = ((bcode >> 4) & 15) - 1;
+  const int ba = code_f(bcode) - 1, bb = code_g(bcode) - 1;
   for (int i = 0; i < TILE / ERI_WAVES; ++i) {
     const int j = w + ERI_WAVES * i;
     const int64_t krow = (int64_t)kt * TILE + j;
@@ -527,7 +527,7 @@ __device__ __forceinline__ void eri_cart_tile_body(const EriTileArgs &a, const d
     const bool keep_bk = out && (qb * qk) * dk >= a.tau;
     const bool keep_kb = outT && (qk * qb) * db >= a.tau;
     if (keep_bk || keep_kb) {
-      const int kc = (kcode & 15) - 1, kd = ((kcode >> 4) & 15) - 1;
+      const int kc = code_f(kcode) - 1, kd = code_g(kcode) - 1;
       const int kt_p = (kc >= 0) + (kd >= 0);
       CartDirs r;
       r.ha = ba >= 0;
@@ -610,16 +610,19 @@ __global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles_queue_cart(EriTileArg
   eri_count(a, kept);
 }
 
-// ---- general (s, p, d) tiles: bases with d functions
+// ---- general (s .. f) tiles: bases with d or f functions
 
 // Contracted value of one (bra row, ket row) pair of a general tile (codes
-// cf | (cg << 4)), in the factorized McMurchie-Davidson form of common.h.  The
-// lane's bra primitive outside (its Hermite coefficients held in registers),
-// the wavefront-uniform ket primitives inside (scalar loads).
+// pair_code(cf, cg)), in the factorized McMurchie-Davidson form of common.h,
+// with TB, TK bounding the Hermite orders of the tile's bra pairs and of the
+// ket pair.  The lane's bra primitive outside (its Hermite coefficients held
+// in registers), the wavefront-uniform ket primitives inside (scalar loads).
+template <int TB, int TK>
 __device__ __forceinline__ double gen_row_pair(const EriTileArgs &A, const double *tab,
                                                int64_t kf0, int64_t kf1, int64_t b0, int64_t b1,
                                                int bcode, int kcode) {
-  const int fa = bcode & 15, fb = (bcode >> 4) & 15, fc = kcode & 15, fd = (kcode >> 4) & 15;
+  constexpr int TS = TB + TK;
+  const int fa = code_f(bcode), fb = code_g(bcode), fc = code_f(kcode), fd = code_g(kcode);
   const cdptr kip = as_const(A.pp.ip), kx = as_const(A.pp.x), ky = as_const(A.pp.y),
               kz = as_const(A.pp.z), ke = as_const(A.pp.e), kax = as_const(A.pp.ax),
               kay = as_const(A.pp.ay), kaz = as_const(A.pp.az), kbx = as_const(A.pp.bx),
@@ -628,10 +631,10 @@ __device__ __forceinline__ double gen_row_pair(const EriTileArgs &A, const doubl
   for (int64_t b = b0; b < b1; ++b) {
     const double ip = A.pp.ip[b], px = A.pp.x[b], py = A.pp.y[b], pz = A.pp.z[b];
     const double hb = 0.5 * ip;
-    double Ebx[GEN_T + 1], Eby[GEN_T + 1], Ebz[GEN_T + 1];
-    herm_1d(cart_pow(fa, 0), cart_pow(fb, 0), A.pp.ax[b], A.pp.bx[b], hb, Ebx);
-    herm_1d(cart_pow(fa, 1), cart_pow(fb, 1), A.pp.ay[b], A.pp.by[b], hb, Eby);
-    herm_1d(cart_pow(fa, 2), cart_pow(fb, 2), A.pp.az[b], A.pp.bz[b], hb, Ebz);
+    double Ebx[TB + 1], Eby[TB + 1], Ebz[TB + 1];
+    herm_1d<TB>(cart_pow(fa, 0), cart_pow(fb, 0), A.pp.ax[b], A.pp.bx[b], hb, Ebx);
+    herm_1d<TB>(cart_pow(fa, 1), cart_pow(fb, 1), A.pp.ay[b], A.pp.by[b], hb, Eby);
+    herm_1d<TB>(cart_pow(fa, 2), cart_pow(fb, 2), A.pp.az[b], A.pp.bz[b], hb, Ebz);
     double s = 0.0;
     for (int64_t k = kf0; k < kf1; ++k) {
       const double iq = kip[k], hk = 0.5 * iq;
@@ -639,27 +642,36 @@ __device__ __forceinline__ double gen_row_pair(const EriTileArgs &A, const doubl
       const double sr = rsqrt_pos(ip + iq);
       const double rho = sr * sr;
       const double r2 = X0 * X0 + X1 * X1 + X2 * X2;
-      double G[GEN_NG];
-      boys_g_tab_n<GEN_NG, BOYS_LDG>(tab, r2 * rho, r2, sr, G);
+      double G[TS + 1];
+      boys_g_tab_n<TS + 1, BOYS_LDG>(tab, r2 * rho, r2, sr, G);
       const double m2r = -2.0 * rho;
       double f = m2r;
 #pragma unroll
-      for (int n = 1; n < GEN_NG; ++n) {
+      for (int n = 1; n <= TS; ++n) {
         G[n] *= f;
         f *= m2r;
       }
-      double Ek[GEN_T + 1], Px[GEN_S + 1], Py[GEN_S + 1], Pz[GEN_S + 1];
-      herm_1d(cart_pow(fc, 0), cart_pow(fd, 0), kax[k], kbx[k], hk, Ek);
-      herm_dir(Ebx, Ek, X0, Px);
-      herm_1d(cart_pow(fc, 1), cart_pow(fd, 1), kay[k], kby[k], hk, Ek);
-      herm_dir(Eby, Ek, X1, Py);
-      herm_1d(cart_pow(fc, 2), cart_pow(fd, 2), kaz[k], kbz[k], hk, Ek);
-      herm_dir(Ebz, Ek, X2, Pz);
-      s = fma(ke[k], herm_sum(Px, Py, Pz, G), s);
+      double Ek[TK + 1], Px[TS + 1], Py[TS + 1], Pz[TS + 1];
+      herm_1d<TK>(cart_pow(fc, 0), cart_pow(fd, 0), kax[k], kbx[k], hk, Ek);
+      herm_dir<TB, TK>(Ebx, Ek, X0, Px);
+      herm_1d<TK>(cart_pow(fc, 1), cart_pow(fd, 1), kay[k], kby[k], hk, Ek);
+      herm_dir<TB, TK>(Eby, Ek, X1, Py);
+      herm_1d<TK>(cart_pow(fc, 2), cart_pow(fd, 2), kaz[k], kbz[k], hk, Ek);
+      herm_dir<TB, TK>(Ebz, Ek, X2, Pz);
+      s = fma(ke[k], herm_sum<TS>(Px, Py, Pz, G), s);
     }
     v = fma(A.pp.e[b], s, v);
   }
   return v;
+}
+
+template <int TB>
+__device__ __forceinline__ double gen_row_pair_k(const EriTileArgs &A, const double *tab,
+                                                 int64_t kf0, int64_t kf1, int64_t b0,
+                                                 int64_t b1, int bcode, int kcode, int tk) {
+  if (tk == 2) return gen_row_pair<TB, 2>(A, tab, kf0, kf1, b0, b1, bcode, kcode);
+  if (tk == 4) return gen_row_pair<TB, 4>(A, tab, kf0, kf1, b0, b1, bcode, kcode);
+  return gen_row_pair<TB, 6>(A, tab, kf0, kf1, b0, b1, bcode, kcode);
 }
 
 __device__ __forceinline__ void eri_gen_one_tile(const EriTileArgs &a, const double *tab,
@@ -682,6 +694,10 @@ __device__ __forceinline__ void eri_gen_one_tile(const EriTileArgs &a, const dou
   const int cb = a.cls[brow];
   const int bcode = a.code[brow];
   const int64_t bfirst = a.row_first[brow], blast = a.row_first[brow + 1];
+  // the Hermite order bound of the tile's bra pairs (uniform)
+  int tb = gen_bucket(bcode);
+  for (int o = 32; o > 0; o >>= 1) tb = max(tb, __shfl_xor(tb, o, 64));
+  tb = __builtin_amdgcn_readfirstlane(tb);
   for (int i = 0; i < TILE / ERI_WAVES; ++i) {
     const int j = w + ERI_WAVES * i;
     const int64_t krow = (int64_t)kt * TILE + j;
@@ -693,7 +709,13 @@ __device__ __forceinline__ void eri_gen_one_tile(const EriTileArgs &a, const dou
     const bool keep_bk = out && (qb * qk) * dk >= a.tau;
     const bool keep_kb = outT && (qk * qb) * db >= a.tau;
     if (keep_bk || keep_kb) {
-      v = gen_row_pair(a, tab, kf0, kf1, bfirst, blast, bcode, kcode);
+      const int tk = gen_bucket(kcode);
+      if (tb == 2)
+        v = gen_row_pair_k<2>(a, tab, kf0, kf1, bfirst, blast, bcode, kcode, tk);
+      else if (tb == 4)
+        v = gen_row_pair_k<4>(a, tab, kf0, kf1, bfirst, blast, bcode, kcode, tk);
+      else
+        v = gen_row_pair_k<6>(a, tab, kf0, kf1, bfirst, blast, bcode, kcode, tk);
       if (cb >= 0 && ck >= 0) {
         if (keep_bk) kept[cb * 2 + ck] += 1;
         if (keep_kb) kept[ck * 2 + cb] += 1;

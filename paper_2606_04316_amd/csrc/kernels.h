@@ -20,7 +20,7 @@ void launch_pair_data(int64_t npairs, const int32_t *mu, const int32_t *nu,
                       const double *centB, const int32_t *firstB, const double *expB,
                       const double *ncB, const int32_t *cartB, PrimPairs out, hipStream_t s);
 // Q[i] = sqrt((i|i)) over the primitive pairs [pair_first[i], pair_first[i+1]).
-// code: per pair cf | (cg << 4) for Cartesian bases, else NULL.
+// code: per pair pair_code(cf, cg) for Cartesian bases, else NULL.
 void launch_schwarz(int64_t npairs, const int64_t *pair_first, PrimPairsC pp,
                     const int32_t *code, double *Q, hipStream_t s);
 // Primitive-pair screening: kept[r] = number of the cnt[r] primitive pairs of

@@ -65,8 +65,8 @@ __global__ void k_quartet_ranges(int64_t nq, const int32_t *idx, const int64_t *
   bf[q] = pfB[pb];
   bc[q] = (int32_t)(pfB[pb + 1] - pfB[pb]);
   if (codes) {
-    codes[2 * q] = (cartA ? cartA[a0] : 0) | ((cartA ? cartA[a1] : 0) << 4);
-    codes[2 * q + 1] = (cartB ? cartB[b0] : 0) | ((cartB ? cartB[b1] : 0) << 4);
+    codes[2 * q] = pair_code(cartA ? cartA[a0] : 0, cartA ? cartA[a1] : 0);
+    codes[2 * q + 1] = pair_code(cartB ? cartB[b0] : 0, cartB ? cartB[b1] : 0);
   }
 }
 

@@ -131,13 +131,13 @@ struct qdcb_plan {
   qdcb::DBuf<double> boys;   // Taylor table of the Boys function F0
   qdcb::DBuf<double> boys3;  // F0 .. F9 on the same grid (gauge tiles)
   bool cart = false;         // a basis has p functions: Cartesian integral tiles
-  bool gen = false;          // a basis has d functions: the general integral tiles
+  bool gen = false;          // a basis has d or f functions: the general integral tiles
   // integral tiles in the intra-tile row order of each transform, first half
   // skipping masked 16-row steps (environment QDCB_TILE_ORDER=0 at plan
   // creation turns it off, for comparisons)
   bool tile_order = true;
   qdcb::DBuf<double> boysc;  // F0 .. F11 on the same grid (Cartesian tiles)
-  qdcb::DBuf<double> boysg;  // F0 .. F15 on the same grid (general tiles, bases with d)
+  qdcb::DBuf<double> boysg;  // F0 .. F19 on the same grid (general tiles: d or f functions)
   bool have_last = false;
   int64_t tiles_made = 0;  // integral tiles generated by the last eager transform
   int v_i0 = 0, v_i1 = 0;  // MO pairs whose first-half columns V holds (last chunk)

@@ -27,7 +27,7 @@ struct RowSrc {
   int32_t cnt;
   int which;        // which source store
   int32_t kept = 0;  // primitive pairs kept by primitive screening
-  int32_t code = 0;  // pair code cf | (cg << 4) of Cartesian bases (0: s s)
+  int32_t code = 0;  // pair_code(cf, cg) of Cartesian bases (0: s s)
 };
 
 // Rows ordered by Schwarz factor; band_rows > 0: within each band of that many
@@ -434,7 +434,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
     p.gauge = desc->ham == QDCB_HAM_DCB;
     p.fused_breit = p.gauge && desc->prec == QDCB_PREC_FP64;
     p.cart = L->has_p() || (S && S->has_p());
-    p.gen = L->has_d() || (S && S->has_d());
+    p.gen = L->has_gen() || (S && S->has_gen());
     {
       const char *e = std::getenv("QDCB_TILE_ORDER");
       p.tile_order = !(e && e[0] == '0');
@@ -462,7 +462,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
             int64_t c = qdcb_basis::canon(mu, nu);
             RowSrc r{B->Q[c], cls, mu, nu, c, B->pair_first[c],
                      (int32_t)(B->pair_first[c + 1] - B->pair_first[c]), which};
-            r.code = B->cart_of(mu) | (B->cart_of(nu) << 4);
+            r.code = pair_code(B->cart_of(mu), B->cart_of(nu));
             rows.push_back(r);
           }
       };
@@ -502,7 +502,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
                        ls.view(), nullptr);
       std::vector<int32_t> lcode(p.cart ? nls : 0);
       for (int64_t i = 0; p.cart && i < nls; ++i)
-        lcode[i] = L->cart_of(pm[i]) | (S->cart_of(pn[i]) << 4);
+        lcode[i] = pair_code(L->cart_of(pm[i]), S->cart_of(pn[i]));
       DBuf<int32_t> dlcode(POOLED);
       if (p.cart) dlcode.upload(ctx, lcode);
       dQ.alloc(ctx, nls);

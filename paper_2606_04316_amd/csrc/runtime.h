@@ -228,11 +228,12 @@ struct qdcb_basis {
   std::vector<int64_t> pair_first;  // canonical pairs (mu <= nu, nu-major) [npairs+1]
   std::vector<double> Q;            // host copy of the Schwarz factors
   // [nfunc] 0 = s, 1..3 = p_x, p_y, p_z, 4..9 = d_xx, d_yy, d_zz, d_xy, d_xz,
-  // d_yz (empty: all s)
+  // d_yz, 10..19 = f_xxx, f_yyy, f_zzz, f_xxy, f_xxz, f_xyy, f_yyz, f_xzz,
+  // f_yzz, f_xyz (empty: all s)
   std::vector<int32_t> cart;
   int64_t npairs = 0;
-  bool has_p() const { return !cart.empty(); }  // any Cartesian function (p or d)
-  bool has_d() const {
+  bool has_p() const { return !cart.empty(); }  // any Cartesian function (p, d or f)
+  bool has_gen() const {  // a d or f function (the general integral form)
     for (int32_t c : cart)
       if (c >= 4) return true;
     return false;

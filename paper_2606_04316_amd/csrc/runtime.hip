@@ -228,7 +228,7 @@ qdcb_status qdcb_basis_create_cart(qdcb_ctx *ctx, int32_t nfunc, const double *c
     }
     bool any_p = false;
     for (int f = 0; cart && f < nfunc; ++f) {
-      if (cart[f] < 0 || cart[f] > 9) fail(QDCB_E_INVALID, "cart codes must be in [0, 9]");
+      if (cart[f] < 0 || cart[f] > 19) fail(QDCB_E_INVALID, "cart codes must be in [0, 19]");
       any_p = any_p || cart[f] != 0;
     }
     DeviceGuard g(ctx->device);
@@ -275,7 +275,7 @@ qdcb_status qdcb_basis_create_cart(qdcb_ctx *ctx, int32_t nfunc, const double *c
     DBuf<int32_t> dcode(POOLED);
     if (any_p) {
       std::vector<int32_t> code(npairs);
-      for (int64_t i = 0; i < npairs; ++i) code[i] = b->cart[pm[i]] | (b->cart[pn[i]] << 4);
+      for (int64_t i = 0; i < npairs; ++i) code[i] = pair_code(b->cart[pm[i]], b->cart[pn[i]]);
       dcode.upload(ctx, code);
     }
     b->dQ.alloc(ctx, npairs);
@@ -433,8 +433,8 @@ qdcb_status qdcb_eri_quartets(const qdcb_basis *A, const qdcb_basis *B, int64_t 
         // canonical pair (mu <= nu): first function mu, second nu
         const int a0 = std::min(i4[0], i4[1]), a1 = std::max(i4[0], i4[1]);
         const int b0 = std::min(i4[2], i4[3]), b1 = std::max(i4[2], i4[3]);
-        codes[2 * q] = A->cart_of(a0) | (A->cart_of(a1) << 4);
-        codes[2 * q + 1] = B->cart_of(b0) | (B->cart_of(b1) << 4);
+        codes[2 * q] = pair_code(A->cart_of(a0), A->cart_of(a1));
+        codes[2 * q + 1] = pair_code(B->cart_of(b0), B->cart_of(b1));
       }
     }
     qdcb_ctx *ctx = A->ctx;

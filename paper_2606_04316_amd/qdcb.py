@@ -201,7 +201,8 @@ class Context:
 
 class Basis:
     """Device-resident basis: ``basis`` has centers, nprim, exps, coefs and
-    optionally cart (0 = s, 1..3 = p_x, p_y, p_z, 4..9 = d_xx, d_yy, d_zz, d_xy, d_xz, d_yz;
+    optionally cart (0 = s, 1..3 = p_x, p_y, p_z, 4..9 = d_xx, d_yy, d_zz, d_xy, d_xz, d_yz,
+    10..19 = f_xxx, f_yyy, f_zzz, f_xxy, f_xxz, f_xyy, f_yyz, f_xzz, f_yzz, f_xyz;
     qdcb_basis_create_cart)."""
 
     def __init__(self, ctx: Context, basis):

@@ -337,11 +337,13 @@ def cluster(seed: int = 3, n_atoms: int = 60, radius: float = 20.0, min_sep: flo
 
 def make_sp_basis(rng: np.random.Generator, atoms: np.ndarray, s_per_atom: int,
                   p_shells_per_atom: int, nprim, exp_lo: float, exp_hi: float,
-                  exp_scale: float = 1.0, d_shells_per_atom: int = 0) -> Basis:
+                  exp_scale: float = 1.0, d_shells_per_atom: int = 0,
+                  f_shells_per_atom: int = 0) -> Basis:
     """Per atom ``s_per_atom`` s functions, ``p_shells_per_atom`` p shells
     (p_x, p_y, p_z with one shared set of exponents and coefficients) and
     ``d_shells_per_atom`` Cartesian d shells (codes 4..9: d_xx, d_yy, d_zz,
-    d_xy, d_xz, d_yz, shared exponents and coefficients), drawn as in
+    d_xy, d_xz, d_yz, shared exponents and coefficients) and
+    ``f_shells_per_atom`` Cartesian f shells (codes 10..19), drawn as in
     make_basis; functions are listed atom by atom."""
     centers, nprim_l, exps, coefs, cart = [], [], [], [], []
 
@@ -367,6 +369,13 @@ def make_sp_basis(rng: np.random.Generator, atoms: np.ndarray, s_per_atom: int,
             e = exp_scale * 10.0 ** rng.uniform(math.log10(exp_lo), math.log10(exp_hi), size=k)
             c = rng.uniform(0.1, 1.0, size=k)
             for comp in range(4, 10):
+                centers.append(a); nprim_l.append(k); exps.append(e); coefs.append(c)
+                cart.append(comp)
+        for _ in range(f_shells_per_atom):
+            k = draw()
+            e = exp_scale * 10.0 ** rng.uniform(math.log10(exp_lo), math.log10(exp_hi), size=k)
+            c = rng.uniform(0.1, 1.0, size=k)
+            for comp in range(10, 20):
                 centers.append(a); nprim_l.append(k); exps.append(e); coefs.append(c)
                 cart.append(comp)
     return Basis(np.ascontiguousarray(np.array(centers, dtype=np.float64)),
@@ -399,17 +408,20 @@ def sp_cluster(seed: int = 5, n_atoms: int = 8, edge: float = 6.0, s_per_atom: i
 
 
 def spd_cluster(seed: int = 7, n_atoms: int = 4, edge: float = 4.0, nprim=(1, 2), n: int = 4,
-                tau: float = 0.0, ham: str = "DC", d_l: int = 1, d_s: int = 0) -> System:
-    """Atoms uniform in a cube with one s function, one p shell and ``d_l``
-    Cartesian d shells per atom in L (10 functions per atom by default) and
-    one s function, one p shell and ``d_s`` d shells in S (exponents x4).  MO
-    coefficients as in sp_cluster (quaternion QR, |C| <= 1)."""
+                tau: float = 0.0, ham: str = "DC", d_l: int = 1, d_s: int = 0, f_l: int = 0,
+                p_s: int = 1) -> System:
+    """Atoms uniform in a cube with one s function, one p shell, ``d_l``
+    Cartesian d shells and ``f_l`` Cartesian f shells per atom in L (10
+    functions per atom by default) and one s function, ``p_s`` p shells and
+    ``d_s`` d shells in S (exponents x4).  MO coefficients as in sp_cluster
+    (quaternion QR, |C| <= 1)."""
     ra, rb, rc, _ = _streams(seed)
     atoms = cube(ra, n_atoms, edge)
-    L = make_sp_basis(rb, atoms, 1, 1, nprim, 0.1, 10.0, d_shells_per_atom=d_l)
+    L = make_sp_basis(rb, atoms, 1, 1, nprim, 0.1, 10.0, d_shells_per_atom=d_l,
+                      f_shells_per_atom=f_l)
     S = None
     if ham != "LL":
-        S = make_sp_basis(rb, atoms, 1, 1, nprim, 0.1, 10.0, exp_scale=4.0,
+        S = make_sp_basis(rb, atoms, 1, p_s, nprim, 0.1, 10.0, exp_scale=4.0,
                           d_shells_per_atom=d_s)
     NL, NS = L.nfunc, (S.nfunc if S is not None else 0)
     Q = quat_qr_plus(gaussian_quat(rc, NL + NS, n))

@@ -8,7 +8,7 @@ counts (exact) and the MO integrals of LL, DC and DCG transforms
 (max|G_gpu - G_oracle| <= 1e-12 max|G_oracle|), on systems whose pair spaces
 span several 64-pair tiles with a ragged last tile, under both integral
 schedules, with directed and unique tiles and in the primitive-band row order.  DCB plans with p functions
-are refused (the gauge integrals take s functions only), and so are codes beyond d.
+are refused (the gauge integrals take s functions only), and so are codes beyond f.
 """
 import numpy as np
 import pytest
@@ -125,7 +125,7 @@ def test_cart_refuses_gauge(q, ctx):
     assert e.value.status == -4
     with pytest.raises(q.QdcbError):
         q.Basis(ctx, wl.Basis(s.L.centers, s.L.nprim, s.L.exps, s.L.coefs,
-                              np.full(s.L.nfunc, 10, np.int32)))
+                              np.full(s.L.nfunc, 20, np.int32)))
 
 
 def test_cart_spinor_plan_matches_oracle(q, ctx):

@@ -1,10 +1,15 @@
-"""GPU parity for bases with Cartesian d functions (codes 4..9).
+"""GPU parity for bases with Cartesian d functions (codes 4..9) and f
+functions (codes 10..19).
 
-A basis with a d function takes the general integral kernels: the pair
+A basis with a d or f function takes the general integral kernels: the pair
 product in McMurchie-Davidson form with the Hermite coefficients of each
 direction from their recursion and the Hermite integrals factorized by
-direction (common.h), Boys orders to 8; the oracle uses the Obara-Saika
-recursion (its d functions are pinned in test_oracle_p.py).  Compared here:
+direction (common.h), Boys orders to 12; the oracle uses the Obara-Saika
+recursion (its d and f functions are pinned in test_oracle_p.py).  For f the
+oracle's recursion carries up to 1.3e-13 relative rounding (measured against
+the same integrals in extended precision), so single f integrals are compared
+at 1e-12 of the largest; the f transform is LL over two atoms (the oracle's
+recursion for (ff|ff) is slow).  Compared here:
 Schwarz factors and single integrals (1e-13 of the largest), kept
 contribution counts (exact) and the MO integrals of LL, DC and DCG transforms
 (max|G_gpu - G_oracle| <= 1e-12 max|G_oracle| on QR coefficients), on pair
@@ -12,7 +17,7 @@ spaces of several 64-pair tiles with a ragged last tile, under both integral
 schedules, with directed and unique tiles, in both row orders, with d
 functions in one basis or in both; two-spinor plans, the FP32 tier, the
 MO-driven variant and graph replays.  DCB plans with d functions are refused,
-and codes beyond d are refused at basis creation.
+and codes beyond f are refused at basis creation.
 """
 import numpy as np
 import pytest
@@ -123,7 +128,7 @@ def test_d_schedules(q, ctx, eri_sched, flags):
            tune={"eri_sched": eri_sched, "fh_order": 0, "sq_tile": 64})
 
 
-def test_d_refuses_gauge_and_f(q, ctx):
+def test_d_refuses_gauge_and_codes_beyond_f(q, ctx):
     s = _sys("DC", 0.0, n_atoms=2, n=2)
     L, S = q.Basis(ctx, s.L), q.Basis(ctx, s.S)
     with pytest.raises(q.QdcbError) as e:
@@ -131,7 +136,7 @@ def test_d_refuses_gauge_and_f(q, ctx):
     assert e.value.status == -4
     with pytest.raises(q.QdcbError):
         q.Basis(ctx, wl.Basis(s.L.centers, s.L.nprim, s.L.exps, s.L.coefs,
-                              np.full(s.L.nfunc, 10, np.int32)))
+                              np.full(s.L.nfunc, 20, np.int32)))
 
 
 def test_d_spinor_plan_matches_oracle(q, ctx):
@@ -192,3 +197,41 @@ def test_d_graph_replays_equal_eager(q, ctx):
         torch.cuda.synchronize()
         assert st["kept"] == ste["kept"]
         assert torch.equal(Gr, Ge)
+
+
+def _f_sys(ham="LL", tau=1e-10, seed=71):
+    # two atoms, s + p shell + f shell in L (N_L = 28: 406 pairs, 6.3 tiles)
+    return wl.spd_cluster(seed=seed, n_atoms=2, edge=5.0, n=3, ham=ham, tau=tau, d_l=0, f_l=1,
+                          nprim=1, p_s=0)
+
+
+def test_f_schwarz_factors(q, ctx):
+    s = wl.spd_cluster(seed=72, n_atoms=2, edge=5.0, n=2, ham="LL", d_l=1, f_l=1)
+    Qg = q.Basis(ctx, s.L).schwarz()
+    Qo = oracle.schwarz(s.L)
+    assert np.abs(Qg**2 - Qo**2).max() <= 1e-12 * (Qo**2).max()
+
+
+def test_f_eri_quartets(q, ctx):
+    s = wl.spd_cluster(seed=73, n_atoms=2, edge=4.0, n=2, ham="DC", d_l=1, f_l=1, d_s=1)
+    A, B = q.Basis(ctx, s.L), q.Basis(ctx, s.S)
+    rng = np.random.default_rng(4)
+    NL, NS = s.L.nfunc, s.S.nfunc
+    fl = np.array([f for f in range(NL) if s.L.cart[f] >= 10])
+    idx = np.stack([rng.choice(fl, 300), rng.integers(0, NL, 300),
+                    rng.integers(0, NS, 300), rng.integers(0, NS, 300)], 1)
+    idx[:30, 1] = idx[:30, 0]
+    got = q.eri_quartets(A, B, idx)
+    ref = np.array([oracle.eri(s.L, a, b, s.S, c, d) for a, b, c, d in idx])
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    # (ff|ff) over one f shell and (ff|ds) across the two atoms
+    idx2 = np.array([(a, b, c, d) for a in fl[:10:3] for b in fl[:10:2] for c in fl[10::3]
+                     for d in fl[10::4]])
+    got2 = q.eri_quartets(A, A, idx2)
+    ref2 = np.array([oracle.eri(s.L, a, b, s.L, c, d) for a, b, c, d in idx2])
+    assert np.abs(got2 - ref2).max() <= 1e-12 * np.abs(ref2).max()
+
+
+def test_f_transform(q, ctx):
+    s = _f_sys()
+    _check(q, ctx, s, 1e-10)
