@@ -89,6 +89,7 @@ def lib():
         L.orc_norm_coefs.argtypes = [bp, dp]
         L.orc_prim_eri_cart.restype = ctypes.c_double
         L.orc_prim_eri_cart.argtypes = [ctypes.c_double, dp, ctypes.c_int] * 4
+        L.orc_prim_eri3_cart.argtypes = [ctypes.c_double, dp, ctypes.c_int] * 4 + [dp]
         L.orc_eri.restype = ctypes.c_double
         L.orc_eri.argtypes = [bp, ctypes.c_int, ctypes.c_int, bp, ctypes.c_int, ctypes.c_int]
         L.orc_eri_tensor.argtypes = [bp, bp, bp, bp, dp]
@@ -168,6 +169,19 @@ def prim_eri_cart(a, A, ca, b, B, cb, c, C, cc, d, D, cd) -> float:
     v = lib().orc_prim_eri_cart(*call)
     del keep
     return v
+
+
+def prim_eri3_cart(a, A, ca, b, B, cb, c, C, cc, d, D, cd) -> np.ndarray:
+    """[ab| r_K r_L / r^3 |cd] over unnormalized Cartesian primitives (codes as
+    prim_eri_cart), as a 3 x 3 array [K][L], McMurchie-Davidson form."""
+    keep, call = [], []
+    for e, X, k in ((a, A, ca), (b, B, cb), (c, C, cc), (d, D, cd)):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        keep.append(X)
+        call += [float(e), _dp(X), int(k)]
+    out = np.zeros(9)
+    lib().orc_prim_eri3_cart(*call, _dp(out))
+    return out.reshape(3, 3)
 
 
 def eri3(A, mu, B, nu, C, ka, D, la) -> np.ndarray:

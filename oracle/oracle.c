@@ -92,13 +92,6 @@ static int carts_valid(const orc_basis *b)
     return 1;
 }
 
-static int has_p(const orc_basis *b)
-{
-    for (int f = 0; b && f < b->nfunc; ++f)
-        if (cart_of(b, f)) return 1;
-    return 0;
-}
-
 /* Cartesian exponents of a function code: 0 = s; 1, 2, 3 = p_x, p_y, p_z;
  * 4 .. 9 = d_xx, d_yy, d_zz, d_xy, d_xz, d_yz; 10 .. 19 = f_xxx, f_yyy, f_zzz,
  * f_xxy, f_xxz, f_xyy, f_yyz, f_xzz, f_yzz, f_xyz. */
@@ -315,6 +308,151 @@ static void prim_eri3(double a, const double *A, double b, const double *B, doub
             out[K * 3 + L] = pre * ((K == L ? F1 : 0.0) + 2.0 * rho * R[K] * R[L] * (F1 - F2));
 }
 
+/* Gauge-kernel integrals over unnormalized Cartesian Gaussians,
+ * out[K * 3 + L] = [ab| r12_K r12_L / r12^3 |cd], in McMurchie-Davidson form
+ * (a different method from the Obara-Saika recursion of the Coulomb
+ * integrals; the two meet in the trace, sum_K [ab|KK|cd] = [ab|cd]).
+ * Per direction the product of a pair's two functions is a sum of Hermite
+ * Gaussians with the coefficients E^{ij}_t of the recursion
+ *   E^{i+1,j}_t = E^{ij}_{t-1} / (2p) + (P - A) E^{ij}_t + (t + 1) E^{ij}_{t+1}
+ * (likewise j with P - B), E^{00}_0 = 1.  For Hermite Gaussians of orders t
+ * at P and u at Q the integral is (-1)^{|u|} times the derivative of orders
+ * t + u, with respect to X = P - Q, of the kernel of two s distributions
+ * (prim_eri3)
+ *   W_KL(X) = pre (delta_KL F1(rho X^2) + 2 rho X_K X_L (F1 - F2)(rho X^2)).
+ * The derivatives of F_k(rho X^2) come from the Hermite recursion
+ * R^{(n)}_{t+1,u,v} = t R^{(n+1)}_{t-1,u,v} + X_x R^{(n+1)}_{t,u,v} (likewise
+ * u, v) with R^{(n)}_{000} = (-2 rho)^n F_{k+n}, and those of X_K X_L g by
+ * the Leibniz rule. */
+#define GMAXL 12 /* highest total Hermite order (four f functions) */
+#define GDIM (GMAXL + 1)
+
+static void herm_E_table(double PA, double PB, double p, double E[4][4][7])
+{
+    memset(E, 0, sizeof(double) * 4 * 4 * 7);
+    E[0][0][0] = 1.0;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            if (i == 0 && j == 0) continue;
+            /* raise i from (i - 1, j) when i > 0, else j from (i, j - 1) */
+            const double(*src)[7] = i > 0 ? &E[i - 1][j] : &E[i][j - 1];
+            const double X = i > 0 ? PA : PB;
+            for (int t = 0; t < 7; ++t) {
+                double v = X * (*src)[t];
+                if (t + 1 < 7) v += (t + 1) * (*src)[t + 1];
+                if (t > 0) v += (*src)[t - 1] / (2.0 * p);
+                E[i][j][t] = v;
+            }
+        }
+}
+
+/* R^{(0)}_{tuv} for t + u + v <= L of F_k(rho X^2), out[(t * GDIM + u) * GDIM + v]. */
+static void herm_R_table(int k, double rho, const double X[3], double T, int L, double *out)
+{
+    double *R = (double *)calloc((size_t)(L + 1) * GDIM * GDIM * GDIM, sizeof(double));
+#define RI(n, t, u, v) R[(((size_t)(n) * GDIM + (t)) * GDIM + (u)) * GDIM + (v)]
+    for (int n = 0; n <= L; ++n) RI(n, 0, 0, 0) = pow(-2.0 * rho, n) * orc_boys(k + n, T);
+    for (int n = L - 1; n >= 0; --n)
+        for (int t = 0; t <= L - n; ++t)
+            for (int u = 0; t + u <= L - n; ++u)
+                for (int v = 0; t + u + v <= L - n; ++v) {
+                    if (t > 0)
+                        RI(n, t, u, v) = (t > 1 ? (t - 1) * RI(n + 1, t - 2, u, v) : 0.0) +
+                                         X[0] * RI(n + 1, t - 1, u, v);
+                    else if (u > 0)
+                        RI(n, t, u, v) = (u > 1 ? (u - 1) * RI(n + 1, t, u - 2, v) : 0.0) +
+                                         X[1] * RI(n + 1, t, u - 1, v);
+                    else if (v > 0)
+                        RI(n, t, u, v) = (v > 1 ? (v - 1) * RI(n + 1, t, u, v - 2) : 0.0) +
+                                         X[2] * RI(n + 1, t, u, v - 1);
+                }
+    for (int t = 0; t <= L; ++t)
+        for (int u = 0; t + u <= L; ++u)
+            for (int v = 0; t + u + v <= L; ++v) out[(t * GDIM + u) * GDIM + v] = RI(0, t, u, v);
+#undef RI
+    free(R);
+}
+
+void orc_prim_eri3_cart(double a, const double *A, int ca, double b, const double *B, int cb,
+                        double c, const double *C, int cc, double d, const double *D, int cd,
+                        double out[9])
+{
+    int la[3], lb[3], lc[3], ld[3];
+    cart_powers(ca, la);
+    cart_powers(cb, lb);
+    cart_powers(cc, lc);
+    cart_powers(cd, ld);
+    const double p = a + b, q = c + d, rho = p * q / (p + q);
+    double X[3], Eb[3][4][4][7], Ek[3][4][4][7], rab2 = 0, rcd2 = 0, x2 = 0;
+    for (int k = 0; k < 3; ++k) {
+        const double P = (a * A[k] + b * B[k]) / p, Q = (c * C[k] + d * D[k]) / q;
+        herm_E_table(P - A[k], P - B[k], p, Eb[k]);
+        herm_E_table(Q - C[k], Q - D[k], q, Ek[k]);
+        X[k] = P - Q;
+        x2 += X[k] * X[k];
+        rab2 += (A[k] - B[k]) * (A[k] - B[k]);
+        rcd2 += (C[k] - D[k]) * (C[k] - D[k]);
+    }
+    const double pre = 2.0 * pow(M_PI, 2.5) / (p * q * sqrt(p + q)) * exp(-a * b / p * rab2) *
+                       exp(-c * d / q * rcd2);
+    int L = 0;
+    for (int k = 0; k < 3; ++k) L += la[k] + lb[k] + lc[k] + ld[k];
+    const size_t nr = (size_t)GDIM * GDIM * GDIM;
+    double *R1 = (double *)calloc(nr, sizeof(double)), *G = (double *)calloc(nr, sizeof(double));
+    herm_R_table(1, rho, X, rho * x2, L, R1);
+    herm_R_table(2, rho, X, rho * x2, L, G);
+    for (size_t i = 0; i < nr; ++i) G[i] = R1[i] - G[i]; /* derivatives of F1 - F2 */
+#define AT(arr, t, u, v) ((t) < 0 || (u) < 0 || (v) < 0 ? 0.0 : (arr)[((t) * GDIM + (u)) * GDIM + (v)])
+    for (int K = 0; K < 3; ++K)
+        for (int Lc = 0; Lc < 3; ++Lc) {
+            double sum = 0.0;
+            for (int t0 = 0; t0 <= la[0] + lb[0]; ++t0)
+                for (int t1 = 0; t1 <= la[1] + lb[1]; ++t1)
+                    for (int t2 = 0; t2 <= la[2] + lb[2]; ++t2) {
+                        const double eb = Eb[0][la[0]][lb[0]][t0] * Eb[1][la[1]][lb[1]][t1] *
+                                          Eb[2][la[2]][lb[2]][t2];
+                        if (eb == 0.0) continue;
+                        for (int u0 = 0; u0 <= lc[0] + ld[0]; ++u0)
+                            for (int u1 = 0; u1 <= lc[1] + ld[1]; ++u1)
+                                for (int u2 = 0; u2 <= lc[2] + ld[2]; ++u2) {
+                                    const double ek = Ek[0][lc[0]][ld[0]][u0] *
+                                                      Ek[1][lc[1]][ld[1]][u1] *
+                                                      Ek[2][lc[2]][ld[2]][u2];
+                                    if (ek == 0.0) continue;
+                                    const int n[3] = {t0 + u0, t1 + u1, t2 + u2};
+                                    const double sg = ((u0 + u1 + u2) & 1) ? -1.0 : 1.0;
+                                    /* derivative of orders n of delta_KL F1 + 2 rho X_K X_L g */
+                                    double w = K == Lc ? AT(R1, n[0], n[1], n[2]) : 0.0;
+                                    int m1[3] = {n[0], n[1], n[2]}, m2[3] = {n[0], n[1], n[2]},
+                                        m12[3] = {n[0], n[1], n[2]};
+                                    double lz;
+                                    if (K != Lc) {
+                                        m1[K] -= 1;
+                                        m2[Lc] -= 1;
+                                        m12[K] -= 1;
+                                        m12[Lc] -= 1;
+                                        lz = X[K] * X[Lc] * AT(G, n[0], n[1], n[2]) +
+                                             n[K] * X[Lc] * AT(G, m1[0], m1[1], m1[2]) +
+                                             n[Lc] * X[K] * AT(G, m2[0], m2[1], m2[2]) +
+                                             n[K] * n[Lc] * AT(G, m12[0], m12[1], m12[2]);
+                                    } else {
+                                        m1[K] -= 1;
+                                        m2[K] -= 2;
+                                        lz = X[K] * X[K] * AT(G, n[0], n[1], n[2]) +
+                                             2.0 * n[K] * X[K] * AT(G, m1[0], m1[1], m1[2]) +
+                                             n[K] * (n[K] - 1) * AT(G, m2[0], m2[1], m2[2]);
+                                    }
+                                    w += 2.0 * rho * lz;
+                                    sum += sg * eb * ek * w;
+                                }
+                    }
+            out[K * 3 + Lc] = pre * sum;
+        }
+#undef AT
+    free(R1);
+    free(G);
+}
+
 /* Contracted ERI with per-basis normalized coefficient arrays; s-type
  * quartets take the closed form, quartets with a p function the recursion. */
 static double eri4(const orc_basis *A, const double *nA, const int64_t *oA, int i,
@@ -343,21 +481,30 @@ static double eri4(const orc_basis *A, const double *nA, const int64_t *oA, int 
     return s;
 }
 
-/* Contracted r12 r12^T / r12^3 integrals, out[K * 3 + L]. */
+/* Contracted r12 r12^T / r12^3 integrals, out[K * 3 + L]; s-type quartets
+ * take the closed form, quartets with a Cartesian function the Hermite form. */
 static void eri4_3(const orc_basis *A, const double *nA, const int64_t *oA, int i,
                    const orc_basis *B, const double *nB, const int64_t *oB, int j,
                    const orc_basis *C, const double *nC, const int64_t *oC, int k,
                    const orc_basis *D, const double *nD, const int64_t *oD, int l, double out[9])
 {
+    int ca = cart_of(A, i), cb = cart_of(B, j), cc = cart_of(C, k), cd = cart_of(D, l);
+    int ang = ca || cb || cc || cd;
     for (int c = 0; c < 9; ++c) out[c] = 0.0;
     for (int64_t pi = oA[i]; pi < oA[i + 1]; ++pi)
         for (int64_t pj = oB[j]; pj < oB[j + 1]; ++pj)
             for (int64_t pk = oC[k]; pk < oC[k + 1]; ++pk)
                 for (int64_t pl = oD[l]; pl < oD[l + 1]; ++pl) {
                     double t[9], w = nA[pi] * nB[pj] * nC[pk] * nD[pl];
-                    prim_eri3(A->exps[pi], A->centers + 3 * i, B->exps[pj], B->centers + 3 * j,
-                              C->exps[pk], C->centers + 3 * k, D->exps[pl], D->centers + 3 * l,
-                              t);
+                    if (ang)
+                        orc_prim_eri3_cart(A->exps[pi], A->centers + 3 * i, ca, B->exps[pj],
+                                           B->centers + 3 * j, cb, C->exps[pk],
+                                           C->centers + 3 * k, cc, D->exps[pl],
+                                           D->centers + 3 * l, cd, t);
+                    else
+                        prim_eri3(A->exps[pi], A->centers + 3 * i, B->exps[pj],
+                                  B->centers + 3 * j, C->exps[pk], C->centers + 3 * k,
+                                  D->exps[pl], D->centers + 3 * l, t);
                     for (int c = 0; c < 9; ++c) out[c] += w * t[c];
                 }
 }
@@ -689,7 +836,6 @@ static int def_impl(const orc_basis *L, const orc_basis *S, const double *CL, co
     if (NF > 64 || m > 64 || n <= 0) return -1;
     if (ham_gauge(ham) && NF > 32) return -1;
     if (!carts_valid(L) || (with_S && !carts_valid(S))) return -1;
-    if (ham_gauge(ham) && (has_p(L) || (with_S && has_p(S)))) return -1;
 
     /* combined scalar basis */
     nbasis bl = nb_make(L), bs;
@@ -993,7 +1139,6 @@ static int direct_impl(const orc_basis *L, const orc_basis *S, const double *CL,
     if (n <= 0 || tau < 0 || ham < 0 || ham > 5) return -1;
     if (general && Vq) return -1;
     if (!carts_valid(L) || (with_S && !carts_valid(S))) return -1;
-    if (ham_gauge(ham) && (has_p(L) || (with_S && has_p(S)))) return -1;
     int NL = L->nfunc, NS = with_S ? S->nfunc : 0, m = general ? n : 2 * n;
     size_t m2 = (size_t)m * m;
     /* spinor pairs (c, d) of the first half: all m^2, or (cols: first-half

@@ -73,6 +73,13 @@ void orc_norm_coefs(const orc_basis *b, double *out);
 double orc_prim_eri_cart(double a, const double *A, int ca, double b, const double *B, int cb,
                          double c, const double *C, int cc, double d, const double *D, int cd);
 
+/* Primitive integrals of the kernel r12_K r12_L / r12^3 over unnormalized
+ * Cartesian Gaussians (arguments as orc_prim_eri_cart), out[K * 3 + L],
+ * McMurchie-Davidson form. */
+void orc_prim_eri3_cart(double a, const double *A, int ca, double b, const double *B, int cb,
+                        double c, const double *C, int cc, double d, const double *D, int cd,
+                        double out[9]);
+
 /* Contracted ERI (mu nu | ka la) in chemists' notation; mu, nu index basis A,
  * ka, la index basis B. */
 double orc_eri(const orc_basis *A, int mu, int nu, const orc_basis *B, int ka, int la);

@@ -160,10 +160,14 @@ def test_schwarz_inequality_with_p():
     np.testing.assert_allclose(oracle.schwarz(sy.L), Q, rtol=1e-13, atol=0)
 
 
-def test_gauge_hams_refuse_p_functions():
-    sy = wl.sp_cluster(seed=9, n_atoms=2, edge=3.0, nprim=(1, 1), n=2, ham="DC")
-    with pytest.raises(ValueError):
-        oracle.transform_direct(sy.L, sy.S, sy.CL, sy.CS, ham="DCB")
+def test_gauge_hams_over_p_functions_two_routes():
+    # the gauge integrals over p functions (pinned in test_oracle_gauge_cart.py)
+    # through the unscreened definition route (literal four-spinor operators)
+    # and the direct quaternion route agree
+    sy = wl.sp_cluster(seed=9, n_atoms=2, edge=3.0, nprim=(1, 1), n=2, ham="DCB")
+    Gd, _ = oracle.transform_def(sy.L, sy.S, sy.CL, sy.CS, ham="DCB")
+    Go, so = oracle.transform_direct(sy.L, sy.S, sy.CL, sy.CS, ham="DCB")
+    assert np.abs(Gd - Go).max() <= 1e-12 * np.abs(Go).max()
 
 
 # --------------------------------------------------------------------------
