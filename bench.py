@@ -75,6 +75,11 @@ def parse():
                     help="serving: precisions to serve the stream in, one run each "
                          "(mixed: tiers 1e-6 / 1e-9 with the G-bound rule)")
     ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--serving-sizes", default="reduced", choices=["reduced", "full"],
+                    help="serving: request sizes (reduced: 10-40 atoms, N_L 40-160, n 8-32, "
+                         "the default leg; full: the recipe's 10-80 atoms, N_L 100-800, "
+                         "n 16-128, where one GPU is saturated and a short stream is "
+                         "measured with --requests)")
     ap.add_argument("--schwarz-rows", action="store_true",
                     help="transform: plans with QDCB_PLAN_SCHWARZ_ROWS (plain Schwarz row "
                          "order instead of the default primitive bands)")
@@ -474,13 +479,22 @@ def main_mixed(args):
                    "n_mo": n, "ham": sysm.ham, "tau": sysm.tau}}), flush=True)
 
 
+SERVING_SIZES = {
+    # the stream recipe's ranges, and the reduced ranges of the default leg
+    "full": {"atoms": (10, 80), "nl": (100, 800), "n_mo": (16, 128)},
+    "reduced": {"atoms": (10, 40), "nl": (40, 160), "n_mo": (8, 32)},
+}
+
+
 def serving_run(args, prec):
-    """One run of the request stream (256 requests, mean gap 20 ms, reduced
-    sizes) in one precision; eight requests re-run alone and compared bitwise."""
+    """One run of the request stream (args.requests requests, mean gap 20 ms,
+    the reduced or the full sizes) in one precision; eight requests re-run
+    alone and compared bitwise."""
     import torch
     from paper_2606_04316_amd import qdcb, serving
+    sz = SERVING_SIZES[args.serving_sizes]
     reqs = serving.request_stream(args.requests, seed=5, mean_gap_s=0.02, pool=12,
-                                  atoms=(10, 40), nl=(40, 160), n_mo=(8, 32),
+                                  atoms=sz["atoms"], nl=sz["nl"], n_mo=sz["n_mo"],
                                   radius_scale=20.0)
     pf = 0 if args.serving_rows == "bands" else qdcb.PLAN_SCHWARZ_ROWS
     # the eight requests re-run alone below (every len/8-th by arrival) are the
@@ -503,11 +517,12 @@ def serving_run(args, prec):
         same += (r.error is None and
                  alone(solo, 0)["digest"] == r.result["digest"])
     alone.drain()
-    summ.update({"stream": {"arrivals": "Poisson, mean gap 20 ms", "atoms": [10, 40],
-                            "N_L": [40, 160], "N_S": "2 N_L", "n_mo": [8, 32],
-                            "contraction_depths": [1, 6], "ham": "DC or DCG, 50/50",
-                            "tau": 1e-10, "pool": 12,
-                            "note": "reduced from 10-80 atoms, N_L 100-800, n_mo 16-128"},
+    summ.update({"stream": {"arrivals": "Poisson, mean gap 20 ms", "requests": len(reqs),
+                            "atoms": list(sz["atoms"]), "N_L": list(sz["nl"]), "N_S": "2 N_L",
+                            "n_mo": list(sz["n_mo"]), "contraction_depths": [1, 6],
+                            "ham": "DC or DCG, 50/50", "tau": 1e-10, "pool": 12,
+                            "note": ("the recipe's sizes" if args.serving_sizes == "full" else
+                                     "reduced from 10-80 atoms, N_L 100-800, n_mo 16-128")},
                  "slots": args.slots, "max_concurrency": srv.max_concurrency,
                  "row_order": "primitive bands" if args.serving_rows == "bands" else "Schwarz",
                  "peak_reserved_GB": srv.peak_in_use / 2 ** 30,

@@ -125,10 +125,9 @@ qdcb_status qdcb_basis_create(qdcb_ctx *ctx, int32_t nfunc, const double *center
  * f).  Integrals with p functions are generated in McMurchie-Davidson form,
  * and bases with a d or f function take its general form for every
  * integral; Schwarz factors are per function pair, and primitive-pair
- * screening is not applied to pairs with a p, d or f function.  Plans over such bases support QDCB_HAM_LL,
- * QDCB_HAM_DC and QDCB_HAM_DCG (QDCB_HAM_DCB returns QDCB_E_UNSUPPORTED: its
- * gauge integrals take s functions only).  QDCB_E_INVALID for a code outside
- * [0, 19]. */
+ * screening is not applied to pairs with a p, d or f function.  Plans over
+ * such bases support every Hamiltonian (QDCB_HAM_DCB: the gauge integrals in
+ * the same general form).  QDCB_E_INVALID for a code outside [0, 19]. */
 qdcb_status qdcb_basis_create_cart(qdcb_ctx *ctx, int32_t nfunc, const double *centers,
                                    const int32_t *nprim, const double *exps,
                                    const double *coefs, const int32_t *cart,

@@ -86,9 +86,10 @@ constexpr int BOYS_LD = 10;
 // Columns of the table of the Cartesian (s/p) integral tiles: F_0 .. F_11, so
 // that F_0 .. F_4 each take eight Taylor terms
 constexpr int BOYS_LDC = 12;
-// Columns of the table of the general (s .. f) tiles: F_0 .. F_19 (F_0 .. F_12
-// with eight Taylor terms each)
-constexpr int BOYS_LDG = 20;
+// Columns of the table of the general (s .. f) tiles: F_0 .. F_21 (F_0 .. F_14
+// with eight Taylor terms each: Boys orders to 12 for the Coulomb kernel, to
+// 14 for the gauge kernel)
+constexpr int BOYS_LDG = 22;
 
 // 1/sqrt(x) for finite x > 0: the hardware estimate y and one second-order
 // correction from the binomial series, y (1 + e/2 + 3 e^2/8), e = 1 - x y^2.
@@ -443,6 +444,70 @@ __device__ __forceinline__ double herm_sum(const double Px[TS + 1], const double
     v = fma(Q[m], w, v);
   }
   return v;
+}
+
+// Gauge kernel r_K r_L / r^3 in the same form.  For two s distributions the
+// gauge (or Breit) tile element is A(X^2) delta_KL + B(X^2) X_K X_L with
+// A = g_1 / 2 + diag g_0 (diag = -1/2 gauge, +1/2 Breit) and
+// B = rho (g_1 - g_2); the derivative of orders (T, U, V) of a radial
+// function F(X^2) is sum h_T^a h_U^b h_V^c 2^n F^{(n)} (n = T+U+V-a-b-c), so
+// A and B enter through D_A[n] = (-2 rho)^n (g_{n+1} / 2 + diag g_n) and
+// D_B[n] = rho (-2 rho)^n (g_{n+1} - g_{n+2}), and the factor X_K X_L by the
+// Leibniz rule, d^T (x f) = x d^T f + T d^{T-1} f and
+// d^T (x^2 f) = x^2 d^T f + 2T x d^{T-1} f + T(T-1) d^{T-2} f.  Per direction
+// three polynomials: P0 (no factor), P1 (factor x), P2 (factor x^2).
+template <int TB, int TK>
+__device__ __forceinline__ void herm_dir3(const double Eb[TB + 1], const double Ek[TK + 1],
+                                          double x, double P0[TB + TK + 1],
+                                          double P1[TB + TK + 1], double P2[TB + TK + 1]) {
+  constexpr int TS = TB + TK;
+  double H[TS + 1];
+#pragma unroll
+  for (int t = 0; t <= TS; ++t) H[t] = 0.0;
+#pragma unroll
+  for (int t = 0; t <= TB; ++t)
+#pragma unroll
+    for (int u = 0; u <= TK; ++u) H[t + u] = fma(Eb[t], (u & 1) ? -Ek[u] : Ek[u], H[t + u]);
+  double xp[TS + 3];
+  xp[0] = 1.0;
+#pragma unroll
+  for (int k = 1; k <= TS + 2; ++k) xp[k] = xp[k - 1] * x;
+#pragma unroll
+  for (int q = 0; q <= TS; ++q) P0[q] = P1[q] = P2[q] = 0.0;
+#pragma unroll
+  for (int t = 0; t <= TS; ++t) {
+    // d^t of f, x f, x^2 f: h_t^a at order t - a (times 1, x, x^2), h_{t-1}^a
+    // at order t - 1 - a (times t for x f, 2t x for x^2 f), h_{t-2}^a at
+    // order t - 2 - a (times t(t - 1) for x^2 f)
+    double c = 1.0;
+#pragma unroll
+    for (int a = 0; 2 * a <= t; ++a) {
+      const double hc = H[t] * c;
+      P0[t - a] = fma(hc, xp[t - 2 * a], P0[t - a]);
+      P1[t - a] = fma(hc, xp[t - 2 * a + 1], P1[t - a]);
+      P2[t - a] = fma(hc, xp[t - 2 * a + 2], P2[t - a]);
+      c = c * (double)((t - 2 * a) * (t - 2 * a - 1)) / (double)(2 * (a + 1));
+    }
+    if (t >= 1) {
+      double c1 = 1.0;
+#pragma unroll
+      for (int a = 0; 2 * a <= t - 1; ++a) {
+        const double hc = H[t] * c1 * (double)t;
+        P1[t - 1 - a] = fma(hc, xp[t - 1 - 2 * a], P1[t - 1 - a]);
+        P2[t - 1 - a] = fma(2.0 * hc, xp[t - 2 * a], P2[t - 1 - a]);
+        c1 = c1 * (double)((t - 1 - 2 * a) * (t - 2 - 2 * a)) / (double)(2 * (a + 1));
+      }
+    }
+    if (t >= 2) {
+      double c2 = 1.0;
+#pragma unroll
+      for (int a = 0; 2 * a <= t - 2; ++a) {
+        const double hc = H[t] * c2 * (double)(t * (t - 1));
+        P2[t - 2 - a] = fma(hc, xp[t - 2 - 2 * a], P2[t - 2 - a]);
+        c2 = c2 * (double)((t - 2 - 2 * a) * (t - 3 - 2 * a)) / (double)(2 * (a + 1));
+      }
+    }
+  }
 }
 
 // g_n = (2/sqrt(pi)) sqrt(rho) F_n(T), n < NG, without a table: below T = 15

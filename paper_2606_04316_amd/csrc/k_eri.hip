@@ -759,6 +759,168 @@ __global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles_queue_gen(EriTileArgs
   eri_count(a, kept);
 }
 
+// ---- gauge (or Breit) tiles over Cartesian bases (p, d, f): six components
+// (xx, xy, xz, yy, yz, zz) of A delta_KL + B X_K X_L in the general form
+// (common.h, herm_dir3), T bounding the Hermite orders of the tile's bra
+// pairs and of the ket pair.
+template <int T>
+__device__ __forceinline__ void gauge_gen_row_pair(const EriTileArgs &A, const double *tab,
+                                                   int64_t kf0, int64_t kf1, int64_t b0,
+                                                   int64_t b1, int bcode, int kcode,
+                                                   double v[6]) {
+  constexpr int TS = 2 * T;
+  const int fa = code_f(bcode), fb = code_g(bcode), fc = code_f(kcode), fd = code_g(kcode);
+  const double diag = A.gauge_diag;
+  const cdptr kip = as_const(A.pp.ip), kx = as_const(A.pp.x), ky = as_const(A.pp.y),
+              kz = as_const(A.pp.z), ke = as_const(A.pp.e), kax = as_const(A.pp.ax),
+              kay = as_const(A.pp.ay), kaz = as_const(A.pp.az), kbx = as_const(A.pp.bx),
+              kby = as_const(A.pp.by), kbz = as_const(A.pp.bz);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) v[c] = 0.0;
+  for (int64_t b = b0; b < b1; ++b) {
+    const double ip = A.pp.ip[b], px = A.pp.x[b], py = A.pp.y[b], pz = A.pp.z[b];
+    const double hb = 0.5 * ip, eb = A.pp.e[b];
+    double Ebx[T + 1], Eby[T + 1], Ebz[T + 1];
+    herm_1d<T>(cart_pow(fa, 0), cart_pow(fb, 0), A.pp.ax[b], A.pp.bx[b], hb, Ebx);
+    herm_1d<T>(cart_pow(fa, 1), cart_pow(fb, 1), A.pp.ay[b], A.pp.by[b], hb, Eby);
+    herm_1d<T>(cart_pow(fa, 2), cart_pow(fb, 2), A.pp.az[b], A.pp.bz[b], hb, Ebz);
+    for (int64_t k = kf0; k < kf1; ++k) {
+      const double iq = kip[k], hk = 0.5 * iq;
+      const double X0 = px - kx[k], X1 = py - ky[k], X2 = pz - kz[k];
+      const double sr = rsqrt_pos(ip + iq);
+      const double rho = sr * sr;
+      const double r2 = X0 * X0 + X1 * X1 + X2 * X2;
+      double g[TS + 3];
+      boys_g_tab_n<TS + 3, BOYS_LDG>(tab, r2 * rho, r2, sr, g);
+      double DA[TS + 1], DB[TS + 1];
+      const double m2r = -2.0 * rho;
+      double f = 1.0;
+#pragma unroll
+      for (int n = 0; n <= TS; ++n) {
+        DA[n] = f * fma(0.5, g[n + 1], diag * g[n]);
+        DB[n] = f * rho * (g[n + 1] - g[n + 2]);
+        f *= m2r;
+      }
+      double Ek[T + 1];
+      double P0x[TS + 1], P1x[TS + 1], P2x[TS + 1];
+      double P0y[TS + 1], P1y[TS + 1], P2y[TS + 1];
+      double P0z[TS + 1], P1z[TS + 1], P2z[TS + 1];
+      herm_1d<T>(cart_pow(fc, 0), cart_pow(fd, 0), kax[k], kbx[k], hk, Ek);
+      herm_dir3<T, T>(Ebx, Ek, X0, P0x, P1x, P2x);
+      herm_1d<T>(cart_pow(fc, 1), cart_pow(fd, 1), kay[k], kby[k], hk, Ek);
+      herm_dir3<T, T>(Eby, Ek, X1, P0y, P1y, P2y);
+      herm_1d<T>(cart_pow(fc, 2), cart_pow(fd, 2), kaz[k], kbz[k], hk, Ek);
+      herm_dir3<T, T>(Ebz, Ek, X2, P0z, P1z, P2z);
+      const double w = eb * ke[k];
+      const double sa = herm_sum<TS>(P0x, P0y, P0z, DA);
+      v[0] = fma(w, herm_sum<TS>(P2x, P0y, P0z, DB) + sa, v[0]);
+      v[1] = fma(w, herm_sum<TS>(P1x, P1y, P0z, DB), v[1]);
+      v[2] = fma(w, herm_sum<TS>(P1x, P0y, P1z, DB), v[2]);
+      v[3] = fma(w, herm_sum<TS>(P0x, P2y, P0z, DB) + sa, v[3]);
+      v[4] = fma(w, herm_sum<TS>(P0x, P1y, P1z, DB), v[4]);
+      v[5] = fma(w, herm_sum<TS>(P0x, P0y, P2z, DB) + sa, v[5]);
+    }
+  }
+}
+
+// the d- and f-sized forms in functions of their own: their register
+// pressure (and spills) stays out of the p-sized form's code
+template <int T>
+__device__ __attribute__((noinline)) void gauge_gen_row_pair_call(const EriTileArgs &A,
+                                                                  const double *tab,
+                                                                  int64_t kf0, int64_t kf1,
+                                                                  int64_t b0, int64_t b1,
+                                                                  int bcode, int kcode,
+                                                                  double v[6]) {
+  gauge_gen_row_pair<T>(A, tab, kf0, kf1, b0, b1, bcode, kcode, v);
+}
+
+__device__ __forceinline__ void eri_gauge_gen_one_tile(const EriTileArgs &a, const double *tab,
+                                                       int64_t slot, long long kept[4]) {
+  const int kt = a.tasks[slot];
+  const int bt = a.task_bra[slot];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double *out, *outT = nullptr;
+  constexpr int64_t SL = 6 * (int64_t)TILE * TILE;
+  if (a.uslot_bk) {
+    const int32_t s1 = a.uslot_bk[slot], s2 = a.uslot_kb[slot];
+    out = s1 >= 0 ? a.panel + (int64_t)s1 * SL : nullptr;
+    outT = s2 >= 0 ? a.panel + (int64_t)s2 * SL : nullptr;
+  } else {
+    out = a.panel + (slot - a.slot0) * SL;
+  }
+  const int64_t brow = (int64_t)bt * TILE + lane;
+  const double qb = a.Q[brow];
+  const double db = a.Dmax[brow];
+  const int cb = a.cls[brow];
+  const int bcode = a.code[brow];
+  const int64_t bfirst = a.row_first[brow], blast = a.row_first[brow + 1];
+  int tb = gen_bucket(bcode);
+  for (int o = 32; o > 0; o >>= 1) tb = max(tb, __shfl_xor(tb, o, 64));
+  tb = __builtin_amdgcn_readfirstlane(tb);
+  for (int i = 0; i < TILE / ERI_WAVES; ++i) {
+    const int j = w + ERI_WAVES * i;
+    const int64_t krow = (int64_t)kt * TILE + j;
+    const double qk = a.Q[krow], dk = a.Dmax[krow];
+    const int ck = a.cls[krow];
+    const int kcode = __builtin_amdgcn_readfirstlane(a.code[krow]);
+    const int64_t kf0 = a.row_first[krow], kf1 = a.row_first[krow + 1];
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const bool keep_bk = out && (qb * qk) * dk >= a.tau;
+    const bool keep_kb = outT && (qk * qb) * db >= a.tau;
+    if (keep_bk || keep_kb) {
+      const int t = max(tb, gen_bucket(kcode));
+      if (t == 2)
+        gauge_gen_row_pair<2>(a, tab, kf0, kf1, bfirst, blast, bcode, kcode, v);
+      else if (t == 4)
+        gauge_gen_row_pair_call<4>(a, tab, kf0, kf1, bfirst, blast, bcode, kcode, v);
+      else
+        gauge_gen_row_pair_call<6>(a, tab, kf0, kf1, bfirst, blast, bcode, kcode, v);
+      if (cb >= 0 && ck >= 0) {
+        if (keep_bk) kept[cb * 2 + ck] += 1;
+        if (keep_kb) kept[ck * 2 + cb] += 1;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      if (out) out[c * TILE * TILE + j * TILE + lane] = keep_bk ? v[c] : 0.0;
+      if (outT) outT[c * TILE * TILE + lane * TILE + j] = keep_kb ? v[c] : 0.0;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(ERI_THREADS) k_eri_gauge_tiles_gen(EriTileArgs a) {
+  __shared__ double tab[BOYS_N * BOYS_LDG];
+  if (a.overflow && *a.overflow) return;  // uniform
+  if (a.d_total && (int64_t)blockIdx.x >= min(*a.d_total, a.cap)) return;  // uniform
+  for (int t = threadIdx.x; t < BOYS_N * BOYS_LDG; t += ERI_THREADS) tab[t] = a.boysg[t];
+  __syncthreads();
+  long long kept[4] = {0, 0, 0, 0};
+  eri_gauge_gen_one_tile(a, tab, a.slot0 + blockIdx.x, kept);
+  eri_count(a, kept);
+}
+
+// Persistent variant; same queue protocol as k_eri_tiles_queue.
+__global__ void __launch_bounds__(ERI_THREADS) k_eri_gauge_tiles_queue_gen(
+    EriTileArgs a, const int32_t *order, unsigned long long *qctr, int64_t n_host) {
+  __shared__ double tab[BOYS_N * BOYS_LDG];
+  __shared__ int64_t s_next;
+  if (a.overflow && *a.overflow) return;  // uniform
+  const int64_t n = a.d_total ? min(*a.d_total, a.cap) : n_host;
+  for (int t = threadIdx.x; t < BOYS_N * BOYS_LDG; t += ERI_THREADS) tab[t] = a.boysg[t];
+  long long kept[4] = {0, 0, 0, 0};
+  for (;;) {
+    __syncthreads();  // table staged; the previous s_next read by every thread
+    if (threadIdx.x == 0) s_next = (int64_t)atomicAdd(qctr, 1ull);
+    __syncthreads();
+    const int64_t i = s_next;
+    if (i >= n) break;  // uniform
+    eri_gauge_gen_one_tile(a, tab, order[i], kept);
+  }
+  eri_count(a, kept);
+}
+
 void launch_eri_tiles(const EriTileArgs &a, int64_t nslots, hipStream_t s) {
   if (nslots <= 0) return;
   if (a.boysg)
@@ -785,15 +947,23 @@ void launch_eri_tiles_queue(const EriTileArgs &a, const int32_t *order, unsigned
 
 void launch_eri_gauge_tiles(const EriTileArgs &a, int64_t nslots, hipStream_t s) {
   if (nslots <= 0) return;
-  hipLaunchKernelGGL(k_eri_tiles<true>, dim3((unsigned)nslots), dim3(ERI_THREADS), 0, s, a);
+  if (a.code)  // Cartesian bases: the general form
+    hipLaunchKernelGGL(k_eri_gauge_tiles_gen, dim3((unsigned)nslots), dim3(ERI_THREADS), 0, s,
+                       a);
+  else
+    hipLaunchKernelGGL(k_eri_tiles<true>, dim3((unsigned)nslots), dim3(ERI_THREADS), 0, s, a);
 }
 
 void launch_eri_gauge_tiles_queue(const EriTileArgs &a, const int32_t *order,
                                   unsigned long long *qctr, int64_t n_host, int nblocks,
                                   hipStream_t s) {
   if (nblocks <= 0) return;
-  hipLaunchKernelGGL(k_eri_tiles_queue<true>, dim3((unsigned)nblocks), dim3(ERI_THREADS), 0, s,
-                     a, order, qctr, n_host);
+  if (a.code)
+    hipLaunchKernelGGL(k_eri_gauge_tiles_queue_gen, dim3((unsigned)nblocks), dim3(ERI_THREADS),
+                       0, s, a, order, qctr, n_host);
+  else
+    hipLaunchKernelGGL(k_eri_tiles_queue<true>, dim3((unsigned)nblocks), dim3(ERI_THREADS), 0,
+                       s, a, order, qctr, n_host);
 }
 
 }  // namespace qdcb

@@ -439,8 +439,6 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
       const char *e = std::getenv("QDCB_TILE_ORDER");
       p.tile_order = !(e && e[0] == '0');
     }
-    if (p.cart && p.gauge)
-      fail(QDCB_E_UNSUPPORTED, "the gauge term takes s functions only");
     p.spinor = desc->flags & QDCB_PLAN_SPINOR;
     if (p.spinor) {  // pairs of spinors c <= d, two pairs per four-column group
       p.npair_s = p.n * (p.n + 1) / 2;
@@ -612,7 +610,8 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
     p.boys.upload(ctx, boys_table());
     if (p.gauge) p.boys3.upload(ctx, boys_table3());
     if (p.cart) p.boysc.upload(ctx, boys_table_cart());
-    if (p.gen) p.boysg.upload(ctx, boys_table_cart<BOYS_LDG>());
+    // general tiles: Coulomb tiles of d / f bases, gauge tiles of Cartesian bases
+    if (p.gen || (p.cart && p.gauge)) p.boysg.upload(ctx, boys_table_cart<BOYS_LDG>());
     trace.mark("tables");
     HIPC(hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking));
     trace.mark("stream");
@@ -666,9 +665,7 @@ qdcb_status qdcb_plan_estimate(const qdcb_basis *L, const qdcb_basis *S,
     double prims = (double)L->pair_first.back() + (S ? (double)S->pair_first.back() : 0.0);
     if (gaunt) prims += 2.0 * (double)L->first.back() * (double)S->first.back();
     const bool cart = L->has_p() || (S && S->has_p());
-    if (cart && desc->ham == QDCB_HAM_DCB)
-      fail(QDCB_E_UNSUPPORTED, "the gauge term takes s functions only");
-    double b = 2.0 * (cart ? 56.0 : 40.0) * prims;        // primitive-pair data (two orders)
+    double b = 2.0 * (cart ? 104.0 : 40.0) * prims;       // primitive-pair data (two orders)
     b += 88.0 * (PC + PG);                                // row metadata
     b += (desc->prec == QDCB_PREC_MIXED ? 20.0 : 16.0) *
          (PC * ldK + 3.0 * PG * ldK);                     // D~, V (and FP32 D~), all columns

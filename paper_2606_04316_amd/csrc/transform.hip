@@ -249,9 +249,12 @@ EriTileArgs eri_args(qdcb_plan &p, Space &sp, int64_t slot0, bool count, bool ga
   ea.boys3 = gauge ? p.boys3.p : nullptr;
   ea.code = p.cart ? (w ? sp.wcode.p : sp.code.p) : nullptr;
   ea.boysc = p.cart ? p.boysc.p : nullptr;
-  ea.boysg = p.gen ? p.boysg.p : nullptr;
-  if (p.gen && !ea.boysg) fail(QDCB_E_DEVICE, "general tiles without their table");
-  if (p.cart && (!ea.code || !ea.boysc || !sp.pp.pa.p || gauge))
+  // the general tiles: Coulomb tiles of bases with d or f functions, gauge
+  // tiles of every Cartesian basis
+  const bool general = p.gen || (p.cart && gauge);
+  ea.boysg = general ? p.boysg.p : nullptr;
+  if (general && !ea.boysg) fail(QDCB_E_DEVICE, "general tiles without their table");
+  if (p.cart && (!ea.code || !ea.boysc || !sp.pp.pa.p || !sp.pp.ax.p))
     fail(QDCB_E_DEVICE, "Cartesian tiles without their codes, table or pair data");
   ea.gauge_diag = breit ? 0.5 : -0.5;
   if (gauge && !ea.boys3) fail(QDCB_E_DEVICE, "gauge tiles without their table");

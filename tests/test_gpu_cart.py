@@ -7,8 +7,8 @@ Schwarz factors and single integrals (normwise 1e-13), kept contribution
 counts (exact) and the MO integrals of LL, DC and DCG transforms
 (max|G_gpu - G_oracle| <= 1e-12 max|G_oracle|), on systems whose pair spaces
 span several 64-pair tiles with a ragged last tile, under both integral
-schedules, with directed and unique tiles and in the primitive-band row order.  DCB plans with p functions
-are refused (the gauge integrals take s functions only), and so are codes beyond f.
+schedules, with directed and unique tiles and in the primitive-band row order.  Codes beyond f
+are refused (DCB plans over Cartesian bases: test_gpu_gauge_cart.py).
 """
 import numpy as np
 import pytest
@@ -117,12 +117,8 @@ def test_cart_p_in_one_basis_only(q, ctx):
     _check(q, ctx, s2, 1e-10)
 
 
-def test_cart_refuses_gauge(q, ctx):
+def test_cart_refuses_codes_beyond_f(q, ctx):
     s = _sys("DC", 0.0, n_atoms=2, n=2)
-    L, S = q.Basis(ctx, s.L), q.Basis(ctx, s.S)
-    with pytest.raises(q.QdcbError) as e:
-        q.Plan(ctx, L, S, "DCB", 2, 0.0)
-    assert e.value.status == -4
     with pytest.raises(q.QdcbError):
         q.Basis(ctx, wl.Basis(s.L.centers, s.L.nprim, s.L.exps, s.L.coefs,
                               np.full(s.L.nfunc, 20, np.int32)))

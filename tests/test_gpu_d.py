@@ -16,8 +16,8 @@ contribution counts (exact) and the MO integrals of LL, DC and DCG transforms
 spaces of several 64-pair tiles with a ragged last tile, under both integral
 schedules, with directed and unique tiles, in both row orders, with d
 functions in one basis or in both; two-spinor plans, the FP32 tier, the
-MO-driven variant and graph replays.  DCB plans with d functions are refused,
-and codes beyond f are refused at basis creation.
+MO-driven variant and graph replays.  Codes beyond f are refused at basis
+creation (DCB plans over Cartesian bases: test_gpu_gauge_cart.py).
 """
 import numpy as np
 import pytest
@@ -128,12 +128,8 @@ def test_d_schedules(q, ctx, eri_sched, flags):
            tune={"eri_sched": eri_sched, "fh_order": 0, "sq_tile": 64})
 
 
-def test_d_refuses_gauge_and_codes_beyond_f(q, ctx):
+def test_d_refuses_codes_beyond_f(q, ctx):
     s = _sys("DC", 0.0, n_atoms=2, n=2)
-    L, S = q.Basis(ctx, s.L), q.Basis(ctx, s.S)
-    with pytest.raises(q.QdcbError) as e:
-        q.Plan(ctx, L, S, "DCB", 2, 0.0)
-    assert e.value.status == -4
     with pytest.raises(q.QdcbError):
         q.Basis(ctx, wl.Basis(s.L.centers, s.L.nprim, s.L.exps, s.L.coefs,
                               np.full(s.L.nfunc, 20, np.int32)))
