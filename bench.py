@@ -504,7 +504,11 @@ def serving_run(args, prec):
     ex = serving.GpuExecutor(slots=args.slots, prec=prec, plan_flags=pf,
                              digest_ids=check_ids)
     budget = int(0.5 * torch.cuda.mem_get_info()[0])
-    srv = serving.Server(ex, ex.reserve, slots=args.slots, budget_bytes=budget)
+    def done(r):  # progress of long streams: one line per served request
+        if args.serving_sizes == "full":
+            print(f"request {r.rid} served ({r.latency_ms:.0f} ms)", file=sys.stderr, flush=True)
+
+    srv = serving.Server(ex, ex.reserve, slots=args.slots, budget_bytes=budget, on_done=done)
     out = srv.run(reqs)
     ex.drain()
     summ = serving.summarize(out)

@@ -47,9 +47,11 @@ class Server:
     """``executor(request, slot) -> result`` runs one request; ``reserve(request)``
     gives its device-memory reservation in bytes."""
 
-    def __init__(self, executor: Callable, reserve: Callable, slots: int, budget_bytes: int):
+    def __init__(self, executor: Callable, reserve: Callable, slots: int, budget_bytes: int,
+                 on_done: Optional[Callable] = None):
         if slots < 1:
             raise ValueError("need at least one slot")
+        self.on_done = on_done  # called with each request once it is served
         self.executor = executor
         self.reserve = reserve
         self.slots = slots
@@ -124,6 +126,8 @@ class Server:
                 self._free_slots.append(slot)
                 self._free_slots.sort()
                 self._lock.notify_all()
+            if self.on_done is not None:
+                self.on_done(r)
 
         def launch(batch):
             for r, slot in batch:
