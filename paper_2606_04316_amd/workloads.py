@@ -478,6 +478,7 @@ def config(name: str) -> System:
     ``chain40_sp`` the chain40 shape with p shells: per atom 4 s + 2 p shells in
                L (N_L = 400) and 8 s + 4 p shells in S (N_S = 800), K = 3, n = 64,
                DC, tau 1e-10.
+    ``chain40_sp_dcb`` ``chain40_sp`` with the whole Breit term (Gaunt + gauge).
     ``chain40_spd`` the chain40 shape with p and d shells: per atom 4 s + 1 p +
                1 Cartesian d shell in L (N_L = 520) and 8 s + 4 p shells in S
                (N_S = 800), K = 3, n = 64, DC, tau 1e-10.
@@ -502,6 +503,8 @@ def config(name: str) -> System:
         return sp_chain(seed=6)
     if name == "chain40_spd":
         return sp_chain(seed=6, l_p=1, l_d=1)
+    if name == "chain40_sp_dcb":
+        return sp_chain(seed=6, ham="DCB")
     if name == "cluster24":
         # the cluster recipe at 24 atoms (radius scaled by (24/60)^(1/3)), n = 64
         return cluster(seed=3, n_atoms=24, radius=20.0 * (24 / 60) ** (1 / 3), n=64)
