@@ -3,7 +3,7 @@
  *
  * The library implements the paper's AO-driven direct transformation
  * (Sec. 2.4): scalar AO two-electron integrals over contracted Cartesian
- * Gaussians (s and p functions; restricted-kinetic-balance gradient functions
+ * Gaussians (s, p, d and f functions; restricted-kinetic-balance gradient functions
  * for the small component, Eq. RKB) are generated on the GPU, filtered by the quaternion-density-
  * weighted Cauchy-Schwarz bound (Sec. 2.5, Eq. SchwarzDen), contracted with
  * quaternion MO-pair densities in the first half (Eq. firsthalf, Eqs. Den and

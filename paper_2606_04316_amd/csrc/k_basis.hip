@@ -159,7 +159,7 @@ void launch_schwarz(int64_t npairs, const int64_t *pair_first, PrimPairsC pp,
 // primitive integral obeys |[i|k]| <= sqrt([i|i][k|k]), so the dropped part of
 // any contracted integral (A|B) is at most 2 eps S_A S_B in Schwarz units:
 // about eps of the sum of its absolute primitive contributions.  Rows of
-// pairs with a p function keep every primitive pair (code[r] != 0), since
+// pairs with a p, d or f function keep every primitive pair (code[r] != 0), since
 // their primitive Schwarz factors are not proportional to q_i.
 __device__ __forceinline__ double prim_weight(const PrimPairsC &s, int64_t i) {
   return fabs(s.e[i]) * sqrt(sqrt(1.0 / s.ip[i]));

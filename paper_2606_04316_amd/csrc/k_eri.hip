@@ -32,7 +32,11 @@
 // layout and masks; each primitive quartet is evaluated in McMurchie-Davidson
 // form (Hermite expansion of each pair, derivatives of the Boys kernel up to
 // fourth order, common.h) with F_0 .. F_4 from one Taylor table; bra
-// primitives are read from global memory (no LDS staging).
+// primitives are read from global memory (no LDS staging).  General tiles
+// (bases with d or f functions, k_eri_tiles_gen*; gauge tiles of every
+// Cartesian basis, k_eri_gauge_tiles_gen*): the same layout and masks, the
+// Hermite coefficients from their recursion and the Hermite integrals
+// factorized by direction (common.h).
 //
 // Schedules: one workgroup per tile in list order (k_eri_tiles), or a
 // persistent grid of a few workgroups per compute unit that pull tiles from a

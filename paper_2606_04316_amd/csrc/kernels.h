@@ -25,7 +25,7 @@ void launch_schwarz(int64_t npairs, const int64_t *pair_first, PrimPairsC pp,
                     const int32_t *code, double *Q, hipStream_t s);
 // Primitive-pair screening: kept[r] = number of the cnt[r] primitive pairs of
 // row r (starting at src_first[r]) whose Schwarz weight exceeds eps times the
-// row's mean weight; rows with code[r] != 0 (a p function) keep all.
+// row's mean weight; rows with code[r] != 0 (a p, d or f function) keep all.
 void launch_prim_count(int64_t nrows, const int64_t *src_first, const int32_t *cnt,
                        const int32_t *code, PrimPairsC src, double eps, int32_t *kept,
                        hipStream_t s);
@@ -159,9 +159,9 @@ struct EriTileArgs {
   // are counted
   const int32_t *uslot_bk = nullptr, *uslot_kb = nullptr;
   const double *boys = nullptr;  // [BOYS_N][8] Taylor table of F0 (see common.h)
-  // bases with p functions: per sorted row its pair code (see common.h), and
-  // the table [BOYS_N][BOYS_LDC] of (2/sqrt(pi)) F_k(T_i), k < BOYS_LDC; the
-  // integral launches then run the Cartesian tile kernels
+  // Cartesian bases: per sorted row its pair code (see common.h), and the
+  // table [BOYS_N][BOYS_LDC] of (2/sqrt(pi)) F_k(T_i), k < BOYS_LDC; the
+  // integral launches then run the Cartesian (s, p) tile kernels
   const int32_t *code = nullptr;
   const double *boysc = nullptr;
   // bases with d functions: the general tiles (codes as above) with the table

@@ -20,7 +20,7 @@ struct Space {
   DBuf<int64_t> row_first;
   DBuf<double> Q;
   PairStore pp;
-  DBuf<int32_t> code;  // per row: pair code of bases with p functions (else empty)
+  DBuf<int32_t> code;  // per row: pair code of Cartesian bases (else empty)
   int nK = 1;
   // row layout of D~ and V for the current column chunk: nK blocks of ldK
   // columns (ld = nK ldK), packed to the chunk's width; ld_cap = the allocation
@@ -130,7 +130,7 @@ struct qdcb_plan {
   std::atomic<int> busy{0};      // a call is using the plan
   qdcb::DBuf<double> boys;   // Taylor table of the Boys function F0
   qdcb::DBuf<double> boys3;  // F0 .. F9 on the same grid (gauge tiles)
-  bool cart = false;         // a basis has p functions: Cartesian integral tiles
+  bool cart = false;         // a basis has Cartesian (p, d, f) functions
   bool gen = false;          // a basis has d or f functions: the general integral tiles
   // integral tiles in the intra-tile row order of each transform, first half
   // skipping masked 16-row steps (environment QDCB_TILE_ORDER=0 at plan
