@@ -231,3 +231,16 @@ def test_f_eri_quartets(q, ctx):
 def test_f_transform(q, ctx):
     s = _f_sys()
     _check(q, ctx, s, 1e-10)
+
+
+@pytest.mark.parametrize("budget_mb", [40, 24])
+def test_d_small_budgets(q, budget_mb):
+    # small context budgets: several integral-panel batches, the general
+    # kernels writing at slot offsets
+    s = _sys("DCG", 1e-10, seed=69, n=6)
+    c = q.Context(0, budget_bytes=budget_mb << 20)
+    try:
+        st, _ = _check(q, c, s, 1e-10, flags=q.PLAN_DIRECTED_TILES if budget_mb == 24 else 0)
+        assert st["n_batches"] > 1, (st["n_chunks"], st["n_batches"])
+    finally:
+        c.close()

@@ -100,3 +100,15 @@ def test_dcb_sp_graph_replay_equals_eager(q, ctx):
     Ge, _ = plan.transform(CL, CS)
     torch.cuda.synchronize()
     assert torch.equal(Gr, Ge)
+
+
+def test_dcb_sp_small_budget(q):
+    # several integral-panel batches: gauge tiles over p functions made per
+    # batch in the general kernel
+    s = _sp(seed=87, n=5, tau=1e-10)
+    c = q.Context(0, budget_bytes=24 << 20)
+    try:
+        _, _, st = _cmp(q, c, s, 1e-10)
+        assert st["n_batches"] > 1, (st["n_chunks"], st["n_batches"])
+    finally:
+        c.close()
