@@ -30,8 +30,11 @@ __host__ __device__ __forceinline__ int code_g(int c) { return (c >> 5) & 31; }
 
 // Primitive-pair data: 1/p, P, the charge factor e, and for Cartesian bases
 // pa / pb = (P - A) and (P - B) along the direction of a p function (0 for
-// an s function) and the full vectors P - A = (ax, ay, az), P - B = (bx, by,
-// bz) (the general kernels of bases with d functions).
+// an s function), the full vectors P - A = (ax, ay, az), P - B = (bx, by, bz)
+// and the pair's Hermite coefficients E^{ij}_t of each direction
+// (E[PAIR_E * i + 7 d + t], t <= 6; the general kernels of bases with d or f
+// functions).
+constexpr int PAIR_E = 21;  // Hermite coefficients per primitive pair (3 directions x 7)
 struct PrimPairs {
   double *ip;
   double *x;
@@ -42,17 +45,20 @@ struct PrimPairs {
   double *pb = nullptr;
   double *ax = nullptr, *ay = nullptr, *az = nullptr;
   double *bx = nullptr, *by = nullptr, *bz = nullptr;
+  double *E = nullptr;
 };
 
 struct PrimPairsC {
   const double *ip, *x, *y, *z, *e, *pa, *pb;
   const double *ax, *ay, *az, *bx, *by, *bz;
+  const double *E;
   __host__ __device__ PrimPairsC()
       : ip(nullptr), x(nullptr), y(nullptr), z(nullptr), e(nullptr), pa(nullptr), pb(nullptr),
-        ax(nullptr), ay(nullptr), az(nullptr), bx(nullptr), by(nullptr), bz(nullptr) {}
+        ax(nullptr), ay(nullptr), az(nullptr), bx(nullptr), by(nullptr), bz(nullptr),
+        E(nullptr) {}
   __host__ __device__ PrimPairsC(const PrimPairs &s)
       : ip(s.ip), x(s.x), y(s.y), z(s.z), e(s.e), pa(s.pa), pb(s.pb), ax(s.ax), ay(s.ay),
-        az(s.az), bx(s.bx), by(s.by), bz(s.bz) {}
+        az(s.az), bx(s.bx), by(s.by), bz(s.bz), E(s.E) {}
 };
 
 // erf(sqrt(rho) R) / R for one primitive quartet; two Taylor terms of
@@ -334,6 +340,7 @@ __device__ inline double contracted_eri_cart(const PrimPairsC &A, int64_t a0, in
 // ---------------------------------------------------------------------------
 constexpr int GEN_TMAX = 6;                  // Hermite order of a pair per direction (two f)
 constexpr int GEN_NGMAX = 2 * GEN_TMAX + 1;  // Boys orders g_0 .. g_12 (four f functions)
+static_assert(PAIR_E == 3 * (GEN_TMAX + 1), "pair Hermite coefficients: 3 directions");
 
 // a pair code with a d or f function (the general form)
 __host__ __device__ __forceinline__ bool gen_code(int c) {

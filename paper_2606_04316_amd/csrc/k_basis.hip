@@ -97,6 +97,13 @@ __global__ void k_pair_data(int64_t npairs, const int32_t *mu, const int32_t *nu
         out.bx[o] = Px - Bx;
         out.by[o] = Py - By;
         out.bz[o] = Pz - Bz;
+        // Hermite coefficients of the pair per direction
+        const double PA[3] = {Px - Ax, Py - Ay, Pz - Az}, PB[3] = {Px - Bx, Py - By, Pz - Bz};
+        for (int d = 0; d < 3; ++d) {
+          double Ed[GEN_TMAX + 1];
+          herm_1d<GEN_TMAX>(cart_pow(ca, d), cart_pow(cb, d), PA[d], PB[d], 0.5 * ip, Ed);
+          for (int t = 0; t <= GEN_TMAX; ++t) out.E[PAIR_E * o + 7 * d + t] = Ed[t];
+        }
       }
       ++o;
     }
@@ -218,6 +225,9 @@ __global__ void k_gather_pairs(int64_t nrows, const int64_t *src_first, const in
       dst.bx[d] = c ? src.bx[si] : 0.0;
       dst.by[d] = c ? src.by[si] : 0.0;
       dst.bz[d] = c ? src.bz[si] : 0.0;
+      // an s pair's coefficients: E_0 = 1 in each direction
+      for (int k = 0; k < PAIR_E; ++k)
+        dst.E[PAIR_E * d + k] = c ? src.E[PAIR_E * si + k] : (k % 7 == 0 ? 1.0 : 0.0);
     }
     ++d;
   }

@@ -619,29 +619,32 @@ __global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles_queue_cart(EriTileArg
 // Contracted value of one (bra row, ket row) pair of a general tile (codes
 // pair_code(cf, cg)), in the factorized McMurchie-Davidson form of common.h,
 // with TB, TK bounding the Hermite orders of the tile's bra pairs and of the
-// ket pair.  The lane's bra primitive outside (its Hermite coefficients held
-// in registers), the wavefront-uniform ket primitives inside (scalar loads).
+// ket pair.  The pairs' Hermite coefficients come with the pair data (made
+// with it, for the pair's codes).  The lane's bra primitive outside (its
+// coefficients held in registers), the wavefront-uniform ket primitives
+// inside (scalar loads).
 template <int TB, int TK>
 __device__ __forceinline__ double gen_row_pair(const EriTileArgs &A, const double *tab,
                                                int64_t kf0, int64_t kf1, int64_t b0, int64_t b1,
                                                int bcode, int kcode) {
   constexpr int TS = TB + TK;
-  const int fa = code_f(bcode), fb = code_g(bcode), fc = code_f(kcode), fd = code_g(kcode);
   const cdptr kip = as_const(A.pp.ip), kx = as_const(A.pp.x), ky = as_const(A.pp.y),
-              kz = as_const(A.pp.z), ke = as_const(A.pp.e), kax = as_const(A.pp.ax),
-              kay = as_const(A.pp.ay), kaz = as_const(A.pp.az), kbx = as_const(A.pp.bx),
-              kby = as_const(A.pp.by), kbz = as_const(A.pp.bz);
+              kz = as_const(A.pp.z), ke = as_const(A.pp.e), kE = as_const(A.pp.E);
   double v = 0.0;
   for (int64_t b = b0; b < b1; ++b) {
     const double ip = A.pp.ip[b], px = A.pp.x[b], py = A.pp.y[b], pz = A.pp.z[b];
-    const double hb = 0.5 * ip;
+    // the pair's Hermite coefficients (pair data, t <= TB)
     double Ebx[TB + 1], Eby[TB + 1], Ebz[TB + 1];
-    herm_1d<TB>(cart_pow(fa, 0), cart_pow(fb, 0), A.pp.ax[b], A.pp.bx[b], hb, Ebx);
-    herm_1d<TB>(cart_pow(fa, 1), cart_pow(fb, 1), A.pp.ay[b], A.pp.by[b], hb, Eby);
-    herm_1d<TB>(cart_pow(fa, 2), cart_pow(fb, 2), A.pp.az[b], A.pp.bz[b], hb, Ebz);
+    const double *Eb = A.pp.E + PAIR_E * b;
+#pragma unroll
+    for (int t = 0; t <= TB; ++t) {
+      Ebx[t] = Eb[t];
+      Eby[t] = Eb[7 + t];
+      Ebz[t] = Eb[14 + t];
+    }
     double s = 0.0;
     for (int64_t k = kf0; k < kf1; ++k) {
-      const double iq = kip[k], hk = 0.5 * iq;
+      const double iq = kip[k];
       const double X0 = px - kx[k], X1 = py - ky[k], X2 = pz - kz[k];
       const double sr = rsqrt_pos(ip + iq);
       const double rho = sr * sr;
@@ -656,11 +659,15 @@ __device__ __forceinline__ double gen_row_pair(const EriTileArgs &A, const doubl
         f *= m2r;
       }
       double Ek[TK + 1], Px[TS + 1], Py[TS + 1], Pz[TS + 1];
-      herm_1d<TK>(cart_pow(fc, 0), cart_pow(fd, 0), kax[k], kbx[k], hk, Ek);
+      const int64_t ko = PAIR_E * k;
+#pragma unroll
+      for (int t = 0; t <= TK; ++t) Ek[t] = kE[ko + t];
       herm_dir<TB, TK>(Ebx, Ek, X0, Px);
-      herm_1d<TK>(cart_pow(fc, 1), cart_pow(fd, 1), kay[k], kby[k], hk, Ek);
+#pragma unroll
+      for (int t = 0; t <= TK; ++t) Ek[t] = kE[ko + 7 + t];
       herm_dir<TB, TK>(Eby, Ek, X1, Py);
-      herm_1d<TK>(cart_pow(fc, 2), cart_pow(fd, 2), kaz[k], kbz[k], hk, Ek);
+#pragma unroll
+      for (int t = 0; t <= TK; ++t) Ek[t] = kE[ko + 14 + t];
       herm_dir<TB, TK>(Ebz, Ek, X2, Pz);
       s = fma(ke[k], herm_sum<TS>(Px, Py, Pz, G), s);
     }
@@ -773,23 +780,24 @@ __device__ __forceinline__ void gauge_gen_row_pair(const EriTileArgs &A, const d
                                                    int64_t b1, int bcode, int kcode,
                                                    double v[6]) {
   constexpr int TS = 2 * T;
-  const int fa = code_f(bcode), fb = code_g(bcode), fc = code_f(kcode), fd = code_g(kcode);
   const double diag = A.gauge_diag;
   const cdptr kip = as_const(A.pp.ip), kx = as_const(A.pp.x), ky = as_const(A.pp.y),
-              kz = as_const(A.pp.z), ke = as_const(A.pp.e), kax = as_const(A.pp.ax),
-              kay = as_const(A.pp.ay), kaz = as_const(A.pp.az), kbx = as_const(A.pp.bx),
-              kby = as_const(A.pp.by), kbz = as_const(A.pp.bz);
+              kz = as_const(A.pp.z), ke = as_const(A.pp.e), kE = as_const(A.pp.E);
 #pragma unroll
   for (int c = 0; c < 6; ++c) v[c] = 0.0;
   for (int64_t b = b0; b < b1; ++b) {
     const double ip = A.pp.ip[b], px = A.pp.x[b], py = A.pp.y[b], pz = A.pp.z[b];
-    const double hb = 0.5 * ip, eb = A.pp.e[b];
+    const double eb = A.pp.e[b];
     double Ebx[T + 1], Eby[T + 1], Ebz[T + 1];
-    herm_1d<T>(cart_pow(fa, 0), cart_pow(fb, 0), A.pp.ax[b], A.pp.bx[b], hb, Ebx);
-    herm_1d<T>(cart_pow(fa, 1), cart_pow(fb, 1), A.pp.ay[b], A.pp.by[b], hb, Eby);
-    herm_1d<T>(cart_pow(fa, 2), cart_pow(fb, 2), A.pp.az[b], A.pp.bz[b], hb, Ebz);
+    const double *Eb = A.pp.E + PAIR_E * b;
+#pragma unroll
+    for (int t = 0; t <= T; ++t) {
+      Ebx[t] = Eb[t];
+      Eby[t] = Eb[7 + t];
+      Ebz[t] = Eb[14 + t];
+    }
     for (int64_t k = kf0; k < kf1; ++k) {
-      const double iq = kip[k], hk = 0.5 * iq;
+      const double iq = kip[k];
       const double X0 = px - kx[k], X1 = py - ky[k], X2 = pz - kz[k];
       const double sr = rsqrt_pos(ip + iq);
       const double rho = sr * sr;
@@ -809,11 +817,15 @@ __device__ __forceinline__ void gauge_gen_row_pair(const EriTileArgs &A, const d
       double P0x[TS + 1], P1x[TS + 1], P2x[TS + 1];
       double P0y[TS + 1], P1y[TS + 1], P2y[TS + 1];
       double P0z[TS + 1], P1z[TS + 1], P2z[TS + 1];
-      herm_1d<T>(cart_pow(fc, 0), cart_pow(fd, 0), kax[k], kbx[k], hk, Ek);
+      const int64_t ko = PAIR_E * k;
+#pragma unroll
+      for (int t = 0; t <= T; ++t) Ek[t] = kE[ko + t];
       herm_dir3<T, T>(Ebx, Ek, X0, P0x, P1x, P2x);
-      herm_1d<T>(cart_pow(fc, 1), cart_pow(fd, 1), kay[k], kby[k], hk, Ek);
+#pragma unroll
+      for (int t = 0; t <= T; ++t) Ek[t] = kE[ko + 7 + t];
       herm_dir3<T, T>(Eby, Ek, X1, P0y, P1y, P2y);
-      herm_1d<T>(cart_pow(fc, 2), cart_pow(fd, 2), kaz[k], kbz[k], hk, Ek);
+#pragma unroll
+      for (int t = 0; t <= T; ++t) Ek[t] = kE[ko + 14 + t];
       herm_dir3<T, T>(Ebz, Ek, X2, P0z, P1z, P2z);
       const double w = eb * ke[k];
       const double sa = herm_sum<TS>(P0x, P0y, P0z, DA);

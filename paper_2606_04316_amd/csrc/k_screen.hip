@@ -504,6 +504,7 @@ __global__ void __launch_bounds__(TILE) k_gather_rows(int ntiles, const int32_t 
       wpp.bx[to] = pp.bx[from];
       wpp.by[to] = pp.by[from];
       wpp.bz[to] = pp.bz[from];
+      for (int k = 0; k < PAIR_E; ++k) wpp.E[PAIR_E * to + k] = pp.E[PAIR_E * from + k];
     }
   }
 }

@@ -665,7 +665,7 @@ qdcb_status qdcb_plan_estimate(const qdcb_basis *L, const qdcb_basis *S,
     double prims = (double)L->pair_first.back() + (S ? (double)S->pair_first.back() : 0.0);
     if (gaunt) prims += 2.0 * (double)L->first.back() * (double)S->first.back();
     const bool cart = L->has_p() || (S && S->has_p());
-    double b = 2.0 * (cart ? 104.0 : 40.0) * prims;       // primitive-pair data (two orders)
+    double b = 2.0 * (cart ? 272.0 : 40.0) * prims;       // primitive-pair data (two orders)
     b += 88.0 * (PC + PG);                                // row metadata
     b += (desc->prec == QDCB_PREC_MIXED ? 20.0 : 16.0) *
          (PC * ldK + 3.0 * PG * ldK);                     // D~, V (and FP32 D~), all columns

@@ -180,10 +180,11 @@ struct PairStore {
   DBuf<double> p, x, y, z, e;
   DBuf<double> pa, pb;                  // Cartesian bases only (see PrimPairs)
   DBuf<double> ax, ay, az, bx, by, bz;  // likewise
+  DBuf<double> E;                       // likewise, PAIR_E per primitive pair
   PairStore() = default;
   explicit PairStore(Pooled)
       : p(POOLED), x(POOLED), y(POOLED), z(POOLED), e(POOLED), pa(POOLED), pb(POOLED),
-        ax(POOLED), ay(POOLED), az(POOLED), bx(POOLED), by(POOLED), bz(POOLED) {}
+        ax(POOLED), ay(POOLED), az(POOLED), bx(POOLED), by(POOLED), bz(POOLED), E(POOLED) {}
   // cart: pa / pb and the P - A, P - B vectors (bases with p or d functions)
   void alloc(qdcb_ctx *c, size_t n, bool cart = false) {
     p.alloc(c, n);
@@ -197,6 +198,10 @@ struct PairStore {
       else
         b->free();
     }
+    if (cart)
+      E.alloc(c, n * PAIR_E);
+    else
+      E.free();
   }
   PrimPairs view() {
     PrimPairs v{p.p, x.p, y.p, z.p, e.p, pa.p, pb.p};
@@ -206,15 +211,18 @@ struct PairStore {
     v.bx = bx.p;
     v.by = by.p;
     v.bz = bz.p;
+    v.E = E.p;
     return v;
   }
   PrimPairsC cview() const { return PrimPairsC(const_cast<PairStore *>(this)->view()); }
   void free() {
-    for (DBuf<double> *b : {&p, &x, &y, &z, &e, &pa, &pb, &ax, &ay, &az, &bx, &by, &bz}) b->free();
+    for (DBuf<double> *b : {&p, &x, &y, &z, &e, &pa, &pb, &ax, &ay, &az, &bx, &by, &bz, &E})
+      b->free();
   }
   size_t bytes() const {
     return p.bytes() * 5 + pa.bytes() + pb.bytes() +
-           (ax.bytes() + ay.bytes() + az.bytes() + bx.bytes() + by.bytes() + bz.bytes());
+           (ax.bytes() + ay.bytes() + az.bytes() + bx.bytes() + by.bytes() + bz.bytes()) +
+           E.bytes();
   }
 };
 
