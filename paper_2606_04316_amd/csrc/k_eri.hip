@@ -676,15 +676,19 @@ __device__ __forceinline__ double gen_row_pair(const EriTileArgs &A, const doubl
   return v;
 }
 
-template <int TB>
+// TMAX: the largest Hermite order bound of the launch (4 when neither basis
+// has an f function: the f-sized forms, and their registers, stay out of the
+// kernel)
+template <int TB, int TMAX>
 __device__ __forceinline__ double gen_row_pair_k(const EriTileArgs &A, const double *tab,
                                                  int64_t kf0, int64_t kf1, int64_t b0,
                                                  int64_t b1, int bcode, int kcode, int tk) {
   if (tk == 2) return gen_row_pair<TB, 2>(A, tab, kf0, kf1, b0, b1, bcode, kcode);
-  if (tk == 4) return gen_row_pair<TB, 4>(A, tab, kf0, kf1, b0, b1, bcode, kcode);
-  return gen_row_pair<TB, 6>(A, tab, kf0, kf1, b0, b1, bcode, kcode);
+  if (TMAX == 4 || tk == 4) return gen_row_pair<TB, 4>(A, tab, kf0, kf1, b0, b1, bcode, kcode);
+  return gen_row_pair<TB, TMAX>(A, tab, kf0, kf1, b0, b1, bcode, kcode);
 }
 
+template <int TMAX>
 __device__ __forceinline__ void eri_gen_one_tile(const EriTileArgs &a, const double *tab,
                                                  int64_t slot, long long kept[4]) {
   const int kt = a.tasks[slot];
@@ -722,11 +726,11 @@ __device__ __forceinline__ void eri_gen_one_tile(const EriTileArgs &a, const dou
     if (keep_bk || keep_kb) {
       const int tk = gen_bucket(kcode);
       if (tb == 2)
-        v = gen_row_pair_k<2>(a, tab, kf0, kf1, bfirst, blast, bcode, kcode, tk);
-      else if (tb == 4)
-        v = gen_row_pair_k<4>(a, tab, kf0, kf1, bfirst, blast, bcode, kcode, tk);
+        v = gen_row_pair_k<2, TMAX>(a, tab, kf0, kf1, bfirst, blast, bcode, kcode, tk);
+      else if (TMAX == 4 || tb == 4)
+        v = gen_row_pair_k<4, TMAX>(a, tab, kf0, kf1, bfirst, blast, bcode, kcode, tk);
       else
-        v = gen_row_pair_k<6>(a, tab, kf0, kf1, bfirst, blast, bcode, kcode, tk);
+        v = gen_row_pair_k<TMAX, TMAX>(a, tab, kf0, kf1, bfirst, blast, bcode, kcode, tk);
       if (cb >= 0 && ck >= 0) {
         if (keep_bk) kept[cb * 2 + ck] += 1;
         if (keep_kb) kept[ck * 2 + cb] += 1;
@@ -737,6 +741,7 @@ __device__ __forceinline__ void eri_gen_one_tile(const EriTileArgs &a, const dou
   }
 }
 
+template <int TMAX>
 __global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles_gen(EriTileArgs a) {
   __shared__ double tab[BOYS_N * BOYS_LDG];
   if (a.overflow && *a.overflow) return;  // uniform
@@ -744,11 +749,12 @@ __global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles_gen(EriTileArgs a) {
   for (int t = threadIdx.x; t < BOYS_N * BOYS_LDG; t += ERI_THREADS) tab[t] = a.boysg[t];
   __syncthreads();
   long long kept[4] = {0, 0, 0, 0};
-  eri_gen_one_tile(a, tab, a.slot0 + blockIdx.x, kept);
+  eri_gen_one_tile<TMAX>(a, tab, a.slot0 + blockIdx.x, kept);
   eri_count(a, kept);
 }
 
 // Persistent variant; same queue protocol as k_eri_tiles_queue.
+template <int TMAX>
 __global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles_queue_gen(EriTileArgs a,
                                                                      const int32_t *order,
                                                                      unsigned long long *qctr,
@@ -765,7 +771,7 @@ __global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles_queue_gen(EriTileArgs
     __syncthreads();
     const int64_t i = s_next;
     if (i >= n) break;  // uniform
-    eri_gen_one_tile(a, tab, order[i], kept);
+    eri_gen_one_tile<TMAX>(a, tab, order[i], kept);
   }
   eri_count(a, kept);
 }
@@ -851,6 +857,10 @@ __device__ __attribute__((noinline)) void gauge_gen_row_pair_call(const EriTileA
   gauge_gen_row_pair<T>(A, tab, kf0, kf1, b0, b1, bcode, kcode, v);
 }
 
+// TMAX: the largest Hermite order bound of the launch (2 for s and p bases, 4
+// with d and no f functions, else 6): the larger forms, and their registers,
+// stay out of kernels that never run them
+template <int TMAX>
 __device__ __forceinline__ void eri_gauge_gen_one_tile(const EriTileArgs &a, const double *tab,
                                                        int64_t slot, long long kept[4]) {
   const int kt = a.tasks[slot];
@@ -887,9 +897,9 @@ __device__ __forceinline__ void eri_gauge_gen_one_tile(const EriTileArgs &a, con
     const bool keep_kb = outT && (qk * qb) * db >= a.tau;
     if (keep_bk || keep_kb) {
       const int t = max(tb, gen_bucket(kcode));
-      if (t == 2)
+      if (TMAX == 2 || t == 2)
         gauge_gen_row_pair<2>(a, tab, kf0, kf1, bfirst, blast, bcode, kcode, v);
-      else if (t == 4)
+      else if (TMAX == 4 || t == 4)
         gauge_gen_row_pair_call<4>(a, tab, kf0, kf1, bfirst, blast, bcode, kcode, v);
       else
         gauge_gen_row_pair_call<6>(a, tab, kf0, kf1, bfirst, blast, bcode, kcode, v);
@@ -906,6 +916,7 @@ __device__ __forceinline__ void eri_gauge_gen_one_tile(const EriTileArgs &a, con
   }
 }
 
+template <int TMAX>
 __global__ void __launch_bounds__(ERI_THREADS) k_eri_gauge_tiles_gen(EriTileArgs a) {
   __shared__ double tab[BOYS_N * BOYS_LDG];
   if (a.overflow && *a.overflow) return;  // uniform
@@ -913,11 +924,12 @@ __global__ void __launch_bounds__(ERI_THREADS) k_eri_gauge_tiles_gen(EriTileArgs
   for (int t = threadIdx.x; t < BOYS_N * BOYS_LDG; t += ERI_THREADS) tab[t] = a.boysg[t];
   __syncthreads();
   long long kept[4] = {0, 0, 0, 0};
-  eri_gauge_gen_one_tile(a, tab, a.slot0 + blockIdx.x, kept);
+  eri_gauge_gen_one_tile<TMAX>(a, tab, a.slot0 + blockIdx.x, kept);
   eri_count(a, kept);
 }
 
 // Persistent variant; same queue protocol as k_eri_tiles_queue.
+template <int TMAX>
 __global__ void __launch_bounds__(ERI_THREADS) k_eri_gauge_tiles_queue_gen(
     EriTileArgs a, const int32_t *order, unsigned long long *qctr, int64_t n_host) {
   __shared__ double tab[BOYS_N * BOYS_LDG];
@@ -932,15 +944,17 @@ __global__ void __launch_bounds__(ERI_THREADS) k_eri_gauge_tiles_queue_gen(
     __syncthreads();
     const int64_t i = s_next;
     if (i >= n) break;  // uniform
-    eri_gauge_gen_one_tile(a, tab, order[i], kept);
+    eri_gauge_gen_one_tile<TMAX>(a, tab, order[i], kept);
   }
   eri_count(a, kept);
 }
 
 void launch_eri_tiles(const EriTileArgs &a, int64_t nslots, hipStream_t s) {
   if (nslots <= 0) return;
-  if (a.boysg)
-    hipLaunchKernelGGL(k_eri_tiles_gen, dim3((unsigned)nslots), dim3(ERI_THREADS), 0, s, a);
+  if (a.boysg && a.gen_tmax <= 4)
+    hipLaunchKernelGGL(k_eri_tiles_gen<4>, dim3((unsigned)nslots), dim3(ERI_THREADS), 0, s, a);
+  else if (a.boysg)
+    hipLaunchKernelGGL(k_eri_tiles_gen<6>, dim3((unsigned)nslots), dim3(ERI_THREADS), 0, s, a);
   else if (a.code)
     hipLaunchKernelGGL(k_eri_tiles_cart, dim3((unsigned)nslots), dim3(ERI_THREADS), 0, s, a);
   else
@@ -950,9 +964,12 @@ void launch_eri_tiles(const EriTileArgs &a, int64_t nslots, hipStream_t s) {
 void launch_eri_tiles_queue(const EriTileArgs &a, const int32_t *order, unsigned long long *qctr,
                             int64_t n_host, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return;
-  if (a.boysg)
-    hipLaunchKernelGGL(k_eri_tiles_queue_gen, dim3((unsigned)nblocks), dim3(ERI_THREADS), 0, s,
-                       a, order, qctr, n_host);
+  if (a.boysg && a.gen_tmax <= 4)
+    hipLaunchKernelGGL(k_eri_tiles_queue_gen<4>, dim3((unsigned)nblocks), dim3(ERI_THREADS), 0,
+                       s, a, order, qctr, n_host);
+  else if (a.boysg)
+    hipLaunchKernelGGL(k_eri_tiles_queue_gen<6>, dim3((unsigned)nblocks), dim3(ERI_THREADS), 0,
+                       s, a, order, qctr, n_host);
   else if (a.code)
     hipLaunchKernelGGL(k_eri_tiles_queue_cart, dim3((unsigned)nblocks), dim3(ERI_THREADS), 0, s,
                        a, order, qctr, n_host);
@@ -963,9 +980,15 @@ void launch_eri_tiles_queue(const EriTileArgs &a, const int32_t *order, unsigned
 
 void launch_eri_gauge_tiles(const EriTileArgs &a, int64_t nslots, hipStream_t s) {
   if (nslots <= 0) return;
-  if (a.code)  // Cartesian bases: the general form
-    hipLaunchKernelGGL(k_eri_gauge_tiles_gen, dim3((unsigned)nslots), dim3(ERI_THREADS), 0, s,
-                       a);
+  if (a.code && a.gen_tmax <= 2)  // Cartesian bases: the general form
+    hipLaunchKernelGGL(k_eri_gauge_tiles_gen<2>, dim3((unsigned)nslots), dim3(ERI_THREADS), 0,
+                       s, a);
+  else if (a.code && a.gen_tmax <= 4)
+    hipLaunchKernelGGL(k_eri_gauge_tiles_gen<4>, dim3((unsigned)nslots), dim3(ERI_THREADS), 0,
+                       s, a);
+  else if (a.code)
+    hipLaunchKernelGGL(k_eri_gauge_tiles_gen<6>, dim3((unsigned)nslots), dim3(ERI_THREADS), 0,
+                       s, a);
   else
     hipLaunchKernelGGL(k_eri_tiles<true>, dim3((unsigned)nslots), dim3(ERI_THREADS), 0, s, a);
 }
@@ -974,9 +997,15 @@ void launch_eri_gauge_tiles_queue(const EriTileArgs &a, const int32_t *order,
                                   unsigned long long *qctr, int64_t n_host, int nblocks,
                                   hipStream_t s) {
   if (nblocks <= 0) return;
-  if (a.code)
-    hipLaunchKernelGGL(k_eri_gauge_tiles_queue_gen, dim3((unsigned)nblocks), dim3(ERI_THREADS),
-                       0, s, a, order, qctr, n_host);
+  if (a.code && a.gen_tmax <= 2)
+    hipLaunchKernelGGL(k_eri_gauge_tiles_queue_gen<2>, dim3((unsigned)nblocks),
+                       dim3(ERI_THREADS), 0, s, a, order, qctr, n_host);
+  else if (a.code && a.gen_tmax <= 4)
+    hipLaunchKernelGGL(k_eri_gauge_tiles_queue_gen<4>, dim3((unsigned)nblocks),
+                       dim3(ERI_THREADS), 0, s, a, order, qctr, n_host);
+  else if (a.code)
+    hipLaunchKernelGGL(k_eri_gauge_tiles_queue_gen<6>, dim3((unsigned)nblocks),
+                       dim3(ERI_THREADS), 0, s, a, order, qctr, n_host);
   else
     hipLaunchKernelGGL(k_eri_tiles_queue<true>, dim3((unsigned)nblocks), dim3(ERI_THREADS), 0,
                        s, a, order, qctr, n_host);

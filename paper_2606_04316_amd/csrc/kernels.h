@@ -167,6 +167,10 @@ struct EriTileArgs {
   // bases with d functions: the general tiles (codes as above) with the table
   // [BOYS_N][BOYS_LDG] of (2/sqrt(pi)) F_k(T_i), k < BOYS_LDG
   const double *boysg = nullptr;
+  // the largest Hermite order bound of the general tiles: 2 when the rows
+  // hold s and p functions only, 4 with d and no f functions, else 6 (the
+  // kernels without the larger forms)
+  int gen_tmax = 6;
   const int32_t *tasks;       // [slots] ket tile per slot
   const int32_t *task_bra;    // [slots] bra tile per slot
   int64_t slot0;              // slot index of the panel buffer's first entry

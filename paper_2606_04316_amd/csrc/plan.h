@@ -132,6 +132,7 @@ struct qdcb_plan {
   qdcb::DBuf<double> boys3;  // F0 .. F9 on the same grid (gauge tiles)
   bool cart = false;         // a basis has Cartesian (p, d, f) functions
   bool gen = false;          // a basis has d or f functions: the general integral tiles
+  bool gen_f = false;        // ... and f functions (the general tiles' largest orders)
   // integral tiles in the intra-tile row order of each transform, first half
   // skipping masked 16-row steps (environment QDCB_TILE_ORDER=0 at plan
   // creation turns it off, for comparisons)

@@ -435,6 +435,7 @@ qdcb_status qdcb_plan_create(qdcb_ctx *ctx, const qdcb_basis *L, const qdcb_basi
     p.fused_breit = p.gauge && desc->prec == QDCB_PREC_FP64;
     p.cart = L->has_p() || (S && S->has_p());
     p.gen = L->has_gen() || (S && S->has_gen());
+    p.gen_f = L->has_f() || (S && S->has_f());
     {
       const char *e = std::getenv("QDCB_TILE_ORDER");
       p.tile_order = !(e && e[0] == '0');

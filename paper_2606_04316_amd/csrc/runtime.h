@@ -246,6 +246,11 @@ struct qdcb_basis {
       if (c >= 4) return true;
     return false;
   }
+  bool has_f() const {
+    for (int32_t c : cart)
+      if (c >= 10) return true;
+    return false;
+  }
   int32_t cart_of(int f) const { return cart.empty() ? 0 : cart[f]; }
   qdcb::DBuf<double> cent, exps, coefs, nc;
   qdcb::DBuf<int32_t> dfirst, dcart;

@@ -253,6 +253,7 @@ EriTileArgs eri_args(qdcb_plan &p, Space &sp, int64_t slot0, bool count, bool ga
   // tiles of every Cartesian basis
   const bool general = p.gen || (p.cart && gauge);
   ea.boysg = general ? p.boysg.p : nullptr;
+  ea.gen_tmax = p.gen_f ? 6 : (p.gen ? 4 : 2);
   if (general && !ea.boysg) fail(QDCB_E_DEVICE, "general tiles without their table");
   if (p.cart && (!ea.code || !ea.boysc || !sp.pp.pa.p || !sp.pp.ax.p))
     fail(QDCB_E_DEVICE, "Cartesian tiles without their codes, table or pair data");
