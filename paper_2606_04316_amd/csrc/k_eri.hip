@@ -616,6 +616,17 @@ __global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles_queue_cart(EriTileArg
 
 // ---- general (s .. f) tiles: bases with d or f functions
 
+// Workgroups of four wavefronts (each 16 ket rows of the tile): the general
+// form holds more registers than the s and p kernels, and smaller workgroups
+// let three of them share a compute unit when the registers allow it (the
+// d-sized kernel; the f-sized one is held to two).
+constexpr int GEN_WAVES = 4;
+constexpr int GEN_THREADS = 64 * GEN_WAVES;
+template <int TMAX>
+constexpr int gen_blocks() {  // workgroups per compute unit the registers are sized for
+  return TMAX <= 4 ? 3 : 2;
+}
+
 // Contracted value of one (bra row, ket row) pair of a general tile (codes
 // pair_code(cf, cg)), in the factorized McMurchie-Davidson form of common.h,
 // with TB, TK bounding the Hermite orders of the tile's bra pairs and of the
@@ -713,8 +724,8 @@ __device__ __forceinline__ void eri_gen_one_tile(const EriTileArgs &a, const dou
   int tb = gen_bucket(bcode);
   for (int o = 32; o > 0; o >>= 1) tb = max(tb, __shfl_xor(tb, o, 64));
   tb = __builtin_amdgcn_readfirstlane(tb);
-  for (int i = 0; i < TILE / ERI_WAVES; ++i) {
-    const int j = w + ERI_WAVES * i;
+  for (int i = 0; i < TILE / GEN_WAVES; ++i) {
+    const int j = w + GEN_WAVES * i;
     const int64_t krow = (int64_t)kt * TILE + j;
     const double qk = a.Q[krow], dk = a.Dmax[krow];
     const int ck = a.cls[krow];
@@ -742,11 +753,11 @@ __device__ __forceinline__ void eri_gen_one_tile(const EriTileArgs &a, const dou
 }
 
 template <int TMAX>
-__global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles_gen(EriTileArgs a) {
+__global__ void __launch_bounds__(GEN_THREADS, gen_blocks<TMAX>()) k_eri_tiles_gen(EriTileArgs a) {
   __shared__ double tab[BOYS_N * BOYS_LDG];
   if (a.overflow && *a.overflow) return;  // uniform
   if (a.d_total && (int64_t)blockIdx.x >= min(*a.d_total, a.cap)) return;  // uniform
-  for (int t = threadIdx.x; t < BOYS_N * BOYS_LDG; t += ERI_THREADS) tab[t] = a.boysg[t];
+  for (int t = threadIdx.x; t < BOYS_N * BOYS_LDG; t += GEN_THREADS) tab[t] = a.boysg[t];
   __syncthreads();
   long long kept[4] = {0, 0, 0, 0};
   eri_gen_one_tile<TMAX>(a, tab, a.slot0 + blockIdx.x, kept);
@@ -755,7 +766,7 @@ __global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles_gen(EriTileArgs a) {
 
 // Persistent variant; same queue protocol as k_eri_tiles_queue.
 template <int TMAX>
-__global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles_queue_gen(EriTileArgs a,
+__global__ void __launch_bounds__(GEN_THREADS, gen_blocks<TMAX>()) k_eri_tiles_queue_gen(EriTileArgs a,
                                                                      const int32_t *order,
                                                                      unsigned long long *qctr,
                                                                      int64_t n_host) {
@@ -763,7 +774,7 @@ __global__ void __launch_bounds__(ERI_THREADS) k_eri_tiles_queue_gen(EriTileArgs
   __shared__ int64_t s_next;
   if (a.overflow && *a.overflow) return;  // uniform
   const int64_t n = a.d_total ? min(*a.d_total, a.cap) : n_host;
-  for (int t = threadIdx.x; t < BOYS_N * BOYS_LDG; t += ERI_THREADS) tab[t] = a.boysg[t];
+  for (int t = threadIdx.x; t < BOYS_N * BOYS_LDG; t += GEN_THREADS) tab[t] = a.boysg[t];
   long long kept[4] = {0, 0, 0, 0};
   for (;;) {
     __syncthreads();  // table staged; the previous s_next read by every thread
@@ -952,9 +963,9 @@ __global__ void __launch_bounds__(ERI_THREADS) k_eri_gauge_tiles_queue_gen(
 void launch_eri_tiles(const EriTileArgs &a, int64_t nslots, hipStream_t s) {
   if (nslots <= 0) return;
   if (a.boysg && a.gen_tmax <= 4)
-    hipLaunchKernelGGL(k_eri_tiles_gen<4>, dim3((unsigned)nslots), dim3(ERI_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_eri_tiles_gen<4>, dim3((unsigned)nslots), dim3(GEN_THREADS), 0, s, a);
   else if (a.boysg)
-    hipLaunchKernelGGL(k_eri_tiles_gen<6>, dim3((unsigned)nslots), dim3(ERI_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_eri_tiles_gen<6>, dim3((unsigned)nslots), dim3(GEN_THREADS), 0, s, a);
   else if (a.code)
     hipLaunchKernelGGL(k_eri_tiles_cart, dim3((unsigned)nslots), dim3(ERI_THREADS), 0, s, a);
   else
@@ -964,11 +975,14 @@ void launch_eri_tiles(const EriTileArgs &a, int64_t nslots, hipStream_t s) {
 void launch_eri_tiles_queue(const EriTileArgs &a, const int32_t *order, unsigned long long *qctr,
                             int64_t n_host, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return;
+  // the d-sized general kernel's smaller workgroups: three per compute unit
+  // where the others run two (nblocks is sized for two)
+  const int gblocks = nblocks / 2 * gen_blocks<4>() + nblocks % 2;
   if (a.boysg && a.gen_tmax <= 4)
-    hipLaunchKernelGGL(k_eri_tiles_queue_gen<4>, dim3((unsigned)nblocks), dim3(ERI_THREADS), 0,
+    hipLaunchKernelGGL(k_eri_tiles_queue_gen<4>, dim3((unsigned)gblocks), dim3(GEN_THREADS), 0,
                        s, a, order, qctr, n_host);
   else if (a.boysg)
-    hipLaunchKernelGGL(k_eri_tiles_queue_gen<6>, dim3((unsigned)nblocks), dim3(ERI_THREADS), 0,
+    hipLaunchKernelGGL(k_eri_tiles_queue_gen<6>, dim3((unsigned)nblocks), dim3(GEN_THREADS), 0,
                        s, a, order, qctr, n_host);
   else if (a.code)
     hipLaunchKernelGGL(k_eri_tiles_queue_cart, dim3((unsigned)nblocks), dim3(ERI_THREADS), 0, s,
