@@ -34,9 +34,11 @@
 // fourth order, common.h) with F_0 .. F_4 from one Taylor table; bra
 // primitives are read from global memory (no LDS staging).  General tiles
 // (bases with d or f functions, k_eri_tiles_gen*; gauge tiles of every
-// Cartesian basis, k_eri_gauge_tiles_gen*): the same layout and masks, the
-// Hermite coefficients from their recursion and the Hermite integrals
-// factorized by direction (common.h).
+// Cartesian basis, k_eri_gauge_tiles_gen*): lane = bra row and the same
+// masks, the pairs' Hermite coefficients from the pair data and the Hermite
+// integrals factorized by direction (common.h); each kernel instantiated for
+// the largest Hermite orders of the plan's bases, and the general Coulomb
+// tiles in workgroups of four wavefronts x 16 ket rows.
 //
 // Schedules: one workgroup per tile in list order (k_eri_tiles), or a
 // persistent grid of a few workgroups per compute unit that pull tiles from a
