@@ -314,7 +314,8 @@ class GpuExecutor:
                "flops": st["flops_first_half"] + st["flops_second_half"],
                "ms_plan": 1e3 * (t_plan - t_start), "ms_transform_call": 1e3 * (t_tr - t_plan),
                "ms_copy": 1e3 * (t_result - t_tr),
-               "ms_digest": 1e3 * (time.perf_counter() - t_result)}
+               "ms_digest": 1e3 * (time.perf_counter() - t_result),
+               "path": {k: st[k] for k in ("n_batches", "n_chunks", "tiles_made")}}
         if self.keep_outputs:
             out["G"] = G
         return out
