@@ -318,6 +318,11 @@ void size_plan(qdcb_plan &p, int64_t slotsC, int64_t slotsG) {
     if (p.desc.prec == QDCB_PREC_MIXED) sp->Dlo.alloc(ctx, (size_t)sp->Ppad * sp->ld);
     sp->V.alloc(ctx, (size_t)sp->Ppad * sp->ld);
   }
+  // the zeroing runs on the null stream, which is not ordered with the
+  // caller's (non-blocking) streams, and may wait there behind other threads'
+  // set-up work: it must be complete before a transform on another stream
+  // writes the densities (a resize happens inside the first transform)
+  HIPC(hipStreamSynchronize(nullptr));
   // --- second-half slice: W and G slices
   {
     const double avail = fixed ? (double)room() - panels : (double)room() / 8;
